@@ -1,0 +1,102 @@
+"""Write the interval/eigengap fixtures used by the tests and the bench.
+
+Calls only ``oracle`` (and the shared input generators in ``pencils``).  Run
+from the repository root:
+
+    python tests/golden/make_windows.py c0          # 10^3 grid, dense LAPACK
+    python tests/golden/make_windows.py c1          # 64^3 grid, shift-invert Lanczos
+    python tests/golden/make_windows.py small       # the small parity pencils
+
+Each fixture stores the workload recipe (grid, seeds), the window of
+eigenvalues (ascending, the oracle's values) and the eigengaps
+(a_-, a_+, b_-, b_+) following the experiments' convention (Sec. 3.1): the
+gap endpoints are the true neighbouring eigenvalues and a, b the gap midpoints.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import pencils  # noqa: E402
+from oracle.dense import pencil_eigh_lapack  # noqa: E402
+from oracle.sparse import count_interval, window_near  # noqa: E402
+
+
+def _dump(name, obj):
+    path = os.path.join(HERE, name)
+    with open(path, "w") as f:
+        json.dump(obj, f, indent=1)
+    print("wrote", path)
+
+
+def dense_window(n, n_lambda, start=None, name=None):
+    p = pencils.grid7(n)
+    A, B = p.scipy()
+    lam, _ = pencil_eigh_lapack(A.toarray(), B.toarray())
+    if start is None:
+        start = p.n // 2 - n_lambda // 2
+    w = pencils.window_from_eigenvalues(lam, start, n_lambda)
+    w.update(
+        {
+            "workload": f"grid7 {n}^3",
+            "grid": [n, n, n],
+            "seed_v": 0,
+            "start_index": int(start),
+            "eigenvalues": [float(x) for x in lam[start : start + n_lambda]],
+            "source": "oracle.dense.pencil_eigh_lapack (LAPACK generalized Hermitian)",
+        }
+    )
+    _dump(name or f"window_grid7_{n}.json", w)
+
+
+def c1_window(n=64, n_lambda=64, sigma0=6.0, k=80, verify=True):
+    p = pencils.grid7(n)
+    A, B = p.scipy()
+    t = time.time()
+    lam, _ = window_near(A.tocsc(), B.tocsc(), sigma0, k)
+    t_eig = time.time() - t
+    # central n_lambda of the k nearest, with one neighbour on each side for the gaps
+    i0 = (k - n_lambda) // 2
+    w = pencils.window_from_eigenvalues(lam, i0, n_lambda)
+    cnt = None
+    t_cnt = None
+    if verify:
+        t = time.time()
+        cnt = count_interval(A, B, w["a"], w["b"])
+        t_cnt = time.time() - t
+    w.update(
+        {
+            "workload": f"grid7 {n}^3 mid-spectrum window near {sigma0}",
+            "grid": [n, n, n],
+            "seed_v": 0,
+            "sigma0": sigma0,
+            "eigenvalues": [float(x) for x in lam[i0 : i0 + n_lambda]],
+            "neighbours": [float(x) for x in lam],
+            "inertia_count": cnt,
+            "source": "oracle.sparse.window_near (shift-invert Lanczos, ARPACK) + Sylvester inertia count",
+            "seconds": {"eigsh": t_eig, "inertia": t_cnt},
+        }
+    )
+    _dump(f"window_grid7_{n}.json", w)
+
+
+if __name__ == "__main__":
+    what = sys.argv[1] if len(sys.argv) > 1 else "c0"
+    if what == "c0":
+        dense_window(10, 16)
+    elif what == "small":
+        dense_window(6, 8)
+        dense_window(8, 12)
+        dense_window(12, 16)
+    elif what == "c1":
+        c1_window()
+    elif what.startswith("grid"):
+        n = int(what[4:])
+        c1_window(n=n, verify=True)
