@@ -1,0 +1,237 @@
+/*
+ * zolo.h -- C ABI of the MI355X (gfx950) Zolotarev spectrum-filter eigensolver.
+ *
+ * Problem (Li & Yang, Sec. 1, eq. IGEVP): for a sparse Hermitian definite
+ * pencil (A, B) and an interval (a, b), find all (lambda, x) with
+ * A x = lambda B x and a < lambda < b.  The solver is subspace iteration
+ * (Algorithm 1) with the rational filter
+ *     R_ab(x) = (Z_2r2(Zhat_2r1(T(x); l1); l2) + 1) / 2      (eq. Rab / R2)
+ * applied by the hybrid algorithm (Algorithm 2): r1 sparse LDL^T
+ * factorizations of A - sigma_hat_j B build the operator G of eq. (solve),
+ * and shift-invariant block GMRES on G solves the outer shifts of eq. (solve2).
+ *
+ * Conventions for every call below.
+ *  - Errors never abort: a call returns a zolo_status and zolo_last_error()
+ *    gives a thread-local message for the last failing call.
+ *  - Host arrays passed in are copied during the call; the caller keeps them.
+ *  - Handles (ctx, pencil, factors, result) are owned by the library until
+ *    their *_free / *_destroy call.
+ *  - "d_" arguments are device pointers owned by the caller (for instance
+ *    PyTorch tensors on the context's device); dense blocks are row-major
+ *    N x p with leading dimension ld >= p (element stride between rows).
+ *    Real pencils use double; complex Hermitian pencils use interleaved
+ *    complex128 (re, im).
+ *  - stream: a hipStream_t passed as void*; NULL means the default stream.
+ *    Device entry points enqueue on that stream and synchronise it before
+ *    returning, so outputs are ready when the call returns.
+ *  - Indices of the CSR inputs are 0-based, rows sorted by column, A and B
+ *    share one pattern stored in full (both triangles).
+ */
+#ifndef ZOLO_H
+#define ZOLO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZOLO_OK = 0,
+  ZOLO_EINVAL = 1,     /* invalid argument (sizes, pointers, gap order, CSR) */
+  ZOLO_ENOTHERM = 2,   /* A or B not Hermitian, or patterns differ           */
+  ZOLO_ENOMEM = 3,     /* device or host allocation failed                  */
+  ZOLO_ENOCONV = 4,    /* GMRES or subspace iteration missed its tolerance  */
+  ZOLO_EGAP = 5,       /* a Ritz value fell inside a stated eigengap         */
+  ZOLO_ESUBSPACE = 6,  /* subspace too small for the count found             */
+  ZOLO_EDEVICE = 7,    /* HIP runtime error                                  */
+  ZOLO_EBREAKDOWN = 8  /* zero pivot in a factorization or Gram matrix       */
+} zolo_status;
+
+typedef enum { ZOLO_REAL64 = 0, ZOLO_COMPLEX128 = 1 } zolo_scalar;
+typedef enum { ZOLO_PREC_FP64 = 0, ZOLO_PREC_MIXED = 1 } zolo_precision;
+
+#define ZOLO_MAX_R 16
+
+/*
+ * Coefficient set of the filter (Algorithm 2, lines 2-4; Remark after
+ * Proposition 2 for the hatted names).  Filled by zolo_filter_plan.
+ *   Moebius map T(x) = gamma (x - alpha)/(x - beta)          (eq. mo, eq. req)
+ *   inner function g(x) = Zhat_2r1(T(x); l1)
+ *     = M_hat [c0 + sum_j (w_hat_j/(x - sigma_hat_j) + conj(w_hat_j)/(x - conj(sigma_hat_j)))]
+ *                                                             (Proposition 2)
+ *   outer Z_2r2(g; l2) = (M/2) sum_j a_j (1/(g + i sqrt c_j) + 1/(g - i sqrt c_j))
+ *                                                             (Corollary 1)
+ */
+typedef struct {
+  int r1, r2;
+  double a_minus, a_plus, b_minus, b_plus;
+  double l1, l2;
+  double alpha, beta, gamma;
+  double M_hat, c0, delta1;
+  double sigma_hat_re[ZOLO_MAX_R], sigma_hat_im[ZOLO_MAX_R];
+  double w_hat_re[ZOLO_MAX_R], w_hat_im[ZOLO_MAX_R];
+  double a_hat[ZOLO_MAX_R], c_hat[ZOLO_MAX_R]; /* c_hat_{2j-1}, j = 1..r1 */
+  double M;
+  double a[ZOLO_MAX_R], c[ZOLO_MAX_R];         /* c_{2j-1} of Z_2r2(.; l2) */
+  double delta_S, delta0;                      /* composite error; delta0 = delta_S/2 */
+} zolo_filter_coeffs;
+
+typedef struct {
+  double a_minus, a_plus, b_minus, b_plus; /* eigengaps; a_minus may be -INF or b_plus +INF */
+  int r1;                  /* number of factorizations (inner order)               */
+  int r2;                  /* outer order; 0 = smallest r2 with delta0 <= filter_eps */
+  double filter_eps;       /* target delta0 when r2 == 0 (Remark after Algorithm 2) */
+  int n_ss;                /* subspace size; 0 = ceil(1.5 n_lambda_est)             */
+  int max_subspace_iter;   /* Algorithm 1 iterations                                */
+  int max_gmres_iter;      /* block GMRES steps per filter application              */
+  double tol_resid;        /* ||Ax - lam Bx|| / ((||A|| + |lam| ||B||) ||x||)        */
+  double tol_gmres;        /* per shift and column, relative LS residual            */
+  int precision;           /* zolo_precision                                        */
+  uint64_t seed;           /* start block when none is passed                       */
+  int max_refine;          /* mixed precision: refinement steps per pole solve      */
+  double tol_refine;       /* mixed precision: inner relative residual              */
+} zolo_opts;
+
+typedef struct {
+  int n_iter;              /* subspace iterations                                   */
+  int n_gmres_total;       /* GMRES steps summed over iterations                    */
+  int n_gmres_last;
+  long long n_solv;        /* RHS solves: r1 * n_ss * n_gmres (x2 complex pencils)  */
+  long long n_refine;      /* extra FP32 solves (mixed)                             */
+  int n_found;
+  double max_resid;        /* spec residual over returned pairs               */
+  double e_lambda_x;       /* eq. (relerr)                                          */
+  double b_orth;           /* max |X^H B X - I|                                     */
+  double t_plan, t_symbolic, t_factor, t_iter, t_total;   /* seconds              */
+  double gmres_resid;      /* worst final LS residual                               */
+  double norm_a, norm_b;   /* infinity norms used in the residual                   */
+  int r1, r2;
+  double l1, l2, delta0;
+  long long factor_bytes;  /* device bytes of all factors                           */
+  long long nnz_l;         /* entries of one factor (panel + diagonal-block inverse) */
+  double factor_flops;     /* per pole                                              */
+} zolo_stats;
+
+typedef struct zolo_ctx zolo_ctx;
+typedef struct zolo_pencil zolo_pencil;
+typedef struct zolo_factors zolo_factors;
+typedef struct zolo_result zolo_result;
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* zolo_last_error(void);
+const char* zolo_version(void);
+
+/* Defaults: r1 = 2, r2 = 0 (auto), filter_eps = 1e-10, tol_resid = 1e-8,
+ * tol_gmres = 1e-10, max_subspace_iter = 6, max_gmres_iter = 60, FP64. */
+zolo_status zolo_opts_default(zolo_opts* out);
+
+/* Context on one HIP device: selects the device, creates nothing else. */
+zolo_status zolo_ctx_create(int hip_device, zolo_ctx** out);
+void zolo_ctx_destroy(zolo_ctx* ctx);
+
+/*
+ * Upload a pencil (host CSR) and run nested dissection + symbolic analysis on
+ * the host (multifrontal method, Sec. 2.3: the pre-factorization phase).
+ * grid (may be NULL): {nx, ny, nz} when the rows are the points x + nx*y +
+ * nx*ny*z of a box grid whose stencil couples only neighbours within distance
+ * one; then separators are grid planes.  Otherwise a graph bisection by
+ * breadth-first level structures is used.  leaf_size: largest subdomain
+ * left undissected (0 = default 64).
+ * Errors: ZOLO_EINVAL (bad CSR), ZOLO_ENOTHERM (A or B not Hermitian).
+ */
+zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                               const void* a_vals, const void* b_vals, int scalar, const int32_t* grid,
+                               int leaf_size, zolo_pencil** out);
+void zolo_pencil_free(zolo_pencil* p);
+/* Symbolic figures: fronts, levels, entries of one factor, flops per pole. */
+zolo_status zolo_pencil_info(const zolo_pencil* p, int64_t* n_fronts, int64_t* n_levels, int64_t* nnz_l,
+                             double* flops_per_pole, int64_t* max_front);
+/*
+ * Host only (no device needed): nested dissection + symbolic analysis of a
+ * CSR pattern, as zolo_pencil_create runs it.  perm (may be NULL): n entries,
+ * perm[new] = old.  info (may be NULL): 8 entries = {fronts, levels,
+ * panel entries (sum k*ns), inverse entries (sum ns^2), update entries
+ * (sum nb^2), largest front, struct entries (sum nb), flops per pole}.
+ */
+zolo_status zolo_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* grid, int leaf_size,
+                          int32_t* perm, double* info);
+/* Nested-dissection permutation: perm[new] = old (host array of n). */
+zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm);
+
+/*
+ * Filter coefficients from the eigengaps (Algorithm 2, lines 2-4): Moebius
+ * map, inner Zhat_2r1(.; l1) poles/weights, l2 and the outer Z_2r2(.; l2).
+ * r2 == 0 selects the smallest r2 <= 16 with delta0 <= eps (Remark).
+ * Host only.  Errors: ZOLO_EINVAL (gaps not ordered, r out of range).
+ */
+zolo_status zolo_filter_plan(double a_minus, double a_plus, double b_minus, double b_plus, int r1, int r2,
+                             double eps, zolo_filter_coeffs* out);
+
+/*
+ * Numeric factorization of K_j = A - sigma_hat_j B, j = 1..r1 (Algorithm 2,
+ * lines 5-6), as complex-symmetric LDL^T on the device (real pencils).
+ * precision ZOLO_PREC_MIXED stores complex64 factors.
+ * Errors: ZOLO_EBREAKDOWN (zero pivot), ZOLO_ENOMEM, ZOLO_EDEVICE.
+ */
+zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* p, const zolo_filter_coeffs* co, int precision,
+                        void* stream, zolo_factors** out);
+void zolo_factors_free(zolo_factors* f);
+
+/* d_Y = A d_X or B d_X (which = 0 for A, 1 for B); real pencils: double,
+ * N x p row-major blocks in the ORIGINAL ordering. */
+zolo_status zolo_spmm(zolo_pencil* p, int which, const void* d_X, int64_t ldx, int ncols, void* d_Y, int64_t ldy,
+                      void* stream);
+
+/* d_X (complex128, N x p) = K_j^-1 d_T for pole j (0-based), d_T real N x p
+ * (real pencils).  Original ordering.  In mixed precision the FP32 factor is
+ * refined against FP64 residuals until tol_refine (opts of the factors). */
+zolo_status zolo_pole_solve(zolo_factors* f, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
+                            int64_t ldx, void* stream);
+
+/* d_W = G d_V with G = Zhat(T(B^-1 A); l1) applied through the factors
+ * (eq. solve).  Real pencils, original ordering. */
+zolo_status zolo_apply_G(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_W, int64_t ldw,
+                         void* stream);
+
+/* Per-call statistics of zolo_filter_apply. */
+typedef struct {
+  int n_gmres;             /* block GMRES steps                                  */
+  double worst_resid;      /* max over shifts and columns of the relative LS residual */
+  int breakdown;           /* 1 if the block Krylov space was exhausted          */
+} zolo_filter_stats;
+
+/*
+ * d_Y = R_ab(B^-1 A) d_V (Algorithm 2, lines 8-9): multi-shift block GMRES
+ * on G with the outer shifts +- i sqrt(c_j), then Y = V/2 + (M/2) sum_j
+ * a_j Re((G + i sqrt c_j)^-1 V).  Real pencils.  tol_gmres <= 0 and
+ * max_iter <= 0 take the defaults.  Returns ZOLO_ENOCONV (with d_Y filled
+ * by the best iterate) if max_iter steps do not reach tol_gmres.
+ */
+zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_Y,
+                              int64_t ldy, double tol_gmres, int max_iter, zolo_filter_stats* st, void* stream);
+
+/*
+ * Eigenpairs of (A, B) in (a, b) (Algorithm 1 with Algorithm 2).
+ * n_lambda_est: estimated count (footnote of Sec. 1); opts may be NULL.
+ * d_Q0 (may be NULL): N x n_ss start block (row-major, ld n_ss) in the
+ * original ordering; NULL draws a Gaussian block from opts->seed.
+ * The result holds Ritz pairs with a < theta < b and residual <= tol_resid.
+ * Errors: ZOLO_ENOCONV (best results and stats still filled),
+ * ZOLO_ESUBSPACE (found >= n_ss - 1), ZOLO_EINVAL.
+ */
+zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* p, double a, double b, int n_lambda_est, const zolo_opts* opts,
+                       const double* d_Q0, void* stream, zolo_result** out);
+int64_t zolo_result_count(const zolo_result* r);
+/* ascending eigenvalues, host array of zolo_result_count entries, owned by r */
+const double* zolo_result_eigenvalues(const zolo_result* r);
+/* copy the B-orthonormal eigenvectors (N x count, row-major, ld) to a device buffer */
+zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_dst, int64_t ld, void* stream);
+zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out);
+void zolo_result_free(zolo_result* r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZOLO_H */

@@ -1,0 +1,309 @@
+"""Thin Python binding of libzolo.so (the MI355X Zolotarev spectrum-filter eigensolver).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels and host C++ code.  PyTorch supplies device memory (tensors on the
+GPU, passed by ``data_ptr()``) and the current HIP stream.  The names follow
+``include/zolo.h``; the library raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzolo.so")
+
+ZOLO_OK, ZOLO_EINVAL, ZOLO_ENOTHERM, ZOLO_ENOMEM, ZOLO_ENOCONV = 0, 1, 2, 3, 4
+ZOLO_EGAP, ZOLO_ESUBSPACE, ZOLO_EDEVICE, ZOLO_EBREAKDOWN = 5, 6, 7, 8
+ZOLO_REAL64, ZOLO_COMPLEX128 = 0, 1
+ZOLO_PREC_FP64, ZOLO_PREC_MIXED = 0, 1
+ZOLO_MAX_R = 16
+STATUS_NAMES = {0: "ZOLO_OK", 1: "ZOLO_EINVAL", 2: "ZOLO_ENOTHERM", 3: "ZOLO_ENOMEM", 4: "ZOLO_ENOCONV",
+                5: "ZOLO_EGAP", 6: "ZOLO_ESUBSPACE", 7: "ZOLO_EDEVICE", 8: "ZOLO_EBREAKDOWN"}
+
+_R = ZOLO_MAX_R
+_d = ctypes.c_double
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+
+
+class zolo_filter_coeffs(ctypes.Structure):
+    _fields_ = [("r1", _i), ("r2", _i), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d),
+                ("l1", _d), ("l2", _d), ("alpha", _d), ("beta", _d), ("gamma", _d), ("M_hat", _d), ("c0", _d),
+                ("delta1", _d), ("sigma_hat_re", _d * _R), ("sigma_hat_im", _d * _R), ("w_hat_re", _d * _R),
+                ("w_hat_im", _d * _R), ("a_hat", _d * _R), ("c_hat", _d * _R), ("M", _d), ("a", _d * _R),
+                ("c", _d * _R), ("delta_S", _d), ("delta0", _d)]
+
+
+class zolo_opts(ctypes.Structure):
+    _fields_ = [("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d), ("r1", _i), ("r2", _i),
+                ("filter_eps", _d), ("n_ss", _i), ("max_subspace_iter", _i), ("max_gmres_iter", _i),
+                ("tol_resid", _d), ("tol_gmres", _d), ("precision", _i), ("seed", ctypes.c_uint64),
+                ("max_refine", _i), ("tol_refine", _d)]
+
+
+class zolo_stats(ctypes.Structure):
+    _fields_ = [("n_iter", _i), ("n_gmres_total", _i), ("n_gmres_last", _i), ("n_solv", ctypes.c_longlong),
+                ("n_refine", ctypes.c_longlong), ("n_found", _i), ("max_resid", _d), ("e_lambda_x", _d),
+                ("b_orth", _d), ("t_plan", _d), ("t_symbolic", _d), ("t_factor", _d), ("t_iter", _d),
+                ("t_total", _d), ("gmres_resid", _d), ("norm_a", _d), ("norm_b", _d), ("r1", _i), ("r2", _i),
+                ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
+                ("nnz_l", ctypes.c_longlong), ("factor_flops", _d)]
+
+
+class zolo_filter_stats(ctypes.Structure):
+    _fields_ = [("n_gmres", _i), ("worst_resid", _d), ("breakdown", _i)]
+
+
+def struct_dict(s) -> dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = list(v) if hasattr(v, "__len__") else v
+    return out
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "zolo_last_error": (ctypes.c_char_p, []),
+    "zolo_version": (ctypes.c_char_p, []),
+    "zolo_opts_default": (_i, [ctypes.POINTER(zolo_opts)]),
+    "zolo_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
+    "zolo_ctx_destroy": (None, [_vp]),
+    "zolo_pencil_create": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _i, _vp, _i, ctypes.POINTER(_vp)]),
+    "zolo_pencil_free": (None, [_vp]),
+    "zolo_pencil_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                              ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
+    "zolo_pencil_perm": (_i, [_vp, _vp]),
+    "zolo_symbolic": (_i, [_i64, _vp, _vp, _vp, _i, _vp, _vp]),
+    "zolo_filter_plan": (_i, [_d, _d, _d, _d, _i, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
+    "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
+    "zolo_factors_free": (None, [_vp]),
+    "zolo_spmm": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
+    "zolo_pole_solve": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
+    "zolo_apply_G": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _vp]),
+    "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
+    "zolo_solve": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, _vp, ctypes.POINTER(_vp)]),
+    "zolo_result_count": (_i64, [_vp]),
+    "zolo_result_eigenvalues": (ctypes.POINTER(_d), [_vp]),
+    "zolo_result_copy_vectors": (_i, [_vp, _vp, _i64, _vp]),
+    "zolo_result_stats": (_i, [_vp, ctypes.POINTER(zolo_stats)]),
+    "zolo_result_free": (None, [_vp]),
+}
+
+
+class ZoloError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libzolo.so; raises if the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1701_08935_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, allow=()):
+    if rc != ZOLO_OK and rc not in allow:
+        raise ZoloError(rc, lib().zolo_last_error().decode())
+    return rc
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+def zolo_filter_plan(a_minus, a_plus, b_minus, b_plus, r1, r2=0, eps=1e-10) -> zolo_filter_coeffs:
+    co = zolo_filter_coeffs()
+    _check(lib().zolo_filter_plan(float(a_minus), float(a_plus), float(b_minus), float(b_plus), int(r1), int(r2),
+                                  float(eps), ctypes.byref(co)))
+    return co
+
+
+def zolo_opts_default() -> zolo_opts:
+    o = zolo_opts()
+    _check(lib().zolo_opts_default(ctypes.byref(o)))
+    return o
+
+
+def zolo_symbolic(rowptr, colind, grid=None, leaf_size=0):
+    import numpy as np
+
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    colind = np.ascontiguousarray(colind, dtype=np.int32)
+    n = rowptr.shape[0] - 1
+    perm = np.empty(n, dtype=np.int32)
+    info = np.empty(8, dtype=np.float64)
+    g = None if grid is None else np.ascontiguousarray(grid, dtype=np.int32)
+    _check(lib().zolo_symbolic(n, _np_ptr(rowptr), _np_ptr(colind), None if g is None else _np_ptr(g),
+                               int(leaf_size), _np_ptr(perm), _np_ptr(info)))
+    keys = ["fronts", "levels", "panel_entries", "inv_entries", "update_entries", "max_front", "struct_entries",
+            "flops"]
+    return perm, dict(zip(keys, info.tolist()))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(lib().zolo_ctx_create(int(device), ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zolo_ctx_destroy(self.h)
+            self.h = None
+
+
+class Pencil:
+    """zolo_pencil_create on host CSR arrays (numpy)."""
+
+    def __init__(self, ctx: Context, rowptr, colind, a_vals, b_vals, grid=None, leaf_size=0):
+        import numpy as np
+
+        self.ctx = ctx
+        self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+        self._colind = np.ascontiguousarray(colind, dtype=np.int32)
+        self._a = np.ascontiguousarray(a_vals, dtype=np.float64)
+        self._b = np.ascontiguousarray(b_vals, dtype=np.float64)
+        self.n = self._rowptr.shape[0] - 1
+        g = None if grid is None else np.ascontiguousarray(grid, dtype=np.int32)
+        h = _vp()
+        _check(lib().zolo_pencil_create(ctx.h, self.n, _np_ptr(self._rowptr), _np_ptr(self._colind), _np_ptr(self._a),
+                                        _np_ptr(self._b), ZOLO_REAL64, None if g is None else _np_ptr(g),
+                                        int(leaf_size), ctypes.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_grid(cls, ctx, gp, leaf_size=0, use_grid=True):
+        return cls(ctx, gp.rowptr, gp.colind, gp.a_vals, gp.b_vals, gp.grid if use_grid else None, leaf_size)
+
+    def info(self):
+        nf, nl, nnz, mf = _i64(), _i64(), _i64(), _i64()
+        fl = _d()
+        _check(lib().zolo_pencil_info(self.h, ctypes.byref(nf), ctypes.byref(nl), ctypes.byref(nnz), ctypes.byref(fl),
+                                      ctypes.byref(mf)))
+        return {"fronts": nf.value, "levels": nl.value, "nnz_l": nnz.value, "flops": fl.value, "max_front": mf.value}
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zolo_pencil_free(self.h)
+            self.h = None
+
+
+class Factors:
+    """zolo_factor: LDL^T of A - sigma_hat_j B for j = 1..r1."""
+
+    def __init__(self, ctx: Context, pencil: Pencil, coeffs: zolo_filter_coeffs, precision=ZOLO_PREC_FP64):
+        h = _vp()
+        self.pencil = pencil
+        self.coeffs = coeffs
+        _check(lib().zolo_factor(ctx.h, pencil.h, ctypes.byref(coeffs), int(precision), _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zolo_factors_free(self.h)
+            self.h = None
+
+
+def zolo_spmm(pencil: Pencil, which: int, X):
+    import torch
+
+    Y = torch.empty_like(X)
+    _check(lib().zolo_spmm(pencil.h, int(which), _ptr(X), X.stride(0), X.shape[1], _ptr(Y), Y.stride(0), _stream()))
+    return Y
+
+
+def zolo_pole_solve(f: Factors, j: int, T):
+    import torch
+
+    X = torch.empty(T.shape, dtype=torch.complex128, device=T.device)
+    _check(lib().zolo_pole_solve(f.h, int(j), _ptr(T), T.stride(0), T.shape[1], _ptr(X), X.stride(0), _stream()))
+    return X
+
+
+def zolo_apply_G(f: Factors, V):
+    import torch
+
+    W = torch.empty_like(V)
+    _check(lib().zolo_apply_G(f.h, _ptr(V), V.stride(0), V.shape[1], _ptr(W), W.stride(0), _stream()))
+    return W
+
+
+def zolo_filter_apply(f: Factors, V, tol=1e-10, max_iter=60, allow_noconv=False):
+    import torch
+
+    Y = torch.empty_like(V)
+    st = zolo_filter_stats()
+    _check(lib().zolo_filter_apply(f.h, _ptr(V), V.stride(0), V.shape[1], _ptr(Y), Y.stride(0), float(tol),
+                                   int(max_iter), ctypes.byref(st), _stream()),
+           allow=(ZOLO_ENOCONV,) if allow_noconv else ())
+    return Y, struct_dict(st)
+
+
+def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None,
+               allow=(ZOLO_ENOCONV,)):
+    """Returns (eigenvalues list, vectors tensor N x count (device), stats dict, status)."""
+    import torch
+
+    if opts is None:
+        opts = zolo_opts_default()
+    h = _vp()
+    rc = lib().zolo_solve(ctx.h, pencil.h, float(a), float(b), int(n_lambda_est), ctypes.byref(opts),
+                          None if Q0 is None else _ptr(Q0), _stream(), ctypes.byref(h))
+    if rc != ZOLO_OK and (rc not in allow or not h):
+        raise ZoloError(rc, lib().zolo_last_error().decode())
+    try:
+        L = lib()
+        cnt = L.zolo_result_count(h)
+        ev = L.zolo_result_eigenvalues(h)
+        eig = [ev[i] for i in range(cnt)]
+        vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.float64, device=f"cuda:{ctx.device}")
+        if cnt:
+            _check(L.zolo_result_copy_vectors(h, _ptr(vec), vec.stride(0), _stream()))
+        st = zolo_stats()
+        _check(L.zolo_result_stats(h, ctypes.byref(st)))
+    finally:
+        lib().zolo_result_free(h)
+    return eig, vec[:, :cnt], struct_dict(st), rc
+
+
+def opts_from_window(w: dict, r1=2, r2=0, n_ss=0, precision=ZOLO_PREC_FP64, **kw) -> zolo_opts:
+    o = zolo_opts_default()
+    o.a_minus = w["a_minus"] if math.isfinite(w["a_minus"]) else -math.inf
+    o.a_plus = w["a_plus"]
+    o.b_minus = w["b_minus"]
+    o.b_plus = w["b_plus"] if math.isfinite(w["b_plus"]) else math.inf
+    o.r1 = r1
+    o.r2 = r2
+    o.n_ss = n_ss
+    o.precision = precision
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o

@@ -1,0 +1,1650 @@
+// C ABI and host orchestration of the hot path on one GPU.
+//
+//   zolo_pencil_create : CSR upload + nested dissection + symbolic analysis
+//   zolo_factor        : numeric LDL^T of K_j = A - sigma_hat_j B (Algorithm 2, lines 5-6)
+//   zolo_apply_G       : G V of eq. (solve)
+//   zolo_filter_apply  : multi-shift block GMRES on G + weighted sum (Algorithm 2, lines 8-9)
+//   zolo_solve         : Algorithm 1 (subspace iteration + Rayleigh-Ritz)
+//
+// Internally every N x p block lives in the nested-dissection ordering, so a
+// front's own rows are contiguous; blocks are permuted at the ABI boundary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "front.h"
+#include "gemm.h"
+#include "krylov.h"
+#include "sparse.h"
+#include "zolo_internal.h"
+
+using namespace zolo;
+
+namespace zolo {
+static thread_local std::string g_err;
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+}  // namespace zolo
+
+#define HIPC(x)                                                                     \
+  do {                                                                              \
+    hipError_t e_ = (x);                                                            \
+    if (e_ != hipSuccess) {                                                         \
+      zolo::set_error("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return ZOLO_EDEVICE;                                                          \
+    }                                                                               \
+  } while (0)
+
+#define CHK(x)                  \
+  do {                          \
+    int rc_ = (x);              \
+    if (rc_ != ZOLO_OK) return (zolo_status)rc_; \
+  } while (0)
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// RAII owner of device allocations
+struct DevArena {
+  std::vector<void*> ptrs;
+  ~DevArena() { release(); }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  template <typename T>
+  int alloc(T** out, size_t count) {
+    void* p = nullptr;
+    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+      return ZOLO_ENOMEM;
+    }
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return ZOLO_OK;
+  }
+  template <typename T>
+  int upload(T** out, const T* host, size_t count) {
+    CHK(alloc(out, count));
+    if (count) {
+      hipError_t e = hipMemcpy(*out, host, count * sizeof(T), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        set_error("hipMemcpy failed: %s", hipGetErrorString(e));
+        return ZOLO_EDEVICE;
+      }
+    }
+    return ZOLO_OK;
+  }
+};
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// splitmix64 + Box-Muller Gaussian start block (used when none is passed in)
+void gaussian_host(uint64_t seed, size_t n, std::vector<double>* out) {
+  out->resize(n);
+  uint64_t x = seed * 0x9E3779B97F4A7C15ULL + 0x1234567ULL;
+  auto next = [&x]() {
+    uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  };
+  for (size_t i = 0; i < n; i += 2) {
+    double u1 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double u2 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    double r = std::sqrt(-2.0 * std::log(u1));
+    (*out)[i] = r * std::cos(2.0 * M_PI * u2);
+    if (i + 1 < n) (*out)[i + 1] = r * std::sin(2.0 * M_PI * u2);
+  }
+}
+
+struct GemmLaunch {
+  int off = 0, cnt = 0, tiles = 0;
+};
+
+}  // namespace
+
+// ===========================================================================
+// handles
+// ===========================================================================
+struct zolo_ctx {
+  int device = 0;
+};
+
+struct zolo_pencil {
+  zolo_ctx* ctx = nullptr;
+  int64_t n = 0, nnz = 0;
+  int scalar = 0;
+  Symbolic S;
+  DevArena mem;
+  int64_t* prow = nullptr;
+  int32_t* pcol = nullptr;
+  double* pa = nullptr;
+  double* pb = nullptr;
+  int32_t* perm = nullptr;   // perm[new] = old
+  int32_t* iperm = nullptr;  // iperm[old] = new
+  int32_t* struct_rows = nullptr;
+  int32_t* pmap = nullptr;
+  double normA = 0.0, normB = 0.0;
+  double t_symbolic = 0.0;
+  // sigma-independent numeric layout
+  std::vector<int> lvl_order;       // fronts ordered by level
+  std::vector<int64_t> panel_off, inv_off, upd_off;
+  std::vector<int64_t> lvl_panel_begin, lvl_panel_end, lvl_inv_begin, lvl_inv_end, lvl_upd_begin, lvl_upd_end;
+  int64_t panel_total = 0, inv_total = 0, upd_total = 0;
+  int64_t* asm_dst = nullptr;
+  int64_t* asm_src = nullptr;
+  std::vector<int64_t> lvl_asm_begin, lvl_asm_end;
+  ExtDesc* ext = nullptr;
+  std::vector<std::vector<GemmLaunch>> lvl_ext;  // per level per slot: off/cnt/max_nb (tiles)
+  DiagDesc* diag = nullptr;
+  std::vector<int> lvl_diag_off, lvl_diag_cnt;
+  std::vector<std::vector<int>> lvl_diag_nJ, lvl_trsm_rows;  // per level per step
+  int64_t inv_scratch = 0;  // FB x ns per front of a level (L11 inverse temporaries)
+};
+
+template <typename T>
+struct PoleMF {
+  T* panel = nullptr;
+  T* inv = nullptr;
+  T* dvec = nullptr;
+};
+
+template <typename T>
+struct SolveProg {
+  int p = 0;
+  DevArena mem;
+  T* W = nullptr;
+  T* U = nullptr;
+  T* Xb = nullptr;
+  T* tb = nullptr;
+  T* Y = nullptr;
+  T* X = nullptr;
+  SolveDesc* sd = nullptr;
+  SolveExt* se = nullptr;
+  std::vector<int> lvl_sd_off, lvl_sd_cnt, lvl_maxk, lvl_maxnb;
+  std::vector<std::vector<GemmLaunch>> lvl_se;  // per slot (tiles = max nb)
+  // per pole: GEMM descriptors and launches
+  std::vector<GemmDesc<T>*> gd;
+  std::vector<std::vector<GemmLaunch>> f2, f3, b2, b3;  // [pole][level]
+};
+
+struct Workspace {
+  DevArena mem;
+  int p = 0, mmax = 0, nshift = 0;
+  int64_t n = 0;
+  double* Vb = nullptr;   // N x Mp
+  double* W = nullptr;    // N x p
+  double* T1 = nullptr;   // N x p
+  double* Tb = nullptr;   // N x p (B V)
+  zd* Xc = nullptr;       // N x p complex (pole solution)
+  zd* Rc = nullptr;       // N x p complex (refinement residual)
+  zd* Dc = nullptr;       // N x p complex (refinement correction)
+  double* H = nullptr;    // ldh x mmax p
+  int64_t ldh = 0;
+  double* hbuf = nullptr; // (mmax+1)p x p
+  double* partial = nullptr;
+  int64_t partial_len = 0;
+  double* G = nullptr;    // p x p
+  double* R1 = nullptr;
+  double* R1i = nullptr;
+  double* R2 = nullptr;
+  double* R2i = nullptr;
+  double* R0 = nullptr;
+  double* Rk = nullptr;
+  int* flag = nullptr;
+  double* res = nullptr;  // nshift x p
+  double* coef = nullptr;
+  double* shift_im = nullptr;
+  double* Cm = nullptr;   // mmax p x p
+  zd* Ys = nullptr;       // nshift x (mmax p) x p
+  HlsState hls{};
+  GemmDesc<double>* gdesc = nullptr;
+  int gdesc_cap = 0;
+  double* cn_partial = nullptr;
+  double* cn_out = nullptr;
+};
+
+struct zolo_factors {
+  zolo_pencil* P = nullptr;
+  zolo_filter_coeffs co{};
+  int precision = 0;
+  DevArena mem;
+  std::vector<PoleMF<zd>> pd;
+  std::vector<PoleMF<zf>> pf;
+  std::map<int, std::unique_ptr<SolveProg<zd>>> prog_d;
+  std::map<int, std::unique_ptr<SolveProg<zf>>> prog_f;
+  std::unique_ptr<Workspace> ws;
+  double t_factor = 0.0;
+  int max_refine = 8;
+  double tol_refine = 1e-13;
+  long long n_refine = 0;
+  long long n_solv = 0;
+  int64_t bytes = 0;
+};
+
+struct zolo_result {
+  int64_t n = 0, count = 0;
+  std::vector<double> eig;
+  DevArena mem;
+  double* vec = nullptr;  // N x count row-major, original ordering
+  zolo_stats st{};
+};
+
+// ===========================================================================
+// small helpers
+// ===========================================================================
+namespace {
+
+template <typename T>
+int upload_gemm(DevArena& mem, const std::vector<GemmDesc<T>>& h, GemmDesc<T>** d) {
+  return mem.upload(d, h.data(), h.size());
+}
+
+template <typename T>
+void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s) {
+  if (L.cnt > 0 && L.tiles > 0) gemm_batched<T>(base + L.off, L.cnt, L.tiles, s);
+}
+
+// out (m x n, col-major ld ldo) [+]= X^T Y with X: N x m row-major (ld ldx), Y: N x n row-major (ld ldy)
+int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t N, int m, int n,
+            double* out, int64_t ldo, bool add, hipStream_t s) {
+  int tiles = gemm_tiles<double>(m, n);
+  int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
+  while (S * (int64_t)m * n > ws.partial_len && S > 1) S /= 2;
+  if (S * (int64_t)m * n > ws.partial_len) {
+    set_error("gemm_tn: partial buffer too small");
+    return ZOLO_ENOMEM;
+  }
+  if (S > ws.gdesc_cap) S = ws.gdesc_cap;
+  int64_t chunk = (N + S - 1) / S;
+  std::vector<GemmDesc<double>> h;
+  for (int64_t q = 0; q < S; ++q) {
+    int64_t r0 = q * chunk;
+    if (r0 >= N) break;
+    GemmDesc<double> d{};
+    d.A = X + r0 * ldx;
+    d.lda = ldx;
+    d.B = Y + r0 * ldy;
+    d.ldb = ldy;
+    d.C = ws.partial + (int64_t)h.size() * m * n;
+    d.ldc = m;
+    d.M = m;
+    d.N = n;
+    d.K = (int)std::min<int64_t>(chunk, N - r0);
+    d.flags = GF_TRANSB;
+    d.alpha = 1.0;
+    d.beta = 0.0;
+    h.push_back(d);
+  }
+  HIPC(hipMemcpyAsync(ws.gdesc, h.data(), h.size() * sizeof(GemmDesc<double>), hipMemcpyHostToDevice, s));
+  gemm_batched<double>(ws.gdesc, (int)h.size(), tiles, s);
+  reduce_partials(out, ldo, ws.partial, (int)h.size(), m, n, add, s);
+  HIPC(hipStreamSynchronize(s));  // h is host memory
+  return ZOLO_OK;
+}
+
+// C^T (p x N col-major view of row-major C, ld ldc) = beta C^T + alpha opA(Msmall) Bv^T
+// Used for W -= V h and V_new = W R^-1 style updates: C_rm = beta C_rm + alpha Bv_rm opA^T
+int gemm_nt_big(Workspace& ws, double* C, int64_t ldc, const double* Cin, int64_t ldcin, double beta, double alpha,
+                const double* Msmall, int64_t ldm, bool transM, const double* Bv, int64_t ldb, int64_t N, int p, int K,
+                hipStream_t s) {
+  GemmDesc<double> d{};
+  d.C = C;
+  d.ldc = ldc;
+  d.Cin = Cin;
+  d.ldcin = ldcin;
+  d.beta = beta;
+  d.alpha = alpha;
+  d.A = Msmall;
+  d.lda = ldm;
+  d.flags = transM ? GF_TRANSA : 0;
+  d.B = Bv;
+  d.ldb = ldb;
+  d.M = p;
+  d.N = (int)N;
+  d.K = K;
+  HIPC(hipMemcpyAsync(ws.gdesc + ws.gdesc_cap, &d, sizeof(d), hipMemcpyHostToDevice, s));
+  gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, gemm_tiles<double>(p, (int)N), s);
+  HIPC(hipStreamSynchronize(s));
+  return ZOLO_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// pencil
+// ===========================================================================
+extern "C" const char* zolo_last_error(void) { return zolo::g_err.c_str(); }
+extern "C" const char* zolo_version(void) { return "zolo-mi355x 0.1"; }
+
+extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
+  if (!o) {
+    set_error("null opts");
+    return ZOLO_EINVAL;
+  }
+  std::memset(o, 0, sizeof(*o));
+  o->a_minus = o->a_plus = o->b_minus = o->b_plus = NAN;
+  o->r1 = 2;
+  o->r2 = 0;
+  o->filter_eps = 1e-10;
+  o->n_ss = 0;
+  o->max_subspace_iter = 6;
+  o->max_gmres_iter = 60;
+  o->tol_resid = 1e-8;
+  o->tol_gmres = 1e-10;
+  o->precision = ZOLO_PREC_FP64;
+  o->seed = 2;
+  o->max_refine = 8;
+  o->tol_refine = 1e-13;
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_ctx_create(int dev, zolo_ctx** out) {
+  if (!out) {
+    set_error("null output");
+    return ZOLO_EINVAL;
+  }
+  int nd = 0;
+  HIPC(hipGetDeviceCount(&nd));
+  if (dev < 0 || dev >= nd) {
+    set_error("device %d out of range (%d devices)", dev, nd);
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(dev));
+  auto* c = new zolo_ctx();
+  c->device = dev;
+  *out = c;
+  return ZOLO_OK;
+}
+
+extern "C" void zolo_ctx_destroy(zolo_ctx* c) { delete c; }
+
+static zolo_status build_layout(zolo_pencil* P) {
+  const Symbolic& S = P->S;
+  const int nf = (int)S.fronts.size();
+  const int nl = (int)S.levels.size();
+  P->panel_off.assign(nf, 0);
+  P->inv_off.assign(nf, 0);
+  P->upd_off.assign(nf, 0);
+  P->lvl_order.clear();
+  P->lvl_panel_begin.assign(nl, 0);
+  P->lvl_panel_end.assign(nl, 0);
+  P->lvl_inv_begin.assign(nl, 0);
+  P->lvl_inv_end.assign(nl, 0);
+  P->lvl_upd_begin.assign(nl, 0);
+  P->lvl_upd_end.assign(nl, 0);
+  int64_t po = 0, io = 0, uo = 0;
+  P->inv_scratch = 0;
+  for (int L = 0; L < nl; ++L) {
+    P->lvl_panel_begin[L] = po;
+    P->lvl_inv_begin[L] = io;
+    P->lvl_upd_begin[L] = uo;
+    int64_t scr = 0;
+    for (int f : S.levels[L]) {
+      const Front& F = S.fronts[f];
+      int64_t k = (int64_t)F.ns + F.nb;
+      P->panel_off[f] = po;
+      po += k * F.ns;
+      P->inv_off[f] = io;
+      io += (int64_t)F.ns * F.ns;
+      P->upd_off[f] = uo;
+      uo += (int64_t)F.nb * F.nb;
+      scr += (int64_t)FB * F.ns;
+      P->lvl_order.push_back(f);
+    }
+    P->inv_scratch = std::max(P->inv_scratch, scr);
+    P->lvl_panel_end[L] = po;
+    P->lvl_inv_end[L] = io;
+    P->lvl_upd_end[L] = uo;
+  }
+  P->panel_total = po;
+  P->inv_total = io;
+  P->upd_total = uo;
+  // assembly lists in level order
+  std::vector<int64_t> dst, src;
+  P->lvl_asm_begin.assign(nl, 0);
+  P->lvl_asm_end.assign(nl, 0);
+  for (int L = 0; L < nl; ++L) {
+    P->lvl_asm_begin[L] = (int64_t)dst.size();
+    for (int f : S.levels[L]) {
+      const Front& F = S.fronts[f];
+      for (int64_t e = F.asm_begin; e < F.asm_end; ++e) {
+        dst.push_back(P->panel_off[f] + S.asm_pos[e]);
+        src.push_back(S.asm_entry[e]);
+      }
+    }
+    P->lvl_asm_end[L] = (int64_t)dst.size();
+  }
+  CHK(P->mem.upload(&P->asm_dst, dst.data(), dst.size()));
+  CHK(P->mem.upload(&P->asm_src, src.data(), src.size()));
+  // extend-add descriptors: per parent level, per child slot
+  std::vector<ExtDesc> ext;
+  P->lvl_ext.assign(nl, {});
+  for (int L = 0; L < nl; ++L) {
+    int maxc = 0;
+    for (int f : S.levels[L]) maxc = std::max(maxc, S.fronts[f].child_count);
+    for (int slot = 0; slot < maxc; ++slot) {
+      GemmLaunch g;
+      g.off = (int)ext.size();
+      int maxnb = 0;
+      for (int f : S.levels[L]) {
+        const Front& F = S.fronts[f];
+        if (slot >= F.child_count) continue;
+        int c = S.children[F.child_begin + slot];
+        const Front& C = S.fronts[c];
+        if (C.nb == 0) continue;
+        ExtDesc d{};
+        d.child_upd = P->upd_off[c];
+        d.pmap = C.struct_off;
+        d.par_panel = P->panel_off[f];
+        d.par_upd = P->upd_off[f];
+        d.nb_c = C.nb;
+        d.k_p = F.ns + F.nb;
+        d.ns_p = F.ns;
+        ext.push_back(d);
+        maxnb = std::max(maxnb, C.nb);
+      }
+      g.cnt = (int)ext.size() - g.off;
+      g.tiles = maxnb;
+      P->lvl_ext[L].push_back(g);
+    }
+  }
+  CHK(P->mem.upload(&P->ext, ext.data(), ext.size()));
+  // diagonal-block descriptors, per level sorted by ns descending
+  std::vector<DiagDesc> dg;
+  P->lvl_diag_off.assign(nl, 0);
+  P->lvl_diag_cnt.assign(nl, 0);
+  P->lvl_diag_nJ.assign(nl, {});
+  P->lvl_trsm_rows.assign(nl, {});
+  for (int L = 0; L < nl; ++L) {
+    std::vector<int> fs = S.levels[L];
+    std::stable_sort(fs.begin(), fs.end(), [&](int a, int b) { return S.fronts[a].ns > S.fronts[b].ns; });
+    P->lvl_diag_off[L] = (int)dg.size();
+    int maxns = 0;
+    for (int f : fs) {
+      const Front& F = S.fronts[f];
+      DiagDesc d{};
+      d.panel = P->panel_off[f];
+      d.inv = P->inv_off[f];
+      d.k = F.ns + F.nb;
+      d.ns = F.ns;
+      d.first = F.first;
+      dg.push_back(d);
+      maxns = std::max(maxns, F.ns);
+    }
+    P->lvl_diag_cnt[L] = (int)fs.size();
+    for (int J = 0; J < maxns; J += FB) {
+      int cnt = 0, rows = 0;
+      for (int f : fs) {
+        const Front& F = S.fronts[f];
+        if (F.ns <= J) break;
+        ++cnt;
+        int jb = std::min(FB, F.ns - J);
+        rows = std::max(rows, F.ns + F.nb - J - jb);
+      }
+      P->lvl_diag_nJ[L].push_back(cnt);
+      P->lvl_trsm_rows[L].push_back(rows);
+    }
+  }
+  CHK(P->mem.upload(&P->diag, dg.data(), dg.size()));
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                                          const void* a_vals, const void* b_vals, int scalar, const int32_t* grid,
+                                          int leaf_size, zolo_pencil** out) {
+  if (!ctx || !rowptr || !colind || !a_vals || !b_vals || !out || n <= 0) {
+    set_error("zolo_pencil_create: null argument or n <= 0");
+    return ZOLO_EINVAL;
+  }
+  if (scalar != ZOLO_REAL64) {
+    set_error("zolo_pencil_create: only real (ZOLO_REAL64) pencils are supported by this build");
+    return ZOLO_EINVAL;
+  }
+  if (n > INT32_MAX) {
+    set_error("n too large");
+    return ZOLO_EINVAL;
+  }
+  const int64_t nnz = rowptr[n];
+  if (rowptr[0] != 0 || nnz < n) {
+    set_error("CSR: rowptr[0] must be 0 and the diagonal stored");
+    return ZOLO_EINVAL;
+  }
+  const double* a = (const double*)a_vals;
+  const double* b = (const double*)b_vals;
+  // validate: sorted columns in range, diagonal present, symmetric pattern and values
+  for (int64_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) {
+      set_error("CSR: rowptr not monotone at row %lld", (long long)i);
+      return ZOLO_EINVAL;
+    }
+    bool diag = false;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      int32_t j = colind[e];
+      if (j < 0 || j >= n || (e > rowptr[i] && colind[e - 1] >= j)) {
+        set_error("CSR: column indices must be in range and strictly increasing (row %lld)", (long long)i);
+        return ZOLO_EINVAL;
+      }
+      if (j == i) diag = true;
+    }
+    if (!diag) {
+      set_error("CSR: diagonal entry missing in row %lld", (long long)i);
+      return ZOLO_EINVAL;
+    }
+  }
+  double na = 0.0, nb = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    double ra = 0.0, rb = 0.0;
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      int32_t j = colind[e];
+      ra += std::fabs(a[e]);
+      rb += std::fabs(b[e]);
+      const int32_t* lo = colind + rowptr[j];
+      const int32_t* hi = colind + rowptr[j + 1];
+      const int32_t* it = std::lower_bound(lo, hi, (int32_t)i);
+      if (it == hi || *it != i) {
+        set_error("CSR: pattern not symmetric at (%lld, %d)", (long long)i, (int)j);
+        return ZOLO_ENOTHERM;
+      }
+      int64_t et = it - colind;
+      double sa = std::max(1.0, std::fabs(a[e])), sb = std::max(1.0, std::fabs(b[e]));
+      if (std::fabs(a[et] - a[e]) > 1e-14 * sa || std::fabs(b[et] - b[e]) > 1e-14 * sb) {
+        set_error("A or B not symmetric at (%lld, %d)", (long long)i, (int)j);
+        return ZOLO_ENOTHERM;
+      }
+    }
+    na = std::max(na, ra);
+    nb = std::max(nb, rb);
+  }
+  HIPC(hipSetDevice(ctx->device));
+  std::unique_ptr<zolo_pencil> P(new zolo_pencil());
+  P->ctx = ctx;
+  P->n = n;
+  P->nnz = nnz;
+  P->scalar = scalar;
+  P->normA = na;
+  P->normB = nb;
+  double t0 = now_s();
+  CHK(symbolic_analyze(n, rowptr, colind, grid, leaf_size, &P->S));
+  P->t_symbolic = now_s() - t0;
+  const Symbolic& S = P->S;
+  std::vector<double> pa(nnz), pb(nnz);
+  for (int64_t e = 0; e < nnz; ++e) {
+    pa[e] = a[S.psrc[e]];
+    pb[e] = b[S.psrc[e]];
+  }
+  CHK(P->mem.upload(&P->prow, S.prow.data(), S.prow.size()));
+  CHK(P->mem.upload(&P->pcol, S.pcol.data(), S.pcol.size()));
+  CHK(P->mem.upload(&P->pa, pa.data(), pa.size()));
+  CHK(P->mem.upload(&P->pb, pb.data(), pb.size()));
+  CHK(P->mem.upload(&P->perm, S.perm.data(), S.perm.size()));
+  CHK(P->mem.upload(&P->iperm, S.iperm.data(), S.iperm.size()));
+  CHK(P->mem.upload(&P->struct_rows, S.struct_rows.data(), S.struct_rows.size()));
+  CHK(P->mem.upload(&P->pmap, S.parent_map.data(), S.parent_map.size()));
+  CHK(build_layout(P.get()));
+  *out = P.release();
+  return ZOLO_OK;
+}
+
+extern "C" void zolo_pencil_free(zolo_pencil* p) { delete p; }
+
+extern "C" zolo_status zolo_pencil_info(const zolo_pencil* p, int64_t* n_fronts, int64_t* n_levels, int64_t* nnz_l,
+                                        double* flops, int64_t* max_front) {
+  if (!p) {
+    set_error("null pencil");
+    return ZOLO_EINVAL;
+  }
+  if (n_fronts) *n_fronts = (int64_t)p->S.fronts.size();
+  if (n_levels) *n_levels = (int64_t)p->S.levels.size();
+  if (nnz_l) *nnz_l = p->S.panel_entries + p->S.inv_entries;
+  if (flops) *flops = p->S.flops;
+  if (max_front) *max_front = p->S.max_front;
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* grid,
+                                     int leaf_size, int32_t* perm, double* info) {
+  if (n <= 0 || !rowptr || !colind || n > INT32_MAX) {
+    set_error("zolo_symbolic: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+      if (colind[e] < 0 || colind[e] >= n) {
+        set_error("zolo_symbolic: column index out of range in row %lld", (long long)i);
+        return ZOLO_EINVAL;
+      }
+  Symbolic S;
+  CHK(symbolic_analyze(n, rowptr, colind, grid, leaf_size, &S));
+  if (perm) std::memcpy(perm, S.perm.data(), sizeof(int32_t) * n);
+  if (info) {
+    info[0] = (double)S.fronts.size();
+    info[1] = (double)S.levels.size();
+    info[2] = (double)S.panel_entries;
+    info[3] = (double)S.inv_entries;
+    info[4] = (double)S.update_entries;
+    info[5] = (double)S.max_front;
+    info[6] = (double)S.struct_total;
+    info[7] = S.flops;
+  }
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm) {
+  if (!p || !perm) {
+    set_error("null argument");
+    return ZOLO_EINVAL;
+  }
+  std::memcpy(perm, p->S.perm.data(), sizeof(int32_t) * p->n);
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_filter_plan(double am, double ap, double bm, double bp, int r1, int r2, double eps,
+                                        zolo_filter_coeffs* out) {
+  if (!out) {
+    set_error("null output");
+    return ZOLO_EINVAL;
+  }
+  char err[256] = {0};
+  int rc = plan_filter(am, ap, bm, bp, r1, r2, eps > 0 ? eps : 1e-10, out, err, sizeof(err));
+  if (rc != ZOLO_OK) set_error("%s", err);
+  return (zolo_status)rc;
+}
+
+// ===========================================================================
+// numeric factorization
+// ===========================================================================
+namespace {
+
+template <typename T>
+zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, PoleMF<T>* pole, hipStream_t s) {
+  const Symbolic& S = P->S;
+  const int nl = (int)S.levels.size();
+  CHK(F->mem.alloc(&pole->panel, P->panel_total));
+  CHK(F->mem.alloc(&pole->inv, P->inv_total));
+  CHK(F->mem.alloc(&pole->dvec, P->n));
+  F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
+  DevArena tmp;
+  T* upd = nullptr;
+  T* scratch = nullptr;
+  int* flag = nullptr;
+  CHK(tmp.alloc(&upd, P->upd_total));
+  CHK(tmp.alloc(&scratch, std::max<int64_t>(P->inv_scratch, 1)));
+  CHK(tmp.alloc(&flag, 1));
+  HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
+  HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
+  HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
+  HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
+  // GEMM descriptors of the whole program (pointers into this pole's arrays)
+  std::vector<GemmDesc<T>> gd;
+  struct LevelG {
+    std::vector<GemmLaunch> trail;  // per step J
+    GemmLaunch schur;
+    std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
+  };
+  std::vector<LevelG> lg(nl);
+  const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
+  for (int L = 0; L < nl; ++L) {
+    std::vector<int> fs = S.levels[L];
+    int maxns = 0;
+    for (int f : fs) maxns = std::max(maxns, S.fronts[f].ns);
+    // trailing updates inside the panel, per step J
+    for (int J = 0; J < maxns; J += FB) {
+      GemmLaunch g;
+      g.off = (int)gd.size();
+      for (int f : fs) {
+        const Front& Fr = S.fronts[f];
+        int jb = std::min(FB, Fr.ns - J);
+        if (Fr.ns <= J + jb) continue;
+        int64_t k = (int64_t)Fr.ns + Fr.nb;
+        T* Pn = pole->panel + P->panel_off[f];
+        GemmDesc<T> d{};
+        int r0 = J + jb;
+        d.C = Pn + r0 + (int64_t)r0 * k;
+        d.Cin = d.C;
+        d.ldc = d.ldcin = k;
+        d.A = Pn + r0 + (int64_t)J * k;
+        d.lda = k;
+        d.B = Pn + r0 + (int64_t)J * k;
+        d.ldb = k;
+        d.dk = pole->dvec + Fr.first + J;
+        d.M = (int)(k - r0);
+        d.N = Fr.ns - r0;
+        d.K = jb;
+        d.flags = GF_TRANSB | GF_TRI;
+        d.tri_off = 0;
+        d.alpha = mone;
+        d.beta = one;
+        gd.push_back(d);
+        g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+      }
+      g.cnt = (int)gd.size() - g.off;
+      lg[L].trail.push_back(g);
+    }
+    // Schur complement update U -= L21 D L21^T (lower)
+    {
+      GemmLaunch g;
+      g.off = (int)gd.size();
+      for (int f : fs) {
+        const Front& Fr = S.fronts[f];
+        if (Fr.nb == 0) continue;
+        int64_t k = (int64_t)Fr.ns + Fr.nb;
+        T* Pn = pole->panel + P->panel_off[f];
+        GemmDesc<T> d{};
+        d.C = upd + P->upd_off[f];
+        d.Cin = d.C;
+        d.ldc = d.ldcin = Fr.nb;
+        d.A = Pn + Fr.ns;
+        d.lda = k;
+        d.B = Pn + Fr.ns;
+        d.ldb = k;
+        d.dk = pole->dvec + Fr.first;
+        d.M = Fr.nb;
+        d.N = Fr.nb;
+        d.K = Fr.ns;
+        d.flags = GF_TRANSB | GF_TRI;
+        d.tri_off = 0;
+        d.alpha = mone;
+        d.beta = one;
+        gd.push_back(d);
+        g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+      }
+      g.cnt = (int)gd.size() - g.off;
+      lg[L].schur = g;
+    }
+    // inverse of L11 by block rows: Tmp = L(I, 0:I) X(0:I, 0:I); X(I, 0:I) = -X(I,I) Tmp
+    int maxblk = (maxns + FB - 1) / FB;
+    for (int I = 1; I < maxblk; ++I) {
+      GemmLaunch g1, g2;
+      g1.off = (int)gd.size();
+      int64_t so = 0;
+      std::vector<std::pair<int, int64_t>> act;
+      for (int f : fs) {
+        const Front& Fr = S.fronts[f];
+        int nblk = (Fr.ns + FB - 1) / FB;
+        if (I < nblk) {
+          act.push_back({f, so});
+        }
+        so += (int64_t)FB * Fr.ns;
+      }
+      for (auto& fa : act) {
+        const Front& Fr = S.fronts[fa.first];
+        int64_t k = (int64_t)Fr.ns + Fr.nb;
+        int ib = std::min(FB, Fr.ns - I * FB);
+        T* Pn = pole->panel + P->panel_off[fa.first];
+        T* X = pole->inv + P->inv_off[fa.first];
+        GemmDesc<T> d{};
+        d.C = scratch + fa.second;
+        d.ldc = ib;
+        d.A = Pn + (int64_t)I * FB;
+        d.lda = k;
+        d.B = X;
+        d.ldb = Fr.ns;
+        d.M = ib;
+        d.N = I * FB;
+        d.K = I * FB;
+        d.flags = 0;
+        d.alpha = one;
+        d.beta = zero;
+        gd.push_back(d);
+        g1.tiles = std::max(g1.tiles, gemm_tiles<T>(d.M, d.N));
+      }
+      g1.cnt = (int)gd.size() - g1.off;
+      g2.off = (int)gd.size();
+      for (auto& fa : act) {
+        const Front& Fr = S.fronts[fa.first];
+        int ib = std::min(FB, Fr.ns - I * FB);
+        T* X = pole->inv + P->inv_off[fa.first];
+        GemmDesc<T> d{};
+        d.C = X + (int64_t)I * FB;
+        d.ldc = Fr.ns;
+        d.A = X + (int64_t)I * FB + (int64_t)I * FB * Fr.ns;
+        d.lda = Fr.ns;
+        d.B = scratch + fa.second;
+        d.ldb = ib;
+        d.M = ib;
+        d.N = I * FB;
+        d.K = ib;
+        d.flags = 0;
+        d.alpha = mone;
+        d.beta = zero;
+        gd.push_back(d);
+        g2.tiles = std::max(g2.tiles, gemm_tiles<T>(d.M, d.N));
+      }
+      g2.cnt = (int)gd.size() - g2.off;
+      lg[L].inv1.push_back(g1);
+      lg[L].inv2.push_back(g2);
+    }
+  }
+  GemmDesc<T>* dgd = nullptr;
+  CHK(tmp.upload(&dgd, gd.data(), gd.size()));
+  // run the program level by level
+  for (int L = 0; L < nl; ++L) {
+    front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L],
+                      P->lvl_asm_end[L] - P->lvl_asm_begin[L], P->pa, P->pb, sr, si, s);
+    for (const GemmLaunch& g : P->lvl_ext[L])
+      front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+    const DiagDesc* dd = P->diag + P->lvl_diag_off[L];
+    for (size_t jj = 0; jj < P->lvl_diag_nJ[L].size(); ++jj) {
+      int J = (int)jj * FB;
+      int nd = P->lvl_diag_nJ[L][jj];
+      front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+      front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+      run_gemm<T>(dgd, lg[L].trail[jj], s);
+    }
+    run_gemm<T>(dgd, lg[L].schur, s);
+    for (size_t I = 0; I < lg[L].inv1.size(); ++I) {
+      run_gemm<T>(dgd, lg[L].inv1[I], s);
+      run_gemm<T>(dgd, lg[L].inv2[I], s);
+    }
+  }
+  int hflag = 0;
+  HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  if (hflag) {
+    set_error("zero pivot in the LDL^T of A - sigma B");
+    return ZOLO_EBREAKDOWN;
+  }
+  return ZOLO_OK;
+}
+
+}  // namespace
+
+extern "C" zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* P, const zolo_filter_coeffs* co, int precision,
+                                   void* stream, zolo_factors** out) {
+  if (!ctx || !P || !co || !out) {
+    set_error("zolo_factor: null argument");
+    return ZOLO_EINVAL;
+  }
+  if (co->r1 < 1 || co->r1 > ZOLO_MAX_R || co->r2 < 1 || co->r2 > ZOLO_MAX_R) {
+    set_error("zolo_factor: coefficients not planned (r1=%d, r2=%d)", co->r1, co->r2);
+    return ZOLO_EINVAL;
+  }
+  if (precision != ZOLO_PREC_FP64 && precision != ZOLO_PREC_MIXED) {
+    set_error("zolo_factor: unknown precision %d", precision);
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  std::unique_ptr<zolo_factors> F(new zolo_factors());
+  F->P = P;
+  F->co = *co;
+  F->precision = precision;
+  double t0 = now_s();
+  for (int j = 0; j < co->r1; ++j) {
+    if (precision == ZOLO_PREC_FP64) {
+      F->pd.emplace_back();
+      CHK(factor_pole<zd>(F.get(), P, co->sigma_hat_re[j], co->sigma_hat_im[j], &F->pd.back(), s));
+    } else {
+      F->pf.emplace_back();
+      CHK(factor_pole<zf>(F.get(), P, co->sigma_hat_re[j], co->sigma_hat_im[j], &F->pf.back(), s));
+    }
+  }
+  F->t_factor = now_s() - t0;
+  *out = F.release();
+  return ZOLO_OK;
+}
+
+extern "C" void zolo_factors_free(zolo_factors* f) { delete f; }
+
+// ===========================================================================
+// supernodal solves
+// ===========================================================================
+namespace {
+
+template <typename T>
+zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std::vector<PoleMF<T>>& poles) {
+  zolo_pencil* P = F->P;
+  const Symbolic& S = P->S;
+  const int nl = (int)S.levels.size();
+  G->p = p;
+  int64_t wmax = 0, xbmax = 0, tmax = 0;
+  std::vector<int64_t> uoff(S.fronts.size(), 0);
+  int64_t utot = 0;
+  for (int L = 0; L < nl; ++L) {
+    int64_t w = 0, xb = 0, t = 0;
+    for (int f : S.levels[L]) {
+      const Front& Fr = S.fronts[f];
+      w += (int64_t)(Fr.ns + Fr.nb) * p;
+      xb += (int64_t)Fr.nb * p;
+      t += (int64_t)Fr.ns * p;
+      uoff[f] = utot;
+      utot += (int64_t)Fr.nb * p;
+    }
+    wmax = std::max(wmax, w);
+    xbmax = std::max(xbmax, xb);
+    tmax = std::max(tmax, t);
+  }
+  CHK(G->mem.alloc(&G->W, wmax));
+  CHK(G->mem.alloc(&G->U, utot));
+  CHK(G->mem.alloc(&G->Xb, xbmax));
+  CHK(G->mem.alloc(&G->tb, tmax));
+  CHK(G->mem.alloc(&G->Y, P->n * p));
+  CHK(G->mem.alloc(&G->X, P->n * p));
+  std::vector<SolveDesc> sd;
+  std::vector<SolveExt> se;
+  G->lvl_sd_off.assign(nl, 0);
+  G->lvl_sd_cnt.assign(nl, 0);
+  G->lvl_maxk.assign(nl, 0);
+  G->lvl_maxnb.assign(nl, 0);
+  G->lvl_se.assign(nl, {});
+  std::vector<std::vector<int64_t>> woff(nl), xboff(nl), toff(nl);
+  for (int L = 0; L < nl; ++L) {
+    G->lvl_sd_off[L] = (int)sd.size();
+    int64_t w = 0, xb = 0, t = 0;
+    for (int f : S.levels[L]) {
+      const Front& Fr = S.fronts[f];
+      SolveDesc d{};
+      d.w = w;
+      d.u = uoff[f];
+      d.xb = xb;
+      d.srow = Fr.struct_off;
+      d.first = Fr.first;
+      d.ns = Fr.ns;
+      d.nb = Fr.nb;
+      d.k = Fr.ns + Fr.nb;
+      sd.push_back(d);
+      woff[L].push_back(w);
+      xboff[L].push_back(xb);
+      toff[L].push_back(t);
+      w += (int64_t)d.k * p;
+      xb += (int64_t)Fr.nb * p;
+      t += (int64_t)Fr.ns * p;
+      G->lvl_maxk[L] = std::max(G->lvl_maxk[L], d.k);
+      G->lvl_maxnb[L] = std::max(G->lvl_maxnb[L], (int)Fr.nb);
+    }
+    G->lvl_sd_cnt[L] = (int)sd.size() - G->lvl_sd_off[L];
+    int maxc = 0;
+    for (int f : S.levels[L]) maxc = std::max(maxc, S.fronts[f].child_count);
+    for (int slot = 0; slot < maxc; ++slot) {
+      GemmLaunch g;
+      g.off = (int)se.size();
+      int i = 0;
+      for (int f : S.levels[L]) {
+        const Front& Fr = S.fronts[f];
+        int64_t wf = woff[L][i++];
+        if (slot >= Fr.child_count) continue;
+        int c = S.children[Fr.child_begin + slot];
+        const Front& C = S.fronts[c];
+        if (C.nb == 0) continue;
+        SolveExt e{};
+        e.child_u = uoff[c];
+        e.par_w = wf;
+        e.pmap = C.struct_off;
+        e.nb_c = C.nb;
+        se.push_back(e);
+        g.tiles = std::max(g.tiles, (int)C.nb);
+      }
+      g.cnt = (int)se.size() - g.off;
+      G->lvl_se[L].push_back(g);
+    }
+  }
+  CHK(G->mem.upload(&G->sd, sd.data(), sd.size()));
+  CHK(G->mem.upload(&G->se, se.data(), se.size()));
+  const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
+  const int np = (int)poles.size();
+  G->gd.assign(np, nullptr);
+  G->f2.assign(np, std::vector<GemmLaunch>(nl));
+  G->f3.assign(np, std::vector<GemmLaunch>(nl));
+  G->b2.assign(np, std::vector<GemmLaunch>(nl));
+  G->b3.assign(np, std::vector<GemmLaunch>(nl));
+  for (int j = 0; j < np; ++j) {
+    std::vector<GemmDesc<T>> gd;
+    for (int L = 0; L < nl; ++L) {
+      const std::vector<int>& fs = S.levels[L];
+      auto emit = [&](GemmLaunch& g, auto mk) {
+        g.off = (int)gd.size();
+        for (size_t i = 0; i < fs.size(); ++i) {
+          const Front& Fr = S.fronts[fs[i]];
+          GemmDesc<T> d{};
+          if (!mk(Fr, fs[i], i, d)) continue;
+          gd.push_back(d);
+          g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+        }
+        g.cnt = (int)gd.size() - g.off;
+      };
+      const PoleMF<T>& pm = poles[j];
+      // F2: Y[first:first+ns] = inv * W[0:ns]
+      emit(G->f2[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+        if (Fr.ns == 0) return false;
+        d.C = G->Y + (int64_t)Fr.first * p;
+        d.ldc = p;
+        d.A = pm.inv + P->inv_off[f];
+        d.lda = Fr.ns;
+        d.B = G->W + woff[L][i];
+        d.ldb = p;
+        d.M = Fr.ns;
+        d.N = p;
+        d.K = Fr.ns;
+        d.flags = GF_TRANSB | GF_TRANSC;
+        d.alpha = one;
+        d.beta = zero;
+        return true;
+      });
+      // F3: U = W[ns:k] - L21 * Y[first:first+ns]
+      emit(G->f3[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+        if (Fr.nb == 0) return false;
+        int64_t k = (int64_t)Fr.ns + Fr.nb;
+        d.C = G->U + uoff[f];
+        d.ldc = p;
+        d.Cin = G->W + woff[L][i] + (int64_t)Fr.ns * p;
+        d.ldcin = p;
+        d.A = pm.panel + P->panel_off[f] + Fr.ns;
+        d.lda = k;
+        d.B = G->Y + (int64_t)Fr.first * p;
+        d.ldb = p;
+        d.M = Fr.nb;
+        d.N = p;
+        d.K = Fr.ns;
+        d.flags = GF_TRANSB | GF_TRANSC;
+        d.alpha = mone;
+        d.beta = one;
+        return true;
+      });
+      // B2: t = D^-1 Y[first:] - L21^T Xb
+      emit(G->b2[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+        if (Fr.ns == 0) return false;
+        int64_t k = (int64_t)Fr.ns + Fr.nb;
+        d.C = G->tb + toff[L][i];
+        d.ldc = p;
+        d.Cin = G->Y + (int64_t)Fr.first * p;
+        d.ldcin = p;
+        d.crs = pm.dvec + Fr.first;
+        d.A = pm.panel + P->panel_off[f] + Fr.ns;
+        d.lda = k;
+        d.B = G->Xb + xboff[L][i];
+        d.ldb = p;
+        d.M = Fr.ns;
+        d.N = p;
+        d.K = Fr.nb;
+        d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV;
+        d.alpha = mone;
+        d.beta = one;
+        return true;
+      });
+      // B3: X[first:] = inv^T t
+      emit(G->b3[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+        if (Fr.ns == 0) return false;
+        d.C = G->X + (int64_t)Fr.first * p;
+        d.ldc = p;
+        d.A = pm.inv + P->inv_off[f];
+        d.lda = Fr.ns;
+        d.B = G->tb + toff[L][i];
+        d.ldb = p;
+        d.M = Fr.ns;
+        d.N = p;
+        d.K = Fr.ns;
+        d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC;
+        d.alpha = one;
+        d.beta = zero;
+        return true;
+      });
+    }
+    CHK(G->mem.upload(&G->gd[j], gd.data(), gd.size()));
+  }
+  return ZOLO_OK;
+}
+
+template <typename T>
+SolveProg<T>* get_prog(zolo_factors* F, int p);
+template <>
+SolveProg<zd>* get_prog<zd>(zolo_factors* F, int p) {
+  auto it = F->prog_d.find(p);
+  if (it != F->prog_d.end()) return it->second.get();
+  std::unique_ptr<SolveProg<zd>> G(new SolveProg<zd>());
+  if (build_solve_prog<zd>(F, p, G.get(), F->pd) != ZOLO_OK) return nullptr;
+  SolveProg<zd>* r = G.get();
+  F->prog_d[p] = std::move(G);
+  return r;
+}
+template <>
+SolveProg<zf>* get_prog<zf>(zolo_factors* F, int p) {
+  auto it = F->prog_f.find(p);
+  if (it != F->prog_f.end()) return it->second.get();
+  std::unique_ptr<SolveProg<zf>> G(new SolveProg<zf>());
+  if (build_solve_prog<zf>(F, p, G.get(), F->pf) != ZOLO_OK) return nullptr;
+  SolveProg<zf>* r = G.get();
+  F->prog_f[p] = std::move(G);
+  return r;
+}
+
+// X (new ordering, N x p, in G->X) = K_j^-1 src, src: N x p row-major (new ordering)
+template <typename Ts, typename T>
+void run_solve(zolo_factors* F, SolveProg<T>* G, int j, const Ts* src, int64_t lds, hipStream_t s) {
+  zolo_pencil* P = F->P;
+  const int nl = (int)P->S.levels.size();
+  const int p = G->p;
+  for (int L = 0; L < nl; ++L) {
+    solve_gather_own<Ts, T>(G->W, src, lds, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
+    for (const GemmLaunch& g : G->lvl_se[L]) solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
+    run_gemm<T>(G->gd[j], G->f2[j][L], s);
+    run_gemm<T>(G->gd[j], G->f3[j][L], s);
+  }
+  for (int L = nl - 1; L >= 0; --L) {
+    solve_gather_struct<T>(G->Xb, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
+                           G->lvl_maxnb[L], s);
+    run_gemm<T>(G->gd[j], G->b2[j][L], s);
+    run_gemm<T>(G->gd[j], G->b3[j][L], s);
+  }
+}
+
+int ensure_ws(zolo_factors* F, int p, int mmax) {
+  Workspace* ws = F->ws.get();
+  const int nshift = F->co.r2;
+  if (ws && ws->p == p && ws->mmax >= mmax && ws->nshift == nshift) return ZOLO_OK;
+  F->ws.reset(new Workspace());
+  ws = F->ws.get();
+  const int64_t n = F->P->n;
+  ws->p = p;
+  ws->mmax = mmax;
+  ws->nshift = nshift;
+  ws->n = n;
+  const int64_t Mp = (int64_t)(mmax + 1) * p;
+  CHK(ws->mem.alloc(&ws->Vb, n * Mp));
+  CHK(ws->mem.alloc(&ws->W, n * p));
+  CHK(ws->mem.alloc(&ws->T1, n * p));
+  CHK(ws->mem.alloc(&ws->Tb, n * p));
+  CHK(ws->mem.alloc(&ws->Xc, n * p));
+  CHK(ws->mem.alloc(&ws->Rc, n * p));
+  CHK(ws->mem.alloc(&ws->Dc, n * p));
+  ws->ldh = Mp;
+  CHK(ws->mem.alloc(&ws->H, Mp * (int64_t)mmax * p));
+  CHK(ws->mem.alloc(&ws->hbuf, Mp * p));
+  ws->partial_len = std::max<int64_t>(Mp * p * 8, (int64_t)p * p * 256);
+  CHK(ws->mem.alloc(&ws->partial, ws->partial_len));
+  for (double** q : {&ws->G, &ws->R1, &ws->R1i, &ws->R2, &ws->R2i, &ws->R0, &ws->Rk}) CHK(ws->mem.alloc(q, (size_t)p * p));
+  CHK(ws->mem.alloc(&ws->flag, 4));
+  CHK(ws->mem.alloc(&ws->res, (size_t)nshift * p));
+  CHK(ws->mem.alloc(&ws->coef, nshift));
+  CHK(ws->mem.alloc(&ws->shift_im, nshift));
+  CHK(ws->mem.alloc(&ws->Cm, (size_t)mmax * p * p));
+  CHK(ws->mem.alloc(&ws->Ys, (size_t)nshift * mmax * p * p));
+  ws->gdesc_cap = 1024;
+  CHK(ws->mem.alloc(&ws->gdesc, ws->gdesc_cap + 4));
+  CHK(ws->mem.alloc(&ws->cn_partial, (size_t)colnorm_partials(n) * p + 16));
+  CHK(ws->mem.alloc(&ws->cn_out, (size_t)p));
+  HlsState& h = ws->hls;
+  h.ldr = Mp;
+  h.mmax = mmax;
+  h.p = p;
+  h.nshift = nshift;
+  CHK(ws->mem.alloc(&h.R, (size_t)nshift * Mp * mmax * p));
+  CHK(ws->mem.alloc(&h.refl, (size_t)nshift * mmax * p * (p + 1)));
+  CHK(ws->mem.alloc(&h.tau, (size_t)nshift * mmax * p));
+  CHK(ws->mem.alloc(&h.g, (size_t)nshift * Mp * p));
+  std::vector<double> sh(nshift), cf(nshift);
+  for (int q = 0; q < nshift; ++q) {
+    sh[q] = std::sqrt(F->co.c[q]);
+    cf[q] = 0.5 * F->co.M * F->co.a[q];
+  }
+  HIPC(hipMemcpy(ws->shift_im, sh.data(), sizeof(double) * nshift, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ws->coef, cf.data(), sizeof(double) * nshift, hipMemcpyHostToDevice));
+  h.shift_im = ws->shift_im;
+  return ZOLO_OK;
+}
+
+// X (zd, N x p, new ordering) = K_j^{-1} T (T real, new ordering, ld p)
+zolo_status pole_solve_new(zolo_factors* F, int j, const double* T, int p, zd* X, hipStream_t s) {
+  zolo_pencil* P = F->P;
+  const int64_t n = P->n;
+  if (F->precision == ZOLO_PREC_FP64) {
+    SolveProg<zd>* G = get_prog<zd>(F, p);
+    if (!G) return ZOLO_ENOMEM;
+    run_solve<double, zd>(F, G, j, T, p, s);
+    HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * n * p, hipMemcpyDeviceToDevice, s));
+    F->n_solv += p;
+    return ZOLO_OK;
+  }
+  // mixed: complex64 factors as a preconditioner against FP64 residuals (iterative refinement)
+  SolveProg<zf>* G = get_prog<zf>(F, p);
+  if (!G) return ZOLO_ENOMEM;
+  Workspace& ws = *F->ws;
+  run_solve<double, zf>(F, G, j, T, p, s);
+  HIPC(hipMemsetAsync(X, 0, sizeof(zd) * n * p, s));
+  add_lowp(X, G->X, n * p, s);
+  F->n_solv += p;
+  std::vector<double> tn(p), rn(p);
+  colnorm2_real(T, p, n, p, ws.cn_partial, ws.cn_out, s);
+  HIPC(hipMemcpyAsync(tn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  const double sr = F->co.sigma_hat_re[j], si = F->co.sigma_hat_im[j];
+  for (int it = 0; it < F->max_refine; ++it) {
+    spmm_shift_resid(n, P->prow, P->pcol, P->pa, P->pb, sr, si, X, T, p, p, ws.Rc, s);
+    colnorm2_cplx(ws.Rc, n, p, ws.cn_partial, ws.cn_out, s);
+    HIPC(hipMemcpyAsync(rn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double worst = 0.0;
+    for (int c = 0; c < p; ++c) worst = std::max(worst, std::sqrt(rn[c]) / std::max(std::sqrt(tn[c]), 1e-300));
+    if (worst <= F->tol_refine) break;
+    run_solve<zd, zf>(F, G, j, ws.Rc, p, s);
+    add_lowp(X, G->X, n * p, s);
+    F->n_refine += p;
+  }
+  return ZOLO_OK;
+}
+
+// W (N x p, ld ldw) = G V (V: N x p new ordering, ld ldv)
+zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* W, int64_t ldw, hipStream_t s) {
+  zolo_pencil* P = F->P;
+  const int64_t n = P->n;
+  Workspace& ws = *F->ws;
+  const zolo_filter_coeffs& co = F->co;
+  // T = B V
+  spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, ws.Tb, p, nullptr, 0, s);
+  scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
+  for (int j = 0; j < co.r1; ++j) {
+    CHK(pole_solve_new(F, j, ws.Tb, p, ws.Xc, s));
+    axpy_re(W, ldw, ws.Xc, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
+  }
+  return ZOLO_OK;
+}
+
+// CholQR2 of Win (N x p row-major, ld ldin) into Qout (ld ldq); R (p x p) = R2 R1 into ws.Rk
+zolo_status cholqr2(zolo_factors* F, const double* Win, int64_t ldin, double* Qout, int64_t ldq, int p, bool* breakdown,
+                    hipStream_t s) {
+  Workspace& ws = *F->ws;
+  const int64_t n = F->P->n;
+  int hf[2] = {0, 0};
+  HIPC(hipMemsetAsync(ws.flag, 0, sizeof(int) * 4, s));
+  CHK(gemm_tn(ws, Win, ldin, Win, ldin, n, p, p, ws.G, p, false, s));
+  chol_upper_inv(ws.G, p, 1e-15, ws.R1, ws.R1i, ws.flag, s);
+  CHK(gemm_nt_big(ws, ws.T1, p, nullptr, 0, 0.0, 1.0, ws.R1i, p, true, Win, ldin, n, p, p, s));
+  CHK(gemm_tn(ws, ws.T1, p, ws.T1, p, n, p, p, ws.G, p, false, s));
+  chol_upper_inv(ws.G, p, 0.0, ws.R2, ws.R2i, ws.flag + 1, s);
+  CHK(gemm_nt_big(ws, Qout, ldq, nullptr, 0, 0.0, 1.0, ws.R2i, p, true, ws.T1, p, n, p, p, s));
+  upper_mul(ws.R2, ws.R1, ws.Rk, p, s);
+  HIPC(hipMemcpyAsync(hf, ws.flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  *breakdown = hf[0] || hf[1];
+  return ZOLO_OK;
+}
+
+// Y (ld ldy) = R_ab(B^-1 A) V, everything in the new ordering
+zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* Y, int64_t ldy, double tol,
+                             int maxit, zolo_filter_stats* st, hipStream_t s) {
+  CHK(ensure_ws(F, p, maxit));
+  Workspace& ws = *F->ws;
+  const int64_t n = F->P->n;
+  const int64_t Mp = ws.ldh;
+  const int ns = F->co.r2;
+  bool bd = false;
+  // V = V0 R0
+  CHK(cholqr2(F, V, ldv, ws.Vb, Mp, p, &bd, s));
+  if (bd) {
+    set_error("filter: input block is rank deficient");
+    return ZOLO_EBREAKDOWN;
+  }
+  HIPC(hipMemcpyAsync(ws.R0, ws.Rk, sizeof(double) * p * p, hipMemcpyDeviceToDevice, s));
+  std::vector<double> r0(p * p), r0n(p, 0.0);
+  HIPC(hipMemcpyAsync(r0.data(), ws.R0, sizeof(double) * p * p, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  for (int c = 0; c < p; ++c)
+    for (int i = 0; i <= c; ++i) r0n[c] += r0[i + c * p] * r0[i + c * p];
+  for (int c = 0; c < p; ++c) r0n[c] = std::sqrt(r0n[c]);
+  hls_init(ws.hls, ws.R0, s);
+  HIPC(hipMemsetAsync(ws.H, 0, sizeof(double) * Mp * (int64_t)maxit * p, s));
+  std::vector<double> res((size_t)ns * p);
+  int m = 0;
+  double worst = 1.0;
+  bool exhausted = false;
+  for (int k = 0; k < maxit; ++k) {
+    CHK(apply_G_new(F, ws.Vb + (int64_t)k * p, Mp, p, ws.W, p, s));
+    const int kp1 = (k + 1) * p;
+    for (int pass = 0; pass < 2; ++pass) {
+      CHK(gemm_tn(ws, ws.Vb, Mp, ws.W, p, n, kp1, p, ws.hbuf, kp1, false, s));
+      CHK(gemm_nt_big(ws, ws.W, p, ws.W, p, 1.0, -1.0, ws.hbuf, kp1, true, ws.Vb, Mp, n, p, kp1, s));
+      reduce_partials(ws.H + (int64_t)k * p * Mp, Mp, ws.hbuf, 1, kp1, p, true, s);
+    }
+    CHK(cholqr2(F, ws.W, p, ws.Vb + (int64_t)kp1, Mp, p, &bd, s));
+    put_block(ws.H, Mp, kp1, (int64_t)k * p, ws.Rk, p, s);
+    hls_step(ws.hls, ws.H, Mp, k, ws.res, s);
+    HIPC(hipMemcpyAsync(res.data(), ws.res, sizeof(double) * ns * p, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    HIPC(hipGetLastError());
+    worst = 0.0;
+    for (int q = 0; q < ns; ++q)
+      for (int c = 0; c < p; ++c) worst = std::max(worst, res[(size_t)q * p + c] / std::max(r0n[c], 1e-300));
+    m = k + 1;
+    if (bd) exhausted = true;
+    if (worst <= tol || exhausted) break;
+  }
+  hls_backsolve(ws.hls, m, ws.Ys, s);
+  hls_combine_real(ws.Ys, m, p, ns, ws.coef, ws.Cm, s);
+  // Y = V/2 + V_m C
+  CHK(gemm_nt_big(ws, Y, ldy, V, ldv, 0.5, 1.0, ws.Cm, (int64_t)m * p, true, ws.Vb, Mp, n, p, m * p, s));
+  HIPC(hipStreamSynchronize(s));
+  if (st) {
+    st->n_gmres = m;
+    st->worst_resid = worst;
+    st->breakdown = exhausted ? 1 : 0;
+  }
+  if (worst > tol && !exhausted) {
+    set_error("block GMRES reached %d steps with relative residual %.3e > %.3e", m, worst, tol);
+    return ZOLO_ENOCONV;
+  }
+  return ZOLO_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI entry points on blocks in the original ordering
+// ===========================================================================
+extern "C" zolo_status zolo_spmm(zolo_pencil* P, int which, const void* d_X, int64_t ldx, int ncols, void* d_Y,
+                                 int64_t ldy, void* stream) {
+  if (!P || !d_X || !d_Y || ncols <= 0 || ldx < ncols || ldy < ncols || (which != 0 && which != 1)) {
+    set_error("zolo_spmm: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  DevArena tmp;
+  double *xn = nullptr, *yn = nullptr;
+  const int64_t n = P->n;
+  CHK(tmp.alloc(&xn, n * ncols));
+  CHK(tmp.alloc(&yn, n * ncols));
+  rows_gather<double>(xn, ncols, (const double*)d_X, ldx, P->perm, n, ncols, s);
+  spmm_real(n, P->prow, P->pcol, which == 0 ? P->pa : P->pb, nullptr, xn, ncols, ncols, yn, ncols, nullptr, 0, s);
+  rows_scatter<double>((double*)d_Y, ldy, yn, ncols, P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_pole_solve(zolo_factors* F, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
+                                       int64_t ldx, void* stream) {
+  if (!F || !d_T || !d_X || j < 0 || j >= F->co.r1 || ncols <= 0 || ldt < ncols || ldx < ncols) {
+    set_error("zolo_pole_solve: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  double* tn = nullptr;
+  zd* xn = nullptr;
+  CHK(tmp.alloc(&tn, n * ncols));
+  CHK(tmp.alloc(&xn, n * ncols));
+  rows_gather<double>(tn, ncols, d_T, ldt, F->P->perm, n, ncols, s);
+  CHK(pole_solve_new(F, j, tn, ncols, xn, s));
+  rows_scatter<zd>((zd*)d_X, ldx, xn, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_apply_G(zolo_factors* F, const double* d_V, int64_t ldv, int ncols, double* d_W,
+                                    int64_t ldw, void* stream) {
+  if (!F || !d_V || !d_W || ncols <= 0 || ldv < ncols || ldw < ncols) {
+    set_error("zolo_apply_G: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  hipStream_t s = as_stream(stream);
+  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  double *vn = nullptr, *wn = nullptr;
+  CHK(tmp.alloc(&vn, n * ncols));
+  CHK(tmp.alloc(&wn, n * ncols));
+  rows_gather<double>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
+  CHK(apply_G_new(F, vn, ncols, ncols, wn, ncols, s));
+  rows_scatter<double>(d_W, ldw, wn, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int64_t ldv, int ncols, double* d_Y,
+                                         int64_t ldy, double tol, int maxit, zolo_filter_stats* st, void* stream) {
+  if (!F || !d_V || !d_Y || ncols <= 0 || ldv < ncols || ldy < ncols) {
+    set_error("zolo_filter_apply: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  if (tol <= 0) tol = 1e-10;
+  if (maxit <= 0) maxit = 60;
+  hipStream_t s = as_stream(stream);
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  double *vn = nullptr, *yn = nullptr;
+  CHK(tmp.alloc(&vn, n * ncols));
+  CHK(tmp.alloc(&yn, n * ncols));
+  rows_gather<double>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
+  zolo_status rc = filter_apply_new(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
+  if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
+  rows_scatter<double>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return rc;
+}
+
+// ===========================================================================
+// Algorithm 1
+// ===========================================================================
+extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
+                                  const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_result** out) {
+  if (!ctx || !P || !out || !(a < b) || n_lambda_est < 0) {
+    set_error("zolo_solve: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  zolo_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    zolo_opts_default(&o);
+  if (std::isnan(o.a_minus) || std::isnan(o.a_plus) || std::isnan(o.b_minus) || std::isnan(o.b_plus)) {
+    set_error("zolo_solve: eigengaps (a_minus, a_plus, b_minus, b_plus) must be given");
+    return ZOLO_EINVAL;
+  }
+  if (!(o.a_minus < a && a < o.a_plus && o.b_minus < b && b < o.b_plus)) {
+    set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  const double t_start = now_s();
+  const int64_t n = P->n;
+  int nss = o.n_ss > 0 ? o.n_ss : (int)std::ceil(1.5 * std::max(n_lambda_est, 1));
+  nss = (int)std::min<int64_t>(nss, n);
+  if (nss > 512) {
+    set_error("zolo_solve: subspace size %d above 512", nss);
+    return ZOLO_EINVAL;
+  }
+  std::unique_ptr<zolo_result> R(new zolo_result());
+  R->n = n;
+  zolo_stats& st = R->st;
+  double t0 = now_s();
+  zolo_filter_coeffs co;
+  CHK(zolo_filter_plan(o.a_minus, o.a_plus, o.b_minus, o.b_plus, o.r1, o.r2, o.filter_eps, &co));
+  st.t_plan = now_s() - t0;
+  st.t_symbolic = P->t_symbolic;
+  st.r1 = co.r1;
+  st.r2 = co.r2;
+  st.l1 = co.l1;
+  st.l2 = co.l2;
+  st.delta0 = co.delta0;
+  st.norm_a = P->normA;
+  st.norm_b = P->normB;
+  t0 = now_s();
+  zolo_factors* Fp = nullptr;
+  CHK(zolo_factor(ctx, P, &co, o.precision, stream, &Fp));
+  std::unique_ptr<zolo_factors> F(Fp);
+  F->max_refine = o.max_refine > 0 ? o.max_refine : 8;
+  F->tol_refine = o.tol_refine > 0 ? o.tol_refine : 1e-13;
+  st.t_factor = now_s() - t0;
+  st.factor_bytes = F->bytes;
+  st.nnz_l = P->S.panel_entries + P->S.inv_entries;
+  st.factor_flops = P->S.flops;
+  const int maxit = o.max_gmres_iter > 0 ? o.max_gmres_iter : 60;
+  const double tol_g = o.tol_gmres > 0 ? o.tol_gmres : 1e-10;
+  CHK(ensure_ws(F.get(), nss, maxit));
+  Workspace& ws = *F->ws;
+  // subspace buffers (new ordering)
+  DevArena mem;
+  double *Q, *Y, *AY, *BY, *X, *AX, *BX, *At, *Bt, *theta, *Cm, *work, *rp, *rn, *Gx;
+  int* kdev;
+  CHK(mem.alloc(&Q, n * nss));
+  CHK(mem.alloc(&Y, n * nss));
+  CHK(mem.alloc(&AY, n * nss));
+  CHK(mem.alloc(&BY, n * nss));
+  CHK(mem.alloc(&X, n * nss));
+  CHK(mem.alloc(&AX, n * nss));
+  CHK(mem.alloc(&BX, n * nss));
+  CHK(mem.alloc(&At, (size_t)nss * nss));
+  CHK(mem.alloc(&Bt, (size_t)nss * nss));
+  CHK(mem.alloc(&Gx, (size_t)nss * nss));
+  CHK(mem.alloc(&theta, nss));
+  CHK(mem.alloc(&Cm, (size_t)nss * nss));
+  CHK(mem.alloc(&work, (size_t)7 * nss * nss + 8 * nss + 64));
+  CHK(mem.alloc(&rp, (size_t)((n + 511) / 512) * 3 * nss + 16));
+  CHK(mem.alloc(&rn, (size_t)3 * nss));
+  CHK(mem.alloc(&kdev, 1));
+  if (d_Q0) {
+    rows_gather<double>(Q, nss, d_Q0, nss, P->perm, n, nss, s);
+  } else {
+    std::vector<double> g;
+    gaussian_host(o.seed, (size_t)n * nss, &g);
+    CHK(mem.upload(&X, g.data(), g.size()));  // reuse X as staging
+    rows_gather<double>(Q, nss, X, nss, P->perm, n, nss, s);
+  }
+  t0 = now_s();
+  std::vector<double> th(nss), rnh(3 * nss);
+  std::vector<int> sel;
+  int k = 0;
+  bool converged = false;
+  zolo_status frc = ZOLO_OK;
+  for (int it = 1; it <= std::max(1, o.max_subspace_iter); ++it) {
+    zolo_filter_stats fs{};
+    frc = filter_apply_new(F.get(), Q, nss, nss, Y, nss, tol_g, maxit, &fs, s);
+    if (frc != ZOLO_OK && frc != ZOLO_ENOCONV) return frc;
+    st.n_iter = it;
+    st.n_gmres_total += fs.n_gmres;
+    st.n_gmres_last = fs.n_gmres;
+    st.gmres_resid = fs.worst_resid;
+    // Rayleigh-Ritz
+    spmm_real(n, P->prow, P->pcol, P->pa, P->pb, Y, nss, nss, AY, nss, BY, nss, s);
+    CHK(gemm_tn(ws, Y, nss, AY, nss, n, nss, nss, At, nss, false, s));
+    CHK(gemm_tn(ws, Y, nss, BY, nss, n, nss, nss, Bt, nss, false, s));
+    rr_reduce(At, Bt, nss, 1e-12, theta, Cm, kdev, work, s);
+    HIPC(hipMemcpyAsync(&k, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    HIPC(hipGetLastError());
+    if (k <= 0) {
+      set_error("Rayleigh-Ritz: filtered block has rank 0");
+      return ZOLO_EBREAKDOWN;
+    }
+    // X = Y C, AX = AY C, BX = BY C  (row-major N x k)
+    CHK(gemm_nt_big(ws, X, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, Y, nss, n, k, nss, s));
+    CHK(gemm_nt_big(ws, AX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, AY, nss, n, k, nss, s));
+    CHK(gemm_nt_big(ws, BX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, BY, nss, n, k, nss, s));
+    resid_norms(AX, BX, X, theta, n, k, rp, rn, s);
+    HIPC(hipMemcpyAsync(th.data(), theta, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(rnh.data(), rn, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    sel.clear();
+    double worst = 0.0;
+    for (int c = 0; c < k; ++c) {
+      if (!(th[c] > a && th[c] < b)) continue;
+      sel.push_back(c);
+      double r = std::sqrt(rnh[3 * c]) / ((P->normA + std::fabs(th[c]) * P->normB) * std::sqrt(rnh[3 * c + 1]));
+      worst = std::max(worst, r);
+    }
+    st.max_resid = worst;
+    // next block: Ritz vectors, padded with the previous block's columns
+    HIPC(hipMemcpy2DAsync(Q, sizeof(double) * nss, X, sizeof(double) * k, sizeof(double) * k, n,
+                          hipMemcpyDeviceToDevice, s));
+    if (!sel.empty() && worst <= o.tol_resid) {
+      converged = true;
+      break;
+    }
+  }
+  st.t_iter = now_s() - t0;
+  st.n_solv = F->n_solv;
+  st.n_refine = F->n_refine;
+  // results: selected pairs, original ordering
+  const int cnt = (int)sel.size();
+  R->count = cnt;
+  R->eig.resize(cnt);
+  double emax = 0.0;
+  for (int i = 0; i < cnt; ++i) {
+    int c = sel[i];
+    R->eig[i] = th[c];
+    emax = std::max(emax, std::sqrt(rnh[3 * c]) / (std::max(std::fabs(a), std::fabs(b)) * std::sqrt(rnh[3 * c + 2])));
+  }
+  st.e_lambda_x = emax;
+  st.n_found = cnt;
+  if (cnt > 0) {
+    CHK(R->mem.alloc(&R->vec, n * cnt));
+    double* tmpv = nullptr;
+    CHK(mem.alloc(&tmpv, n * cnt));
+    int c0 = sel[0];
+    // selected Ritz values are consecutive in the ascending order
+    HIPC(hipMemcpy2DAsync(tmpv, sizeof(double) * cnt, X + c0, sizeof(double) * k, sizeof(double) * cnt, n,
+                          hipMemcpyDeviceToDevice, s));
+    rows_scatter<double>(R->vec, cnt, tmpv, cnt, P->perm, n, cnt, s);
+    // B-orthonormality of the returned vectors: X^T B X - I
+    spmm_real(n, P->prow, P->pcol, P->pb, nullptr, tmpv, cnt, cnt, AX, cnt, nullptr, 0, s);
+    CHK(gemm_tn(ws, tmpv, cnt, AX, cnt, n, cnt, cnt, Gx, cnt, false, s));
+    std::vector<double> gx((size_t)cnt * cnt);
+    HIPC(hipMemcpyAsync(gx.data(), Gx, sizeof(double) * cnt * cnt, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    double bo = 0.0;
+    for (int i = 0; i < cnt; ++i)
+      for (int j2 = 0; j2 < cnt; ++j2) bo = std::max(bo, std::fabs(gx[i + (size_t)j2 * cnt] - (i == j2 ? 1.0 : 0.0)));
+    st.b_orth = bo;
+  }
+  st.t_total = now_s() - t_start;
+  *out = R.release();
+  if (cnt >= nss - 1) {
+    set_error("found %d eigenpairs with a subspace of %d: estimate too small", cnt, nss);
+    return ZOLO_ESUBSPACE;
+  }
+  if (!converged) {
+    set_error("subspace iteration did not reach tol_resid (worst %.3e)", st.max_resid);
+    return ZOLO_ENOCONV;
+  }
+  return frc == ZOLO_ENOCONV ? ZOLO_ENOCONV : ZOLO_OK;
+}
+
+extern "C" int64_t zolo_result_count(const zolo_result* r) { return r ? r->count : 0; }
+extern "C" const double* zolo_result_eigenvalues(const zolo_result* r) { return r ? r->eig.data() : nullptr; }
+extern "C" zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_dst, int64_t ld, void* stream) {
+  if (!r || !d_dst || ld < r->count) {
+    set_error("zolo_result_copy_vectors: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  if (r->count == 0) return ZOLO_OK;
+  hipStream_t s = as_stream(stream);
+  HIPC(hipMemcpy2DAsync(d_dst, sizeof(double) * ld, r->vec, sizeof(double) * r->count, sizeof(double) * r->count, r->n,
+                        hipMemcpyDeviceToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+  return ZOLO_OK;
+}
+extern "C" zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out) {
+  if (!r || !out) {
+    set_error("null argument");
+    return ZOLO_EINVAL;
+  }
+  *out = r->st;
+  return ZOLO_OK;
+}
+extern "C" void zolo_result_free(zolo_result* r) { delete r; }

@@ -1,0 +1,77 @@
+// Multifrontal complex-symmetric LDL^T kernels: front assembly, extend-add,
+// diagonal-block factorization and inversion, panel triangular solve, and the
+// row gathers / extend-adds of the supernodal triangular solves.
+#pragma once
+
+#include "dev_common.h"
+
+namespace zolo {
+
+constexpr int FB = 64;  // block size of the blocked partial factorization
+
+// One extend-add: child contribution block (nb_c x nb_c, column-major, lower
+// triangle) into the parent front (panel k_p x ns_p col-major + update block
+// nb_p x nb_p col-major), rows mapped by pmap.
+struct ExtDesc {
+  int64_t child_upd;  // element offset of the child's update block
+  int64_t pmap;       // offset into the parent-map array (nb_c entries)
+  int64_t par_panel;  // element offset of the parent panel
+  int64_t par_upd;    // element offset of the parent update block
+  int32_t nb_c, k_p, ns_p, pad;
+};
+
+struct DiagDesc {
+  int64_t panel;  // element offset of the panel (k x ns, col-major, ld k)
+  int64_t inv;    // element offset of the ns x ns inverse block (ld ns)
+  int32_t k, ns, first, pad;
+};
+
+// Solve: per front RHS block W (k x p row-major), contributions U (nb x p).
+struct SolveDesc {
+  int64_t w;      // element offset of W in the level's W buffer
+  int64_t u;      // element offset of U in the U buffer (global over fronts)
+  int64_t xb;     // element offset of the struct gather buffer
+  int64_t srow;   // offset into struct_rows
+  int32_t first, ns, nb, k;
+};
+
+struct SolveExt {  // child U (nb_c x p) into parent W rows pmap
+  int64_t child_u;
+  int64_t par_w;
+  int64_t pmap;
+  int32_t nb_c, pad;
+};
+
+// assembly: panel[dst[e]] = a[src[e]] - sigma * b[src[e]]  (real pencil values)
+template <typename T>
+void front_assemble(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const double* a, const double* b,
+                    double sig_re, double sig_im, hipStream_t s);
+
+template <typename T>
+void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb, hipStream_t s);
+
+// Factor the FB x FB (or smaller) diagonal block at step J of each listed front,
+// write L (unit lower, strictly lower part), D (into dvec at first + J + c and the
+// panel diagonal) and the inverse of the unit lower block into the inverse array.
+template <typename T>
+void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s);
+
+// rows J+jb .. k-1 of each panel: L(r, J:J+jb) = P(r, J:J+jb) inv(J,J)^T D_J^-1 (in place)
+template <typename T>
+void front_panel_trsm(T* panel, const T* inv, const T* dvec, const DiagDesc* d, int nd, int J, int max_rows,
+                      hipStream_t s);
+
+// W rows [0, ns) <- src rows [first, first+ns) (converted), rows [ns, k) <- 0.
+template <typename Ts, typename T>
+void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
+                      hipStream_t s);
+// W_parent[pmap[i]] += U_child[i]
+template <typename T>
+void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, int nd, int p, int max_nb,
+                      hipStream_t s);
+// Xb[i] = X[struct_rows[srow + i]]
+template <typename T>
+void solve_gather_struct(T* Xb, const T* X, const int32_t* struct_rows, const SolveDesc* d, int nd, int p,
+                         int max_nb, hipStream_t s);
+
+}  // namespace zolo

@@ -1,0 +1,263 @@
+// Multifrontal LDL^T kernels (numeric factorization and solve helpers) for
+// the r1 shifted matrices K_j = A - sigma_hat_j B of Algorithm 2, lines 5-6.
+// Real pencils give complex-symmetric K_j, factored without pivoting in the
+// nested-dissection order (A - sigma B with Im sigma != 0 has a definite
+// skew-Hermitian part, so every leading principal block is nonsingular).
+#include "front.h"
+
+namespace zolo {
+namespace {
+
+template <typename T>
+__global__ void assemble_kernel(T* __restrict__ panel, const int64_t* __restrict__ dst, const int64_t* __restrict__ src,
+                                int64_t n, const double* __restrict__ a, const double* __restrict__ b, double sr,
+                                double si) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int64_t s = src[e];
+  double av = a[s], bv = b[s];
+  zd v{av - sr * bv, -si * bv};
+  panel[dst[e]] = cvt<T, zd>(v);
+}
+
+template <typename T>
+__global__ void extend_add_kernel(T* __restrict__ panel, T* __restrict__ upd, const int32_t* __restrict__ pmap,
+                                  const ExtDesc* __restrict__ descs) {
+  const ExtDesc d = descs[blockIdx.y];
+  const int64_t nb = d.nb_c;
+  // column j of the child block handled by blockIdx.x, rows by threads
+  const int64_t j = blockIdx.x;
+  if (j >= nb) return;
+  const int32_t* pm = pmap + d.pmap;
+  const T* cu = upd + d.child_upd;
+  const int pj = pm[j];
+  for (int64_t i = j + threadIdx.x; i < nb; i += blockDim.x) {
+    T v = cu[i + j * nb];
+    int pi = pm[i];
+    if (pj < d.ns_p) {
+      T* dst = panel + d.par_panel + pi + (int64_t)pj * d.k_p;
+      *dst = add(*dst, v);
+    } else {
+      int64_t nbp = (int64_t)d.k_p - d.ns_p;
+      T* dst = upd + d.par_upd + (pi - d.ns_p) + (int64_t)(pj - d.ns_p) * nbp;
+      *dst = add(*dst, v);
+    }
+  }
+}
+
+// One workgroup per front: LDL^T of the jb x jb diagonal block in LDS, then the
+// inverse of its unit lower factor.
+template <typename T>
+__global__ __launch_bounds__(256) void diag_block_kernel(T* __restrict__ panel, T* __restrict__ inv,
+                                                         T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
+                                                         int J, int* breakdown) {
+  const DiagDesc d = descs[blockIdx.x];
+  if (J >= d.ns) return;
+  const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
+  __shared__ T Ab[FB][FB + 1];  // Ab[r][c]
+  __shared__ T Xb[FB][FB + 1];
+  const int tid = threadIdx.x;
+  T* P = panel + d.panel;
+  const int64_t k = d.k;
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    int r = e % jb, c = e / jb;
+    Ab[r][c] = (r >= c) ? P[(J + r) + (int64_t)(J + c) * k] : ST<T>::zero();
+  }
+  __syncthreads();
+  // right-looking unblocked LDL^T
+  for (int c = 0; c < jb; ++c) {
+    T dc = Ab[c][c];
+    if (abs2(dc) == 0.0) {
+      if (tid == 0) atomicExch(breakdown, 1);
+      dc = ST<T>::one();
+    }
+    T dinv = inv_(dc);
+    __syncthreads();
+    for (int r = c + 1 + tid; r < jb; r += blockDim.x) Ab[r][c] = mul(Ab[r][c], dinv);
+    __syncthreads();
+    // trailing lower update: A(r, q) -= L(r,c) d L(q,c), q in (c, jb), r >= q
+    const int m = jb - c - 1;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      int r = c + 1 + e % m, q = c + 1 + e / m;
+      if (r >= q) Ab[r][q] = sub(Ab[r][q], mul(mul(Ab[r][c], dc), Ab[q][c]));
+    }
+    __syncthreads();
+  }
+  // write back L (strict lower) and D
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    int r = e % jb, c = e / jb;
+    if (r >= c) P[(J + r) + (int64_t)(J + c) * k] = Ab[r][c];
+  }
+  for (int c = tid; c < jb; c += blockDim.x) dvec[d.first + J + c] = Ab[c][c];
+  // inverse of the unit lower block: X(r, c) = -sum_{c <= t < r} L(r, t) X(t, c)
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    int r = e % jb, c = e / jb;
+    Xb[r][c] = (r == c) ? ST<T>::one() : ST<T>::zero();
+  }
+  __syncthreads();
+  for (int r = 1; r < jb; ++r) {
+    for (int c = tid; c < r; c += blockDim.x) {
+      T s = ST<T>::zero();
+      for (int t = c; t < r; ++t) s = fma_(s, Ab[r][t], Xb[t][c]);
+      Xb[r][c] = neg(s);
+    }
+    __syncthreads();
+  }
+  T* X = inv + d.inv;
+  const int64_t ns = d.ns;
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    int r = e % jb, c = e / jb;
+    X[(J + r) + (int64_t)(J + c) * ns] = (r >= c) ? Xb[r][c] : ST<T>::zero();
+  }
+}
+
+// rows handled per workgroup in the panel solve
+constexpr int PT_ROWS = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void panel_trsm_kernel(T* __restrict__ panel, const T* __restrict__ inv,
+                                                         const T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
+                                                         int J) {
+  const DiagDesc d = descs[blockIdx.y];
+  if (J >= d.ns) return;
+  const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
+  const int r0 = J + jb + blockIdx.x * PT_ROWS;
+  if (r0 >= d.k) return;
+  const int nr = (d.k - r0) < PT_ROWS ? (d.k - r0) : PT_ROWS;
+  __shared__ T Xs[FB][FB + 1];      // Xs[c][t] = inv(J+c, J+t)
+  __shared__ T Ps[PT_ROWS][FB + 1];  // panel rows
+  __shared__ T Di[FB];
+  const int tid = threadIdx.x;
+  T* P = panel + d.panel;
+  const T* X = inv + d.inv;
+  const int64_t k = d.k, ns = d.ns;
+  for (int e = tid; e < jb * jb; e += blockDim.x) {
+    int c = e % jb, t = e / jb;
+    Xs[c][t] = X[(J + c) + (int64_t)(J + t) * ns];
+  }
+  for (int e = tid; e < nr * jb; e += blockDim.x) {
+    int r = e % nr, t = e / nr;
+    Ps[r][t] = P[(r0 + r) + (int64_t)(J + t) * k];
+  }
+  for (int c = tid; c < jb; c += blockDim.x) Di[c] = inv_(dvec[d.first + J + c]);
+  __syncthreads();
+  // L(r, c) = (sum_{t <= c} P(r, t) X(c, t)) / D(c)
+  for (int e = tid; e < nr * jb; e += blockDim.x) {
+    int r = e % nr, c = e / nr;
+    T s = ST<T>::zero();
+    for (int t = 0; t <= c; ++t) s = fma_(s, Ps[r][t], Xs[c][t]);
+    P[(r0 + r) + (int64_t)(J + c) * k] = mul(s, Di[c]);
+  }
+}
+
+template <typename Ts, typename T>
+__global__ void gather_own_kernel(T* __restrict__ W, const Ts* __restrict__ src, int64_t ldsrc,
+                                  const SolveDesc* __restrict__ descs, int p) {
+  const SolveDesc d = descs[blockIdx.y];
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t tot = (int64_t)d.k * p;
+  if (e >= tot) return;
+  int64_t r = e / p, c = e % p;
+  T v = ST<T>::zero();
+  if (r < d.ns) v = cvt<T, Ts>(src[(d.first + r) * ldsrc + c]);
+  W[d.w + e] = v;
+}
+
+template <typename T>
+__global__ void solve_ext_kernel(T* __restrict__ W, const T* __restrict__ U, const int32_t* __restrict__ pmap,
+                                 const SolveExt* __restrict__ descs, int p) {
+  const SolveExt d = descs[blockIdx.y];
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t tot = (int64_t)d.nb_c * p;
+  if (e >= tot) return;
+  int64_t i = e / p, c = e % p;
+  int64_t pr = pmap[d.pmap + i];
+  T* dst = W + d.par_w + pr * p + c;
+  *dst = add(*dst, U[d.child_u + e]);
+}
+
+template <typename T>
+__global__ void gather_struct_kernel(T* __restrict__ Xb, const T* __restrict__ X, const int32_t* __restrict__ srows,
+                                     const SolveDesc* __restrict__ descs, int p) {
+  const SolveDesc d = descs[blockIdx.y];
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t tot = (int64_t)d.nb * p;
+  if (e >= tot) return;
+  int64_t i = e / p, c = e % p;
+  int64_t row = srows[d.srow + i];
+  Xb[d.xb + e] = X[row * p + c];
+}
+
+}  // namespace
+
+template <typename T>
+void front_assemble(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const double* a, const double* b,
+                    double sr, double si, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, panel, dst, src, n, a, b,
+                     sr, si);
+}
+
+template <typename T>
+void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb, hipStream_t s) {
+  if (nd <= 0 || max_nb <= 0) return;
+  hipLaunchKernelGGL(extend_add_kernel<T>, dim3(max_nb, nd), dim3(256), 0, s, panel, upd, pmap, d);
+}
+
+template <typename T>
+void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(diag_block_kernel<T>, dim3(nd), dim3(256), 0, s, panel, inv, dvec, d, J, breakdown);
+}
+
+template <typename T>
+void front_panel_trsm(T* panel, const T* inv, const T* dvec, const DiagDesc* d, int nd, int J, int max_rows,
+                      hipStream_t s) {
+  if (nd <= 0 || max_rows <= 0) return;
+  int gx = (max_rows + PT_ROWS - 1) / PT_ROWS;
+  hipLaunchKernelGGL(panel_trsm_kernel<T>, dim3(gx, nd), dim3(256), 0, s, panel, inv, dvec, d, J);
+}
+
+template <typename Ts, typename T>
+void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
+                      hipStream_t s) {
+  if (nd <= 0) return;
+  int64_t tot = (int64_t)max_k * p;
+  hipLaunchKernelGGL((gather_own_kernel<Ts, T>), dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, src,
+                     ldsrc, d, p);
+}
+
+template <typename T>
+void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, int nd, int p, int max_nb,
+                      hipStream_t s) {
+  if (nd <= 0 || max_nb <= 0) return;
+  int64_t tot = (int64_t)max_nb * p;
+  hipLaunchKernelGGL(solve_ext_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, U, pmap, d, p);
+}
+
+template <typename T>
+void solve_gather_struct(T* Xb, const T* X, const int32_t* srows, const SolveDesc* d, int nd, int p, int max_nb,
+                         hipStream_t s) {
+  if (nd <= 0 || max_nb <= 0) return;
+  int64_t tot = (int64_t)max_nb * p;
+  hipLaunchKernelGGL(gather_struct_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, Xb, X, srows,
+                     d, p);
+}
+
+#define INST(T)                                                                                                      \
+  template void front_assemble<T>(T*, const int64_t*, const int64_t*, int64_t, const double*, const double*, double, \
+                                  double, hipStream_t);                                                              \
+  template void front_extend_add<T>(T*, T*, const int32_t*, const ExtDesc*, int, int, hipStream_t);                  \
+  template void front_diag_block<T>(T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);                       \
+  template void front_panel_trsm<T>(T*, const T*, const T*, const DiagDesc*, int, int, int, hipStream_t);            \
+  template void solve_extend_add<T>(T*, const T*, const int32_t*, const SolveExt*, int, int, int, hipStream_t);      \
+  template void solve_gather_struct<T>(T*, const T*, const int32_t*, const SolveDesc*, int, int, int, hipStream_t);
+INST(zd)
+INST(zf)
+#undef INST
+template void solve_gather_own<double, zd>(zd*, const double*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
+template void solve_gather_own<zd, zd>(zd*, const zd*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
+template void solve_gather_own<double, zf>(zf*, const double*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
+template void solve_gather_own<zd, zf>(zf*, const zd*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
+
+}  // namespace zolo

@@ -1,0 +1,54 @@
+// Batched dense matrix product used by the factorization, the solves, the
+// block Arnoldi process and Rayleigh-Ritz.
+//
+//   C(i,j) = s(i) Cin(i,j) + alpha * sum_t opA(i,t) * dk(t) * opB(t,j)
+//
+// with s(i) = beta, or crs(i) (row scale), or 1/crs(i) (flag GF_CRS_INV);
+// opA/opB optionally transposed / conjugated; C and Cin column-major with
+// leading dimensions ldc/ldcin, or row-major with GF_TRANSC.  GF_TRI keeps
+// only entries with i - j >= tri_off (lower-triangular updates of symmetric
+// fronts).  One descriptor per independent product; a launch covers a list.
+#pragma once
+
+#include "dev_common.h"
+
+namespace zolo {
+
+enum GemmFlags {
+  GF_TRANSA = 1,
+  GF_TRANSB = 2,
+  GF_TRANSC = 4,
+  GF_CONJA = 8,
+  GF_CONJB = 16,
+  GF_TRI = 32,
+  GF_CRS_INV = 64,
+  GF_CRS = 128,
+};
+
+template <typename T>
+struct GemmDesc {
+  const T* A;
+  const T* B;
+  T* C;
+  const T* Cin;  // may equal C; null when beta == 0 and no row scale
+  const T* dk;   // inner-dimension scale (length K), may be null
+  const T* crs;  // row scale of Cin (GF_CRS / GF_CRS_INV), may be null
+  int64_t lda, ldb, ldc, ldcin;
+  int M, N, K;
+  int tri_off;
+  int flags;
+  T alpha, beta;
+};
+
+constexpr int GEMM_TILE = 64;
+
+template <typename T>
+inline int gemm_tiles(int M, int N) {
+  return ((M + GEMM_TILE - 1) / GEMM_TILE) * ((N + GEMM_TILE - 1) / GEMM_TILE);
+}
+
+// d_desc: device array of n descriptors; max_tiles = max over descriptors of gemm_tiles.
+template <typename T>
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s);
+
+}  // namespace zolo

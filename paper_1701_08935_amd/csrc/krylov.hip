@@ -1,0 +1,582 @@
+// Kernels of the multi-shift block GMRES (Algorithm 2, line 8; eq. solve2)
+// and of the Rayleigh-Ritz step (Algorithm 1, lines 4-6).
+//
+// Shifted least squares.  Block Arnoldi gives G V_m = V_{m+1} Hbar_m with a
+// real block upper Hessenberg Hbar; by shift invariance
+// (G + s I) V_m = V_{m+1} (Hbar_m + s Ibar), so each outer shift s = i sqrt(c_j)
+// needs min || E1 R0 - (Hbar + s Ibar) Y ||.  Every shift keeps its own
+// incremental QR: each new block column receives the earlier Householder
+// reflectors, its 2p x p panel (upper-triangular subdiagonal block) is reduced
+// by p new reflectors of length p + 1, and the transformed right-hand side
+// gives the residual norm of every column.  Reductions are wave-level
+// (64-lane shuffles); one wave owns the rows r with r % 64 == lane, so no
+// barrier is needed between reflectors applied to one column.
+#include "krylov.h"
+
+namespace zolo {
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ void reduce_partials_kernel(double* __restrict__ out, int64_t ld_out, const double* __restrict__ partial,
+                                       int S, int M, int N, int add) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t MN = (int64_t)M * N;
+  if (e >= MN) return;
+  double s = 0.0;
+  for (int q = 0; q < S; ++q) s += partial[q * MN + e];
+  int64_t i = e % M, j = e / M;
+  double* o = out + i + j * ld_out;
+  *o = add ? *o + s : s;
+}
+
+// single workgroup; G is read, R/Rinv written (all col-major p x p)
+__global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __restrict__ G, int p, double rel_shift,
+                                                              double* __restrict__ R, double* __restrict__ Rinv,
+                                                              int* flag) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double trace_s;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += G[i + (int64_t)i * p];
+    trace_s = tr;
+  }
+  __syncthreads();
+  const double shift = rel_shift * trace_s / (p > 0 ? p : 1);
+  // R := upper part of G (+ shift on the diagonal), factor in place
+  for (int e = tid; e < p * p; e += nt) {
+    int i = e % p, j = e / p;
+    double v = (i <= j) ? G[e] : 0.0;
+    if (i == j) v += shift;
+    R[e] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    double dkk = R[k + (int64_t)k * p];
+    if (!(dkk > 1e-300)) {
+      if (tid == 0) *flag = 1;
+      dkk = 1.0;
+    }
+    double rk = sqrt(dkk);
+    __syncthreads();
+    // row k: R(k, k) = sqrt(d_kk), R(k, j) /= R(k, k) for j > k
+    for (int j = k + tid; j < p; j += nt) {
+      if (j == k)
+        R[k + (int64_t)k * p] = rk;
+      else
+        R[k + (int64_t)j * p] /= rk;
+    }
+    __threadfence_block();
+    __syncthreads();
+    // trailing: R(i, j) -= R(k, i) R(k, j) for k < i <= j
+    int m = p - k - 1;
+    for (int e = tid; e < m * m; e += nt) {
+      int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (i <= j) R[i + (int64_t)j * p] -= R[k + (int64_t)i * p] * R[k + (int64_t)j * p];
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // Rinv: column j, back substitution
+  for (int j = tid; j < p; j += nt) {
+    for (int i = 0; i < p; ++i) Rinv[i + (int64_t)j * p] = 0.0;
+    Rinv[j + (int64_t)j * p] = 1.0 / R[j + (int64_t)j * p];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int t = i + 1; t <= j; ++t) s += R[i + (int64_t)t * p] * Rinv[t + (int64_t)j * p];
+      Rinv[i + (int64_t)j * p] = -s / R[i + (int64_t)i * p];
+    }
+  }
+}
+
+__global__ void upper_mul_kernel(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
+                                 int p) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  int i = e % p, j = e / p;
+  double s = 0.0;
+  for (int t = i; t <= j; ++t) s += A[i + t * p] * B[t + j * p];
+  C[e] = (i <= j) ? s : 0.0;
+}
+
+__global__ void put_block_kernel(double* __restrict__ H, int64_t ldh, int64_t r0, int64_t c0,
+                                 const double* __restrict__ X, int p) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  int i = e % p, j = e / p;
+  H[(r0 + i) + (c0 + j) * ldh] = X[e];
+}
+
+// ---------------- shifted least squares ----------------
+__global__ void hls_init_kernel(HlsState st, const double* __restrict__ R0) {
+  const int s = blockIdx.y;
+  const int64_t tot = st.ldr * st.p;
+  zd* g = st.g + (int64_t)s * tot;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e % st.ldr, c = e / st.ldr;
+    g[e] = (i < st.p) ? zd{R0[i + c * st.p], 0.0} : zd{0.0, 0.0};
+  }
+}
+
+// one wave per (column c, shift s): load block column k, apply reflectors of blocks < k
+__global__ __launch_bounds__(64) void hls_apply_prev_kernel(HlsState st, const double* __restrict__ H, int64_t ldh,
+                                                            int k) {
+  const int c = blockIdx.x, s = blockIdx.y, lane = threadIdx.x;
+  const int p = st.p;
+  const int64_t ldr = st.ldr;
+  zd* Rs = st.R + (int64_t)s * ldr * st.mmax * p;
+  zd* col = Rs + ((int64_t)k * p + c) * ldr;
+  const int64_t rows = (int64_t)(k + 2) * p;
+  const double* hc = H + ((int64_t)k * p + c) * ldh;
+  const double sh = st.shift_im[s];
+  for (int64_t i = lane; i < ldr; i += 64) {
+    zd v{i < rows ? hc[i] : 0.0, 0.0};
+    if (i == (int64_t)k * p + c) v.im += sh;
+    col[i] = v;
+  }
+  const zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  const double* tau = st.tau + (int64_t)s * st.mmax * p;
+  for (int j = 0; j < k; ++j) {
+    for (int q = 0; q < p; ++q) {
+      const zd* v = refl + ((int64_t)j * p + q) * (p + 1);
+      const double t = tau[(int64_t)j * p + q];
+      const int64_t base = (int64_t)j * p + q;
+      // lane owns rows r with r % 64 == lane: i = r - base
+      int i0 = (int)((lane - base % 64 + 64) % 64);
+      double dr = 0.0, di = 0.0;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i], x = col[base + i];
+        dr += vv.re * x.re + vv.im * x.im;  // conj(v) x
+        di += vv.re * x.im - vv.im * x.re;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double fr = t * dr, fi = t * di;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i];
+        zd x = col[base + i];
+        x.re -= fr * vv.re - fi * vv.im;
+        x.im -= fr * vv.im + fi * vv.re;
+        col[base + i] = x;
+      }
+    }
+  }
+}
+
+// one workgroup (4 waves) per shift: reduce the new panel, update g, residuals
+__global__ __launch_bounds__(256) void hls_factor_kernel(HlsState st, int k, double* __restrict__ res) {
+  const int s = blockIdx.x;
+  const int p = st.p;
+  const int64_t ldr = st.ldr;
+  const int tid = threadIdx.x, lane = tid % 64, wave = tid / 64;
+  zd* Rs = st.R + (int64_t)s * ldr * st.mmax * p;
+  zd* g = st.g + (int64_t)s * ldr * p;
+  zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  double* tau = st.tau + (int64_t)s * st.mmax * p;
+  __shared__ double tau_s;
+  for (int q = 0; q < p; ++q) {
+    const int64_t base = (int64_t)k * p + q;
+    zd* colq = Rs + base * ldr;  // column k p + q
+    zd* v = refl + ((int64_t)k * p + q) * (p + 1);
+    if (wave == 0) {
+      int i0 = (int)((lane - base % 64 + 64) % 64);
+      double nrm = 0.0;
+      for (int i = i0; i <= p; i += 64) {
+        zd x = colq[base + i];
+        nrm += x.re * x.re + x.im * x.im;
+      }
+      nrm = sqrt(wave_sum(nrm));
+      zd x0 = colq[base];
+      double ax0 = sqrt(x0.re * x0.re + x0.im * x0.im);
+      double phr = ax0 > 0.0 ? x0.re / ax0 : 1.0, phi = ax0 > 0.0 ? x0.im / ax0 : 0.0;
+      // v = x + phase(x0) ||x|| e1 ; P = I - tau v v^H ; P x = -phase ||x|| e1
+      double vn2 = 0.0;
+      for (int i = i0; i <= p; i += 64) {
+        zd x = colq[base + i];
+        if (i == 0) {
+          x.re += phr * nrm;
+          x.im += phi * nrm;
+        }
+        v[i] = x;
+        vn2 += x.re * x.re + x.im * x.im;
+      }
+      vn2 = wave_sum(vn2);
+      double t = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      for (int i = i0; i <= p; i += 64) colq[base + i] = (i == 0) ? zd{-phr * nrm, -phi * nrm} : zd{0.0, 0.0};
+      if (lane == 0) {
+        tau[(int64_t)k * p + q] = t;
+        tau_s = t;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    const double t = tau_s;
+    // apply to panel columns q+1..p-1 and to the p columns of g (fixed wave per column)
+    const int ncols = (p - q - 1) + p;
+    for (int cc = wave; cc < ncols; cc += 4) {
+      zd* y = (cc < p - q - 1) ? Rs + ((int64_t)k * p + q + 1 + cc) * ldr : g + (int64_t)(cc - (p - q - 1)) * ldr;
+      int i0 = (int)((lane - base % 64 + 64) % 64);
+      double dr = 0.0, di = 0.0;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i], x = y[base + i];
+        dr += vv.re * x.re + vv.im * x.im;
+        di += vv.re * x.im - vv.im * x.re;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double fr = t * dr, fi = t * di;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i], x = y[base + i];
+        x.re -= fr * vv.re - fi * vv.im;
+        x.im -= fr * vv.im + fi * vv.re;
+        y[base + i] = x;
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // residual norms: rows (k+1)p .. (k+2)p of g
+  for (int c = wave; c < p; c += 4) {
+    const zd* y = g + (int64_t)c * ldr;
+    double n2 = 0.0;
+    for (int i = lane; i < p; i += 64) {
+      zd x = y[(int64_t)(k + 1) * p + i];
+      n2 += x.re * x.re + x.im * x.im;
+    }
+    n2 = wave_sum(n2);
+    if (lane == 0) res[(int64_t)s * p + c] = sqrt(n2);
+  }
+}
+
+// one wave per (column c, shift s): Y = R^{-1} g over the first m p rows
+__global__ __launch_bounds__(64) void hls_backsolve_kernel(HlsState st, int m, zd* __restrict__ Y) {
+  const int c = blockIdx.x, s = blockIdx.y, lane = threadIdx.x;
+  const int p = st.p;
+  const int64_t ldr = st.ldr, mp = (int64_t)m * p;
+  const zd* Rs = st.R + (int64_t)s * ldr * st.mmax * p;
+  const zd* gs = st.g + (int64_t)s * ldr * p + (int64_t)c * ldr;
+  zd* y = Y + (int64_t)s * mp * p + (int64_t)c * mp;
+  for (int64_t i = lane; i < mp; i += 64) y[i] = gs[i];
+  for (int64_t t = mp - 1; t >= 0; --t) {
+    // owner lane of row t computes y_t and broadcasts it
+    zd yt{0.0, 0.0};
+    if (lane == (int)(t % 64)) {
+      zd r = Rs[t + t * ldr], v = y[t];
+      double den = r.re * r.re + r.im * r.im;
+      yt = zd{(v.re * r.re + v.im * r.im) / den, (v.im * r.re - v.re * r.im) / den};
+      y[t] = yt;
+    }
+    yt.re = __shfl(yt.re, (int)(t % 64), 64);
+    yt.im = __shfl(yt.im, (int)(t % 64), 64);
+    const zd* rc = Rs + t * ldr;
+    for (int64_t i = lane; i < t; i += 64) {
+      zd r = rc[i], v = y[i];
+      v.re -= r.re * yt.re - r.im * yt.im;
+      v.im -= r.re * yt.im + r.im * yt.re;
+      y[i] = v;
+    }
+  }
+}
+
+__global__ void hls_combine_real_kernel(const zd* __restrict__ Y, int64_t mp, int p, int nshift,
+                                        const double* __restrict__ coef, double* __restrict__ C) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * p) return;
+  double s = 0.0;
+  for (int q = 0; q < nshift; ++q) s += coef[q] * Y[(int64_t)q * mp * p + e].re;
+  C[e] = s;
+}
+
+// ---------------- Rayleigh-Ritz (single workgroup) ----------------
+// cyclic Jacobi, round-robin parallel order, on a symmetric n x n matrix A
+// (col-major, global), accumulating V.  All threads of the block participate.
+__device__ void jacobi_block(double* A, double* V, int n, int max_sweeps, double tol) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int m = n + (n & 1);
+  const int half = m / 2;
+  __shared__ double cs_s[512], sn_s[512];
+  __shared__ int pp_s[512], qq_s[512];
+  __shared__ double red[1024];
+  for (int e = tid; e < n * n; e += nt) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  __threadfence_block();
+  __syncthreads();
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // off-diagonal and total Frobenius norms
+    double off = 0.0, tot = 0.0;
+    for (int e = tid; e < n * n; e += nt) {
+      double v = A[e];
+      tot += v * v;
+      if (e % n != e / n) off += v * v;
+    }
+    red[tid] = off;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    off = red[0];
+    __syncthreads();
+    red[tid] = tot;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    tot = red[0];
+    __syncthreads();
+    if (off <= tol * tol * tot || tot == 0.0) break;
+    for (int r = 0; r < m - 1; ++r) {
+      if (tid < half) {
+        int k = tid;
+        int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
+        int bpos = m - 1 - k;
+        int b = ((bpos - 1 + r) % (m - 1)) + 1;
+        int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          double apq = A[p + (int64_t)q * n];
+          if (apq != 0.0) {
+            double tau = (A[q + (int64_t)q * n] - A[p + (int64_t)p * n]) / (2.0 * apq);
+            double t;
+            if (fabs(tau) > 1e150)
+              t = 0.5 / tau;
+            else
+              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        cs_s[k] = c;
+        sn_s[k] = s;
+        pp_s[k] = p;
+        qq_s[k] = q < n ? q : -1;
+      }
+      __syncthreads();
+      // columns of A and V
+      for (int e = tid; e < n * half; e += nt) {
+        int i = e % n, k = e / n;
+        int q = qq_s[k];
+        if (q < 0) continue;
+        int p = pp_s[k];
+        double c = cs_s[k], s = sn_s[k];
+        double ap = A[i + (int64_t)p * n], aq = A[i + (int64_t)q * n];
+        A[i + (int64_t)p * n] = c * ap - s * aq;
+        A[i + (int64_t)q * n] = s * ap + c * aq;
+        double vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
+        V[i + (int64_t)p * n] = c * vp - s * vq;
+        V[i + (int64_t)q * n] = s * vp + c * vq;
+      }
+      __threadfence_block();
+      __syncthreads();
+      // rows of A
+      for (int e = tid; e < n * half; e += nt) {
+        int j = e % n, k = e / n;
+        int q = qq_s[k];
+        if (q < 0) continue;
+        int p = pp_s[k];
+        double c = cs_s[k], s = sn_s[k];
+        double ap = A[p + (int64_t)j * n], aq = A[q + (int64_t)j * n];
+        A[p + (int64_t)j * n] = c * ap - s * aq;
+        A[q + (int64_t)j * n] = s * ap + c * aq;
+      }
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restrict__ At, const double* __restrict__ Bt,
+                                                         int n, double tau_rank, double* __restrict__ theta,
+                                                         double* __restrict__ Cmat, int* k_out, double* work) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t nn = (int64_t)n * n;
+  double* As = work;
+  double* Bs = work + nn;
+  double* U = work + 2 * nn;
+  double* T = work + 3 * nn;
+  double* M1 = work + 4 * nn;
+  double* W = work + 5 * nn;
+  double* d = work + 6 * nn;
+  double* sv = d + n;
+  int* idx = (int*)(sv + n);
+  int* rank = idx + n;
+  __shared__ int k_s;
+  __shared__ double smax_s;
+  for (int i = tid; i < n; i += nt) {
+    double b = Bt[i + (int64_t)i * n];
+    d[i] = b > 0.0 ? sqrt(b) : 1.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int64_t e = tid; e < nn; e += nt) {
+    int i = (int)(e % n), j = (int)(e / n);
+    double s = 1.0 / (d[i] * d[j]);
+    // symmetrise
+    As[e] = 0.5 * (At[e] + At[j + (int64_t)i * n]) * s;
+    Bs[e] = 0.5 * (Bt[e] + Bt[j + (int64_t)i * n]) * s;
+  }
+  __threadfence_block();
+  __syncthreads();
+  jacobi_block(Bs, U, n, 40, 1e-15);
+  __syncthreads();
+  for (int i = tid; i < n; i += nt) sv[i] = Bs[i + (int64_t)i * n];
+  __threadfence_block();
+  __syncthreads();
+  if (tid == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = sv[i] > mx ? sv[i] : mx;
+    smax_s = mx;
+    int k = 0;
+    for (int i = 0; i < n; ++i)
+      if (sv[i] > tau_rank * mx) idx[k++] = i;
+    k_s = k;
+  }
+  __threadfence_block();
+  __syncthreads();
+  const int k = k_s;
+  // T(:, j) = U(:, idx_j) / sqrt(s_idx_j)   (n x k, ld n)
+  for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
+    int i = (int)(e % n), j = (int)(e / n);
+    int c = idx[j];
+    T[e] = U[i + (int64_t)c * n] / sqrt(sv[c]);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // M1 = As T (n x k); Ar = T^T M1 (k x k, ld n) into Bs
+  for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
+    int i = (int)(e % n), j = (int)(e / n);
+    double s = 0.0;
+    for (int t = 0; t < n; ++t) s += As[i + (int64_t)t * n] * T[t + (int64_t)j * n];
+    M1[e] = s;
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)k * k; e += nt) {
+    int i = (int)(e % k), j = (int)(e / k);
+    double s = 0.0;
+    for (int t = 0; t < n; ++t) s += T[t + (int64_t)i * n] * M1[t + (int64_t)j * n];
+    As[i + (int64_t)j * k] = s;  // reuse As as k x k (ld k)
+  }
+  __threadfence_block();
+  __syncthreads();
+  for (int64_t e = tid; e < (int64_t)k * k; e += nt) {
+    int i = (int)(e % k), j = (int)(e / k);
+    Bs[e] = 0.5 * (As[i + (int64_t)j * k] + As[j + (int64_t)i * k]);
+  }
+  __threadfence_block();
+  __syncthreads();
+  jacobi_block(Bs, W, k, 40, 1e-15);
+  __syncthreads();
+  // ascending order of the Ritz values
+  for (int i = tid; i < k; i += nt) {
+    double ti = Bs[i + (int64_t)i * k];
+    int r = 0;
+    for (int j = 0; j < k; ++j) {
+      double tj = Bs[j + (int64_t)j * k];
+      if (tj < ti || (tj == ti && j < i)) ++r;
+    }
+    rank[i] = r;
+    theta[r] = ti;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // Cmat(:, rank_j) = D^-1 T W(:, j)
+  for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
+    int i = (int)(e % n), j = (int)(e / n);
+    double s = 0.0;
+    for (int t = 0; t < k; ++t) s += T[i + (int64_t)t * n] * W[t + (int64_t)j * k];
+    Cmat[i + (int64_t)rank[j] * n] = s / d[i];
+  }
+  if (tid == 0) *k_out = k;
+}
+
+constexpr int RN_ROWS = 512;
+
+__global__ void resid_partial_kernel(const double* __restrict__ AX, const double* __restrict__ BX,
+                                     const double* __restrict__ X, const double* __restrict__ theta, int64_t n, int k,
+                                     double* __restrict__ partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * RN_ROWS;
+  const int64_t r1 = r0 + RN_ROWS < n ? r0 + RN_ROWS : n;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double th = theta[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int64_t i = r0; i < r1; ++i) {
+      double bx = BX[i * k + c], ax = AX[i * k + c], x = X[i * k + c];
+      double r = ax - th * bx;
+      s1 = fma(r, r, s1);
+      s2 = fma(x, x, s2);
+      s3 = fma(bx, bx, s3);
+    }
+    double* o = partial + (int64_t)blockIdx.x * 3 * k;
+    o[3 * c] = s1;
+    o[3 * c + 1] = s2;
+    o[3 * c + 2] = s3;
+  }
+}
+
+__global__ void resid_final_kernel(const double* __restrict__ partial, int nb, int k3, double* __restrict__ out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k3) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * k3 + c];
+  out[c] = s;
+}
+
+}  // namespace
+
+void reduce_partials(double* out, int64_t ld_out, const double* partial, int S, int M, int N, bool add,
+                     hipStream_t s) {
+  int64_t MN = (int64_t)M * N;
+  if (MN == 0) return;
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, out, ld_out,
+                     partial, S, M, N, add ? 1 : 0);
+}
+
+void chol_upper_inv(const double* G, int p, double rel_shift, double* R, double* Rinv, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
+}
+
+void upper_mul(const double* A, const double* B, double* C, int p, hipStream_t s) {
+  hipLaunchKernelGGL(upper_mul_kernel, dim3((p * p + 255) / 256), dim3(256), 0, s, A, B, C, p);
+}
+
+void put_block(double* H, int64_t ldh, int64_t r0, int64_t c0, const double* X, int p, hipStream_t s) {
+  hipLaunchKernelGGL(put_block_kernel, dim3((p * p + 255) / 256), dim3(256), 0, s, H, ldh, r0, c0, X, p);
+}
+
+void hls_init(const HlsState& st, const double* R0, hipStream_t s) {
+  hipLaunchKernelGGL(hls_init_kernel, dim3(64, st.nshift), dim3(256), 0, s, st, R0);
+}
+
+void hls_step(const HlsState& st, const double* H, int64_t ldh, int k, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(hls_apply_prev_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, H, ldh, k);
+  hipLaunchKernelGGL(hls_factor_kernel, dim3(st.nshift), dim3(256), 0, s, st, k, res);
+}
+
+void hls_backsolve(const HlsState& st, int m, zd* Y, hipStream_t s) {
+  hipLaunchKernelGGL(hls_backsolve_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, m, Y);
+}
+
+void hls_combine_real(const zd* Y, int m, int p, int nshift, const double* coef, double* C, hipStream_t s) {
+  int64_t mp = (int64_t)m * p;
+  hipLaunchKernelGGL(hls_combine_real_kernel, dim3((unsigned)((mp * p + 255) / 256)), dim3(256), 0, s, Y, mp, p,
+                     nshift, coef, C);
+}
+
+void rr_reduce(const double* At, const double* Bt, int n, double tau_rank, double* theta, double* Cmat, int* k_out,
+               double* work, hipStream_t s) {
+  hipLaunchKernelGGL(rr_reduce_kernel, dim3(1), dim3(1024), 0, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
+}
+
+void resid_norms(const double* AX, const double* BX, const double* X, const double* theta, int64_t n, int k,
+                 double* partial, double* out, hipStream_t s) {
+  int nb = (int)((n + RN_ROWS - 1) / RN_ROWS);
+  if (nb == 0 || k == 0) return;
+  hipLaunchKernelGGL(resid_partial_kernel, dim3(nb), dim3(128), 0, s, AX, BX, X, theta, n, k, partial);
+  hipLaunchKernelGGL(resid_final_kernel, dim3((3 * k + 127) / 128), dim3(128), 0, s, partial, nb, 3 * k, out);
+}
+
+}  // namespace zolo

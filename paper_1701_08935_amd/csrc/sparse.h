@@ -1,0 +1,35 @@
+// CSR products and elementwise kernels on N x p row-major blocks.
+#pragma once
+
+#include "dev_common.h"
+
+namespace zolo {
+
+// Ya = A X, and Yb = B X when Yb != null (A, B share the CSR pattern).
+void spmm_real(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* a, const double* b,
+               const double* X, int64_t ldx, int p, double* Ya, int64_t ldya, double* Yb, int64_t ldyb,
+               hipStream_t s);
+// R = T - (A - sigma B) X  with X complex, T real (refinement residual, FP64).
+void spmm_shift_resid(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* a, const double* b,
+                      double sr, double si, const zd* X, const double* T, int64_t ldt, int p, zd* R, hipStream_t s);
+// row permutations of N x p blocks: gather dst[i] = src[idx[i]], scatter dst[idx[i]] = src[i]
+template <typename T>
+void rows_gather(T* dst, int64_t ldd, const T* src, int64_t lds, const int32_t* idx, int64_t n, int p, hipStream_t s);
+template <typename T>
+void rows_scatter(T* dst, int64_t ldd, const T* src, int64_t lds, const int32_t* idx, int64_t n, int p,
+                  hipStream_t s);
+// W = alpha V (real)
+void scale_copy(double* W, int64_t ldw, const double* V, int64_t ldv, double alpha, int64_t n, int p, hipStream_t s);
+// W += 2 * Re(w * X)  (X complex, contiguous N x p)
+void axpy_re(double* W, int64_t ldw, const zd* X, double wr, double wi, int64_t n, int p, hipStream_t s);
+// X += cvt(D)
+void add_lowp(zd* X, const zf* D, int64_t n, hipStream_t s);
+void add_same(zd* X, const zd* D, int64_t n, hipStream_t s);
+// column sums of |x|^2 (N x p row-major, real or complex) into out[p] (device)
+void colnorm2_real(const double* X, int64_t ldx, int64_t n, int p, double* partial, double* out, hipStream_t s);
+void colnorm2_cplx(const zd* X, int64_t n, int p, double* partial, double* out, hipStream_t s);
+int colnorm_partials(int64_t n);
+// C = Y + V (both N x p real, row-major), used for Y = V/2 + ...
+void fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace zolo

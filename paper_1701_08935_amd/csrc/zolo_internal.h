@@ -1,0 +1,67 @@
+// Internal declarations shared by the host code of the library.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/zolo.h"
+
+namespace zolo {
+
+void set_error(const char* fmt, ...);
+
+int plan_filter(double am, double ap, double bm, double bp, int r1, int r2, double eps, zolo_filter_coeffs* out,
+                char* err, size_t errlen);
+
+// ---------------------------------------------------------------------------
+// Symbolic analysis (multifrontal method, Sec. 2.3 pre-factorization phase).
+// Vertices are renumbered by nested dissection in post-order, so the
+// vertices of a front are a contiguous range [first, first + ns) and all its
+// off-diagonal rows ("struct") belong to ancestors (indices >= first + ns).
+// ---------------------------------------------------------------------------
+struct Front {
+  int32_t first = 0;
+  int32_t ns = 0;          // fully summed (eliminated) variables
+  int32_t nb = 0;          // rows of the update (contribution) block
+  int32_t parent = -1;
+  int32_t level = 0;       // height: leaves 0
+  int64_t struct_off = 0;  // into Symbolic::struct_rows, nb entries
+  int32_t child_begin = 0; // into Symbolic::children
+  int32_t child_count = 0;
+  int64_t asm_begin = 0, asm_end = 0;  // into asm_entry / asm_pos
+};
+
+struct Symbolic {
+  int64_t n = 0;
+  std::vector<int32_t> perm;   // perm[new] = old
+  std::vector<int32_t> iperm;  // iperm[old] = new
+  std::vector<Front> fronts;   // post-order
+  std::vector<int32_t> struct_rows;  // concatenated struct lists (new indices, ascending)
+  std::vector<int32_t> parent_map;   // per struct entry: local row in the parent front
+  std::vector<int32_t> children;
+  std::vector<std::vector<int32_t>> levels;  // front ids by height
+  // permuted CSR (new ordering); psrc[e_new] = e_old
+  std::vector<int64_t> prow;
+  std::vector<int32_t> pcol;
+  std::vector<int64_t> psrc;
+  // assembly of original entries: lower-triangle entries of each front's columns
+  std::vector<int64_t> asm_entry;  // entry index in the permuted CSR
+  std::vector<int64_t> asm_pos;    // row_local + col_local * k in the front panel
+  // figures
+  int64_t panel_entries = 0;   // sum k * ns
+  int64_t inv_entries = 0;     // sum ns * ns
+  int64_t update_entries = 0;  // sum nb * nb
+  int64_t struct_total = 0;    // sum nb
+  int64_t max_front = 0;
+  int max_children = 0;
+  double flops = 0.0;          // real flops of one complex factorization
+};
+
+// Build the symbolic structure.  grid may be null.  Returns ZOLO_OK or an error code.
+int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* grid, int leaf_size,
+                     Symbolic* S);
+
+}  // namespace zolo

@@ -1,0 +1,148 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle.
+
+Every test prints the case it is about to run before touching the GPU.
+Tolerances: SpMM 1e-13 relative (reordered sums of at most 27 terms);
+pole solves 1e-10 relative (kappa(A - sigma B) ~ 1e3-1e4 times FP64 rounding);
+operator G and the filter 1e-10/1e-9 relative (G combines r1 solves; the filter
+adds the GMRES tolerance 1e-12 used here); eigenpairs: exact count,
+eigenvalues 1e-10 relative, residual 1e-8, B-orthonormality 1e-10.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import pencils
+from oracle.dense import exact_filter, exact_G, pencil_eigh_lapack
+from oracle.filt import FilterPlan
+from oracle.subspace import inf_norm
+
+from .conftest import golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+zolo = pytest.importorskip("paper_1701_08935_amd")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return zolo.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _window(n):
+    return json.load(open(golden(f"window_grid7_{n}.json")))
+
+
+@pytest.mark.parametrize("shape", [(10, 10, 10), (13, 9, 11), (4, 4, 4)])
+@pytest.mark.parametrize("p", [24, 13, 1])
+def test_spmm_parity(ctx, shape, p):
+    say(f"spmm grid {shape} p={p}")
+    gp = pencils.grid7(shape[0], ny=shape[1], nz=shape[2])
+    A, B = gp.scipy()
+    X = pencils.gaussian_block(gp.n, p, seed=11)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=16)
+    for which, M in ((0, A), (1, B)):
+        Y = zolo.zolo_spmm(P, which, _dev(X)).cpu().numpy()
+        ref = M @ X
+        assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("n,leaf,use_grid", [(8, 16, True), (10, 64, True), (10, 8, False), (12, 32, True)])
+def test_pole_solve_parity(ctx, n, leaf, use_grid):
+    say(f"pole solve grid {n}^3 leaf={leaf} grid={use_grid}")
+    w = _window(n)
+    gp = pencils.grid7(n)
+    A, B = gp.scipy()
+    co = zolo.zolo_filter_plan(w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"], 2, 3)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=leaf, use_grid=use_grid)
+    F = zolo.Factors(ctx, P, co, zolo.ZOLO_PREC_FP64)
+    V = pencils.gaussian_block(gp.n, 7, seed=3)
+    T = B @ V
+    for j in range(2):
+        sig = co.sigma_hat_re[j] + 1j * co.sigma_hat_im[j]
+        X = zolo.zolo_pole_solve(F, j, _dev(T)).cpu().numpy()
+        ref = np.linalg.solve((A - sig * B).toarray(), T.astype(np.complex128))
+        err = np.max(np.abs(X - ref)) / np.max(np.abs(ref))
+        say(f"  pole {j}: rel err {err:.2e}")
+        assert err < 1e-10
+
+
+def test_pole_solve_mixed_refines_to_fp64(ctx):
+    say("pole solve mixed precision grid 10^3")
+    n = 10
+    w = _window(n)
+    gp = pencils.grid7(n)
+    A, B = gp.scipy()
+    co = zolo.zolo_filter_plan(w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"], 2, 3)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    F = zolo.Factors(ctx, P, co, zolo.ZOLO_PREC_MIXED)
+    V = pencils.gaussian_block(gp.n, 5, seed=4)
+    T = B @ V
+    sig = co.sigma_hat_re[0] + 1j * co.sigma_hat_im[0]
+    X = zolo.zolo_pole_solve(F, 0, _dev(T)).cpu().numpy()
+    ref = np.linalg.solve((A - sig * B).toarray(), T.astype(np.complex128))
+    err = np.max(np.abs(X - ref)) / np.max(np.abs(ref))
+    say(f"  mixed rel err {err:.2e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("n", [8, 10])
+def test_apply_G_and_filter_parity(ctx, n):
+    say(f"G and filter grid {n}^3")
+    w = _window(n)
+    gp = pencils.grid7(n)
+    A, B = gp.scipy()
+    lam, Xall = pencil_eigh_lapack(A.toarray(), B.toarray())
+    for r2 in (2, 5):
+        f = FilterPlan(w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"], 2, r2)
+        co = zolo.zolo_filter_plan(w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"], 2, r2)
+        P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+        F = zolo.Factors(ctx, P, co, zolo.ZOLO_PREC_FP64)
+        V = pencils.gaussian_block(gp.n, 12, seed=5)
+        G = zolo.zolo_apply_G(F, _dev(V)).cpu().numpy()
+        Gref = exact_G(lam, Xall, B, V, f.g)
+        eg = np.max(np.abs(G - Gref)) / np.max(np.abs(Gref))
+        say(f"  r2={r2} G rel err {eg:.2e}")
+        assert eg < 1e-10
+        Y, st = zolo.zolo_filter_apply(F, _dev(V), tol=1e-12, max_iter=60)
+        Y = Y.cpu().numpy()
+        Yref = exact_filter(lam, Xall, B, V, f.R)
+        ey = np.max(np.abs(Y - Yref)) / np.max(np.abs(Yref))
+        say(f"  r2={r2} filter rel err {ey:.2e} gmres {st}")
+        assert ey < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_window_10(ctx, precision):
+    say(f"zolo_solve grid 10^3 window 16 precision={precision}")
+    w = _window(10)
+    gp = pencils.grid7(10)
+    A, B = gp.scipy()
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    Q0 = pencils.gaussian_block(gp.n, 24, seed=2)
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=24, precision=precision)
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts, Q0=_dev(Q0))
+    say(f"  rc={rc} stats={ {k: st[k] for k in ('n_iter', 'n_gmres_total', 'max_resid', 'b_orth', 'r2', 'n_found')} }")
+    assert rc == 0
+    ref = np.array(w["eigenvalues"])
+    assert len(eig) == 16
+    assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) < 1e-10
+    X = vec.cpu().numpy()
+    r = np.linalg.norm(A @ X - (B @ X) * np.array(eig)[None, :], axis=0) / (
+        (inf_norm(A) + np.abs(eig) * inf_norm(B)) * np.linalg.norm(X, axis=0))
+    assert np.max(r) < 1e-8
+    assert np.max(np.abs(X.T @ (B @ X) - np.eye(16))) < 1e-10
+    assert st["max_resid"] < 1e-8
