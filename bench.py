@@ -1,0 +1,228 @@
+"""Benchmark of the hot path on one MI355X: eigenpairs/s of Algorithm 1 with
+the hybrid Zolotarev filter (Algorithm 2) on a synthetic stencil pencil.
+
+A step is one full interval query -- filter plan, numeric factorization of the
+r1 shifted matrices, subspace iterations (block multi-shift GMRES on G, the
+weighted sum, Rayleigh-Ritz), residual check -- on a pencil whose CSR, nested
+dissection and symbolic analysis are resident (done once per pencil, reported
+separately).  Inputs (CSR, start block) are in HBM before the timed region.
+
+Workloads (seeded, see pencils/ and tests/golden/make_windows.py):
+  c1  grid7 64^3, N = 262144, mid-spectrum window of 64 eigenvalues, block 96,
+      r1 = 2 factored shifts, FP64 / complex128 factors           (default)
+  c2  the c1 pencil with complex64 factors refined against FP64 residuals
+  c0  grid7 10^3, N = 1000, window of 16, subspace 24
+  m32 / m32x  grid7 32^3 (N = 32768), window of 64, block 96, FP64 / mixed
+Prints one JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "eigenpairs/s at resid≤1e-8, mixed vs FP64 filter; p50/p99 slice-query latency"
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "c0": {"grid": 10, "n_lambda": 16, "n_ss": 24, "precision": 0},
+    "c1": {"grid": 64, "n_lambda": 64, "n_ss": 96, "precision": 0},
+    "c2": {"grid": 64, "n_lambda": 64, "n_ss": 96, "precision": 1},
+    "m32": {"grid": 32, "n_lambda": 64, "n_ss": 96, "precision": 0},
+    "m32x": {"grid": 32, "n_lambda": 64, "n_ss": 96, "precision": 1},
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(name, steps, warmup, leaf, r1, profile=True):
+    import numpy as np
+    import torch
+
+    import paper_1701_08935_amd as z
+    import pencils
+
+    wl = WORKLOADS[name]
+    n = wl["grid"]
+    w = json.load(open(os.path.join(ROOT, "tests", "golden", f"window_grid7_{n}.json")))
+    gp = pencils.grid7(n)
+    log(f"[bench] {name}: grid {n}^3 N={gp.n} nnz={gp.nnz}")
+    ctx = z.Context(0)
+    t0 = time.perf_counter()
+    P = z.Pencil.from_grid(ctx, gp, leaf_size=leaf)
+    t_sym = time.perf_counter() - t0
+    info = P.info()
+    log(f"[bench] symbolic {t_sym:.2f}s {info}")
+    Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, wl["n_ss"], seed=2)).to("cuda:0")
+    opts = z.opts_from_window(w, r1=r1, r2=0, n_ss=wl["n_ss"], precision=wl["precision"])
+    lat = []
+    last = None
+    for it in range(warmup + steps):
+        timed = it >= warmup
+        if timed and profile and it == warmup:
+            z.zolo_profile_enable(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eig, vec, st, rc = z.zolo_solve(ctx, P, w["a"], w["b"], wl["n_lambda"], opts, Q0=Q0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        log(f"[bench] step {it} {'timed' if timed else 'warmup'} {dt:.3f}s rc={rc} found={len(eig)} "
+            f"iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e} "
+            f"t_factor={st['t_factor']:.3f} t_iter={st['t_iter']:.3f}")
+        if timed:
+            lat.append(dt)
+        last = (eig, st, rc)
+    prof = z.zolo_profile_query() if profile else None
+    if profile:
+        z.zolo_profile_enable(False)
+    eig, st, rc = last
+    ref = np.array(w["eigenvalues"])
+    ok = (rc == 0 and len(eig) == len(ref) and st["max_resid"] <= 1e-8)
+    err = float(np.max(np.abs(np.array(eig) - ref) / np.abs(ref))) if len(eig) == len(ref) else float("inf")
+    verified = len(eig) if ok and err <= 1e-10 else 0
+    return {"lat": lat, "stats": st, "verified": verified, "eig_err": err, "prof": prof, "t_sym": t_sym,
+            "info": info, "n": gp.n, "nnz": gp.nnz, "rc": rc}
+
+
+def roofline(prof, steps, fp32=False):
+    if not prof:
+        return None
+    cand = {k: v for k, v in prof.items() if k in ("gemm_factor", "gemm_solve", "gemm_krylov", "spmm") and v["ms"] > 0}
+    if not cand:
+        return None
+    k, v = max(cand.items(), key=lambda kv: kv[1]["ms"])
+    sec = v["ms"] * 1e-3
+    if k == "spmm":
+        ach = v["bytes"] / sec / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "launches": v["launches"],
+                "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
+    peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
+    ach = v["flops"] / sec / 1e12
+    return {"kernel": k, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "traffic": None, "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
+
+
+def cpu_baseline(sample_grid=16, n_lambda=64, n_ss=96):
+    """The oracle's CPU Algorithm 1+2 (SuperLU factors, numpy block GMRES) on a
+    bounded sample: the same stencil construction on a smaller grid."""
+    import numpy as np
+
+    import pencils
+    from oracle.filt import FilterPlan, select_r2
+    from oracle.sparse import zoloeig_cpu
+
+    path = os.path.join(ROOT, "tests", "golden", f"window_grid7_{sample_grid}.json")
+    if not os.path.exists(path):
+        return None
+    w = json.load(open(path))
+    gp = pencils.grid7(sample_grid)
+    A, B = gp.scipy()
+    g = (w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"])
+    r2 = select_r2(*g, r1=2, eps=1e-10)
+    plan = FilterPlan(*g, 2, r2)
+    Q0 = pencils.gaussian_block(gp.n, n_ss, seed=2)
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([1] + [int(d.get("num_threads", 1)) for d in threadpool_info()])
+    except Exception:
+        pass
+    t = time.perf_counter()
+    out = zoloeig_cpu(A, B, plan, w["a"], w["b"], Q0)
+    dt = time.perf_counter() - t
+    ok = len(out["theta"]) == w["n_lambda"] and out["res"].size and float(np.max(out["res"])) <= 1e-8
+    return {"value": (len(out["theta"]) if ok else 0) / dt, "unit": "eigenpairs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"grid7 {sample_grid}^3 (N={gp.n}), mid-spectrum window of {w['n_lambda']} eigenvalues, "
+                      f"n_ss={n_ss}, r1=2, r2={r2}: full Algorithm 1+2 on the CPU (SuperLU complex factors, "
+                      f"single-threaded; numpy BLAS {threads} threads), {dt:.1f}s",
+            "seconds": dt, "n_gmres": out["n_gmres"], "n_iter": out["n_iter"]}
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--r1", type=int, default=2)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
+              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    res = run_gpu(args.config, args.steps, args.warmup, args.leaf, args.r1)
+    lat = res["lat"]
+    ms = 1e3 * sum(lat) / len(lat)
+    value = res["verified"] / (ms * 1e-3)
+    st = res["stats"]
+    wl = WORKLOADS[args.config]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if wl["precision"] == 0 else "c64-factors+f64",
+        "data": "synthetic",
+        "config": {"workload": f"grid7 {wl['grid']}^3 stencil pencil (N={res['n']}), mid-spectrum window of "
+                               f"{wl['n_lambda']} eigenvalues, block {wl['n_ss']}, r1={st['r1']} factored shifts, "
+                               f"r2={st['r2']}",
+                   "N": res["n"], "nnz": res["nnz"], "n_lambda": wl["n_lambda"], "n_ss": wl["n_ss"],
+                   "r1": st["r1"], "r2": st["r2"], "leaf": args.leaf,
+                   "precision": "fp64" if wl["precision"] == 0 else "mixed"},
+        "latency_s": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)},
+        "eig_rel_err": res["eig_err"],
+        "max_resid": st["max_resid"],
+        "n_iter": st["n_iter"],
+        "n_gmres": st["n_gmres_total"],
+        "rhs_solves_per_s": st["n_solv"] / max(st["t_iter"], 1e-9),
+        "t_factor_s": st["t_factor"],
+        "t_iter_s": st["t_iter"],
+        "t_symbolic_s": res["t_sym"],
+        "roofline": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1),
+        "profile": res["prof"],
+    }
+    if args.config in ("c1", "m32") and not args.no_mixed:
+        mres = run_gpu("c2" if args.config == "c1" else "m32x", max(1, args.steps - 1), 1, args.leaf, args.r1, profile=False)
+        mms = 1e3 * sum(mres["lat"]) / len(mres["lat"])
+        mval = mres["verified"] / (mms * 1e-3)
+        out["mixed"] = {"value": mval, "ms_per_step": mms, "speedup_vs_fp64": mval / value if value else None,
+                        "eig_rel_err": mres["eig_err"], "max_resid": mres["stats"]["max_resid"],
+                        "n_refine": mres["stats"]["n_refine"], "t_factor_s": mres["stats"]["t_factor"]}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

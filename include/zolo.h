@@ -231,6 +231,34 @@ zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_dst, int64_t 
 zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out);
 void zolo_result_free(zolo_result* r);
 
+/*
+ * Kernel-class timing for measurement: when enabled, every launch of the
+ * library is bracketed by HIP events on the stream it is launched on, and
+ * the algorithmic work of the launch (flops, and the bytes the operation
+ * must move at least once) is accumulated per class.  Enabling resets the
+ * counters.  Not thread safe; for benchmarks.
+ */
+enum {
+  ZOLO_PROF_SPMM = 0,          /* CSR products B V, A Y, B Y                     */
+  ZOLO_PROF_GEMM_FACTOR = 1,   /* front trailing / Schur / inverse updates        */
+  ZOLO_PROF_GEMM_SOLVE = 2,    /* supernodal solve products                       */
+  ZOLO_PROF_GEMM_KRYLOV = 3,   /* CGS2, CholQR, assembly, Rayleigh-Ritz products  */
+  ZOLO_PROF_FRONT_OTHER = 4,   /* assembly, extend-add, diagonal blocks, panels   */
+  ZOLO_PROF_SOLVE_GATHER = 5,  /* row gathers / extend-adds of the solves         */
+  ZOLO_PROF_HLS = 6,           /* shifted Hessenberg least squares                */
+  ZOLO_PROF_RR = 7,            /* reduced eigenproblem                            */
+  ZOLO_PROF_ELEMWISE = 8,      /* G combine, reductions                           */
+  ZOLO_PROF_COUNT = 9
+};
+typedef struct {
+  long long launches;
+  double ms;      /* summed event time                      */
+  double flops;   /* algorithmic flops of those launches    */
+  double bytes;   /* algorithmic bytes of those launches    */
+} zolo_kernel_profile;
+zolo_status zolo_profile_enable(int on);
+zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -53,6 +53,14 @@ class zolo_stats(ctypes.Structure):
                 ("nnz_l", ctypes.c_longlong), ("factor_flops", _d)]
 
 
+class zolo_kernel_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_longlong), ("ms", _d), ("flops", _d), ("bytes", _d)]
+
+
+PROF_CLASSES = ["spmm", "gemm_factor", "gemm_solve", "gemm_krylov", "front_other", "solve_gather", "hls", "rr",
+                "elemwise"]
+
+
 class zolo_filter_stats(ctypes.Structure):
     _fields_ = [("n_gmres", _i), ("worst_resid", _d), ("breakdown", _i)]
 
@@ -93,6 +101,8 @@ _SIGS = {
     "zolo_result_copy_vectors": (_i, [_vp, _vp, _i64, _vp]),
     "zolo_result_stats": (_i, [_vp, ctypes.POINTER(zolo_stats)]),
     "zolo_result_free": (None, [_vp]),
+    "zolo_profile_enable": (_i, [_i]),
+    "zolo_profile_query": (_i, [_i, ctypes.POINTER(zolo_kernel_profile)]),
 }
 
 
@@ -292,6 +302,19 @@ def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts
     finally:
         lib().zolo_result_free(h)
     return eig, vec[:, :cnt], struct_dict(st), rc
+
+
+def zolo_profile_enable(on: bool = True):
+    _check(lib().zolo_profile_enable(1 if on else 0))
+
+
+def zolo_profile_query() -> dict:
+    out = {}
+    for i, name in enumerate(PROF_CLASSES):
+        p = zolo_kernel_profile()
+        _check(lib().zolo_profile_query(i, ctypes.byref(p)))
+        out[name] = struct_dict(p)
+    return out
 
 
 def opts_from_window(w: dict, r1=2, r2=0, n_ss=0, precision=ZOLO_PREC_FP64, **kw) -> zolo_opts:

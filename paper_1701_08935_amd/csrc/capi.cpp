@@ -119,7 +119,69 @@ void gaussian_host(uint64_t seed, size_t n, std::vector<double>* out) {
 
 struct GemmLaunch {
   int off = 0, cnt = 0, tiles = 0;
+  double flops = 0.0, bytes = 0.0;  // algorithmic work of the launch
 };
+
+// ---- per-kernel-class timing with HIP events on the launching stream ----
+namespace prof {
+bool on = false;
+struct Pend {
+  hipEvent_t a, b;
+  int cls;
+  double flops, bytes;
+};
+std::vector<Pend> pend;
+std::vector<hipEvent_t> pool;
+double ms[ZOLO_PROF_COUNT], fl[ZOLO_PROF_COUNT], by[ZOLO_PROF_COUNT];
+long long cnt[ZOLO_PROF_COUNT];
+hipEvent_t get_event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+void resolve() {
+  for (Pend& p : pend) {
+    float t = 0.0f;
+    (void)hipEventSynchronize(p.b);
+    if (hipEventElapsedTime(&t, p.a, p.b) == hipSuccess) ms[p.cls] += t;
+    fl[p.cls] += p.flops;
+    by[p.cls] += p.bytes;
+    cnt[p.cls] += 1;
+    pool.push_back(p.a);
+    pool.push_back(p.b);
+  }
+  pend.clear();
+}
+void reset() {
+  resolve();
+  for (int i = 0; i < ZOLO_PROF_COUNT; ++i) ms[i] = fl[i] = by[i] = 0.0, cnt[i] = 0;
+}
+struct Scope {
+  bool act;
+  Pend p;
+  hipStream_t s;
+  Scope(int cls, double flops, double bytes, hipStream_t st) : act(on), s(st) {
+    if (!act) return;
+    p.a = get_event();
+    p.b = get_event();
+    p.cls = cls;
+    p.flops = flops;
+    p.bytes = bytes;
+    (void)hipEventRecord(p.a, s);
+  }
+  ~Scope() {
+    if (!act) return;
+    (void)hipEventRecord(p.b, s);
+    pend.push_back(p);
+    if (pend.size() > 20000) resolve();
+  }
+};
+}  // namespace prof
 
 }  // namespace
 
@@ -261,8 +323,11 @@ int upload_gemm(DevArena& mem, const std::vector<GemmDesc<T>>& h, GemmDesc<T>** 
 }
 
 template <typename T>
-void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s) {
-  if (L.cnt > 0 && L.tiles > 0) gemm_batched<T>(base + L.off, L.cnt, L.tiles, s);
+void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s, int tag) {
+  if (L.cnt <= 0 || L.tiles <= 0) return;
+  prof::Scope ps(tag == 0 ? ZOLO_PROF_GEMM_FACTOR : tag == 1 ? ZOLO_PROF_GEMM_SOLVE : ZOLO_PROF_GEMM_KRYLOV, L.flops,
+                 L.bytes, s);
+  gemm_batched<T>(base + L.off, L.cnt, L.tiles, s, tag);
 }
 
 // out (m x n, col-major ld ldo) [+]= X^T Y with X: N x m row-major (ld ldx), Y: N x n row-major (ld ldy)
@@ -297,8 +362,16 @@ int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_
     h.push_back(d);
   }
   HIPC(hipMemcpyAsync(ws.gdesc, h.data(), h.size() * sizeof(GemmDesc<double>), hipMemcpyHostToDevice, s));
-  gemm_batched<double>(ws.gdesc, (int)h.size(), tiles, s);
-  reduce_partials(out, ldo, ws.partial, (int)h.size(), m, n, add, s);
+  {
+    double fl = 0.0, by = 0.0;
+    for (auto& d : h) gemm_work(d, &fl, &by);
+    prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
+    gemm_batched<double>(ws.gdesc, (int)h.size(), tiles, s, 2);
+  }
+  {
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 8.0 * (double)m * n * (h.size() + 1), s);
+    reduce_partials(out, ldo, ws.partial, (int)h.size(), m, n, add, s);
+  }
   HIPC(hipStreamSynchronize(s));  // h is host memory
   return ZOLO_OK;
 }
@@ -324,7 +397,12 @@ int gemm_nt_big(Workspace& ws, double* C, int64_t ldc, const double* Cin, int64_
   d.N = (int)N;
   d.K = K;
   HIPC(hipMemcpyAsync(ws.gdesc + ws.gdesc_cap, &d, sizeof(d), hipMemcpyHostToDevice, s));
-  gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, gemm_tiles<double>(p, (int)N), s);
+  {
+    double fl = 0.0, by = 0.0;
+    gemm_work(d, &fl, &by);
+    prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
+    gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, gemm_tiles<double>(p, (int)N), s, 2);
+  }
   HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
 }
@@ -736,6 +814,7 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.alpha = mone;
         d.beta = one;
         gd.push_back(d);
+        gemm_work(d, &g.flops, &g.bytes);
         g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
       }
       g.cnt = (int)gd.size() - g.off;
@@ -767,6 +846,7 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.alpha = mone;
         d.beta = one;
         gd.push_back(d);
+        gemm_work(d, &g.flops, &g.bytes);
         g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
       }
       g.cnt = (int)gd.size() - g.off;
@@ -807,6 +887,7 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.alpha = one;
         d.beta = zero;
         gd.push_back(d);
+        gemm_work(d, &g1.flops, &g1.bytes);
         g1.tiles = std::max(g1.tiles, gemm_tiles<T>(d.M, d.N));
       }
       g1.cnt = (int)gd.size() - g1.off;
@@ -829,6 +910,7 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.alpha = mone;
         d.beta = zero;
         gd.push_back(d);
+        gemm_work(d, &g2.flops, &g2.bytes);
         g2.tiles = std::max(g2.tiles, gemm_tiles<T>(d.M, d.N));
       }
       g2.cnt = (int)gd.size() - g2.off;
@@ -840,22 +922,28 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   CHK(tmp.upload(&dgd, gd.data(), gd.size()));
   // run the program level by level
   for (int L = 0; L < nl; ++L) {
-    front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L],
-                      P->lvl_asm_end[L] - P->lvl_asm_begin[L], P->pa, P->pb, sr, si, s);
-    for (const GemmLaunch& g : P->lvl_ext[L])
-      front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+    {
+      prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
+      front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L],
+                        P->lvl_asm_end[L] - P->lvl_asm_begin[L], P->pa, P->pb, sr, si, s);
+      for (const GemmLaunch& g : P->lvl_ext[L])
+        front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+    }
     const DiagDesc* dd = P->diag + P->lvl_diag_off[L];
     for (size_t jj = 0; jj < P->lvl_diag_nJ[L].size(); ++jj) {
       int J = (int)jj * FB;
       int nd = P->lvl_diag_nJ[L][jj];
-      front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
-      front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
-      run_gemm<T>(dgd, lg[L].trail[jj], s);
+      {
+        prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
+        front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+        front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+      }
+      run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
     }
-    run_gemm<T>(dgd, lg[L].schur, s);
+    run_gemm<T>(dgd, lg[L].schur, s, 0);
     for (size_t I = 0; I < lg[L].inv1.size(); ++I) {
-      run_gemm<T>(dgd, lg[L].inv1[I], s);
-      run_gemm<T>(dgd, lg[L].inv2[I], s);
+      run_gemm<T>(dgd, lg[L].inv1[I], s, 0);
+      run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
     }
   }
   int hflag = 0;
@@ -1020,6 +1108,7 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
           GemmDesc<T> d{};
           if (!mk(Fr, fs[i], i, d)) continue;
           gd.push_back(d);
+          gemm_work(d, &g.flops, &g.bytes);
           g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
         }
         g.cnt = (int)gd.size() - g.off;
@@ -1136,16 +1225,23 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, int j, const Ts* src, int64_t l
   const int nl = (int)P->S.levels.size();
   const int p = G->p;
   for (int L = 0; L < nl; ++L) {
-    solve_gather_own<Ts, T>(G->W, src, lds, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
-    for (const GemmLaunch& g : G->lvl_se[L]) solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
-    run_gemm<T>(G->gd[j], G->f2[j][L], s);
-    run_gemm<T>(G->gd[j], G->f3[j][L], s);
+    {
+      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
+      solve_gather_own<Ts, T>(G->W, src, lds, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
+      for (const GemmLaunch& g : G->lvl_se[L])
+        solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
+    }
+    run_gemm<T>(G->gd[j], G->f2[j][L], s, 1);
+    run_gemm<T>(G->gd[j], G->f3[j][L], s, 1);
   }
   for (int L = nl - 1; L >= 0; --L) {
-    solve_gather_struct<T>(G->Xb, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
-                           G->lvl_maxnb[L], s);
-    run_gemm<T>(G->gd[j], G->b2[j][L], s);
-    run_gemm<T>(G->gd[j], G->b3[j][L], s);
+    {
+      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
+      solve_gather_struct<T>(G->Xb, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
+                             G->lvl_maxnb[L], s);
+    }
+    run_gemm<T>(G->gd[j], G->b2[j][L], s, 1);
+    run_gemm<T>(G->gd[j], G->b3[j][L], s, 1);
   }
 }
 
@@ -1251,10 +1347,17 @@ zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, do
   Workspace& ws = *F->ws;
   const zolo_filter_coeffs& co = F->co;
   // T = B V
-  spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, ws.Tb, p, nullptr, 0, s);
-  scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
+  {
+    prof::Scope ps(ZOLO_PROF_SPMM, 2.0 * P->nnz * p, 12.0 * P->nnz + 8.0 * (n + 1) + 16.0 * n * p, s);
+    spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, ws.Tb, p, nullptr, 0, s);
+  }
+  {
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 16.0 * n * p, s);
+    scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
+  }
   for (int j = 0; j < co.r1; ++j) {
     CHK(pole_solve_new(F, j, ws.Tb, p, ws.Xc, s));
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 32.0 * n * p, s);
     axpy_re(W, ldw, ws.Xc, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
   }
   return ZOLO_OK;
@@ -1318,7 +1421,10 @@ zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int 
     }
     CHK(cholqr2(F, ws.W, p, ws.Vb + (int64_t)kp1, Mp, p, &bd, s));
     put_block(ws.H, Mp, kp1, (int64_t)k * p, ws.Rk, p, s);
-    hls_step(ws.hls, ws.H, Mp, k, ws.res, s);
+    {
+      prof::Scope ps(ZOLO_PROF_HLS, 0.0, 0.0, s);
+      hls_step(ws.hls, ws.H, Mp, k, ws.res, s);
+    }
     HIPC(hipMemcpyAsync(res.data(), ws.res, sizeof(double) * ns * p, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     HIPC(hipGetLastError());
@@ -1541,10 +1647,16 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     st.n_gmres_last = fs.n_gmres;
     st.gmres_resid = fs.worst_resid;
     // Rayleigh-Ritz
-    spmm_real(n, P->prow, P->pcol, P->pa, P->pb, Y, nss, nss, AY, nss, BY, nss, s);
+    {
+      prof::Scope ps(ZOLO_PROF_SPMM, 4.0 * P->nnz * nss, 20.0 * P->nnz + 8.0 * (n + 1) + 24.0 * n * nss, s);
+      spmm_real(n, P->prow, P->pcol, P->pa, P->pb, Y, nss, nss, AY, nss, BY, nss, s);
+    }
     CHK(gemm_tn(ws, Y, nss, AY, nss, n, nss, nss, At, nss, false, s));
     CHK(gemm_tn(ws, Y, nss, BY, nss, n, nss, nss, Bt, nss, false, s));
-    rr_reduce(At, Bt, nss, 1e-12, theta, Cm, kdev, work, s);
+    {
+      prof::Scope ps(ZOLO_PROF_RR, 0.0, 0.0, s);
+      rr_reduce(At, Bt, nss, 1e-12, theta, Cm, kdev, work, s);
+    }
     HIPC(hipMemcpyAsync(&k, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     HIPC(hipGetLastError());
@@ -1623,6 +1735,25 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     return ZOLO_ENOCONV;
   }
   return frc == ZOLO_ENOCONV ? ZOLO_ENOCONV : ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_profile_enable(int on) {
+  prof::reset();
+  prof::on = on != 0;
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out) {
+  if (!out || cls < 0 || cls >= ZOLO_PROF_COUNT) {
+    set_error("zolo_profile_query: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  prof::resolve();
+  out->launches = prof::cnt[cls];
+  out->ms = prof::ms[cls];
+  out->flops = prof::fl[cls];
+  out->bytes = prof::by[cls];
+  return ZOLO_OK;
 }
 
 extern "C" int64_t zolo_result_count(const zolo_result* r) { return r ? r->count : 0; }

@@ -48,7 +48,28 @@ inline int gemm_tiles(int M, int N) {
 }
 
 // d_desc: device array of n descriptors; max_tiles = max over descriptors of gemm_tiles.
+// tag: 0 front updates, 1 supernodal solves, 2 Krylov / Rayleigh-Ritz (profile names only).
 template <typename T>
-void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s);
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s, int tag);
+
+// Algorithmic work of one descriptor: entries of C computed and flops
+// (8 per complex multiply-add, 2 per real one), and the bytes a product
+// must move at least once: A, B, C written, Cin read.
+template <typename T>
+inline void gemm_work(const GemmDesc<T>& d, double* flops, double* bytes) {
+  double M = d.M, N = d.N, K = d.K;
+  double ent = M * N;
+  if (d.flags & GF_TRI) {
+    ent = 0.0;
+    for (int j = 0; j < d.N; ++j) {
+      int i0 = j + d.tri_off;
+      if (i0 < 0) i0 = 0;
+      if (i0 < d.M) ent += (double)(d.M - i0);
+    }
+  }
+  const double fm = ST<T>::cplx ? 8.0 : 2.0;
+  *flops += fm * ent * K;
+  *bytes += (double)sizeof(T) * (M * K + K * N + ent * (d.Cin ? 2.0 : 1.0));
+}
 
 }  // namespace zolo

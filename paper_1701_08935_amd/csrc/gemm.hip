@@ -1,5 +1,20 @@
-// Batched tiled matrix product (LDS tiles of 64 x 16, 4 x 4 outputs per
-// thread).  See gemm.h for the operation.
+// Batched matrix product on the CDNA4 matrix cores (see gemm.h for the
+// operation).
+//
+// Tiling: one 256-thread workgroup (4 waves) computes a 64 x 64 tile of C;
+// each wave owns a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.  The inner
+// dimension advances in chunks of 16 staged through LDS (real and imaginary
+// parts in separate arrays), double-buffered so the global loads of chunk
+// c+1 overlap the MFMAs of chunk c.  Each 16 x 16 x 4 step uses
+// v_mfma_f64_16x16x4_f64 (double, complex double) or v_mfma_f32_16x16x4_f32
+// (complex float); a complex product is four real ones:
+//   Cre += Are Bre - Aim Bim,  Cim += Are Bim + Aim Bre.
+// Fragment layout of the 16x16x4 instructions (lane l of 64, checked on the
+// device):
+//   A(i, k): i = l % 16, k = l / 16;  B(k, j): j = l % 16, k = l / 16;
+//   D(i, j): j = l % 16 and, for accumulator value v = 0..3,
+//            i = l / 16 + 4 v      (f64 instruction)
+//            i = 4 (l / 16) + v    (f32 instruction).
 #include "gemm.h"
 
 namespace zolo {
@@ -7,15 +22,66 @@ namespace zolo {
 namespace {
 
 constexpr int TK = 16;
+constexpr int LDT = GEMM_TILE + 4;  // padded LDS row
 
-template <typename T, bool CONJ>
-__device__ inline T maybe_conj(T x) {
-  if constexpr (CONJ) return conj_(x);
-  return x;
+template <typename T>
+struct MfmaTraits;
+template <>
+struct MfmaTraits<double> {
+  typedef double R;
+  typedef double __attribute__((ext_vector_type(4))) V4;
+  static constexpr bool cplx = false;
+  __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct MfmaTraits<zd> {
+  typedef double R;
+  typedef double __attribute__((ext_vector_type(4))) V4;
+  static constexpr bool cplx = true;
+  __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct MfmaTraits<zf> {
+  typedef float R;
+  typedef float __attribute__((ext_vector_type(4))) V4;
+  static constexpr bool cplx = true;
+  __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
+};
+
+__device__ inline MfmaTraits<double>::V4 mfma(double a, double b, MfmaTraits<double>::V4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline MfmaTraits<zf>::V4 mfma(float a, float b, MfmaTraits<zf>::V4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
 template <typename T>
+__device__ inline void split(const T& v, typename MfmaTraits<T>::R* re, typename MfmaTraits<T>::R* im);
+template <>
+__device__ inline void split<double>(const double& v, double* re, double* im) {
+  *re = v;
+  (void)im;
+}
+template <>
+__device__ inline void split<zd>(const zd& v, double* re, double* im) {
+  *re = v.re;
+  *im = v.im;
+}
+template <>
+__device__ inline void split<zf>(const zf& v, float* re, float* im) {
+  *re = v.re;
+  *im = v.im;
+}
+
+// TAG only separates the uses in profiles: 0 front updates, 1 supernodal
+// solves, 2 Krylov / Rayleigh-Ritz products.
+template <typename T, int TAG>
 __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs) {
+  typedef typename MfmaTraits<T>::R R;
+  typedef typename MfmaTraits<T>::V4 V4;
+  constexpr bool CPLX = MfmaTraits<T>::cplx;
+  constexpr int NP = CPLX ? 2 : 1;  // real planes
+
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tilesM = (d.M + GEMM_TILE - 1) / GEMM_TILE;
   const int tilesN = (d.N + GEMM_TILE - 1) / GEMM_TILE;
@@ -26,22 +92,28 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
   const bool tri = (d.flags & GF_TRI) != 0;
   if (tri && (m0 + GEMM_TILE - 1) - n0 < d.tri_off) return;
 
-  __shared__ T As[TK][GEMM_TILE + 1];
-  __shared__ T Bs[TK][GEMM_TILE + 1];
+  // [buffer][plane][k][row]
+  __shared__ R As[2][NP][TK][LDT];
+  __shared__ R Bs[2][NP][TK][LDT];
 
   const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = ST<T>::zero();
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
 
   const bool ta = (d.flags & GF_TRANSA) != 0, tb = (d.flags & GF_TRANSB) != 0;
   const bool ca = (d.flags & GF_CONJA) != 0, cb = (d.flags & GF_CONJB) != 0;
 
-  for (int k0 = 0; k0 < d.K; k0 += TK) {
-    // A tile: 64 rows x 16 inner
+  V4 acc[2][2][NP];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[a][b][q] = V4{0, 0, 0, 0};
+
+  T ra[4], rb[4];  // staged global values of the next chunk
+  auto gload = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int e = tid + 256 * q;
@@ -60,9 +132,8 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
         if (ca) v = conj_(v);
         if (d.dk) v = mul(v, d.dk[gt]);
       }
-      As[t][i] = v;
+      ra[q] = v;
     }
-    // B tile: 16 inner x 64 cols
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       int e = tid + 256 * q;
@@ -80,21 +151,80 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
         v = tb ? d.B[gj + (int64_t)gt * d.ldb] : d.B[gt + (int64_t)gj * d.ldb];
         if (cb) v = conj_(v);
       }
-      Bs[t][j] = v;
+      rb[q] = v;
     }
-    __syncthreads();
+  };
+  auto sstore = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < TK; ++t) {
-      T ar[4], br[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) ar[a] = As[t][tx + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) br[b] = Bs[t][ty + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma_(acc[a][b], ar[a], br[b]);
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int i, t;
+      if (!ta) {
+        i = e % GEMM_TILE;
+        t = e / GEMM_TILE;
+      } else {
+        i = e / TK;
+        t = e % TK;
+      }
+      R re, im = 0;
+      split<T>(ra[q], &re, &im);
+      As[buf][0][t][i] = re;
+      if constexpr (CPLX) As[buf][NP - 1][t][i] = im;
     }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int t, j;
+      if (!tb) {
+        t = e % TK;
+        j = e / TK;
+      } else {
+        j = e % GEMM_TILE;
+        t = e / GEMM_TILE;
+      }
+      R re, im = 0;
+      split<T>(rb[q], &re, &im);
+      Bs[buf][0][t][j] = re;
+      if constexpr (CPLX) Bs[buf][NP - 1][t][j] = im;
+    }
+  };
+
+  const int nchunk = (d.K + TK - 1) / TK;
+  if (nchunk > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunk; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunk) gload((c + 1) * TK);
+#pragma unroll
+    for (int kk = 0; kk < TK / 4; ++kk) {
+      const int k = 4 * kk + lk;
+      R are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        are[a] = As[buf][0][k][wm + 16 * a + li];
+        if constexpr (CPLX) aim[a] = As[buf][NP - 1][k][wm + 16 * a + li];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        bre[b] = Bs[buf][0][k][wn + 16 * b + li];
+        if constexpr (CPLX) bim[b] = Bs[buf][NP - 1][k][wn + 16 * b + li];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b][0] = mfma(are[a], bre[b], acc[a][b][0]);
+          if constexpr (CPLX) {
+            acc[a][b][0] = mfma(-aim[a], bim[b], acc[a][b][0]);
+            acc[a][b][1] = mfma(are[a], bim[b], acc[a][b][1]);
+            acc[a][b][1] = mfma(aim[a], bre[b], acc[a][b][1]);
+          }
+        }
+    }
+    if (c + 1 < nchunk) sstore(buf ^ 1);
     __syncthreads();
   }
 
@@ -102,42 +232,54 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
   const bool use_crs = (d.flags & (GF_CRS | GF_CRS_INV)) != 0;
   const bool crs_inv = (d.flags & GF_CRS_INV) != 0;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    int i = m0 + tx + 16 * a;
-    if (i >= d.M) continue;
-    T s = d.beta;
-    if (use_crs) s = crs_inv ? inv_(d.crs[i]) : d.crs[i];
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int j = n0 + ty + 16 * b;
-      if (j >= d.N) continue;
-      if (tri && i - j < d.tri_off) continue;
-      T out = mul(d.alpha, acc[a][b]);
-      if (d.Cin) {
-        T cin = tc ? d.Cin[(int64_t)i * d.ldcin + j] : d.Cin[i + (int64_t)j * d.ldcin];
-        out = fma_(out, s, cin);
+    for (int v = 0; v < 4; ++v) {
+      const int i = m0 + wm + 16 * a + MfmaTraits<T>::row(lk, v);
+      if (i >= d.M) continue;
+      T s = d.beta;
+      if (use_crs) s = crs_inv ? inv_(d.crs[i]) : d.crs[i];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = n0 + wn + 16 * b + li;
+        if (j >= d.N) continue;
+        if (tri && i - j < d.tri_off) continue;
+        T accv;
+        if constexpr (CPLX)
+          accv = T{acc[a][b][0][v], acc[a][b][1][v]};
+        else
+          accv = acc[a][b][0][v];
+        T out = mul(d.alpha, accv);
+        if (d.Cin) {
+          T cin = tc ? d.Cin[(int64_t)i * d.ldcin + j] : d.Cin[i + (int64_t)j * d.ldcin];
+          out = fma_(out, s, cin);
+        }
+        if (tc)
+          d.C[(int64_t)i * d.ldc + j] = out;
+        else
+          d.C[i + (int64_t)j * d.ldc] = out;
       }
-      if (tc)
-        d.C[(int64_t)i * d.ldc + j] = out;
-      else
-        d.C[i + (int64_t)j * d.ldc] = out;
     }
-  }
 }
 
 }  // namespace
 
 template <typename T>
-void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s) {
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s, int tag) {
   if (n <= 0 || max_tiles <= 0) return;
   for (int b0 = 0; b0 < n; b0 += 65535) {
     int nb = n - b0 < 65535 ? n - b0 : 65535;
-    hipLaunchKernelGGL(gemm_batched_kernel<T>, dim3(max_tiles, nb), dim3(256), 0, s, d_desc + b0);
+    if (tag == 0)
+      hipLaunchKernelGGL((gemm_batched_kernel<T, 0>), dim3(max_tiles, nb), dim3(256), 0, s, d_desc + b0);
+    else if (tag == 1)
+      hipLaunchKernelGGL((gemm_batched_kernel<T, 1>), dim3(max_tiles, nb), dim3(256), 0, s, d_desc + b0);
+    else
+      hipLaunchKernelGGL((gemm_batched_kernel<T, 2>), dim3(max_tiles, nb), dim3(256), 0, s, d_desc + b0);
   }
 }
 
-template void gemm_batched<double>(const GemmDesc<double>*, int, int, hipStream_t);
-template void gemm_batched<zd>(const GemmDesc<zd>*, int, int, hipStream_t);
-template void gemm_batched<zf>(const GemmDesc<zf>*, int, int, hipStream_t);
+template void gemm_batched<double>(const GemmDesc<double>*, int, int, hipStream_t, int);
+template void gemm_batched<zd>(const GemmDesc<zd>*, int, int, hipStream_t, int);
+template void gemm_batched<zf>(const GemmDesc<zf>*, int, int, hipStream_t, int);
 
 }  // namespace zolo

@@ -34,20 +34,26 @@ __global__ void reduce_partials_kernel(double* __restrict__ out, int64_t ld_out,
   *o = add ? *o + s : s;
 }
 
-// single workgroup; G is read, R/Rinv written (all col-major p x p)
+// single workgroup; G is read, R/Rinv written (all col-major p x p).  With
+// USE_LDS the factorization runs in LDS (p <= 128) and only R, R^-1 are
+// written to global memory.
+template <bool USE_LDS>
 __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __restrict__ G, int p, double rel_shift,
-                                                              double* __restrict__ R, double* __restrict__ Rinv,
+                                                              double* __restrict__ Rg, double* __restrict__ Rinv,
                                                               int* flag) {
+  extern __shared__ double lds_R[];
+  double* R = USE_LDS ? lds_R : Rg;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double trace_s;
+  __shared__ int bad_s;
   if (tid == 0) {
     double tr = 0.0;
     for (int i = 0; i < p; ++i) tr += G[i + (int64_t)i * p];
     trace_s = tr;
+    bad_s = 0;
   }
   __syncthreads();
   const double shift = rel_shift * trace_s / (p > 0 ? p : 1);
-  // R := upper part of G (+ shift on the diagonal), factor in place
   for (int e = tid; e < p * p; e += nt) {
     int i = e % p, j = e / p;
     double v = (i <= j) ? G[e] : 0.0;
@@ -58,12 +64,11 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
   for (int k = 0; k < p; ++k) {
     double dkk = R[k + (int64_t)k * p];
     if (!(dkk > 1e-300)) {
-      if (tid == 0) *flag = 1;
+      if (tid == 0) bad_s = 1;
       dkk = 1.0;
     }
     double rk = sqrt(dkk);
     __syncthreads();
-    // row k: R(k, k) = sqrt(d_kk), R(k, j) /= R(k, k) for j > k
     for (int j = k + tid; j < p; j += nt) {
       if (j == k)
         R[k + (int64_t)k * p] = rk;
@@ -72,7 +77,6 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
     }
     __threadfence_block();
     __syncthreads();
-    // trailing: R(i, j) -= R(k, i) R(k, j) for k < i <= j
     int m = p - k - 1;
     for (int e = tid; e < m * m; e += nt) {
       int i = k + 1 + e % m, j = k + 1 + e / m;
@@ -81,14 +85,24 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
     __threadfence_block();
     __syncthreads();
   }
-  // Rinv: column j, back substitution
+  if (tid == 0 && bad_s) *flag = 1;
+  // Rinv: column j by back substitution
   for (int j = tid; j < p; j += nt) {
-    for (int i = 0; i < p; ++i) Rinv[i + (int64_t)j * p] = 0.0;
-    Rinv[j + (int64_t)j * p] = 1.0 / R[j + (int64_t)j * p];
+    for (int i = j + 1; i < p; ++i) Rinv[i + (int64_t)j * p] = 0.0;
+    double xj = 1.0 / R[j + (int64_t)j * p];
+    Rinv[j + (int64_t)j * p] = xj;
+    // x_i = -(sum_{t=i+1..j} R(i,t) x_t) / R(i,i), using a running column in global Rinv
     for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int t = i + 1; t <= j; ++t) s += R[i + (int64_t)t * p] * Rinv[t + (int64_t)j * p];
-      Rinv[i + (int64_t)j * p] = -s / R[i + (int64_t)i * p];
+      double acc = 0.0;
+      for (int t = i + 1; t <= j; ++t) acc += R[i + (int64_t)t * p] * Rinv[t + (int64_t)j * p];
+      Rinv[i + (int64_t)j * p] = -acc / R[i + (int64_t)i * p];
+    }
+  }
+  if (USE_LDS) {
+    __syncthreads();
+    for (int e = tid; e < p * p; e += nt) {
+      int i = e % p, j = e / p;
+      Rg[e] = (i <= j) ? R[e] : 0.0;
     }
   }
 }
@@ -252,6 +266,220 @@ __global__ __launch_bounds__(256) void hls_factor_kernel(HlsState st, int k, dou
   }
 }
 
+// ---- faster variants for p <= 128 ----------------------------------------
+// Active-window formulation: reflectors of block j touch rows [jp, (j+2)p).
+// Each wave owns one column and keeps that window in LDS as a circular buffer
+// of W = roundup(2p, 64) slots; lane l only ever touches rows r = l (mod 64),
+// which always map to its own slots, so a wave needs no barrier.
+__device__ inline int win_slots(int p) { return ((2 * p + 63) / 64) * 64; }
+
+__global__ __launch_bounds__(256) void hls_apply_prev_lds_kernel(HlsState st, const double* __restrict__ H,
+                                                                 int64_t ldh, int k) {
+  extern __shared__ zd win_all[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wave, s = blockIdx.y;
+  const int p = st.p;
+  if (c >= p) return;
+  const int W = win_slots(p);
+  zd* win = win_all + wave * W;
+  const int64_t ldr = st.ldr;
+  zd* col = st.R + (int64_t)s * ldr * st.mmax * p + ((int64_t)k * p + c) * ldr;
+  const double* hc = H + ((int64_t)k * p + c) * ldh;
+  const double sh = st.shift_im[s];
+  const int64_t diag = (int64_t)k * p + c;
+  auto load_rows = [&](int64_t r0, int64_t r1) {  // rows [r0, r1) from H into the window
+    for (int64_t r = r0 + ((lane - r0 % 64) + 64) % 64; r < r1; r += 64) {
+      zd v{hc[r], 0.0};
+      if (r == diag) v.im += sh;
+      win[r % W] = v;
+    }
+  };
+  load_rows(0, 2 * (int64_t)p);
+  const zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  const double* tau = st.tau + (int64_t)s * st.mmax * p;
+  for (int j = 0; j < k; ++j) {
+    for (int q = 0; q < p; ++q) {
+      const zd* v = refl + ((int64_t)j * p + q) * (p + 1);
+      const double t = tau[(int64_t)j * p + q];
+      const int64_t base = (int64_t)j * p + q;
+      const int i0 = (int)(((lane - base % 64) + 64) % 64);
+      double dr = 0.0, di = 0.0;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i], x = win[(base + i) % W];
+        dr += vv.re * x.re + vv.im * x.im;
+        di += vv.re * x.im - vv.im * x.re;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double fr = t * dr, fi = t * di;
+      for (int i = i0; i <= p; i += 64) {
+        zd vv = v[i];
+        zd& x = win[(base + i) % W];
+        x.re -= fr * vv.re - fi * vv.im;
+        x.im -= fr * vv.im + fi * vv.re;
+      }
+    }
+    // rows [jp, (j+1)p) are final; rows [(j+2)p, (j+3)p) enter the window
+    const int64_t r0 = (int64_t)j * p, r1 = r0 + p;
+    for (int64_t r = r0 + ((lane - r0 % 64) + 64) % 64; r < r1; r += 64) col[r] = win[r % W];
+    load_rows((int64_t)(j + 2) * p, (int64_t)(j + 3) * p);
+  }
+  const int64_t r0 = (int64_t)k * p, r1 = r0 + 2 * (int64_t)p;
+  for (int64_t r = r0 + ((lane - r0 % 64) + 64) % 64; r < r1; r += 64) col[r] = win[r % W];
+  // rows below the window are zero
+  for (int64_t r = r1 + ((lane - r1 % 64) + 64) % 64; r < ldr; r += 64) col[r] = zd{0.0, 0.0};
+}
+
+// Panel reduction with the 2p x p panel in registers: 8 lanes per column,
+// lane `sub` owns window rows w = sub + 8 t.
+template <int PB>
+__global__ __launch_bounds__(8 * PB) void hls_factor_reg_kernel(HlsState st, int k) {
+  constexpr int NT = PB / 4;  // 2 PB rows / 8 lanes
+  const int s = blockIdx.x;
+  const int p = st.p;
+  const int tid = threadIdx.x, c = tid >> 3, sub = tid & 7;
+  const int64_t ldr = st.ldr;
+  const bool active = c < p;
+  zd* Rs = st.R + (int64_t)s * ldr * st.mmax * p;
+  zd* colp = Rs + ((int64_t)k * p + (active ? c : 0)) * ldr + (int64_t)k * p;
+  zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  double* tau = st.tau + (int64_t)s * st.mmax * p;
+  double xr[NT], xi[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    int w = sub + 8 * t;
+    zd v = (active && w < 2 * p) ? colp[w] : zd{0.0, 0.0};
+    xr[t] = v.re;
+    xi[t] = v.im;
+  }
+  __shared__ double vre[2][PB + 1], vim[2][PB + 1], tau_s[2];
+  const int gbase = (tid & 63) & ~7;
+  for (int q = 0; q < p; ++q) {
+    const int b = q & 1;
+    if (c == q) {
+      double n2 = 0.0, x0r = 0.0, x0i = 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        int w = sub + 8 * t;
+        if (w >= q && w <= q + p) n2 += xr[t] * xr[t] + xi[t] * xi[t];
+        if (w == q) {
+          x0r = xr[t];
+          x0i = xi[t];
+        }
+      }
+      n2 += __shfl_xor(n2, 1, 64);
+      n2 += __shfl_xor(n2, 2, 64);
+      n2 += __shfl_xor(n2, 4, 64);
+      x0r = __shfl(x0r, gbase + (q & 7), 64);
+      x0i = __shfl(x0i, gbase + (q & 7), 64);
+      const double nrm = sqrt(n2), ax0 = sqrt(x0r * x0r + x0i * x0i);
+      const double phr = ax0 > 0.0 ? x0r / ax0 : 1.0, phi = ax0 > 0.0 ? x0i / ax0 : 0.0;
+      const double tq = nrm > 0.0 ? 1.0 / (n2 + ax0 * nrm) : 0.0;  // 2 / ||v||^2
+      zd* vg = refl + ((int64_t)k * p + q) * (p + 1);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        int w = sub + 8 * t;
+        if (w >= q && w <= q + p) {
+          double a = xr[t], bb = xi[t];
+          if (w == q) {
+            a += phr * nrm;
+            bb += phi * nrm;
+          }
+          vre[b][w - q] = a;
+          vim[b][w - q] = bb;
+          vg[w - q] = zd{a, bb};
+          xr[t] = (w == q) ? -phr * nrm : 0.0;
+          xi[t] = (w == q) ? -phi * nrm : 0.0;
+        }
+      }
+      if (sub == 0) {
+        tau_s[b] = tq;
+        tau[(int64_t)k * p + q] = tq;
+      }
+    }
+    __syncthreads();
+    if (active && c > q) {
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        int w = sub + 8 * t;
+        if (w >= q && w <= q + p) {
+          double a = vre[b][w - q], bb = vim[b][w - q];
+          dr += a * xr[t] + bb * xi[t];
+          di += a * xi[t] - bb * xr[t];
+        }
+      }
+      dr += __shfl_xor(dr, 1, 64);
+      dr += __shfl_xor(dr, 2, 64);
+      dr += __shfl_xor(dr, 4, 64);
+      di += __shfl_xor(di, 1, 64);
+      di += __shfl_xor(di, 2, 64);
+      di += __shfl_xor(di, 4, 64);
+      const double fr = tau_s[b] * dr, fi = tau_s[b] * di;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        int w = sub + 8 * t;
+        if (w >= q && w <= q + p) {
+          double a = vre[b][w - q], bb = vim[b][w - q];
+          xr[t] -= fr * a - fi * bb;
+          xi[t] -= fr * bb + fi * a;
+        }
+      }
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      int w = sub + 8 * t;
+      if (w < 2 * p) colp[w] = zd{xr[t], xi[t]};
+    }
+  }
+}
+
+// apply the p reflectors of block k to the right-hand side g, then the
+// residual norms of rows [(k+1)p, (k+2)p): one wave per (column, shift)
+__global__ __launch_bounds__(256) void hls_apply_g_kernel(HlsState st, int k, double* __restrict__ res) {
+  extern __shared__ zd gwin_all[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = blockIdx.x * 4 + wave, s = blockIdx.y;
+  const int p = st.p;
+  if (c >= p) return;
+  const int W = win_slots(p);
+  zd* win = gwin_all + wave * W;
+  const int64_t ldr = st.ldr;
+  zd* gc = st.g + (int64_t)s * ldr * p + (int64_t)c * ldr + (int64_t)k * p;  // window row 0
+  for (int w = lane; w < 2 * p; w += 64) win[w] = gc[w];
+  const zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  const double* tau = st.tau + (int64_t)s * st.mmax * p;
+  for (int q = 0; q < p; ++q) {
+    const zd* v = refl + ((int64_t)k * p + q) * (p + 1);
+    const double t = tau[(int64_t)k * p + q];
+    const int i0 = ((lane - q % 64) + 64) % 64;
+    double dr = 0.0, di = 0.0;
+    for (int i = i0; i <= p; i += 64) {
+      zd vv = v[i], x = win[q + i];
+      dr += vv.re * x.re + vv.im * x.im;
+      di += vv.re * x.im - vv.im * x.re;
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double fr = t * dr, fi = t * di;
+    for (int i = i0; i <= p; i += 64) {
+      zd vv = v[i];
+      zd& x = win[q + i];
+      x.re -= fr * vv.re - fi * vv.im;
+      x.im -= fr * vv.im + fi * vv.re;
+    }
+  }
+  double n2 = 0.0;
+  for (int w = lane; w < 2 * p; w += 64) {
+    gc[w] = win[w];
+    if (w >= p) n2 += win[w].re * win[w].re + win[w].im * win[w].im;
+  }
+  n2 = wave_sum(n2);
+  if (lane == 0) res[(int64_t)s * p + c] = sqrt(n2);
+}
+
 // one wave per (column c, shift s): Y = R^{-1} g over the first m p rows
 __global__ __launch_bounds__(64) void hls_backsolve_kernel(HlsState st, int m, zd* __restrict__ Y) {
   const int c = blockIdx.x, s = blockIdx.y, lane = threadIdx.x;
@@ -389,9 +617,27 @@ __device__ void jacobi_block(double* A, double* V, int n, int max_sweeps, double
   }
 }
 
+// Jacobi on an m x m matrix M (global, col-major): in LDS when it fits.
+__device__ void jacobi_maybe_lds(double* M, double* V, int m, double* lds, bool use_lds) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (use_lds) {
+    for (int e = tid; e < m * m; e += nt) lds[e] = M[e];
+    __syncthreads();
+    jacobi_block(lds, V, m, 40, 1e-15);
+    __syncthreads();
+    for (int e = tid; e < m * m; e += nt) M[e] = lds[e];
+    __threadfence_block();
+    __syncthreads();
+  } else {
+    jacobi_block(M, V, m, 40, 1e-15);
+  }
+}
+
 __global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restrict__ At, const double* __restrict__ Bt,
                                                          int n, double tau_rank, double* __restrict__ theta,
                                                          double* __restrict__ Cmat, int* k_out, double* work) {
+  extern __shared__ double rr_lds[];
+  const bool use_lds = n <= 128;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t nn = (int64_t)n * n;
   double* As = work;
@@ -421,7 +667,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restric
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_block(Bs, U, n, 40, 1e-15);
+  jacobi_maybe_lds(Bs, U, n, rr_lds, use_lds);
   __syncthreads();
   for (int i = tid; i < n; i += nt) sv[i] = Bs[i + (int64_t)i * n];
   __threadfence_block();
@@ -469,7 +715,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restric
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_block(Bs, W, k, 40, 1e-15);
+  jacobi_maybe_lds(Bs, W, k, rr_lds, use_lds);
   __syncthreads();
   // ascending order of the Ritz values
   for (int i = tid; i < k; i += nt) {
@@ -536,7 +782,15 @@ void reduce_partials(double* out, int64_t ld_out, const double* partial, int S, 
 }
 
 void chol_upper_inv(const double* G, int p, double rel_shift, double* R, double* Rinv, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
+  if (p <= 128) {
+    (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * p * p));
+  }
+  if (p <= 128)
+    hipLaunchKernelGGL(chol_upper_inv_kernel<true>, dim3(1), dim3(1024), sizeof(double) * p * p, s, G, p, rel_shift,
+                       R, Rinv, flag);
+  else
+    hipLaunchKernelGGL(chol_upper_inv_kernel<false>, dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
 }
 
 void upper_mul(const double* A, const double* B, double* C, int p, hipStream_t s) {
@@ -552,8 +806,23 @@ void hls_init(const HlsState& st, const double* R0, hipStream_t s) {
 }
 
 void hls_step(const HlsState& st, const double* H, int64_t ldh, int k, double* res, hipStream_t s) {
-  hipLaunchKernelGGL(hls_apply_prev_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, H, ldh, k);
-  hipLaunchKernelGGL(hls_factor_kernel, dim3(st.nshift), dim3(256), 0, s, st, k, res);
+  if (st.p > 128) {
+    hipLaunchKernelGGL(hls_apply_prev_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, H, ldh, k);
+    hipLaunchKernelGGL(hls_factor_kernel, dim3(st.nshift), dim3(256), 0, s, st, k, res);
+    return;
+  }
+  const size_t lds = sizeof(zd) * 4 * (size_t)(((2 * st.p + 63) / 64) * 64);
+  const dim3 g4((st.p + 3) / 4, st.nshift);
+  hipLaunchKernelGGL(hls_apply_prev_lds_kernel, g4, dim3(256), lds, s, st, H, ldh, k);
+  if (st.p <= 32)
+    hipLaunchKernelGGL(hls_factor_reg_kernel<32>, dim3(st.nshift), dim3(256), 0, s, st, k);
+  else if (st.p <= 64)
+    hipLaunchKernelGGL(hls_factor_reg_kernel<64>, dim3(st.nshift), dim3(512), 0, s, st, k);
+  else if (st.p <= 96)
+    hipLaunchKernelGGL(hls_factor_reg_kernel<96>, dim3(st.nshift), dim3(768), 0, s, st, k);
+  else
+    hipLaunchKernelGGL(hls_factor_reg_kernel<128>, dim3(st.nshift), dim3(1024), 0, s, st, k);
+  hipLaunchKernelGGL(hls_apply_g_kernel, g4, dim3(256), lds, s, st, k, res);
 }
 
 void hls_backsolve(const HlsState& st, int m, zd* Y, hipStream_t s) {
@@ -568,7 +837,9 @@ void hls_combine_real(const zd* Y, int m, int p, int nshift, const double* coef,
 
 void rr_reduce(const double* At, const double* Bt, int n, double tau_rank, double* theta, double* Cmat, int* k_out,
                double* work, hipStream_t s) {
-  hipLaunchKernelGGL(rr_reduce_kernel, dim3(1), dim3(1024), 0, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
+  size_t lds = n <= 128 ? sizeof(double) * n * n : 0;
+  if (lds) (void)hipFuncSetAttribute((const void*)rr_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(rr_reduce_kernel, dim3(1), dim3(1024), lds, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
 }
 
 void resid_norms(const double* AX, const double* BX, const double* X, const double* theta, int64_t n, int k,
