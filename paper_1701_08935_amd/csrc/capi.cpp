@@ -241,13 +241,15 @@ struct SolveProg {
   T* tb = nullptr;
   T* Y = nullptr;
   T* X = nullptr;
-  SolveDesc* sd = nullptr;
+  SolveDesc* sd = nullptr;     // shared right-hand side
+  SolveDesc* sd_pp = nullptr;  // per-pole right-hand sides (pole j at j * xstride)
   SolveExt* se = nullptr;
   std::vector<int> lvl_sd_off, lvl_sd_cnt, lvl_maxk, lvl_maxnb;
   std::vector<std::vector<GemmLaunch>> lvl_se;  // per slot (tiles = max nb)
-  // per pole: GEMM descriptors and launches
-  std::vector<GemmDesc<T>*> gd;
-  std::vector<std::vector<GemmLaunch>> f2, f3, b2, b3;  // [pole][level]
+  int np = 0;                                    // poles solved together
+  int64_t xstride = 0;                           // elements between poles' X (and Y) blocks
+  GemmDesc<T>* gd = nullptr;                     // all poles, per level
+  std::vector<GemmLaunch> f2, f3, b2, b3;        // [level]
 };
 
 struct Workspace {
@@ -1003,10 +1005,14 @@ namespace {
 
 template <typename T>
 zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std::vector<PoleMF<T>>& poles) {
+  // One program solves all r1 poles at once: every launch of a level covers the
+  // level's fronts for every pole, with per-pole buffer regions.
   zolo_pencil* P = F->P;
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
+  const int np = (int)poles.size();
   G->p = p;
+  G->np = np;
   int64_t wmax = 0, xbmax = 0, tmax = 0;
   std::vector<int64_t> uoff(S.fronts.size(), 0);
   int64_t utot = 0;
@@ -1024,12 +1030,14 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
     xbmax = std::max(xbmax, xb);
     tmax = std::max(tmax, t);
   }
-  CHK(G->mem.alloc(&G->W, wmax));
-  CHK(G->mem.alloc(&G->U, utot));
-  CHK(G->mem.alloc(&G->Xb, xbmax));
-  CHK(G->mem.alloc(&G->tb, tmax));
-  CHK(G->mem.alloc(&G->Y, P->n * p));
-  CHK(G->mem.alloc(&G->X, P->n * p));
+  const int64_t npx = P->n * p;
+  G->xstride = npx;
+  CHK(G->mem.alloc(&G->W, wmax * np));
+  CHK(G->mem.alloc(&G->U, utot * np));
+  CHK(G->mem.alloc(&G->Xb, xbmax * np));
+  CHK(G->mem.alloc(&G->tb, tmax * np));
+  CHK(G->mem.alloc(&G->Y, npx * np));
+  CHK(G->mem.alloc(&G->X, npx * np));
   std::vector<SolveDesc> sd;
   std::vector<SolveExt> se;
   G->lvl_sd_off.assign(nl, 0);
@@ -1037,30 +1045,40 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   G->lvl_maxk.assign(nl, 0);
   G->lvl_maxnb.assign(nl, 0);
   G->lvl_se.assign(nl, {});
+  // per level, per front (level order): offsets within one pole's regions
   std::vector<std::vector<int64_t>> woff(nl), xboff(nl), toff(nl);
   for (int L = 0; L < nl; ++L) {
-    G->lvl_sd_off[L] = (int)sd.size();
     int64_t w = 0, xb = 0, t = 0;
     for (int f : S.levels[L]) {
       const Front& Fr = S.fronts[f];
-      SolveDesc d{};
-      d.w = w;
-      d.u = uoff[f];
-      d.xb = xb;
-      d.srow = Fr.struct_off;
-      d.first = Fr.first;
-      d.ns = Fr.ns;
-      d.nb = Fr.nb;
-      d.k = Fr.ns + Fr.nb;
-      sd.push_back(d);
       woff[L].push_back(w);
       xboff[L].push_back(xb);
       toff[L].push_back(t);
-      w += (int64_t)d.k * p;
+      w += (int64_t)(Fr.ns + Fr.nb) * p;
       xb += (int64_t)Fr.nb * p;
       t += (int64_t)Fr.ns * p;
-      G->lvl_maxk[L] = std::max(G->lvl_maxk[L], d.k);
+      G->lvl_maxk[L] = std::max(G->lvl_maxk[L], Fr.ns + Fr.nb);
       G->lvl_maxnb[L] = std::max(G->lvl_maxnb[L], (int)Fr.nb);
+    }
+    G->lvl_sd_off[L] = (int)sd.size();
+    for (int j = 0; j < np; ++j) {
+      size_t i = 0;
+      for (int f : S.levels[L]) {
+        const Front& Fr = S.fronts[f];
+        SolveDesc d{};
+        d.w = j * wmax + woff[L][i];
+        d.u = j * utot + uoff[f];
+        d.xb = j * xbmax + xboff[L][i];
+        d.srow = Fr.struct_off;
+        d.xo = j * npx;
+        d.so = 0;
+        d.first = Fr.first;
+        d.ns = Fr.ns;
+        d.nb = Fr.nb;
+        d.k = Fr.ns + Fr.nb;
+        sd.push_back(d);
+        ++i;
+      }
     }
     G->lvl_sd_cnt[L] = (int)sd.size() - G->lvl_sd_off[L];
     int maxc = 0;
@@ -1068,130 +1086,130 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
     for (int slot = 0; slot < maxc; ++slot) {
       GemmLaunch g;
       g.off = (int)se.size();
-      int i = 0;
-      for (int f : S.levels[L]) {
-        const Front& Fr = S.fronts[f];
-        int64_t wf = woff[L][i++];
-        if (slot >= Fr.child_count) continue;
-        int c = S.children[Fr.child_begin + slot];
-        const Front& C = S.fronts[c];
-        if (C.nb == 0) continue;
-        SolveExt e{};
-        e.child_u = uoff[c];
-        e.par_w = wf;
-        e.pmap = C.struct_off;
-        e.nb_c = C.nb;
-        se.push_back(e);
-        g.tiles = std::max(g.tiles, (int)C.nb);
+      for (int j = 0; j < np; ++j) {
+        size_t i = 0;
+        for (int f : S.levels[L]) {
+          const Front& Fr = S.fronts[f];
+          int64_t wf = j * wmax + woff[L][i++];
+          if (slot >= Fr.child_count) continue;
+          int ch = S.children[Fr.child_begin + slot];
+          const Front& C = S.fronts[ch];
+          if (C.nb == 0) continue;
+          SolveExt e{};
+          e.child_u = j * utot + uoff[ch];
+          e.par_w = wf;
+          e.pmap = C.struct_off;
+          e.nb_c = C.nb;
+          se.push_back(e);
+          g.tiles = std::max(g.tiles, (int)C.nb);
+        }
       }
       g.cnt = (int)se.size() - g.off;
       G->lvl_se[L].push_back(g);
     }
   }
   CHK(G->mem.upload(&G->sd, sd.data(), sd.size()));
+  for (SolveDesc& d : sd) d.so = d.xo;
+  CHK(G->mem.upload(&G->sd_pp, sd.data(), sd.size()));
   CHK(G->mem.upload(&G->se, se.data(), se.size()));
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
-  const int np = (int)poles.size();
-  G->gd.assign(np, nullptr);
-  G->f2.assign(np, std::vector<GemmLaunch>(nl));
-  G->f3.assign(np, std::vector<GemmLaunch>(nl));
-  G->b2.assign(np, std::vector<GemmLaunch>(nl));
-  G->b3.assign(np, std::vector<GemmLaunch>(nl));
-  for (int j = 0; j < np; ++j) {
-    std::vector<GemmDesc<T>> gd;
-    for (int L = 0; L < nl; ++L) {
-      const std::vector<int>& fs = S.levels[L];
-      auto emit = [&](GemmLaunch& g, auto mk) {
-        g.off = (int)gd.size();
+  G->f2.assign(nl, GemmLaunch());
+  G->f3.assign(nl, GemmLaunch());
+  G->b2.assign(nl, GemmLaunch());
+  G->b3.assign(nl, GemmLaunch());
+  std::vector<GemmDesc<T>> gd;
+  for (int L = 0; L < nl; ++L) {
+    const std::vector<int>& fs = S.levels[L];
+    auto emit = [&](GemmLaunch& g, auto mk) {
+      g.off = (int)gd.size();
+      for (int j = 0; j < np; ++j)
         for (size_t i = 0; i < fs.size(); ++i) {
           const Front& Fr = S.fronts[fs[i]];
           GemmDesc<T> d{};
-          if (!mk(Fr, fs[i], i, d)) continue;
+          if (!mk(j, Fr, fs[i], i, d)) continue;
           gd.push_back(d);
           gemm_work(d, &g.flops, &g.bytes);
           g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
         }
-        g.cnt = (int)gd.size() - g.off;
-      };
-      const PoleMF<T>& pm = poles[j];
-      // F2: Y[first:first+ns] = inv * W[0:ns]
-      emit(G->f2[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-        if (Fr.ns == 0) return false;
-        d.C = G->Y + (int64_t)Fr.first * p;
-        d.ldc = p;
-        d.A = pm.inv + P->inv_off[f];
-        d.lda = Fr.ns;
-        d.B = G->W + woff[L][i];
-        d.ldb = p;
-        d.M = Fr.ns;
-        d.N = p;
-        d.K = Fr.ns;
-        d.flags = GF_TRANSB | GF_TRANSC;
-        d.alpha = one;
-        d.beta = zero;
-        return true;
-      });
-      // F3: U = W[ns:k] - L21 * Y[first:first+ns]
-      emit(G->f3[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-        if (Fr.nb == 0) return false;
-        int64_t k = (int64_t)Fr.ns + Fr.nb;
-        d.C = G->U + uoff[f];
-        d.ldc = p;
-        d.Cin = G->W + woff[L][i] + (int64_t)Fr.ns * p;
-        d.ldcin = p;
-        d.A = pm.panel + P->panel_off[f] + Fr.ns;
-        d.lda = k;
-        d.B = G->Y + (int64_t)Fr.first * p;
-        d.ldb = p;
-        d.M = Fr.nb;
-        d.N = p;
-        d.K = Fr.ns;
-        d.flags = GF_TRANSB | GF_TRANSC;
-        d.alpha = mone;
-        d.beta = one;
-        return true;
-      });
-      // B2: t = D^-1 Y[first:] - L21^T Xb
-      emit(G->b2[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-        if (Fr.ns == 0) return false;
-        int64_t k = (int64_t)Fr.ns + Fr.nb;
-        d.C = G->tb + toff[L][i];
-        d.ldc = p;
-        d.Cin = G->Y + (int64_t)Fr.first * p;
-        d.ldcin = p;
-        d.crs = pm.dvec + Fr.first;
-        d.A = pm.panel + P->panel_off[f] + Fr.ns;
-        d.lda = k;
-        d.B = G->Xb + xboff[L][i];
-        d.ldb = p;
-        d.M = Fr.ns;
-        d.N = p;
-        d.K = Fr.nb;
-        d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV;
-        d.alpha = mone;
-        d.beta = one;
-        return true;
-      });
-      // B3: X[first:] = inv^T t
-      emit(G->b3[j][L], [&](const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-        if (Fr.ns == 0) return false;
-        d.C = G->X + (int64_t)Fr.first * p;
-        d.ldc = p;
-        d.A = pm.inv + P->inv_off[f];
-        d.lda = Fr.ns;
-        d.B = G->tb + toff[L][i];
-        d.ldb = p;
-        d.M = Fr.ns;
-        d.N = p;
-        d.K = Fr.ns;
-        d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC;
-        d.alpha = one;
-        d.beta = zero;
-        return true;
-      });
-    }
-    CHK(G->mem.upload(&G->gd[j], gd.data(), gd.size()));
+      g.cnt = (int)gd.size() - g.off;
+    };
+    // F2: Y[first:first+ns] = inv * W[0:ns]
+    emit(G->f2[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+      if (Fr.ns == 0) return false;
+      d.C = G->Y + j * npx + (int64_t)Fr.first * p;
+      d.ldc = p;
+      d.A = poles[j].inv + P->inv_off[f];
+      d.lda = Fr.ns;
+      d.B = G->W + j * wmax + woff[L][i];
+      d.ldb = p;
+      d.M = Fr.ns;
+      d.N = p;
+      d.K = Fr.ns;
+      d.flags = GF_TRANSB | GF_TRANSC;
+      d.alpha = one;
+      d.beta = zero;
+      return true;
+    });
+    // F3: U = W[ns:k] - L21 * Y[first:first+ns]
+    emit(G->f3[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+      if (Fr.nb == 0) return false;
+      int64_t k = (int64_t)Fr.ns + Fr.nb;
+      d.C = G->U + j * utot + uoff[f];
+      d.ldc = p;
+      d.Cin = G->W + j * wmax + woff[L][i] + (int64_t)Fr.ns * p;
+      d.ldcin = p;
+      d.A = poles[j].panel + P->panel_off[f] + Fr.ns;
+      d.lda = k;
+      d.B = G->Y + j * npx + (int64_t)Fr.first * p;
+      d.ldb = p;
+      d.M = Fr.nb;
+      d.N = p;
+      d.K = Fr.ns;
+      d.flags = GF_TRANSB | GF_TRANSC;
+      d.alpha = mone;
+      d.beta = one;
+      return true;
+    });
+    // B2: t = D^-1 Y[first:] - L21^T Xb
+    emit(G->b2[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+      if (Fr.ns == 0) return false;
+      int64_t k = (int64_t)Fr.ns + Fr.nb;
+      d.C = G->tb + j * tmax + toff[L][i];
+      d.ldc = p;
+      d.Cin = G->Y + j * npx + (int64_t)Fr.first * p;
+      d.ldcin = p;
+      d.crs = poles[j].dvec + Fr.first;
+      d.A = poles[j].panel + P->panel_off[f] + Fr.ns;
+      d.lda = k;
+      d.B = G->Xb + j * xbmax + xboff[L][i];
+      d.ldb = p;
+      d.M = Fr.ns;
+      d.N = p;
+      d.K = Fr.nb;
+      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV;
+      d.alpha = mone;
+      d.beta = one;
+      return true;
+    });
+    // B3: X[first:] = inv^T t
+    emit(G->b3[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
+      if (Fr.ns == 0) return false;
+      d.C = G->X + j * npx + (int64_t)Fr.first * p;
+      d.ldc = p;
+      d.A = poles[j].inv + P->inv_off[f];
+      d.lda = Fr.ns;
+      d.B = G->tb + j * tmax + toff[L][i];
+      d.ldb = p;
+      d.M = Fr.ns;
+      d.N = p;
+      d.K = Fr.ns;
+      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC;
+      d.alpha = one;
+      d.beta = zero;
+      return true;
+    });
   }
+  CHK(G->mem.upload(&G->gd, gd.data(), gd.size()));
   return ZOLO_OK;
 }
 
@@ -1218,21 +1236,25 @@ SolveProg<zf>* get_prog<zf>(zolo_factors* F, int p) {
   return r;
 }
 
-// X (new ordering, N x p, in G->X) = K_j^-1 src, src: N x p row-major (new ordering)
+// X_j (in G->X + j xstride, new ordering, N x p) = K_j^-1 src_j for all poles j.
+// src: N x p row-major (new ordering); src_stride = 0 shares one right-hand
+// side, otherwise pole j reads src + j * src_stride.
+// per_pole: pole j reads its right-hand side at src + j * xstride (ld p)
 template <typename Ts, typename T>
-void run_solve(zolo_factors* F, SolveProg<T>* G, int j, const Ts* src, int64_t lds, hipStream_t s) {
+void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, bool per_pole, hipStream_t s) {
   zolo_pencil* P = F->P;
   const int nl = (int)P->S.levels.size();
   const int p = G->p;
+  const SolveDesc* sdesc = per_pole ? G->sd_pp : G->sd;
   for (int L = 0; L < nl; ++L) {
     {
       prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
-      solve_gather_own<Ts, T>(G->W, src, lds, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
+      solve_gather_own<Ts, T>(G->W, src, lds, sdesc + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
       for (const GemmLaunch& g : G->lvl_se[L])
         solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
     }
-    run_gemm<T>(G->gd[j], G->f2[j][L], s, 1);
-    run_gemm<T>(G->gd[j], G->f3[j][L], s, 1);
+    run_gemm<T>(G->gd, G->f2[L], s, 1);
+    run_gemm<T>(G->gd, G->f3[L], s, 1);
   }
   for (int L = nl - 1; L >= 0; --L) {
     {
@@ -1240,8 +1262,8 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, int j, const Ts* src, int64_t l
       solve_gather_struct<T>(G->Xb, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
                              G->lvl_maxnb[L], s);
     }
-    run_gemm<T>(G->gd[j], G->b2[j][L], s, 1);
-    run_gemm<T>(G->gd[j], G->b3[j][L], s, 1);
+    run_gemm<T>(G->gd, G->b2[L], s, 1);
+    run_gemm<T>(G->gd, G->b3[L], s, 1);
   }
 }
 
@@ -1261,9 +1283,10 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   CHK(ws->mem.alloc(&ws->W, n * p));
   CHK(ws->mem.alloc(&ws->T1, n * p));
   CHK(ws->mem.alloc(&ws->Tb, n * p));
-  CHK(ws->mem.alloc(&ws->Xc, n * p));
-  CHK(ws->mem.alloc(&ws->Rc, n * p));
-  CHK(ws->mem.alloc(&ws->Dc, n * p));
+  const int np = F->co.r1;
+  CHK(ws->mem.alloc(&ws->Xc, n * p * np));
+  CHK(ws->mem.alloc(&ws->Rc, n * p * np));
+  CHK(ws->mem.alloc(&ws->Dc, 1));
   ws->ldh = Mp;
   CHK(ws->mem.alloc(&ws->H, Mp * (int64_t)mmax * p));
   CHK(ws->mem.alloc(&ws->hbuf, Mp * p));
@@ -1300,48 +1323,55 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   return ZOLO_OK;
 }
 
-// X (zd, N x p, new ordering) = K_j^{-1} T (T real, new ordering, ld p)
-zolo_status pole_solve_new(zolo_factors* F, int j, const double* T, int p, zd* X, hipStream_t s) {
+// X_j (zd, N x p, new ordering, at X + j n p) = K_j^{-1} T for every pole j
+// (T real, new ordering, ld p).  Mixed precision: complex64 factors, and
+// iterative refinement against FP64 residuals R_j = T - (A - sigma_j B) X_j
+// until max_j ||R_j|| / ||T|| <= tol_inner (column-wise).
+zolo_status poles_solve_all(zolo_factors* F, const double* T, int p, zd* X, double tol_inner, hipStream_t s) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
+  const int np = F->co.r1;
+  const int64_t npx = n * p;
   if (F->precision == ZOLO_PREC_FP64) {
     SolveProg<zd>* G = get_prog<zd>(F, p);
     if (!G) return ZOLO_ENOMEM;
-    run_solve<double, zd>(F, G, j, T, p, s);
-    HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * n * p, hipMemcpyDeviceToDevice, s));
-    F->n_solv += p;
+    run_solve<double, zd>(F, G, T, p, false, s);
+    HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * npx * np, hipMemcpyDeviceToDevice, s));
+    F->n_solv += (long long)p * np;
     return ZOLO_OK;
   }
-  // mixed: complex64 factors as a preconditioner against FP64 residuals (iterative refinement)
   SolveProg<zf>* G = get_prog<zf>(F, p);
   if (!G) return ZOLO_ENOMEM;
   Workspace& ws = *F->ws;
-  run_solve<double, zf>(F, G, j, T, p, s);
-  HIPC(hipMemsetAsync(X, 0, sizeof(zd) * n * p, s));
-  add_lowp(X, G->X, n * p, s);
-  F->n_solv += p;
+  run_solve<double, zf>(F, G, T, p, false, s);
+  HIPC(hipMemsetAsync(X, 0, sizeof(zd) * npx * np, s));
+  add_lowp(X, G->X, npx * np, s);
+  F->n_solv += (long long)p * np;
   std::vector<double> tn(p), rn(p);
   colnorm2_real(T, p, n, p, ws.cn_partial, ws.cn_out, s);
   HIPC(hipMemcpyAsync(tn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
-  const double sr = F->co.sigma_hat_re[j], si = F->co.sigma_hat_im[j];
   for (int it = 0; it < F->max_refine; ++it) {
-    spmm_shift_resid(n, P->prow, P->pcol, P->pa, P->pb, sr, si, X, T, p, p, ws.Rc, s);
-    colnorm2_cplx(ws.Rc, n, p, ws.cn_partial, ws.cn_out, s);
-    HIPC(hipMemcpyAsync(rn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
-    HIPC(hipStreamSynchronize(s));
     double worst = 0.0;
-    for (int c = 0; c < p; ++c) worst = std::max(worst, std::sqrt(rn[c]) / std::max(std::sqrt(tn[c]), 1e-300));
-    if (worst <= F->tol_refine) break;
-    run_solve<zd, zf>(F, G, j, ws.Rc, p, s);
-    add_lowp(X, G->X, n * p, s);
-    F->n_refine += p;
+    for (int j = 0; j < np; ++j) {
+      spmm_shift_resid(n, P->prow, P->pcol, P->pa, P->pb, F->co.sigma_hat_re[j], F->co.sigma_hat_im[j], X + j * npx,
+                       T, p, p, ws.Rc + j * npx, s);
+      colnorm2_cplx(ws.Rc + j * npx, n, p, ws.cn_partial, ws.cn_out, s);
+      HIPC(hipMemcpyAsync(rn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      for (int c = 0; c < p; ++c) worst = std::max(worst, std::sqrt(rn[c]) / std::max(std::sqrt(tn[c]), 1e-300));
+    }
+    if (worst <= tol_inner) break;
+    run_solve<zd, zf>(F, G, ws.Rc, p, true, s);
+    add_lowp(X, G->X, npx * np, s);
+    F->n_refine += (long long)p * np;
   }
   return ZOLO_OK;
 }
 
 // W (N x p, ld ldw) = G V (V: N x p new ordering, ld ldv)
-zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* W, int64_t ldw, hipStream_t s) {
+zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* W, int64_t ldw,
+                        double tol_inner, hipStream_t s) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
   Workspace& ws = *F->ws;
@@ -1355,10 +1385,10 @@ zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, do
     prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 16.0 * n * p, s);
     scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
   }
+  CHK(poles_solve_all(F, ws.Tb, p, ws.Xc, tol_inner, s));
   for (int j = 0; j < co.r1; ++j) {
-    CHK(pole_solve_new(F, j, ws.Tb, p, ws.Xc, s));
     prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 32.0 * n * p, s);
-    axpy_re(W, ldw, ws.Xc, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
+    axpy_re(W, ldw, ws.Xc + j * n * p, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
   }
   return ZOLO_OK;
 }
@@ -1412,7 +1442,10 @@ zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int 
   double worst = 1.0;
   bool exhausted = false;
   for (int k = 0; k < maxit; ++k) {
-    CHK(apply_G_new(F, ws.Vb + (int64_t)k * p, Mp, p, ws.W, p, s));
+    // inexact inner solves (mixed precision): the tolerance grows as the outer
+    // residual falls, tol_refine / ||r_{k-1}|| capped at 1e-4
+    const double tol_inner = std::min(1e-4, F->tol_refine / std::max(worst, 1e-300));
+    CHK(apply_G_new(F, ws.Vb + (int64_t)k * p, Mp, p, ws.W, p, tol_inner, s));
     const int kp1 = (k + 1) * p;
     for (int pass = 0; pass < 2; ++pass) {
       CHK(gemm_tn(ws, ws.Vb, Mp, ws.W, p, n, kp1, p, ws.hbuf, kp1, false, s));
@@ -1490,10 +1523,10 @@ extern "C" zolo_status zolo_pole_solve(zolo_factors* F, int j, const double* d_T
   double* tn = nullptr;
   zd* xn = nullptr;
   CHK(tmp.alloc(&tn, n * ncols));
-  CHK(tmp.alloc(&xn, n * ncols));
+  (void)xn;
   rows_gather<double>(tn, ncols, d_T, ldt, F->P->perm, n, ncols, s);
-  CHK(pole_solve_new(F, j, tn, ncols, xn, s));
-  rows_scatter<zd>((zd*)d_X, ldx, xn, ncols, F->P->perm, n, ncols, s);
+  CHK(poles_solve_all(F, tn, ncols, F->ws->Xc, F->tol_refine, s));
+  rows_scatter<zd>((zd*)d_X, ldx, F->ws->Xc + (int64_t)j * n * ncols, ncols, F->P->perm, n, ncols, s);
   HIPC(hipStreamSynchronize(s));
   HIPC(hipGetLastError());
   return ZOLO_OK;
@@ -1513,7 +1546,7 @@ extern "C" zolo_status zolo_apply_G(zolo_factors* F, const double* d_V, int64_t 
   CHK(tmp.alloc(&vn, n * ncols));
   CHK(tmp.alloc(&wn, n * ncols));
   rows_gather<double>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
-  CHK(apply_G_new(F, vn, ncols, ncols, wn, ncols, s));
+  CHK(apply_G_new(F, vn, ncols, ncols, wn, ncols, F->tol_refine, s));
   rows_scatter<double>(d_W, ldw, wn, ncols, F->P->perm, n, ncols, s);
   HIPC(hipStreamSynchronize(s));
   HIPC(hipGetLastError());

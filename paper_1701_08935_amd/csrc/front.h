@@ -32,6 +32,8 @@ struct SolveDesc {
   int64_t u;      // element offset of U in the U buffer (global over fronts)
   int64_t xb;     // element offset of the struct gather buffer
   int64_t srow;   // offset into struct_rows
+  int64_t xo;     // element offset of this pole's solution block X
+  int64_t so;     // element offset of this pole's right-hand side (0 = shared)
   int32_t first, ns, nb, k;
 };
 

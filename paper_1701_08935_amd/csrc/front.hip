@@ -56,6 +56,7 @@ __global__ __launch_bounds__(256) void diag_block_kernel(T* __restrict__ panel, 
   const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
   __shared__ T Ab[FB][FB + 1];  // Ab[r][c]
   __shared__ T Xb[FB][FB + 1];
+  __shared__ T Tm[16][FB];
   const int tid = threadIdx.x;
   T* P = panel + d.panel;
   const int64_t k = d.k;
@@ -89,17 +90,42 @@ __global__ __launch_bounds__(256) void diag_block_kernel(T* __restrict__ panel, 
     if (r >= c) P[(J + r) + (int64_t)(J + c) * k] = Ab[r][c];
   }
   for (int c = tid; c < jb; c += blockDim.x) dvec[d.first + J + c] = Ab[c][c];
-  // inverse of the unit lower block: X(r, c) = -sum_{c <= t < r} L(r, t) X(t, c)
+  // inverse of the unit lower block, by 16 x 16 sub-blocks:
+  //  (1) X_II = L_II^-1 for every diagonal sub-block (in parallel);
+  //  (2) for block rows I = 1, 2, ...: X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ.
+  constexpr int SB = 16;
+  const int nsb = (jb + SB - 1) / SB;
   for (int e = tid; e < jb * jb; e += blockDim.x) {
     int r = e % jb, c = e / jb;
     Xb[r][c] = (r == c) ? ST<T>::one() : ST<T>::zero();
   }
   __syncthreads();
-  for (int r = 1; r < jb; ++r) {
-    for (int c = tid; c < r; c += blockDim.x) {
+  if (tid < nsb * SB) {
+    const int b = tid / SB, c = b * SB + tid % SB;
+    const int rend = min(jb, (b + 1) * SB);
+    if (c < jb)
+      for (int r = c + 1; r < rend; ++r) {
+        T s = ST<T>::zero();
+        for (int t = c; t < r; ++t) s = fma_(s, Ab[r][t], Xb[t][c]);
+        Xb[r][c] = neg(s);
+      }
+  }
+  __syncthreads();
+  for (int I = 1; I < nsb; ++I) {
+    const int r0 = I * SB, rn = min(SB, jb - r0), cols = r0;
+    // Tm(r, c) = sum_{t in [c's block start, r0)} L(r0 + r, t) X(t, c)
+    for (int e = tid; e < rn * cols; e += blockDim.x) {
+      int r = e % rn, c = e / rn;
       T s = ST<T>::zero();
-      for (int t = c; t < r; ++t) s = fma_(s, Ab[r][t], Xb[t][c]);
-      Xb[r][c] = neg(s);
+      for (int t = (c / SB) * SB; t < r0; ++t) s = fma_(s, Ab[r0 + r][t], Xb[t][c]);
+      Tm[r][c] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < rn * cols; e += blockDim.x) {
+      int r = e % rn, c = e / rn;
+      T s = ST<T>::zero();
+      for (int t = 0; t <= r; ++t) s = fma_(s, Xb[r0 + r][r0 + t], Tm[t][c]);
+      Xb[r0 + r][c] = neg(s);
     }
     __syncthreads();
   }
@@ -159,7 +185,7 @@ __global__ void gather_own_kernel(T* __restrict__ W, const Ts* __restrict__ src,
   if (e >= tot) return;
   int64_t r = e / p, c = e % p;
   T v = ST<T>::zero();
-  if (r < d.ns) v = cvt<T, Ts>(src[(d.first + r) * ldsrc + c]);
+  if (r < d.ns) v = cvt<T, Ts>(src[d.so + (d.first + r) * ldsrc + c]);
   W[d.w + e] = v;
 }
 
@@ -185,7 +211,7 @@ __global__ void gather_struct_kernel(T* __restrict__ Xb, const T* __restrict__ X
   if (e >= tot) return;
   int64_t i = e / p, c = e % p;
   int64_t row = srows[d.srow + i];
-  Xb[d.xb + e] = X[row * p + c];
+  Xb[d.xb + e] = X[d.xo + row * p + c];
 }
 
 }  // namespace

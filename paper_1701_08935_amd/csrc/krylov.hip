@@ -43,6 +43,8 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
                                                               int* flag) {
   extern __shared__ double lds_R[];
   double* R = USE_LDS ? lds_R : Rg;
+  // the inverse also lives in LDS when both fit (p <= 96)
+  double* Ri = (USE_LDS && p <= 96) ? lds_R + p * p : Rinv;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double trace_s;
   __shared__ int bad_s;
@@ -86,16 +88,14 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
     __syncthreads();
   }
   if (tid == 0 && bad_s) *flag = 1;
-  // Rinv: column j by back substitution
+  // R^-1: column j by back substitution, x_i = -(sum_{t=i+1..j} R(i,t) x_t) / R(i,i)
   for (int j = tid; j < p; j += nt) {
-    for (int i = j + 1; i < p; ++i) Rinv[i + (int64_t)j * p] = 0.0;
-    double xj = 1.0 / R[j + (int64_t)j * p];
-    Rinv[j + (int64_t)j * p] = xj;
-    // x_i = -(sum_{t=i+1..j} R(i,t) x_t) / R(i,i), using a running column in global Rinv
+    for (int i = j + 1; i < p; ++i) Ri[i + (int64_t)j * p] = 0.0;
+    Ri[j + (int64_t)j * p] = 1.0 / R[j + (int64_t)j * p];
     for (int i = j - 1; i >= 0; --i) {
       double acc = 0.0;
-      for (int t = i + 1; t <= j; ++t) acc += R[i + (int64_t)t * p] * Rinv[t + (int64_t)j * p];
-      Rinv[i + (int64_t)j * p] = -acc / R[i + (int64_t)i * p];
+      for (int t = i + 1; t <= j; ++t) acc += R[i + (int64_t)t * p] * Ri[t + (int64_t)j * p];
+      Ri[i + (int64_t)j * p] = -acc / R[i + (int64_t)i * p];
     }
   }
   if (USE_LDS) {
@@ -103,6 +103,7 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
     for (int e = tid; e < p * p; e += nt) {
       int i = e % p, j = e / p;
       Rg[e] = (i <= j) ? R[e] : 0.0;
+      if (Ri != Rinv) Rinv[e] = Ri[e];
     }
   }
 }
@@ -784,11 +785,11 @@ void reduce_partials(double* out, int64_t ld_out, const double* partial, int S, 
 void chol_upper_inv(const double* G, int p, double rel_shift, double* R, double* Rinv, int* flag, hipStream_t s) {
   if (p <= 128) {
     (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * p * p));
+                              (int)(sizeof(double) * p * p * (p <= 96 ? 2 : 1)));
   }
   if (p <= 128)
-    hipLaunchKernelGGL(chol_upper_inv_kernel<true>, dim3(1), dim3(1024), sizeof(double) * p * p, s, G, p, rel_shift,
-                       R, Rinv, flag);
+    hipLaunchKernelGGL(chol_upper_inv_kernel<true>, dim3(1), dim3(1024), sizeof(double) * p * p * (p <= 96 ? 2 : 1),
+                       s, G, p, rel_shift, R, Rinv, flag);
   else
     hipLaunchKernelGGL(chol_upper_inv_kernel<false>, dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
 }
