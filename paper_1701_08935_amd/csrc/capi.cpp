@@ -1145,7 +1145,7 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       d.M = Fr.ns;
       d.N = p;
       d.K = Fr.ns;
-      d.flags = GF_TRANSB | GF_TRANSC;
+      d.flags = GF_TRANSB | GF_TRANSC | GF_ALOW;
       d.alpha = one;
       d.beta = zero;
       return true;
@@ -1203,7 +1203,7 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       d.M = Fr.ns;
       d.N = p;
       d.K = Fr.ns;
-      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC;
+      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_AUP;
       d.alpha = one;
       d.beta = zero;
       return true;

@@ -14,6 +14,32 @@ struct zf {
   float re, im;
 };
 
+// ---- global-memory access ---------------------------------------------------
+// Pointers read from descriptor arrays are generic (flat) pointers.  Accessing
+// them through the global address space lets the compiler emit global loads
+// and stores, whose completion counter is separate from the LDS one; a flat
+// load would make every later LDS wait also wait for it.
+typedef __attribute__((address_space(1))) const double* gcdp;
+typedef __attribute__((address_space(1))) double* gdp;
+typedef __attribute__((address_space(1))) const float* gcfp;
+typedef __attribute__((address_space(1))) float* gfp;
+__device__ inline double gld(const double* p) { return *(gcdp)p; }
+__device__ inline float gld(const float* p) { return *(gcfp)p; }
+__device__ inline void gst(double* p, double v) { *(gdp)p = v; }
+__device__ inline void gst(float* p, float v) { *(gfp)p = v; }
+typedef double dpair __attribute__((ext_vector_type(2)));
+typedef float fpair __attribute__((ext_vector_type(2)));
+__device__ inline zd gld(const zd* p) {
+  dpair v = *(__attribute__((address_space(1))) const dpair*)p;
+  return zd{v.x, v.y};
+}
+__device__ inline zf gld(const zf* p) {
+  fpair v = *(__attribute__((address_space(1))) const fpair*)p;
+  return zf{v.x, v.y};
+}
+__device__ inline void gst(zd* p, const zd& v) { *(__attribute__((address_space(1))) dpair*)p = dpair{v.re, v.im}; }
+__device__ inline void gst(zf* p, const zf& v) { *(__attribute__((address_space(1))) fpair*)p = fpair{v.re, v.im}; }
+
 // ---- scalar traits --------------------------------------------------------
 template <typename T>
 struct ST;

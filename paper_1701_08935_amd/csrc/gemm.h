@@ -7,7 +7,11 @@
 // opA/opB optionally transposed / conjugated; C and Cin column-major with
 // leading dimensions ldc/ldcin, or row-major with GF_TRANSC.  GF_TRI keeps
 // only entries with i - j >= tri_off (lower-triangular updates of symmetric
-// fronts).  One descriptor per independent product; a launch covers a list.
+// fronts).  GF_ALOW / GF_AUP declare opA lower / upper triangular (square,
+// M == K; the other triangle is stored as zeros): each row tile then runs its
+// inner loop only over the nonzero part, which halves the work of products
+// with an explicit triangular inverse.  One descriptor per independent
+// product; a launch covers a list.
 #pragma once
 
 #include "dev_common.h"
@@ -23,6 +27,8 @@ enum GemmFlags {
   GF_TRI = 32,
   GF_CRS_INV = 64,
   GF_CRS = 128,
+  GF_ALOW = 256,
+  GF_AUP = 512,
 };
 
 template <typename T>
@@ -68,6 +74,11 @@ inline void gemm_work(const GemmDesc<T>& d, double* flops, double* bytes) {
     }
   }
   const double fm = ST<T>::cplx ? 8.0 : 2.0;
+  if (d.flags & (GF_ALOW | GF_AUP)) {
+    *flops += fm * N * (M * (M + 1.0) / 2.0);  // row i of a triangular opA has i+1 (or M-i) nonzeros
+    *bytes += (double)sizeof(T) * (M * (M + 1.0) / 2.0 + K * N + ent * (d.Cin ? 2.0 : 1.0));
+    return;
+  }
   *flops += fm * ent * K;
   *bytes += (double)sizeof(T) * (M * K + K * N + ent * (d.Cin ? 2.0 : 1.0));
 }

@@ -4,8 +4,9 @@
 // Tiling: one 256-thread workgroup (4 waves) computes a 64 x 64 tile of C;
 // each wave owns a 32 x 32 quarter as 2 x 2 blocks of 16 x 16.  The inner
 // dimension advances in chunks of 16 staged through LDS (real and imaginary
-// parts in separate arrays), double-buffered so the global loads of chunk
-// c+1 overlap the MFMAs of chunk c.  Each 16 x 16 x 4 step uses
+// parts in separate arrays), double-buffered: the global loads of chunk c+1
+// are issued into registers before the MFMAs of chunk c and written to the
+// other LDS buffer after them, with one barrier per chunk.  Each 16 x 16 x 4 step uses
 // v_mfma_f64_16x16x4_f64 (double, complex double) or v_mfma_f32_16x16x4_f32
 // (complex float); a complex product is four real ones:
 //   Cre += Are Bre - Aim Bim,  Cim += Are Bim + Aim Bre.
@@ -76,11 +77,12 @@ __device__ inline void split<zf>(const zf& v, float* re, float* im) {
 // TAG only separates the uses in profiles: 0 front updates, 1 supernodal
 // solves, 2 Krylov / Rayleigh-Ritz products.
 template <typename T, int TAG>
-__global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(256, 2) void gemm_batched_kernel(const GemmDesc<T>* __restrict__ descs) {
   typedef typename MfmaTraits<T>::R R;
   typedef typename MfmaTraits<T>::V4 V4;
   constexpr bool CPLX = MfmaTraits<T>::cplx;
-  constexpr int NP = CPLX ? 2 : 1;  // real planes
+  constexpr int NP = CPLX ? 2 : 1;                    // real planes
+  constexpr int NL = GEMM_TILE * TK / 256;            // staged elements per thread and operand
 
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tilesM = (d.M + GEMM_TILE - 1) / GEMM_TILE;
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
   const bool tri = (d.flags & GF_TRI) != 0;
   if (tri && (m0 + GEMM_TILE - 1) - n0 < d.tri_off) return;
 
-  // [buffer][plane][k][row]
+  // [buffer][plane][k][row]: double-buffered chunks
   __shared__ R As[2][NP][TK][LDT];
   __shared__ R Bs[2][NP][TK][LDT];
 
@@ -104,102 +106,106 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
   const bool ta = (d.flags & GF_TRANSA) != 0, tb = (d.flags & GF_TRANSB) != 0;
   const bool ca = (d.flags & GF_CONJA) != 0, cb = (d.flags & GF_CONJB) != 0;
 
-  V4 acc[2][2][NP];
+  V4 acc[NP][2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int q = 0; q < NP; ++q)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int q = 0; q < NP; ++q) acc[a][b][q] = V4{0, 0, 0, 0};
+      for (int b = 0; b < 2; ++b) acc[q][a][b] = V4{0, 0, 0, 0};
 
-  T ra[4], rb[4];  // staged global values of the next chunk
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
-      int i, t;
-      if (!ta) {
-        i = e % GEMM_TILE;
-        t = e / GEMM_TILE;
-      } else {
-        i = e / TK;
-        t = e % TK;
-      }
-      int gi = m0 + i, gt = k0 + t;
-      T v = ST<T>::zero();
-      if (gi < d.M && gt < d.K) {
-        v = ta ? d.A[gt + (int64_t)gi * d.lda] : d.A[gi + (int64_t)gt * d.lda];
-        if (ca) v = conj_(v);
-        if (d.dk) v = mul(v, d.dk[gt]);
-      }
-      ra[q] = v;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
-      int t, j;
-      if (!tb) {
-        t = e % TK;
-        j = e / TK;
-      } else {
-        j = e % GEMM_TILE;
-        t = e / GEMM_TILE;
-      }
-      int gj = n0 + j, gt = k0 + t;
-      T v = ST<T>::zero();
-      if (gj < d.N && gt < d.K) {
-        v = tb ? d.B[gj + (int64_t)gt * d.ldb] : d.B[gt + (int64_t)gj * d.ldb];
-        if (cb) v = conj_(v);
-      }
-      rb[q] = v;
+  // element e of a 64 x TK (A) or TK x 64 (B) chunk, laid out so that
+  // consecutive threads read consecutive addresses
+  auto a_idx = [&](int e, int* i, int* t) {
+    if (!ta) {
+      *i = e % GEMM_TILE;
+      *t = e / GEMM_TILE;
+    } else {
+      *i = e / TK;
+      *t = e % TK;
     }
   };
-  auto sstore = [&](int buf) {
+  auto b_idx = [&](int e, int* t, int* j) {
+    if (!tb) {
+      *t = e % TK;
+      *j = e / TK;
+    } else {
+      *j = e % GEMM_TILE;
+      *t = e / GEMM_TILE;
+    }
+  };
+  // inner range: all of K, or the nonzero part of a triangular opA
+  int kbeg = 0, kend = d.K;
+  if (d.flags & GF_ALOW) kend = min(d.K, m0 + GEMM_TILE);
+  if (d.flags & GF_AUP) kbeg = m0;
+  const bool has_dk = d.dk != nullptr;
+
+  // Global loads of a chunk go straight into registers: out-of-range elements
+  // read the (valid) first element instead and are zeroed when the chunk is
+  // written to LDS, so no load waits on a branch and all of them are in
+  // flight together while the MFMAs of the previous chunk run.
+  T ra[NL], rb[NL], rd[NL];
+  auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
+    for (int q = 0; q < NL; ++q) {
       int i, t;
-      if (!ta) {
-        i = e % GEMM_TILE;
-        t = e / GEMM_TILE;
-      } else {
-        i = e / TK;
-        t = e % TK;
-      }
+      a_idx(tid + 256 * q, &i, &t);
+      const int gi = m0 + i, gt = k0 + t;
+      const bool ok = gi < d.M && gt < kend;
+      ra[q] = gld(ok ? (ta ? d.A + gt + (int64_t)gi * d.lda : d.A + gi + (int64_t)gt * d.lda) : d.A);
+      if (has_dk) rd[q] = gld(d.dk + (ok ? gt : 0));
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      int t, j;
+      b_idx(tid + 256 * q, &t, &j);
+      const int gj = n0 + j, gt = k0 + t;
+      const bool ok = gj < d.N && gt < kend;
+      rb[q] = gld(ok ? (tb ? d.B + gj + (int64_t)gt * d.ldb : d.B + gt + (int64_t)gj * d.ldb) : d.B);
+    }
+  };
+  auto sstore = [&](int buf, int k0) {
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      int i, t;
+      a_idx(tid + 256 * q, &i, &t);
+      const bool ok = m0 + i < d.M && k0 + t < kend;
+      T v = ok ? ra[q] : ST<T>::zero();
+      if (ca) v = conj_(v);
+      if (has_dk) v = mul(v, rd[q]);
       R re, im = 0;
-      split<T>(ra[q], &re, &im);
+      split<T>(v, &re, &im);
       As[buf][0][t][i] = re;
       if constexpr (CPLX) As[buf][NP - 1][t][i] = im;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
+    for (int q = 0; q < NL; ++q) {
       int t, j;
-      if (!tb) {
-        t = e % TK;
-        j = e / TK;
-      } else {
-        j = e % GEMM_TILE;
-        t = e / GEMM_TILE;
-      }
+      b_idx(tid + 256 * q, &t, &j);
+      const bool ok = n0 + j < d.N && k0 + t < kend;
+      T v = ok ? rb[q] : ST<T>::zero();
+      if (cb) v = conj_(v);
       R re, im = 0;
-      split<T>(rb[q], &re, &im);
+      split<T>(v, &re, &im);
       Bs[buf][0][t][j] = re;
       if constexpr (CPLX) Bs[buf][NP - 1][t][j] = im;
     }
   };
 
-  const int nchunk = (d.K + TK - 1) / TK;
+  const int nchunk = kend > kbeg ? (kend - kbeg + TK - 1) / TK : 0;
   if (nchunk > 0) {
-    gload(0);
-    sstore(0);
+    gload(kbeg);
+    sstore(0, kbeg);
   }
   __syncthreads();
   for (int c = 0; c < nchunk; ++c) {
+    const int k0 = kbeg + c * TK;
     const int buf = c & 1;
-    if (c + 1 < nchunk) gload((c + 1) * TK);
+    if (c + 1 < nchunk) gload(k0 + TK);  // in flight during this chunk's MFMAs
+    const int ksteps = min(TK, kend - k0);  // a short last chunk skips its empty steps
 #pragma unroll
     for (int kk = 0; kk < TK / 4; ++kk) {
+      if (4 * kk >= ksteps) break;
       const int k = 4 * kk + lk;
       R are[2], aim[2], bre[2], bim[2];
 #pragma unroll
@@ -212,25 +218,53 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
         bre[b] = Bs[buf][0][k][wn + 16 * b + li];
         if constexpr (CPLX) bim[b] = Bs[buf][NP - 1][k][wn + 16 * b + li];
       }
+      // four independent accumulators per group, so dependent MFMAs are spaced
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc[a][b][0] = mfma(are[a], bre[b], acc[a][b][0]);
-          if constexpr (CPLX) {
-            acc[a][b][0] = mfma(-aim[a], bim[b], acc[a][b][0]);
-            acc[a][b][1] = mfma(are[a], bim[b], acc[a][b][1]);
-            acc[a][b][1] = mfma(aim[a], bre[b], acc[a][b][1]);
-          }
-        }
+        for (int b = 0; b < 2; ++b) acc[0][a][b] = mfma(are[a], bre[b], acc[0][a][b]);
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[1][a][b] = mfma(are[a], bim[b], acc[1][a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[0][a][b] = mfma(-aim[a], bim[b], acc[0][a][b]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) acc[1][a][b] = mfma(aim[a], bre[b], acc[1][a][b]);
+      }
     }
-    if (c + 1 < nchunk) sstore(buf ^ 1);
-    __syncthreads();
+    if (c + 1 < nchunk) sstore(buf ^ 1, k0 + TK);
+    __syncthreads();  // buf^1 is written; every wave is done reading buf
   }
 
+  // Epilogue.  All loads (row scales, Cin) are issued before any of them is
+  // used, so their latency is paid once per tile.
   const bool tc = (d.flags & GF_TRANSC) != 0;
   const bool use_crs = (d.flags & (GF_CRS | GF_CRS_INV)) != 0;
   const bool crs_inv = (d.flags & GF_CRS_INV) != 0;
+  const bool has_cin = d.Cin != nullptr;
+  T rs[2][4], cv[2][4][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = m0 + wm + 16 * a + MfmaTraits<T>::row(lk, v);
+      const bool iok = i < d.M;
+      if (use_crs) rs[a][v] = gld(d.crs + (iok ? i : 0));
+      if (has_cin) {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int j = n0 + wn + 16 * b + li;
+          const bool ok = iok && j < d.N;
+          cv[a][v][b] = gld(ok ? (tc ? d.Cin + (int64_t)i * d.ldcin + j : d.Cin + i + (int64_t)j * d.ldcin) : d.Cin);
+        }
+      }
+    }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -238,7 +272,7 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
       const int i = m0 + wm + 16 * a + MfmaTraits<T>::row(lk, v);
       if (i >= d.M) continue;
       T s = d.beta;
-      if (use_crs) s = crs_inv ? inv_(d.crs[i]) : d.crs[i];
+      if (use_crs) s = crs_inv ? inv_(rs[a][v]) : rs[a][v];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int j = n0 + wn + 16 * b + li;
@@ -246,18 +280,12 @@ __global__ __launch_bounds__(256) void gemm_batched_kernel(const GemmDesc<T>* __
         if (tri && i - j < d.tri_off) continue;
         T accv;
         if constexpr (CPLX)
-          accv = T{acc[a][b][0][v], acc[a][b][1][v]};
+          accv = T{acc[0][a][b][v], acc[1][a][b][v]};
         else
-          accv = acc[a][b][0][v];
+          accv = acc[0][a][b][v];
         T out = mul(d.alpha, accv);
-        if (d.Cin) {
-          T cin = tc ? d.Cin[(int64_t)i * d.ldcin + j] : d.Cin[i + (int64_t)j * d.ldcin];
-          out = fma_(out, s, cin);
-        }
-        if (tc)
-          d.C[(int64_t)i * d.ldc + j] = out;
-        else
-          d.C[i + (int64_t)j * d.ldc] = out;
+        if (has_cin) out = fma_(out, s, cv[a][v][b]);
+        gst(tc ? d.C + (int64_t)i * d.ldc + j : d.C + i + (int64_t)j * d.ldc, out);
       }
     }
 }
