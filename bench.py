@@ -94,6 +94,38 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True):
             "info": info, "n": gp.n, "nnz": gp.nnz, "rc": rc}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_batched_c1.txt")
+GEMM_SOURCES = [os.path.join(ROOT, "paper_1701_08935_amd", "csrc", f) for f in ("gemm.hip", "gemm.h", "dev_common.h")]
+
+
+def gemm_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in GEMM_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, scaled by the copy-kernel calibration;
+    None when no summary exists or the GEMM sources changed since it was
+    taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != gemm_source_hash():
+        return None
+    key = f"{kernel}_bytes_per_launch"
+    return float(kv[key]) if key in kv else None
+
+
 def roofline(prof, steps, fp32=False):
     if not prof:
         return None
@@ -109,8 +141,10 @@ def roofline(prof, steps, fp32=False):
                 "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     ach = v["flops"] / sec / 1e12
+    launches = max(v["launches"], 1)
     return {"kernel": k, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-            "traffic": None, "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
+            "traffic": measured_traffic(k), "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / launches,
+            "flops_per_launch": v["flops"] / launches, "algorithmic_bytes_per_launch": v["bytes"] / launches}
 
 
 def cpu_baseline(sample_grid=16, n_lambda=64, n_ss=96):
@@ -170,7 +204,20 @@ def main():
     ap.add_argument("--r1", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+
+        n = args.calib_copy * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": 8 * n, "calib_copy_bytes_written": 8 * n, "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
               "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
