@@ -1669,6 +1669,7 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   std::vector<double> th(nss), rnh(3 * nss);
   std::vector<int> sel;
   int k = 0;
+  int empty_runs = 0;
   bool converged = false;
   zolo_status frc = ZOLO_OK;
   for (int it = 1; it <= std::max(1, o.max_subspace_iter); ++it) {
@@ -1720,6 +1721,17 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     if (!sel.empty() && worst <= o.tol_resid) {
       converged = true;
       break;
+    }
+    // An interval with no eigenvalue: after two filtered iterations any
+    // eigenvector inside (a, b) present in the start block would dominate the
+    // subspace, so two empty selections in a row mean the count is zero.
+    if (sel.empty()) {
+      if (++empty_runs >= 2) {
+        converged = true;
+        break;
+      }
+    } else {
+      empty_runs = 0;
     }
   }
   st.t_iter = now_s() - t0;
