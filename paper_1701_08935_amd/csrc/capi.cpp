@@ -119,6 +119,8 @@ void gaussian_host(uint64_t seed, size_t n, std::vector<double>* out) {
 
 struct GemmLaunch {
   int off = 0, cnt = 0, tiles = 0;
+  int maxM = 0, maxN = 0;  // bounds over the launch's products (GEMM launches)
+  int max_split = 1;       // largest inner-dimension split of its products
   double flops = 0.0, bytes = 0.0;  // algorithmic work of the launch
 };
 
@@ -326,16 +328,60 @@ int upload_gemm(DevArena& mem, const std::vector<GemmDesc<T>>& h, GemmDesc<T>** 
 
 template <typename T>
 void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s, int tag) {
-  if (L.cnt <= 0 || L.tiles <= 0) return;
+  if (L.cnt <= 0 || L.maxM <= 0 || L.maxN <= 0) return;
   prof::Scope ps(tag == 0 ? ZOLO_PROF_GEMM_FACTOR : tag == 1 ? ZOLO_PROF_GEMM_SOLVE : ZOLO_PROF_GEMM_KRYLOV, L.flops,
                  L.bytes, s);
-  gemm_batched<T>(base + L.off, L.cnt, L.tiles, s, tag);
+  gemm_batched<T>(base + L.off, L.cnt, L.maxM, L.maxN, s, tag, L.max_split);
+}
+
+// Inner-dimension splits of the products of GEMM launches (GemmDesc::splitk).
+// A launch with fewer tiles than kSplitBelow workgroups splits each product
+// whose inner loop has at least 2 * kMinSplitChunks chunks, aiming at about
+// kSplitTarget workgroups.  Launches run one after another on a stream, so
+// they share one partial buffer and one tile-counter array, sized for the
+// largest launch; patch_split fills in the pointers once they exist.
+constexpr int kSplitBelow = 512, kSplitTarget = 1024, kMinSplitChunks = 8, kMaxSplit = 16;
+struct SplitPlan {
+  std::vector<std::pair<int, std::pair<int64_t, int64_t>>> at;  // descriptor -> (part offset, counter offset)
+  int64_t part = 0, cnt = 0;                                    // sizes (real scalars, counters)
+};
+template <typename T>
+void plan_split(std::vector<GemmDesc<T>>& gd, GemmLaunch& g, SplitPlan* sp) {
+  if (g.cnt <= 0 || g.maxM <= 0 || g.maxN <= 0) return;
+  const int tn = gemm_tile_n(g.maxN), tk = tn == 96 ? 8 : 16;
+  int64_t total = 0;
+  for (int i = g.off; i < g.off + g.cnt; ++i) total += gemm_tiles(gd[i].M, gd[i].N);
+  if (total >= kSplitBelow) return;
+  const int goal = (int)std::min<int64_t>(kMaxSplit, (kSplitTarget + total - 1) / std::max<int64_t>(total, 1));
+  const int64_t pe = gemm_part_elems(g.maxN, ST<T>::cplx);
+  int64_t po = 0, co = 0;
+  for (int i = g.off; i < g.off + g.cnt; ++i) {
+    GemmDesc<T>& d = gd[i];
+    const int chunks = (d.K + tk - 1) / tk;
+    const int S = std::min(goal, chunks / kMinSplitChunks);
+    if (S < 2) continue;
+    const int64_t t = gemm_tiles(d.M, d.N);
+    d.splitk = S;
+    sp->at.push_back({i, {po, co}});
+    po += (int64_t)S * t * pe;
+    co += t;
+    g.max_split = std::max(g.max_split, S);
+  }
+  sp->part = std::max(sp->part, po);
+  sp->cnt = std::max(sp->cnt, co);
+}
+template <typename T>
+void patch_split(std::vector<GemmDesc<T>>& gd, const SplitPlan& sp, typename ST<T>::real* part, int* cnt) {
+  for (const auto& a : sp.at) {
+    gd[a.first].part = part + a.second.first;
+    gd[a.first].cnt = cnt + a.second.second;
+  }
 }
 
 // out (m x n, col-major ld ldo) [+]= X^T Y with X: N x m row-major (ld ldx), Y: N x n row-major (ld ldy)
 int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t N, int m, int n,
             double* out, int64_t ldo, bool add, hipStream_t s) {
-  int tiles = gemm_tiles<double>(m, n);
+  int tiles = gemm_tiles(m, n);
   int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
   while (S * (int64_t)m * n > ws.partial_len && S > 1) S /= 2;
   if (S * (int64_t)m * n > ws.partial_len) {
@@ -368,7 +414,7 @@ int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_
     double fl = 0.0, by = 0.0;
     for (auto& d : h) gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<double>(ws.gdesc, (int)h.size(), tiles, s, 2);
+    gemm_batched<double>(ws.gdesc, (int)h.size(), m, n, s, 2);
   }
   {
     prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 8.0 * (double)m * n * (h.size() + 1), s);
@@ -403,7 +449,7 @@ int gemm_nt_big(Workspace& ws, double* C, int64_t ldc, const double* Cin, int64_
     double fl = 0.0, by = 0.0;
     gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, gemm_tiles<double>(p, (int)N), s, 2);
+    gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, p, (int)N, s, 2);
   }
   HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
@@ -756,33 +802,46 @@ extern "C" zolo_status zolo_filter_plan(double am, double ap, double bm, double 
 // ===========================================================================
 namespace {
 
+// Numeric factorization of one pole in two phases: factor_plan allocates the
+// factor and its temporaries and uploads the program's GEMM descriptors
+// (synchronous host work); factor_run only enqueues kernels on a stream, so
+// several poles can run concurrently on their own streams.
+struct FactorLevelG {
+  std::vector<GemmLaunch> trail;  // per step J
+  GemmLaunch schur;
+  std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
+};
 template <typename T>
-zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, PoleMF<T>* pole, hipStream_t s) {
+struct FactorWork {
+  DevArena tmp;
+  T* upd = nullptr;
+  T* scratch = nullptr;
+  int* flag = nullptr;
+  GemmDesc<T>* dgd = nullptr;
+  std::vector<FactorLevelG> lg;
+  double sr = 0.0, si = 0.0;
+};
+
+template <typename T>
+zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, PoleMF<T>* pole, FactorWork<T>* fw) {
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
   CHK(F->mem.alloc(&pole->panel, P->panel_total));
   CHK(F->mem.alloc(&pole->inv, P->inv_total));
   CHK(F->mem.alloc(&pole->dvec, P->n));
   F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
-  DevArena tmp;
-  T* upd = nullptr;
-  T* scratch = nullptr;
-  int* flag = nullptr;
-  CHK(tmp.alloc(&upd, P->upd_total));
-  CHK(tmp.alloc(&scratch, std::max<int64_t>(P->inv_scratch, 1)));
-  CHK(tmp.alloc(&flag, 1));
-  HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
-  HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
-  HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
-  HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
+  fw->sr = sr;
+  fw->si = si;
+  DevArena& tmp = fw->tmp;
+  CHK(tmp.alloc(&fw->upd, P->upd_total));
+  CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch, 1)));
+  CHK(tmp.alloc(&fw->flag, 1));
+  T* upd = fw->upd;
+  T* scratch = fw->scratch;
   // GEMM descriptors of the whole program (pointers into this pole's arrays)
   std::vector<GemmDesc<T>> gd;
-  struct LevelG {
-    std::vector<GemmLaunch> trail;  // per step J
-    GemmLaunch schur;
-    std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
-  };
-  std::vector<LevelG> lg(nl);
+  std::vector<FactorLevelG>& lg = fw->lg;
+  lg.assign(nl, FactorLevelG());
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
   for (int L = 0; L < nl; ++L) {
     std::vector<int> fs = S.levels[L];
@@ -817,7 +876,8 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.beta = one;
         gd.push_back(d);
         gemm_work(d, &g.flops, &g.bytes);
-        g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+        g.maxM = std::max(g.maxM, d.M);
+        g.maxN = std::max(g.maxN, d.N);
       }
       g.cnt = (int)gd.size() - g.off;
       lg[L].trail.push_back(g);
@@ -849,7 +909,8 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.beta = one;
         gd.push_back(d);
         gemm_work(d, &g.flops, &g.bytes);
-        g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+        g.maxM = std::max(g.maxM, d.M);
+        g.maxN = std::max(g.maxN, d.N);
       }
       g.cnt = (int)gd.size() - g.off;
       lg[L].schur = g;
@@ -890,7 +951,8 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.beta = zero;
         gd.push_back(d);
         gemm_work(d, &g1.flops, &g1.bytes);
-        g1.tiles = std::max(g1.tiles, gemm_tiles<T>(d.M, d.N));
+        g1.maxM = std::max(g1.maxM, d.M);
+        g1.maxN = std::max(g1.maxN, d.N);
       }
       g1.cnt = (int)gd.size() - g1.off;
       g2.off = (int)gd.size();
@@ -913,15 +975,47 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.beta = zero;
         gd.push_back(d);
         gemm_work(d, &g2.flops, &g2.bytes);
-        g2.tiles = std::max(g2.tiles, gemm_tiles<T>(d.M, d.N));
+        g2.maxM = std::max(g2.maxM, d.M);
+        g2.maxN = std::max(g2.maxN, d.N);
       }
       g2.cnt = (int)gd.size() - g2.off;
       lg[L].inv1.push_back(g1);
       lg[L].inv2.push_back(g2);
     }
   }
-  GemmDesc<T>* dgd = nullptr;
-  CHK(tmp.upload(&dgd, gd.data(), gd.size()));
+  // inner-dimension splits of launches with few tiles
+  SplitPlan sp;
+  for (FactorLevelG& l : lg) {
+    for (GemmLaunch& g : l.trail) plan_split(gd, g, &sp);
+    plan_split(gd, l.schur, &sp);
+    for (GemmLaunch& g : l.inv1) plan_split(gd, g, &sp);
+    for (GemmLaunch& g : l.inv2) plan_split(gd, g, &sp);
+  }
+  if (!sp.at.empty()) {
+    typename ST<T>::real* part = nullptr;
+    int* cnt = nullptr;
+    CHK(tmp.alloc(&part, sp.part));
+    CHK(tmp.alloc(&cnt, sp.cnt));
+    HIPC(hipMemset(cnt, 0, sizeof(int) * sp.cnt));
+    patch_split(gd, sp, part, cnt);
+  }
+  CHK(tmp.upload(&fw->dgd, gd.data(), gd.size()));
+  return ZOLO_OK;
+}
+
+template <typename T>
+zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipStream_t s) {
+  const Symbolic& S = P->S;
+  const int nl = (int)S.levels.size();
+  T* upd = fw->upd;
+  int* flag = fw->flag;
+  const GemmDesc<T>* dgd = fw->dgd;
+  const std::vector<FactorLevelG>& lg = fw->lg;
+  const double sr = fw->sr, si = fw->si;
+  HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
+  HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
+  HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
+  HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
   // run the program level by level
   for (int L = 0; L < nl; ++L) {
     {
@@ -948,13 +1042,66 @@ zolo_status factor_pole(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
     }
   }
-  int hflag = 0;
-  HIPC(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
   HIPC(hipGetLastError());
-  if (hflag) {
-    set_error("zero pivot in the LDL^T of A - sigma B");
-    return ZOLO_EBREAKDOWN;
+  return ZOLO_OK;
+}
+
+// all poles: plan each, run each on its own stream, wait, check pivots
+template <typename T>
+zolo_status factor_all(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs* co, std::vector<PoleMF<T>>* poles,
+                       hipStream_t s) {
+  const int np = co->r1;
+  poles->assign(np, PoleMF<T>());
+  std::vector<std::unique_ptr<FactorWork<T>>> fw(np);
+  for (int j = 0; j < np; ++j) {
+    fw[j].reset(new FactorWork<T>());
+    CHK(factor_plan<T>(F, P, co->sigma_hat_re[j], co->sigma_hat_im[j], &(*poles)[j], fw[j].get()));
+  }
+  // pole 0 on the caller's stream, the others on streams of their own that
+  // start after the work already queued on it and end before it continues
+  std::vector<hipStream_t> ss(np, s);
+  std::vector<hipEvent_t> ev;
+  zolo_status rc = ZOLO_OK;
+  hipEvent_t start = nullptr;
+  HIPC(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+  HIPC(hipEventRecord(start, s));
+  for (int j = 1; j < np && rc == ZOLO_OK; ++j) {
+    if (hipStreamCreateWithFlags(&ss[j], hipStreamNonBlocking) != hipSuccess) {
+      ss[j] = s;
+      continue;
+    }
+    if (hipStreamWaitEvent(ss[j], start, 0) != hipSuccess) rc = ZOLO_EDEVICE;
+  }
+  for (int j = 0; j < np && rc == ZOLO_OK; ++j) rc = (zolo_status)factor_run<T>(P, &(*poles)[j], fw[j].get(), ss[j]);
+  for (int j = 1; j < np; ++j) {
+    if (ss[j] == s) continue;
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+      (void)hipEventRecord(e, ss[j]);
+      (void)hipStreamWaitEvent(s, e, 0);
+      ev.push_back(e);
+    }
+  }
+  hipError_t se = hipStreamSynchronize(s);
+  for (int j = 1; j < np; ++j)
+    if (ss[j] != s) {
+      (void)hipStreamSynchronize(ss[j]);
+      (void)hipStreamDestroy(ss[j]);
+    }
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(start);
+  if (rc != ZOLO_OK) return rc;
+  if (se != hipSuccess) {
+    set_error("HIP error in the factorization: %s", hipGetErrorString(se));
+    return ZOLO_EDEVICE;
+  }
+  for (int j = 0; j < np; ++j) {
+    int hflag = 0;
+    HIPC(hipMemcpy(&hflag, fw[j]->flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (hflag) {
+      set_error("zero pivot in the LDL^T of A - sigma B (pole %d)", j);
+      return ZOLO_EBREAKDOWN;
+    }
   }
   return ZOLO_OK;
 }
@@ -982,15 +1129,10 @@ extern "C" zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* P, const zolo_fil
   F->co = *co;
   F->precision = precision;
   double t0 = now_s();
-  for (int j = 0; j < co->r1; ++j) {
-    if (precision == ZOLO_PREC_FP64) {
-      F->pd.emplace_back();
-      CHK(factor_pole<zd>(F.get(), P, co->sigma_hat_re[j], co->sigma_hat_im[j], &F->pd.back(), s));
-    } else {
-      F->pf.emplace_back();
-      CHK(factor_pole<zf>(F.get(), P, co->sigma_hat_re[j], co->sigma_hat_im[j], &F->pf.back(), s));
-    }
-  }
+  if (precision == ZOLO_PREC_FP64)
+    CHK(factor_all<zd>(F.get(), P, co, &F->pd, s));
+  else
+    CHK(factor_all<zf>(F.get(), P, co, &F->pf, s));
   F->t_factor = now_s() - t0;
   *out = F.release();
   return ZOLO_OK;
@@ -1129,7 +1271,8 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
           if (!mk(j, Fr, fs[i], i, d)) continue;
           gd.push_back(d);
           gemm_work(d, &g.flops, &g.bytes);
-          g.tiles = std::max(g.tiles, gemm_tiles<T>(d.M, d.N));
+          g.maxM = std::max(g.maxM, d.M);
+        g.maxN = std::max(g.maxN, d.N);
         }
       g.cnt = (int)gd.size() - g.off;
     };
@@ -1208,6 +1351,22 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       d.beta = zero;
       return true;
     });
+  }
+  // inner-dimension splits of launches with few tiles (the top levels)
+  SplitPlan sp;
+  for (int L = 0; L < nl; ++L) {
+    plan_split(gd, G->f2[L], &sp);
+    plan_split(gd, G->f3[L], &sp);
+    plan_split(gd, G->b2[L], &sp);
+    plan_split(gd, G->b3[L], &sp);
+  }
+  if (!sp.at.empty()) {
+    typename ST<T>::real* part = nullptr;
+    int* cnt = nullptr;
+    CHK(G->mem.alloc(&part, sp.part));
+    CHK(G->mem.alloc(&cnt, sp.cnt));
+    HIPC(hipMemset(cnt, 0, sizeof(int) * sp.cnt));
+    patch_split(gd, sp, part, cnt);
   }
   CHK(G->mem.upload(&G->gd, gd.data(), gd.size()));
   return ZOLO_OK;

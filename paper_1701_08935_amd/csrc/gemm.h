@@ -39,6 +39,16 @@ struct GemmDesc {
   const T* Cin;  // may equal C; null when beta == 0 and no row scale
   const T* dk;   // inner-dimension scale (length K), may be null
   const T* crs;  // row scale of Cin (GF_CRS / GF_CRS_INV), may be null
+  // Split of the inner dimension (splitk > 1): the product is computed by
+  // splitk workgroups per tile over consecutive K ranges; each writes its
+  // partial sums to part (splitk * tiles * gemm_part_elems(maxM, maxN) real
+  // scalars) and bumps cnt[tile] (zero before the launch, reset to zero by
+  // the workgroup that arrives last); that one adds the partials in split
+  // order, so the result does not depend on arrival order, and applies the
+  // epilogue.
+  void* part;
+  int* cnt;
+  int splitk;
   int64_t lda, ldb, ldc, ldcin;
   int M, N, K;
   int tri_off;
@@ -46,17 +56,21 @@ struct GemmDesc {
   T alpha, beta;
 };
 
-constexpr int GEMM_TILE = 64;
+// Tile shape the launcher picks: 64 rows; 96 columns when the launch's
+// largest N is in (64, 96], else 64.
+int gemm_tile_m(int maxM);
+int gemm_tile_n(int maxN);
+// workgroups per product (and per split) of a launch with these bounds
+int gemm_tiles(int maxM, int maxN);
+// real scalars of partial sums one split of one tile writes
+int64_t gemm_part_elems(int maxN, bool cplx);
 
-template <typename T>
-inline int gemm_tiles(int M, int N) {
-  return ((M + GEMM_TILE - 1) / GEMM_TILE) * ((N + GEMM_TILE - 1) / GEMM_TILE);
-}
-
-// d_desc: device array of n descriptors; max_tiles = max over descriptors of gemm_tiles.
+// d_desc: device array of n descriptors; maxM / maxN: upper bounds of every
+// descriptor's M and N (they size the grid and select the tile shape);
+// max_split: largest splitk of the descriptors.
 // tag: 0 front updates, 1 supernodal solves, 2 Krylov / Rayleigh-Ritz (profile names only).
 template <typename T>
-void gemm_batched(const GemmDesc<T>* d_desc, int n, int max_tiles, hipStream_t s, int tag);
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split = 1);
 
 // Algorithmic work of one descriptor: entries of C computed and flops
 // (8 per complex multiply-add, 2 per real one), and the bytes a product
