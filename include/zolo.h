@@ -46,7 +46,8 @@ typedef enum {
   ZOLO_EGAP = 5,       /* a Ritz value fell inside a stated eigengap         */
   ZOLO_ESUBSPACE = 6,  /* subspace too small for the count found             */
   ZOLO_EDEVICE = 7,    /* HIP runtime error                                  */
-  ZOLO_EBREAKDOWN = 8  /* zero pivot in a factorization or Gram matrix       */
+  ZOLO_EBREAKDOWN = 8, /* zero pivot in a factorization or Gram matrix       */
+  ZOLO_ETIMEOUT = 9    /* zolo_wait: the query has not finished in time      */
 } zolo_status;
 
 typedef enum { ZOLO_REAL64 = 0, ZOLO_COMPLEX128 = 1 } zolo_scalar;
@@ -258,6 +259,53 @@ typedef struct {
 } zolo_kernel_profile;
 zolo_status zolo_profile_enable(int on);
 zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out);
+
+/*
+ * Serving: a request loop over resident pencils (not in the paper; it runs
+ * Algorithm 1 per query as zolo_solve does).
+ *
+ *  - zolo_server_create starts `slots` worker threads on the context's
+ *    device, each with its own HIP stream, so up to `slots` queries run on the
+ *    GPU at once and their kernels overlap.
+ *  - Admission: a query's device memory is estimated before it starts
+ *    (factors of its r1 poles from the pencil's symbolic analysis, the block
+ *    Krylov basis of max_gmres_iter steps, subspace and solve buffers); queued
+ *    queries start in arrival order while the estimates of the running ones
+ *    plus the next stay within hbm_budget_bytes (0 = 80% of the free device
+ *    memory at creation).  A query whose estimate alone exceeds the budget
+ *    fails with ZOLO_ENOMEM.
+ *  - Batching: queued queries with the same pencil, interval, eigengaps,
+ *    r1, r2 and precision share one filter (the same poles and factors); the
+ *    worker that starts the first takes the others with it and runs one
+ *    Algorithm 1 on their concatenated start blocks (block GMRES over all
+ *    their columns, up to 512).  Each of them receives the eigenpairs of
+ *    (a, b) found by that joint run.
+ *  - zolo_submit copies opts and the optional host start block (N x n_ss
+ *    row-major, n_ss = opts->n_ss or ceil(1.5 n_lambda_est); NULL draws it
+ *    from opts->seed) and returns at once.  The pencil must outlive the query.
+ *  - zolo_wait returns the query's status and hands over its result (freed
+ *    by the caller with zolo_result_free); timeout_ms < 0 waits forever; on
+ *    ZOLO_ETIMEOUT nothing is handed over and the query keeps running.
+ *  - zolo_server_destroy lets running and queued queries finish first; every
+ *    query handle of the server must be freed before it.  Functions of one
+ *    server may be called from several threads.
+ */
+typedef struct zolo_server zolo_server;
+typedef struct zolo_query zolo_query;
+typedef struct {
+  double t_submit, t_start, t_end;  /* seconds on a monotonic clock            */
+  int batch;                        /* queries in the joint run (1 = alone)    */
+  long long est_bytes;              /* admission estimate of the joint run     */
+  int done;                         /* 1 once the result is ready              */
+} zolo_query_info;
+zolo_status zolo_server_create(zolo_ctx* ctx, int slots, size_t hbm_budget_bytes, zolo_server** out);
+zolo_status zolo_submit(zolo_server* srv, zolo_pencil* p, double a, double b, int n_lambda_est, const zolo_opts* opts,
+                        const double* h_Q0, zolo_query** out);
+zolo_status zolo_wait(zolo_query* q, int timeout_ms, zolo_result** out);
+zolo_status zolo_query_get_info(const zolo_query* q, zolo_query_info* out);
+/* frees a query handle; waits for the query if it is still queued or running */
+void zolo_query_free(zolo_query* q);
+void zolo_server_destroy(zolo_server* srv);
 
 #ifdef __cplusplus
 }

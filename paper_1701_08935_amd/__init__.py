@@ -15,12 +15,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libzolo.so")
 
 ZOLO_OK, ZOLO_EINVAL, ZOLO_ENOTHERM, ZOLO_ENOMEM, ZOLO_ENOCONV = 0, 1, 2, 3, 4
-ZOLO_EGAP, ZOLO_ESUBSPACE, ZOLO_EDEVICE, ZOLO_EBREAKDOWN = 5, 6, 7, 8
+ZOLO_EGAP, ZOLO_ESUBSPACE, ZOLO_EDEVICE, ZOLO_EBREAKDOWN, ZOLO_ETIMEOUT = 5, 6, 7, 8, 9
 ZOLO_REAL64, ZOLO_COMPLEX128 = 0, 1
 ZOLO_PREC_FP64, ZOLO_PREC_MIXED = 0, 1
 ZOLO_MAX_R = 16
 STATUS_NAMES = {0: "ZOLO_OK", 1: "ZOLO_EINVAL", 2: "ZOLO_ENOTHERM", 3: "ZOLO_ENOMEM", 4: "ZOLO_ENOCONV",
-                5: "ZOLO_EGAP", 6: "ZOLO_ESUBSPACE", 7: "ZOLO_EDEVICE", 8: "ZOLO_EBREAKDOWN"}
+                5: "ZOLO_EGAP", 6: "ZOLO_ESUBSPACE", 7: "ZOLO_EDEVICE", 8: "ZOLO_EBREAKDOWN",
+                9: "ZOLO_ETIMEOUT"}
 
 _R = ZOLO_MAX_R
 _d = ctypes.c_double
@@ -59,6 +60,11 @@ class zolo_kernel_profile(ctypes.Structure):
 
 PROF_CLASSES = ["spmm", "gemm_factor", "gemm_solve", "gemm_krylov", "front_other", "solve_gather", "hls", "rr",
                 "elemwise"]
+
+
+class zolo_query_info(ctypes.Structure):
+    _fields_ = [("t_submit", _d), ("t_start", _d), ("t_end", _d), ("batch", _i), ("est_bytes", ctypes.c_longlong),
+                ("done", _i)]
 
 
 class zolo_filter_stats(ctypes.Structure):
@@ -103,6 +109,12 @@ _SIGS = {
     "zolo_result_free": (None, [_vp]),
     "zolo_profile_enable": (_i, [_i]),
     "zolo_profile_query": (_i, [_i, ctypes.POINTER(zolo_kernel_profile)]),
+    "zolo_server_create": (_i, [_vp, _i, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "zolo_submit": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, ctypes.POINTER(_vp)]),
+    "zolo_wait": (_i, [_vp, _i, ctypes.POINTER(_vp)]),
+    "zolo_query_get_info": (_i, [_vp, ctypes.POINTER(zolo_query_info)]),
+    "zolo_query_free": (None, [_vp]),
+    "zolo_server_destroy": (None, [_vp]),
 }
 
 
@@ -302,6 +314,82 @@ def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts
     finally:
         lib().zolo_result_free(h)
     return eig, vec[:, :cnt], struct_dict(st), rc
+
+
+class Server:
+    """zolo_server_create: worker threads with their own streams, admission by a
+    device-memory budget (bytes; 0 = 80% of free memory), batching of queries
+    that share a filter."""
+
+    def __init__(self, ctx: Context, slots: int = 4, budget_bytes: int = 0):
+        h = _vp()
+        _check(lib().zolo_server_create(ctx.h, int(slots), int(budget_bytes), ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+
+    def submit(self, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None) -> "Query":
+        """Q0: optional host numpy array N x n_ss (row-major float64)."""
+        import numpy as np
+
+        if opts is None:
+            opts = zolo_opts_default()
+        q0 = None if Q0 is None else np.ascontiguousarray(Q0, dtype=np.float64)
+        h = _vp()
+        _check(lib().zolo_submit(self.h, pencil.h, float(a), float(b), int(n_lambda_est), ctypes.byref(opts),
+                                 None if q0 is None else _np_ptr(q0), ctypes.byref(h)))
+        return Query(h, pencil, self)
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zolo_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Query:
+    def __init__(self, h, pencil: Pencil, server: Server):
+        self.h, self.pencil, self.server = h, pencil, server
+
+    def wait(self, timeout_ms: int = -1, allow=(ZOLO_ENOCONV,)):
+        """Returns (eigenvalues, vectors N x count on the device, stats, status, info)."""
+        import torch
+
+        r = _vp()
+        rc = lib().zolo_wait(self.h, int(timeout_ms), ctypes.byref(r))
+        if rc == ZOLO_ETIMEOUT:
+            raise ZoloError(rc, lib().zolo_last_error().decode())
+        if rc != ZOLO_OK and (rc not in allow or not r):
+            if r:
+                lib().zolo_result_free(r)
+            raise ZoloError(rc, lib().zolo_last_error().decode())
+        try:
+            L = lib()
+            cnt = L.zolo_result_count(r)
+            ev = L.zolo_result_eigenvalues(r)
+            eig = [ev[i] for i in range(cnt)]
+            vec = torch.empty((self.pencil.n, max(cnt, 1)), dtype=torch.float64, device=f"cuda:{self.server.ctx.device}")
+            if cnt:
+                _check(L.zolo_result_copy_vectors(r, _ptr(vec), vec.stride(0), _stream()))
+            st = zolo_stats()
+            _check(L.zolo_result_stats(r, ctypes.byref(st)))
+        finally:
+            lib().zolo_result_free(r)
+        return eig, vec[:, :cnt], struct_dict(st), rc, self.info()
+
+    def info(self) -> dict:
+        inf = zolo_query_info()
+        _check(lib().zolo_query_get_info(self.h, ctypes.byref(inf)))
+        return struct_dict(inf)
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.zolo_query_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.free()
 
 
 def zolo_profile_enable(on: bool = True):

@@ -1983,3 +1983,41 @@ extern "C" zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out) 
   return ZOLO_OK;
 }
 extern "C" void zolo_result_free(zolo_result* r) { delete r; }
+
+// ===========================================================================
+// internal helpers for the serving loop (serve.cpp)
+// ===========================================================================
+namespace zolo {
+
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision) {
+  const int64_t n = P->n;
+  const int64_t elem = precision == ZOLO_PREC_FP64 ? 16 : 8;
+  const int64_t factors = (int64_t)r1 * (P->panel_total + P->inv_total + n) * elem;
+  const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + P->inv_scratch) * elem;
+  const int64_t p = nss;
+  const int64_t solve = (int64_t)r1 * (6 * n * p) * elem;             // W, U, Xb, t, Y, X of the solve program
+  const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * 8  // basis, W, T1, Tb
+                         + 2 * (int64_t)r1 * n * p * 16;                   // per-pole solutions and residuals
+  const int64_t subspace = 8 * n * p * 8;                                   // Q, Y, AY, BY, X, AX, BX, result
+  const int64_t total = factors + std::max(factor_tmp, solve + krylov) + subspace;
+  return total + total / 10 + ((int64_t)64 << 20);
+}
+
+int64_t pencil_n(const zolo_pencil* P) { return P->n; }
+
+zolo_result* result_clone(const zolo_result* r) {
+  std::unique_ptr<zolo_result> c(new zolo_result());
+  c->n = r->n;
+  c->count = r->count;
+  c->eig = r->eig;
+  c->st = r->st;
+  if (r->count > 0) {
+    if (c->mem.alloc(&c->vec, r->n * r->count) != ZOLO_OK) return nullptr;
+    if (hipMemcpy(c->vec, r->vec, sizeof(double) * r->n * r->count, hipMemcpyDeviceToDevice) != hipSuccess) return nullptr;
+  }
+  return c.release();
+}
+
+void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out) { gaussian_host(seed, n, out); }
+
+}  // namespace zolo

@@ -64,4 +64,12 @@ struct Symbolic {
 int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* grid, int leaf_size,
                      Symbolic* S);
 
+// For the serving loop: device bytes one query needs at most (factors of r1
+// poles, solve program, Krylov basis of maxit block steps, subspace blocks);
+// a deep copy of a result; the seeded Gaussian start block zolo_solve draws.
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision);
+int64_t pencil_n(const zolo_pencil* P);
+zolo_result* result_clone(const zolo_result* r);
+void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
+
 }  // namespace zolo

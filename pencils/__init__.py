@@ -205,3 +205,29 @@ def serving_stream(n_queries: int, n_pencils: int, rate: float, seed: int = 3):
         {"t": float(t[i]), "pencil": int(pencil[i]), "n_lambda": int(nl[i]), "start_frac": float(frac[i])}
         for i in range(n_queries)
     ]
+
+
+def serving_queries(clusters: dict, n_queries: int, rate: float, seed: int = 3, max_lambda: int = 128):
+    """Queries of the serving workload drawn from stored eigenvalue clusters.
+
+    ``clusters`` is the fixture written by the window generator (per grid and
+    center sigma0, the consecutive eigenvalues nearest sigma0).  Arrival times,
+    pencils and n_lambda (log-uniform in [8, max_lambda]) follow
+    ``serving_stream``; the start fraction picks the cluster (center) of that
+    pencil, and the window is the run of n_lambda eigenvalues in the middle of
+    the cluster, with its neighbours as eigengaps.
+    """
+    grids = clusters["grids"]
+    centers = clusters["centers"]
+    k = clusters["k"]
+    out = []
+    for q in serving_stream(n_queries, len(grids), rate, seed):
+        n = grids[q["pencil"]]
+        c = centers[min(int(q["start_frac"] * len(centers)), len(centers) - 1)]
+        lam = np.asarray(clusters["clusters"][f"{n}:{c}"], dtype=np.float64)
+        nl = int(min(q["n_lambda"], max_lambda, k - 2))
+        start = (k - nl) // 2
+        w = window_from_eigenvalues(lam, start, nl)
+        w["eigenvalues"] = [float(x) for x in lam[start : start + nl]]
+        out.append({"t": q["t"], "grid": n, "center": c, "window": w})
+    return out

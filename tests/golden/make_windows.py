@@ -6,6 +6,7 @@ from the repository root:
     python tests/golden/make_windows.py c0          # 10^3 grid, dense LAPACK
     python tests/golden/make_windows.py c1          # 64^3 grid, shift-invert Lanczos
     python tests/golden/make_windows.py small       # the small parity pencils
+    python tests/golden/make_windows.py serving     # eigenvalue clusters of the serving pencils
 
 Each fixture stores the workload recipe (grid, seeds), the window of
 eigenvalues (ascending, the oracle's values) and the eigengaps
@@ -87,6 +88,30 @@ def c1_window(n=64, n_lambda=64, sigma0=6.0, k=80, verify=True):
     _dump(f"window_grid7_{n}.json", w)
 
 
+SERVING_GRIDS = [16, 20, 24, 28, 32]
+SERVING_CENTERS = [4.0, 5.5, 7.0, 8.5]
+SERVING_K = 150
+
+
+def serving_clusters():
+    """Per serving pencil (grid7 n^3, potential seed 0) and per center sigma0,
+    the SERVING_K eigenvalues nearest sigma0 (consecutive in the spectrum):
+    every run of n_lambda of them with a neighbour on each side is a query
+    window with known eigengaps."""
+    out = {"grids": SERVING_GRIDS, "centers": SERVING_CENTERS, "k": SERVING_K, "seed_v": 0, "clusters": {},
+           "source": "oracle.sparse.window_near (shift-invert Lanczos, ARPACK)"}
+    for n in SERVING_GRIDS:
+        p = pencils.grid7(n)
+        A, B = p.scipy()
+        A, B = A.tocsc(), B.tocsc()
+        for c in SERVING_CENTERS:
+            t = time.time()
+            lam, _ = window_near(A, B, c, SERVING_K)
+            out["clusters"][f"{n}:{c}"] = [float(x) for x in lam]
+            print(f"grid {n} center {c}: {time.time() - t:.1f}s", flush=True)
+    _dump("serving_clusters.json", out)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "c0"
     if what == "c0":
@@ -97,6 +122,8 @@ if __name__ == "__main__":
         dense_window(12, 16)
     elif what == "c1":
         c1_window()
+    elif what == "serving":
+        serving_clusters()
     elif what.startswith("grid"):
         n = int(what[4:])
         c1_window(n=n, verify=True)

@@ -1,0 +1,192 @@
+"""Serving loop (zolo_server_*, zolo_submit, zolo_wait) on the GPU.
+
+* Alone vs in the mix: queries on several resident pencils run one by one
+  through zolo_solve and then together through a server with several slots;
+  each query's eigenvalues match its solo run to 1e-12 relative and the
+  oracle's stored values to 1e-10, its eigenvector block spans the same
+  space (B-inner products of the two bases: singular values within 1e-8 of 1).
+* Batching: queries that share a filter and wait in the queue behind another
+  query run as one joint Algorithm 1; each gets the full set of eigenpairs.
+* Admission: a budget below one query's estimate fails it with ZOLO_ENOMEM;
+  a budget for one query at a time serializes queries.
+* zolo_wait with a zero timeout on a queued query returns ZOLO_ETIMEOUT.
+"""
+import json
+import sys
+
+import numpy as np
+import pytest
+
+import pencils
+
+from .conftest import golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+zolo = pytest.importorskip("paper_1701_08935_amd")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return zolo.Context(0)
+
+
+@pytest.fixture(scope="module")
+def clusters():
+    return json.load(open(golden("serving_clusters.json")))
+
+
+@pytest.fixture(scope="module")
+def resident(ctx):
+    out = {}
+    for n in (16, 20, 24):
+        gp = pencils.grid7(n)
+        out[n] = (gp, zolo.Pencil.from_grid(ctx, gp, leaf_size=32))
+    return out
+
+
+def _opts(w, n_ss, seed):
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=n_ss)
+    o.seed = seed
+    return o
+
+
+def _nss(nl):
+    return int(np.ceil(1.5 * nl)) + 4
+
+
+def _span_check(B, X1, X2):
+    s = np.linalg.svd(X1.T @ (B @ X2), compute_uv=False)
+    return float(np.max(np.abs(s - 1.0)))
+
+
+def test_alone_vs_mix(ctx, clusters, resident):
+    qs = [q for q in pencils.serving_queries(clusters, 24, rate=50.0, seed=5, max_lambda=48) if q["grid"] in resident][:8]
+    assert len(qs) >= 5
+    solo = []
+    for i, q in enumerate(qs):
+        gp, P = resident[q["grid"]]
+        w = q["window"]
+        say(f"solo query {i}: grid {q['grid']} center {q['center']} n_lambda {w['n_lambda']}")
+        eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], w["n_lambda"], _opts(w, _nss(w["n_lambda"]), 100 + i))
+        assert rc == 0
+        solo.append((np.array(eig), vec.cpu().numpy()))
+    say("same queries through a server with 3 slots")
+    srv = zolo.Server(ctx, slots=3)
+    handles = []
+    for i, q in enumerate(qs):
+        gp, P = resident[q["grid"]]
+        w = q["window"]
+        handles.append(srv.submit(P, w["a"], w["b"], w["n_lambda"], _opts(w, _nss(w["n_lambda"]), 100 + i)))
+    overlap = 0
+    infos = []
+    for i, (q, h) in enumerate(zip(qs, handles)):
+        eig, vec, st, rc, info = h.wait()
+        infos.append(info)
+        gp, P = resident[q["grid"]]
+        A, B = gp.scipy()
+        w = q["window"]
+        say(f"  query {i}: rc={rc} found={len(eig)} batch={info['batch']} latency={info['t_end'] - info['t_submit']:.3f}s")
+        assert rc == 0 and len(eig) == w["n_lambda"]
+        eig = np.array(eig)
+        ref = np.array(w["eigenvalues"])
+        assert np.max(np.abs(eig - ref) / np.abs(ref)) <= 1e-10
+        e0, x0 = solo[i]
+        assert np.max(np.abs(eig - e0) / np.abs(e0)) <= 1e-12
+        assert _span_check(B, x0, vec.cpu().numpy()) <= 1e-8
+        h.free()
+    for i in range(len(infos)):
+        for j in range(i + 1, len(infos)):
+            a, b = infos[i], infos[j]
+            if a["t_start"] < b["t_end"] and b["t_start"] < a["t_end"]:
+                overlap += 1
+    say(f"  overlapping query pairs: {overlap}")
+    assert overlap > 0
+    srv.close()
+
+
+def test_same_filter_batched(ctx, clusters, resident):
+    gp16, P16 = resident[16]
+    gp24, P24 = resident[24]
+    A, B = gp16.scipy()
+    lam = np.asarray(clusters["clusters"]["16:5.5"])
+    w = pencils.window_from_eigenvalues(lam, 60, 12)
+    wb = pencils.window_from_eigenvalues(np.asarray(clusters["clusters"]["24:7.0"]), 40, 48)
+    say("batching: one blocker query, then three queries with the same filter, one slot")
+    srv = zolo.Server(ctx, slots=1)
+    hb = srv.submit(P24, wb["a"], wb["b"], 48, _opts(wb, 76, 1))
+    hs = [srv.submit(P16, w["a"], w["b"], 12, _opts(w, 20, 200 + i)) for i in range(3)]
+    eb, _, _, rcb, infob = hb.wait()
+    assert rcb == 0 and len(eb) == 48
+    ref = lam[60:72]
+    for i, h in enumerate(hs):
+        eig, vec, st, rc, info = h.wait()
+        say(f"  query {i}: rc={rc} found={len(eig)} batch={info['batch']}")
+        assert rc == 0 and info["batch"] == 3 and len(eig) == 12
+        assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) <= 1e-10
+        X = vec.cpu().numpy()
+        assert np.max(np.abs(X.T @ (B @ X) - np.eye(12))) <= 1e-10
+        h.free()
+    hb.free()
+    srv.close()
+
+
+def test_admission_budget(ctx, clusters, resident):
+    gp, P = resident[20]
+    lam = np.asarray(clusters["clusters"]["20:7.0"])
+    w1 = pencils.window_from_eigenvalues(lam, 30, 16)
+    w2 = pencils.window_from_eigenvalues(lam, 80, 16)
+    say("admission: budget of 1 MiB fails the query with ZOLO_ENOMEM")
+    srv = zolo.Server(ctx, slots=2, budget_bytes=1 << 20)
+    h = srv.submit(P, w1["a"], w1["b"], 16, _opts(w1, 28, 1))
+    with pytest.raises(zolo.ZoloError) as e:
+        h.wait()
+    assert e.value.status == zolo.ZOLO_ENOMEM
+    h.free()
+    srv.close()
+    say("admission: a budget for one query at a time serializes two queries on two slots")
+    probe = zolo.Server(ctx, slots=1)
+    hp = probe.submit(P, w1["a"], w1["b"], 16, _opts(w1, 28, 1))
+    hp.wait()
+    est = hp.info()["est_bytes"]
+    hp.free()
+    probe.close()
+    srv = zolo.Server(ctx, slots=2, budget_bytes=int(est * 1.5))
+    h1 = srv.submit(P, w1["a"], w1["b"], 16, _opts(w1, 28, 1))
+    h2 = srv.submit(P, w2["a"], w2["b"], 16, _opts(w2, 28, 2))
+    _, _, _, rc1, i1 = h1.wait()
+    _, _, _, rc2, i2 = h2.wait()
+    say(f"  est {est} B; first {i1['t_start']:.3f}-{i1['t_end']:.3f}, second {i2['t_start']:.3f}-{i2['t_end']:.3f}")
+    assert rc1 == 0 and rc2 == 0
+    assert i2["t_start"] >= i1["t_end"] or i1["t_start"] >= i2["t_end"]
+    h1.free()
+    h2.free()
+    srv.close()
+
+
+def test_wait_timeout(ctx, clusters, resident):
+    gp, P = resident[24]
+    lam = np.asarray(clusters["clusters"]["24:5.5"])
+    wb = pencils.window_from_eigenvalues(lam, 40, 64)
+    w = pencils.window_from_eigenvalues(lam, 10, 8)
+    say("zolo_wait timeout on a query queued behind another, one slot")
+    srv = zolo.Server(ctx, slots=1)
+    hb = srv.submit(P, wb["a"], wb["b"], 64, _opts(wb, 100, 1))
+    h = srv.submit(P, w["a"], w["b"], 8, _opts(w, 16, 2))
+    with pytest.raises(zolo.ZoloError) as e:
+        h.wait(timeout_ms=0)
+    assert e.value.status == zolo.ZOLO_ETIMEOUT
+    eig, _, _, rc, _ = h.wait()
+    assert rc == 0 and len(eig) == 8
+    hb.wait()
+    h.free()
+    hb.free()
+    srv.close()

@@ -173,3 +173,26 @@ def test_rr_rank_revealing_and_metrics():
     r = rel_residuals(As, Bs, lam[:4], X[:, :4], inf_norm(As), inf_norm(Bs))
     assert np.max(r) < 1e-13
     assert inf_norm(As) >= np.linalg.norm(A, 2) - 1e-12
+
+
+def test_serving_queries_windows_are_consistent():
+    """The serving query generator (input construction only) yields windows whose
+    eigengaps are the neighbours of a consecutive run of stored eigenvalues."""
+    import json
+
+    import pencils
+
+    from .conftest import golden
+
+    c = json.load(open(golden("serving_clusters.json")))
+    qs = pencils.serving_queries(c, 64, rate=10.0, seed=3)
+    assert len(qs) == 64 and all(qs[i]["t"] <= qs[i + 1]["t"] for i in range(63))
+    for q in qs:
+        w = q["window"]
+        lam = np.asarray(c["clusters"][f"{q['grid']}:{q['center']}"])
+        ev = np.asarray(w["eigenvalues"])
+        assert 8 <= w["n_lambda"] == len(ev) <= 128
+        assert w["a_minus"] < w["a"] < w["a_plus"] == ev[0] <= ev[-1] == w["b_minus"] < w["b"] < w["b_plus"]
+        i = int(np.searchsorted(lam, ev[0]))
+        assert np.array_equal(lam[i : i + len(ev)], ev)
+        assert lam[i - 1] == w["a_minus"] and lam[i + len(ev)] == w["b_plus"]
