@@ -126,6 +126,63 @@ def measured_traffic(kernel):
     return float(kv[key]) if key in kv else None
 
 
+def run_serving(n_queries=48, rate=6.0, slots=4, seed=3, precision=0):
+    """Serving workload: Poisson arrivals of interval queries on resident grid7
+    pencils (16^3 ... 32^3), windows of n_lambda in [8, 128] from the stored
+    eigenvalue clusters; replayed in real time against a zolo server."""
+    import numpy as np
+
+    import paper_1701_08935_amd as z
+    import pencils
+
+    clusters = json.load(open(os.path.join(ROOT, "tests", "golden", "serving_clusters.json")))
+    ctx = z.Context(0)
+    resident = {}
+    for n in clusters["grids"]:
+        gp = pencils.grid7(n)
+        resident[n] = (gp, z.Pencil.from_grid(ctx, gp, leaf_size=32))
+    qs = pencils.serving_queries(clusters, n_queries, rate, seed)
+    srv = z.Server(ctx, slots=slots)
+    handles = []
+    t0 = time.perf_counter()
+    for q in qs:
+        dt = q["t"] - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        w = q["window"]
+        o = z.opts_from_window(w, r1=2, r2=0, n_ss=int(math.ceil(1.5 * w["n_lambda"])) + 4, precision=precision)
+        o.seed = 1000 + len(handles)
+        handles.append(srv.submit(resident[q["grid"]][1], w["a"], w["b"], w["n_lambda"], o))
+    lat, verified, batches, bad = [], 0, [], 0
+    t_last = 0.0
+    for q, h in zip(qs, handles):
+        try:
+            eig, vec, st, rc, info = h.wait()
+        except z.ZoloError as e:
+            log(f"[serving] query failed: {e}")
+            bad += 1
+            h.free()
+            continue
+        w = q["window"]
+        ref = np.array(w["eigenvalues"])
+        ok = rc == 0 and len(eig) == len(ref) and st["max_resid"] <= 1e-8 and \
+            float(np.max(np.abs(np.array(eig) - ref) / np.abs(ref))) <= 1e-10
+        verified += len(eig) if ok else 0
+        bad += 0 if ok else 1
+        lat.append(info["t_end"] - info["t_submit"])
+        batches.append(info["batch"])
+        t_last = max(t_last, info["t_end"])
+        t_first = info["t_submit"] if len(lat) == 1 else min(t_first, info["t_submit"])
+        h.free()
+    srv.close()
+    wall = t_last - t_first if lat else float("nan")
+    return {"queries": n_queries, "rate_qps": rate, "slots": slots, "precision": "fp64" if precision == 0 else "mixed",
+            "pencils": f"grid7 {clusters['grids'][0]}^3 .. {clusters['grids'][-1]}^3 ({len(clusters['grids'])} resident)",
+            "eigenpairs_per_s": verified / wall if wall > 0 else None, "queries_per_s": len(lat) / wall if wall > 0 else None,
+            "latency_s": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)}, "failed_or_unverified": bad,
+            "mean_batch": float(np.mean(batches)) if batches else None, "wall_s": wall}
+
+
 def roofline(prof, steps, fp32=False):
     if not prof:
         return None
@@ -204,6 +261,9 @@ def main():
     ap.add_argument("--r1", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serving-queries", type=int, default=48)
+    ap.add_argument("--serving-rate", type=float, default=6.0, help="Poisson arrival rate, queries/s")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -266,6 +326,8 @@ def main():
         out["mixed"] = {"value": mval, "ms_per_step": mms, "speedup_vs_fp64": mval / value if value else None,
                         "eig_rel_err": mres["eig_err"], "max_resid": mres["stats"]["max_resid"],
                         "n_refine": mres["stats"]["n_refine"], "t_factor_s": mres["stats"]["t_factor"]}
+    if not args.no_serving:
+        out["serving"] = run_serving(args.serving_queries, args.serving_rate)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
