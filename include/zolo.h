@@ -172,27 +172,33 @@ zolo_status zolo_filter_plan(double a_minus, double a_plus, double b_minus, doub
 
 /*
  * Numeric factorization of K_j = A - sigma_hat_j B, j = 1..r1 (Algorithm 2,
- * lines 5-6), as complex-symmetric LDL^T on the device (real pencils).
- * precision ZOLO_PREC_MIXED stores complex64 factors.
+ * lines 5-6), without pivoting in the nested-dissection order: complex-
+ * symmetric LDL^T for real pencils, LU = L D U for complex Hermitian pencils
+ * (whose conjugate poles are solved with K_j^-H).  Poles are factored
+ * concurrently on streams of their own and joined to `stream`.
+ * precision ZOLO_PREC_MIXED stores complex64 factors (real pencils only).
  * Errors: ZOLO_EBREAKDOWN (zero pivot), ZOLO_ENOMEM, ZOLO_EDEVICE.
  */
 zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* p, const zolo_filter_coeffs* co, int precision,
                         void* stream, zolo_factors** out);
 void zolo_factors_free(zolo_factors* f);
 
-/* d_Y = A d_X or B d_X (which = 0 for A, 1 for B); real pencils: double,
- * N x p row-major blocks in the ORIGINAL ordering. */
+/* d_Y = A d_X or B d_X (which = 0 for A, 1 for B); N x p row-major blocks in
+ * the ORIGINAL ordering, double for real pencils, complex128 for complex ones. */
 zolo_status zolo_spmm(zolo_pencil* p, int which, const void* d_X, int64_t ldx, int ncols, void* d_Y, int64_t ldy,
                       void* stream);
 
-/* d_X (complex128, N x p) = K_j^-1 d_T for pole j (0-based), d_T real N x p
- * (real pencils).  Original ordering.  In mixed precision the FP32 factor is
- * refined against FP64 residuals until tol_refine (opts of the factors). */
+/* d_X (complex128, N x p) = K_j^-1 d_T for pole j (0-based) (eq. solve).
+ * Real pencils: j < r1, d_T real.  Complex Hermitian pencils: d_T complex128,
+ * j < r1 gives K_j^-1 and r1 <= j < 2 r1 gives K_{j-r1}^-H
+ * = (A - conj(sigma_hat) B)^-1.  Original ordering.  In mixed precision the
+ * FP32 factor is refined against FP64 residuals until tol_refine. */
 zolo_status zolo_pole_solve(zolo_factors* f, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
                             int64_t ldx, void* stream);
 
 /* d_W = G d_V with G = Zhat(T(B^-1 A); l1) applied through the factors
- * (eq. solve).  Real pencils, original ordering. */
+ * (eq. solve, Proposition 2).  Blocks of the pencil's scalar type (double or
+ * complex128), original ordering. */
 zolo_status zolo_apply_G(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_W, int64_t ldw,
                          void* stream);
 
@@ -205,10 +211,13 @@ typedef struct {
 
 /*
  * d_Y = R_ab(B^-1 A) d_V (Algorithm 2, lines 8-9): multi-shift block GMRES
- * on G with the outer shifts +- i sqrt(c_j), then Y = V/2 + (M/2) sum_j
- * a_j Re((G + i sqrt c_j)^-1 V).  Real pencils.  tol_gmres <= 0 and
- * max_iter <= 0 take the defaults.  Returns ZOLO_ENOCONV (with d_Y filled
- * by the best iterate) if max_iter steps do not reach tol_gmres.
+ * on G with the outer shifts +- i sqrt(c_j) (eq. solve2, Corollary 1), then
+ * Y = V/2 + sum_j (M a_j / 4) [(G + i sqrt c_j)^-1 + (G - i sqrt c_j)^-1] V.
+ * Real pencils solve only the + shifts (the - solutions are their
+ * conjugates); complex Hermitian pencils solve both.  Blocks of the pencil's
+ * scalar type.  tol_gmres <= 0 and max_iter <= 0 take the defaults.  Returns
+ * ZOLO_ENOCONV (with d_Y filled by the best iterate) if max_iter steps do
+ * not reach tol_gmres.
  */
 zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_Y,
                               int64_t ldy, double tol_gmres, int max_iter, zolo_filter_stats* st, void* stream);
@@ -217,8 +226,12 @@ zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, i
  * Eigenpairs of (A, B) in (a, b) (Algorithm 1 with Algorithm 2).
  * n_lambda_est: estimated count (footnote of Sec. 1); opts may be NULL.
  * d_Q0 (may be NULL): N x n_ss start block (row-major, ld n_ss) in the
- * original ordering; NULL draws a Gaussian block from opts->seed.
- * The result holds Ritz pairs with a < theta < b and residual <= tol_resid.
+ * original ordering, of the pencil's scalar type (double or complex128);
+ * NULL draws a Gaussian block from opts->seed.  Complex Hermitian pencils
+ * run with FP64 factors only (ZOLO_EINVAL for ZOLO_PREC_MIXED).
+ * The result holds Ritz pairs with a < theta < b and residual <= tol_resid;
+ * its vectors are complex128 for complex pencils.  An interval with no
+ * eigenvalue returns count 0 once two filtered iterations select none.
  * Errors: ZOLO_ENOCONV (best results and stats still filled),
  * ZOLO_ESUBSPACE (found >= n_ss - 1), ZOLO_EINVAL.
  */

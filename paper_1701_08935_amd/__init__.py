@@ -211,14 +211,16 @@ class Pencil:
         self.ctx = ctx
         self._rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
         self._colind = np.ascontiguousarray(colind, dtype=np.int32)
-        self._a = np.ascontiguousarray(a_vals, dtype=np.float64)
-        self._b = np.ascontiguousarray(b_vals, dtype=np.float64)
+        self.cplx = np.iscomplexobj(a_vals) or np.iscomplexobj(b_vals)
+        vt = np.complex128 if self.cplx else np.float64
+        self._a = np.ascontiguousarray(a_vals, dtype=vt)
+        self._b = np.ascontiguousarray(b_vals, dtype=vt)
         self.n = self._rowptr.shape[0] - 1
         g = None if grid is None else np.ascontiguousarray(grid, dtype=np.int32)
         h = _vp()
         _check(lib().zolo_pencil_create(ctx.h, self.n, _np_ptr(self._rowptr), _np_ptr(self._colind), _np_ptr(self._a),
-                                        _np_ptr(self._b), ZOLO_REAL64, None if g is None else _np_ptr(g),
-                                        int(leaf_size), ctypes.byref(h)))
+                                        _np_ptr(self._b), ZOLO_COMPLEX128 if self.cplx else ZOLO_REAL64,
+                                        None if g is None else _np_ptr(g), int(leaf_size), ctypes.byref(h)))
         self.h = h
 
     @classmethod
@@ -306,7 +308,8 @@ def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts
         cnt = L.zolo_result_count(h)
         ev = L.zolo_result_eigenvalues(h)
         eig = [ev[i] for i in range(cnt)]
-        vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.float64, device=f"cuda:{ctx.device}")
+        vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.complex128 if pencil.cplx else torch.float64,
+                          device=f"cuda:{ctx.device}")
         if cnt:
             _check(L.zolo_result_copy_vectors(h, _ptr(vec), vec.stride(0), _stream()))
         st = zolo_stats()
@@ -369,7 +372,8 @@ class Query:
             cnt = L.zolo_result_count(r)
             ev = L.zolo_result_eigenvalues(r)
             eig = [ev[i] for i in range(cnt)]
-            vec = torch.empty((self.pencil.n, max(cnt, 1)), dtype=torch.float64, device=f"cuda:{self.server.ctx.device}")
+            vec = torch.empty((self.pencil.n, max(cnt, 1)), dtype=torch.complex128 if self.pencil.cplx else torch.float64,
+                              device=f"cuda:{self.server.ctx.device}")
             if cnt:
                 _check(L.zolo_result_copy_vectors(r, _ptr(vec), vec.stride(0), _stream()))
             st = zolo_stats()

@@ -202,8 +202,10 @@ struct zolo_pencil {
   DevArena mem;
   int64_t* prow = nullptr;
   int32_t* pcol = nullptr;
-  double* pa = nullptr;
+  double* pa = nullptr;  // real pencils: permuted CSR values
   double* pb = nullptr;
+  zd* za = nullptr;      // complex Hermitian pencils: permuted CSR values
+  zd* zb = nullptr;
   int32_t* perm = nullptr;   // perm[new] = old
   int32_t* iperm = nullptr;  // iperm[old] = new
   int32_t* struct_rows = nullptr;
@@ -217,6 +219,7 @@ struct zolo_pencil {
   int64_t panel_total = 0, inv_total = 0, upd_total = 0;
   int64_t* asm_dst = nullptr;
   int64_t* asm_src = nullptr;
+  int64_t* asm_src_t = nullptr;  // complex pencils: the CSR entry transposed to asm_src's
   std::vector<int64_t> lvl_asm_begin, lvl_asm_end;
   ExtDesc* ext = nullptr;
   std::vector<std::vector<GemmLaunch>> lvl_ext;  // per level per slot: off/cnt/max_nb (tiles)
@@ -224,13 +227,21 @@ struct zolo_pencil {
   std::vector<int> lvl_diag_off, lvl_diag_cnt;
   std::vector<std::vector<int>> lvl_diag_nJ, lvl_trsm_rows;  // per level per step
   int64_t inv_scratch = 0;  // FB x ns per front of a level (L11 inverse temporaries)
+  bool cplx() const { return scalar == ZOLO_COMPLEX128; }
 };
 
+// One factored pole.  Real pencils: complex-symmetric LDL^T (panel = L,
+// inv = L11^-1 blocks).  Complex Hermitian pencils: LU = L D U with the U
+// factor stored transposed (upanel = U^T, uinv = (U11^T)^-1 blocks) and
+// dconj = conj(D) for the solves with K^-H.
 template <typename T>
 struct PoleMF {
   T* panel = nullptr;
   T* inv = nullptr;
   T* dvec = nullptr;
+  T* upanel = nullptr;
+  T* uinv = nullptr;
+  T* dconj = nullptr;
 };
 
 template <typename T>
@@ -254,9 +265,12 @@ struct SolveProg {
   std::vector<GemmLaunch> f2, f3, b2, b3;        // [level]
 };
 
+// Krylov-side buffers.  Blocks hold real values for real pencils and complex
+// values for complex Hermitian pencils (ef = 2 doubles per entry); they are
+// typed double* and read through the block scalar type where used.
 struct Workspace {
   DevArena mem;
-  int p = 0, mmax = 0, nshift = 0;
+  int p = 0, mmax = 0, nshift = 0, ef = 1;
   int64_t n = 0;
   double* Vb = nullptr;   // N x Mp
   double* W = nullptr;    // N x p
@@ -284,7 +298,7 @@ struct Workspace {
   double* Cm = nullptr;   // mmax p x p
   zd* Ys = nullptr;       // nshift x (mmax p) x p
   HlsState hls{};
-  GemmDesc<double>* gdesc = nullptr;
+  void* gdesc = nullptr;  // room for gdesc_cap + 4 descriptors of either scalar type
   int gdesc_cap = 0;
   double* cn_partial = nullptr;
   double* cn_out = nullptr;
@@ -310,6 +324,7 @@ struct zolo_factors {
 
 struct zolo_result {
   int64_t n = 0, count = 0;
+  int ef = 1;  // doubles per vector entry: 1 real, 2 complex (interleaved)
   std::vector<double> eig;
   DevArena mem;
   double* vec = nullptr;  // N x count row-major, original ordering
@@ -378,9 +393,10 @@ void patch_split(std::vector<GemmDesc<T>>& gd, const SplitPlan& sp, typename ST<
   }
 }
 
-// out (m x n, col-major ld ldo) [+]= X^T Y with X: N x m row-major (ld ldx), Y: N x n row-major (ld ldy)
-int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_t ldy, int64_t N, int m, int n,
-            double* out, int64_t ldo, bool add, hipStream_t s) {
+// out (m x n, col-major ld ldo) [+]= X^H Y with X: N x m row-major (ld ldx), Y: N x n row-major (ld ldy)
+template <typename VT>
+int gemm_tn(Workspace& ws, const VT* X, int64_t ldx, const VT* Y, int64_t ldy, int64_t N, int m, int n, VT* out,
+            int64_t ldo, bool add, hipStream_t s) {
   int tiles = gemm_tiles(m, n);
   int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
   while (S * (int64_t)m * n > ws.partial_len && S > 1) S /= 2;
@@ -390,35 +406,37 @@ int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_
   }
   if (S > ws.gdesc_cap) S = ws.gdesc_cap;
   int64_t chunk = (N + S - 1) / S;
-  std::vector<GemmDesc<double>> h;
+  VT* partial = (VT*)ws.partial;
+  std::vector<GemmDesc<VT>> h;
   for (int64_t q = 0; q < S; ++q) {
     int64_t r0 = q * chunk;
     if (r0 >= N) break;
-    GemmDesc<double> d{};
+    GemmDesc<VT> d{};
     d.A = X + r0 * ldx;
     d.lda = ldx;
     d.B = Y + r0 * ldy;
     d.ldb = ldy;
-    d.C = ws.partial + (int64_t)h.size() * m * n;
+    d.C = partial + (int64_t)h.size() * m * n;
     d.ldc = m;
     d.M = m;
     d.N = n;
     d.K = (int)std::min<int64_t>(chunk, N - r0);
-    d.flags = GF_TRANSB;
-    d.alpha = 1.0;
-    d.beta = 0.0;
+    d.flags = GF_TRANSB | (ST<VT>::cplx ? GF_CONJA : 0);
+    d.alpha = ST<VT>::one();
+    d.beta = ST<VT>::zero();
     h.push_back(d);
   }
-  HIPC(hipMemcpyAsync(ws.gdesc, h.data(), h.size() * sizeof(GemmDesc<double>), hipMemcpyHostToDevice, s));
+  GemmDesc<VT>* dg = (GemmDesc<VT>*)ws.gdesc;
+  HIPC(hipMemcpyAsync(dg, h.data(), h.size() * sizeof(GemmDesc<VT>), hipMemcpyHostToDevice, s));
   {
     double fl = 0.0, by = 0.0;
     for (auto& d : h) gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<double>(ws.gdesc, (int)h.size(), m, n, s, 2);
+    gemm_batched<VT>(dg, (int)h.size(), m, n, s, 2);
   }
   {
-    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 8.0 * (double)m * n * (h.size() + 1), s);
-    reduce_partials(out, ldo, ws.partial, (int)h.size(), m, n, add, s);
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, (double)sizeof(VT) * m * n * (h.size() + 1), s);
+    reduce_partials<VT>(out, ldo, partial, (int)h.size(), m, n, add, s);
   }
   HIPC(hipStreamSynchronize(s));  // h is host memory
   return ZOLO_OK;
@@ -426,16 +444,17 @@ int gemm_tn(Workspace& ws, const double* X, int64_t ldx, const double* Y, int64_
 
 // C^T (p x N col-major view of row-major C, ld ldc) = beta C^T + alpha opA(Msmall) Bv^T
 // Used for W -= V h and V_new = W R^-1 style updates: C_rm = beta C_rm + alpha Bv_rm opA^T
-int gemm_nt_big(Workspace& ws, double* C, int64_t ldc, const double* Cin, int64_t ldcin, double beta, double alpha,
-                const double* Msmall, int64_t ldm, bool transM, const double* Bv, int64_t ldb, int64_t N, int p, int K,
+template <typename VT>
+int gemm_nt_big(Workspace& ws, VT* C, int64_t ldc, const VT* Cin, int64_t ldcin, double beta, double alpha,
+                const VT* Msmall, int64_t ldm, bool transM, const VT* Bv, int64_t ldb, int64_t N, int p, int K,
                 hipStream_t s) {
-  GemmDesc<double> d{};
+  GemmDesc<VT> d{};
   d.C = C;
   d.ldc = ldc;
   d.Cin = Cin;
   d.ldcin = ldcin;
-  d.beta = beta;
-  d.alpha = alpha;
+  d.beta = cvt<VT, double>(beta);
+  d.alpha = cvt<VT, double>(alpha);
   d.A = Msmall;
   d.lda = ldm;
   d.flags = transM ? GF_TRANSA : 0;
@@ -444,12 +463,13 @@ int gemm_nt_big(Workspace& ws, double* C, int64_t ldc, const double* Cin, int64_
   d.M = p;
   d.N = (int)N;
   d.K = K;
-  HIPC(hipMemcpyAsync(ws.gdesc + ws.gdesc_cap, &d, sizeof(d), hipMemcpyHostToDevice, s));
+  GemmDesc<VT>* dg = (GemmDesc<VT>*)ws.gdesc + ws.gdesc_cap;
+  HIPC(hipMemcpyAsync(dg, &d, sizeof(d), hipMemcpyHostToDevice, s));
   {
     double fl = 0.0, by = 0.0;
     gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<double>(ws.gdesc + ws.gdesc_cap, 1, p, (int)N, s, 2);
+    gemm_batched<VT>(dg, 1, p, (int)N, s, 2);
   }
   HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
@@ -563,6 +583,20 @@ static zolo_status build_layout(zolo_pencil* P) {
   }
   CHK(P->mem.upload(&P->asm_dst, dst.data(), dst.size()));
   CHK(P->mem.upload(&P->asm_src, src.data(), src.size()));
+  if (P->cplx()) {
+    // LU fronts need both triangles: the CSR entry transposed to each
+    // assembly entry (the permuted CSR has sorted columns)
+    std::vector<int64_t> srct(src.size());
+    for (size_t q = 0; q < src.size(); ++q) {
+      const int64_t e = src[q];
+      const int32_t j = S.pcol[e];
+      const int64_t i = std::upper_bound(S.prow.begin(), S.prow.end(), e) - S.prow.begin() - 1;
+      const int32_t* lo = S.pcol.data() + S.prow[j];
+      const int32_t* hi = S.pcol.data() + S.prow[j + 1];
+      srct[q] = std::lower_bound(lo, hi, (int32_t)i) - S.pcol.data();
+    }
+    CHK(P->mem.upload(&P->asm_src_t, srct.data(), srct.size()));
+  }
   // extend-add descriptors: per parent level, per child slot
   std::vector<ExtDesc> ext;
   P->lvl_ext.assign(nl, {});
@@ -643,8 +677,8 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
     set_error("zolo_pencil_create: null argument or n <= 0");
     return ZOLO_EINVAL;
   }
-  if (scalar != ZOLO_REAL64) {
-    set_error("zolo_pencil_create: only real (ZOLO_REAL64) pencils are supported by this build");
+  if (scalar != ZOLO_REAL64 && scalar != ZOLO_COMPLEX128) {
+    set_error("zolo_pencil_create: unknown scalar type %d", scalar);
     return ZOLO_EINVAL;
   }
   if (n > INT32_MAX) {
@@ -656,9 +690,13 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
     set_error("CSR: rowptr[0] must be 0 and the diagonal stored");
     return ZOLO_EINVAL;
   }
-  const double* a = (const double*)a_vals;
-  const double* b = (const double*)b_vals;
-  // validate: sorted columns in range, diagonal present, symmetric pattern and values
+  const bool cx = scalar == ZOLO_COMPLEX128;
+  // value e of A or B as (re, im)
+  const double* av = (const double*)a_vals;
+  const double* bv = (const double*)b_vals;
+  auto aval = [&](int64_t e) { return cx ? zd{av[2 * e], av[2 * e + 1]} : zd{av[e], 0.0}; };
+  auto bval = [&](int64_t e) { return cx ? zd{bv[2 * e], bv[2 * e + 1]} : zd{bv[e], 0.0}; };
+  // validate: sorted columns in range, diagonal present, symmetric pattern, Hermitian values
   for (int64_t i = 0; i < n; ++i) {
     if (rowptr[i + 1] < rowptr[i]) {
       set_error("CSR: rowptr not monotone at row %lld", (long long)i);
@@ -683,8 +721,9 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
     double ra = 0.0, rb = 0.0;
     for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
       int32_t j = colind[e];
-      ra += std::fabs(a[e]);
-      rb += std::fabs(b[e]);
+      const zd ae = aval(e), be = bval(e);
+      ra += std::sqrt(abs2(ae));
+      rb += std::sqrt(abs2(be));
       const int32_t* lo = colind + rowptr[j];
       const int32_t* hi = colind + rowptr[j + 1];
       const int32_t* it = std::lower_bound(lo, hi, (int32_t)i);
@@ -692,10 +731,12 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
         set_error("CSR: pattern not symmetric at (%lld, %d)", (long long)i, (int)j);
         return ZOLO_ENOTHERM;
       }
-      int64_t et = it - colind;
-      double sa = std::max(1.0, std::fabs(a[e])), sb = std::max(1.0, std::fabs(b[e]));
-      if (std::fabs(a[et] - a[e]) > 1e-14 * sa || std::fabs(b[et] - b[e]) > 1e-14 * sb) {
-        set_error("A or B not symmetric at (%lld, %d)", (long long)i, (int)j);
+      const int64_t et = it - colind;
+      const zd at = aval(et), bt = bval(et);
+      const double sa = std::max(1.0, std::sqrt(abs2(ae))), sb = std::max(1.0, std::sqrt(abs2(be)));
+      if (std::fabs(at.re - ae.re) > 1e-14 * sa || std::fabs(at.im + ae.im) > 1e-14 * sa ||
+          std::fabs(bt.re - be.re) > 1e-14 * sb || std::fabs(bt.im + be.im) > 1e-14 * sb) {
+        set_error("A or B not Hermitian at (%lld, %d)", (long long)i, (int)j);
         return ZOLO_ENOTHERM;
       }
     }
@@ -714,15 +755,25 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
   CHK(symbolic_analyze(n, rowptr, colind, grid, leaf_size, &P->S));
   P->t_symbolic = now_s() - t0;
   const Symbolic& S = P->S;
-  std::vector<double> pa(nnz), pb(nnz);
-  for (int64_t e = 0; e < nnz; ++e) {
-    pa[e] = a[S.psrc[e]];
-    pb[e] = b[S.psrc[e]];
-  }
   CHK(P->mem.upload(&P->prow, S.prow.data(), S.prow.size()));
   CHK(P->mem.upload(&P->pcol, S.pcol.data(), S.pcol.size()));
-  CHK(P->mem.upload(&P->pa, pa.data(), pa.size()));
-  CHK(P->mem.upload(&P->pb, pb.data(), pb.size()));
+  if (cx) {
+    std::vector<zd> pa(nnz), pb(nnz);
+    for (int64_t e = 0; e < nnz; ++e) {
+      pa[e] = aval(S.psrc[e]);
+      pb[e] = bval(S.psrc[e]);
+    }
+    CHK(P->mem.upload(&P->za, pa.data(), pa.size()));
+    CHK(P->mem.upload(&P->zb, pb.data(), pb.size()));
+  } else {
+    std::vector<double> pa(nnz), pb(nnz);
+    for (int64_t e = 0; e < nnz; ++e) {
+      pa[e] = av[S.psrc[e]];
+      pb[e] = bv[S.psrc[e]];
+    }
+    CHK(P->mem.upload(&P->pa, pa.data(), pa.size()));
+    CHK(P->mem.upload(&P->pb, pb.data(), pb.size()));
+  }
   CHK(P->mem.upload(&P->perm, S.perm.data(), S.perm.size()));
   CHK(P->mem.upload(&P->iperm, S.iperm.data(), S.iperm.size()));
   CHK(P->mem.upload(&P->struct_rows, S.struct_rows.data(), S.struct_rows.size()));
@@ -826,15 +877,22 @@ template <typename T>
 zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, PoleMF<T>* pole, FactorWork<T>* fw) {
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
+  const bool lu = P->cplx();
   CHK(F->mem.alloc(&pole->panel, P->panel_total));
   CHK(F->mem.alloc(&pole->inv, P->inv_total));
   CHK(F->mem.alloc(&pole->dvec, P->n));
   F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
+  if (lu) {
+    CHK(F->mem.alloc(&pole->upanel, P->panel_total));
+    CHK(F->mem.alloc(&pole->uinv, P->inv_total));
+    CHK(F->mem.alloc(&pole->dconj, P->n));
+    F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
+  }
   fw->sr = sr;
   fw->si = si;
   DevArena& tmp = fw->tmp;
   CHK(tmp.alloc(&fw->upd, P->upd_total));
-  CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch, 1)));
+  CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch * (lu ? 2 : 1), 1)));
   CHK(tmp.alloc(&fw->flag, 1));
   T* upd = fw->upd;
   T* scratch = fw->scratch;
@@ -857,27 +915,34 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         if (Fr.ns <= J + jb) continue;
         int64_t k = (int64_t)Fr.ns + Fr.nb;
         T* Pn = pole->panel + P->panel_off[f];
-        GemmDesc<T> d{};
-        int r0 = J + jb;
-        d.C = Pn + r0 + (int64_t)r0 * k;
-        d.Cin = d.C;
-        d.ldc = d.ldcin = k;
-        d.A = Pn + r0 + (int64_t)J * k;
-        d.lda = k;
-        d.B = Pn + r0 + (int64_t)J * k;
-        d.ldb = k;
-        d.dk = pole->dvec + Fr.first + J;
-        d.M = (int)(k - r0);
-        d.N = Fr.ns - r0;
-        d.K = jb;
-        d.flags = GF_TRANSB | GF_TRI;
-        d.tri_off = 0;
-        d.alpha = mone;
-        d.beta = one;
-        gd.push_back(d);
-        gemm_work(d, &g.flops, &g.bytes);
-        g.maxM = std::max(g.maxM, d.M);
-        g.maxN = std::max(g.maxN, d.N);
+        T* Un = lu ? pole->upanel + P->panel_off[f] : Pn;
+        const int r0 = J + jb;
+        // LDL^T: L(r0:, r0:) -= L(r0:, J) D L(r0:, J)^T; LU: the same for L with U^T
+        // on the right, and for U^T with L on the right
+        for (int side = 0; side < (lu ? 2 : 1); ++side) {
+          T* Cb = side == 0 ? Pn : Un;
+          T* Bb = side == 0 ? Un : Pn;
+          GemmDesc<T> d{};
+          d.C = Cb + r0 + (int64_t)r0 * k;
+          d.Cin = d.C;
+          d.ldc = d.ldcin = k;
+          d.A = Cb + r0 + (int64_t)J * k;
+          d.lda = k;
+          d.B = Bb + r0 + (int64_t)J * k;
+          d.ldb = k;
+          d.dk = pole->dvec + Fr.first + J;
+          d.M = (int)(k - r0);
+          d.N = Fr.ns - r0;
+          d.K = jb;
+          d.flags = GF_TRANSB | GF_TRI;
+          d.tri_off = 0;
+          d.alpha = mone;
+          d.beta = one;
+          gd.push_back(d);
+          gemm_work(d, &g.flops, &g.bytes);
+          g.maxM = std::max(g.maxM, d.M);
+          g.maxN = std::max(g.maxN, d.N);
+        }
       }
       g.cnt = (int)gd.size() - g.off;
       lg[L].trail.push_back(g);
@@ -897,13 +962,13 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         d.ldc = d.ldcin = Fr.nb;
         d.A = Pn + Fr.ns;
         d.lda = k;
-        d.B = Pn + Fr.ns;
+        d.B = (lu ? pole->upanel + P->panel_off[f] : Pn) + Fr.ns;  // LU: full update L21 D U12
         d.ldb = k;
         d.dk = pole->dvec + Fr.first;
         d.M = Fr.nb;
         d.N = Fr.nb;
         d.K = Fr.ns;
-        d.flags = GF_TRANSB | GF_TRI;
+        d.flags = lu ? GF_TRANSB : (GF_TRANSB | GF_TRI);
         d.tri_off = 0;
         d.alpha = mone;
         d.beta = one;
@@ -930,14 +995,15 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
         }
         so += (int64_t)FB * Fr.ns;
       }
+      for (int side = 0; side < (lu ? 2 : 1); ++side)
       for (auto& fa : act) {
         const Front& Fr = S.fronts[fa.first];
         int64_t k = (int64_t)Fr.ns + Fr.nb;
         int ib = std::min(FB, Fr.ns - I * FB);
-        T* Pn = pole->panel + P->panel_off[fa.first];
-        T* X = pole->inv + P->inv_off[fa.first];
+        T* Pn = (side ? pole->upanel : pole->panel) + P->panel_off[fa.first];
+        T* X = (side ? pole->uinv : pole->inv) + P->inv_off[fa.first];
         GemmDesc<T> d{};
-        d.C = scratch + fa.second;
+        d.C = scratch + fa.second + side * P->inv_scratch;
         d.ldc = ib;
         d.A = Pn + (int64_t)I * FB;
         d.lda = k;
@@ -956,16 +1022,17 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       }
       g1.cnt = (int)gd.size() - g1.off;
       g2.off = (int)gd.size();
+      for (int side = 0; side < (lu ? 2 : 1); ++side)
       for (auto& fa : act) {
         const Front& Fr = S.fronts[fa.first];
         int ib = std::min(FB, Fr.ns - I * FB);
-        T* X = pole->inv + P->inv_off[fa.first];
+        T* X = (side ? pole->uinv : pole->inv) + P->inv_off[fa.first];
         GemmDesc<T> d{};
         d.C = X + (int64_t)I * FB;
         d.ldc = Fr.ns;
         d.A = X + (int64_t)I * FB + (int64_t)I * FB * Fr.ns;
         d.lda = Fr.ns;
-        d.B = scratch + fa.second;
+        d.B = scratch + fa.second + side * P->inv_scratch;
         d.ldb = ib;
         d.M = ib;
         d.N = I * FB;
@@ -1012,18 +1079,35 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
   const GemmDesc<T>* dgd = fw->dgd;
   const std::vector<FactorLevelG>& lg = fw->lg;
   const double sr = fw->sr, si = fw->si;
+  const bool lu = P->cplx();
   HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
   HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
   HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
   HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
+  if (lu) {
+    HIPC(hipMemsetAsync(pole->upanel, 0, sizeof(T) * P->panel_total, s));
+    HIPC(hipMemsetAsync(pole->uinv, 0, sizeof(T) * P->inv_total, s));
+  }
   // run the program level by level
   for (int L = 0; L < nl; ++L) {
     {
       prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-      front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L],
-                        P->lvl_asm_end[L] - P->lvl_asm_begin[L], P->pa, P->pb, sr, si, s);
-      for (const GemmLaunch& g : P->lvl_ext[L])
-        front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+      const int64_t na = P->lvl_asm_end[L] - P->lvl_asm_begin[L];
+      if (lu) {
+        // asm_src holds the CSR entry (j, i) for the lower position (i, j) (equal for symmetric
+        // matrices); the L panel takes (i, j) itself, the transposed U panel takes (j, i)
+        front_assemble_cplx<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src_t + P->lvl_asm_begin[L], na,
+                               P->za, P->zb, sr, si, s);
+        front_assemble_cplx<T>(pole->upanel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L], na,
+                               P->za, P->zb, sr, si, s);
+        for (const GemmLaunch& g : P->lvl_ext[L])
+          front_extend_add_lu<T>(pole->panel, pole->upanel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+      } else {
+        front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L], na, P->pa,
+                          P->pb, sr, si, s);
+        for (const GemmLaunch& g : P->lvl_ext[L])
+          front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+      }
     }
     const DiagDesc* dd = P->diag + P->lvl_diag_off[L];
     for (size_t jj = 0; jj < P->lvl_diag_nJ[L].size(); ++jj) {
@@ -1031,8 +1115,15 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
       int nd = P->lvl_diag_nJ[L][jj];
       {
         prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-        front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
-        front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+        if (lu) {
+          // L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
+          front_diag_block_lu<T>(pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, dd, nd, J, flag, s);
+          front_panel_trsm<T>(pole->panel, pole->uinv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+          front_panel_trsm<T>(pole->upanel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+        } else {
+          front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+          front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
+        }
       }
       run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
     }
@@ -1042,6 +1133,7 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
       run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
     }
   }
+  if (lu) conj_copy(pole->dconj, pole->dvec, P->n, s);
   HIPC(hipGetLastError());
   return ZOLO_OK;
 }
@@ -1152,7 +1244,22 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   zolo_pencil* P = F->P;
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
-  const int np = (int)poles.size();
+  // Solves of one program ("virtual poles").  LDL^T: K_j^-1 for every pole.
+  // LU (complex Hermitian pencils): K_j^-1 = U^-1 D^-1 L^-1, then
+  // K_j^-H = L^-H conj(D)^-1 U^-H, whose triangles are the conjugates of the
+  // stored U^T and L factors: the forward pass runs on (U^T, its inverse
+  // blocks), the backward pass on (L, its inverse blocks), all conjugated.
+  struct Role {
+    const T *fp, *fi, *bp, *bi, *dv;
+    int cj;
+  };
+  const bool lu = P->cplx();
+  std::vector<Role> roles;
+  for (const PoleMF<T>& pm : poles)
+    roles.push_back({pm.panel, pm.inv, lu ? pm.upanel : pm.panel, lu ? pm.uinv : pm.inv, pm.dvec, 0});
+  if (lu)
+    for (const PoleMF<T>& pm : poles) roles.push_back({pm.upanel, pm.uinv, pm.panel, pm.inv, pm.dconj, GF_CONJA});
+  const int np = (int)roles.size();
   G->p = p;
   G->np = np;
   int64_t wmax = 0, xbmax = 0, tmax = 0;
@@ -1281,14 +1388,14 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       if (Fr.ns == 0) return false;
       d.C = G->Y + j * npx + (int64_t)Fr.first * p;
       d.ldc = p;
-      d.A = poles[j].inv + P->inv_off[f];
+      d.A = roles[j].fi + P->inv_off[f];
       d.lda = Fr.ns;
       d.B = G->W + j * wmax + woff[L][i];
       d.ldb = p;
       d.M = Fr.ns;
       d.N = p;
       d.K = Fr.ns;
-      d.flags = GF_TRANSB | GF_TRANSC | GF_ALOW;
+      d.flags = GF_TRANSB | GF_TRANSC | GF_ALOW | roles[j].cj;
       d.alpha = one;
       d.beta = zero;
       return true;
@@ -1301,14 +1408,14 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       d.ldc = p;
       d.Cin = G->W + j * wmax + woff[L][i] + (int64_t)Fr.ns * p;
       d.ldcin = p;
-      d.A = poles[j].panel + P->panel_off[f] + Fr.ns;
+      d.A = roles[j].fp + P->panel_off[f] + Fr.ns;
       d.lda = k;
       d.B = G->Y + j * npx + (int64_t)Fr.first * p;
       d.ldb = p;
       d.M = Fr.nb;
       d.N = p;
       d.K = Fr.ns;
-      d.flags = GF_TRANSB | GF_TRANSC;
+      d.flags = GF_TRANSB | GF_TRANSC | roles[j].cj;
       d.alpha = mone;
       d.beta = one;
       return true;
@@ -1321,15 +1428,15 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       d.ldc = p;
       d.Cin = G->Y + j * npx + (int64_t)Fr.first * p;
       d.ldcin = p;
-      d.crs = poles[j].dvec + Fr.first;
-      d.A = poles[j].panel + P->panel_off[f] + Fr.ns;
+      d.crs = roles[j].dv + Fr.first;
+      d.A = roles[j].bp + P->panel_off[f] + Fr.ns;
       d.lda = k;
       d.B = G->Xb + j * xbmax + xboff[L][i];
       d.ldb = p;
       d.M = Fr.ns;
       d.N = p;
       d.K = Fr.nb;
-      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV;
+      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV | roles[j].cj;
       d.alpha = mone;
       d.beta = one;
       return true;
@@ -1339,14 +1446,14 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       if (Fr.ns == 0) return false;
       d.C = G->X + j * npx + (int64_t)Fr.first * p;
       d.ldc = p;
-      d.A = poles[j].inv + P->inv_off[f];
+      d.A = roles[j].bi + P->inv_off[f];
       d.lda = Fr.ns;
       d.B = G->tb + j * tmax + toff[L][i];
       d.ldb = p;
       d.M = Fr.ns;
       d.N = p;
       d.K = Fr.ns;
-      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_AUP;
+      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_AUP | roles[j].cj;
       d.alpha = one;
       d.beta = zero;
       return true;
@@ -1428,38 +1535,44 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, boo
 
 int ensure_ws(zolo_factors* F, int p, int mmax) {
   Workspace* ws = F->ws.get();
-  const int nshift = F->co.r2;
+  const bool cx = F->P->cplx();
+  const int nshift = F->co.r2 * (cx ? 2 : 1);  // complex pencils: +i sqrt(c_j) and -i sqrt(c_j)
   if (ws && ws->p == p && ws->mmax >= mmax && ws->nshift == nshift) return ZOLO_OK;
   F->ws.reset(new Workspace());
   ws = F->ws.get();
   const int64_t n = F->P->n;
+  const int ef = cx ? 2 : 1;
   ws->p = p;
   ws->mmax = mmax;
   ws->nshift = nshift;
+  ws->ef = ef;
   ws->n = n;
   const int64_t Mp = (int64_t)(mmax + 1) * p;
-  CHK(ws->mem.alloc(&ws->Vb, n * Mp));
-  CHK(ws->mem.alloc(&ws->W, n * p));
-  CHK(ws->mem.alloc(&ws->T1, n * p));
-  CHK(ws->mem.alloc(&ws->Tb, n * p));
-  const int np = F->co.r1;
+  CHK(ws->mem.alloc(&ws->Vb, n * Mp * ef));
+  CHK(ws->mem.alloc(&ws->W, n * p * ef));
+  CHK(ws->mem.alloc(&ws->T1, n * p * ef));
+  CHK(ws->mem.alloc(&ws->Tb, n * p * ef));
+  const int np = F->co.r1 * (cx ? 2 : 1);
   CHK(ws->mem.alloc(&ws->Xc, n * p * np));
   CHK(ws->mem.alloc(&ws->Rc, n * p * np));
   CHK(ws->mem.alloc(&ws->Dc, 1));
   ws->ldh = Mp;
-  CHK(ws->mem.alloc(&ws->H, Mp * (int64_t)mmax * p));
-  CHK(ws->mem.alloc(&ws->hbuf, Mp * p));
+  CHK(ws->mem.alloc(&ws->H, Mp * (int64_t)mmax * p * ef));
+  CHK(ws->mem.alloc(&ws->hbuf, Mp * p * ef));
   ws->partial_len = std::max<int64_t>(Mp * p * 8, (int64_t)p * p * 256);
-  CHK(ws->mem.alloc(&ws->partial, ws->partial_len));
-  for (double** q : {&ws->G, &ws->R1, &ws->R1i, &ws->R2, &ws->R2i, &ws->R0, &ws->Rk}) CHK(ws->mem.alloc(q, (size_t)p * p));
+  CHK(ws->mem.alloc(&ws->partial, ws->partial_len * ef));
+  for (double** q : {&ws->G, &ws->R1, &ws->R1i, &ws->R2, &ws->R2i, &ws->R0, &ws->Rk})
+    CHK(ws->mem.alloc(q, (size_t)p * p * ef));
   CHK(ws->mem.alloc(&ws->flag, 4));
   CHK(ws->mem.alloc(&ws->res, (size_t)nshift * p));
   CHK(ws->mem.alloc(&ws->coef, nshift));
   CHK(ws->mem.alloc(&ws->shift_im, nshift));
-  CHK(ws->mem.alloc(&ws->Cm, (size_t)mmax * p * p));
+  CHK(ws->mem.alloc(&ws->Cm, (size_t)mmax * p * p * ef));
   CHK(ws->mem.alloc(&ws->Ys, (size_t)nshift * mmax * p * p));
   ws->gdesc_cap = 1024;
-  CHK(ws->mem.alloc(&ws->gdesc, ws->gdesc_cap + 4));
+  char* gd = nullptr;
+  CHK(ws->mem.alloc(&gd, sizeof(GemmDesc<zd>) * (ws->gdesc_cap + 4)));
+  ws->gdesc = gd;
   CHK(ws->mem.alloc(&ws->cn_partial, (size_t)colnorm_partials(n) * p + 16));
   CHK(ws->mem.alloc(&ws->cn_out, (size_t)p));
   HlsState& h = ws->hls;
@@ -1471,10 +1584,14 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   CHK(ws->mem.alloc(&h.refl, (size_t)nshift * mmax * p * (p + 1)));
   CHK(ws->mem.alloc(&h.tau, (size_t)nshift * mmax * p));
   CHK(ws->mem.alloc(&h.g, (size_t)nshift * Mp * p));
+  // Corollary 1: Z_2r2(g) = (M/2) sum_j a_j [(g + i sqrt c_j)^-1 + (g - i sqrt c_j)^-1], so the
+  // filter is Y = V/2 + sum over shifts of (M a_j / 4) (G + s)^-1 V.  Real pencils solve only
+  // s = +i sqrt c_j and take twice the real part.
   std::vector<double> sh(nshift), cf(nshift);
   for (int q = 0; q < nshift; ++q) {
-    sh[q] = std::sqrt(F->co.c[q]);
-    cf[q] = 0.5 * F->co.M * F->co.a[q];
+    const int j = q % F->co.r2;
+    sh[q] = (q < F->co.r2 ? 1.0 : -1.0) * std::sqrt(F->co.c[j]);
+    cf[q] = (cx ? 0.25 : 0.5) * F->co.M * F->co.a[j];
   }
   HIPC(hipMemcpy(ws->shift_im, sh.data(), sizeof(double) * nshift, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ws->coef, cf.data(), sizeof(double) * nshift, hipMemcpyHostToDevice));
@@ -1486,19 +1603,26 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
 // (T real, new ordering, ld p).  Mixed precision: complex64 factors, and
 // iterative refinement against FP64 residuals R_j = T - (A - sigma_j B) X_j
 // until max_j ||R_j|| / ||T|| <= tol_inner (column-wise).
-zolo_status poles_solve_all(zolo_factors* F, const double* T, int p, zd* X, double tol_inner, hipStream_t s) {
+// Complex Hermitian pencils (VT = zd, FP64 factors): X_j = K_j^-1 T for
+// j < r1 and X_{r1+j} = K_j^-H T.
+template <typename VT>
+zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double tol_inner, hipStream_t s) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
-  const int np = F->co.r1;
+  const int np = F->co.r1 * (P->cplx() ? 2 : 1);
   const int64_t npx = n * p;
   if (F->precision == ZOLO_PREC_FP64) {
     SolveProg<zd>* G = get_prog<zd>(F, p);
     if (!G) return ZOLO_ENOMEM;
-    run_solve<double, zd>(F, G, T, p, false, s);
+    run_solve<VT, zd>(F, G, T, p, false, s);
     HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * npx * np, hipMemcpyDeviceToDevice, s));
     F->n_solv += (long long)p * np;
     return ZOLO_OK;
   }
+  if constexpr (ST<VT>::cplx) {
+    set_error("complex pencils: mixed precision is not available");
+    return ZOLO_EINVAL;
+  } else {
   SolveProg<zf>* G = get_prog<zf>(F, p);
   if (!G) return ZOLO_ENOMEM;
   Workspace& ws = *F->ws;
@@ -1526,46 +1650,61 @@ zolo_status poles_solve_all(zolo_factors* F, const double* T, int p, zd* X, doub
     F->n_refine += (long long)p * np;
   }
   return ZOLO_OK;
+  }
 }
 
-// W (N x p, ld ldw) = G V (V: N x p new ordering, ld ldv)
-zolo_status apply_G_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* W, int64_t ldw,
-                        double tol_inner, hipStream_t s) {
+// W (N x p, ld ldw) = G V (V: N x p new ordering, ld ldv).  Proposition 2:
+// G V = M_hat [c0 V + sum_j (w_hat_j K_j^-1 + conj(w_hat_j) conj-pole solve) B V];
+// for real pencils the conjugate-pole solve is conj(K_j^-1 B V).
+template <typename VT>
+zolo_status apply_G_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* W, int64_t ldw, double tol_inner,
+                        hipStream_t s) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
   Workspace& ws = *F->ws;
   const zolo_filter_coeffs& co = F->co;
+  VT* Tb = (VT*)ws.Tb;
   // T = B V
   {
-    prof::Scope ps(ZOLO_PROF_SPMM, 2.0 * P->nnz * p, 12.0 * P->nnz + 8.0 * (n + 1) + 16.0 * n * p, s);
-    spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, ws.Tb, p, nullptr, 0, s);
+    prof::Scope ps(ZOLO_PROF_SPMM, 2.0 * P->nnz * p * (ST<VT>::cplx ? 4 : 1),
+                   (ST<VT>::cplx ? 20.0 : 12.0) * P->nnz + 8.0 * (n + 1) + 2.0 * sizeof(VT) * n * p, s);
+    if constexpr (ST<VT>::cplx)
+      spmm_cplx(n, P->prow, P->pcol, P->zb, nullptr, V, ldv, p, Tb, p, nullptr, 0, s);
+    else
+      spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, Tb, p, nullptr, 0, s);
   }
   {
-    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 16.0 * n * p, s);
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 2.0 * sizeof(VT) * n * p, s);
     scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
   }
-  CHK(poles_solve_all(F, ws.Tb, p, ws.Xc, tol_inner, s));
+  CHK(poles_solve_all<VT>(F, Tb, p, ws.Xc, tol_inner, s));
   for (int j = 0; j < co.r1; ++j) {
     prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 32.0 * n * p, s);
-    axpy_re(W, ldw, ws.Xc + j * n * p, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
+    if constexpr (ST<VT>::cplx)
+      axpy_pair(W, ldw, ws.Xc + (int64_t)j * n * p, ws.Xc + (int64_t)(co.r1 + j) * n * p, co.M_hat * co.w_hat_re[j],
+                co.M_hat * co.w_hat_im[j], n, p, s);
+    else
+      axpy_re(W, ldw, ws.Xc + (int64_t)j * n * p, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
   }
   return ZOLO_OK;
 }
 
 // CholQR2 of Win (N x p row-major, ld ldin) into Qout (ld ldq); R (p x p) = R2 R1 into ws.Rk
-zolo_status cholqr2(zolo_factors* F, const double* Win, int64_t ldin, double* Qout, int64_t ldq, int p, bool* breakdown,
+template <typename VT>
+zolo_status cholqr2(zolo_factors* F, const VT* Win, int64_t ldin, VT* Qout, int64_t ldq, int p, bool* breakdown,
                     hipStream_t s) {
   Workspace& ws = *F->ws;
   const int64_t n = F->P->n;
+  VT *G = (VT*)ws.G, *R1 = (VT*)ws.R1, *R1i = (VT*)ws.R1i, *R2 = (VT*)ws.R2, *R2i = (VT*)ws.R2i, *T1 = (VT*)ws.T1;
   int hf[2] = {0, 0};
   HIPC(hipMemsetAsync(ws.flag, 0, sizeof(int) * 4, s));
-  CHK(gemm_tn(ws, Win, ldin, Win, ldin, n, p, p, ws.G, p, false, s));
-  chol_upper_inv(ws.G, p, 1e-15, ws.R1, ws.R1i, ws.flag, s);
-  CHK(gemm_nt_big(ws, ws.T1, p, nullptr, 0, 0.0, 1.0, ws.R1i, p, true, Win, ldin, n, p, p, s));
-  CHK(gemm_tn(ws, ws.T1, p, ws.T1, p, n, p, p, ws.G, p, false, s));
-  chol_upper_inv(ws.G, p, 0.0, ws.R2, ws.R2i, ws.flag + 1, s);
-  CHK(gemm_nt_big(ws, Qout, ldq, nullptr, 0, 0.0, 1.0, ws.R2i, p, true, ws.T1, p, n, p, p, s));
-  upper_mul(ws.R2, ws.R1, ws.Rk, p, s);
+  CHK(gemm_tn<VT>(ws, Win, ldin, Win, ldin, n, p, p, G, p, false, s));
+  chol_upper_inv<VT>(G, p, 1e-15, R1, R1i, ws.flag, s);
+  CHK(gemm_nt_big<VT>(ws, T1, p, nullptr, 0, 0.0, 1.0, R1i, p, true, Win, ldin, n, p, p, s));
+  CHK(gemm_tn<VT>(ws, T1, p, T1, p, n, p, p, G, p, false, s));
+  chol_upper_inv<VT>(G, p, 0.0, R2, R2i, ws.flag + 1, s);
+  CHK(gemm_nt_big<VT>(ws, Qout, ldq, nullptr, 0, 0.0, 1.0, R2i, p, true, T1, p, n, p, p, s));
+  upper_mul<VT>(R2, R1, (VT*)ws.Rk, p, s);
   HIPC(hipMemcpyAsync(hf, ws.flag, sizeof(int) * 2, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   *breakdown = hf[0] || hf[1];
@@ -1573,29 +1712,32 @@ zolo_status cholqr2(zolo_factors* F, const double* Win, int64_t ldin, double* Qo
 }
 
 // Y (ld ldy) = R_ab(B^-1 A) V, everything in the new ordering
-zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int p, double* Y, int64_t ldy, double tol,
+template <typename VT>
+zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, double tol,
                              int maxit, zolo_filter_stats* st, hipStream_t s) {
   CHK(ensure_ws(F, p, maxit));
   Workspace& ws = *F->ws;
   const int64_t n = F->P->n;
   const int64_t Mp = ws.ldh;
-  const int ns = F->co.r2;
+  const int ns = ws.nshift;
+  VT *Vb = (VT*)ws.Vb, *W = (VT*)ws.W, *H = (VT*)ws.H, *hbuf = (VT*)ws.hbuf, *R0 = (VT*)ws.R0, *Rk = (VT*)ws.Rk;
   bool bd = false;
   // V = V0 R0
-  CHK(cholqr2(F, V, ldv, ws.Vb, Mp, p, &bd, s));
+  CHK(cholqr2<VT>(F, V, ldv, Vb, Mp, p, &bd, s));
   if (bd) {
     set_error("filter: input block is rank deficient");
     return ZOLO_EBREAKDOWN;
   }
-  HIPC(hipMemcpyAsync(ws.R0, ws.Rk, sizeof(double) * p * p, hipMemcpyDeviceToDevice, s));
-  std::vector<double> r0(p * p), r0n(p, 0.0);
-  HIPC(hipMemcpyAsync(r0.data(), ws.R0, sizeof(double) * p * p, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(R0, Rk, sizeof(VT) * p * p, hipMemcpyDeviceToDevice, s));
+  std::vector<VT> r0(p * p);
+  std::vector<double> r0n(p, 0.0);
+  HIPC(hipMemcpyAsync(r0.data(), R0, sizeof(VT) * p * p, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
   for (int c = 0; c < p; ++c)
-    for (int i = 0; i <= c; ++i) r0n[c] += r0[i + c * p] * r0[i + c * p];
+    for (int i = 0; i <= c; ++i) r0n[c] += abs2(r0[i + c * p]);
   for (int c = 0; c < p; ++c) r0n[c] = std::sqrt(r0n[c]);
-  hls_init(ws.hls, ws.R0, s);
-  HIPC(hipMemsetAsync(ws.H, 0, sizeof(double) * Mp * (int64_t)maxit * p, s));
+  hls_init<VT>(ws.hls, R0, s);
+  HIPC(hipMemsetAsync(H, 0, sizeof(VT) * Mp * (int64_t)maxit * p, s));
   std::vector<double> res((size_t)ns * p);
   int m = 0;
   double worst = 1.0;
@@ -1604,18 +1746,18 @@ zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int 
     // inexact inner solves (mixed precision): the tolerance grows as the outer
     // residual falls, tol_refine / ||r_{k-1}|| capped at 1e-4
     const double tol_inner = std::min(1e-4, F->tol_refine / std::max(worst, 1e-300));
-    CHK(apply_G_new(F, ws.Vb + (int64_t)k * p, Mp, p, ws.W, p, tol_inner, s));
+    CHK(apply_G_new<VT>(F, Vb + (int64_t)k * p, Mp, p, W, p, tol_inner, s));
     const int kp1 = (k + 1) * p;
     for (int pass = 0; pass < 2; ++pass) {
-      CHK(gemm_tn(ws, ws.Vb, Mp, ws.W, p, n, kp1, p, ws.hbuf, kp1, false, s));
-      CHK(gemm_nt_big(ws, ws.W, p, ws.W, p, 1.0, -1.0, ws.hbuf, kp1, true, ws.Vb, Mp, n, p, kp1, s));
-      reduce_partials(ws.H + (int64_t)k * p * Mp, Mp, ws.hbuf, 1, kp1, p, true, s);
+      CHK(gemm_tn<VT>(ws, Vb, Mp, W, p, n, kp1, p, hbuf, kp1, false, s));
+      CHK(gemm_nt_big<VT>(ws, W, p, W, p, 1.0, -1.0, hbuf, kp1, true, Vb, Mp, n, p, kp1, s));
+      reduce_partials<VT>(H + (int64_t)k * p * Mp, Mp, hbuf, 1, kp1, p, true, s);
     }
-    CHK(cholqr2(F, ws.W, p, ws.Vb + (int64_t)kp1, Mp, p, &bd, s));
-    put_block(ws.H, Mp, kp1, (int64_t)k * p, ws.Rk, p, s);
+    CHK(cholqr2<VT>(F, W, p, Vb + (int64_t)kp1, Mp, p, &bd, s));
+    put_block<VT>(H, Mp, kp1, (int64_t)k * p, Rk, p, s);
     {
       prof::Scope ps(ZOLO_PROF_HLS, 0.0, 0.0, s);
-      hls_step(ws.hls, ws.H, Mp, k, ws.res, s);
+      hls_step<VT>(ws.hls, H, Mp, k, ws.res, s);
     }
     HIPC(hipMemcpyAsync(res.data(), ws.res, sizeof(double) * ns * p, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1628,9 +1770,9 @@ zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int 
     if (worst <= tol || exhausted) break;
   }
   hls_backsolve(ws.hls, m, ws.Ys, s);
-  hls_combine_real(ws.Ys, m, p, ns, ws.coef, ws.Cm, s);
+  hls_combine(ws.Ys, m, p, ns, ws.coef, (VT*)ws.Cm, s);
   // Y = V/2 + V_m C
-  CHK(gemm_nt_big(ws, Y, ldy, V, ldv, 0.5, 1.0, ws.Cm, (int64_t)m * p, true, ws.Vb, Mp, n, p, m * p, s));
+  CHK(gemm_nt_big<VT>(ws, Y, ldy, V, ldv, 0.5, 1.0, (VT*)ws.Cm, (int64_t)m * p, true, Vb, Mp, n, p, m * p, s));
   HIPC(hipStreamSynchronize(s));
   if (st) {
     st->n_gmres = m;
@@ -1649,6 +1791,77 @@ zolo_status filter_apply_new(zolo_factors* F, const double* V, int64_t ldv, int 
 // ===========================================================================
 // ABI entry points on blocks in the original ordering
 // ===========================================================================
+namespace {
+// the ABI block entry points, on blocks of the pencil's scalar type
+template <typename VT>
+zolo_status spmm_abi(zolo_pencil* P, int which, const VT* d_X, int64_t ldx, int ncols, VT* d_Y, int64_t ldy,
+                     hipStream_t s) {
+  DevArena tmp;
+  VT *xn = nullptr, *yn = nullptr;
+  const int64_t n = P->n;
+  CHK(tmp.alloc(&xn, n * ncols));
+  CHK(tmp.alloc(&yn, n * ncols));
+  rows_gather<VT>(xn, ncols, d_X, ldx, P->perm, n, ncols, s);
+  if constexpr (ST<VT>::cplx)
+    spmm_cplx(n, P->prow, P->pcol, which == 0 ? P->za : P->zb, nullptr, xn, ncols, ncols, yn, ncols, nullptr, 0, s);
+  else
+    spmm_real(n, P->prow, P->pcol, which == 0 ? P->pa : P->pb, nullptr, xn, ncols, ncols, yn, ncols, nullptr, 0, s);
+  rows_scatter<VT>(d_Y, ldy, yn, ncols, P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+template <typename VT>
+zolo_status pole_solve_abi(zolo_factors* F, int j, const VT* d_T, int64_t ldt, int ncols, zd* d_X, int64_t ldx,
+                           hipStream_t s) {
+  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  VT* tn = nullptr;
+  CHK(tmp.alloc(&tn, n * ncols));
+  rows_gather<VT>(tn, ncols, d_T, ldt, F->P->perm, n, ncols, s);
+  CHK(poles_solve_all<VT>(F, tn, ncols, F->ws->Xc, F->tol_refine, s));
+  rows_scatter<zd>(d_X, ldx, F->ws->Xc + (int64_t)j * n * ncols, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+template <typename VT>
+zolo_status apply_G_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int ncols, VT* d_W, int64_t ldw, hipStream_t s) {
+  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  VT *vn = nullptr, *wn = nullptr;
+  CHK(tmp.alloc(&vn, n * ncols));
+  CHK(tmp.alloc(&wn, n * ncols));
+  rows_gather<VT>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
+  CHK(apply_G_new<VT>(F, vn, ncols, ncols, wn, ncols, F->tol_refine, s));
+  rows_scatter<VT>(d_W, ldw, wn, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+
+template <typename VT>
+zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int ncols, VT* d_Y, int64_t ldy, double tol,
+                             int maxit, zolo_filter_stats* st, hipStream_t s) {
+  const int64_t n = F->P->n;
+  DevArena tmp;
+  VT *vn = nullptr, *yn = nullptr;
+  CHK(tmp.alloc(&vn, n * ncols));
+  CHK(tmp.alloc(&yn, n * ncols));
+  rows_gather<VT>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
+  zolo_status rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
+  if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
+  rows_scatter<VT>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
+  HIPC(hipStreamSynchronize(s));
+  HIPC(hipGetLastError());
+  return rc;
+}
+}  // namespace
+
 extern "C" zolo_status zolo_spmm(zolo_pencil* P, int which, const void* d_X, int64_t ldx, int ncols, void* d_Y,
                                  int64_t ldy, void* stream) {
   if (!P || !d_X || !d_Y || ncols <= 0 || ldx < ncols || ldy < ncols || (which != 0 && which != 1)) {
@@ -1656,39 +1869,20 @@ extern "C" zolo_status zolo_spmm(zolo_pencil* P, int which, const void* d_X, int
     return ZOLO_EINVAL;
   }
   hipStream_t s = as_stream(stream);
-  DevArena tmp;
-  double *xn = nullptr, *yn = nullptr;
-  const int64_t n = P->n;
-  CHK(tmp.alloc(&xn, n * ncols));
-  CHK(tmp.alloc(&yn, n * ncols));
-  rows_gather<double>(xn, ncols, (const double*)d_X, ldx, P->perm, n, ncols, s);
-  spmm_real(n, P->prow, P->pcol, which == 0 ? P->pa : P->pb, nullptr, xn, ncols, ncols, yn, ncols, nullptr, 0, s);
-  rows_scatter<double>((double*)d_Y, ldy, yn, ncols, P->perm, n, ncols, s);
-  HIPC(hipStreamSynchronize(s));
-  HIPC(hipGetLastError());
-  return ZOLO_OK;
+  if (P->cplx()) return spmm_abi<zd>(P, which, (const zd*)d_X, ldx, ncols, (zd*)d_Y, ldy, s);
+  return spmm_abi<double>(P, which, (const double*)d_X, ldx, ncols, (double*)d_Y, ldy, s);
 }
 
 extern "C" zolo_status zolo_pole_solve(zolo_factors* F, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
                                        int64_t ldx, void* stream) {
-  if (!F || !d_T || !d_X || j < 0 || j >= F->co.r1 || ncols <= 0 || ldt < ncols || ldx < ncols) {
+  const int nj = F ? F->co.r1 * (F->P->cplx() ? 2 : 1) : 0;
+  if (!F || !d_T || !d_X || j < 0 || j >= nj || ncols <= 0 || ldt < ncols || ldx < ncols) {
     set_error("zolo_pole_solve: invalid argument");
     return ZOLO_EINVAL;
   }
   hipStream_t s = as_stream(stream);
-  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
-  const int64_t n = F->P->n;
-  DevArena tmp;
-  double* tn = nullptr;
-  zd* xn = nullptr;
-  CHK(tmp.alloc(&tn, n * ncols));
-  (void)xn;
-  rows_gather<double>(tn, ncols, d_T, ldt, F->P->perm, n, ncols, s);
-  CHK(poles_solve_all(F, tn, ncols, F->ws->Xc, F->tol_refine, s));
-  rows_scatter<zd>((zd*)d_X, ldx, F->ws->Xc + (int64_t)j * n * ncols, ncols, F->P->perm, n, ncols, s);
-  HIPC(hipStreamSynchronize(s));
-  HIPC(hipGetLastError());
-  return ZOLO_OK;
+  if (F->P->cplx()) return pole_solve_abi<zd>(F, j, (const zd*)d_T, ldt, ncols, (zd*)d_X, ldx, s);
+  return pole_solve_abi<double>(F, j, d_T, ldt, ncols, (zd*)d_X, ldx, s);
 }
 
 extern "C" zolo_status zolo_apply_G(zolo_factors* F, const double* d_V, int64_t ldv, int ncols, double* d_W,
@@ -1698,18 +1892,8 @@ extern "C" zolo_status zolo_apply_G(zolo_factors* F, const double* d_V, int64_t 
     return ZOLO_EINVAL;
   }
   hipStream_t s = as_stream(stream);
-  CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
-  const int64_t n = F->P->n;
-  DevArena tmp;
-  double *vn = nullptr, *wn = nullptr;
-  CHK(tmp.alloc(&vn, n * ncols));
-  CHK(tmp.alloc(&wn, n * ncols));
-  rows_gather<double>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
-  CHK(apply_G_new(F, vn, ncols, ncols, wn, ncols, F->tol_refine, s));
-  rows_scatter<double>(d_W, ldw, wn, ncols, F->P->perm, n, ncols, s);
-  HIPC(hipStreamSynchronize(s));
-  HIPC(hipGetLastError());
-  return ZOLO_OK;
+  if (F->P->cplx()) return apply_G_abi<zd>(F, (const zd*)d_V, ldv, ncols, (zd*)d_W, ldw, s);
+  return apply_G_abi<double>(F, d_V, ldv, ncols, d_W, ldw, s);
 }
 
 extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int64_t ldv, int ncols, double* d_Y,
@@ -1721,43 +1905,18 @@ extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int
   if (tol <= 0) tol = 1e-10;
   if (maxit <= 0) maxit = 60;
   hipStream_t s = as_stream(stream);
-  const int64_t n = F->P->n;
-  DevArena tmp;
-  double *vn = nullptr, *yn = nullptr;
-  CHK(tmp.alloc(&vn, n * ncols));
-  CHK(tmp.alloc(&yn, n * ncols));
-  rows_gather<double>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
-  zolo_status rc = filter_apply_new(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
-  if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
-  rows_scatter<double>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
-  HIPC(hipStreamSynchronize(s));
-  HIPC(hipGetLastError());
-  return rc;
+  if (F->P->cplx()) return filter_apply_abi<zd>(F, (const zd*)d_V, ldv, ncols, (zd*)d_Y, ldy, tol, maxit, st, s);
+  return filter_apply_abi<double>(F, d_V, ldv, ncols, d_Y, ldy, tol, maxit, st, s);
 }
 
 // ===========================================================================
 // Algorithm 1
 // ===========================================================================
-extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
-                                  const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_result** out) {
-  if (!ctx || !P || !out || !(a < b) || n_lambda_est < 0) {
-    set_error("zolo_solve: invalid argument");
-    return ZOLO_EINVAL;
-  }
-  zolo_opts o;
-  if (opts_in)
-    o = *opts_in;
-  else
-    zolo_opts_default(&o);
-  if (std::isnan(o.a_minus) || std::isnan(o.a_plus) || std::isnan(o.b_minus) || std::isnan(o.b_plus)) {
-    set_error("zolo_solve: eigengaps (a_minus, a_plus, b_minus, b_plus) must be given");
-    return ZOLO_EINVAL;
-  }
-  if (!(o.a_minus < a && a < o.a_plus && o.b_minus < b && b < o.b_plus)) {
-    set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
-    return ZOLO_EINVAL;
-  }
-  HIPC(hipSetDevice(ctx->device));
+namespace {
+// Algorithm 1 on blocks of scalar VT (double: real pencils, zd: complex Hermitian pencils)
+template <typename VT>
+zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est, zolo_opts o,
+                       const double* d_Q0, void* stream, zolo_result** out) {
   hipStream_t s = as_stream(stream);
   const double t_start = now_s();
   const int64_t n = P->n;
@@ -1769,6 +1928,7 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   }
   std::unique_ptr<zolo_result> R(new zolo_result());
   R->n = n;
+  R->ef = ST<VT>::cplx ? 2 : 1;
   zolo_stats& st = R->st;
   double t0 = now_s();
   zolo_filter_coeffs co;
@@ -1798,7 +1958,8 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   Workspace& ws = *F->ws;
   // subspace buffers (new ordering)
   DevArena mem;
-  double *Q, *Y, *AY, *BY, *X, *AX, *BX, *At, *Bt, *theta, *Cm, *work, *rp, *rn, *Gx;
+  VT *Q, *Y, *AY, *BY, *X, *AX, *BX, *At, *Bt, *Cm, *work, *Gx;
+  double *theta, *rp, *rn;
   int* kdev;
   CHK(mem.alloc(&Q, n * nss));
   CHK(mem.alloc(&Y, n * nss));
@@ -1812,17 +1973,18 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   CHK(mem.alloc(&Gx, (size_t)nss * nss));
   CHK(mem.alloc(&theta, nss));
   CHK(mem.alloc(&Cm, (size_t)nss * nss));
-  CHK(mem.alloc(&work, (size_t)7 * nss * nss + 8 * nss + 64));
+  CHK(mem.alloc(&work, (size_t)7 * nss * nss + 8 * nss + 64));  // 6 n^2 values + 2 n doubles + 2 n ints
   CHK(mem.alloc(&rp, (size_t)((n + 511) / 512) * 3 * nss + 16));
   CHK(mem.alloc(&rn, (size_t)3 * nss));
   CHK(mem.alloc(&kdev, 1));
   if (d_Q0) {
-    rows_gather<double>(Q, nss, d_Q0, nss, P->perm, n, nss, s);
+    rows_gather<VT>(Q, nss, (const VT*)d_Q0, nss, P->perm, n, nss, s);
   } else {
+    // seeded Gaussian start block (complex pencils: independent real and imaginary parts)
     std::vector<double> g;
-    gaussian_host(o.seed, (size_t)n * nss, &g);
-    CHK(mem.upload(&X, g.data(), g.size()));  // reuse X as staging
-    rows_gather<double>(Q, nss, X, nss, P->perm, n, nss, s);
+    gaussian_host(o.seed, (size_t)n * nss * (ST<VT>::cplx ? 2 : 1), &g);
+    HIPC(hipMemcpy(X, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));  // X as staging
+    rows_gather<VT>(Q, nss, X, nss, P->perm, n, nss, s);
   }
   t0 = now_s();
   std::vector<double> th(nss), rnh(3 * nss);
@@ -1833,7 +1995,7 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   zolo_status frc = ZOLO_OK;
   for (int it = 1; it <= std::max(1, o.max_subspace_iter); ++it) {
     zolo_filter_stats fs{};
-    frc = filter_apply_new(F.get(), Q, nss, nss, Y, nss, tol_g, maxit, &fs, s);
+    frc = filter_apply_new<VT>(F.get(), Q, nss, nss, Y, nss, tol_g, maxit, &fs, s);
     if (frc != ZOLO_OK && frc != ZOLO_ENOCONV) return frc;
     st.n_iter = it;
     st.n_gmres_total += fs.n_gmres;
@@ -1841,14 +2003,18 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     st.gmres_resid = fs.worst_resid;
     // Rayleigh-Ritz
     {
-      prof::Scope ps(ZOLO_PROF_SPMM, 4.0 * P->nnz * nss, 20.0 * P->nnz + 8.0 * (n + 1) + 24.0 * n * nss, s);
-      spmm_real(n, P->prow, P->pcol, P->pa, P->pb, Y, nss, nss, AY, nss, BY, nss, s);
+      prof::Scope ps(ZOLO_PROF_SPMM, 4.0 * P->nnz * nss * (ST<VT>::cplx ? 4 : 1),
+                     (ST<VT>::cplx ? 36.0 : 20.0) * P->nnz + 8.0 * (n + 1) + 3.0 * sizeof(VT) * n * nss, s);
+      if constexpr (ST<VT>::cplx)
+        spmm_cplx(n, P->prow, P->pcol, P->za, P->zb, Y, nss, nss, AY, nss, BY, nss, s);
+      else
+        spmm_real(n, P->prow, P->pcol, P->pa, P->pb, Y, nss, nss, AY, nss, BY, nss, s);
     }
-    CHK(gemm_tn(ws, Y, nss, AY, nss, n, nss, nss, At, nss, false, s));
-    CHK(gemm_tn(ws, Y, nss, BY, nss, n, nss, nss, Bt, nss, false, s));
+    CHK(gemm_tn<VT>(ws, Y, nss, AY, nss, n, nss, nss, At, nss, false, s));
+    CHK(gemm_tn<VT>(ws, Y, nss, BY, nss, n, nss, nss, Bt, nss, false, s));
     {
       prof::Scope ps(ZOLO_PROF_RR, 0.0, 0.0, s);
-      rr_reduce(At, Bt, nss, 1e-12, theta, Cm, kdev, work, s);
+      rr_reduce<VT>(At, Bt, nss, 1e-12, theta, Cm, kdev, work, s);
     }
     HIPC(hipMemcpyAsync(&k, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1858,10 +2024,10 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
       return ZOLO_EBREAKDOWN;
     }
     // X = Y C, AX = AY C, BX = BY C  (row-major N x k)
-    CHK(gemm_nt_big(ws, X, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, Y, nss, n, k, nss, s));
-    CHK(gemm_nt_big(ws, AX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, AY, nss, n, k, nss, s));
-    CHK(gemm_nt_big(ws, BX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, BY, nss, n, k, nss, s));
-    resid_norms(AX, BX, X, theta, n, k, rp, rn, s);
+    CHK(gemm_nt_big<VT>(ws, X, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, Y, nss, n, k, nss, s));
+    CHK(gemm_nt_big<VT>(ws, AX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, AY, nss, n, k, nss, s));
+    CHK(gemm_nt_big<VT>(ws, BX, k, nullptr, 0, 0.0, 1.0, Cm, nss, true, BY, nss, n, k, nss, s));
+    resid_norms<VT>(AX, BX, X, theta, n, k, rp, rn, s);
     HIPC(hipMemcpyAsync(th.data(), theta, sizeof(double) * k, hipMemcpyDeviceToHost, s));
     HIPC(hipMemcpyAsync(rnh.data(), rn, sizeof(double) * 3 * k, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
@@ -1875,8 +2041,7 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     }
     st.max_resid = worst;
     // next block: Ritz vectors, padded with the previous block's columns
-    HIPC(hipMemcpy2DAsync(Q, sizeof(double) * nss, X, sizeof(double) * k, sizeof(double) * k, n,
-                          hipMemcpyDeviceToDevice, s));
+    HIPC(hipMemcpy2DAsync(Q, sizeof(VT) * nss, X, sizeof(VT) * k, sizeof(VT) * k, n, hipMemcpyDeviceToDevice, s));
     if (!sel.empty() && worst <= o.tol_resid) {
       converged = true;
       break;
@@ -1909,23 +2074,29 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   st.e_lambda_x = emax;
   st.n_found = cnt;
   if (cnt > 0) {
-    CHK(R->mem.alloc(&R->vec, n * cnt));
-    double* tmpv = nullptr;
+    VT* vec = nullptr;
+    CHK(R->mem.alloc(&vec, n * cnt));
+    R->vec = (double*)vec;
+    VT* tmpv = nullptr;
     CHK(mem.alloc(&tmpv, n * cnt));
     int c0 = sel[0];
     // selected Ritz values are consecutive in the ascending order
-    HIPC(hipMemcpy2DAsync(tmpv, sizeof(double) * cnt, X + c0, sizeof(double) * k, sizeof(double) * cnt, n,
-                          hipMemcpyDeviceToDevice, s));
-    rows_scatter<double>(R->vec, cnt, tmpv, cnt, P->perm, n, cnt, s);
-    // B-orthonormality of the returned vectors: X^T B X - I
-    spmm_real(n, P->prow, P->pcol, P->pb, nullptr, tmpv, cnt, cnt, AX, cnt, nullptr, 0, s);
-    CHK(gemm_tn(ws, tmpv, cnt, AX, cnt, n, cnt, cnt, Gx, cnt, false, s));
-    std::vector<double> gx((size_t)cnt * cnt);
-    HIPC(hipMemcpyAsync(gx.data(), Gx, sizeof(double) * cnt * cnt, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpy2DAsync(tmpv, sizeof(VT) * cnt, X + c0, sizeof(VT) * k, sizeof(VT) * cnt, n, hipMemcpyDeviceToDevice,
+                          s));
+    rows_scatter<VT>(vec, cnt, tmpv, cnt, P->perm, n, cnt, s);
+    // B-orthonormality of the returned vectors: X^H B X - I
+    if constexpr (ST<VT>::cplx)
+      spmm_cplx(n, P->prow, P->pcol, P->zb, nullptr, tmpv, cnt, cnt, AX, cnt, nullptr, 0, s);
+    else
+      spmm_real(n, P->prow, P->pcol, P->pb, nullptr, tmpv, cnt, cnt, AX, cnt, nullptr, 0, s);
+    CHK(gemm_tn<VT>(ws, tmpv, cnt, AX, cnt, n, cnt, cnt, Gx, cnt, false, s));
+    std::vector<VT> gx((size_t)cnt * cnt);
+    HIPC(hipMemcpyAsync(gx.data(), Gx, sizeof(VT) * cnt * cnt, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     double bo = 0.0;
     for (int i = 0; i < cnt; ++i)
-      for (int j2 = 0; j2 < cnt; ++j2) bo = std::max(bo, std::fabs(gx[i + (size_t)j2 * cnt] - (i == j2 ? 1.0 : 0.0)));
+      for (int j2 = 0; j2 < cnt; ++j2)
+        bo = std::max(bo, std::sqrt(abs2(sub(gx[i + (size_t)j2 * cnt], cvt<VT, double>(i == j2 ? 1.0 : 0.0)))));
     st.b_orth = bo;
   }
   st.t_total = now_s() - t_start;
@@ -1939,6 +2110,35 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     return ZOLO_ENOCONV;
   }
   return frc == ZOLO_ENOCONV ? ZOLO_ENOCONV : ZOLO_OK;
+}
+}  // namespace
+
+extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
+                                  const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_result** out) {
+  if (!ctx || !P || !out || !(a < b) || n_lambda_est < 0) {
+    set_error("zolo_solve: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  zolo_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    zolo_opts_default(&o);
+  if (std::isnan(o.a_minus) || std::isnan(o.a_plus) || std::isnan(o.b_minus) || std::isnan(o.b_plus)) {
+    set_error("zolo_solve: eigengaps (a_minus, a_plus, b_minus, b_plus) must be given");
+    return ZOLO_EINVAL;
+  }
+  if (!(o.a_minus < a && a < o.a_plus && o.b_minus < b && b < o.b_plus)) {
+    set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(ctx->device));
+  if (P->cplx() && o.precision != ZOLO_PREC_FP64) {
+    set_error("zolo_solve: complex pencils are solved with FP64 factors only");
+    return ZOLO_EINVAL;
+  }
+  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
+  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
 }
 
 extern "C" zolo_status zolo_profile_enable(int on) {
@@ -1969,8 +2169,8 @@ extern "C" zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_ds
   }
   if (r->count == 0) return ZOLO_OK;
   hipStream_t s = as_stream(stream);
-  HIPC(hipMemcpy2DAsync(d_dst, sizeof(double) * ld, r->vec, sizeof(double) * r->count, sizeof(double) * r->count, r->n,
-                        hipMemcpyDeviceToDevice, s));
+  const size_t e = sizeof(double) * r->ef;
+  HIPC(hipMemcpy2DAsync(d_dst, e * ld, r->vec, e * r->count, e * r->count, r->n, hipMemcpyDeviceToDevice, s));
   HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
 }
@@ -2009,11 +2209,13 @@ zolo_result* result_clone(const zolo_result* r) {
   std::unique_ptr<zolo_result> c(new zolo_result());
   c->n = r->n;
   c->count = r->count;
+  c->ef = r->ef;
   c->eig = r->eig;
   c->st = r->st;
   if (r->count > 0) {
-    if (c->mem.alloc(&c->vec, r->n * r->count) != ZOLO_OK) return nullptr;
-    if (hipMemcpy(c->vec, r->vec, sizeof(double) * r->n * r->count, hipMemcpyDeviceToDevice) != hipSuccess) return nullptr;
+    if (c->mem.alloc(&c->vec, r->n * r->count * r->ef) != ZOLO_OK) return nullptr;
+    if (hipMemcpy(c->vec, r->vec, sizeof(double) * r->n * r->count * r->ef, hipMemcpyDeviceToDevice) != hipSuccess)
+      return nullptr;
   }
   return c.release();
 }

@@ -129,6 +129,11 @@ __host__ __device__ inline float abs2(float a) { return a * a; }
 __host__ __device__ inline double abs2(zd a) { return a.re * a.re + a.im * a.im; }
 __host__ __device__ inline float abs2(zf a) { return a.re * a.re + a.im * a.im; }
 
+__host__ __device__ inline double re_(double a) { return a; }
+__host__ __device__ inline double re_(zd a) { return a.re; }
+__host__ __device__ inline double scl(double a, double r) { return a * r; }
+__host__ __device__ inline zd scl(zd a, double r) { return zd{a.re * r, a.im * r}; }
+
 // conversions
 template <typename To, typename From>
 __host__ __device__ inline To cvt(From x);

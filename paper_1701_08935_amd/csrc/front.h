@@ -58,6 +58,20 @@ void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, i
 template <typename T>
 void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s);
 
+// LU fronts of complex Hermitian pencils (no pivoting).  Each front keeps an
+// L panel (k x ns: the front's lower part) and a U panel of the same layout
+// holding the transpose of its upper part, so L, U^T, their diagonal-block
+// inverses and D are laid out as in the LDL^T case.
+template <typename T>
+void front_assemble_cplx(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const zd* a, const zd* b,
+                         double sr, double si, hipStream_t s);
+template <typename T>
+void front_extend_add_lu(T* panel, T* upanel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
+                         hipStream_t s);
+template <typename T>
+void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
+                         int* breakdown, hipStream_t s);
+
 // rows J+jb .. k-1 of each panel: L(r, J:J+jb) = P(r, J:J+jb) inv(J,J)^T D_J^-1 (in place)
 template <typename T>
 void front_panel_trsm(T* panel, const T* inv, const T* dvec, const DiagDesc* d, int nd, int J, int max_rows,

@@ -22,35 +22,37 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-__global__ void reduce_partials_kernel(double* __restrict__ out, int64_t ld_out, const double* __restrict__ partial,
-                                       int S, int M, int N, int add) {
+template <typename T>
+__global__ void reduce_partials_kernel(T* __restrict__ out, int64_t ld_out, const T* __restrict__ partial, int S, int M,
+                                       int N, int addto) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t MN = (int64_t)M * N;
   if (e >= MN) return;
-  double s = 0.0;
-  for (int q = 0; q < S; ++q) s += partial[q * MN + e];
+  T s = ST<T>::zero();
+  for (int q = 0; q < S; ++q) s = add(s, partial[q * MN + e]);
   int64_t i = e % M, j = e / M;
-  double* o = out + i + j * ld_out;
-  *o = add ? *o + s : s;
+  T* o = out + i + j * ld_out;
+  *o = addto ? add(*o, s) : s;
 }
 
 // single workgroup; G is read, R/Rinv written (all col-major p x p).  With
 // USE_LDS the factorization runs in LDS (p <= 128) and only R, R^-1 are
-// written to global memory.
-template <bool USE_LDS>
-__global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __restrict__ G, int p, double rel_shift,
-                                                              double* __restrict__ Rg, double* __restrict__ Rinv,
-                                                              int* flag) {
-  extern __shared__ double lds_R[];
-  double* R = USE_LDS ? lds_R : Rg;
-  // the inverse also lives in LDS when both fit (p <= 96)
-  double* Ri = (USE_LDS && p <= 96) ? lds_R + p * p : Rinv;
+// written to global memory.  Hermitian G = R^H R for complex T.
+template <typename T, bool USE_LDS>
+__global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const T* __restrict__ G, int p, double rel_shift,
+                                                              T* __restrict__ Rg, T* __restrict__ Rinv, int* flag) {
+  extern __shared__ char lds_raw[];
+  T* lds_R = (T*)lds_raw;
+  T* R = USE_LDS ? lds_R : Rg;
+  // the inverse also lives in LDS when both fit
+  const bool inv_lds = USE_LDS && (int64_t)2 * p * p * sizeof(T) <= 160 * 1024 - 4096;
+  T* Ri = inv_lds ? lds_R + p * p : Rinv;
   const int tid = threadIdx.x, nt = blockDim.x;
   __shared__ double trace_s;
   __shared__ int bad_s;
   if (tid == 0) {
     double tr = 0.0;
-    for (int i = 0; i < p; ++i) tr += G[i + (int64_t)i * p];
+    for (int i = 0; i < p; ++i) tr += re_(G[i + (int64_t)i * p]);
     trace_s = tr;
     bad_s = 0;
   }
@@ -58,13 +60,13 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
   const double shift = rel_shift * trace_s / (p > 0 ? p : 1);
   for (int e = tid; e < p * p; e += nt) {
     int i = e % p, j = e / p;
-    double v = (i <= j) ? G[e] : 0.0;
-    if (i == j) v += shift;
+    T v = (i <= j) ? G[e] : ST<T>::zero();
+    if (i == j) v = cvt<T, double>(re_(v) + shift);
     R[e] = v;
   }
   __syncthreads();
   for (int k = 0; k < p; ++k) {
-    double dkk = R[k + (int64_t)k * p];
+    double dkk = re_(R[k + (int64_t)k * p]);
     if (!(dkk > 1e-300)) {
       if (tid == 0) bad_s = 1;
       dkk = 1.0;
@@ -73,16 +75,16 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
     __syncthreads();
     for (int j = k + tid; j < p; j += nt) {
       if (j == k)
-        R[k + (int64_t)k * p] = rk;
+        R[k + (int64_t)k * p] = cvt<T, double>(rk);
       else
-        R[k + (int64_t)j * p] /= rk;
+        R[k + (int64_t)j * p] = scl(R[k + (int64_t)j * p], 1.0 / rk);
     }
     __threadfence_block();
     __syncthreads();
     int m = p - k - 1;
     for (int e = tid; e < m * m; e += nt) {
       int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (i <= j) R[i + (int64_t)j * p] -= R[k + (int64_t)i * p] * R[k + (int64_t)j * p];
+      if (i <= j) R[i + (int64_t)j * p] = sub(R[i + (int64_t)j * p], mul(conj_(R[k + (int64_t)i * p]), R[k + (int64_t)j * p]));
     }
     __threadfence_block();
     __syncthreads();
@@ -90,36 +92,37 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const double* __re
   if (tid == 0 && bad_s) *flag = 1;
   // R^-1: column j by back substitution, x_i = -(sum_{t=i+1..j} R(i,t) x_t) / R(i,i)
   for (int j = tid; j < p; j += nt) {
-    for (int i = j + 1; i < p; ++i) Ri[i + (int64_t)j * p] = 0.0;
-    Ri[j + (int64_t)j * p] = 1.0 / R[j + (int64_t)j * p];
+    for (int i = j + 1; i < p; ++i) Ri[i + (int64_t)j * p] = ST<T>::zero();
+    Ri[j + (int64_t)j * p] = inv_(R[j + (int64_t)j * p]);
     for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int t = i + 1; t <= j; ++t) acc += R[i + (int64_t)t * p] * Ri[t + (int64_t)j * p];
-      Ri[i + (int64_t)j * p] = -acc / R[i + (int64_t)i * p];
+      T acc = ST<T>::zero();
+      for (int t = i + 1; t <= j; ++t) acc = fma_(acc, R[i + (int64_t)t * p], Ri[t + (int64_t)j * p]);
+      Ri[i + (int64_t)j * p] = neg(mul(acc, inv_(R[i + (int64_t)i * p])));
     }
   }
   if (USE_LDS) {
     __syncthreads();
     for (int e = tid; e < p * p; e += nt) {
       int i = e % p, j = e / p;
-      Rg[e] = (i <= j) ? R[e] : 0.0;
+      Rg[e] = (i <= j) ? R[e] : ST<T>::zero();
       if (Ri != Rinv) Rinv[e] = Ri[e];
     }
   }
 }
 
-__global__ void upper_mul_kernel(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
-                                 int p) {
+template <typename T>
+__global__ void upper_mul_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int p) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= p * p) return;
   int i = e % p, j = e / p;
-  double s = 0.0;
-  for (int t = i; t <= j; ++t) s += A[i + t * p] * B[t + j * p];
-  C[e] = (i <= j) ? s : 0.0;
+  T s = ST<T>::zero();
+  for (int t = i; t <= j; ++t) s = fma_(s, A[i + t * p], B[t + j * p]);
+  C[e] = (i <= j) ? s : ST<T>::zero();
 }
 
-__global__ void put_block_kernel(double* __restrict__ H, int64_t ldh, int64_t r0, int64_t c0,
-                                 const double* __restrict__ X, int p) {
+template <typename T>
+__global__ void put_block_kernel(T* __restrict__ H, int64_t ldh, int64_t r0, int64_t c0, const T* __restrict__ X,
+                                 int p) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= p * p) return;
   int i = e % p, j = e / p;
@@ -127,29 +130,30 @@ __global__ void put_block_kernel(double* __restrict__ H, int64_t ldh, int64_t r0
 }
 
 // ---------------- shifted least squares ----------------
-__global__ void hls_init_kernel(HlsState st, const double* __restrict__ R0) {
+template <typename T>
+__global__ void hls_init_kernel(HlsState st, const T* __restrict__ R0) {
   const int s = blockIdx.y;
   const int64_t tot = st.ldr * st.p;
   zd* g = st.g + (int64_t)s * tot;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t i = e % st.ldr, c = e / st.ldr;
-    g[e] = (i < st.p) ? zd{R0[i + c * st.p], 0.0} : zd{0.0, 0.0};
+    g[e] = (i < st.p) ? cvt<zd, T>(R0[i + c * st.p]) : zd{0.0, 0.0};
   }
 }
 
 // one wave per (column c, shift s): load block column k, apply reflectors of blocks < k
-__global__ __launch_bounds__(64) void hls_apply_prev_kernel(HlsState st, const double* __restrict__ H, int64_t ldh,
-                                                            int k) {
+template <typename HT>
+__global__ __launch_bounds__(64) void hls_apply_prev_kernel(HlsState st, const HT* __restrict__ H, int64_t ldh, int k) {
   const int c = blockIdx.x, s = blockIdx.y, lane = threadIdx.x;
   const int p = st.p;
   const int64_t ldr = st.ldr;
   zd* Rs = st.R + (int64_t)s * ldr * st.mmax * p;
   zd* col = Rs + ((int64_t)k * p + c) * ldr;
   const int64_t rows = (int64_t)(k + 2) * p;
-  const double* hc = H + ((int64_t)k * p + c) * ldh;
+  const HT* hc = H + ((int64_t)k * p + c) * ldh;
   const double sh = st.shift_im[s];
   for (int64_t i = lane; i < ldr; i += 64) {
-    zd v{i < rows ? hc[i] : 0.0, 0.0};
+    zd v = i < rows ? cvt<zd, HT>(hc[i]) : zd{0.0, 0.0};
     if (i == (int64_t)k * p + c) v.im += sh;
     col[i] = v;
   }
@@ -274,8 +278,9 @@ __global__ __launch_bounds__(256) void hls_factor_kernel(HlsState st, int k, dou
 // which always map to its own slots, so a wave needs no barrier.
 __device__ inline int win_slots(int p) { return ((2 * p + 63) / 64) * 64; }
 
-__global__ __launch_bounds__(256) void hls_apply_prev_lds_kernel(HlsState st, const double* __restrict__ H,
-                                                                 int64_t ldh, int k) {
+template <typename HT>
+__global__ __launch_bounds__(256) void hls_apply_prev_lds_kernel(HlsState st, const HT* __restrict__ H, int64_t ldh,
+                                                                 int k) {
   extern __shared__ zd win_all[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int c = blockIdx.x * 4 + wave, s = blockIdx.y;
@@ -285,12 +290,12 @@ __global__ __launch_bounds__(256) void hls_apply_prev_lds_kernel(HlsState st, co
   zd* win = win_all + wave * W;
   const int64_t ldr = st.ldr;
   zd* col = st.R + (int64_t)s * ldr * st.mmax * p + ((int64_t)k * p + c) * ldr;
-  const double* hc = H + ((int64_t)k * p + c) * ldh;
+  const HT* hc = H + ((int64_t)k * p + c) * ldh;
   const double sh = st.shift_im[s];
   const int64_t diag = (int64_t)k * p + c;
   auto load_rows = [&](int64_t r0, int64_t r1) {  // rows [r0, r1) from H into the window
     for (int64_t r = r0 + ((lane - r0 % 64) + 64) % 64; r < r1; r += 64) {
-      zd v{hc[r], 0.0};
+      zd v = cvt<zd, HT>(hc[r]);
       if (r == diag) v.im += sh;
       win[r % W] = v;
     }
@@ -520,26 +525,40 @@ __global__ void hls_combine_real_kernel(const zd* __restrict__ Y, int64_t mp, in
   C[e] = s;
 }
 
+__global__ void hls_combine_cplx_kernel(const zd* __restrict__ Y, int64_t mp, int p, int nshift,
+                                        const double* __restrict__ coef, zd* __restrict__ C) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * p) return;
+  zd s{0.0, 0.0};
+  for (int q = 0; q < nshift; ++q) s = add(s, scl(Y[(int64_t)q * mp * p + e], coef[q]));
+  C[e] = s;
+}
+
 // ---------------- Rayleigh-Ritz (single workgroup) ----------------
-// cyclic Jacobi, round-robin parallel order, on a symmetric n x n matrix A
-// (col-major, global), accumulating V.  All threads of the block participate.
-__device__ void jacobi_block(double* A, double* V, int n, int max_sweeps, double tol) {
+// Cyclic Jacobi, round-robin parallel order, on a Hermitian n x n matrix A
+// (col-major), accumulating V.  All threads of the block participate.  For a
+// pair (p, q) with A(p, q) = r e^{i phi}, the unitary
+//   J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]   (columns p, q)
+// with the real rotation (c, s) of [[A(p,p), r], [r, A(q,q)]] zeroes A(p, q)
+// in J^H A J; for real A the phase is the sign of A(p, q).
+template <typename T>
+__device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m = n + (n & 1);
   const int half = m / 2;
   __shared__ double cs_s[512], sn_s[512];
+  __shared__ T ph_s[512];
   __shared__ int pp_s[512], qq_s[512];
   __shared__ double red[1024];
-  for (int e = tid; e < n * n; e += nt) V[e] = (e % n == e / n) ? 1.0 : 0.0;
+  for (int e = tid; e < n * n; e += nt) V[e] = (e % n == e / n) ? ST<T>::one() : ST<T>::zero();
   __threadfence_block();
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    // off-diagonal and total Frobenius norms
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += nt) {
-      double v = A[e];
-      tot += v * v;
-      if (e % n != e / n) off += v * v;
+      double v = abs2(A[e]);
+      tot += v;
+      if (e % n != e / n) off += v;
     }
     red[tid] = off;
     __syncthreads();
@@ -565,52 +584,58 @@ __device__ void jacobi_block(double* A, double* V, int n, int max_sweeps, double
         int bpos = m - 1 - k;
         int b = ((bpos - 1 + r) % (m - 1)) + 1;
         int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sn = 0.0;
+        T ph = ST<T>::one();
         if (q < n) {
-          double apq = A[p + (int64_t)q * n];
-          if (apq != 0.0) {
-            double tau = (A[q + (int64_t)q * n] - A[p + (int64_t)p * n]) / (2.0 * apq);
+          const T apq = A[p + (int64_t)q * n];
+          const double rr = sqrt(abs2(apq));
+          if (rr != 0.0) {
+            ph = scl(apq, 1.0 / rr);
+            double tau = (re_(A[q + (int64_t)q * n]) - re_(A[p + (int64_t)p * n])) / (2.0 * rr);
             double t;
             if (fabs(tau) > 1e150)
               t = 0.5 / tau;
             else
               t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sn = t * c;
           }
         }
         cs_s[k] = c;
-        sn_s[k] = s;
+        sn_s[k] = sn;
+        ph_s[k] = ph;
         pp_s[k] = p;
         qq_s[k] = q < n ? q : -1;
       }
       __syncthreads();
-      // columns of A and V
+      // columns of A and V: col_p <- c col_p - s conj(ph) col_q ; col_q <- s ph col_p + c col_q
       for (int e = tid; e < n * half; e += nt) {
         int i = e % n, k = e / n;
         int q = qq_s[k];
         if (q < 0) continue;
         int p = pp_s[k];
-        double c = cs_s[k], s = sn_s[k];
-        double ap = A[i + (int64_t)p * n], aq = A[i + (int64_t)q * n];
-        A[i + (int64_t)p * n] = c * ap - s * aq;
-        A[i + (int64_t)q * n] = s * ap + c * aq;
-        double vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
-        V[i + (int64_t)p * n] = c * vp - s * vq;
-        V[i + (int64_t)q * n] = s * vp + c * vq;
+        const double c = cs_s[k], sn = sn_s[k];
+        const T ph = ph_s[k], phc = conj_(ph);
+        T ap = A[i + (int64_t)p * n], aq = A[i + (int64_t)q * n];
+        A[i + (int64_t)p * n] = sub(scl(ap, c), scl(mul(phc, aq), sn));
+        A[i + (int64_t)q * n] = add(scl(mul(ph, ap), sn), scl(aq, c));
+        T vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
+        V[i + (int64_t)p * n] = sub(scl(vp, c), scl(mul(phc, vq), sn));
+        V[i + (int64_t)q * n] = add(scl(mul(ph, vp), sn), scl(vq, c));
       }
       __threadfence_block();
       __syncthreads();
-      // rows of A
+      // rows of A: row_p <- c row_p - s ph row_q ; row_q <- s conj(ph) row_p + c row_q
       for (int e = tid; e < n * half; e += nt) {
         int j = e % n, k = e / n;
         int q = qq_s[k];
         if (q < 0) continue;
         int p = pp_s[k];
-        double c = cs_s[k], s = sn_s[k];
-        double ap = A[p + (int64_t)j * n], aq = A[q + (int64_t)j * n];
-        A[p + (int64_t)j * n] = c * ap - s * aq;
-        A[q + (int64_t)j * n] = s * ap + c * aq;
+        const double c = cs_s[k], sn = sn_s[k];
+        const T ph = ph_s[k], phc = conj_(ph);
+        T ap = A[p + (int64_t)j * n], aq = A[q + (int64_t)j * n];
+        A[p + (int64_t)j * n] = sub(scl(ap, c), scl(mul(ph, aq), sn));
+        A[q + (int64_t)j * n] = add(scl(mul(phc, ap), sn), scl(aq, c));
       }
       __threadfence_block();
       __syncthreads();
@@ -619,64 +644,73 @@ __device__ void jacobi_block(double* A, double* V, int n, int max_sweeps, double
 }
 
 // Jacobi on an m x m matrix M (global, col-major): in LDS when it fits.
-__device__ void jacobi_maybe_lds(double* M, double* V, int m, double* lds, bool use_lds) {
+template <typename T>
+__device__ void jacobi_maybe_lds(T* M, T* V, int m, T* lds, bool use_lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   if (use_lds) {
     for (int e = tid; e < m * m; e += nt) lds[e] = M[e];
     __syncthreads();
-    jacobi_block(lds, V, m, 40, 1e-15);
+    jacobi_block<T>(lds, V, m, 40, 1e-15);
     __syncthreads();
     for (int e = tid; e < m * m; e += nt) M[e] = lds[e];
     __threadfence_block();
     __syncthreads();
   } else {
-    jacobi_block(M, V, m, 40, 1e-15);
+    jacobi_block<T>(M, V, m, 40, 1e-15);
   }
 }
 
-__global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restrict__ At, const double* __restrict__ Bt,
-                                                         int n, double tau_rank, double* __restrict__ theta,
-                                                         double* __restrict__ Cmat, int* k_out, double* work) {
-  extern __shared__ double rr_lds[];
-  const bool use_lds = n <= 128;
+template <typename T>
+constexpr int rr_lds_max() {
+  return ST<T>::cplx ? 90 : 128;
+}
+
+// Rank-revealing Rayleigh-Ritz: scale to unit diagonal of Bt, eigendecompose
+// Bt, keep directions with eigenvalue > tau_rank * max, reduce At on them and
+// eigendecompose the reduced Hermitian matrix.
+template <typename T>
+__global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ At, const T* __restrict__ Bt, int n,
+                                                         double tau_rank, double* __restrict__ theta,
+                                                         T* __restrict__ Cmat, int* k_out, T* work) {
+  extern __shared__ char rr_raw[];
+  T* rr_lds = (T*)rr_raw;
+  const bool use_lds = n <= rr_lds_max<T>();
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t nn = (int64_t)n * n;
-  double* As = work;
-  double* Bs = work + nn;
-  double* U = work + 2 * nn;
-  double* T = work + 3 * nn;
-  double* M1 = work + 4 * nn;
-  double* W = work + 5 * nn;
-  double* d = work + 6 * nn;
+  T* As = work;
+  T* Bs = work + nn;
+  T* U = work + 2 * nn;
+  T* Tm = work + 3 * nn;
+  T* M1 = work + 4 * nn;
+  T* W = work + 5 * nn;
+  double* d = (double*)(work + 6 * nn);
   double* sv = d + n;
   int* idx = (int*)(sv + n);
   int* rank = idx + n;
   __shared__ int k_s;
-  __shared__ double smax_s;
   for (int i = tid; i < n; i += nt) {
-    double b = Bt[i + (int64_t)i * n];
+    double b = re_(Bt[i + (int64_t)i * n]);
     d[i] = b > 0.0 ? sqrt(b) : 1.0;
   }
   __threadfence_block();
   __syncthreads();
   for (int64_t e = tid; e < nn; e += nt) {
     int i = (int)(e % n), j = (int)(e / n);
-    double s = 1.0 / (d[i] * d[j]);
-    // symmetrise
-    As[e] = 0.5 * (At[e] + At[j + (int64_t)i * n]) * s;
-    Bs[e] = 0.5 * (Bt[e] + Bt[j + (int64_t)i * n]) * s;
+    double sc = 0.5 / (d[i] * d[j]);
+    // Hermitian part
+    As[e] = scl(add(At[e], conj_(At[j + (int64_t)i * n])), sc);
+    Bs[e] = scl(add(Bt[e], conj_(Bt[j + (int64_t)i * n])), sc);
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds(Bs, U, n, rr_lds, use_lds);
+  jacobi_maybe_lds<T>(Bs, U, n, rr_lds, use_lds);
   __syncthreads();
-  for (int i = tid; i < n; i += nt) sv[i] = Bs[i + (int64_t)i * n];
+  for (int i = tid; i < n; i += nt) sv[i] = re_(Bs[i + (int64_t)i * n]);
   __threadfence_block();
   __syncthreads();
   if (tid == 0) {
     double mx = 0.0;
     for (int i = 0; i < n; ++i) mx = sv[i] > mx ? sv[i] : mx;
-    smax_s = mx;
     int k = 0;
     for (int i = 0; i < n; ++i)
       if (sv[i] > tau_rank * mx) idx[k++] = i;
@@ -685,45 +719,45 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restric
   __threadfence_block();
   __syncthreads();
   const int k = k_s;
-  // T(:, j) = U(:, idx_j) / sqrt(s_idx_j)   (n x k, ld n)
+  // Tm(:, j) = U(:, idx_j) / sqrt(s_idx_j)   (n x k, ld n)
   for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
     int i = (int)(e % n), j = (int)(e / n);
     int c = idx[j];
-    T[e] = U[i + (int64_t)c * n] / sqrt(sv[c]);
+    Tm[e] = scl(U[i + (int64_t)c * n], 1.0 / sqrt(sv[c]));
   }
   __threadfence_block();
   __syncthreads();
-  // M1 = As T (n x k); Ar = T^T M1 (k x k, ld n) into Bs
+  // M1 = As Tm (n x k); Ar = Tm^H M1 (k x k, ld k) into As
   for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
     int i = (int)(e % n), j = (int)(e / n);
-    double s = 0.0;
-    for (int t = 0; t < n; ++t) s += As[i + (int64_t)t * n] * T[t + (int64_t)j * n];
-    M1[e] = s;
+    T sacc = ST<T>::zero();
+    for (int t = 0; t < n; ++t) sacc = fma_(sacc, As[i + (int64_t)t * n], Tm[t + (int64_t)j * n]);
+    M1[e] = sacc;
   }
   __threadfence_block();
   __syncthreads();
   for (int64_t e = tid; e < (int64_t)k * k; e += nt) {
     int i = (int)(e % k), j = (int)(e / k);
-    double s = 0.0;
-    for (int t = 0; t < n; ++t) s += T[t + (int64_t)i * n] * M1[t + (int64_t)j * n];
-    As[i + (int64_t)j * k] = s;  // reuse As as k x k (ld k)
+    T sacc = ST<T>::zero();
+    for (int t = 0; t < n; ++t) sacc = fma_(sacc, conj_(Tm[t + (int64_t)i * n]), M1[t + (int64_t)j * n]);
+    As[i + (int64_t)j * k] = sacc;
   }
   __threadfence_block();
   __syncthreads();
   for (int64_t e = tid; e < (int64_t)k * k; e += nt) {
     int i = (int)(e % k), j = (int)(e / k);
-    Bs[e] = 0.5 * (As[i + (int64_t)j * k] + As[j + (int64_t)i * k]);
+    Bs[e] = scl(add(As[i + (int64_t)j * k], conj_(As[j + (int64_t)i * k])), 0.5);
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds(Bs, W, k, rr_lds, use_lds);
+  jacobi_maybe_lds<T>(Bs, W, k, rr_lds, use_lds);
   __syncthreads();
   // ascending order of the Ritz values
   for (int i = tid; i < k; i += nt) {
-    double ti = Bs[i + (int64_t)i * k];
+    double ti = re_(Bs[i + (int64_t)i * k]);
     int r = 0;
     for (int j = 0; j < k; ++j) {
-      double tj = Bs[j + (int64_t)j * k];
+      double tj = re_(Bs[j + (int64_t)j * k]);
       if (tj < ti || (tj == ti && j < i)) ++r;
     }
     rank[i] = r;
@@ -731,31 +765,31 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const double* __restric
   }
   __threadfence_block();
   __syncthreads();
-  // Cmat(:, rank_j) = D^-1 T W(:, j)
+  // Cmat(:, rank_j) = D^-1 Tm W(:, j)
   for (int64_t e = tid; e < (int64_t)n * k; e += nt) {
     int i = (int)(e % n), j = (int)(e / n);
-    double s = 0.0;
-    for (int t = 0; t < k; ++t) s += T[i + (int64_t)t * n] * W[t + (int64_t)j * k];
-    Cmat[i + (int64_t)rank[j] * n] = s / d[i];
+    T sacc = ST<T>::zero();
+    for (int t = 0; t < k; ++t) sacc = fma_(sacc, Tm[i + (int64_t)t * n], W[t + (int64_t)j * k]);
+    Cmat[i + (int64_t)rank[j] * n] = scl(sacc, 1.0 / d[i]);
   }
   if (tid == 0) *k_out = k;
 }
 
 constexpr int RN_ROWS = 512;
 
-__global__ void resid_partial_kernel(const double* __restrict__ AX, const double* __restrict__ BX,
-                                     const double* __restrict__ X, const double* __restrict__ theta, int64_t n, int k,
-                                     double* __restrict__ partial) {
+template <typename T>
+__global__ void resid_partial_kernel(const T* __restrict__ AX, const T* __restrict__ BX, const T* __restrict__ X,
+                                     const double* __restrict__ theta, int64_t n, int k, double* __restrict__ partial) {
   const int64_t r0 = (int64_t)blockIdx.x * RN_ROWS;
   const int64_t r1 = r0 + RN_ROWS < n ? r0 + RN_ROWS : n;
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double th = theta[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int64_t i = r0; i < r1; ++i) {
-      double bx = BX[i * k + c], ax = AX[i * k + c], x = X[i * k + c];
-      double r = ax - th * bx;
-      s1 = fma(r, r, s1);
-      s2 = fma(x, x, s2);
-      s3 = fma(bx, bx, s3);
+      T bx = BX[i * k + c], ax = AX[i * k + c], x = X[i * k + c];
+      T r = sub(ax, scl(bx, th));
+      s1 += abs2(r);
+      s2 += abs2(x);
+      s3 += abs2(bx);
     }
     double* o = partial + (int64_t)blockIdx.x * 3 * k;
     o[3 * c] = s1;
@@ -774,47 +808,53 @@ __global__ void resid_final_kernel(const double* __restrict__ partial, int nb, i
 
 }  // namespace
 
-void reduce_partials(double* out, int64_t ld_out, const double* partial, int S, int M, int N, bool add,
-                     hipStream_t s) {
+template <typename T>
+void reduce_partials(T* out, int64_t ld_out, const T* partial, int S, int M, int N, bool add, hipStream_t s) {
   int64_t MN = (int64_t)M * N;
   if (MN == 0) return;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, out, ld_out,
+  hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, out, ld_out,
                      partial, S, M, N, add ? 1 : 0);
 }
 
-void chol_upper_inv(const double* G, int p, double rel_shift, double* R, double* Rinv, int* flag, hipStream_t s) {
-  if (p <= 128) {
-    (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(sizeof(double) * p * p * (p <= 96 ? 2 : 1)));
+template <typename T>
+void chol_upper_inv(const T* G, int p, double rel_shift, T* R, T* Rinv, int* flag, hipStream_t s) {
+  const size_t one = sizeof(T) * (size_t)p * p;
+  const bool use_lds = one <= 160 * 1024 - 4096;
+  if (use_lds) {
+    const size_t lds = 2 * one <= 160 * 1024 - 4096 ? 2 * one : one;
+    (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL((chol_upper_inv_kernel<T, true>), dim3(1), dim3(1024), lds, s, G, p, rel_shift, R, Rinv, flag);
+  } else {
+    hipLaunchKernelGGL((chol_upper_inv_kernel<T, false>), dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
   }
-  if (p <= 128)
-    hipLaunchKernelGGL(chol_upper_inv_kernel<true>, dim3(1), dim3(1024), sizeof(double) * p * p * (p <= 96 ? 2 : 1),
-                       s, G, p, rel_shift, R, Rinv, flag);
-  else
-    hipLaunchKernelGGL(chol_upper_inv_kernel<false>, dim3(1), dim3(1024), 0, s, G, p, rel_shift, R, Rinv, flag);
 }
 
-void upper_mul(const double* A, const double* B, double* C, int p, hipStream_t s) {
-  hipLaunchKernelGGL(upper_mul_kernel, dim3((p * p + 255) / 256), dim3(256), 0, s, A, B, C, p);
+template <typename T>
+void upper_mul(const T* A, const T* B, T* C, int p, hipStream_t s) {
+  hipLaunchKernelGGL(upper_mul_kernel<T>, dim3((p * p + 255) / 256), dim3(256), 0, s, A, B, C, p);
 }
 
-void put_block(double* H, int64_t ldh, int64_t r0, int64_t c0, const double* X, int p, hipStream_t s) {
-  hipLaunchKernelGGL(put_block_kernel, dim3((p * p + 255) / 256), dim3(256), 0, s, H, ldh, r0, c0, X, p);
+template <typename T>
+void put_block(T* H, int64_t ldh, int64_t r0, int64_t c0, const T* X, int p, hipStream_t s) {
+  hipLaunchKernelGGL(put_block_kernel<T>, dim3((p * p + 255) / 256), dim3(256), 0, s, H, ldh, r0, c0, X, p);
 }
 
-void hls_init(const HlsState& st, const double* R0, hipStream_t s) {
-  hipLaunchKernelGGL(hls_init_kernel, dim3(64, st.nshift), dim3(256), 0, s, st, R0);
+template <typename T>
+void hls_init(const HlsState& st, const T* R0, hipStream_t s) {
+  hipLaunchKernelGGL(hls_init_kernel<T>, dim3(64, st.nshift), dim3(256), 0, s, st, R0);
 }
 
-void hls_step(const HlsState& st, const double* H, int64_t ldh, int k, double* res, hipStream_t s) {
+template <typename T>
+void hls_step(const HlsState& st, const T* H, int64_t ldh, int k, double* res, hipStream_t s) {
   if (st.p > 128) {
-    hipLaunchKernelGGL(hls_apply_prev_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, H, ldh, k);
+    hipLaunchKernelGGL(hls_apply_prev_kernel<T>, dim3(st.p, st.nshift), dim3(64), 0, s, st, H, ldh, k);
     hipLaunchKernelGGL(hls_factor_kernel, dim3(st.nshift), dim3(256), 0, s, st, k, res);
     return;
   }
   const size_t lds = sizeof(zd) * 4 * (size_t)(((2 * st.p + 63) / 64) * 64);
   const dim3 g4((st.p + 3) / 4, st.nshift);
-  hipLaunchKernelGGL(hls_apply_prev_lds_kernel, g4, dim3(256), lds, s, st, H, ldh, k);
+  hipLaunchKernelGGL(hls_apply_prev_lds_kernel<T>, g4, dim3(256), lds, s, st, H, ldh, k);
   if (st.p <= 32)
     hipLaunchKernelGGL(hls_factor_reg_kernel<32>, dim3(st.nshift), dim3(256), 0, s, st, k);
   else if (st.p <= 64)
@@ -830,25 +870,46 @@ void hls_backsolve(const HlsState& st, int m, zd* Y, hipStream_t s) {
   hipLaunchKernelGGL(hls_backsolve_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, m, Y);
 }
 
-void hls_combine_real(const zd* Y, int m, int p, int nshift, const double* coef, double* C, hipStream_t s) {
+void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, double* C, hipStream_t s) {
   int64_t mp = (int64_t)m * p;
   hipLaunchKernelGGL(hls_combine_real_kernel, dim3((unsigned)((mp * p + 255) / 256)), dim3(256), 0, s, Y, mp, p,
                      nshift, coef, C);
 }
-
-void rr_reduce(const double* At, const double* Bt, int n, double tau_rank, double* theta, double* Cmat, int* k_out,
-               double* work, hipStream_t s) {
-  size_t lds = n <= 128 ? sizeof(double) * n * n : 0;
-  if (lds) (void)hipFuncSetAttribute((const void*)rr_reduce_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(rr_reduce_kernel, dim3(1), dim3(1024), lds, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
+void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, zd* C, hipStream_t s) {
+  int64_t mp = (int64_t)m * p;
+  hipLaunchKernelGGL(hls_combine_cplx_kernel, dim3((unsigned)((mp * p + 255) / 256)), dim3(256), 0, s, Y, mp, p,
+                     nshift, coef, C);
 }
 
-void resid_norms(const double* AX, const double* BX, const double* X, const double* theta, int64_t n, int k,
-                 double* partial, double* out, hipStream_t s) {
+template <typename T>
+void rr_reduce(const T* At, const T* Bt, int n, double tau_rank, double* theta, T* Cmat, int* k_out, T* work,
+               hipStream_t s) {
+  const size_t lds = n <= rr_lds_max<T>() ? sizeof(T) * (size_t)n * n : 0;
+  if (lds) (void)hipFuncSetAttribute((const void*)rr_reduce_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(rr_reduce_kernel<T>, dim3(1), dim3(1024), lds, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
+}
+
+template <typename T>
+void resid_norms(const T* AX, const T* BX, const T* X, const double* theta, int64_t n, int k, double* partial,
+                 double* out, hipStream_t s) {
   int nb = (int)((n + RN_ROWS - 1) / RN_ROWS);
   if (nb == 0 || k == 0) return;
-  hipLaunchKernelGGL(resid_partial_kernel, dim3(nb), dim3(128), 0, s, AX, BX, X, theta, n, k, partial);
+  hipLaunchKernelGGL(resid_partial_kernel<T>, dim3(nb), dim3(128), 0, s, AX, BX, X, theta, n, k, partial);
   hipLaunchKernelGGL(resid_final_kernel, dim3((3 * k + 127) / 128), dim3(128), 0, s, partial, nb, 3 * k, out);
 }
+
+#define KRYLOV_INST(T)                                                                                        \
+  template void reduce_partials<T>(T*, int64_t, const T*, int, int, int, bool, hipStream_t);                 \
+  template void chol_upper_inv<T>(const T*, int, double, T*, T*, int*, hipStream_t);                         \
+  template void upper_mul<T>(const T*, const T*, T*, int, hipStream_t);                                      \
+  template void put_block<T>(T*, int64_t, int64_t, int64_t, const T*, int, hipStream_t);                     \
+  template void hls_init<T>(const HlsState&, const T*, hipStream_t);                                         \
+  template void hls_step<T>(const HlsState&, const T*, int64_t, int, double*, hipStream_t);                   \
+  template void rr_reduce<T>(const T*, const T*, int, double, double*, T*, int*, T*, hipStream_t);            \
+  template void resid_norms<T>(const T*, const T*, const T*, const double*, int64_t, int, double*, double*, \
+                               hipStream_t);
+KRYLOV_INST(double)
+KRYLOV_INST(zd)
+#undef KRYLOV_INST
 
 }  // namespace zolo

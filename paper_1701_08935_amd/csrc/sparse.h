@@ -9,6 +9,9 @@ namespace zolo {
 void spmm_real(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* a, const double* b,
                const double* X, int64_t ldx, int p, double* Ya, int64_t ldya, double* Yb, int64_t ldyb,
                hipStream_t s);
+// complex Hermitian pencils: the same with complex values and blocks
+void spmm_cplx(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd* a, const zd* b, const zd* X,
+               int64_t ldx, int p, zd* Ya, int64_t ldya, zd* Yb, int64_t ldyb, hipStream_t s);
 // R = T - (A - sigma B) X  with X complex, T real (refinement residual, FP64).
 void spmm_shift_resid(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* a, const double* b,
                       double sr, double si, const zd* X, const double* T, int64_t ldt, int p, zd* R, hipStream_t s);
@@ -20,8 +23,14 @@ void rows_scatter(T* dst, int64_t ldd, const T* src, int64_t lds, const int32_t*
                   hipStream_t s);
 // W = alpha V (real)
 void scale_copy(double* W, int64_t ldw, const double* V, int64_t ldv, double alpha, int64_t n, int p, hipStream_t s);
+void scale_copy(zd* W, int64_t ldw, const zd* V, int64_t ldv, double alpha, int64_t n, int p, hipStream_t s);
+// W += w X + conj(w) Xc  (complex pencils: a pole and its conjugate, X and Xc contiguous N x p)
+void axpy_pair(zd* W, int64_t ldw, const zd* X, const zd* Xc, double wr, double wi, int64_t n, int p, hipStream_t s);
 // W += 2 * Re(w * X)  (X complex, contiguous N x p)
 void axpy_re(double* W, int64_t ldw, const zd* X, double wr, double wi, int64_t n, int p, hipStream_t s);
+// dst = conj(src)
+template <typename T>
+void conj_copy(T* dst, const T* src, int64_t n, hipStream_t s);
 // X += cvt(D)
 void add_lowp(zd* X, const zf* D, int64_t n, hipStream_t s);
 void add_same(zd* X, const zd* D, int64_t n, hipStream_t s);

@@ -30,6 +30,26 @@ __global__ void spmm_real_kernel(int64_t n, const int64_t* __restrict__ rp, cons
   Ya[i * ldya + c] = sa;
 }
 
+// complex Hermitian pencils: complex values, complex blocks
+__global__ void spmm_cplx_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                 const zd* __restrict__ a, const zd* __restrict__ b, const zd* __restrict__ X,
+                                 int64_t ldx, int p, zd* __restrict__ Ya, int64_t ldya, zd* __restrict__ Yb,
+                                 int64_t ldyb) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * p) return;
+  int64_t i = e / p;
+  int c = (int)(e % p);
+  zd sa{0.0, 0.0}, sb{0.0, 0.0};
+  const int64_t e0 = rp[i], e1 = rp[i + 1];
+  for (int64_t q = e0; q < e1; ++q) {
+    const zd x = X[(int64_t)ci[q] * ldx + c];
+    sa = fma_(sa, a[q], x);
+    if (Yb) sb = fma_(sb, b[q], x);
+  }
+  Ya[i * ldya + c] = sa;
+  if (Yb) Yb[i * ldyb + c] = sb;
+}
+
 __global__ void spmm_shift_resid_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                         const double* __restrict__ a, const double* __restrict__ b, double sr,
                                         double si, const zd* __restrict__ X, const double* __restrict__ T,
@@ -75,6 +95,34 @@ __global__ void scale_copy_kernel(double* __restrict__ W, int64_t ldw, const dou
   int64_t i = e / p;
   int c = (int)(e % p);
   W[i * ldw + c] = alpha * V[i * ldv + c];
+}
+
+__global__ void scale_copy_cplx_kernel(zd* __restrict__ W, int64_t ldw, const zd* __restrict__ V, int64_t ldv,
+                                       double alpha, int64_t n, int p) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * p) return;
+  int64_t i = e / p;
+  int c = (int)(e % p);
+  W[i * ldw + c] = scl(V[i * ldv + c], alpha);
+}
+
+// W += w X + conj(w) Xc  (the pole and its conjugate, complex pencils)
+__global__ void axpy_pair_kernel(zd* __restrict__ W, int64_t ldw, const zd* __restrict__ X, const zd* __restrict__ Xc,
+                                 double wr, double wi, int64_t n, int p) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * p) return;
+  int64_t i = e / p;
+  int c = (int)(e % p);
+  const zd x = X[e], y = Xc[e];
+  zd& o = W[i * ldw + c];
+  o.re += wr * x.re - wi * x.im + wr * y.re + wi * y.im;
+  o.im += wr * x.im + wi * x.re + wr * y.im - wi * y.re;
+}
+
+template <typename T>
+__global__ void conj_copy_kernel(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = conj_(src[e]);
 }
 
 __global__ void axpy_re_kernel(double* __restrict__ W, int64_t ldw, const zd* __restrict__ X, double wr, double wi,
@@ -136,6 +184,36 @@ __global__ void colnorm_final_kernel(const double* __restrict__ partial, int nb,
 inline unsigned nblk(int64_t tot) { return (unsigned)((tot + 255) / 256); }
 
 }  // namespace
+
+template <typename T>
+void conj_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(conj_copy_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, src, n);
+}
+template void conj_copy<zd>(zd*, const zd*, int64_t, hipStream_t);
+template void conj_copy<zf>(zf*, const zf*, int64_t, hipStream_t);
+
+void spmm_cplx(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd* a, const zd* b, const zd* X,
+               int64_t ldx, int p, zd* Ya, int64_t ldya, zd* Yb, int64_t ldyb, hipStream_t s) {
+  int64_t tot = n * p;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(spmm_cplx_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rowptr, colind, a, b,
+                     X, ldx, p, Ya, ldya, Yb, ldyb);
+}
+
+void scale_copy(zd* W, int64_t ldw, const zd* V, int64_t ldv, double alpha, int64_t n, int p, hipStream_t s) {
+  int64_t tot = n * p;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(scale_copy_cplx_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw, V, ldv,
+                     alpha, n, p);
+}
+
+void axpy_pair(zd* W, int64_t ldw, const zd* X, const zd* Xc, double wr, double wi, int64_t n, int p, hipStream_t s) {
+  int64_t tot = n * p;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(axpy_pair_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, W, ldw, X, Xc, wr, wi, n,
+                     p);
+}
 
 void spmm_real(int64_t n, const int64_t* rp, const int32_t* ci, const double* a, const double* b, const double* X,
                int64_t ldx, int p, double* Ya, int64_t ldya, double* Yb, int64_t ldyb, hipStream_t s) {
