@@ -38,6 +38,10 @@ WORKLOADS = {
     "c2": {"grid": 64, "n_lambda": 64, "n_ss": 96, "precision": 1},
     "m32": {"grid": 32, "n_lambda": 64, "n_ss": 96, "precision": 0},
     "m32x": {"grid": 32, "n_lambda": 64, "n_ss": 96, "precision": 1},
+    # complex Hermitian 27-point Peierls pencils (the complex-pencil workload at a size one oracle
+    # window can be computed for)
+    "c3s": {"grid": 32, "n_lambda": 64, "n_ss": 96, "precision": 0, "gen": "grid27p"},
+    "c3t": {"grid": 24, "n_lambda": 64, "n_ss": 96, "precision": 0, "gen": "grid27p"},
 }
 
 
@@ -54,8 +58,9 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True):
 
     wl = WORKLOADS[name]
     n = wl["grid"]
-    w = json.load(open(os.path.join(ROOT, "tests", "golden", f"window_grid7_{n}.json")))
-    gp = pencils.grid7(n)
+    gen = wl.get("gen", "grid7")
+    w = json.load(open(os.path.join(ROOT, "tests", "golden", f"window_{gen}_{n}.json")))
+    gp = getattr(pencils, gen)(n)
     log(f"[bench] {name}: grid {n}^3 N={gp.n} nnz={gp.nnz}")
     ctx = z.Context(0)
     t0 = time.perf_counter()
@@ -63,7 +68,7 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True):
     t_sym = time.perf_counter() - t0
     info = P.info()
     log(f"[bench] symbolic {t_sym:.2f}s {info}")
-    Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, wl["n_ss"], seed=2)).to("cuda:0")
+    Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, wl["n_ss"], seed=2, complex_=gen == "grid27p")).to("cuda:0")
     opts = z.opts_from_window(w, r1=r1, r2=0, n_ss=wl["n_ss"], precision=wl["precision"])
     lat = []
     last = None
@@ -299,9 +304,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if wl["precision"] == 0 else "c64-factors+f64",
+        "dtype": ("c128" if wl.get("gen") == "grid27p" else "f64") if wl["precision"] == 0 else "c64-factors+f64",
         "data": "synthetic",
-        "config": {"workload": f"grid7 {wl['grid']}^3 stencil pencil (N={res['n']}), mid-spectrum window of "
+        "config": {"workload": f"{wl.get('gen', 'grid7')} {wl['grid']}^3 stencil pencil (N={res['n']}), mid-spectrum window of "
                                f"{wl['n_lambda']} eigenvalues, block {wl['n_ss']}, r1={st['r1']} factored shifts, "
                                f"r2={st['r2']}",
                    "N": res["n"], "nnz": res["nnz"], "n_lambda": wl["n_lambda"], "n_ss": wl["n_ss"],

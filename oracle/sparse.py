@@ -49,7 +49,8 @@ def count_interval(A, B, a: float, b: float) -> int:
 
 
 def window_near(A, B, sigma0: float, k: int, tol: float = 0.0):
-    """The k eigenvalues of (A, B) nearest sigma0 (ascending) and their vectors.
+    """The k eigenvalues of (A, B) nearest sigma0 (ascending) and their vectors
+    (eigenvalues as the Rayleigh quotients of the returned vectors).
 
     Shift-invert Lanczos (ARPACK) with (A - sigma0 B)^-1 applied through the
     symmetric-mode minimum-degree SuperLU factorization used for the inertia
@@ -57,8 +58,14 @@ def window_near(A, B, sigma0: float, k: int, tol: float = 0.0):
     """
     lu = _splu_sym(sp.csc_matrix(A - sigma0 * B))
     n = A.shape[0]
-    op = spla.LinearOperator((n, n), matvec=lambda x: lu.solve(np.asarray(x, dtype=np.float64)), dtype=np.float64)
+    dt = np.result_type(A.dtype, B.dtype, np.float64)  # complex Hermitian pencils stay complex
+    op = spla.LinearOperator((n, n), matvec=lambda x: lu.solve(np.asarray(x, dtype=dt)), dtype=dt)
     w, X = spla.eigsh(A, k=k, M=B, sigma=sigma0, which="LM", tol=tol, OPinv=op)
+    # Rayleigh quotients of the Lanczos vectors: their error is quadratic in the
+    # vectors' error, so they stay exact to rounding even when the unpivoted
+    # shift-invert solves are only accurate to ~1e-10 (indefinite A - sigma0 B)
+    AX, BX = A @ X, B @ X
+    w = np.real(np.einsum("ij,ij->j", X.conj(), AX) / np.einsum("ij,ij->j", X.conj(), BX))
     order = np.argsort(w)
     return w[order], X[:, order]
 

@@ -2192,13 +2192,15 @@ namespace zolo {
 int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision) {
   const int64_t n = P->n;
   const int64_t elem = precision == ZOLO_PREC_FP64 ? 16 : 8;
-  const int64_t factors = (int64_t)r1 * (P->panel_total + P->inv_total + n) * elem;
-  const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + P->inv_scratch) * elem;
+  const int64_t lu = P->cplx() ? 2 : 1;  // LU: two panels and inverses; K^-1 and K^-H solves
+  const int64_t vb = P->cplx() ? 16 : 8;  // bytes per block entry
+  const int64_t factors = (int64_t)r1 * lu * (P->panel_total + P->inv_total + n) * elem;
+  const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + lu * P->inv_scratch) * elem;
   const int64_t p = nss;
-  const int64_t solve = (int64_t)r1 * (6 * n * p) * elem;             // W, U, Xb, t, Y, X of the solve program
-  const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * 8  // basis, W, T1, Tb
-                         + 2 * (int64_t)r1 * n * p * 16;                   // per-pole solutions and residuals
-  const int64_t subspace = 8 * n * p * 8;                                   // Q, Y, AY, BY, X, AX, BX, result
+  const int64_t solve = (int64_t)r1 * lu * (6 * n * p) * elem;         // W, U, Xb, t, Y, X of the solve program
+  const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * vb  // basis, W, T1, Tb
+                         + 2 * (int64_t)r1 * lu * n * p * 16;              // per-pole solutions and residuals
+  const int64_t subspace = 8 * n * p * vb;                                  // Q, Y, AY, BY, X, AX, BX, result
   const int64_t total = factors + std::max(factor_tmp, solve + krylov) + subspace;
   return total + total / 10 + ((int64_t)64 << 20);
 }

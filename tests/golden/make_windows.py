@@ -7,6 +7,7 @@ from the repository root:
     python tests/golden/make_windows.py c1          # 64^3 grid, shift-invert Lanczos
     python tests/golden/make_windows.py small       # the small parity pencils
     python tests/golden/make_windows.py serving     # eigenvalue clusters of the serving pencils
+    python tests/golden/make_windows.py c3 32       # complex Hermitian 27-point Peierls pencil, 32^3
 
 Each fixture stores the workload recipe (grid, seeds), the window of
 eigenvalues (ascending, the oracle's values) and the eigengaps
@@ -88,6 +89,38 @@ def c1_window(n=64, n_lambda=64, sigma0=6.0, k=80, verify=True):
     _dump(f"window_grid7_{n}.json", w)
 
 
+def c3_window(n=32, n_lambda=64, sigma0=0.0, k=80, verify=True):
+    """Complex Hermitian 27-point Peierls pencil: mid-spectrum window of n_lambda
+    eigenvalues near sigma0 by shift-invert Lanczos, count checked by inertia."""
+    p = pencils.grid27p(n)
+    A, B = p.scipy()
+    t = time.time()
+    lam, _ = window_near(A.tocsc(), B.tocsc(), sigma0, k)
+    t_eig = time.time() - t
+    i0 = (k - n_lambda) // 2
+    w = pencils.window_from_eigenvalues(lam, i0, n_lambda)
+    cnt, t_cnt = None, None
+    if verify:
+        t = time.time()
+        cnt = count_interval(A, B, w["a"], w["b"])
+        t_cnt = time.time() - t
+    w.update(
+        {
+            "workload": f"grid27p {n}^3 complex Hermitian mid-spectrum window near {sigma0}",
+            "grid": [n, n, n],
+            "seed_v": 0,
+            "seed_theta": 1,
+            "sigma0": sigma0,
+            "eigenvalues": [float(x) for x in lam[i0 : i0 + n_lambda]],
+            "neighbours": [float(x) for x in lam],
+            "inertia_count": cnt,
+            "source": "oracle.sparse.window_near (shift-invert Lanczos, ARPACK) + Sylvester inertia count",
+            "seconds": {"eigsh": t_eig, "inertia": t_cnt},
+        }
+    )
+    _dump(f"window_grid27p_{n}.json", w)
+
+
 SERVING_GRIDS = [16, 20, 24, 28, 32]
 SERVING_CENTERS = [4.0, 5.5, 7.0, 8.5]
 SERVING_K = 150
@@ -124,6 +157,8 @@ if __name__ == "__main__":
         c1_window()
     elif what == "serving":
         serving_clusters()
+    elif what == "c3":
+        c3_window(n=int(sys.argv[2]) if len(sys.argv) > 2 else 32)
     elif what.startswith("grid"):
         n = int(what[4:])
         c1_window(n=n, verify=True)

@@ -136,3 +136,43 @@ def test_complex_solve_window(ctx, pencil7, start, count):
     assert np.iscomplexobj(Xg)
     assert np.max(rel_residuals(A, B, eig, Xg, inf_norm(A), inf_norm(B))) <= 1e-8
     assert b_orthonormality(B, Xg) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [24, 32])
+def test_complex_window_stored(ctx, n):
+    """The complex workload pencils (grid27p n^3, window of 64 near 0, block 96) against the
+    oracle's stored window: count = inertia count, eigenvalues 1e-10, residual 1e-8,
+    B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors."""
+    import json
+    import os
+
+    from .conftest import golden
+
+    path = golden(f"window_grid27p_{n}.json")
+    if not os.path.exists(path):
+        pytest.skip("window fixture not generated")
+    w = json.load(open(path))
+    say(f"complex zolo_solve grid27p {n}^3 window 64 block 96")
+    gp = pencils.grid27p(n)
+    A, B = gp.scipy()
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=64)
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=96)
+    Q0 = pencils.gaussian_block(gp.n, 96, seed=2, complex_=True)
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, o, Q0=_dev(Q0))
+    say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e}")
+    assert rc == 0 and len(eig) == w["inertia_count"] == 64
+    eig = np.array(eig)
+    ref = np.array(w["eigenvalues"])
+    assert np.max(np.abs(eig - ref) / np.abs(ref)) <= 1e-10
+    X = vec.cpu().numpy()
+    assert np.max(rel_residuals(A, B, eig, X, inf_norm(A), inf_norm(B))) <= 1e-8
+    assert b_orthonormality(B, X) <= 1e-10
+    R = A @ X - (B @ X) * eig[None, :]
+    d = B.diagonal().real
+    lmin_b = float(np.min(d - (np.asarray(abs(B).sum(axis=1)).ravel() - np.abs(d))))
+    allv = np.sort(np.concatenate([ref, np.array(w["neighbours"])]))
+    for i in range(len(eig)):
+        others = allv[np.abs(allv - ref[i]) > 0]
+        gap = np.min(np.abs(others - eig[i]))
+        kt = float(np.real(np.vdot(R[:, i], R[:, i]))) / float(np.real(np.vdot(X[:, i], B @ X[:, i]))) / lmin_b / gap
+        assert abs(eig[i] - ref[i]) <= kt + 1e-13 * abs(ref[i]), (i, abs(eig[i] - ref[i]), kt)

@@ -10,7 +10,7 @@ import scipy.linalg as sla
 import pencils
 from oracle.dense import count_in, exact_filter, exact_G, jacobi_eigh, pencil_eigh_jacobi, pencil_eigh_lapack, shifted_solve
 from oracle.filt import FilterPlan
-from oracle.sparse import HybridFilterCPU, count_interval, inertia_neg, kato_temple, zoloeig_cpu
+from oracle.sparse import HybridFilterCPU, count_interval, inertia_neg, kato_temple, window_near, zoloeig_cpu
 from oracle.subspace import alg1_exact, b_orthonormality, e_lambda_x, inf_norm, rayleigh_ritz, rel_residuals
 
 from .conftest import golden
@@ -196,3 +196,17 @@ def test_serving_queries_windows_are_consistent():
         i = int(np.searchsorted(lam, ev[0]))
         assert np.array_equal(lam[i : i + len(ev)], ev)
         assert lam[i - 1] == w["a_minus"] and lam[i + len(ev)] == w["b_plus"]
+
+
+def test_window_near_and_inertia_complex_hermitian():
+    """Shift-invert Lanczos windows and Sylvester inertia counts on a complex
+    Hermitian (Peierls) pencil agree with dense LAPACK (library special case)."""
+    gp = pencils.grid27p(5, ny=6, nz=4)
+    A, B = gp.scipy()
+    lam, _ = pencil_eigh_lapack(A.toarray(), B.toarray())
+    w, X = window_near(A.tocsc(), B.tocsc(), 0.3, 12)
+    idx = np.argsort(np.abs(lam - 0.3))[:12]
+    assert np.max(np.abs(np.sort(lam[idx]) - w)) < 1e-10
+    assert np.iscomplexobj(X)
+    a, b = -1.0, 1.5
+    assert count_interval(A, B, a, b) == count_in(lam, a, b)
