@@ -49,7 +49,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(name, steps, warmup, leaf, r1, profile=True):
+def run_gpu(name, steps, warmup, leaf, r1, profile=True, tol_refine=0.0):
     import numpy as np
     import torch
 
@@ -70,6 +70,8 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True):
     log(f"[bench] symbolic {t_sym:.2f}s {info}")
     Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, wl["n_ss"], seed=2, complex_=gen == "grid27p")).to("cuda:0")
     opts = z.opts_from_window(w, r1=r1, r2=0, n_ss=wl["n_ss"], precision=wl["precision"])
+    if tol_refine > 0:
+        opts.tol_refine = tol_refine
     lat = []
     last = None
     for it in range(warmup + steps):
@@ -267,6 +269,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--tol-refine", type=float, default=0.0, help="mixed precision: inner refinement tolerance")
     ap.add_argument("--serving-queries", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=6.0, help="Poisson arrival rate, queries/s")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -287,7 +290,7 @@ def main():
         print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
               "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    res = run_gpu(args.config, args.steps, args.warmup, args.leaf, args.r1)
+    res = run_gpu(args.config, args.steps, args.warmup, args.leaf, args.r1, tol_refine=args.tol_refine)
     lat = res["lat"]
     ms = 1e3 * sum(lat) / len(lat)
     value = res["verified"] / (ms * 1e-3)
@@ -325,7 +328,8 @@ def main():
         "profile": res["prof"],
     }
     if args.config in ("c1", "m32") and not args.no_mixed:
-        mres = run_gpu("c2" if args.config == "c1" else "m32x", max(1, args.steps - 1), 1, args.leaf, args.r1, profile=False)
+        mres = run_gpu("c2" if args.config == "c1" else "m32x", max(1, args.steps - 1), 1, args.leaf, args.r1, profile=False,
+                       tol_refine=args.tol_refine)
         mms = 1e3 * sum(mres["lat"]) / len(mres["lat"])
         mval = mres["verified"] / (mms * 1e-3)
         out["mixed"] = {"value": mval, "ms_per_step": mms, "speedup_vs_fp64": mval / value if value else None,

@@ -546,10 +546,12 @@ __device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int m = n + (n & 1);
   const int half = m / 2;
-  __shared__ double cs_s[512], sn_s[512];
-  __shared__ T ph_s[512];
-  __shared__ int pp_s[512], qq_s[512];
-  __shared__ double red[1024];
+  __shared__ double cs_s[256], sn_s[256];
+  __shared__ T ph_s[256];
+  __shared__ int pp_s[256], qq_s[256];
+  __shared__ double red[2][16];
+  __shared__ int rot_s;  // a rotation was applied in the current sweep
+  if (tid == 0) rot_s = 1;
   for (int e = tid; e < n * n; e += nt) V[e] = (e % n == e / n) ? ST<T>::one() : ST<T>::zero();
   __threadfence_block();
   __syncthreads();
@@ -560,23 +562,25 @@ __device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
       tot += v;
       if (e % n != e / n) off += v;
     }
-    red[tid] = off;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    if ((tid & 63) == 0) {
+      red[0][tid >> 6] = off;
+      red[1][tid >> 6] = tot;
     }
-    off = red[0];
     __syncthreads();
-    red[tid] = tot;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+    off = 0.0;
+    tot = 0.0;
+    for (int w = 0; w < nt / 64; ++w) {
+      off += red[0][w];
+      tot += red[1][w];
     }
-    tot = red[0];
     __syncthreads();
-    if (off <= tol * tol * tot || tot == 0.0) break;
+    if (off <= tol * tol * tot || tot == 0.0 || rot_s == 0) break;
+    const double thr = tol * sqrt(tot);
+    __syncthreads();
+    if (tid == 0) rot_s = 0;
+    __syncthreads();
     for (int r = 0; r < m - 1; ++r) {
       if (tid < half) {
         int k = tid;
@@ -589,7 +593,11 @@ __device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
         if (q < n) {
           const T apq = A[p + (int64_t)q * n];
           const double rr = sqrt(abs2(apq));
-          if (rr != 0.0) {
+          // rotate only while |a_pq| is above tol ||A||_F (eigenvalues to absolute accuracy
+          // tol ||A||, which is what the rank decision and the Ritz values need); a sweep
+          // with no rotation ends the iteration
+          if (rr > 1e-300 && rr > thr) {
+            rot_s = 1;
             ph = scl(apq, 1.0 / rr);
             double tau = (re_(A[q + (int64_t)q * n]) - re_(A[p + (int64_t)p * n])) / (2.0 * rr);
             double t;
@@ -644,15 +652,22 @@ __device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
 }
 
 // Jacobi on an m x m matrix M (global, col-major): in LDS when it fits.
+// lds holds lds_elems values: M (and V when 2 m^2 fit) stay there during the sweeps
 template <typename T>
-__device__ void jacobi_maybe_lds(T* M, T* V, int m, T* lds, bool use_lds) {
+__device__ void jacobi_maybe_lds(T* M, T* V, int m, T* lds, int64_t lds_elems) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (use_lds) {
-    for (int e = tid; e < m * m; e += nt) lds[e] = M[e];
+  const int64_t mm = (int64_t)m * m;
+  if (mm <= lds_elems) {
+    const bool vl = 2 * mm <= lds_elems;
+    T* Vw = vl ? lds + mm : V;
+    for (int e = tid; e < mm; e += nt) lds[e] = M[e];
     __syncthreads();
-    jacobi_block<T>(lds, V, m, 40, 1e-15);
+    jacobi_block<T>(lds, Vw, m, 40, 1e-15);
     __syncthreads();
-    for (int e = tid; e < m * m; e += nt) M[e] = lds[e];
+    for (int e = tid; e < mm; e += nt) {
+      M[e] = lds[e];
+      if (vl) V[e] = Vw[e];
+    }
     __threadfence_block();
     __syncthreads();
   } else {
@@ -660,10 +675,8 @@ __device__ void jacobi_maybe_lds(T* M, T* V, int m, T* lds, bool use_lds) {
   }
 }
 
-template <typename T>
-constexpr int rr_lds_max() {
-  return ST<T>::cplx ? 90 : 128;
-}
+// dynamic LDS of the Rayleigh-Ritz kernel (the static part of jacobi_block is ~13 KB)
+constexpr size_t kRrLdsBytes = 144 * 1024;
 
 // Rank-revealing Rayleigh-Ritz: scale to unit diagonal of Bt, eigendecompose
 // Bt, keep directions with eigenvalue > tau_rank * max, reduce At on them and
@@ -674,7 +687,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
                                                          T* __restrict__ Cmat, int* k_out, T* work) {
   extern __shared__ char rr_raw[];
   T* rr_lds = (T*)rr_raw;
-  const bool use_lds = n <= rr_lds_max<T>();
+  const int64_t lds_elems = (int64_t)(kRrLdsBytes / sizeof(T));
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t nn = (int64_t)n * n;
   T* As = work;
@@ -703,7 +716,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds<T>(Bs, U, n, rr_lds, use_lds);
+  jacobi_maybe_lds<T>(Bs, U, n, rr_lds, lds_elems);
   __syncthreads();
   for (int i = tid; i < n; i += nt) sv[i] = re_(Bs[i + (int64_t)i * n]);
   __threadfence_block();
@@ -750,7 +763,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds<T>(Bs, W, k, rr_lds, use_lds);
+  jacobi_maybe_lds<T>(Bs, W, k, rr_lds, lds_elems);
   __syncthreads();
   // ascending order of the Ritz values
   for (int i = tid; i < k; i += nt) {
@@ -884,8 +897,8 @@ void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, zd* 
 template <typename T>
 void rr_reduce(const T* At, const T* Bt, int n, double tau_rank, double* theta, T* Cmat, int* k_out, T* work,
                hipStream_t s) {
-  const size_t lds = n <= rr_lds_max<T>() ? sizeof(T) * (size_t)n * n : 0;
-  if (lds) (void)hipFuncSetAttribute((const void*)rr_reduce_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = kRrLdsBytes;
+  (void)hipFuncSetAttribute((const void*)rr_reduce_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(rr_reduce_kernel<T>, dim3(1), dim3(1024), lds, s, At, Bt, n, tau_rank, theta, Cmat, k_out, work);
 }
 
