@@ -858,6 +858,7 @@ namespace {
 // (synchronous host work); factor_run only enqueues kernels on a stream, so
 // several poles can run concurrently on their own streams.
 struct FactorLevelG {
+  std::vector<GemmLaunch> trsm;   // per step J: panel rows below the diagonal block
   std::vector<GemmLaunch> trail;  // per step J
   GemmLaunch schur;
   std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
@@ -905,6 +906,47 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     std::vector<int> fs = S.levels[L];
     int maxns = 0;
     for (int f : fs) maxns = std::max(maxns, S.fronts[f].ns);
+    // panel solves, per step J: rows r >= J + jb of the block column,
+    //   L(r, c) = sum_t P(r, t) X(c, t) / d(c)   (X: inverse of the unit diagonal block),
+    // computed transposed (c x r) so that the 1/d(c) scale is a row scale of the product; the
+    // panel rows are read and overwritten by the same tile.  LU: L rows with (U^T)^-1 blocks,
+    // U^T rows with L^-1 blocks.
+    for (int J = 0; J < maxns; J += FB) {
+      GemmLaunch g;
+      g.off = (int)gd.size();
+      for (int f : fs) {
+        const Front& Fr = S.fronts[f];
+        if (Fr.ns <= J) continue;
+        const int jb = std::min(FB, Fr.ns - J);
+        const int64_t k = (int64_t)Fr.ns + Fr.nb;
+        const int rows = (int)(k - J - jb);
+        if (rows <= 0) continue;
+        for (int side = 0; side < (lu ? 2 : 1); ++side) {
+          T* Pn = (side == 0 ? pole->panel : pole->upanel) + P->panel_off[f];
+          const T* Xi = (lu ? (side == 0 ? pole->uinv : pole->inv) : pole->inv) + P->inv_off[f];
+          GemmDesc<T> d{};
+          d.A = Xi + J + (int64_t)J * Fr.ns;
+          d.lda = Fr.ns;
+          d.B = Pn + (J + jb) + (int64_t)J * k;
+          d.ldb = k;
+          d.C = Pn + (J + jb) + (int64_t)J * k;
+          d.ldc = k;
+          d.crs = pole->dvec + Fr.first + J;
+          d.M = jb;
+          d.N = rows;
+          d.K = jb;
+          d.flags = GF_TRANSB | GF_TRANSC | GF_CRS | GF_CRS_INV | GF_CRS_ACC;
+          d.alpha = one;
+          d.beta = zero;
+          gd.push_back(d);
+          gemm_work(d, &g.flops, &g.bytes);
+          g.maxM = std::max(g.maxM, d.M);
+          g.maxN = std::max(g.maxN, d.N);
+        }
+      }
+      g.cnt = (int)gd.size() - g.off;
+      lg[L].trsm.push_back(g);
+    }
     // trailing updates inside the panel, per step J
     for (int J = 0; J < maxns; J += FB) {
       GemmLaunch g;
@@ -1053,6 +1095,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   // inner-dimension splits of launches with few tiles
   SplitPlan sp;
   for (FactorLevelG& l : lg) {
+    for (GemmLaunch& g : l.trsm) plan_split(gd, g, &sp);
     for (GemmLaunch& g : l.trail) plan_split(gd, g, &sp);
     plan_split(gd, l.schur, &sp);
     for (GemmLaunch& g : l.inv1) plan_split(gd, g, &sp);
@@ -1115,16 +1158,13 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
       int nd = P->lvl_diag_nJ[L][jj];
       {
         prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-        if (lu) {
-          // L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
+        if (lu)
           front_diag_block_lu<T>(pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, dd, nd, J, flag, s);
-          front_panel_trsm<T>(pole->panel, pole->uinv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
-          front_panel_trsm<T>(pole->upanel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
-        } else {
+        else
           front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
-          front_panel_trsm<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, P->lvl_trsm_rows[L][jj], s);
-        }
       }
+      // LDL^T: L21 = F21 L11^-T D^-1; LU: L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
+      run_gemm<T>(dgd, lg[L].trsm[jj], s, 0);
       run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
     }
     run_gemm<T>(dgd, lg[L].schur, s, 0);

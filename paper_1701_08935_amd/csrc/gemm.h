@@ -4,6 +4,8 @@
 //   C(i,j) = s(i) Cin(i,j) + alpha * sum_t opA(i,t) * dk(t) * opB(t,j)
 //
 // with s(i) = beta, or crs(i) (row scale), or 1/crs(i) (flag GF_CRS_INV);
+// with GF_CRS_ACC the row scale multiplies the product instead:
+//   C(i,j) = beta Cin(i,j) + r(i) alpha sum_t ...;
 // opA/opB optionally transposed / conjugated; C and Cin column-major with
 // leading dimensions ldc/ldcin, or row-major with GF_TRANSC.  GF_TRI keeps
 // only entries with i - j >= tri_off (lower-triangular updates of symmetric
@@ -29,6 +31,7 @@ enum GemmFlags {
   GF_CRS = 128,
   GF_ALOW = 256,
   GF_AUP = 512,
+  GF_CRS_ACC = 1024,  // the row scale (crs or 1/crs) multiplies the product instead of Cin
 };
 
 template <typename T>

@@ -316,6 +316,7 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
   const bool tc = (d.flags & GF_TRANSC) != 0;
   const bool use_crs = (d.flags & (GF_CRS | GF_CRS_INV)) != 0;
   const bool crs_inv = (d.flags & GF_CRS_INV) != 0;
+  const bool crs_acc = (d.flags & GF_CRS_ACC) != 0;
   const bool has_cin = d.Cin != nullptr;
   T rs[2][4], cv[2][4][NB];
 #pragma unroll
@@ -340,8 +341,14 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
     for (int v = 0; v < 4; ++v) {
       const int i = m0 + wm + 16 * a + MfmaTraits<T>::row(lk, v);
       if (i >= d.M) continue;
-      T s = d.beta;
-      if (use_crs) s = crs_inv ? inv_(rs[a][v]) : rs[a][v];
+      T s = d.beta, ra = d.alpha;
+      if (use_crs) {
+        const T r = crs_inv ? inv_(rs[a][v]) : rs[a][v];
+        if (crs_acc)
+          ra = mul(ra, r);
+        else
+          s = r;
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int j = n0 + wn + 16 * b + li;
@@ -352,7 +359,7 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
           accv = T{acc[0][a][b][v], acc[1][a][b][v]};
         else
           accv = acc[0][a][b][v];
-        T out = mul(d.alpha, accv);
+        T out = mul(ra, accv);
         if (has_cin) out = fma_(out, s, cv[a][v][b]);
         gst(tc ? d.C + (int64_t)i * d.ldc + j : d.C + i + (int64_t)j * d.ldc, out);
       }
