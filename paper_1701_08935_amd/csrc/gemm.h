@@ -12,7 +12,9 @@
 // fronts).  GF_ALOW / GF_AUP declare opA lower / upper triangular (square,
 // M == K; the other triangle is stored as zeros): each row tile then runs its
 // inner loop only over the nonzero part, which halves the work of products
-// with an explicit triangular inverse.  One descriptor per independent
+// with an explicit triangular inverse; GF_BLOW does the same for a lower
+// triangular opB (each column tile starts its inner loop at its first
+// column).  One descriptor per independent
 // product; a launch covers a list.
 #pragma once
 
@@ -32,6 +34,7 @@ enum GemmFlags {
   GF_ALOW = 256,
   GF_AUP = 512,
   GF_CRS_ACC = 1024,  // the row scale (crs or 1/crs) multiplies the product instead of Cin
+  GF_BLOW = 2048,     // opB lower triangular (square, K == N): column j sums over t >= j only
 };
 
 template <typename T>
@@ -91,6 +94,11 @@ inline void gemm_work(const GemmDesc<T>& d, double* flops, double* bytes) {
     }
   }
   const double fm = ST<T>::cplx ? 8.0 : 2.0;
+  if (d.flags & GF_BLOW) {
+    *flops += fm * M * (N * (N + 1.0) / 2.0);  // column j of a lower triangular opB has N - j nonzeros
+    *bytes += (double)sizeof(T) * (M * K + N * (N + 1.0) / 2.0 + ent * (d.Cin ? 2.0 : 1.0));
+    return;
+  }
   if (d.flags & (GF_ALOW | GF_AUP)) {
     *flops += fm * N * (M * (M + 1.0) / 2.0);  // row i of a triangular opA has i+1 (or M-i) nonzeros
     *bytes += (double)sizeof(T) * (M * (M + 1.0) / 2.0 + K * N + ent * (d.Cin ? 2.0 : 1.0));

@@ -5,9 +5,17 @@
 // launch from the largest M and N of its products); each wave owns a 32-row
 // strip of half the tile's columns as 16 x 16 blocks.  The inner dimension
 // advances in chunks staged through LDS (real and imaginary parts in separate
-// arrays), double-buffered: the global loads of chunk c+1 are issued into
-// registers before the MFMAs of chunk c and written to the other LDS buffer
-// after them, with one barrier per chunk.  Each 16 x 16 x 4 step uses
+// arrays) in two buffers with one barrier per chunk.  Two schedules:
+//  * two chunks deep (every tile but the 64 x 96 complex-double one): while
+//    chunk c is multiplied out of one buffer, chunk c+1, already in registers,
+//    is written to the other and the global loads of chunk c+2 are issued; the
+//    staging addresses are computed once per tile;
+//  * one chunk deep (64 x 96 complex double, which would spill otherwise): the
+//    loads of chunk c+1 are issued before the MFMAs of chunk c and written to
+//    the other buffer after them.
+// The loop bodies have no branches: out-of-range elements (and chunks past the
+// end) read a valid address and are zeroed on their way to LDS, and a short
+// last chunk is zero-padded.  Each 16 x 16 x 4 step uses
 // v_mfma_f64_16x16x4_f64 (double, complex double) or v_mfma_f32_16x16x4_f32
 // (complex float); a complex product is four real ones:
 //   Cre += Are Bre - Aim Bim,  Cim += Are Bim + Aim Bre.
@@ -76,10 +84,10 @@ __device__ inline void split<zf>(const zf& v, float* re, float* im) {
 // 2 x TN/32 blocks of 16 x 16):
 //   64 x 64  : 256 threads, TK 16
 //   64 x 96  : 256 threads, TK 8  (N in (64, 96], e.g. a 96-column block)
-// Both fit two or more workgroups per CU, so one workgroup's barrier and LDS
-// writes overlap the other's MFMAs.  LDS rows are padded to an odd number of elements so that both the row-wise
-// fragment reads and the column-wise stores of transposed operands spread over
-// all banks.
+// Both fit two workgroups per CU, so one workgroup's barrier and LDS writes
+// overlap the other's MFMAs.  LDS rows are padded to an odd number of elements
+// so that both the row-wise fragment reads and the column-wise stores of
+// transposed operands spread over all banks.
 template <int TM, int TN>
 struct TileCfg {
   static constexpr int NT = TM * 4;                          // threads
@@ -87,6 +95,14 @@ struct TileCfg {
   static constexpr int LDA = TM + 1, LDB = TN + 1;
   static constexpr int NLA = TM * TK / NT, NLB = TN * TK / NT;
   static constexpr int NB = TN / 32;  // 16-column blocks per wave
+};
+
+// Main-loop schedule per tile type: the two-deep pipeline keeps a second
+// chunk's staging registers live across the MFMAs, which the 64 x 96
+// complex-double tile cannot afford without spilling.
+template <typename T, int TN>
+struct PipelinedLoop {
+  static constexpr bool value = !(MfmaTraits<T>::cplx && sizeof(typename MfmaTraits<T>::R) == 8 && TN == 96);
 };
 
 // TAG only separates the uses in profiles: 0 front updates, 1 supernodal
@@ -114,9 +130,10 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
   const bool tri = (d.flags & GF_TRI) != 0;
   if (tri && (m0 + TM - 1) - n0 < d.tri_off) return;
 
-  // [buffer][plane][k][row]: double-buffered chunks
-  __shared__ R As[2][NP][TK][C::LDA];
-  __shared__ R Bs[2][NP][TK][C::LDB];
+  // two LDS buffers as separate arrays, so the compiler can tell the chunk
+  // being read from the one being written: [plane][k][row]
+  __shared__ R As0[NP][TK][C::LDA], As1[NP][TK][C::LDA];
+  __shared__ R Bs0[NP][TK][C::LDB], Bs1[NP][TK][C::LDB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -134,86 +151,13 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
 #pragma unroll
       for (int b = 0; b < NB; ++b) acc[q][a][b] = V4{0, 0, 0, 0};
 
-  // element e of a TM x TK (A) or TK x TN (B) chunk, laid out so that
-  // consecutive threads read consecutive addresses
-  auto a_idx = [&](int e, int* i, int* t) {
-    if (!ta) {
-      *i = e % TM;
-      *t = e / TM;
-    } else {
-      *i = e / TK;
-      *t = e % TK;
-    }
-  };
-  auto b_idx = [&](int e, int* t, int* j) {
-    if (!tb) {
-      *t = e % TK;
-      *j = e / TK;
-    } else {
-      *j = e % TN;
-      *t = e / TN;
-    }
-  };
-
-  // inner range: all of K, or the nonzero part of a triangular opA
+  // inner range: all of K, or the nonzero part of a triangular opA; a split
+  // takes its share of the chunks
   int kbeg = 0, kend = d.K;
   if (d.flags & GF_ALOW) kend = min(d.K, m0 + TM);
   if (d.flags & GF_AUP) kbeg = m0;
-  const bool has_dk = d.dk != nullptr;
-
-  // Global loads of a chunk go straight into registers: out-of-range elements
-  // read the (valid) first element instead and are zeroed when the chunk is
-  // written to LDS, so no load waits on a branch and all of them are in
-  // flight together while the MFMAs of the previous chunk run.
-  T ra[NLA], rb[NLB], rd[NLA];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < NLA; ++q) {
-      int i, t;
-      a_idx(tid + NT * q, &i, &t);
-      const int gi = m0 + i, gt = k0 + t;
-      const bool ok = gi < d.M && gt < kend;
-      ra[q] = gld(ok ? (ta ? d.A + gt + (int64_t)gi * d.lda : d.A + gi + (int64_t)gt * d.lda) : d.A);
-      if (has_dk) rd[q] = gld(d.dk + (ok ? gt : 0));
-    }
-#pragma unroll
-    for (int q = 0; q < NLB; ++q) {
-      int t, j;
-      b_idx(tid + NT * q, &t, &j);
-      const int gj = n0 + j, gt = k0 + t;
-      const bool ok = gj < d.N && gt < kend;
-      rb[q] = gld(ok ? (tb ? d.B + gj + (int64_t)gt * d.ldb : d.B + gt + (int64_t)gj * d.ldb) : d.B);
-    }
-  };
-  auto sstore = [&](int buf, int k0) {
-#pragma unroll
-    for (int q = 0; q < NLA; ++q) {
-      int i, t;
-      a_idx(tid + NT * q, &i, &t);
-      const bool ok = m0 + i < d.M && k0 + t < kend;
-      T v = ok ? ra[q] : ST<T>::zero();
-      if (ca) v = conj_(v);
-      if (has_dk) v = mul(v, rd[q]);
-      R re, im = 0;
-      split<T>(v, &re, &im);
-      As[buf][0][t][i] = re;
-      if constexpr (CPLX) As[buf][NP - 1][t][i] = im;
-    }
-#pragma unroll
-    for (int q = 0; q < NLB; ++q) {
-      int t, j;
-      b_idx(tid + NT * q, &t, &j);
-      const bool ok = n0 + j < d.N && k0 + t < kend;
-      T v = ok ? rb[q] : ST<T>::zero();
-      if (cb) v = conj_(v);
-      R re, im = 0;
-      split<T>(v, &re, &im);
-      Bs[buf][0][t][j] = re;
-      if constexpr (CPLX) Bs[buf][NP - 1][t][j] = im;
-    }
-  };
-
-  if (S > 1) {  // this split's share of the chunks
+  if (d.flags & GF_BLOW) kbeg = max(kbeg, n0);
+  if (S > 1) {
     const int ctot = kend > kbeg ? (kend - kbeg + TK - 1) / TK : 0;
     const int c0 = (int)((int64_t)ks * ctot / S), c1 = (int)((int64_t)(ks + 1) * ctot / S);
     const int kb = kbeg + c0 * TK;
@@ -221,32 +165,24 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
     kbeg = kb;
   }
   const int nchunk = kend > kbeg ? (kend - kbeg + TK - 1) / TK : 0;
-  if (nchunk > 0) {
-    gload(kbeg);
-    sstore(0, kbeg);
-  }
-  __syncthreads();
-  for (int c = 0; c < nchunk; ++c) {
-    const int k0 = kbeg + c * TK;
-    const int buf = c & 1;
-    if (c + 1 < nchunk) gload(k0 + TK);  // in flight during this chunk's MFMAs
-    const int ksteps = min(TK, kend - k0);  // a short last chunk skips its empty steps
+  const bool has_dk = d.dk != nullptr;
+
+  // MFMAs of one chunk held in (As, Bs); a short last chunk is zero-padded
+  auto compute = [&](const R* As, const R* Bs) {
 #pragma unroll
     for (int kk = 0; kk < TK / 4; ++kk) {
-      if (4 * kk >= ksteps) break;
       const int k = 4 * kk + lk;
       R are[2], aim[2], bre[NB], bim[NB];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        are[a] = As[buf][0][k][wm + 16 * a + li];
-        if constexpr (CPLX) aim[a] = As[buf][NP - 1][k][wm + 16 * a + li];
+        are[a] = As[k * C::LDA + wm + 16 * a + li];
+        if constexpr (CPLX) aim[a] = As[TK * C::LDA + k * C::LDA + wm + 16 * a + li];
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        bre[b] = Bs[buf][0][k][wn + 16 * b + li];
-        if constexpr (CPLX) bim[b] = Bs[buf][NP - 1][k][wn + 16 * b + li];
+        bre[b] = Bs[k * C::LDB + wn + 16 * b + li];
+        if constexpr (CPLX) bim[b] = Bs[TK * C::LDB + k * C::LDB + wn + 16 * b + li];
       }
-      // independent accumulators within each group, so dependent MFMAs are spaced
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -266,8 +202,184 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
           for (int b = 0; b < NB; ++b) acc[1][a][b] = mfma(aim[a], bre[b], acc[1][a][b]);
       }
     }
-    if (c + 1 < nchunk) sstore(buf ^ 1, k0 + TK);
-    __syncthreads();  // buf^1 is written; every wave is done reading buf
+  };
+
+  if constexpr (PipelinedLoop<T, TN>::value) {
+    // Staging geometry, fixed for the whole loop: element q of this thread is
+    // (row or column, k offset) of every chunk; consecutive threads read
+    // consecutive addresses.  The global address of a chunk at k0 is the
+    // thread's base plus k0 times a uniform step.
+    const T* pa[NLA];
+    int at[NLA], la[NLA];
+    bool arow[NLA];
+#pragma unroll
+    for (int q = 0; q < NLA; ++q) {
+      const int e = tid + NT * q;
+      const int i = ta ? e / TK : e % TM, t = ta ? e % TK : e / TM;
+      arow[q] = m0 + i < d.M;
+      at[q] = t;
+      la[q] = t * C::LDA + i;
+      pa[q] = ta ? d.A + t + (int64_t)(m0 + i) * d.lda : d.A + (m0 + i) + (int64_t)t * d.lda;
+    }
+    const T* pb[NLB];
+    int bt[NLB], lb[NLB];
+    bool bcol[NLB];
+#pragma unroll
+    for (int q = 0; q < NLB; ++q) {
+      const int e = tid + NT * q;
+      const int j = tb ? e % TN : e / TK, t = tb ? e / TN : e % TK;
+      bcol[q] = n0 + j < d.N;
+      bt[q] = t;
+      lb[q] = t * C::LDB + j;
+      pb[q] = tb ? d.B + (n0 + j) + (int64_t)t * d.ldb : d.B + t + (int64_t)(n0 + j) * d.ldb;
+    }
+    const int64_t sa = ta ? 1 : d.lda, sb = tb ? d.ldb : 1;
+
+    // Global loads of a chunk go straight into registers; out-of-range elements
+    // (and chunks past the end) read the first element instead and are zeroed
+    // when written to LDS, so the loop body has no branches.
+    T ra[NLA], rb[NLB], rd[NLA];
+    auto gload = [&](int k0) {
+      const int64_t oa = (int64_t)k0 * sa, ob = (int64_t)k0 * sb;
+#pragma unroll
+      for (int q = 0; q < NLA; ++q) {
+        const bool ok = arow[q] && at[q] + k0 < kend;
+        ra[q] = gld(ok ? pa[q] + oa : d.A);
+        if (has_dk) rd[q] = gld(d.dk + (ok ? k0 + at[q] : 0));
+      }
+#pragma unroll
+      for (int q = 0; q < NLB; ++q) {
+        const bool ok = bcol[q] && bt[q] + k0 < kend;
+        rb[q] = gld(ok ? pb[q] + ob : d.B);
+      }
+    };
+    auto sstore = [&](R* As, R* Bs, int k0) {
+#pragma unroll
+      for (int q = 0; q < NLA; ++q) {
+        const bool ok = arow[q] && at[q] + k0 < kend;
+        T v = ok ? ra[q] : ST<T>::zero();
+        if (ca) v = conj_(v);
+        if (has_dk) v = mul(v, rd[q]);
+        R re, im = 0;
+        split<T>(v, &re, &im);
+        As[la[q]] = re;
+        if constexpr (CPLX) As[TK * C::LDA + la[q]] = im;
+      }
+#pragma unroll
+      for (int q = 0; q < NLB; ++q) {
+        const bool ok = bcol[q] && bt[q] + k0 < kend;
+        T v = ok ? rb[q] : ST<T>::zero();
+        if (cb) v = conj_(v);
+        R re, im = 0;
+        split<T>(v, &re, &im);
+        Bs[lb[q]] = re;
+        if constexpr (CPLX) Bs[TK * C::LDB + lb[q]] = im;
+      }
+    };
+    // Software pipeline, two chunks deep: while chunk c is multiplied out of
+    // one buffer, chunk c+1 (already in registers) is written to the other
+    // and the loads of chunk c+2 are issued.  One barrier per chunk.
+    if (nchunk > 0) {
+      gload(kbeg);
+      sstore(&As0[0][0][0], &Bs0[0][0][0], kbeg);
+      gload(kbeg + TK);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunk; c += 2) {
+      const int k0 = kbeg + c * TK;
+      sstore(&As1[0][0][0], &Bs1[0][0][0], k0 + TK);
+      gload(k0 + 2 * TK);
+      compute(&As0[0][0][0], &Bs0[0][0][0]);
+      __syncthreads();
+      if (c + 1 >= nchunk) break;
+      sstore(&As0[0][0][0], &Bs0[0][0][0], k0 + 2 * TK);
+      gload(k0 + 3 * TK);
+      compute(&As1[0][0][0], &Bs1[0][0][0]);
+      __syncthreads();
+    }
+  } else {
+    // Staging geometry: element q of this thread is (row or column, k offset)
+    // within every chunk, consecutive threads reading consecutive addresses;
+    // recomputed per chunk (a few integer ops) rather than kept in registers.
+    auto ageo = [&](int q, int* i, int* t) {
+      const int e = tid + NT * q;
+      *i = ta ? e / TK : e % TM;
+      *t = ta ? e % TK : e / TM;
+    };
+    auto bgeo = [&](int q, int* t, int* j) {
+      const int e = tid + NT * q;
+      *j = tb ? e % TN : e / TK;
+      *t = tb ? e / TN : e % TK;
+    };
+
+    T ra[NLA], rb[NLB], rd[NLA];
+    auto gload = [&](int k0) {
+#pragma unroll
+      for (int q = 0; q < NLA; ++q) {
+        int i, t;
+        ageo(q, &i, &t);
+        const int gi = m0 + i, gt = k0 + t;
+        const bool ok = gi < d.M && gt < kend;
+        const int64_t off = ta ? gt + (int64_t)gi * d.lda : gi + (int64_t)gt * d.lda;
+        ra[q] = gld(d.A + (ok ? off : 0));
+        if (has_dk) rd[q] = gld(d.dk + (ok ? gt : 0));
+      }
+#pragma unroll
+      for (int q = 0; q < NLB; ++q) {
+        int t, j;
+        bgeo(q, &t, &j);
+        const int gj = n0 + j, gt = k0 + t;
+        const bool ok = gj < d.N && gt < kend;
+        const int64_t off = tb ? gj + (int64_t)gt * d.ldb : gt + (int64_t)gj * d.ldb;
+        rb[q] = gld(d.B + (ok ? off : 0));
+      }
+    };
+    auto sstore = [&](R* As, R* Bs, int k0) {
+#pragma unroll
+      for (int q = 0; q < NLA; ++q) {
+        int i, t;
+        ageo(q, &i, &t);
+        const bool ok = m0 + i < d.M && k0 + t < kend;
+        T v = ok ? ra[q] : ST<T>::zero();
+        if (ca) v = conj_(v);
+        if (has_dk) v = mul(v, rd[q]);
+        R re, im = 0;
+        split<T>(v, &re, &im);
+        As[t * C::LDA + i] = re;
+        if constexpr (CPLX) As[TK * C::LDA + t * C::LDA + i] = im;
+      }
+#pragma unroll
+      for (int q = 0; q < NLB; ++q) {
+        int t, j;
+        bgeo(q, &t, &j);
+        const bool ok = n0 + j < d.N && k0 + t < kend;
+        T v = ok ? rb[q] : ST<T>::zero();
+        if (cb) v = conj_(v);
+        R re, im = 0;
+        split<T>(v, &re, &im);
+        Bs[t * C::LDB + j] = re;
+        if constexpr (CPLX) Bs[TK * C::LDB + t * C::LDB + j] = im;
+      }
+    };
+    // One chunk ahead: the loads of chunk c+1 are issued before the MFMAs of
+    // chunk c and written to the other buffer after them (fewer registers
+    // live across the MFMAs, for the widest complex tile).
+    if (nchunk > 0) {
+      gload(kbeg);
+      sstore(&As0[0][0][0], &Bs0[0][0][0], kbeg);
+    }
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+      const int k0 = kbeg + c * TK;
+      R* curA = (c & 1) ? &As1[0][0][0] : &As0[0][0][0];
+      R* curB = (c & 1) ? &Bs1[0][0][0] : &Bs0[0][0][0];
+      R* nxtA = (c & 1) ? &As0[0][0][0] : &As1[0][0][0];
+      R* nxtB = (c & 1) ? &Bs0[0][0][0] : &Bs1[0][0][0];
+      if (c + 1 < nchunk) gload(k0 + TK);
+      compute(curA, curB);
+      if (c + 1 < nchunk) sstore(nxtA, nxtB, k0 + TK);
+      __syncthreads();
+    }
   }
 
   if (S > 1) {
