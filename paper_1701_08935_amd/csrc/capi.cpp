@@ -248,21 +248,19 @@ template <typename T>
 struct SolveProg {
   int p = 0;
   DevArena mem;
-  T* W = nullptr;
-  T* U = nullptr;
-  T* Xb = nullptr;
-  T* tb = nullptr;
-  T* Y = nullptr;
-  T* X = nullptr;
+  T* W = nullptr;  // per level: each front's k x p right-hand side (forward, then backward)
+  T* U = nullptr;  // each front's nb x p contribution to its parent (forward)
+  T* Y = nullptr;  // forward solution, N x p per solve
+  T* X = nullptr;  // solution, N x p per solve
   SolveDesc* sd = nullptr;     // shared right-hand side
   SolveDesc* sd_pp = nullptr;  // per-pole right-hand sides (pole j at j * xstride)
   SolveExt* se = nullptr;
-  std::vector<int> lvl_sd_off, lvl_sd_cnt, lvl_maxk, lvl_maxnb;
+  std::vector<int> lvl_sd_off, lvl_sd_cnt, lvl_maxk;
   std::vector<std::vector<GemmLaunch>> lvl_se;  // per slot (tiles = max nb)
   int np = 0;                                    // poles solved together
   int64_t xstride = 0;                           // elements between poles' X (and Y) blocks
   GemmDesc<T>* gd = nullptr;                     // all poles, per level
-  std::vector<GemmLaunch> f2, f3, b2, b3;        // [level]
+  std::vector<GemmLaunch> fw, bw;                // [level]: forward, backward products
 };
 
 // Krylov-side buffers.  Blocks hold real values for real pencils and complex
@@ -862,14 +860,19 @@ struct FactorLevelG {
   std::vector<GemmLaunch> trail;  // per step J
   GemmLaunch schur;
   std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
+  GemmLaunch conv;                     // -L21 L11^-1 of every front (solve panel, lower part)
+  int stk_off = 0, stk_cnt = 0;        // stacking of the solve panels
+  int64_t stk_max = 0;                 // largest k * ns of the level
 };
 template <typename T>
 struct FactorWork {
   DevArena tmp;
   T* upd = nullptr;
   T* scratch = nullptr;
+  T* ctmp = nullptr;  // -L21 L11^-1 of one level's fronts before stacking
   int* flag = nullptr;
   GemmDesc<T>* dgd = nullptr;
+  StackDesc<T>* dstk = nullptr;
   std::vector<FactorLevelG> lg;
   double sr = 0.0, si = 0.0;
 };
@@ -894,16 +897,25 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   DevArena& tmp = fw->tmp;
   CHK(tmp.alloc(&fw->upd, P->upd_total));
   CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch * (lu ? 2 : 1), 1)));
+  int64_t cmax = 0;
+  for (int L = 0; L < nl; ++L) {
+    int64_t c = 0;
+    for (int f : S.levels[L]) c += (int64_t)S.fronts[f].nb * S.fronts[f].ns;
+    cmax = std::max(cmax, c);
+  }
+  CHK(tmp.alloc(&fw->ctmp, std::max<int64_t>(cmax * (lu ? 2 : 1), 1)));
   CHK(tmp.alloc(&fw->flag, 1));
   T* upd = fw->upd;
   T* scratch = fw->scratch;
   // GEMM descriptors of the whole program (pointers into this pole's arrays)
   std::vector<GemmDesc<T>> gd;
+  std::vector<StackDesc<T>> stk;
   std::vector<FactorLevelG>& lg = fw->lg;
   lg.assign(nl, FactorLevelG());
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
   for (int L = 0; L < nl; ++L) {
     std::vector<int> fs = S.levels[L];
+    lg[L].stk_off = (int)stk.size();
     int maxns = 0;
     for (int f : fs) maxns = std::max(maxns, S.fronts[f].ns);
     // panel solves, per step J: rows r >= J + jb of the block column,
@@ -1091,6 +1103,49 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       lg[L].inv1.push_back(g1);
       lg[L].inv2.push_back(g2);
     }
+    // Solve panels.  Once the level is factored, each front's panel is replaced
+    // by [X; -L21 X] with X = L11^-1 (LU: the U^T panel likewise with
+    // (U11^T)^-1), so that a supernodal solve step is one product per front:
+    // forward y1 = X w1, w2 -= L21 X w1; backward x1 = X^T D^-1 y1 - (L21 X)^T x2.
+    {
+      GemmLaunch g;
+      g.off = (int)gd.size();
+      int64_t co = 0;
+      for (int side = 0; side < (lu ? 2 : 1); ++side)
+        for (int f : fs) {
+          const Front& Fr = S.fronts[f];
+          const int64_t k = (int64_t)Fr.ns + Fr.nb;
+          T* Pn = (side ? pole->upanel : pole->panel) + P->panel_off[f];
+          T* X = (side ? pole->uinv : pole->inv) + P->inv_off[f];
+          if (Fr.ns > 0) {
+            StackDesc<T> sdsc{Pn, X, fw->ctmp + co, Fr.ns, Fr.nb};
+            stk.push_back(sdsc);
+            lg[L].stk_max = std::max(lg[L].stk_max, k * Fr.ns);
+          }
+          if (Fr.nb == 0 || Fr.ns == 0) continue;
+          GemmDesc<T> d{};
+          d.C = fw->ctmp + co;
+          d.ldc = Fr.nb;
+          d.A = Pn + Fr.ns;
+          d.lda = k;
+          d.B = X;
+          d.ldb = Fr.ns;
+          d.M = Fr.nb;
+          d.N = Fr.ns;
+          d.K = Fr.ns;
+          d.flags = GF_BLOW;
+          d.alpha = mone;
+          d.beta = zero;
+          gd.push_back(d);
+          gemm_work(d, &g.flops, &g.bytes);
+          g.maxM = std::max(g.maxM, d.M);
+          g.maxN = std::max(g.maxN, d.N);
+          co += (int64_t)Fr.nb * Fr.ns;
+        }
+      g.cnt = (int)gd.size() - g.off;
+      lg[L].conv = g;
+      lg[L].stk_cnt = (int)stk.size() - lg[L].stk_off;
+    }
   }
   // inner-dimension splits of launches with few tiles
   SplitPlan sp;
@@ -1100,6 +1155,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     plan_split(gd, l.schur, &sp);
     for (GemmLaunch& g : l.inv1) plan_split(gd, g, &sp);
     for (GemmLaunch& g : l.inv2) plan_split(gd, g, &sp);
+    plan_split(gd, l.conv, &sp);
   }
   if (!sp.at.empty()) {
     typename ST<T>::real* part = nullptr;
@@ -1110,6 +1166,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     patch_split(gd, sp, part, cnt);
   }
   CHK(tmp.upload(&fw->dgd, gd.data(), gd.size()));
+  CHK(tmp.upload(&fw->dstk, stk.data(), stk.size()));
   return ZOLO_OK;
 }
 
@@ -1171,6 +1228,11 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
     for (size_t I = 0; I < lg[L].inv1.size(); ++I) {
       run_gemm<T>(dgd, lg[L].inv1[I], s, 0);
       run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
+    }
+    run_gemm<T>(dgd, lg[L].conv, s, 0);
+    {
+      prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
+      front_stack<T>(fw->dstk + lg[L].stk_off, lg[L].stk_cnt, lg[L].stk_max, s);
     }
   }
   if (lu) conj_copy(pole->dconj, pole->dvec, P->n, s);
@@ -1289,42 +1351,36 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   // K_j^-H = L^-H conj(D)^-1 U^-H, whose triangles are the conjugates of the
   // stored U^T and L factors: the forward pass runs on (U^T, its inverse
   // blocks), the backward pass on (L, its inverse blocks), all conjugated.
+  // Each front's solve panel is [X; -L21 X] (k x ns, ld k) with X = L11^-1.
   struct Role {
-    const T *fp, *fi, *bp, *bi, *dv;
+    const T *fp, *bp, *dv;
     int cj;
   };
   const bool lu = P->cplx();
   std::vector<Role> roles;
-  for (const PoleMF<T>& pm : poles)
-    roles.push_back({pm.panel, pm.inv, lu ? pm.upanel : pm.panel, lu ? pm.uinv : pm.inv, pm.dvec, 0});
+  for (const PoleMF<T>& pm : poles) roles.push_back({pm.panel, lu ? pm.upanel : pm.panel, pm.dvec, 0});
   if (lu)
-    for (const PoleMF<T>& pm : poles) roles.push_back({pm.upanel, pm.uinv, pm.panel, pm.inv, pm.dconj, GF_CONJA});
+    for (const PoleMF<T>& pm : poles) roles.push_back({pm.upanel, pm.panel, pm.dconj, GF_CONJA});
   const int np = (int)roles.size();
   G->p = p;
   G->np = np;
-  int64_t wmax = 0, xbmax = 0, tmax = 0;
+  int64_t wmax = 0;
   std::vector<int64_t> uoff(S.fronts.size(), 0);
   int64_t utot = 0;
   for (int L = 0; L < nl; ++L) {
-    int64_t w = 0, xb = 0, t = 0;
+    int64_t w = 0;
     for (int f : S.levels[L]) {
       const Front& Fr = S.fronts[f];
       w += (int64_t)(Fr.ns + Fr.nb) * p;
-      xb += (int64_t)Fr.nb * p;
-      t += (int64_t)Fr.ns * p;
       uoff[f] = utot;
       utot += (int64_t)Fr.nb * p;
     }
     wmax = std::max(wmax, w);
-    xbmax = std::max(xbmax, xb);
-    tmax = std::max(tmax, t);
   }
   const int64_t npx = P->n * p;
   G->xstride = npx;
   CHK(G->mem.alloc(&G->W, wmax * np));
   CHK(G->mem.alloc(&G->U, utot * np));
-  CHK(G->mem.alloc(&G->Xb, xbmax * np));
-  CHK(G->mem.alloc(&G->tb, tmax * np));
   CHK(G->mem.alloc(&G->Y, npx * np));
   CHK(G->mem.alloc(&G->X, npx * np));
   std::vector<SolveDesc> sd;
@@ -1332,22 +1388,16 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   G->lvl_sd_off.assign(nl, 0);
   G->lvl_sd_cnt.assign(nl, 0);
   G->lvl_maxk.assign(nl, 0);
-  G->lvl_maxnb.assign(nl, 0);
   G->lvl_se.assign(nl, {});
   // per level, per front (level order): offsets within one pole's regions
-  std::vector<std::vector<int64_t>> woff(nl), xboff(nl), toff(nl);
+  std::vector<std::vector<int64_t>> woff(nl);
   for (int L = 0; L < nl; ++L) {
-    int64_t w = 0, xb = 0, t = 0;
+    int64_t w = 0;
     for (int f : S.levels[L]) {
       const Front& Fr = S.fronts[f];
       woff[L].push_back(w);
-      xboff[L].push_back(xb);
-      toff[L].push_back(t);
       w += (int64_t)(Fr.ns + Fr.nb) * p;
-      xb += (int64_t)Fr.nb * p;
-      t += (int64_t)Fr.ns * p;
       G->lvl_maxk[L] = std::max(G->lvl_maxk[L], Fr.ns + Fr.nb);
-      G->lvl_maxnb[L] = std::max(G->lvl_maxnb[L], (int)Fr.nb);
     }
     G->lvl_sd_off[L] = (int)sd.size();
     for (int j = 0; j < np; ++j) {
@@ -1355,9 +1405,9 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       for (int f : S.levels[L]) {
         const Front& Fr = S.fronts[f];
         SolveDesc d{};
+        d.dv = roles[j].dv;
         d.w = j * wmax + woff[L][i];
         d.u = j * utot + uoff[f];
-        d.xb = j * xbmax + xboff[L][i];
         d.srow = Fr.struct_off;
         d.xo = j * npx;
         d.so = 0;
@@ -1402,110 +1452,92 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   CHK(G->mem.upload(&G->sd_pp, sd.data(), sd.size()));
   CHK(G->mem.upload(&G->se, se.data(), se.size()));
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
-  G->f2.assign(nl, GemmLaunch());
-  G->f3.assign(nl, GemmLaunch());
-  G->b2.assign(nl, GemmLaunch());
-  G->b3.assign(nl, GemmLaunch());
+  G->fw.assign(nl, GemmLaunch());
+  G->bw.assign(nl, GemmLaunch());
   std::vector<GemmDesc<T>> gd;
   for (int L = 0; L < nl; ++L) {
     const std::vector<int>& fs = S.levels[L];
-    auto emit = [&](GemmLaunch& g, auto mk) {
-      g.off = (int)gd.size();
-      for (int j = 0; j < np; ++j)
-        for (size_t i = 0; i < fs.size(); ++i) {
-          const Front& Fr = S.fronts[fs[i]];
-          GemmDesc<T> d{};
-          if (!mk(j, Fr, fs[i], i, d)) continue;
-          gd.push_back(d);
-          gemm_work(d, &g.flops, &g.bytes);
-          g.maxM = std::max(g.maxM, d.M);
-        g.maxN = std::max(g.maxN, d.N);
-        }
-      g.cnt = (int)gd.size() - g.off;
+    auto add = [&](GemmLaunch& g, const GemmDesc<T>& d) {
+      gd.push_back(d);
+      gemm_work(d, &g.flops, &g.bytes);
+      g.maxM = std::max(g.maxM, d.M);
+      g.maxN = std::max(g.maxN, d.N);
     };
-    // F2: Y[first:first+ns] = inv * W[0:ns]
-    emit(G->f2[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-      if (Fr.ns == 0) return false;
-      d.C = G->Y + j * npx + (int64_t)Fr.first * p;
-      d.ldc = p;
-      d.A = roles[j].fi + P->inv_off[f];
-      d.lda = Fr.ns;
-      d.B = G->W + j * wmax + woff[L][i];
-      d.ldb = p;
-      d.M = Fr.ns;
-      d.N = p;
-      d.K = Fr.ns;
-      d.flags = GF_TRANSB | GF_TRANSC | GF_ALOW | roles[j].cj;
-      d.alpha = one;
-      d.beta = zero;
-      return true;
-    });
-    // F3: U = W[ns:k] - L21 * Y[first:first+ns]
-    emit(G->f3[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-      if (Fr.nb == 0) return false;
-      int64_t k = (int64_t)Fr.ns + Fr.nb;
-      d.C = G->U + j * utot + uoff[f];
-      d.ldc = p;
-      d.Cin = G->W + j * wmax + woff[L][i] + (int64_t)Fr.ns * p;
-      d.ldcin = p;
-      d.A = roles[j].fp + P->panel_off[f] + Fr.ns;
-      d.lda = k;
-      d.B = G->Y + j * npx + (int64_t)Fr.first * p;
-      d.ldb = p;
-      d.M = Fr.nb;
-      d.N = p;
-      d.K = Fr.ns;
-      d.flags = GF_TRANSB | GF_TRANSC | roles[j].cj;
-      d.alpha = mone;
-      d.beta = one;
-      return true;
-    });
-    // B2: t = D^-1 Y[first:] - L21^T Xb
-    emit(G->b2[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-      if (Fr.ns == 0) return false;
-      int64_t k = (int64_t)Fr.ns + Fr.nb;
-      d.C = G->tb + j * tmax + toff[L][i];
-      d.ldc = p;
-      d.Cin = G->Y + j * npx + (int64_t)Fr.first * p;
-      d.ldcin = p;
-      d.crs = roles[j].dv + Fr.first;
-      d.A = roles[j].bp + P->panel_off[f] + Fr.ns;
-      d.lda = k;
-      d.B = G->Xb + j * xbmax + xboff[L][i];
-      d.ldb = p;
-      d.M = Fr.ns;
-      d.N = p;
-      d.K = Fr.nb;
-      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_CRS_INV | roles[j].cj;
-      d.alpha = mone;
-      d.beta = one;
-      return true;
-    });
-    // B3: X[first:] = inv^T t
-    emit(G->b3[L], [&](int j, const Front& Fr, int f, size_t i, GemmDesc<T>& d) {
-      if (Fr.ns == 0) return false;
-      d.C = G->X + j * npx + (int64_t)Fr.first * p;
-      d.ldc = p;
-      d.A = roles[j].bi + P->inv_off[f];
-      d.lda = Fr.ns;
-      d.B = G->tb + j * tmax + toff[L][i];
-      d.ldb = p;
-      d.M = Fr.ns;
-      d.N = p;
-      d.K = Fr.ns;
-      d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_AUP | roles[j].cj;
-      d.alpha = one;
-      d.beta = zero;
-      return true;
-    });
+    // forward: Y[first:first+ns] = X W[0:ns] and U = W[ns:k] + (-L21 X) W[0:ns],
+    // both reading only W, so one launch per level
+    GemmLaunch& gf = G->fw[L];
+    gf.off = (int)gd.size();
+    for (int j = 0; j < np; ++j)
+      for (size_t i = 0; i < fs.size(); ++i) {
+        const Front& Fr = S.fronts[fs[i]];
+        if (Fr.ns == 0) continue;
+        const int64_t k = (int64_t)Fr.ns + Fr.nb;
+        const T* Pn = roles[j].fp + P->panel_off[fs[i]];
+        const T* Wf = G->W + j * wmax + woff[L][i];
+        GemmDesc<T> d{};
+        d.C = G->Y + j * npx + (int64_t)Fr.first * p;
+        d.ldc = p;
+        d.A = Pn;
+        d.lda = k;
+        d.B = Wf;
+        d.ldb = p;
+        d.M = Fr.ns;
+        d.N = p;
+        d.K = Fr.ns;
+        d.flags = GF_TRANSB | GF_TRANSC | GF_ALOW | roles[j].cj;
+        d.alpha = one;
+        d.beta = zero;
+        add(gf, d);
+        if (Fr.nb == 0) continue;
+        GemmDesc<T> e{};
+        e.C = G->U + j * utot + uoff[fs[i]];
+        e.ldc = p;
+        e.Cin = Wf + (int64_t)Fr.ns * p;
+        e.ldcin = p;
+        e.A = Pn + Fr.ns;
+        e.lda = k;
+        e.B = Wf;
+        e.ldb = p;
+        e.M = Fr.nb;
+        e.N = p;
+        e.K = Fr.ns;
+        e.flags = GF_TRANSB | GF_TRANSC | roles[j].cj;
+        e.alpha = one;
+        e.beta = one;
+        add(gf, e);
+      }
+    gf.cnt = (int)gd.size() - gf.off;
+    // backward: X[first:first+ns] = [X; -L21 X]^T [D^-1 y1; x2], with the
+    // stacked right-hand side gathered into W (X^T is upper triangular)
+    GemmLaunch& gb = G->bw[L];
+    gb.off = (int)gd.size();
+    for (int j = 0; j < np; ++j)
+      for (size_t i = 0; i < fs.size(); ++i) {
+        const Front& Fr = S.fronts[fs[i]];
+        if (Fr.ns == 0) continue;
+        const int64_t k = (int64_t)Fr.ns + Fr.nb;
+        GemmDesc<T> d{};
+        d.C = G->X + j * npx + (int64_t)Fr.first * p;
+        d.ldc = p;
+        d.A = roles[j].bp + P->panel_off[fs[i]];
+        d.lda = k;
+        d.B = G->W + j * wmax + woff[L][i];
+        d.ldb = p;
+        d.M = Fr.ns;
+        d.N = p;
+        d.K = (int)k;
+        d.flags = GF_TRANSA | GF_TRANSB | GF_TRANSC | GF_AUP | roles[j].cj;
+        d.alpha = one;
+        d.beta = zero;
+        add(gb, d);
+      }
+    gb.cnt = (int)gd.size() - gb.off;
   }
   // inner-dimension splits of launches with few tiles (the top levels)
   SplitPlan sp;
   for (int L = 0; L < nl; ++L) {
-    plan_split(gd, G->f2[L], &sp);
-    plan_split(gd, G->f3[L], &sp);
-    plan_split(gd, G->b2[L], &sp);
-    plan_split(gd, G->b3[L], &sp);
+    plan_split(gd, G->fw[L], &sp);
+    plan_split(gd, G->bw[L], &sp);
   }
   if (!sp.at.empty()) {
     typename ST<T>::real* part = nullptr;
@@ -1559,17 +1591,15 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, boo
       for (const GemmLaunch& g : G->lvl_se[L])
         solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
     }
-    run_gemm<T>(G->gd, G->f2[L], s, 1);
-    run_gemm<T>(G->gd, G->f3[L], s, 1);
+    run_gemm<T>(G->gd, G->fw[L], s, 1);
   }
   for (int L = nl - 1; L >= 0; --L) {
     {
       prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
-      solve_gather_struct<T>(G->Xb, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
-                             G->lvl_maxnb[L], s);
+      solve_gather_back<T>(G->W, G->Y, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
+                           G->lvl_maxk[L], s);
     }
-    run_gemm<T>(G->gd, G->b2[L], s, 1);
-    run_gemm<T>(G->gd, G->b3[L], s, 1);
+    run_gemm<T>(G->gd, G->bw[L], s, 1);
   }
 }
 

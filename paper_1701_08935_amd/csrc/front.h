@@ -1,6 +1,6 @@
-// Multifrontal complex-symmetric LDL^T kernels: front assembly, extend-add,
-// diagonal-block factorization and inversion, panel triangular solve, and the
-// row gathers / extend-adds of the supernodal triangular solves.
+// Multifrontal kernels: front assembly, extend-add, diagonal-block
+// factorization and inversion, the stacking of each front's solve panel, and
+// the row gathers / extend-adds of the supernodal triangular solves.
 #pragma once
 
 #include "dev_common.h"
@@ -28,12 +28,12 @@ struct DiagDesc {
 
 // Solve: per front RHS block W (k x p row-major), contributions U (nb x p).
 struct SolveDesc {
-  int64_t w;      // element offset of W in the level's W buffer
-  int64_t u;      // element offset of U in the U buffer (global over fronts)
-  int64_t xb;     // element offset of the struct gather buffer
-  int64_t srow;   // offset into struct_rows
-  int64_t xo;     // element offset of this pole's solution block X
-  int64_t so;     // element offset of this pole's right-hand side (0 = shared)
+  const void* dv;  // pivots D of this solve's factor (the backward gather scales by D^-1)
+  int64_t w;       // element offset of W in the level's W buffer
+  int64_t u;       // element offset of U in the U buffer (global over fronts)
+  int64_t srow;    // offset into struct_rows
+  int64_t xo;      // element offset of this solve's blocks in X and Y
+  int64_t so;      // element offset of this pole's right-hand side (0 = shared)
   int32_t first, ns, nb, k;
 };
 
@@ -72,11 +72,6 @@ template <typename T>
 void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
                          int* breakdown, hipStream_t s);
 
-// rows J+jb .. k-1 of each panel: L(r, J:J+jb) = P(r, J:J+jb) inv(J,J)^T D_J^-1 (in place)
-template <typename T>
-void front_panel_trsm(T* panel, const T* inv, const T* dvec, const DiagDesc* d, int nd, int J, int max_rows,
-                      hipStream_t s);
-
 // W rows [0, ns) <- src rows [first, first+ns) (converted), rows [ns, k) <- 0.
 template <typename Ts, typename T>
 void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
@@ -85,9 +80,23 @@ void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, in
 template <typename T>
 void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, int nd, int p, int max_nb,
                       hipStream_t s);
-// Xb[i] = X[struct_rows[srow + i]]
+// Backward right-hand side of each front, into W (k x p, row-major):
+// rows [0, ns): D^-1 Y[first + r]; rows [ns, k): X[struct_rows[srow + r - ns]].
 template <typename T>
-void solve_gather_struct(T* Xb, const T* X, const int32_t* struct_rows, const SolveDesc* d, int nd, int p,
-                         int max_nb, hipStream_t s);
+void solve_gather_back(T* W, const T* Y, const T* X, const int32_t* struct_rows, const SolveDesc* d, int nd, int p,
+                       int max_k, hipStream_t s);
+
+// Solve panel of a front, stacked in place of its factor panel (k x ns,
+// col-major, ld k): rows [0, ns) <- top (ns x ns, ld ns), rows [ns, k) <- bot
+// (nb x ns, ld nb).
+template <typename T>
+struct StackDesc {
+  T* dst;
+  const T* top;
+  const T* bot;
+  int32_t ns, nb;
+};
+template <typename T>
+void front_stack(const StackDesc<T>* d, int nd, int64_t max_elems, hipStream_t s);
 
 }  // namespace zolo

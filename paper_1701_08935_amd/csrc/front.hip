@@ -302,45 +302,6 @@ __global__ __launch_bounds__(256) void diag_block_kernel(T* __restrict__ panel, 
   }
 }
 
-// rows handled per workgroup in the panel solve
-constexpr int PT_ROWS = 32;
-
-template <typename T>
-__global__ __launch_bounds__(256) void panel_trsm_kernel(T* __restrict__ panel, const T* __restrict__ inv,
-                                                         const T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
-                                                         int J) {
-  const DiagDesc d = descs[blockIdx.y];
-  if (J >= d.ns) return;
-  const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
-  const int r0 = J + jb + blockIdx.x * PT_ROWS;
-  if (r0 >= d.k) return;
-  const int nr = (d.k - r0) < PT_ROWS ? (d.k - r0) : PT_ROWS;
-  __shared__ T Xs[FB][FB + 1];      // Xs[c][t] = inv(J+c, J+t)
-  __shared__ T Ps[PT_ROWS][FB + 1];  // panel rows
-  __shared__ T Di[FB];
-  const int tid = threadIdx.x;
-  T* P = panel + d.panel;
-  const T* X = inv + d.inv;
-  const int64_t k = d.k, ns = d.ns;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int c = e % jb, t = e / jb;
-    Xs[c][t] = X[(J + c) + (int64_t)(J + t) * ns];
-  }
-  for (int e = tid; e < nr * jb; e += blockDim.x) {
-    int r = e % nr, t = e / nr;
-    Ps[r][t] = P[(r0 + r) + (int64_t)(J + t) * k];
-  }
-  for (int c = tid; c < jb; c += blockDim.x) Di[c] = inv_(dvec[d.first + J + c]);
-  __syncthreads();
-  // L(r, c) = (sum_{t <= c} P(r, t) X(c, t)) / D(c)
-  for (int e = tid; e < nr * jb; e += blockDim.x) {
-    int r = e % nr, c = e / nr;
-    T s = ST<T>::zero();
-    for (int t = 0; t <= c; ++t) s = fma_(s, Ps[r][t], Xs[c][t]);
-    P[(r0 + r) + (int64_t)(J + c) * k] = mul(s, Di[c]);
-  }
-}
-
 template <typename Ts, typename T>
 __global__ void gather_own_kernel(T* __restrict__ W, const Ts* __restrict__ src, int64_t ldsrc,
                                   const SolveDesc* __restrict__ descs, int p) {
@@ -368,15 +329,31 @@ __global__ void solve_ext_kernel(T* __restrict__ W, const T* __restrict__ U, con
 }
 
 template <typename T>
-__global__ void gather_struct_kernel(T* __restrict__ Xb, const T* __restrict__ X, const int32_t* __restrict__ srows,
-                                     const SolveDesc* __restrict__ descs, int p) {
+__global__ void gather_back_kernel(T* __restrict__ W, const T* __restrict__ Y, const T* __restrict__ X,
+                                   const int32_t* __restrict__ srows, const SolveDesc* __restrict__ descs, int p) {
   const SolveDesc d = descs[blockIdx.y];
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t tot = (int64_t)d.nb * p;
+  int64_t tot = (int64_t)d.k * p;
   if (e >= tot) return;
-  int64_t i = e / p, c = e % p;
-  int64_t row = srows[d.srow + i];
-  Xb[d.xb + e] = X[d.xo + row * p + c];
+  int64_t r = e / p, c = e % p;
+  T v;
+  if (r < d.ns) {
+    const T* dv = (const T*)d.dv;
+    v = mul(Y[d.xo + (d.first + r) * p + c], inv_(dv[d.first + r]));
+  } else {
+    v = X[d.xo + (int64_t)srows[d.srow + r - d.ns] * p + c];
+  }
+  W[d.w + e] = v;
+}
+
+template <typename T>
+__global__ void stack_kernel(const StackDesc<T>* __restrict__ descs) {
+  const StackDesc<T> d = descs[blockIdx.y];
+  const int64_t k = (int64_t)d.ns + d.nb;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * d.ns) return;
+  const int64_t c = e / k, r = e % k;
+  d.dst[e] = r < d.ns ? d.top[r + c * d.ns] : d.bot[(r - d.ns) + c * d.nb];
 }
 
 }  // namespace
@@ -424,14 +401,6 @@ void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int 
   hipLaunchKernelGGL(diag_block_kernel<T>, dim3(nd), dim3(256), 0, s, panel, inv, dvec, d, J, breakdown);
 }
 
-template <typename T>
-void front_panel_trsm(T* panel, const T* inv, const T* dvec, const DiagDesc* d, int nd, int J, int max_rows,
-                      hipStream_t s) {
-  if (nd <= 0 || max_rows <= 0) return;
-  int gx = (max_rows + PT_ROWS - 1) / PT_ROWS;
-  hipLaunchKernelGGL(panel_trsm_kernel<T>, dim3(gx, nd), dim3(256), 0, s, panel, inv, dvec, d, J);
-}
-
 template <typename Ts, typename T>
 void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
                       hipStream_t s) {
@@ -450,12 +419,18 @@ void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, 
 }
 
 template <typename T>
-void solve_gather_struct(T* Xb, const T* X, const int32_t* srows, const SolveDesc* d, int nd, int p, int max_nb,
-                         hipStream_t s) {
-  if (nd <= 0 || max_nb <= 0) return;
-  int64_t tot = (int64_t)max_nb * p;
-  hipLaunchKernelGGL(gather_struct_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, Xb, X, srows,
+void solve_gather_back(T* W, const T* Y, const T* X, const int32_t* srows, const SolveDesc* d, int nd, int p,
+                       int max_k, hipStream_t s) {
+  if (nd <= 0 || max_k <= 0) return;
+  int64_t tot = (int64_t)max_k * p;
+  hipLaunchKernelGGL(gather_back_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, Y, X, srows,
                      d, p);
+}
+
+template <typename T>
+void front_stack(const StackDesc<T>* d, int nd, int64_t max_elems, hipStream_t s) {
+  if (nd <= 0 || max_elems <= 0) return;
+  hipLaunchKernelGGL(stack_kernel<T>, dim3((unsigned)((max_elems + 255) / 256), nd), dim3(256), 0, s, d);
 }
 
 #define INST(T)                                                                                                      \
@@ -467,9 +442,10 @@ void solve_gather_struct(T* Xb, const T* X, const int32_t* srows, const SolveDes
   template void front_extend_add_lu<T>(T*, T*, T*, const int32_t*, const ExtDesc*, int, int, hipStream_t);           \
   template void front_diag_block_lu<T>(T*, T*, T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);            \
   template void front_diag_block<T>(T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);                       \
-  template void front_panel_trsm<T>(T*, const T*, const T*, const DiagDesc*, int, int, int, hipStream_t);            \
   template void solve_extend_add<T>(T*, const T*, const int32_t*, const SolveExt*, int, int, int, hipStream_t);      \
-  template void solve_gather_struct<T>(T*, const T*, const int32_t*, const SolveDesc*, int, int, int, hipStream_t);
+  template void solve_gather_back<T>(T*, const T*, const T*, const int32_t*, const SolveDesc*, int, int, int,        \
+                                     hipStream_t);                                                                   \
+  template void front_stack<T>(const StackDesc<T>*, int, int64_t, hipStream_t);
 INST(zd)
 INST(zf)
 #undef INST
