@@ -87,218 +87,295 @@ __global__ void extend_add_kernel(T* __restrict__ panel, T* __restrict__ upd, co
   }
 }
 
-// One workgroup per front: LDL^T of the jb x jb diagonal block in LDS, then the
-// inverse of its unit lower factor.
-// Inverse of the unit lower triangle stored in Ab (jb x jb) into Xb, by
-// 16 x 16 sub-blocks:
-//  (1) X_II = L_II^-1 for every diagonal sub-block (in parallel);
-//  (2) for block rows I = 1, 2, ...: X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ.
-template <typename T>
-__device__ void unit_lower_inverse(T (*Ab)[FB + 1], T (*Xb)[FB + 1], T (*Tm)[FB], int jb) {
-  const int tid = threadIdx.x;
-  constexpr int SB = 16;
-  const int nsb = (jb + SB - 1) / SB;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    Xb[r][c] = (r == c) ? ST<T>::one() : ST<T>::zero();
-  }
-  __syncthreads();
-  if (tid < nsb * SB) {
-    const int b = tid / SB, c = b * SB + tid % SB;
-    const int rend = min(jb, (b + 1) * SB);
-    if (c < jb)
-      for (int r = c + 1; r < rend; ++r) {
-        T s = ST<T>::zero();
-        for (int t = c; t < r; ++t) s = fma_(s, Ab[r][t], Xb[t][c]);
-        Xb[r][c] = neg(s);
-      }
-  }
-  __syncthreads();
-  for (int I = 1; I < nsb; ++I) {
-    const int r0 = I * SB, rn = min(SB, jb - r0), cols = r0;
-    for (int e = tid; e < rn * cols; e += blockDim.x) {
-      int r = e % rn, c = e / rn;
-      T s = ST<T>::zero();
-      for (int t = (c / SB) * SB; t < r0; ++t) s = fma_(s, Ab[r0 + r][t], Xb[t][c]);
-      Tm[r][c] = s;
-    }
-    __syncthreads();
-    for (int e = tid; e < rn * cols; e += blockDim.x) {
-      int r = e % rn, c = e / rn;
-      T s = ST<T>::zero();
-      for (int t = 0; t <= r; ++t) s = fma_(s, Xb[r0 + r][r0 + t], Tm[t][c]);
-      Xb[r0 + r][c] = neg(s);
-    }
-    __syncthreads();
-  }
+// Blocked factorization of the jb x jb diagonal block of step J (jb <= FB =
+// 64), one workgroup (4 waves) per front, in 16-column panels so that only
+// the 16 x 16 diagonal sub-blocks are eliminated column by column (by one
+// wave, exchanging through LDS without workgroup barriers); everything else is
+// small dense products over all threads.  For panel p (columns c0 = 16p ..):
+//  A. wave 0: LDL^T (LU: L D U) of the 16 x 16 sub-block A_pp, and the
+//     inverse X_pp of its unit lower factor (LU: also Y_pp = (U_pp^T)^-1);
+//  B. rows below: L_ip = A_ip X_pp^T D_p^-1 (LU: A_ip U_pp^-1 D_p^-1 with
+//     U_pp^-1 = Y_pp^T, and the row panel U_pi = D_p^-1 X_pp A_pi);
+//  C. trailing block: A_ij -= L_ip D_p L_jp^T (LU: L_ip D_p U_pj).
+// Then the off-diagonal blocks of X = L^-1 by block rows,
+// X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ (LU: Y from U^T likewise).
+// LDS: A holds the block, then L (strict lower), D (diagonal) and, for LU,
+// U (strict upper); X holds L^-1 in its lower triangle and, for LU, (U^T)^-1
+// transposed in its upper triangle (both unit diagonal).
+constexpr int SBK = 16;  // sub-block (panel) width
+
+// 1 / d for a pivot: conj(d) / |d|^2 with one real division (the pivots here
+// are far from the range where |d|^2 under- or overflows).
+__device__ inline zd recip(zd a) {
+  const double s = 1.0 / (a.re * a.re + a.im * a.im);
+  return zd{a.re * s, -a.im * s};
+}
+__device__ inline zf recip(zf a) {
+  const float s = 1.0f / (a.re * a.re + a.im * a.im);
+  return zf{a.re * s, -a.im * s};
 }
 
-// LU of the jb x jb diagonal block of a front without pivoting (complex
-// Hermitian pencils): L (unit lower) into the L panel, U^T (unit lower) into
-// the U panel, D into dvec, and the inverses of both unit lower blocks.
-template <typename T>
-__global__ __launch_bounds__(256) void diag_block_lu_kernel(T* __restrict__ panel, T* __restrict__ upanel,
-                                                            T* __restrict__ inv, T* __restrict__ uinv,
-                                                            T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
-                                                            int J, int* breakdown) {
+// Component-wise select.  Writing c ? a : b on the complex structs makes the
+// compiler select between their addresses, which keeps register arrays of
+// them in scratch memory.
+__device__ inline zd sel(bool c, zd a, zd b) { return zd{c ? a.re : b.re, c ? a.im : b.im}; }
+__device__ inline zf sel(bool c, zf a, zf b) { return zf{c ? a.re : b.re, c ? a.im : b.im}; }
+
+template <typename T, bool LU>
+__global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel, T* __restrict__ upanel,
+                                                           T* __restrict__ inv, T* __restrict__ uinv,
+                                                           T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
+                                                           int J, int* breakdown) {
   const DiagDesc d = descs[blockIdx.x];
   if (J >= d.ns) return;
   const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
-  __shared__ T Ab[FB][FB + 1];
-  __shared__ T Xb[FB][FB + 1];
-  __shared__ T Tm[16][FB];
-  const int tid = threadIdx.x;
+  __shared__ T A[FB][FB + 1];
+  __shared__ T X[FB][FB + 1];
+  __shared__ T Tm[SBK][FB - SBK + 1];  // block-row products of the inverse
+  __shared__ T Dv[FB], Di[FB];          // pivots and their inverses
+  __shared__ T cb[2][SBK], rb[2][SBK];  // column / row exchange inside a sub-block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const T one = ST<T>::one(), zero = ST<T>::zero();
   T* P = panel + d.panel;
-  T* U = upanel + d.panel;
+  T* U = LU ? upanel + d.panel : nullptr;
   const int64_t k = d.k, ns = d.ns;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    Ab[r][c] = (r >= c) ? P[(J + r) + (int64_t)(J + c) * k] : U[(J + c) + (int64_t)(J + r) * k];
-  }
-  __syncthreads();
-  for (int c = 0; c < jb; ++c) {
-    T dc = Ab[c][c];
-    if (abs2(dc) == 0.0) {
-      if (tid == 0) atomicExch(breakdown, 1);
-      dc = ST<T>::one();
-    }
-    const T dinv = inv_(dc);
-    __syncthreads();
-    for (int r = c + 1 + tid; r < jb; r += blockDim.x) {
-      Ab[r][c] = mul(Ab[r][c], dinv);  // L(r, c)
-      Ab[c][r] = mul(Ab[c][r], dinv);  // U(c, r)
-    }
-    __syncthreads();
-    // trailing update: A(r, q) -= L(r, c) d U(c, q) for r, q in (c, jb)
-    const int m = jb - c - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      int r = c + 1 + e % m, q = c + 1 + e / m;
-      Ab[r][q] = sub(Ab[r][q], mul(mul(Ab[r][c], dc), Ab[c][q]));
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    if (r >= c) {
-      P[(J + r) + (int64_t)(J + c) * k] = Ab[r][c];
-      U[(J + r) + (int64_t)(J + c) * k] = (r == c) ? Ab[r][c] : Ab[c][r];
-    }
-  }
-  for (int c = tid; c < jb; c += blockDim.x) dvec[d.first + J + c] = Ab[c][c];
-  __syncthreads();
-  unit_lower_inverse<T>(Ab, Xb, Tm, jb);
-  T* X = inv + d.inv;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    X[(J + r) + (int64_t)(J + c) * ns] = (r >= c) ? Xb[r][c] : ST<T>::zero();
-  }
-  __syncthreads();
-  // the same for U^T: move its strict lower part into Ab's lower triangle
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    if (r > c) Xb[r][c] = Ab[c][r];
-  }
-  __syncthreads();
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    if (r > c) Ab[r][c] = Xb[r][c];
-  }
-  __syncthreads();
-  unit_lower_inverse<T>(Ab, Xb, Tm, jb);
-  T* XU = uinv + d.inv;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    XU[(J + r) + (int64_t)(J + c) * ns] = (r >= c) ? Xb[r][c] : ST<T>::zero();
-  }
-}
 
-template <typename T>
-__global__ __launch_bounds__(256) void diag_block_kernel(T* __restrict__ panel, T* __restrict__ inv,
-                                                         T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
-                                                         int J, int* breakdown) {
-  const DiagDesc d = descs[blockIdx.x];
-  if (J >= d.ns) return;
-  const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
-  __shared__ T Ab[FB][FB + 1];  // Ab[r][c]
-  __shared__ T Xb[FB][FB + 1];
-  __shared__ T Tm[16][FB];
-  const int tid = threadIdx.x;
-  T* P = panel + d.panel;
-  const int64_t k = d.k;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    Ab[r][c] = (r >= c) ? P[(J + r) + (int64_t)(J + c) * k] : ST<T>::zero();
+  for (int e = tid; e < FB * FB; e += blockDim.x) {
+    const int r = e & (FB - 1), c = e >> 6;
+    T v = zero;
+    if (r < jb && c < jb) {
+      if (r >= c)
+        v = P[(J + r) + (int64_t)(J + c) * k];
+      else if (LU)
+        v = U[(J + c) + (int64_t)(J + r) * k];
+    }
+    A[r][c] = v;
+    X[r][c] = zero;
   }
   __syncthreads();
-  // right-looking unblocked LDL^T
-  for (int c = 0; c < jb; ++c) {
-    T dc = Ab[c][c];
-    if (abs2(dc) == 0.0) {
-      if (tid == 0) atomicExch(breakdown, 1);
-      dc = ST<T>::one();
-    }
-    T dinv = inv_(dc);
-    __syncthreads();
-    for (int r = c + 1 + tid; r < jb; r += blockDim.x) Ab[r][c] = mul(Ab[r][c], dinv);
-    __syncthreads();
-    // trailing lower update: A(r, q) -= L(r,c) d L(q,c), q in (c, jb), r >= q
-    const int m = jb - c - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      int r = c + 1 + e % m, q = c + 1 + e / m;
-      if (r >= q) Ab[r][q] = sub(Ab[r][q], mul(mul(Ab[r][c], dc), Ab[q][c]));
-    }
-    __syncthreads();
-  }
-  // write back L (strict lower) and D
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    if (r >= c) P[(J + r) + (int64_t)(J + c) * k] = Ab[r][c];
-  }
-  for (int c = tid; c < jb; c += blockDim.x) dvec[d.first + J + c] = Ab[c][c];
-  // inverse of the unit lower block, by 16 x 16 sub-blocks:
-  //  (1) X_II = L_II^-1 for every diagonal sub-block (in parallel);
-  //  (2) for block rows I = 1, 2, ...: X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ.
-  constexpr int SB = 16;
-  const int nsb = (jb + SB - 1) / SB;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    Xb[r][c] = (r == c) ? ST<T>::one() : ST<T>::zero();
-  }
-  __syncthreads();
-  if (tid < nsb * SB) {
-    const int b = tid / SB, c = b * SB + tid % SB;
-    const int rend = min(jb, (b + 1) * SB);
-    if (c < jb)
-      for (int r = c + 1; r < rend; ++r) {
-        T s = ST<T>::zero();
-        for (int t = c; t < r; ++t) s = fma_(s, Ab[r][t], Xb[t][c]);
-        Xb[r][c] = neg(s);
+
+  const int np = (jb + SBK - 1) / SBK;
+  for (int p = 0; p < np; ++p) {
+    const int c0 = p * SBK, pb = min(SBK, jb - c0);
+    // ---- A: the diagonal sub-block, by wave 0 ----
+    if (wave == 0) {
+      const int l = lane & (SBK - 1);
+      T a[SBK];
+#pragma unroll
+      for (int t = 0; t < SBK; ++t) a[t] = A[c0 + l][c0 + t];
+#pragma unroll
+      for (int j = 0; j < SBK; ++j) {
+        if (j >= pb) continue;  // partial last panel (uniform)
+        const int b = j & 1;
+        if (lane < SBK) {
+          cb[b][lane] = a[j];  // column j
+          if (LU && lane == j) {
+#pragma unroll
+            for (int t = j + 1; t < SBK; ++t) rb[b][t] = a[t];  // row j
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        T dj = cb[b][j];
+        if (abs2(dj) == 0.0) {
+          if (lane == 0) atomicExch(breakdown, 1);
+          dj = one;
+        }
+        const T dinv = recip(dj);
+        const bool below = l > j;
+        const T g = mul(a[j], dinv);  // L(l, j) for l > j
+#pragma unroll
+        for (int t = j + 1; t < SBK; ++t) {
+          const T w = LU ? rb[b][t] : cb[b][t];  // A(j, t) (= A(t, j) for LDL^T)
+          const T nv = sub(a[t], mul(g, w));
+          a[t] = sel(below, nv, a[t]);
+        }
+        a[j] = sel(below, g, a[j]);
+        if (LU && l == j) {
+#pragma unroll
+          for (int t = j + 1; t < SBK; ++t) a[t] = mul(a[t], dinv);  // U(j, t)
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_sched_barrier(0);
       }
-  }
-  __syncthreads();
-  for (int I = 1; I < nsb; ++I) {
-    const int r0 = I * SB, rn = min(SB, jb - r0), cols = r0;
-    // Tm(r, c) = sum_{t in [c's block start, r0)} L(r0 + r, t) X(t, c)
-    for (int e = tid; e < rn * cols; e += blockDim.x) {
-      int r = e % rn, c = e / rn;
-      T s = ST<T>::zero();
-      for (int t = (c / SB) * SB; t < r0; ++t) s = fma_(s, Ab[r0 + r][t], Xb[t][c]);
-      Tm[r][c] = s;
+      if (lane < pb) {
+#pragma unroll
+        for (int t = 0; t < SBK; ++t)
+          if (t < pb && (LU || t <= l)) A[c0 + l][c0 + t] = a[t];
+        T dl = zero;  // the diagonal entry, selected with static register indices
+#pragma unroll
+        for (int t = 0; t < SBK; ++t) dl = sel(t == l, a[t], dl);
+        Dv[c0 + l] = dl;
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+      // inverses of the unit triangles: lanes 0..15 column l of X_pp (from L),
+      // lanes 16..31 column l of Y_pp (from U^T, i.e. U read transposed)
+      if (lane < (LU ? 2 * SBK : SBK)) {
+        const bool upper = lane >= SBK;
+        T x[SBK];
+#pragma unroll
+        for (int r = 0; r < SBK; ++r) {
+          T s = zero;
+#pragma unroll
+          for (int t = 0; t < r; ++t) s = fma_(s, upper ? A[c0 + t][c0 + r] : A[c0 + r][c0 + t], x[t]);
+          x[r] = sel(r < l, zero, sel(r == l, one, neg(s)));
+          __builtin_amdgcn_sched_barrier(0);  // keep each row's loads with it (register pressure)
+        }
+        if (l < pb) {
+#pragma unroll
+          for (int r = 0; r < SBK; ++r) {
+            if (r < pb && r >= l) {
+              if (upper) {
+                if (r > l) X[c0 + l][c0 + r] = x[r];  // Y(r, l), stored transposed
+              } else {
+                X[c0 + r][c0 + l] = x[r];
+              }
+            }
+          }
+          if (!upper) Di[c0 + l] = recip(Dv[c0 + l]);
+        }
+      }
     }
     __syncthreads();
-    for (int e = tid; e < rn * cols; e += blockDim.x) {
-      int r = e % rn, c = e / rn;
-      T s = ST<T>::zero();
-      for (int t = 0; t <= r; ++t) s = fma_(s, Xb[r0 + r][r0 + t], Tm[t][c]);
-      Xb[r0 + r][c] = neg(s);
+    // ---- B: the panel below (and, for LU, the row panel to the right) ----
+    const int r1 = c0 + SBK, nr = jb - r1;
+    if (nr > 0) {
+      const int items = nr * SBK * (LU ? 2 : 1);
+      constexpr int NIT = (FB - SBK) * SBK * (LU ? 2 : 1) / 256;  // items per thread at most
+      T res[NIT];
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int e = tid + 256 * it;
+        res[it] = zero;
+        if (e >= items) continue;
+        const int side = e / (nr * SBK), f = e % (nr * SBK);
+        const int i = r1 + f / SBK, t = f % SBK;
+        T s = zero;
+        // (unrolled over the 16 terms; the zero triangle of Z contributes 0)
+        if (side == 0) {
+          // L(i, c0+t) = sum_q A(i, c0+q) Z(t, q) / D_t, Z = X_pp (LDL^T) or Y_pp (LU)
+#pragma unroll
+          for (int q = 0; q < SBK; ++q) {
+            const T z = sel(q == t, one, sel(q < t, LU ? X[c0 + q][c0 + t] : X[c0 + t][c0 + q], zero));
+            s = fma_(s, A[i][c0 + q], z);
+          }
+        } else {
+          // U(c0+t, i) = D_t^-1 sum_q X_pp(t, q) A(c0+q, i)
+#pragma unroll
+          for (int q = 0; q < SBK; ++q)
+            s = fma_(s, sel(q == t, one, sel(q < t, X[c0 + t][c0 + q], zero)), A[c0 + q][i]);
+        }
+        res[it] = mul(s, Di[c0 + t]);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int e = tid + 256 * it;
+        if (e >= items) continue;
+        const int side = e / (nr * SBK), f = e % (nr * SBK);
+        const int i = r1 + f / SBK, t = f % SBK;
+        if (side == 0)
+          A[i][c0 + t] = res[it];
+        else
+          A[c0 + t][i] = res[it];
+      }
+      __syncthreads();
+      // ---- C: trailing update, 3 x 3 tiles per thread ----
+      const int nt = (nr + 2) / 3;
+      for (int e = tid; e < nt * nt; e += blockDim.x) {
+        const int ti = e % nt, tj = e / nt;
+        const int i0 = r1 + 3 * ti, j0 = r1 + 3 * tj;
+        if (!LU && i0 + 2 < j0) continue;  // strictly above the diagonal
+        T acc[3][3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+          for (int v = 0; v < 3; ++v) acc[u][v] = zero;
+#pragma unroll 4
+        for (int q = 0; q < SBK; ++q) {
+          T li[3], rj[3];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) {
+            const int i = min(i0 + u, FB - 1), j = min(j0 + u, FB - 1);
+            li[u] = A[i][c0 + q];
+            rj[u] = LU ? A[c0 + q][j] : mul(Dv[c0 + q], A[j][c0 + q]);
+          }
+          if (LU) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) li[u] = mul(li[u], Dv[c0 + q]);
+          }
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) acc[u][v] = fma_(acc[u][v], li[u], rj[v]);
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+          for (int v = 0; v < 3; ++v) {
+            const int i = i0 + u, j = j0 + v;
+            if (i < jb && j < jb && (LU || i >= j)) A[i][j] = sub(A[i][j], acc[u][v]);
+          }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  T* X = inv + d.inv;
-  const int64_t ns = d.ns;
-  for (int e = tid; e < jb * jb; e += blockDim.x) {
-    int r = e % jb, c = e / jb;
-    X[(J + r) + (int64_t)(J + c) * ns] = (r >= c) ? Xb[r][c] : ST<T>::zero();
+
+  // ---- off-diagonal blocks of the inverse(s), by block rows ----
+  for (int I = 1; I < np; ++I) {
+    const int ri = I * SBK, nri = min(SBK, jb - ri), ncol = ri;  // block row I, columns [0, ri)
+    for (int side = 0; side < (LU ? 2 : 1); ++side) {
+      // Tm(r, c) = sum_{t in [c's block start, ri)} Lt(ri + r, t) Z(t, c), with Lt = L (side 0)
+      // or U^T (side 1) and Z = X or Y
+      for (int e = tid; e < SBK * ncol; e += blockDim.x) {
+        const int r = e % SBK, c = e / SBK;
+        T s = zero;
+        if (r < nri) {
+          for (int t0 = (c / SBK) * SBK; t0 < ri; t0 += SBK) {
+#pragma unroll
+            for (int u = 0; u < SBK; ++u) {
+              const int t = t0 + u;
+              const T lt = side ? A[t][ri + r] : A[ri + r][t];
+              const T z = sel(t == c, one, sel(t > c, side ? X[c][t] : X[t][c], zero));
+              s = fma_(s, lt, z);
+            }
+          }
+        }
+        Tm[r][c] = s;
+      }
+      __syncthreads();
+      // Z(ri + r, c) = -sum_{t <= r} Z_II(r, t) Tm(t, c)
+      for (int e = tid; e < SBK * ncol; e += blockDim.x) {
+        const int r = e % SBK, c = e / SBK;
+        if (r >= nri) continue;
+        T s = zero;
+#pragma unroll
+        for (int t = 0; t < SBK; ++t) {
+          const T z = sel(t == r, one, sel(t < r, side ? X[ri + t][ri + r] : X[ri + r][ri + t], zero));
+          s = fma_(s, z, Tm[t][c]);
+        }
+        if (side)
+          X[c][ri + r] = neg(s);
+        else
+          X[ri + r][c] = neg(s);
+      }
+      __syncthreads();
+    }
+  }
+
+  for (int c = tid; c < jb; c += blockDim.x) dvec[d.first + J + c] = Dv[c];
+  T* Xo = inv + d.inv;
+  T* Yo = LU ? uinv + d.inv : nullptr;
+  for (int e = tid; e < FB * FB; e += blockDim.x) {
+    const int r = e & (FB - 1), c = e >> 6;
+    if (r >= jb || c >= jb) continue;
+    if (r >= c) {
+      P[(J + r) + (int64_t)(J + c) * k] = sel(r == c, Dv[c], A[r][c]);
+      if (LU) U[(J + r) + (int64_t)(J + c) * k] = sel(r == c, Dv[c], A[c][r]);
+    }
+    Xo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, X[r][c], sel(r == c, one, zero));
+    if (LU) Yo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, X[c][r], sel(r == c, one, zero));
   }
 }
 
@@ -385,7 +462,7 @@ template <typename T>
 void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
                          int* breakdown, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(diag_block_lu_kernel<T>, dim3(nd), dim3(256), 0, s, panel, upanel, inv, uinv, dvec, d, J,
+  hipLaunchKernelGGL((diag_blocked_kernel<T, true>), dim3(nd), dim3(256), 0, s, panel, upanel, inv, uinv, dvec, d, J,
                      breakdown);
 }
 
@@ -398,7 +475,8 @@ void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, i
 template <typename T>
 void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(diag_block_kernel<T>, dim3(nd), dim3(256), 0, s, panel, inv, dvec, d, J, breakdown);
+  hipLaunchKernelGGL((diag_blocked_kernel<T, false>), dim3(nd), dim3(256), 0, s, panel, nullptr, inv, nullptr, dvec,
+                     d, J, breakdown);
 }
 
 template <typename Ts, typename T>
