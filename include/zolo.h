@@ -128,7 +128,10 @@ const char* zolo_version(void);
  * tol_gmres = 1e-10, max_subspace_iter = 6, max_gmres_iter = 60, FP64. */
 zolo_status zolo_opts_default(zolo_opts* out);
 
-/* Context on one HIP device: selects the device, creates nothing else. */
+/* Context on one HIP device: selects the device, creates nothing else.
+ * Device memory released by the library (factors, workspaces, results) is
+ * kept in a process-wide cache and reused by later allocations of about the
+ * same size; destroying a context returns the cached blocks to HIP. */
 zolo_status zolo_ctx_create(int hip_device, zolo_ctx** out);
 void zolo_ctx_destroy(zolo_ctx* ctx);
 

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,24 +62,90 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// RAII owner of device allocations
+// Device memory cache.  Blocks released by arenas are kept, after a device
+// synchronization (what hipFree would imply), and handed out again to later
+// allocations of about the same size, so that repeated queries do not pay for
+// hipMalloc / hipFree of their multi-gigabyte factors.  When hipMalloc fails
+// the cached blocks are freed and the allocation is tried once more.  The
+// cache is never destroyed (it lives until the process ends).
+class DevicePool {
+ public:
+  static DevicePool& get() {
+    static DevicePool* p = new DevicePool();
+    return *p;
+  }
+  // rounded request: 1 MiB granules from 1 MiB up, powers of two below
+  static size_t round(size_t bytes) {
+    if (bytes >= (1u << 20)) return (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    size_t r = 256;
+    while (r < bytes) r <<= 1;
+    return r;
+  }
+  void* take(size_t bytes, int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    auto it = free_.lower_bound(bytes);
+    for (; it != free_.end() && it->first <= bytes + bytes / 8; ++it)
+      if (it->second.first == dev) {
+        void* p = it->second.second;
+        cached_ -= it->first;
+        free_.erase(it);
+        return p;
+      }
+    return nullptr;
+  }
+  void give(void* p, size_t bytes, int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    free_.insert({bytes, {dev, p}});
+    cached_ += bytes;
+  }
+  void trim() {
+    std::lock_guard<std::mutex> lk(m_);
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : free_) (void)hipFree(kv.second.second);
+    free_.clear();
+    cached_ = 0;
+  }
+
+ private:
+  std::mutex m_;
+  std::multimap<size_t, std::pair<int, void*>> free_;  // block size -> (device, pointer)
+  size_t cached_ = 0;
+};
+
+// RAII owner of device allocations (through the cache above)
 struct DevArena {
-  std::vector<void*> ptrs;
+  struct Block {
+    void* p;
+    size_t bytes;
+    int dev;
+  };
+  std::vector<Block> ptrs;
   ~DevArena() { release(); }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    if (ptrs.empty()) return;
+    (void)hipDeviceSynchronize();  // no kernel may still use a block handed out again
+    for (const Block& b : ptrs) DevicePool::get().give(b.p, b.bytes, b.dev);
     ptrs.clear();
   }
   template <typename T>
   int alloc(T** out, size_t count) {
-    void* p = nullptr;
-    size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-      return ZOLO_ENOMEM;
+    const size_t bytes = DevicePool::round(std::max<size_t>(count, 1) * sizeof(T));
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    void* p = DevicePool::get().take(bytes, dev);
+    if (!p) {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        DevicePool::get().trim();
+        e = hipMalloc(&p, bytes);
+      }
+      if (e != hipSuccess) {
+        set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        return ZOLO_ENOMEM;
+      }
     }
-    ptrs.push_back(p);
+    ptrs.push_back({p, bytes, dev});
     *out = (T*)p;
     return ZOLO_OK;
   }
@@ -521,7 +588,10 @@ extern "C" zolo_status zolo_ctx_create(int dev, zolo_ctx** out) {
   return ZOLO_OK;
 }
 
-extern "C" void zolo_ctx_destroy(zolo_ctx* c) { delete c; }
+extern "C" void zolo_ctx_destroy(zolo_ctx* c) {
+  delete c;
+  DevicePool::get().trim();  // return cached device memory
+}
 
 static zolo_status build_layout(zolo_pencil* P) {
   const Symbolic& S = P->S;
