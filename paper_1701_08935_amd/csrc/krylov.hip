@@ -613,37 +613,61 @@ __device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
         sn_s[k] = sn;
         ph_s[k] = ph;
         pp_s[k] = p;
-        qq_s[k] = q < n ? q : -1;
+        // q >= 0: rotate the pair; -2: q is the padding index of an odd n; -(q + 3): no rotation
+        qq_s[k] = q >= n ? -2 : (sn != 0.0 ? q : -q - 3);
       }
       __syncthreads();
-      // columns of A and V: col_p <- c col_p - s conj(ph) col_q ; col_q <- s ph col_p + c col_q
+      // One phase per round.  With J_k = [[c, s ph], [-s conj(ph), c]] on the index pair
+      // (p_k, q_k) (columns: col_p <- c col_p - s conj(ph) col_q, col_q <- s ph col_p + c col_q;
+      // rows: the conjugate transpose), A <- J^H A J acts on each 2 x 2 block of rows
+      // {p_k1, q_k1} and columns {p_k2, q_k2} independently, and the pairs partition the
+      // indices, so every entry is read and written by one thread; V <- V J likewise by rows.
+      for (int e = tid; e < half * half; e += nt) {
+        const int k1 = e / half, k2 = e - k1 * half;
+        const int p1 = pp_s[k1], q1 = qq_s[k1], p2 = pp_s[k2], q2 = qq_s[k2];
+        const bool r1 = q1 >= 0, r2 = q2 >= 0;  // a rotation on this pair
+        const bool h1 = q1 != -2, h2 = q2 != -2;  // q index inside the matrix (not the padding)
+        const int qa = h1 ? (r1 ? q1 : -q1 - 3) : 0, qb = h2 ? (r2 ? q2 : -q2 - 3) : 0;
+        if (!r1 && !r2) continue;  // J = I on both sides
+        T a00 = A[p1 + (int64_t)p2 * n];
+        T a01 = h2 ? A[p1 + (int64_t)qb * n] : ST<T>::zero();
+        T a10 = h1 ? A[qa + (int64_t)p2 * n] : ST<T>::zero();
+        T a11 = (h1 && h2) ? A[qa + (int64_t)qb * n] : ST<T>::zero();
+        if (r2) {  // columns: M <- M J_k2
+          const double c = cs_s[k2], sn = sn_s[k2];
+          const T ph = ph_s[k2], phc = conj_(ph);
+          const T b00 = sub(scl(a00, c), scl(mul(phc, a01), sn)), b01 = add(scl(mul(ph, a00), sn), scl(a01, c));
+          const T b10 = sub(scl(a10, c), scl(mul(phc, a11), sn)), b11 = add(scl(mul(ph, a10), sn), scl(a11, c));
+          a00 = b00;
+          a01 = b01;
+          a10 = b10;
+          a11 = b11;
+        }
+        if (r1) {  // rows: M <- J_k1^H M
+          const double c = cs_s[k1], sn = sn_s[k1];
+          const T ph = ph_s[k1], phc = conj_(ph);
+          const T b00 = sub(scl(a00, c), scl(mul(ph, a10), sn)), b10 = add(scl(mul(phc, a00), sn), scl(a10, c));
+          const T b01 = sub(scl(a01, c), scl(mul(ph, a11), sn)), b11 = add(scl(mul(phc, a01), sn), scl(a11, c));
+          a00 = b00;
+          a10 = b10;
+          a01 = b01;
+          a11 = b11;
+        }
+        A[p1 + (int64_t)p2 * n] = a00;
+        if (h2) A[p1 + (int64_t)qb * n] = a01;
+        if (h1) A[qa + (int64_t)p2 * n] = a10;
+        if (h1 && h2) A[qa + (int64_t)qb * n] = a11;
+      }
       for (int e = tid; e < n * half; e += nt) {
-        int i = e % n, k = e / n;
-        int q = qq_s[k];
+        const int k = e / n, i = e - k * n;
+        const int q = qq_s[k];
         if (q < 0) continue;
-        int p = pp_s[k];
+        const int p = pp_s[k];
         const double c = cs_s[k], sn = sn_s[k];
         const T ph = ph_s[k], phc = conj_(ph);
-        T ap = A[i + (int64_t)p * n], aq = A[i + (int64_t)q * n];
-        A[i + (int64_t)p * n] = sub(scl(ap, c), scl(mul(phc, aq), sn));
-        A[i + (int64_t)q * n] = add(scl(mul(ph, ap), sn), scl(aq, c));
-        T vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
+        const T vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
         V[i + (int64_t)p * n] = sub(scl(vp, c), scl(mul(phc, vq), sn));
         V[i + (int64_t)q * n] = add(scl(mul(ph, vp), sn), scl(vq, c));
-      }
-      __threadfence_block();
-      __syncthreads();
-      // rows of A: row_p <- c row_p - s ph row_q ; row_q <- s conj(ph) row_p + c row_q
-      for (int e = tid; e < n * half; e += nt) {
-        int j = e % n, k = e / n;
-        int q = qq_s[k];
-        if (q < 0) continue;
-        int p = pp_s[k];
-        const double c = cs_s[k], sn = sn_s[k];
-        const T ph = ph_s[k], phc = conj_(ph);
-        T ap = A[p + (int64_t)j * n], aq = A[q + (int64_t)j * n];
-        A[p + (int64_t)j * n] = sub(scl(ap, c), scl(mul(ph, aq), sn));
-        A[q + (int64_t)j * n] = add(scl(mul(phc, ap), sn), scl(aq, c));
       }
       __threadfence_block();
       __syncthreads();
