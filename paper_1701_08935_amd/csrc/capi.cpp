@@ -293,7 +293,8 @@ struct zolo_pencil {
   DiagDesc* diag = nullptr;
   std::vector<int> lvl_diag_off, lvl_diag_cnt;
   std::vector<std::vector<int>> lvl_diag_nJ, lvl_trsm_rows;  // per level per step
-  int64_t inv_scratch = 0;  // FB x ns per front of a level (L11 inverse temporaries)
+  int64_t inv_scratch = 0;   // L11 inverse temporaries of one level (recursive doubling, per side)
+  int64_t conv_scratch = 0;  // -L21 X of one level's fronts before stacking (per side)
   bool cplx() const { return scalar == ZOLO_COMPLEX128; }
 };
 
@@ -609,6 +610,7 @@ static zolo_status build_layout(zolo_pencil* P) {
   P->lvl_upd_end.assign(nl, 0);
   int64_t po = 0, io = 0, uo = 0;
   P->inv_scratch = 0;
+  P->conv_scratch = 0;
   for (int L = 0; L < nl; ++L) {
     P->lvl_panel_begin[L] = po;
     P->lvl_inv_begin[L] = io;
@@ -623,10 +625,28 @@ static zolo_status build_layout(zolo_pencil* P) {
       io += (int64_t)F.ns * F.ns;
       P->upd_off[f] = uo;
       uo += (int64_t)F.nb * F.nb;
-      scr += (int64_t)FB * F.ns;
       P->lvl_order.push_back(f);
     }
+    // recursive doubling of the inverse: at block size s every block holds an h2 x h
+    // temporary (h = s / 2); the level needs the largest sum over its fronts at one s
+    for (int64_t sz = 2 * FB;; sz *= 2) {
+      const int64_t h = sz / 2;
+      int64_t tot = 0;
+      bool any = false;
+      for (int f : S.levels[L]) {
+        const int64_t ns = S.fronts[f].ns;
+        for (int64_t r0 = 0; r0 + h < ns; r0 += sz) {
+          tot += std::min(h, ns - r0 - h) * h;
+          any = true;
+        }
+      }
+      if (!any) break;
+      scr = std::max(scr, tot);
+    }
+    int64_t cv = 0;
+    for (int f : S.levels[L]) cv += (int64_t)S.fronts[f].nb * S.fronts[f].ns;
     P->inv_scratch = std::max(P->inv_scratch, scr);
+    P->conv_scratch = std::max(P->conv_scratch, cv);
     P->lvl_panel_end[L] = po;
     P->lvl_inv_end[L] = io;
     P->lvl_upd_end[L] = uo;
@@ -967,13 +987,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   DevArena& tmp = fw->tmp;
   CHK(tmp.alloc(&fw->upd, P->upd_total));
   CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch * (lu ? 2 : 1), 1)));
-  int64_t cmax = 0;
-  for (int L = 0; L < nl; ++L) {
-    int64_t c = 0;
-    for (int f : S.levels[L]) c += (int64_t)S.fronts[f].nb * S.fronts[f].ns;
-    cmax = std::max(cmax, c);
-  }
-  CHK(tmp.alloc(&fw->ctmp, std::max<int64_t>(cmax * (lu ? 2 : 1), 1)));
+  CHK(tmp.alloc(&fw->ctmp, std::max<int64_t>(P->conv_scratch * (lu ? 2 : 1), 1)));
   CHK(tmp.alloc(&fw->flag, 1));
   T* upd = fw->upd;
   T* scratch = fw->scratch;
@@ -1104,70 +1118,70 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       g.cnt = (int)gd.size() - g.off;
       lg[L].schur = g;
     }
-    // inverse of L11 by block rows: Tmp = L(I, 0:I) X(0:I, 0:I); X(I, 0:I) = -X(I,I) Tmp
-    int maxblk = (maxns + FB - 1) / FB;
-    for (int I = 1; I < maxblk; ++I) {
+    // Inverse of L11 (LU: also of U11^T) from its 64 x 64 diagonal-block inverses by
+    // recursive doubling: at block size s = 128, 256, ... every block [X1 0; L21 X2] with
+    // inverted halves X1 = L1^-1, X2 = L2^-1 gets its lower-left quarter
+    //   X21 = -X2 (L21 X1)
+    // (T = L21 X1 with X1 lower triangular, then -X2 T with X2 lower triangular); all blocks
+    // of one size, over every front and side, are one launch each.
+    for (int64_t sz = 2 * FB;; sz *= 2) {
+      const int64_t h = sz / 2;
       GemmLaunch g1, g2;
       g1.off = (int)gd.size();
-      int64_t so = 0;
-      std::vector<std::pair<int, int64_t>> act;
-      for (int f : fs) {
-        const Front& Fr = S.fronts[f];
-        int nblk = (Fr.ns + FB - 1) / FB;
-        if (I < nblk) {
-          act.push_back({f, so});
+      std::vector<GemmDesc<T>> second;
+      for (int side = 0; side < (lu ? 2 : 1); ++side) {
+        int64_t so = 0;
+        for (int f : fs) {
+          const Front& Fr = S.fronts[f];
+          const int64_t k = (int64_t)Fr.ns + Fr.nb;
+          const T* Pn = (side ? pole->upanel : pole->panel) + P->panel_off[f];
+          T* X = (side ? pole->uinv : pole->inv) + P->inv_off[f];
+          for (int64_t r0 = 0; r0 + h < Fr.ns; r0 += sz) {
+            const int64_t h2 = std::min(h, (int64_t)Fr.ns - r0 - h);
+            T* Tb = scratch + side * P->inv_scratch + so;
+            so += h2 * h;
+            GemmDesc<T> d{};
+            d.C = Tb;  // T = L21 X1 (h2 x h)
+            d.ldc = h2;
+            d.A = Pn + (r0 + h) + r0 * k;
+            d.lda = k;
+            d.B = X + r0 + r0 * Fr.ns;
+            d.ldb = Fr.ns;
+            d.M = (int)h2;
+            d.N = (int)h;
+            d.K = (int)h;
+            d.flags = GF_BLOW;
+            d.alpha = one;
+            d.beta = zero;
+            gd.push_back(d);
+            gemm_work(d, &g1.flops, &g1.bytes);
+            g1.maxM = std::max(g1.maxM, d.M);
+            g1.maxN = std::max(g1.maxN, d.N);
+            GemmDesc<T> e{};
+            e.C = X + (r0 + h) + r0 * Fr.ns;  // X21 = -X2 T
+            e.ldc = Fr.ns;
+            e.A = X + (r0 + h) + (r0 + h) * Fr.ns;
+            e.lda = Fr.ns;
+            e.B = Tb;
+            e.ldb = h2;
+            e.M = (int)h2;
+            e.N = (int)h;
+            e.K = (int)h2;
+            e.flags = GF_ALOW;
+            e.alpha = mone;
+            e.beta = zero;
+            second.push_back(e);
+          }
         }
-        so += (int64_t)FB * Fr.ns;
-      }
-      for (int side = 0; side < (lu ? 2 : 1); ++side)
-      for (auto& fa : act) {
-        const Front& Fr = S.fronts[fa.first];
-        int64_t k = (int64_t)Fr.ns + Fr.nb;
-        int ib = std::min(FB, Fr.ns - I * FB);
-        T* Pn = (side ? pole->upanel : pole->panel) + P->panel_off[fa.first];
-        T* X = (side ? pole->uinv : pole->inv) + P->inv_off[fa.first];
-        GemmDesc<T> d{};
-        d.C = scratch + fa.second + side * P->inv_scratch;
-        d.ldc = ib;
-        d.A = Pn + (int64_t)I * FB;
-        d.lda = k;
-        d.B = X;
-        d.ldb = Fr.ns;
-        d.M = ib;
-        d.N = I * FB;
-        d.K = I * FB;
-        d.flags = 0;
-        d.alpha = one;
-        d.beta = zero;
-        gd.push_back(d);
-        gemm_work(d, &g1.flops, &g1.bytes);
-        g1.maxM = std::max(g1.maxM, d.M);
-        g1.maxN = std::max(g1.maxN, d.N);
       }
       g1.cnt = (int)gd.size() - g1.off;
+      if (g1.cnt == 0) break;
       g2.off = (int)gd.size();
-      for (int side = 0; side < (lu ? 2 : 1); ++side)
-      for (auto& fa : act) {
-        const Front& Fr = S.fronts[fa.first];
-        int ib = std::min(FB, Fr.ns - I * FB);
-        T* X = (side ? pole->uinv : pole->inv) + P->inv_off[fa.first];
-        GemmDesc<T> d{};
-        d.C = X + (int64_t)I * FB;
-        d.ldc = Fr.ns;
-        d.A = X + (int64_t)I * FB + (int64_t)I * FB * Fr.ns;
-        d.lda = Fr.ns;
-        d.B = scratch + fa.second + side * P->inv_scratch;
-        d.ldb = ib;
-        d.M = ib;
-        d.N = I * FB;
-        d.K = ib;
-        d.flags = 0;
-        d.alpha = mone;
-        d.beta = zero;
-        gd.push_back(d);
-        gemm_work(d, &g2.flops, &g2.bytes);
-        g2.maxM = std::max(g2.maxM, d.M);
-        g2.maxN = std::max(g2.maxN, d.N);
+      for (const GemmDesc<T>& e : second) {
+        gd.push_back(e);
+        gemm_work(e, &g2.flops, &g2.bytes);
+        g2.maxM = std::max(g2.maxM, e.M);
+        g2.maxN = std::max(g2.maxN, e.N);
       }
       g2.cnt = (int)gd.size() - g2.off;
       lg[L].inv1.push_back(g1);
@@ -2335,7 +2349,7 @@ int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, i
   const int64_t lu = P->cplx() ? 2 : 1;  // LU: two panels and inverses; K^-1 and K^-H solves
   const int64_t vb = P->cplx() ? 16 : 8;  // bytes per block entry
   const int64_t factors = (int64_t)r1 * lu * (P->panel_total + P->inv_total + n) * elem;
-  const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + lu * P->inv_scratch) * elem;
+  const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + lu * (P->inv_scratch + P->conv_scratch)) * elem;
   const int64_t p = nss;
   const int64_t solve = (int64_t)r1 * lu * (6 * n * p) * elem;         // W, U, Xb, t, Y, X of the solve program
   const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * vb  // basis, W, T1, Tb
