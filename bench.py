@@ -102,7 +102,11 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True, tol_refine=0.0):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_batched_c1.txt")
-GEMM_SOURCES = [os.path.join(ROOT, "paper_1701_08935_amd", "csrc", f) for f in ("gemm.hip", "gemm.h", "dev_common.h")]
+# the GEMM kernel and the host code that plans its launches (the per-launch traffic
+# depends on both)
+GEMM_SOURCES = [
+    os.path.join(ROOT, "paper_1701_08935_amd", "csrc", f) for f in ("gemm.hip", "gemm.h", "dev_common.h", "capi.cpp")
+]
 
 
 def gemm_source_hash():
