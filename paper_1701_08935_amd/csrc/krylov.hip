@@ -110,6 +110,76 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const T* __restric
   }
 }
 
+// Cholesky G + shift I = R^H R together with R^-1, for p small enough that both
+// live in LDS: one workgroup, one barrier per elimination step.  Step k reads the
+// (not yet scaled) row k of A and of Z and updates the rows below it:
+//   A(i, j) -= conj(A(k, i)) A(k, j) / d_k         (k < i <= j, the trailing upper part)
+//   Z(i, c) -= conj(A(k, i)) Z(k, c) / d_k         (i > k, c <= k)
+// where Z starts as I and ends, row by row, as R(k, k) Y with Y = R^-H (forward
+// substitution on R^H run right-looking); row k of both is scaled by 1 / sqrt(d_k)
+// at the next step, when nothing reads it.  R^-1 = Y^H.
+template <typename T>
+__global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict__ G, int p, double rel_shift,
+                                                            T* __restrict__ Rg, T* __restrict__ Rinv, int* flag) {
+  extern __shared__ char lds_raw[];
+  T* A = (T*)lds_raw;
+  T* Z = A + (int64_t)p * p;
+  const int tid = threadIdx.x, nt = blockDim.x, tx = tid & 31, ty = tid >> 5;
+  __shared__ double trace_s;
+  __shared__ int bad_s;
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < p; ++i) tr += re_(G[i + (int64_t)i * p]);
+    trace_s = tr;
+    bad_s = 0;
+  }
+  __syncthreads();
+  const double shift = rel_shift * trace_s / (p > 0 ? p : 1);
+  for (int e = tid; e < p * p; e += nt) {
+    const int i = e % p, j = e / p;
+    T v = (i <= j) ? G[e] : ST<T>::zero();
+    if (i == j) v = cvt<T, double>(re_(v) + shift);
+    A[e] = v;
+    Z[e] = i == j ? ST<T>::one() : ST<T>::zero();
+  }
+  __syncthreads();
+  double irk_prev = 1.0;
+  for (int k = 0; k <= p; ++k) {
+    // scale row k - 1 (final values of R and of Y)
+    if (k > 0) {
+      const int r = k - 1;
+      for (int j = r + tid; j < p; j += nt) A[r + (int64_t)j * p] = scl(A[r + (int64_t)j * p], irk_prev);
+      for (int c = tid; c <= r; c += nt) Z[r + (int64_t)c * p] = scl(Z[r + (int64_t)c * p], irk_prev);
+    }
+    if (k == p) break;
+    double dkk = re_(A[k + (int64_t)k * p]);
+    if (!(dkk > 1e-300)) {
+      if (tid == 0) bad_s = 1;
+      dkk = 1.0;
+    }
+    const double idk = 1.0 / dkk;
+    irk_prev = 1.0 / sqrt(dkk);
+    for (int j = k + 1 + ty; j < p; j += 32) {
+      const T akj = scl(A[k + (int64_t)j * p], idk);
+      for (int i = k + 1 + tx; i <= j; i += 32)
+        A[i + (int64_t)j * p] = sub(A[i + (int64_t)j * p], mul(conj_(A[k + (int64_t)i * p]), akj));
+    }
+    for (int c = ty; c <= k; c += 32) {
+      const T zkc = scl(Z[k + (int64_t)c * p], idk);
+      for (int i = k + 1 + tx; i < p; i += 32)
+        Z[i + (int64_t)c * p] = sub(Z[i + (int64_t)c * p], mul(conj_(A[k + (int64_t)i * p]), zkc));
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (tid == 0 && bad_s) *flag = 1;
+  for (int e = tid; e < p * p; e += nt) {
+    const int i = e % p, j = e / p;
+    Rg[e] = i <= j ? A[e] : ST<T>::zero();
+    Rinv[e] = i <= j ? conj_(Z[j + (int64_t)i * p]) : ST<T>::zero();
+  }
+}
+
 template <typename T>
 __global__ void upper_mul_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C, int p) {
   int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -857,7 +927,11 @@ template <typename T>
 void chol_upper_inv(const T* G, int p, double rel_shift, T* R, T* Rinv, int* flag, hipStream_t s) {
   const size_t one = sizeof(T) * (size_t)p * p;
   const bool use_lds = one <= 160 * 1024 - 4096;
-  if (use_lds) {
+  if (2 * one <= 160 * 1024 - 4096) {
+    (void)hipFuncSetAttribute((const void*)chol_inv_lds_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(2 * one));
+    hipLaunchKernelGGL(chol_inv_lds_kernel<T>, dim3(1), dim3(1024), 2 * one, s, G, p, rel_shift, R, Rinv, flag);
+  } else if (use_lds) {
     const size_t lds = 2 * one <= 160 * 1024 - 4096 ? 2 * one : one;
     (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
