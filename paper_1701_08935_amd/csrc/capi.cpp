@@ -188,6 +188,7 @@ struct GemmLaunch {
   int off = 0, cnt = 0, tiles = 0;
   int maxM = 0, maxN = 0;  // bounds over the launch's products (GEMM launches)
   int max_split = 1;       // largest inner-dimension split of its products
+  int grid_tiles = 0;      // workgroups per split the launch needs (0: tiles of maxM x maxN)
   double flops = 0.0, bytes = 0.0;  // algorithmic work of the launch
 };
 
@@ -412,7 +413,7 @@ void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s, int t
   if (L.cnt <= 0 || L.maxM <= 0 || L.maxN <= 0) return;
   prof::Scope ps(tag == 0 ? ZOLO_PROF_GEMM_FACTOR : tag == 1 ? ZOLO_PROF_GEMM_SOLVE : ZOLO_PROF_GEMM_KRYLOV, L.flops,
                  L.bytes, s);
-  gemm_batched<T>(base + L.off, L.cnt, L.maxM, L.maxN, s, tag, L.max_split);
+  gemm_batched<T>(base + L.off, L.cnt, L.maxM, L.maxN, s, tag, L.max_split, L.grid_tiles);
 }
 
 // Inner-dimension splits of the products of GEMM launches (GemmDesc::splitk).
@@ -431,7 +432,12 @@ void plan_split(std::vector<GemmDesc<T>>& gd, GemmLaunch& g, SplitPlan* sp) {
   if (g.cnt <= 0 || g.maxM <= 0 || g.maxN <= 0) return;
   const int tn = gemm_tile_n(g.maxN), tk = tn == 96 ? 8 : 16;
   int64_t total = 0;
-  for (int i = g.off; i < g.off + g.cnt; ++i) total += gemm_tiles(gd[i].M, gd[i].N);
+  g.grid_tiles = 0;
+  for (int i = g.off; i < g.off + g.cnt; ++i) {
+    const int t = gemm_desc_tiles(gd[i].M, gd[i].N, gd[i].flags, gd[i].tri_off, g.maxN);
+    g.grid_tiles = std::max(g.grid_tiles, t);
+    total += t;
+  }
   if (total >= kSplitBelow) return;
   const int goal = (int)std::min<int64_t>(kMaxSplit, (kSplitTarget + total - 1) / std::max<int64_t>(total, 1));
   const int64_t pe = gemm_part_elems(g.maxN, ST<T>::cplx);

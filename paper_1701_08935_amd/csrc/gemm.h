@@ -70,13 +70,18 @@ int gemm_tile_n(int maxN);
 int gemm_tiles(int maxM, int maxN);
 // real scalars of partial sums one split of one tile writes
 int64_t gemm_part_elems(int maxN, bool cplx);
+// workgroups (per split) one descriptor needs in a launch whose widest product
+// has maxN columns: its tiles, or only those holding kept entries for GF_TRI
+int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxN);
 
 // d_desc: device array of n descriptors; maxM / maxN: upper bounds of every
 // descriptor's M and N (they size the grid and select the tile shape);
-// max_split: largest splitk of the descriptors.
+// max_split: largest splitk of the descriptors; grid_tiles: the largest
+// gemm_desc_tiles of the descriptors (0: the tiles of maxM x maxN).
 // tag: 0 front updates, 1 supernodal solves, 2 Krylov / Rayleigh-Ritz (profile names only).
 template <typename T>
-void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split = 1);
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split = 1,
+                  int grid_tiles = 0);
 
 // Algorithmic work of one descriptor: entries of C computed and flops
 // (8 per complex multiply-add, 2 per real one), and the bytes a product

@@ -105,6 +105,15 @@ struct PipelinedLoop {
   static constexpr bool value = !(MfmaTraits<T>::cplx && sizeof(typename MfmaTraits<T>::R) == 8 && TN == 96);
 };
 
+// First tile row of tile column j holding an entry i - j >= tri_off (rows i of
+// tile row t span [t TM, t TM + TM)): the smallest t with t TM + TM - 1 >= j TN + tri_off.
+template <int TM, int TN>
+__host__ __device__ inline int tri_first_row(int j, int tri_off, int tilesM) {
+  const int need = j * TN + tri_off - (TM - 1);  // t * TM >= need
+  const int t = need <= 0 ? 0 : (need + TM - 1) / TM;
+  return t < tilesM ? t : tilesM;
+}
+
 // TAG only separates the uses in profiles: 0 front updates, 1 supernodal
 // solves, 2 Krylov / Rayleigh-Ritz products.
 template <typename T, int TAG, int TM, int TN>
@@ -121,14 +130,34 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
   const GemmDesc<T> d = descs[blockIdx.y];
   const int tilesM = (d.M + TM - 1) / TM;
   const int tilesN = (d.N + TN - 1) / TN;
-  const int ntiles = tilesM * tilesN;
   const int S = d.splitk > 1 ? d.splitk : 1;
+  const bool tri = (d.flags & GF_TRI) != 0;
+  // Tiles are numbered column by column; a lower-triangular product numbers
+  // only the tiles that hold kept entries (rows i with i - j >= tri_off), so
+  // no workgroup of the grid is spent on the empty upper part.
+  int ntiles = tilesM * tilesN;
+  if (tri) {
+    ntiles = 0;
+    for (int j = 0; j < tilesN; ++j) ntiles += tilesM - tri_first_row<TM, TN>(j, d.tri_off, tilesM);
+  }
   if ((int)blockIdx.x >= ntiles * S) return;
   const int tile = blockIdx.x % ntiles, ks = blockIdx.x / ntiles;  // tile, K split
-  const int m0 = (tile % tilesM) * TM;
-  const int n0 = (tile / tilesM) * TN;
-  const bool tri = (d.flags & GF_TRI) != 0;
-  if (tri && (m0 + TM - 1) - n0 < d.tri_off) return;
+  int m0, n0;
+  if (tri) {
+    int a = tile, j = 0;
+    for (;; ++j) {
+      const int i0 = tri_first_row<TM, TN>(j, d.tri_off, tilesM), cnt = tilesM - i0;
+      if (a < cnt) {
+        m0 = (i0 + a) * TM;
+        break;
+      }
+      a -= cnt;
+    }
+    n0 = j * TN;
+  } else {
+    m0 = (tile % tilesM) * TM;
+    n0 = (tile / tilesM) * TN;
+  }
 
   // two LDS buffers as separate arrays, so the compiler can tell the chunk
   // being read from the one being written: [plane][k][row]
@@ -479,8 +508,10 @@ __global__ __launch_bounds__((TM * 4), 2) void gemm_batched_kernel(
 }
 
 template <typename T, int TM, int TN>
-void launch_cfg(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split) {
-  const int tiles = ((maxM + TM - 1) / TM) * ((maxN + TN - 1) / TN) * (max_split > 1 ? max_split : 1);
+void launch_cfg(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split,
+                int grid_tiles) {
+  const int per = grid_tiles > 0 ? grid_tiles : ((maxM + TM - 1) / TM) * ((maxN + TN - 1) / TN);
+  const int tiles = per * (max_split > 1 ? max_split : 1);
   const dim3 blk(TileCfg<TM, TN>::NT);
   for (int b0 = 0; b0 < n; b0 += 65535) {
     const int nb = n - b0 < 65535 ? n - b0 : 65535;
@@ -502,18 +533,28 @@ int gemm_tiles(int maxM, int maxN) {
   return ((maxM + tm - 1) / tm) * ((maxN + tn - 1) / tn);
 }
 int64_t gemm_part_elems(int maxN, bool cplx) { return (int64_t)64 * gemm_tile_n(maxN) * (cplx ? 2 : 1); }
-
-template <typename T>
-void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split) {
-  if (n <= 0 || maxM <= 0 || maxN <= 0) return;
-  if (gemm_tile_n(maxN) == 64)
-    launch_cfg<T, 64, 64>(d_desc, n, maxM, maxN, s, tag, max_split);
-  else
-    launch_cfg<T, 64, 96>(d_desc, n, maxM, maxN, s, tag, max_split);
+int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxN) {
+  const int tn = gemm_tile_n(maxN);
+  const int tilesM = (M + 63) / 64, tilesN = (N + tn - 1) / tn;
+  if (!(flags & GF_TRI)) return tilesM * tilesN;
+  int n = 0;
+  for (int j = 0; j < tilesN; ++j)
+    n += tilesM - (tn == 64 ? tri_first_row<64, 64>(j, tri_off, tilesM) : tri_first_row<64, 96>(j, tri_off, tilesM));
+  return n;
 }
 
-template void gemm_batched<double>(const GemmDesc<double>*, int, int, int, hipStream_t, int, int);
-template void gemm_batched<zd>(const GemmDesc<zd>*, int, int, int, hipStream_t, int, int);
-template void gemm_batched<zf>(const GemmDesc<zf>*, int, int, int, hipStream_t, int, int);
+template <typename T>
+void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split,
+                  int grid_tiles) {
+  if (n <= 0 || maxM <= 0 || maxN <= 0) return;
+  if (gemm_tile_n(maxN) == 64)
+    launch_cfg<T, 64, 64>(d_desc, n, maxM, maxN, s, tag, max_split, grid_tiles);
+  else
+    launch_cfg<T, 64, 96>(d_desc, n, maxM, maxN, s, tag, max_split, grid_tiles);
+}
+
+template void gemm_batched<double>(const GemmDesc<double>*, int, int, int, hipStream_t, int, int, int);
+template void gemm_batched<zd>(const GemmDesc<zd>*, int, int, int, hipStream_t, int, int, int);
+template void gemm_batched<zf>(const GemmDesc<zf>*, int, int, int, hipStream_t, int, int, int);
 
 }  // namespace zolo
