@@ -431,6 +431,12 @@ template <typename T>
 void plan_split(std::vector<GemmDesc<T>>& gd, GemmLaunch& g, SplitPlan* sp) {
   if (g.cnt <= 0 || g.maxM <= 0 || g.maxN <= 0) return;
   const int tn = gemm_tile_n(g.maxN), tk = tn == 96 ? 8 : 16;
+  // longest products first, so that the launch's last workgroups are short ones
+  // (the products of a launch are independent; their order is free)
+  std::stable_sort(gd.begin() + g.off, gd.begin() + g.off + g.cnt, [&](const GemmDesc<T>& x, const GemmDesc<T>& y) {
+    return (double)gemm_desc_tiles(x.M, x.N, x.flags, x.tri_off, g.maxN) * x.K >
+           (double)gemm_desc_tiles(y.M, y.N, y.flags, y.tri_off, g.maxN) * y.K;
+  });
   int64_t total = 0;
   g.grid_tiles = 0;
   for (int i = g.off; i < g.off + g.cnt; ++i) {
