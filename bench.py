@@ -49,7 +49,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_gpu(name, steps, warmup, leaf, r1, profile=True, tol_refine=0.0):
+def run_gpu(name, steps, warmup, leaf, r1, profile=True, tol_refine=0.0, tol_gmres=0.0):
     import numpy as np
     import torch
 
@@ -72,6 +72,8 @@ def run_gpu(name, steps, warmup, leaf, r1, profile=True, tol_refine=0.0):
     opts = z.opts_from_window(w, r1=r1, r2=0, n_ss=wl["n_ss"], precision=wl["precision"])
     if tol_refine > 0:
         opts.tol_refine = tol_refine
+    if tol_gmres > 0:
+        opts.tol_gmres = tol_gmres
     lat = []
     last = None
     for it in range(warmup + steps):
@@ -274,6 +276,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--tol-refine", type=float, default=0.0, help="mixed precision: inner refinement tolerance")
+    ap.add_argument("--tol-gmres", type=float, default=0.0, help="GMRES relative residual per shift (0: library default)")
     ap.add_argument("--serving-queries", type=int, default=48)
     ap.add_argument("--serving-rate", type=float, default=6.0, help="Poisson arrival rate, queries/s")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -294,7 +297,8 @@ def main():
         print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
               "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
-    res = run_gpu(args.config, args.steps, args.warmup, args.leaf, args.r1, tol_refine=args.tol_refine)
+    res = run_gpu(args.config, args.steps, args.warmup, args.leaf, args.r1, tol_refine=args.tol_refine,
+                  tol_gmres=args.tol_gmres)
     lat = res["lat"]
     ms = 1e3 * sum(lat) / len(lat)
     value = res["verified"] / (ms * 1e-3)

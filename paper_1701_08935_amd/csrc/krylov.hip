@@ -605,172 +605,348 @@ __global__ void hls_combine_cplx_kernel(const zd* __restrict__ Y, int64_t mp, in
 }
 
 // ---------------- Rayleigh-Ritz (single workgroup) ----------------
-// Cyclic Jacobi, round-robin parallel order, on a Hermitian n x n matrix A
-// (col-major), accumulating V.  All threads of the block participate.  For a
-// pair (p, q) with A(p, q) = r e^{i phi}, the unitary
-//   J = [[c, s e^{i phi}], [-s e^{-i phi}, c]]   (columns p, q)
-// with the real rotation (c, s) of [[A(p,p), r], [r, A(q,q)]] zeroes A(p, q)
-// in J^H A J; for real A the phase is the sign of A(p, q).
-template <typename T>
-__device__ void jacobi_block(T* A, T* V, int n, int max_sweeps, double tol) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = n + (n & 1);
-  const int half = m / 2;
-  __shared__ double cs_s[256], sn_s[256];
-  __shared__ T ph_s[256];
-  __shared__ int pp_s[256], qq_s[256];
-  __shared__ double red[2][16];
-  __shared__ int rot_s;  // a rotation was applied in the current sweep
-  if (tid == 0) rot_s = 1;
-  for (int e = tid; e < n * n; e += nt) V[e] = (e % n == e / n) ? ST<T>::one() : ST<T>::zero();
-  __threadfence_block();
-  __syncthreads();
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += nt) {
-      double v = abs2(A[e]);
-      tot += v;
-      if (e % n != e / n) off += v;
-    }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    if ((tid & 63) == 0) {
-      red[0][tid >> 6] = off;
-      red[1][tid >> 6] = tot;
-    }
-    __syncthreads();
-    off = 0.0;
-    tot = 0.0;
-    for (int w = 0; w < nt / 64; ++w) {
-      off += red[0][w];
-      tot += red[1][w];
-    }
-    __syncthreads();
-    if (off <= tol * tol * tot || tot == 0.0 || rot_s == 0) break;
-    const double thr = tol * sqrt(tot);
-    __syncthreads();
-    if (tid == 0) rot_s = 0;
-    __syncthreads();
-    for (int r = 0; r < m - 1; ++r) {
-      if (tid < half) {
-        int k = tid;
-        int a = (k == 0) ? 0 : ((k - 1 + r) % (m - 1)) + 1;
-        int bpos = m - 1 - k;
-        int b = ((bpos - 1 + r) % (m - 1)) + 1;
-        int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, sn = 0.0;
-        T ph = ST<T>::one();
-        if (q < n) {
-          const T apq = A[p + (int64_t)q * n];
-          const double rr = sqrt(abs2(apq));
-          // rotate only while |a_pq| is above tol ||A||_F (eigenvalues to absolute accuracy
-          // tol ||A||, which is what the rank decision and the Ritz values need); a sweep
-          // with no rotation ends the iteration
-          if (rr > 1e-300 && rr > thr) {
-            rot_s = 1;
-            ph = scl(apq, 1.0 / rr);
-            double tau = (re_(A[q + (int64_t)q * n]) - re_(A[p + (int64_t)p * n])) / (2.0 * rr);
-            double t;
-            if (fabs(tau) > 1e150)
-              t = 0.5 / tau;
-            else
-              t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            sn = t * c;
-          }
-        }
-        cs_s[k] = c;
-        sn_s[k] = sn;
-        ph_s[k] = ph;
-        pp_s[k] = p;
-        // q >= 0: rotate the pair; -2: q is the padding index of an odd n; -(q + 3): no rotation
-        qq_s[k] = q >= n ? -2 : (sn != 0.0 ? q : -q - 3);
-      }
-      __syncthreads();
-      // One phase per round.  With J_k = [[c, s ph], [-s conj(ph), c]] on the index pair
-      // (p_k, q_k) (columns: col_p <- c col_p - s conj(ph) col_q, col_q <- s ph col_p + c col_q;
-      // rows: the conjugate transpose), A <- J^H A J acts on each 2 x 2 block of rows
-      // {p_k1, q_k1} and columns {p_k2, q_k2} independently, and the pairs partition the
-      // indices, so every entry is read and written by one thread; V <- V J likewise by rows.
-      for (int e = tid; e < half * half; e += nt) {
-        const int k1 = e / half, k2 = e - k1 * half;
-        const int p1 = pp_s[k1], q1 = qq_s[k1], p2 = pp_s[k2], q2 = qq_s[k2];
-        const bool r1 = q1 >= 0, r2 = q2 >= 0;  // a rotation on this pair
-        const bool h1 = q1 != -2, h2 = q2 != -2;  // q index inside the matrix (not the padding)
-        const int qa = h1 ? (r1 ? q1 : -q1 - 3) : 0, qb = h2 ? (r2 ? q2 : -q2 - 3) : 0;
-        if (!r1 && !r2) continue;  // J = I on both sides
-        T a00 = A[p1 + (int64_t)p2 * n];
-        T a01 = h2 ? A[p1 + (int64_t)qb * n] : ST<T>::zero();
-        T a10 = h1 ? A[qa + (int64_t)p2 * n] : ST<T>::zero();
-        T a11 = (h1 && h2) ? A[qa + (int64_t)qb * n] : ST<T>::zero();
-        if (r2) {  // columns: M <- M J_k2
-          const double c = cs_s[k2], sn = sn_s[k2];
-          const T ph = ph_s[k2], phc = conj_(ph);
-          const T b00 = sub(scl(a00, c), scl(mul(phc, a01), sn)), b01 = add(scl(mul(ph, a00), sn), scl(a01, c));
-          const T b10 = sub(scl(a10, c), scl(mul(phc, a11), sn)), b11 = add(scl(mul(ph, a10), sn), scl(a11, c));
-          a00 = b00;
-          a01 = b01;
-          a10 = b10;
-          a11 = b11;
-        }
-        if (r1) {  // rows: M <- J_k1^H M
-          const double c = cs_s[k1], sn = sn_s[k1];
-          const T ph = ph_s[k1], phc = conj_(ph);
-          const T b00 = sub(scl(a00, c), scl(mul(ph, a10), sn)), b10 = add(scl(mul(phc, a00), sn), scl(a10, c));
-          const T b01 = sub(scl(a01, c), scl(mul(ph, a11), sn)), b11 = add(scl(mul(phc, a01), sn), scl(a11, c));
-          a00 = b00;
-          a10 = b10;
-          a01 = b01;
-          a11 = b11;
-        }
-        A[p1 + (int64_t)p2 * n] = a00;
-        if (h2) A[p1 + (int64_t)qb * n] = a01;
-        if (h1) A[qa + (int64_t)p2 * n] = a10;
-        if (h1 && h2) A[qa + (int64_t)qb * n] = a11;
-      }
-      for (int e = tid; e < n * half; e += nt) {
-        const int k = e / n, i = e - k * n;
-        const int q = qq_s[k];
-        if (q < 0) continue;
-        const int p = pp_s[k];
-        const double c = cs_s[k], sn = sn_s[k];
-        const T ph = ph_s[k], phc = conj_(ph);
-        const T vp = V[i + (int64_t)p * n], vq = V[i + (int64_t)q * n];
-        V[i + (int64_t)p * n] = sub(scl(vp, c), scl(mul(phc, vq), sn));
-        V[i + (int64_t)q * n] = add(scl(mul(ph, vp), sn), scl(vq, c));
-      }
-      __threadfence_block();
-      __syncthreads();
-    }
+// Hermitian eigensolver of one workgroup (1024 threads) for the Rayleigh-Ritz
+// reductions: Householder reduction to tridiagonal form, symmetric QR steps with
+// Wilkinson shifts on the real tridiagonal, and the accumulated transformations
+// (Golub & Van Loan, Matrix Computations, sections 8.3.1-8.3.3).
+//   1. For k = 0 .. m-3: H_k = I - tau v v^H maps A(k+1:, k) to alpha_k e_1, and
+//      A22 <- H_k A22 H_k by p = tau A22 v, w = p - (tau/2)(v^H p) v,
+//      A22 -= v w^H + w v^H.  v overwrites A(k+1:, k).
+//   2. Unit phases delta (delta_0 = 1, delta_{k+1} = delta_k alpha_k / |alpha_k|)
+//      give T = D T_r D^H with T_r real, subdiagonal |alpha_k|.
+//   3. Thread 0 runs the implicit QR steps on T_r; each step is a chain of plane
+//      rotations on neighbouring columns (k, k+1), which the other 15 waves apply
+//      to the rows of V = D (one row per thread) one step behind the producer.
+//   4. V <- H_0 H_1 ... H_{m-3} V, so that A = V diag(d) V^H.
+// In: M (m x m, col-major, global), Hermitian.  Out: the eigenvalues on M's
+// diagonal (unsorted), V (m x m, global) the eigenvectors as columns; M's strict
+// lower part holds the reflectors.  The matrix stage runs in LDS when m^2 values
+// fit beside the vectors, else in global memory.
+constexpr double kHeevEps = 1.1102230246251565e-16;  // 2^-53
+
+// plane rotation (c, s) with c x - s z = r, s x + c z = 0: 1/r from the hardware
+// reciprocal square root and two Newton steps (no divide on the serial chain)
+__device__ inline void heev_givens(double x, double z, double& c, double& s, double& r) {
+  const double r2 = fma(x, x, z * z);
+  if (r2 > 0.0) {
+    double y = __builtin_amdgcn_rsq(r2);
+    const double hh = 0.5 * r2;
+    y = y * fma(-hh * y, y, 1.5);
+    y = y * fma(-hh * y, y, 1.5);
+    c = x * y;
+    s = -z * y;
+    r = r2 * y;
+  } else {
+    c = 1.0;
+    s = 0.0;
+    r = 0.0;
   }
 }
 
-// Jacobi on an m x m matrix M (global, col-major): in LDS when it fits.
-// lds holds lds_elems values: M (and V when 2 m^2 fit) stay there during the sweeps
+// LDS layout: dd, ee, tau, rc[2m], rs[2m] (double), ph, pv, vs (T), then the matrix
 template <typename T>
-__device__ void jacobi_maybe_lds(T* M, T* V, int m, T* lds, int64_t lds_elems) {
+__device__ inline size_t heev_mat_off(int m) {
+  return ((size_t)m * (7 * sizeof(double) + 3 * sizeof(T)) + 255) & ~(size_t)255;
+}
+
+__device__ inline bool heev_negligible(double e, double d0, double d1) {
+  return fabs(e) <= kHeevEps * (fabs(d0) + fabs(d1));
+}
+
+// L: the matrix stage (A, then V) is in LDS.  A compile-time choice, so that every
+// matrix access has a fixed address space (LDS or global), never a flat one.
+template <typename T, bool L>
+__device__ __attribute__((always_inline)) void heev_run(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t mm = (int64_t)m * m;
-  if (mm <= lds_elems) {
-    const bool vl = 2 * mm <= lds_elems;
-    T* Vw = vl ? lds + mm : V;
-    for (int e = tid; e < mm; e += nt) lds[e] = M[e];
+  const int wv = tid >> 6, ln = tid & 63, nw = nt >> 6;
+  __shared__ int sw_l[2], sw_h[2], ql_done[2];
+  // vectors first, the matrix after them
+  double* dd = (double*)lds;  // diagonal of T_r
+  double* ee = dd + m;        // ee[k] couples k and k+1
+  double* tau = ee + m;
+  double* rc = tau + m;       // rotation buffers [2][m] cosines, [2][m] sines
+  double* rs = rc + 2 * m;
+  T* ph = (T*)(rs + 2 * m);   // alpha_k / |alpha_k|
+  T* pv = ph + m;             // p, then the phases delta, then v^H V
+  T* vs = pv + m;             // staged reflector
+  constexpr bool in_lds = L;
+  T* A = L ? (T*)(lds + heev_mat_off<T>(m)) : Mg;
+  if (in_lds) {
+    for (int j = wv; j < m; j += nw)
+      for (int i = ln; i < m; i += 64) A[i + (int64_t)j * m] = Mg[i + (int64_t)j * m];
     __syncthreads();
-    jacobi_block<T>(lds, Vw, m, 40, 1e-15);
-    __syncthreads();
-    for (int e = tid; e < mm; e += nt) {
-      M[e] = lds[e];
-      if (vl) V[e] = Vw[e];
+  }
+  // 1. Householder tridiagonalization
+  for (int k = 0; k + 2 < m; ++k) {
+    const int r0 = k + 1, len = m - r0;
+    T* x = A + r0 + (int64_t)k * m;
+    if (tid < 64) {
+      double rest = 0.0;
+      for (int i = 1 + tid; i < len; i += 64) rest += abs2(x[i]);
+      rest = wave_sum(rest);
+      if (tid == 0) {
+        const T x0 = x[0];
+        const double ax0 = sqrt(abs2(x0));
+        const T phase = ax0 > 0.0 ? scl(x0, 1.0 / ax0) : ST<T>::one();
+        dd[k] = re_(A[k + (int64_t)k * m]);
+        if (rest == 0.0) {  // column already reduced
+          tau[k] = 0.0;
+          ee[k] = ax0;
+          ph[k] = phase;
+        } else {
+          const double nrm = sqrt(rest + ax0 * ax0);
+          const T v0 = add(x0, scl(phase, nrm));  // v = x - alpha e_1, alpha = -phase |x|
+          tau[k] = 2.0 / (rest + abs2(v0));
+          ee[k] = nrm;
+          ph[k] = neg(phase);
+          x[0] = v0;
+        }
+      }
     }
     __threadfence_block();
     __syncthreads();
-  } else {
-    jacobi_block<T>(M, V, m, 40, 1e-15);
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    {  // p = tau A22 v, 8 lanes per row
+      const int row = tid >> 3, l8 = tid & 7;
+      for (int i = row; i < len; i += nt >> 3) {
+        const T* arow = A + (r0 + i) + (int64_t)r0 * m;
+        T acc = ST<T>::zero();
+        for (int j = l8; j < len; j += 8) acc = fma_(acc, arow[(int64_t)j * m], x[j]);
+        double ar = re_(acc), ai = 0.0;
+        if constexpr (ST<T>::cplx) ai = acc.im;
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) {
+          ar += __shfl_xor(ar, o, 8);
+          if constexpr (ST<T>::cplx) ai += __shfl_xor(ai, o, 8);
+        }
+        if (l8 == 0) {
+          if constexpr (ST<T>::cplx)
+            pv[i] = T{ar * tk, ai * tk};
+          else
+            pv[i] = ar * tk;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // K = (tau / 2) v^H p is real: one reduction per wave
+    double kk = 0.0;
+    for (int j = ln; j < len; j += 64) kk += re_(mul(conj_(x[j]), pv[j]));
+    kk = 0.5 * tk * wave_sum(kk);
+    for (int j = wv; j < len; j += nw) {
+      const T xj = x[j];
+      const T wjc = conj_(sub(pv[j], scl(xj, kk))), xjc = conj_(xj);
+      T* acol = A + r0 + (int64_t)(r0 + j) * m;
+      for (int i = ln; i < len; i += 64) {
+        const T xi = x[i];
+        const T wi = sub(pv[i], scl(xi, kk));
+        acol[i] = sub(acol[i], add(mul(xi, wjc), mul(wi, xjc)));
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
   }
+  if (tid == 0) {
+    const int k = m - 2;
+    dd[k] = re_(A[k + (int64_t)k * m]);
+    dd[k + 1] = re_(A[(k + 1) + (int64_t)(k + 1) * m]);
+    const T x0 = A[(k + 1) + (int64_t)k * m];
+    const double ax0 = sqrt(abs2(x0));
+    ee[k] = ax0;
+    ph[k] = ax0 > 0.0 ? scl(x0, 1.0 / ax0) : ST<T>::one();
+    tau[k] = 0.0;
+    ee[m - 1] = 0.0;
+    T dl = ST<T>::one();
+    pv[0] = dl;
+    for (int i = 0; i + 1 < m; ++i) {
+      dl = mul(dl, ph[i]);
+      pv[i + 1] = dl;
+    }
+  }
+  __threadfence_block();
+  __syncthreads();
+  // the reflectors go back to M; V = D takes the matrix space
+  T* V = in_lds ? A : Vg;
+  if (in_lds) {
+    for (int j = wv; j + 2 < m; j += nw)
+      for (int i = j + 1 + ln; i < m; i += 64) Mg[i + (int64_t)j * m] = A[i + (int64_t)j * m];
+    __syncthreads();
+  }
+  for (int j = wv; j < m; j += nw)
+    for (int i = ln; i < m; i += 64) V[i + (int64_t)j * m] = i == j ? pv[i] : ST<T>::zero();
+  __threadfence_block();
+  __syncthreads();
+  // 3. implicit QR steps: thread 0 produces the rotations of step r into buffer r & 1
+  //    while the other waves apply step r - 1 to their rows of V.  The active block
+  //    is [q_l, q_h]: everything below q_h has converged, ee[q_l - 1] is zero.
+  int q_iter = 0, q_h = m - 1, q_l = 0;
+  bool q_done = false;
+  for (int round = 0;; ++round) {
+    const int b = round & 1;
+    if (tid == 0) {
+      int l = 0, h = -1;
+      while (!q_done) {
+        while (q_h > q_l && heev_negligible(ee[q_h - 1], dd[q_h - 1], dd[q_h])) {
+          ee[q_h - 1] = 0.0;
+          --q_h;
+        }
+        if (q_h > q_l) break;
+        if (q_l == 0) {
+          q_done = true;
+          break;
+        }
+        // the block above
+        q_h = q_l - 1;
+        int nl = q_h;
+        while (nl > 0 && !heev_negligible(ee[nl - 1], dd[nl - 1], dd[nl])) --nl;
+        if (nl > 0) ee[nl - 1] = 0.0;
+        q_l = nl;
+      }
+      if (!q_done && q_iter >= 30 * m) q_done = true;
+      if (!q_done) {
+        l = q_l;
+        h = q_h;
+        ++q_iter;
+        // Wilkinson shift from the trailing 2 x 2 block
+        const double da = dd[h - 1], dc = dd[h], eb = ee[h - 1];
+        const double dl2 = 0.5 * (da - dc);
+        const double den = dl2 + (dl2 >= 0.0 ? 1.0 : -1.0) * sqrt(fma(dl2, dl2, eb * eb));
+        const double mu = dc - eb * eb / den;
+        // bulge chase, the state of the moving 2 x 2 window in registers
+        double a0 = dd[l], b0 = ee[l], d0 = dd[l + 1];
+        double e1 = l + 1 < h ? ee[l + 1] : 0.0;
+        double xv = a0 - mu, zv = b0, dprev = 0.0, en = 0.0;
+        double* rcb = rc + b * m;
+        double* rsb = rs + b * m;
+        int split = -1;
+        for (int k = l; k < h; ++k) {
+          const double d_nx = k + 2 <= h ? dd[k + 2] : 0.0;
+          const double e_nx = k + 2 < h ? ee[k + 2] : 0.0;
+          double c, sn, r;
+          heev_givens(xv, zv, c, sn, r);
+          const double cc = c * c, ss = sn * sn, cs = c * sn;
+          const double an = fma(a0, cc, fma(-2.0 * b0, cs, d0 * ss));
+          const double dn = fma(a0, ss, fma(2.0 * b0, cs, d0 * cc));
+          en = fma(a0 - d0, cs, b0 * (cc - ss));
+          dd[k] = an;
+          if (k > l) {
+            ee[k - 1] = r;
+            if (heev_negligible(r, dprev, an)) split = k - 1;
+          }
+          rcb[k - l] = c;
+          rsb[k - l] = sn;
+          dprev = an;
+          xv = en;
+          zv = -sn * e1;
+          b0 = c * e1;
+          a0 = dn;
+          d0 = d_nx;
+          e1 = e_nx;
+        }
+        dd[h] = a0;
+        ee[h - 1] = en;
+        if (split >= 0) {
+          ee[split] = 0.0;
+          q_l = split + 1;
+        }
+      }
+      sw_l[b] = l;
+      sw_h[b] = h;
+      ql_done[b] = q_done ? 1 : 0;
+    } else if (tid >= 64 && round > 0) {
+      const int pb = b ^ 1;
+      const int l = sw_l[pb], h = sw_h[pb];
+      if (h > l) {
+        const double* cb = rc + pb * m;
+        const double* sb = rs + pb * m;
+        for (int r = tid - 64; r < m; r += nt - 64) {
+          T* vr = V + r;
+          T carry = vr[(int64_t)l * m];
+          T zn = vr[(int64_t)(l + 1) * m];
+          for (int k = l; k < h; ++k) {
+            const T znext = k + 2 <= h ? vr[(int64_t)(k + 2) * m] : ST<T>::zero();
+            const double c = cb[k - l], sn = sb[k - l];
+            // columns (k, k+1) <- (c z_k - s z_{k+1}, s z_k + c z_{k+1})
+            vr[(int64_t)k * m] = sub(scl(carry, c), scl(zn, sn));
+            carry = add(scl(carry, sn), scl(zn, c));
+            zn = znext;
+          }
+          vr[(int64_t)h * m] = carry;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (ql_done[b]) break;
+  }
+  // 4. back-transformation V <- H_k V, k = m-3 .. 0 (reflectors from M)
+  for (int k = m - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const int r0 = k + 1, len = m - r0;
+    for (int i = tid; i < len; i += nt) vs[i] = Mg[(r0 + i) + (int64_t)k * m];
+    __threadfence_block();
+    __syncthreads();
+    {  // pv[c] = tau v^H V(r0:, c), 8 lanes per column
+      const int col = tid >> 3, l8 = tid & 7;
+      for (int c = col; c < m; c += nt >> 3) {
+        const T* vc = V + r0 + (int64_t)c * m;
+        T acc = ST<T>::zero();
+        for (int i = l8; i < len; i += 8) acc = fma_(acc, conj_(vs[i]), vc[i]);
+        double ar = re_(acc), ai = 0.0;
+        if constexpr (ST<T>::cplx) ai = acc.im;
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) {
+          ar += __shfl_xor(ar, o, 8);
+          if constexpr (ST<T>::cplx) ai += __shfl_xor(ai, o, 8);
+        }
+        if (l8 == 0) {
+          if constexpr (ST<T>::cplx)
+            pv[c] = T{ar * tk, ai * tk};
+          else
+            pv[c] = ar * tk;
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int c = wv; c < m; c += nw) {
+      const T sc = pv[c];
+      T* vcol = V + r0 + (int64_t)c * m;
+      for (int i = ln; i < len; i += 64) vcol[i] = sub(vcol[i], mul(vs[i], sc));
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  if (in_lds)
+    for (int j = wv; j < m; j += nw)
+      for (int i = ln; i < m; i += 64) Vg[i + (int64_t)j * m] = V[i + (int64_t)j * m];
+  for (int i = tid; i < m; i += nt) Mg[i + (int64_t)i * m] = cvt<T, double>(dd[i]);
+  __threadfence_block();
+  __syncthreads();
 }
 
-// dynamic LDS of the Rayleigh-Ritz kernel (the static part of jacobi_block is ~13 KB)
-constexpr size_t kRrLdsBytes = 144 * 1024;
+template <typename T>
+__device__ __attribute__((always_inline)) void heev_tridiag(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds, size_t lds_bytes) {
+  if (m <= 0) return;
+  if (m == 1) {
+    if (threadIdx.x == 0) {
+      Vg[0] = ST<T>::one();
+      Mg[0] = cvt<T, double>(re_(Mg[0]));
+    }
+    __threadfence_block();
+    __syncthreads();
+    return;
+  }
+  if (heev_mat_off<T>(m) + (size_t)m * m * sizeof(T) <= lds_bytes)
+    heev_run<T, true>(Mg, Vg, m, lds);
+  else
+    heev_run<T, false>(Mg, Vg, m, lds);
+}
+
+// dynamic LDS of the Rayleigh-Ritz kernel: the 160 KB of a CU less its few static words
+constexpr size_t kRrLdsBytes = 160 * 1024 - 256;
 
 // Rank-revealing Rayleigh-Ritz: scale to unit diagonal of Bt, eigendecompose
 // Bt, keep directions with eigenvalue > tau_rank * max, reduce At on them and
@@ -780,8 +956,6 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
                                                          double tau_rank, double* __restrict__ theta,
                                                          T* __restrict__ Cmat, int* k_out, T* work) {
   extern __shared__ char rr_raw[];
-  T* rr_lds = (T*)rr_raw;
-  const int64_t lds_elems = (int64_t)(kRrLdsBytes / sizeof(T));
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t nn = (int64_t)n * n;
   T* As = work;
@@ -810,7 +984,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds<T>(Bs, U, n, rr_lds, lds_elems);
+  heev_tridiag<T>(Bs, U, n, rr_raw, kRrLdsBytes);
   __syncthreads();
   for (int i = tid; i < n; i += nt) sv[i] = re_(Bs[i + (int64_t)i * n]);
   __threadfence_block();
@@ -857,7 +1031,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  jacobi_maybe_lds<T>(Bs, W, k, rr_lds, lds_elems);
+  heev_tridiag<T>(Bs, W, k, rr_raw, kRrLdsBytes);
   __syncthreads();
   // ascending order of the Ritz values
   for (int i = tid; i < k; i += nt) {
