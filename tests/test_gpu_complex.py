@@ -138,11 +138,13 @@ def test_complex_solve_window(ctx, pencil7, start, count):
     assert b_orthonormality(B, Xg) <= 1e-10
 
 
-@pytest.mark.parametrize("n", [24, 32])
-def test_complex_window_stored(ctx, n):
+@pytest.mark.parametrize("n,nss", [(24, 96), (32, 96), (24, 110)])
+def test_complex_window_stored(ctx, n, nss):
     """The complex workload pencils (grid27p n^3, window of 64 near 0, block 96) against the
     oracle's stored window: count = inertia count, eigenvalues 1e-10, residual 1e-8,
-    B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors."""
+    B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors.  With a
+    block of 110 the 110 x 110 complex Rayleigh-Ritz Gram matrix (190 KB) is eigensolved
+    from global memory instead of LDS."""
     import json
     import os
 
@@ -152,12 +154,12 @@ def test_complex_window_stored(ctx, n):
     if not os.path.exists(path):
         pytest.skip("window fixture not generated")
     w = json.load(open(path))
-    say(f"complex zolo_solve grid27p {n}^3 window 64 block 96")
+    say(f"complex zolo_solve grid27p {n}^3 window 64 block {nss}")
     gp = pencils.grid27p(n)
     A, B = gp.scipy()
     P = zolo.Pencil.from_grid(ctx, gp, leaf_size=64)
-    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=96)
-    Q0 = pencils.gaussian_block(gp.n, 96, seed=2, complex_=True)
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss)
+    Q0 = pencils.gaussian_block(gp.n, nss, seed=2, complex_=True)
     eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, o, Q0=_dev(Q0))
     say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e}")
     assert rc == 0 and len(eig) == w["inertia_count"] == 64

@@ -146,3 +146,28 @@ def test_solve_window_10(ctx, precision):
     assert np.max(r) < 1e-8
     assert np.max(np.abs(X.T @ (B @ X) - np.eye(16))) < 1e-10
     assert st["max_resid"] < 1e-8
+
+
+def test_solve_window_10_large_subspace(ctx):
+    """A subspace of 160 for 16 wanted eigenvalues: the 160 x 160 Rayleigh-Ritz
+    Gram matrix (200 KB in FP64) does not fit in one workgroup's LDS, so its
+    eigensolve runs from global memory, and the filtered block is rank
+    deficient, so the rank truncation is exercised too."""
+    say("zolo_solve grid 10^3 window 16, subspace 160")
+    w = _window(10)
+    gp = pencils.grid7(10)
+    A, B = gp.scipy()
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    Q0 = pencils.gaussian_block(gp.n, 160, seed=4)
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=160)
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts, Q0=_dev(Q0))
+    say(f"  rc={rc} stats={ {k: st[k] for k in ('n_iter', 'n_gmres_total', 'max_resid', 'b_orth', 'n_found')} }")
+    assert rc == 0
+    ref = np.array(w["eigenvalues"])
+    assert len(eig) == 16
+    assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) < 1e-10
+    X = vec.cpu().numpy()
+    r = np.linalg.norm(A @ X - (B @ X) * np.array(eig)[None, :], axis=0) / (
+        (inf_norm(A) + np.abs(eig) * inf_norm(B)) * np.linalg.norm(X, axis=0))
+    assert np.max(r) < 1e-8
+    assert np.max(np.abs(X.T @ (B @ X) - np.eye(16))) < 1e-10
