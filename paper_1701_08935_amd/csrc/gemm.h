@@ -9,13 +9,14 @@
 // opA/opB optionally transposed / conjugated; C and Cin column-major with
 // leading dimensions ldc/ldcin, or row-major with GF_TRANSC.  GF_TRI keeps
 // only entries with i - j >= tri_off (lower-triangular updates of symmetric
-// fronts).  GF_ALOW / GF_AUP declare opA lower / upper triangular (square,
-// M == K; the other triangle is stored as zeros): each row tile then runs its
-// inner loop only over the nonzero part, which halves the work of products
-// with an explicit triangular inverse; GF_BLOW does the same for a lower
-// triangular opB (each column tile starts its inner loop at its first
-// column).  One descriptor per independent
-// product; a launch covers a list.
+// fronts).  GF_ALOW / GF_AUP declare opA lower / upper trapezoidal
+// (opA(i,t) = 0 for t > i, resp. t < i; those entries are stored as zeros):
+// each row tile then runs its inner loop only over the nonzero part, which
+// halves the work of products with an explicit triangular inverse, square or
+// stacked on a dense panel; GF_BLOW does the same for a lower trapezoidal opB
+// (opB(t,j) = 0 for t < j; each column tile starts its inner loop at its
+// first column).  One descriptor per independent product; a launch covers a
+// list.
 #pragma once
 
 #include "dev_common.h"
@@ -34,7 +35,7 @@ enum GemmFlags {
   GF_ALOW = 256,
   GF_AUP = 512,
   GF_CRS_ACC = 1024,  // the row scale (crs or 1/crs) multiplies the product instead of Cin
-  GF_BLOW = 2048,     // opB lower triangular (square, K == N): column j sums over t >= j only
+  GF_BLOW = 2048,     // opB lower trapezoidal: column j sums over t >= j only
 };
 
 template <typename T>
@@ -99,14 +100,23 @@ inline void gemm_work(const GemmDesc<T>& d, double* flops, double* bytes) {
     }
   }
   const double fm = ST<T>::cplx ? 8.0 : 2.0;
+  // nonzeros of an R x K operand whose row r holds min(r + 1, K) entries (lower)
+  // or max(K - r, 0) entries (upper)
+  auto nz_lower = [](double R, double KK) { return R <= KK ? R * (R + 1.0) / 2.0 : KK * (KK + 1.0) / 2.0 + (R - KK) * KK; };
+  auto nz_upper = [](double R, double KK) {
+    const double r = R < KK ? R : KK;
+    return r * KK - r * (r - 1.0) / 2.0;
+  };
   if (d.flags & GF_BLOW) {
-    *flops += fm * M * (N * (N + 1.0) / 2.0);  // column j of a lower triangular opB has N - j nonzeros
-    *bytes += (double)sizeof(T) * (M * K + N * (N + 1.0) / 2.0 + ent * (d.Cin ? 2.0 : 1.0));
+    const double nzb = nz_upper(N, K);  // column j of opB sums over t >= j
+    *flops += fm * M * nzb;
+    *bytes += (double)sizeof(T) * (M * K + nzb + ent * (d.Cin ? 2.0 : 1.0));
     return;
   }
   if (d.flags & (GF_ALOW | GF_AUP)) {
-    *flops += fm * N * (M * (M + 1.0) / 2.0);  // row i of a triangular opA has i+1 (or M-i) nonzeros
-    *bytes += (double)sizeof(T) * (M * (M + 1.0) / 2.0 + K * N + ent * (d.Cin ? 2.0 : 1.0));
+    const double nza = (d.flags & GF_ALOW) ? nz_lower(M, K) : nz_upper(M, K);
+    *flops += fm * N * nza;
+    *bytes += (double)sizeof(T) * (nza + K * N + ent * (d.Cin ? 2.0 : 1.0));
     return;
   }
   *flops += fm * ent * K;
