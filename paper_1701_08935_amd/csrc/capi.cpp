@@ -955,8 +955,8 @@ namespace {
 
 // Numeric factorization of one pole in two phases: factor_plan allocates the
 // factor and its temporaries and uploads the program's GEMM descriptors
-// (synchronous host work); factor_run only enqueues kernels on a stream, so
-// several poles can run concurrently on their own streams.
+// (synchronous host work); factor_step only enqueues kernels on a stream, a
+// few launches at a time, so several poles run concurrently on their own streams.
 struct FactorLevelG {
   std::vector<GemmLaunch> trsm;   // per step J: panel rows below the diagonal block
   std::vector<GemmLaunch> trail;  // per step J
@@ -1266,8 +1266,24 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   return ZOLO_OK;
 }
 
+// Where one pole's factorization program stands: level L, and within it the
+// stage (0 assembly and extend-add, 1 diagonal-block chain, 2 Schur update,
+// 3 inverse doubling, 4 conversion and panel stacking) and the index inside a
+// multi-launch stage.
+struct FactorCursor {
+  int L = -1;  // -1: buffers not cleared yet
+  int stage = 0;
+  size_t idx = 0;
+  bool done = false;
+};
+
+// Enqueue the next short group of launches of one pole's factorization on s
+// and advance the cursor.  The poles' groups are enqueued round-robin, so that
+// every pole's stream has work queued from the start: a pole enqueued whole
+// before the next fills the device queue, and the host then blocks until it
+// drains, holding back the other poles.
 template <typename T>
-zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipStream_t s) {
+zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipStream_t s, FactorCursor* c) {
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
   T* upd = fw->upd;
@@ -1276,17 +1292,25 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
   const std::vector<FactorLevelG>& lg = fw->lg;
   const double sr = fw->sr, si = fw->si;
   const bool lu = P->cplx();
-  HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
-  HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
-  HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
-  HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
-  if (lu) {
-    HIPC(hipMemsetAsync(pole->upanel, 0, sizeof(T) * P->panel_total, s));
-    HIPC(hipMemsetAsync(pole->uinv, 0, sizeof(T) * P->inv_total, s));
+  if (c->done) return ZOLO_OK;
+  if (c->L < 0) {
+    HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
+    HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
+    HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
+    HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
+    if (lu) {
+      HIPC(hipMemsetAsync(pole->upanel, 0, sizeof(T) * P->panel_total, s));
+      HIPC(hipMemsetAsync(pole->uinv, 0, sizeof(T) * P->inv_total, s));
+    }
+    c->L = 0;
+    c->stage = 0;
+    c->idx = 0;
+    if (nl == 0) c->done = true;
+    return ZOLO_OK;
   }
-  // run the program level by level
-  for (int L = 0; L < nl; ++L) {
-    {
+  const int L = c->L;
+  switch (c->stage) {
+    case 0: {
       prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
       const int64_t na = P->lvl_asm_end[L] - P->lvl_asm_begin[L];
       if (lu) {
@@ -1304,34 +1328,67 @@ zolo_status factor_run(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipSt
         for (const GemmLaunch& g : P->lvl_ext[L])
           front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
       }
+      c->stage = 1;
+      c->idx = 0;
+      break;
     }
-    const DiagDesc* dd = P->diag + P->lvl_diag_off[L];
-    for (size_t jj = 0; jj < P->lvl_diag_nJ[L].size(); ++jj) {
-      int J = (int)jj * FB;
-      int nd = P->lvl_diag_nJ[L][jj];
+    case 1: {
+      const size_t jj = c->idx;
+      if (jj < P->lvl_diag_nJ[L].size()) {
+        const DiagDesc* dd = P->diag + P->lvl_diag_off[L];
+        const int J = (int)jj * FB;
+        const int nd = P->lvl_diag_nJ[L][jj];
+        {
+          prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
+          if (lu)
+            front_diag_block_lu<T>(pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, dd, nd, J, flag, s);
+          else
+            front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+        }
+        // LDL^T: L21 = F21 L11^-T D^-1; LU: L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
+        run_gemm<T>(dgd, lg[L].trsm[jj], s, 0);
+        run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
+        ++c->idx;
+      }
+      if (c->idx >= P->lvl_diag_nJ[L].size()) {
+        c->stage = 2;
+        c->idx = 0;
+      }
+      break;
+    }
+    case 2:
+      run_gemm<T>(dgd, lg[L].schur, s, 0);
+      c->stage = 3;
+      c->idx = 0;
+      break;
+    case 3: {
+      const size_t I = c->idx;
+      if (I < lg[L].inv1.size()) {
+        run_gemm<T>(dgd, lg[L].inv1[I], s, 0);
+        run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
+        ++c->idx;
+      }
+      if (c->idx >= lg[L].inv1.size()) {
+        c->stage = 4;
+        c->idx = 0;
+      }
+      break;
+    }
+    default: {
+      run_gemm<T>(dgd, lg[L].conv, s, 0);
       {
         prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-        if (lu)
-          front_diag_block_lu<T>(pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, dd, nd, J, flag, s);
-        else
-          front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+        front_stack<T>(fw->dstk + lg[L].stk_off, lg[L].stk_cnt, lg[L].stk_max, s);
       }
-      // LDL^T: L21 = F21 L11^-T D^-1; LU: L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
-      run_gemm<T>(dgd, lg[L].trsm[jj], s, 0);
-      run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
-    }
-    run_gemm<T>(dgd, lg[L].schur, s, 0);
-    for (size_t I = 0; I < lg[L].inv1.size(); ++I) {
-      run_gemm<T>(dgd, lg[L].inv1[I], s, 0);
-      run_gemm<T>(dgd, lg[L].inv2[I], s, 0);
-    }
-    run_gemm<T>(dgd, lg[L].conv, s, 0);
-    {
-      prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-      front_stack<T>(fw->dstk + lg[L].stk_off, lg[L].stk_cnt, lg[L].stk_max, s);
+      c->stage = 0;
+      c->idx = 0;
+      if (++c->L >= nl) {
+        if (lu) conj_copy(pole->dconj, pole->dvec, P->n, s);
+        c->done = true;
+      }
+      break;
     }
   }
-  if (lu) conj_copy(pole->dconj, pole->dvec, P->n, s);
   HIPC(hipGetLastError());
   return ZOLO_OK;
 }
@@ -1362,7 +1419,15 @@ zolo_status factor_all(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs
     }
     if (hipStreamWaitEvent(ss[j], start, 0) != hipSuccess) rc = ZOLO_EDEVICE;
   }
-  for (int j = 0; j < np && rc == ZOLO_OK; ++j) rc = (zolo_status)factor_run<T>(P, &(*poles)[j], fw[j].get(), ss[j]);
+  std::vector<FactorCursor> cur(np);
+  for (bool left = true; left && rc == ZOLO_OK;) {
+    left = false;
+    for (int j = 0; j < np && rc == ZOLO_OK; ++j) {
+      if (cur[j].done) continue;
+      rc = factor_step<T>(P, &(*poles)[j], fw[j].get(), ss[j], &cur[j]);
+      left = left || !cur[j].done;
+    }
+  }
   for (int j = 1; j < np; ++j) {
     if (ss[j] == s) continue;
     hipEvent_t e = nullptr;
