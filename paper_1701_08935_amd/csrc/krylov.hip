@@ -41,7 +41,7 @@ __global__ void reduce_partials_kernel(T* __restrict__ out, int64_t ld_out, cons
 template <typename T, bool USE_LDS>
 __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const T* __restrict__ G, int p, double rel_shift,
                                                               T* __restrict__ Rg, T* __restrict__ Rinv, int* flag) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   T* lds_R = (T*)lds_raw;
   T* R = USE_LDS ? lds_R : Rg;
   // the inverse also lives in LDS when both fit
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(1024) void chol_upper_inv_kernel(const T* __restric
 template <typename T>
 __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict__ G, int p, double rel_shift,
                                                             T* __restrict__ Rg, T* __restrict__ Rinv, int* flag) {
-  extern __shared__ char lds_raw[];
+  extern __shared__ __align__(16) char lds_raw[];
   T* A = (T*)lds_raw;
   T* Z = A + (int64_t)p * p;
   const int tid = threadIdx.x, nt = blockDim.x, tx = tid & 31, ty = tid >> 5;
@@ -955,7 +955,7 @@ template <typename T>
 __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ At, const T* __restrict__ Bt, int n,
                                                          double tau_rank, double* __restrict__ theta,
                                                          T* __restrict__ Cmat, int* k_out, T* work) {
-  extern __shared__ char rr_raw[];
+  extern __shared__ __align__(16) char rr_raw[];
   const int tid = threadIdx.x, nt = blockDim.x;
   const int64_t nn = (int64_t)n * n;
   T* As = work;
