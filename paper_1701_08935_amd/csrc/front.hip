@@ -100,8 +100,11 @@ __global__ void extend_add_kernel(T* __restrict__ panel, T* __restrict__ upd, co
 // Then the off-diagonal blocks of X = L^-1 by block rows,
 // X_IJ = -X_II sum_{J <= K < I} L_IK X_KJ (LU: Y from U^T likewise).
 // LDS: A holds the block, then L (strict lower), D (diagonal) and, for LU,
-// U (strict upper); X holds L^-1 in its lower triangle and, for LU, (U^T)^-1
-// transposed in its upper triangle (both unit diagonal).
+// U (strict upper).  LU: X holds L^-1 in its lower triangle and (U^T)^-1
+// transposed in its upper triangle (both unit diagonal).  LDL^T: the strict
+// lower triangle of L^-1 is kept transposed in A's (otherwise unused) strict
+// upper triangle, so the kernel needs about half the LDS (two workgroups, or
+// one beside a GEMM workgroup, fit on a CU).
 constexpr int SBK = 16;  // sub-block (panel) width
 
 // 1 / d for a pivot: conj(d) / |d|^2 with one real division (the pivots here
@@ -130,10 +133,17 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
   if (J >= d.ns) return;
   const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
   __shared__ T A[FB][FB + 1];
-  __shared__ T X[FB][FB + 1];
-  __shared__ T Tm[SBK][FB - SBK + 1];  // block-row products of the inverse
-  __shared__ T Dv[FB], Di[FB];          // pivots and their inverses
-  __shared__ T cb[2][SBK], rb[2][SBK];  // column / row exchange inside a sub-block
+  __shared__ T X[LU ? FB : 1][LU ? FB + 1 : 1];
+  __shared__ T Tm[SBK][FB - SBK + 1];            // block-row products of the inverse
+  __shared__ T Dv[FB], Di[FB];                    // pivots and their inverses
+  __shared__ T cb[2][SBK], rb[2][LU ? SBK : 1];  // column / row exchange inside a sub-block
+  // entry (r, c), r > c, of the lower inverse L^-1
+  auto XL = [&](int r, int c) -> T& {
+    if constexpr (LU)
+      return X[r][c];
+    else
+      return A[c][r];
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const T one = ST<T>::one(), zero = ST<T>::zero();
   T* P = panel + d.panel;
@@ -150,7 +160,7 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
         v = U[(J + c) + (int64_t)(J + r) * k];
     }
     A[r][c] = v;
-    X[r][c] = zero;
+    if constexpr (LU) X[r][c] = zero;
   }
   __syncthreads();
 
@@ -169,9 +179,11 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
         const int b = j & 1;
         if (lane < SBK) {
           cb[b][lane] = a[j];  // column j
-          if (LU && lane == j) {
+          if constexpr (LU) {
+            if (lane == j) {
 #pragma unroll
-            for (int t = j + 1; t < SBK; ++t) rb[b][t] = a[t];  // row j
+              for (int t = j + 1; t < SBK; ++t) rb[b][t] = a[t];  // row j
+            }
           }
         }
         __builtin_amdgcn_wave_barrier();
@@ -186,7 +198,11 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
         const T g = mul(a[j], dinv);  // L(l, j) for l > j
 #pragma unroll
         for (int t = j + 1; t < SBK; ++t) {
-          const T w = LU ? rb[b][t] : cb[b][t];  // A(j, t) (= A(t, j) for LDL^T)
+          T w;  // A(j, t) (= A(t, j) for LDL^T)
+          if constexpr (LU)
+            w = rb[b][t];
+          else
+            w = cb[b][t];
           const T nv = sub(a[t], mul(g, w));
           a[t] = sel(below, nv, a[t]);
         }
@@ -225,11 +241,14 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
         if (l < pb) {
 #pragma unroll
           for (int r = 0; r < SBK; ++r) {
-            if (r < pb && r >= l) {
-              if (upper) {
-                if (r > l) X[c0 + l][c0 + r] = x[r];  // Y(r, l), stored transposed
+            if (r < pb && r > l) {  // the unit diagonal is implicit
+              if constexpr (LU) {
+                if (upper)
+                  X[c0 + l][c0 + r] = x[r];  // Y(r, l), stored transposed
+                else
+                  X[c0 + r][c0 + l] = x[r];
               } else {
-                X[c0 + r][c0 + l] = x[r];
+                XL(c0 + r, c0 + l) = x[r];
               }
             }
           }
@@ -257,14 +276,21 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
           // L(i, c0+t) = sum_q A(i, c0+q) Z(t, q) / D_t, Z = X_pp (LDL^T) or Y_pp (LU)
 #pragma unroll
           for (int q = 0; q < SBK; ++q) {
-            const T z = sel(q == t, one, sel(q < t, LU ? X[c0 + q][c0 + t] : X[c0 + t][c0 + q], zero));
+            T zq;
+            if constexpr (LU)
+              zq = X[c0 + q][c0 + t];
+            else
+              zq = XL(c0 + t, c0 + q);
+            const T z = sel(q == t, one, sel(q < t, zq, zero));
             s = fma_(s, A[i][c0 + q], z);
           }
         } else {
           // U(c0+t, i) = D_t^-1 sum_q X_pp(t, q) A(c0+q, i)
+          if constexpr (LU) {
 #pragma unroll
-          for (int q = 0; q < SBK; ++q)
-            s = fma_(s, sel(q == t, one, sel(q < t, X[c0 + t][c0 + q], zero)), A[c0 + q][i]);
+            for (int q = 0; q < SBK; ++q)
+              s = fma_(s, sel(q == t, one, sel(q < t, X[c0 + t][c0 + q], zero)), A[c0 + q][i]);
+          }
         }
         res[it] = mul(s, Di[c0 + t]);
       }
@@ -337,7 +363,12 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
             for (int u = 0; u < SBK; ++u) {
               const int t = t0 + u;
               const T lt = side ? A[t][ri + r] : A[ri + r][t];
-              const T z = sel(t == c, one, sel(t > c, side ? X[c][t] : X[t][c], zero));
+              T zt;
+              if constexpr (LU)
+                zt = side ? X[c][t] : X[t][c];
+              else
+                zt = XL(t, c);
+              const T z = sel(t == c, one, sel(t > c, zt, zero));
               s = fma_(s, lt, z);
             }
           }
@@ -352,13 +383,22 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
         T s = zero;
 #pragma unroll
         for (int t = 0; t < SBK; ++t) {
-          const T z = sel(t == r, one, sel(t < r, side ? X[ri + t][ri + r] : X[ri + r][ri + t], zero));
+          T zt;
+          if constexpr (LU)
+            zt = side ? X[ri + t][ri + r] : X[ri + r][ri + t];
+          else
+            zt = XL(ri + r, ri + t);
+          const T z = sel(t == r, one, sel(t < r, zt, zero));
           s = fma_(s, z, Tm[t][c]);
         }
-        if (side)
-          X[c][ri + r] = neg(s);
-        else
-          X[ri + r][c] = neg(s);
+        if constexpr (LU) {
+          if (side)
+            X[c][ri + r] = neg(s);
+          else
+            X[ri + r][c] = neg(s);
+        } else {
+          XL(ri + r, c) = neg(s);
+        }
       }
       __syncthreads();
     }
@@ -374,8 +414,8 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
       P[(J + r) + (int64_t)(J + c) * k] = sel(r == c, Dv[c], A[r][c]);
       if (LU) U[(J + r) + (int64_t)(J + c) * k] = sel(r == c, Dv[c], A[c][r]);
     }
-    Xo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, X[r][c], sel(r == c, one, zero));
-    if (LU) Yo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, X[c][r], sel(r == c, one, zero));
+    Xo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, XL(r, c), sel(r == c, one, zero));
+    if constexpr (LU) Yo[(J + r) + (int64_t)(J + c) * ns] = sel(r > c, X[c][r], sel(r == c, one, zero));
   }
 }
 
