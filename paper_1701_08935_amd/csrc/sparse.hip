@@ -7,65 +7,133 @@
 namespace zolo {
 namespace {
 
-__global__ void spmm_real_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                 const double* __restrict__ a, const double* __restrict__ b,
-                                 const double* __restrict__ X, int64_t ldx, int p, double* __restrict__ Ya,
-                                 int64_t ldya, double* __restrict__ Yb, int64_t ldyb) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * p) return;
-  int64_t i = e / p;
-  int c = (int)(e % p);
-  double sa = 0.0, sb = 0.0;
+// The SpMMs below give one wave to one matrix row: lanes cover the p columns
+// (two per lane per pass of 128), so every X row a nonzero selects is read as
+// whole 512-byte segments, and the row's column indices and values are
+// wave-uniform (scalar loads).  The hardware hands workgroups to the 8 XCDs
+// round-robin and each XCD has its own L2; the logical row block is remapped
+// so that every XCD takes one contiguous range of rows, and the X rows that
+// neighbouring matrix rows share are fetched into one L2, not several.
+constexpr int kSpmmRows = 4;  // rows (waves) per 256-thread workgroup
+
+// logical workgroup of physical workgroup blk in a grid of nb8 (a multiple of 8)
+__device__ inline int64_t xcd_block(int64_t blk, int64_t nb8) { return (blk & 7) * (nb8 >> 3) + (blk >> 3); }
+inline unsigned xcd_grid(int64_t rows) { return (unsigned)((((rows + kSpmmRows - 1) / kSpmmRows) + 7) & ~int64_t(7)); }
+
+__device__ inline int64_t spmm_row() {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  return xcd_block(blockIdx.x, gridDim.x) * kSpmmRows + w;
+}
+
+template <bool HB>
+__global__ __launch_bounds__(256) void spmm_real_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, const double* __restrict__ a,
+                                                        const double* __restrict__ b, const double* __restrict__ X,
+                                                        int64_t ldx, int p, double* __restrict__ Ya, int64_t ldya,
+                                                        double* __restrict__ Yb, int64_t ldyb) {
+  const int64_t i = spmm_row();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
   const int64_t e0 = rp[i], e1 = rp[i + 1];
-  if (Yb) {
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c1 = c0 + lane, c2 = c1 + 64;
+    const bool v1 = c1 < p, v2 = c2 < p;
+    const int l1 = v1 ? c1 : p - 1, l2 = v2 ? c2 : p - 1;  // loads stay in the row; unused lanes are not stored
+    double sa1 = 0.0, sa2 = 0.0, sb1 = 0.0, sb2 = 0.0;
+#pragma unroll 4
     for (int64_t q = e0; q < e1; ++q) {
-      double x = X[(int64_t)ci[q] * ldx + c];
-      sa = fma(a[q], x, sa);
-      sb = fma(b[q], x, sb);
+      const double* xr = X + (int64_t)ci[q] * ldx;
+      const double x1 = xr[l1], x2 = xr[l2];
+      const double av = a[q];
+      sa1 = fma(av, x1, sa1);
+      sa2 = fma(av, x2, sa2);
+      if constexpr (HB) {
+        const double bv = b[q];
+        sb1 = fma(bv, x1, sb1);
+        sb2 = fma(bv, x2, sb2);
+      }
     }
-    Yb[i * ldyb + c] = sb;
-  } else {
-    for (int64_t q = e0; q < e1; ++q) sa = fma(a[q], X[(int64_t)ci[q] * ldx + c], sa);
+    if (v1) {
+      Ya[i * ldya + c1] = sa1;
+      if constexpr (HB) Yb[i * ldyb + c1] = sb1;
+    }
+    if (v2) {
+      Ya[i * ldya + c2] = sa2;
+      if constexpr (HB) Yb[i * ldyb + c2] = sb2;
+    }
   }
-  Ya[i * ldya + c] = sa;
 }
 
 // complex Hermitian pencils: complex values, complex blocks
-__global__ void spmm_cplx_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                 const zd* __restrict__ a, const zd* __restrict__ b, const zd* __restrict__ X,
-                                 int64_t ldx, int p, zd* __restrict__ Ya, int64_t ldya, zd* __restrict__ Yb,
-                                 int64_t ldyb) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * p) return;
-  int64_t i = e / p;
-  int c = (int)(e % p);
-  zd sa{0.0, 0.0}, sb{0.0, 0.0};
+template <bool HB>
+__global__ __launch_bounds__(256) void spmm_cplx_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                        const int32_t* __restrict__ ci, const zd* __restrict__ a,
+                                                        const zd* __restrict__ b, const zd* __restrict__ X, int64_t ldx,
+                                                        int p, zd* __restrict__ Ya, int64_t ldya, zd* __restrict__ Yb,
+                                                        int64_t ldyb) {
+  const int64_t i = spmm_row();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
   const int64_t e0 = rp[i], e1 = rp[i + 1];
-  for (int64_t q = e0; q < e1; ++q) {
-    const zd x = X[(int64_t)ci[q] * ldx + c];
-    sa = fma_(sa, a[q], x);
-    if (Yb) sb = fma_(sb, b[q], x);
+  const zd z0{0.0, 0.0};
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c1 = c0 + lane, c2 = c1 + 64;
+    const bool v1 = c1 < p, v2 = c2 < p;
+    const int l1 = v1 ? c1 : p - 1, l2 = v2 ? c2 : p - 1;  // loads stay in the row; unused lanes are not stored
+    zd sa1 = z0, sa2 = z0, sb1 = z0, sb2 = z0;
+#pragma unroll 4
+    for (int64_t q = e0; q < e1; ++q) {
+      const zd* xr = X + (int64_t)ci[q] * ldx;
+      const zd x1 = xr[l1], x2 = xr[l2];
+      const zd av = a[q];
+      sa1 = fma_(sa1, av, x1);
+      sa2 = fma_(sa2, av, x2);
+      if constexpr (HB) {
+        const zd bv = b[q];
+        sb1 = fma_(sb1, bv, x1);
+        sb2 = fma_(sb2, bv, x2);
+      }
+    }
+    if (v1) {
+      Ya[i * ldya + c1] = sa1;
+      if constexpr (HB) Yb[i * ldyb + c1] = sb1;
+    }
+    if (v2) {
+      Ya[i * ldya + c2] = sa2;
+      if constexpr (HB) Yb[i * ldyb + c2] = sb2;
+    }
   }
-  Ya[i * ldya + c] = sa;
-  if (Yb) Yb[i * ldyb + c] = sb;
 }
 
-__global__ void spmm_shift_resid_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                        const double* __restrict__ a, const double* __restrict__ b, double sr,
-                                        double si, const zd* __restrict__ X, const double* __restrict__ T,
-                                        int64_t ldt, int p, zd* __restrict__ R) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * p) return;
-  int64_t i = e / p;
-  int c = (int)(e % p);
-  double re = 0.0, im = 0.0;
-  for (int64_t q = rp[i]; q < rp[i + 1]; ++q) {
-    zd x = X[(int64_t)ci[q] * p + c];
-    double kr = a[q] - sr * b[q], ki = -si * b[q];  // (A - sigma B)_iq
-    re = fma(kr, x.re, fma(-ki, x.im, re));
-    im = fma(kr, x.im, fma(ki, x.re, im));
+// R = T - (A - sigma B) X  (X complex, ld p; T real, ld ldt; R complex, ld p)
+__global__ __launch_bounds__(256) void spmm_shift_resid_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const double* __restrict__ a,
+                                                               const double* __restrict__ b, double sr, double si,
+                                                               const zd* __restrict__ X, const double* __restrict__ T,
+                                                               int64_t ldt, int p, zd* __restrict__ R) {
+  const int64_t i = spmm_row();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t e0 = rp[i], e1 = rp[i + 1];
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c1 = c0 + lane, c2 = c1 + 64;
+    const bool v1 = c1 < p, v2 = c2 < p;
+    const int l1 = v1 ? c1 : p - 1, l2 = v2 ? c2 : p - 1;  // loads stay in the row; unused lanes are not stored
+    double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
+#pragma unroll 4
+    for (int64_t q = e0; q < e1; ++q) {
+      const zd* xr = X + (int64_t)ci[q] * p;
+      const zd x1 = xr[l1], x2 = xr[l2];
+      const double kr = a[q] - sr * b[q], ki = -si * b[q];  // (A - sigma B)_iq
+      r1 = fma(kr, x1.re, fma(-ki, x1.im, r1));
+      i1 = fma(kr, x1.im, fma(ki, x1.re, i1));
+      r2 = fma(kr, x2.re, fma(-ki, x2.im, r2));
+      i2 = fma(kr, x2.im, fma(ki, x2.re, i2));
+    }
+    if (v1) R[i * p + c1] = zd{T[i * ldt + c1] - r1, -i1};
+    if (v2) R[i * p + c2] = zd{T[i * ldt + c2] - r2, -i2};
   }
-  R[i * p + c] = zd{T[i * ldt + c] - re, -im};
 }
 
 template <typename T>
@@ -195,10 +263,13 @@ template void conj_copy<zf>(zf*, const zf*, int64_t, hipStream_t);
 
 void spmm_cplx(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd* a, const zd* b, const zd* X,
                int64_t ldx, int p, zd* Ya, int64_t ldya, zd* Yb, int64_t ldyb, hipStream_t s) {
-  int64_t tot = n * p;
-  if (tot == 0) return;
-  hipLaunchKernelGGL(spmm_cplx_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, n, rowptr, colind, a, b,
-                     X, ldx, p, Ya, ldya, Yb, ldyb);
+  if (n * p == 0) return;
+  if (Yb)
+    hipLaunchKernelGGL(spmm_cplx_kernel<true>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rowptr, colind, a, b, X, ldx, p,
+                       Ya, ldya, Yb, ldyb);
+  else
+    hipLaunchKernelGGL(spmm_cplx_kernel<false>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rowptr, colind, a, b, X, ldx,
+                       p, Ya, ldya, Yb, ldyb);
 }
 
 void scale_copy(zd* W, int64_t ldw, const zd* V, int64_t ldv, double alpha, int64_t n, int p, hipStream_t s) {
@@ -218,15 +289,19 @@ void axpy_pair(zd* W, int64_t ldw, const zd* X, const zd* Xc, double wr, double 
 void spmm_real(int64_t n, const int64_t* rp, const int32_t* ci, const double* a, const double* b, const double* X,
                int64_t ldx, int p, double* Ya, int64_t ldya, double* Yb, int64_t ldyb, hipStream_t s) {
   if (n * p == 0) return;
-  hipLaunchKernelGGL(spmm_real_kernel, dim3(nblk(n * p)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya, ldya, Yb,
-                     ldyb);
+  if (Yb)
+    hipLaunchKernelGGL(spmm_real_kernel<true>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+                       ldya, Yb, ldyb);
+  else
+    hipLaunchKernelGGL(spmm_real_kernel<false>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+                       ldya, Yb, ldyb);
 }
 
 void spmm_shift_resid(int64_t n, const int64_t* rp, const int32_t* ci, const double* a, const double* b, double sr,
                       double si, const zd* X, const double* T, int64_t ldt, int p, zd* R, hipStream_t s) {
   if (n * p == 0) return;
-  hipLaunchKernelGGL(spmm_shift_resid_kernel, dim3(nblk(n * p)), dim3(256), 0, s, n, rp, ci, a, b, sr, si, X, T, ldt,
-                     p, R);
+  hipLaunchKernelGGL(spmm_shift_resid_kernel, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, sr, si, X, T, ldt, p,
+                     R);
 }
 
 template <typename T>
