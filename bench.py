@@ -220,9 +220,25 @@ def roofline(prof, steps, fp32=False, factor_streams=1):
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     ach = v["flops"] / sec / 1e12
     launches = max(v["launches"], 1)
-    return {"kernel": k, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-            "traffic": measured_traffic(k), "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / launches,
-            "flops_per_launch": v["flops"] / launches, "algorithmic_bytes_per_launch": v["bytes"] / launches}
+    out = {"kernel": k, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+           "traffic": measured_traffic(k), "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / launches,
+           "flops_per_launch": v["flops"] / launches, "algorithmic_bytes_per_launch": v["bytes"] / launches}
+    if out["traffic"]:
+        # the same kernel's measured HBM rate (its second roofline)
+        out["traffic_gbs"] = out["traffic"] / (out["avg_launch_us"] * 1e-6) / 1e9
+        out["traffic_frac_of_hbm"] = out["traffic_gbs"] / PEAK_HBM_GBS
+    return out
+
+
+def spmm_rate(prof):
+    """The CSR SpMM launches' algorithmic HBM rate (matrix values and indices,
+    the X block read once, the outputs written once) against the HBM peak."""
+    if not prof or not prof.get("spmm") or prof["spmm"]["ms"] <= 0:
+        return None
+    v = prof["spmm"]
+    ach = v["bytes"] / (v["ms"] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+            "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
 
 
 def cpu_baseline(sample_grid=16, n_lambda=64, n_ss=96):
@@ -346,6 +362,7 @@ def main():
         "t_iter_s": st["t_iter"],
         "t_symbolic_s": res["t_sym"],
         "roofline": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1, factor_streams=max(1, st["r1"])),
+        "spmm": spmm_rate(res["prof"]),
         "profile": res["prof"],
     }
     if args.config in ("c1", "m32") and not args.no_mixed:
