@@ -296,6 +296,14 @@ struct zolo_pencil {
   std::vector<std::vector<int>> lvl_diag_nJ, lvl_trsm_rows;  // per level per step
   int64_t inv_scratch = 0;   // L11 inverse temporaries of one level (recursive doubling, per side)
   int64_t conv_scratch = 0;  // -L21 X of one level's fronts before stacking (per side)
+  // forward-solve right-hand sides, in rows (independent of the block width):
+  // per row of a level's stacked front blocks, the right-hand-side row it starts
+  // from (-1: a border row) and, in fill_cidx[fill_cbeg[r] .. fill_cbeg[r+1]), the
+  // rows of the children's update blocks added to it, in child order
+  int32_t* fill_own = nullptr;
+  int32_t* fill_cbeg = nullptr;
+  int32_t* fill_cidx = nullptr;
+  std::vector<int64_t> lvl_fill_off, lvl_fill_rows;
   bool cplx() const { return scalar == ZOLO_COMPLEX128; }
 };
 
@@ -321,12 +329,17 @@ struct SolveProg {
   T* U = nullptr;  // each front's nb x p contribution to its parent (forward)
   T* Y = nullptr;  // forward solution, N x p per solve
   T* X = nullptr;  // solution, N x p per solve
-  SolveDesc* sd = nullptr;     // shared right-hand side
-  SolveDesc* sd_pp = nullptr;  // per-pole right-hand sides (pole j at j * xstride)
-  SolveExt* se = nullptr;
+  SolveDesc* sd = nullptr;
   std::vector<int> lvl_sd_off, lvl_sd_cnt, lvl_maxk;
-  std::vector<std::vector<GemmLaunch>> lvl_se;  // per slot (tiles = max nb)
-  int np = 0;                                    // poles solved together
+  // forward right-hand sides: per row of a level's W (levels one after the other),
+  // the right-hand-side row it starts from (-1: none) and, in cidx[cbeg[r] ..
+  // cbeg[r+1]), the rows of U (children's updates) added to it, in child order
+  const int32_t* own = nullptr;  // the pencil's tables (zolo_pencil::fill_*)
+  const int32_t* cbeg = nullptr;
+  const int32_t* cidx = nullptr;
+  std::vector<int64_t> lvl_row_off, lvl_rows;
+  int64_t wstride = 0, ustride = 0;  // elements between the solves' W and U regions
+  int np = 0;                        // poles solved together
   int64_t xstride = 0;                           // elements between poles' X (and Y) blocks
   GemmDesc<T>* gd = nullptr;                     // all poles, per level
   std::vector<GemmLaunch> fw, bw;                // [level]: forward, backward products
@@ -606,7 +619,61 @@ extern "C" void zolo_ctx_destroy(zolo_ctx* c) {
   DevicePool::get().trim();  // return cached device memory
 }
 
-static zolo_status build_layout(zolo_pencil* P) {
+static // Forward-solve fill tables (zolo_pencil::fill_*), by counting: the rows of
+// the update blocks are numbered over all fronts in level order, as the solve
+// program lays its update buffer out.
+zolo_status build_fill(zolo_pencil* P) {
+  const Symbolic& S = P->S;
+  const int nl = (int)S.levels.size();
+  std::vector<int64_t> urow(S.fronts.size(), 0);
+  int64_t ur = 0;
+  for (int L = 0; L < nl; ++L)
+    for (int f : S.levels[L]) {
+      urow[f] = ur;
+      ur += S.fronts[f].nb;
+    }
+  if (ur >= INT32_MAX) {
+    set_error("pencil too large for the solve tables");
+    return ZOLO_EINVAL;
+  }
+  std::vector<int32_t> own, cbeg, cidx, cnt;
+  P->lvl_fill_off.assign(nl, 0);
+  P->lvl_fill_rows.assign(nl, 0);
+  for (int L = 0; L < nl; ++L) {
+    P->lvl_fill_off[L] = (int64_t)own.size();
+    for (int f : S.levels[L]) {
+      const Front& Fr = S.fronts[f];
+      const int k = Fr.ns + Fr.nb;
+      cnt.assign(k + 1, 0);
+      for (int slot = 0; slot < Fr.child_count; ++slot) {
+        const Front& C = S.fronts[S.children[Fr.child_begin + slot]];
+        for (int i = 0; i < C.nb; ++i) ++cnt[S.parent_map[C.struct_off + i] + 1];
+      }
+      const int64_t base = (int64_t)cidx.size();
+      for (int r = 0; r < k; ++r) {
+        cnt[r + 1] += cnt[r];
+        own.push_back(r < Fr.ns ? Fr.first + r : -1);
+        cbeg.push_back((int32_t)(base + cnt[r]));
+      }
+      cidx.resize(base + cnt[k]);
+      for (int slot = 0; slot < Fr.child_count; ++slot) {  // child order within each row
+        const int ch = S.children[Fr.child_begin + slot];
+        const Front& C = S.fronts[ch];
+        for (int i = 0; i < C.nb; ++i) cidx[base + cnt[S.parent_map[C.struct_off + i]]++] = (int32_t)(urow[ch] + i);
+      }
+    }
+    P->lvl_fill_rows[L] = (int64_t)own.size() - P->lvl_fill_off[L];
+  }
+  cbeg.push_back((int32_t)cidx.size());
+  if (own.empty()) own.push_back(-1);
+  if (cidx.empty()) cidx.push_back(0);
+  CHK(P->mem.upload(&P->fill_own, own.data(), own.size()));
+  CHK(P->mem.upload(&P->fill_cbeg, cbeg.data(), cbeg.size()));
+  CHK(P->mem.upload(&P->fill_cidx, cidx.data(), cidx.size()));
+  return ZOLO_OK;
+}
+
+zolo_status build_layout(zolo_pencil* P) {
   const Symbolic& S = P->S;
   const int nf = (int)S.fronts.size();
   const int nl = (int)S.levels.size();
@@ -879,6 +946,7 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
   CHK(P->mem.upload(&P->struct_rows, S.struct_rows.data(), S.struct_rows.size()));
   CHK(P->mem.upload(&P->pmap, S.parent_map.data(), S.parent_map.size()));
   CHK(build_layout(P.get()));
+  CHK(build_fill(P.get()));
   *out = P.release();
   return ZOLO_OK;
 }
@@ -1545,11 +1613,9 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   CHK(G->mem.alloc(&G->Y, npx * np));
   CHK(G->mem.alloc(&G->X, npx * np));
   std::vector<SolveDesc> sd;
-  std::vector<SolveExt> se;
   G->lvl_sd_off.assign(nl, 0);
   G->lvl_sd_cnt.assign(nl, 0);
   G->lvl_maxk.assign(nl, 0);
-  G->lvl_se.assign(nl, {});
   // per level, per front (level order): offsets within one pole's regions
   std::vector<std::vector<int64_t>> woff(nl);
   for (int L = 0; L < nl; ++L) {
@@ -1571,7 +1637,6 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
         d.u = j * utot + uoff[f];
         d.srow = Fr.struct_off;
         d.xo = j * npx;
-        d.so = 0;
         d.first = Fr.first;
         d.ns = Fr.ns;
         d.nb = Fr.nb;
@@ -1581,37 +1646,15 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
       }
     }
     G->lvl_sd_cnt[L] = (int)sd.size() - G->lvl_sd_off[L];
-    int maxc = 0;
-    for (int f : S.levels[L]) maxc = std::max(maxc, S.fronts[f].child_count);
-    for (int slot = 0; slot < maxc; ++slot) {
-      GemmLaunch g;
-      g.off = (int)se.size();
-      for (int j = 0; j < np; ++j) {
-        size_t i = 0;
-        for (int f : S.levels[L]) {
-          const Front& Fr = S.fronts[f];
-          int64_t wf = j * wmax + woff[L][i++];
-          if (slot >= Fr.child_count) continue;
-          int ch = S.children[Fr.child_begin + slot];
-          const Front& C = S.fronts[ch];
-          if (C.nb == 0) continue;
-          SolveExt e{};
-          e.child_u = j * utot + uoff[ch];
-          e.par_w = wf;
-          e.pmap = C.struct_off;
-          e.nb_c = C.nb;
-          se.push_back(e);
-          g.tiles = std::max(g.tiles, (int)C.nb);
-        }
-      }
-      g.cnt = (int)se.size() - g.off;
-      G->lvl_se[L].push_back(g);
-    }
   }
+  G->own = P->fill_own;
+  G->cbeg = P->fill_cbeg;
+  G->cidx = P->fill_cidx;
+  G->lvl_row_off = P->lvl_fill_off;
+  G->lvl_rows = P->lvl_fill_rows;
+  G->wstride = wmax;
+  G->ustride = utot;
   CHK(G->mem.upload(&G->sd, sd.data(), sd.size()));
-  for (SolveDesc& d : sd) d.so = d.xo;
-  CHK(G->mem.upload(&G->sd_pp, sd.data(), sd.size()));
-  CHK(G->mem.upload(&G->se, se.data(), se.size()));
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
   G->fw.assign(nl, GemmLaunch());
   G->bw.assign(nl, GemmLaunch());
@@ -1744,13 +1787,11 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, boo
   zolo_pencil* P = F->P;
   const int nl = (int)P->S.levels.size();
   const int p = G->p;
-  const SolveDesc* sdesc = per_pole ? G->sd_pp : G->sd;
   for (int L = 0; L < nl; ++L) {
     {
       prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
-      solve_gather_own<Ts, T>(G->W, src, lds, sdesc + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p, G->lvl_maxk[L], s);
-      for (const GemmLaunch& g : G->lvl_se[L])
-        solve_extend_add<T>(G->W, G->U, P->pmap, G->se + g.off, g.cnt, p, g.tiles, s);
+      solve_fill<Ts, T>(G->W, G->wstride, src, lds, per_pole ? G->xstride : 0, G->U, G->ustride,
+                        G->own + G->lvl_row_off[L], G->cbeg + G->lvl_row_off[L], G->cidx, G->lvl_rows[L], p, G->np, s);
     }
     run_gemm<T>(G->gd, G->fw[L], s, 1);
   }

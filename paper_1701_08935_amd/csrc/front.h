@@ -33,15 +33,7 @@ struct SolveDesc {
   int64_t u;       // element offset of U in the U buffer (global over fronts)
   int64_t srow;    // offset into struct_rows
   int64_t xo;      // element offset of this solve's blocks in X and Y
-  int64_t so;      // element offset of this pole's right-hand side (0 = shared)
   int32_t first, ns, nb, k;
-};
-
-struct SolveExt {  // child U (nb_c x p) into parent W rows pmap
-  int64_t child_u;
-  int64_t par_w;
-  int64_t pmap;
-  int32_t nb_c, pad;
 };
 
 // assembly: panel[dst[e]] = a[src[e]] - sigma * b[src[e]]  (real pencil values)
@@ -72,14 +64,16 @@ template <typename T>
 void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
                          int* breakdown, hipStream_t s);
 
-// W rows [0, ns) <- src rows [first, first+ns) (converted), rows [ns, k) <- 0.
+// Forward right-hand sides of one level for np solves at once.  Row r of the
+// level's W (its fronts' k x p blocks one after the other, row-major; solve j
+// at j * wstride) = right-hand-side row own[r] (converted to T; zero where
+// own[r] < 0, the border rows) plus the children's update rows
+// cidx[cbeg[r]] .. cidx[cbeg[r+1] - 1] of U (solve j at j * ustride), added in
+// that order.  src: solve j at j * sstride (0: one right-hand side for all).
 template <typename Ts, typename T>
-void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
-                      hipStream_t s);
-// W_parent[pmap[i]] += U_child[i]
-template <typename T>
-void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, int nd, int p, int max_nb,
-                      hipStream_t s);
+void solve_fill(T* W, int64_t wstride, const Ts* src, int64_t ldsrc, int64_t sstride, const T* U, int64_t ustride,
+                const int32_t* own, const int32_t* cbeg, const int32_t* cidx, int64_t rows, int p, int np,
+                hipStream_t s);
 // Backward right-hand side of each front, into W (k x p, row-major):
 // rows [0, ns): D^-1 Y[first + r]; rows [ns, k): X[struct_rows[srow + r - ns]].
 template <typename T>

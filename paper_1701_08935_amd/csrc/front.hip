@@ -419,30 +419,26 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel
   }
 }
 
+// one wave per W row, lanes over the p columns
 template <typename Ts, typename T>
-__global__ void gather_own_kernel(T* __restrict__ W, const Ts* __restrict__ src, int64_t ldsrc,
-                                  const SolveDesc* __restrict__ descs, int p) {
-  const SolveDesc d = descs[blockIdx.y];
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t tot = (int64_t)d.k * p;
-  if (e >= tot) return;
-  int64_t r = e / p, c = e % p;
-  T v = ST<T>::zero();
-  if (r < d.ns) v = cvt<T, Ts>(src[d.so + (d.first + r) * ldsrc + c]);
-  W[d.w + e] = v;
-}
-
-template <typename T>
-__global__ void solve_ext_kernel(T* __restrict__ W, const T* __restrict__ U, const int32_t* __restrict__ pmap,
-                                 const SolveExt* __restrict__ descs, int p) {
-  const SolveExt d = descs[blockIdx.y];
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t tot = (int64_t)d.nb_c * p;
-  if (e >= tot) return;
-  int64_t i = e / p, c = e % p;
-  int64_t pr = pmap[d.pmap + i];
-  T* dst = W + d.par_w + pr * p + c;
-  *dst = add(*dst, U[d.child_u + e]);
+__global__ __launch_bounds__(256) void solve_fill_kernel(T* __restrict__ W, int64_t wstride, const Ts* __restrict__ src,
+                                                         int64_t ldsrc, int64_t sstride, const T* __restrict__ U,
+                                                         int64_t ustride, const int32_t* __restrict__ own,
+                                                         const int32_t* __restrict__ cbeg,
+                                                         const int32_t* __restrict__ cidx, int64_t rows, int p) {
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t r = (int64_t)blockIdx.x * 4 + w;
+  if (r >= rows) return;
+  const int j = blockIdx.y, lane = threadIdx.x & 63;
+  const int o = own[r], q0 = cbeg[r], q1 = cbeg[r + 1];
+  T* wr = W + (int64_t)j * wstride + r * p;
+  const Ts* sr = src + (int64_t)j * sstride + (int64_t)(o < 0 ? 0 : o) * ldsrc;
+  const T* ub = U + (int64_t)j * ustride;
+  for (int c = lane; c < p; c += 64) {
+    T acc = o >= 0 ? cvt<T, Ts>(sr[c]) : ST<T>::zero();
+    for (int q = q0; q < q1; ++q) acc = add(acc, ub[(int64_t)cidx[q] * p + c]);
+    wr[c] = acc;
+  }
 }
 
 template <typename T>
@@ -520,20 +516,12 @@ void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int 
 }
 
 template <typename Ts, typename T>
-void solve_gather_own(T* W, const Ts* src, int64_t ldsrc, const SolveDesc* d, int nd, int p, int max_k,
-                      hipStream_t s) {
-  if (nd <= 0) return;
-  int64_t tot = (int64_t)max_k * p;
-  hipLaunchKernelGGL((gather_own_kernel<Ts, T>), dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, src,
-                     ldsrc, d, p);
-}
-
-template <typename T>
-void solve_extend_add(T* W, const T* U, const int32_t* pmap, const SolveExt* d, int nd, int p, int max_nb,
-                      hipStream_t s) {
-  if (nd <= 0 || max_nb <= 0) return;
-  int64_t tot = (int64_t)max_nb * p;
-  hipLaunchKernelGGL(solve_ext_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, U, pmap, d, p);
+void solve_fill(T* W, int64_t wstride, const Ts* src, int64_t ldsrc, int64_t sstride, const T* U, int64_t ustride,
+                const int32_t* own, const int32_t* cbeg, const int32_t* cidx, int64_t rows, int p, int np,
+                hipStream_t s) {
+  if (rows <= 0 || p <= 0 || np <= 0) return;
+  hipLaunchKernelGGL((solve_fill_kernel<Ts, T>), dim3((unsigned)((rows + 3) / 4), np), dim3(256), 0, s, W, wstride,
+                     src, ldsrc, sstride, U, ustride, own, cbeg, cidx, rows, p);
 }
 
 template <typename T>
@@ -560,16 +548,19 @@ void front_stack(const StackDesc<T>* d, int nd, int64_t max_elems, hipStream_t s
   template void front_extend_add_lu<T>(T*, T*, T*, const int32_t*, const ExtDesc*, int, int, hipStream_t);           \
   template void front_diag_block_lu<T>(T*, T*, T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);            \
   template void front_diag_block<T>(T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);                       \
-  template void solve_extend_add<T>(T*, const T*, const int32_t*, const SolveExt*, int, int, int, hipStream_t);      \
   template void solve_gather_back<T>(T*, const T*, const T*, const int32_t*, const SolveDesc*, int, int, int,        \
                                      hipStream_t);                                                                   \
   template void front_stack<T>(const StackDesc<T>*, int, int64_t, hipStream_t);
 INST(zd)
 INST(zf)
 #undef INST
-template void solve_gather_own<double, zd>(zd*, const double*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
-template void solve_gather_own<zd, zd>(zd*, const zd*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
-template void solve_gather_own<double, zf>(zf*, const double*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
-template void solve_gather_own<zd, zf>(zf*, const zd*, int64_t, const SolveDesc*, int, int, int, hipStream_t);
+#define INST_FILL(Ts, T)                                                                                    \
+  template void solve_fill<Ts, T>(T*, int64_t, const Ts*, int64_t, int64_t, const T*, int64_t, const int32_t*, \
+                                  const int32_t*, const int32_t*, int64_t, int, int, hipStream_t);
+INST_FILL(double, zd)
+INST_FILL(zd, zd)
+INST_FILL(double, zf)
+INST_FILL(zd, zf)
+#undef INST_FILL
 
 }  // namespace zolo
