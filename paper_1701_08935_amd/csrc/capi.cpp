@@ -1032,7 +1032,7 @@ struct FactorLevelG {
   std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
   GemmLaunch conv;                     // -L21 L11^-1 of every front (solve panel, lower part)
   int stk_off = 0, stk_cnt = 0;        // stacking of the solve panels
-  int64_t stk_max = 0;                 // largest k * ns of the level
+  int64_t stk_max = 0;                 // largest ns (panel columns) of the level
 };
 template <typename T>
 struct FactorWork {
@@ -1284,7 +1284,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
           if (Fr.ns > 0) {
             StackDesc<T> sdsc{Pn, X, fw->ctmp + co, Fr.ns, Fr.nb};
             stk.push_back(sdsc);
-            lg[L].stk_max = std::max(lg[L].stk_max, k * Fr.ns);
+            lg[L].stk_max = std::max<int64_t>(lg[L].stk_max, Fr.ns);
           }
           if (Fr.nb == 0 || Fr.ns == 0) continue;
           GemmDesc<T> d{};

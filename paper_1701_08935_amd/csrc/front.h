@@ -91,6 +91,6 @@ struct StackDesc {
   int32_t ns, nb;
 };
 template <typename T>
-void front_stack(const StackDesc<T>* d, int nd, int64_t max_elems, hipStream_t s);
+void front_stack(const StackDesc<T>* d, int nd, int64_t max_cols, hipStream_t s);  // max_cols: largest ns
 
 }  // namespace zolo

@@ -441,32 +441,37 @@ __global__ __launch_bounds__(256) void solve_fill_kernel(T* __restrict__ W, int6
   }
 }
 
+// one wave per row of a front's W, lanes over the p columns
 template <typename T>
-__global__ void gather_back_kernel(T* __restrict__ W, const T* __restrict__ Y, const T* __restrict__ X,
-                                   const int32_t* __restrict__ srows, const SolveDesc* __restrict__ descs, int p) {
+__global__ __launch_bounds__(256) void gather_back_kernel(T* __restrict__ W, const T* __restrict__ Y,
+                                                          const T* __restrict__ X, const int32_t* __restrict__ srows,
+                                                          const SolveDesc* __restrict__ descs, int p) {
   const SolveDesc d = descs[blockIdx.y];
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t tot = (int64_t)d.k * p;
-  if (e >= tot) return;
-  int64_t r = e / p, c = e % p;
-  T v;
+  const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (r >= d.k) return;
+  const int lane = threadIdx.x & 63;
+  T* wr = W + d.w + r * p;
   if (r < d.ns) {
-    const T* dv = (const T*)d.dv;
-    v = mul(Y[d.xo + (d.first + r) * p + c], inv_(dv[d.first + r]));
+    const T dinv = inv_(((const T*)d.dv)[d.first + r]);
+    const T* yr = Y + d.xo + (d.first + r) * p;
+    for (int c = lane; c < p; c += 64) wr[c] = mul(yr[c], dinv);
   } else {
-    v = X[d.xo + (int64_t)srows[d.srow + r - d.ns] * p + c];
+    const T* xr = X + d.xo + (int64_t)srows[d.srow + r - d.ns] * p;
+    for (int c = lane; c < p; c += 64) wr[c] = xr[c];
   }
-  W[d.w + e] = v;
 }
 
+// one workgroup per column of a front's panel, threads over its k rows
 template <typename T>
-__global__ void stack_kernel(const StackDesc<T>* __restrict__ descs) {
+__global__ __launch_bounds__(256) void stack_kernel(const StackDesc<T>* __restrict__ descs) {
   const StackDesc<T> d = descs[blockIdx.y];
+  const int64_t c = blockIdx.x;
+  if (c >= d.ns) return;
   const int64_t k = (int64_t)d.ns + d.nb;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * d.ns) return;
-  const int64_t c = e / k, r = e % k;
-  d.dst[e] = r < d.ns ? d.top[r + c * d.ns] : d.bot[(r - d.ns) + c * d.nb];
+  T* dst = d.dst + c * k;
+  const T* top = d.top + c * d.ns;
+  const T* bot = d.bot + c * d.nb;
+  for (int64_t r = threadIdx.x; r < k; r += blockDim.x) dst[r] = r < d.ns ? top[r] : bot[r - d.ns];
 }
 
 }  // namespace
@@ -528,15 +533,14 @@ template <typename T>
 void solve_gather_back(T* W, const T* Y, const T* X, const int32_t* srows, const SolveDesc* d, int nd, int p,
                        int max_k, hipStream_t s) {
   if (nd <= 0 || max_k <= 0) return;
-  int64_t tot = (int64_t)max_k * p;
-  hipLaunchKernelGGL(gather_back_kernel<T>, dim3((unsigned)((tot + 255) / 256), nd), dim3(256), 0, s, W, Y, X, srows,
-                     d, p);
+  hipLaunchKernelGGL(gather_back_kernel<T>, dim3((unsigned)((max_k + 3) / 4), nd), dim3(256), 0, s, W, Y, X, srows, d,
+                     p);
 }
 
 template <typename T>
-void front_stack(const StackDesc<T>* d, int nd, int64_t max_elems, hipStream_t s) {
-  if (nd <= 0 || max_elems <= 0) return;
-  hipLaunchKernelGGL(stack_kernel<T>, dim3((unsigned)((max_elems + 255) / 256), nd), dim3(256), 0, s, d);
+void front_stack(const StackDesc<T>* d, int nd, int64_t max_cols, hipStream_t s) {
+  if (nd <= 0 || max_cols <= 0) return;
+  hipLaunchKernelGGL(stack_kernel<T>, dim3((unsigned)max_cols, nd), dim3(256), 0, s, d);
 }
 
 #define INST(T)                                                                                                      \
