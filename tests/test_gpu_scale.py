@@ -68,18 +68,19 @@ def grid64(ctx):
     return gp, P
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_solve_window_64(ctx, grid64, precision):
-    say(f"zolo_solve grid7 64^3 window 64 block 96 precision={precision}")
-    gp, P = grid64
-    w = json.load(open(golden("window_grid7_64.json")))
-    A, B = gp.scipy()
-    Q0 = pencils.gaussian_block(gp.n, 96, seed=2)
-    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=96, precision=precision)
-    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, opts, Q0=_dev(Q0))
+@pytest.fixture(scope="module")
+def grid64_leaf128(ctx):
+    say("build grid7 64^3 pencil, leaf 128")
+    gp = pencils.grid7(64)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=128)
+    return gp, P
+
+
+def _check_window_64(gp, w, eig, vec, st, rc):
     say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e}")
     assert rc == 0
     assert len(eig) == w["inertia_count"] == 64
+    A, B = gp.scipy()
     eig = np.array(eig)
     ref = np.array(w["eigenvalues"])
     rel = np.max(np.abs(eig - ref) / np.abs(ref))
@@ -109,6 +110,30 @@ def test_solve_window_64(ctx, grid64, precision):
     # the stored values carry the shift-invert Lanczos reference's own error (observed about 1e-13
     # relative at this N), so they are compared with that slack on top of the bound
     assert np.all(np.abs(eig - ref) <= kt + 5e-13 * np.abs(ref))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_window_64(ctx, grid64, precision):
+    say(f"zolo_solve grid7 64^3 window 64 block 96 precision={precision}")
+    gp, P = grid64
+    w = json.load(open(golden("window_grid7_64.json")))
+    Q0 = pencils.gaussian_block(gp.n, 96, seed=2)
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=96, precision=precision)
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, opts, Q0=_dev(Q0))
+    _check_window_64(gp, w, eig, vec, st, rc)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_window_64_bench_configuration(ctx, grid64_leaf128, precision):
+    """The query bench.py times: leaf 128, GMRES relative tolerance 1e-8 per shift."""
+    say(f"zolo_solve grid7 64^3 window 64 block 96, leaf 128, GMRES 1e-8, precision={precision}")
+    gp, P = grid64_leaf128
+    w = json.load(open(golden("window_grid7_64.json")))
+    Q0 = pencils.gaussian_block(gp.n, 96, seed=2)
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=96, precision=precision)
+    opts.tol_gmres = 1e-8
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, opts, Q0=_dev(Q0))
+    _check_window_64(gp, w, eig, vec, st, rc)
 
 
 def test_pole_solve_64_residual(ctx, grid64):
