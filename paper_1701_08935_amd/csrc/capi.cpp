@@ -1877,8 +1877,11 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
 // until max_j ||R_j|| / ||T|| <= tol_inner (column-wise).
 // Complex Hermitian pencils (VT = zd, FP64 factors): X_j = K_j^-1 T for
 // j < r1 and X_{r1+j} = K_j^-H T.
+// Xres (optional): where the solutions are left.  FP64 factors: the solve
+// program's own buffer (valid until its next solve), so nothing is copied to X.
 template <typename VT>
-zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double tol_inner, hipStream_t s) {
+zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double tol_inner, hipStream_t s,
+                            const zd** Xres = nullptr) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
   const int np = F->co.r1 * (P->cplx() ? 2 : 1);
@@ -1887,7 +1890,10 @@ zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double t
     SolveProg<zd>* G = get_prog<zd>(F, p);
     if (!G) return ZOLO_ENOMEM;
     run_solve<VT, zd>(F, G, T, p, false, s);
-    HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * npx * np, hipMemcpyDeviceToDevice, s));
+    if (Xres)
+      *Xres = G->X;
+    else
+      HIPC(hipMemcpyAsync(X, G->X, sizeof(zd) * npx * np, hipMemcpyDeviceToDevice, s));
     F->n_solv += (long long)p * np;
     return ZOLO_OK;
   }
@@ -1921,6 +1927,7 @@ zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double t
     add_lowp(X, G->X, npx * np, s);
     F->n_refine += (long long)p * np;
   }
+  if (Xres) *Xres = X;
   return ZOLO_OK;
   }
 }
@@ -1945,18 +1952,28 @@ zolo_status apply_G_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* W,
     else
       spmm_real(n, P->prow, P->pcol, P->pb, nullptr, V, ldv, p, Tb, p, nullptr, 0, s);
   }
-  {
-    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 2.0 * sizeof(VT) * n * p, s);
-    scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
-  }
-  CHK(poles_solve_all<VT>(F, Tb, p, ws.Xc, tol_inner, s));
-  for (int j = 0; j < co.r1; ++j) {
-    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 32.0 * n * p, s);
-    if constexpr (ST<VT>::cplx)
-      axpy_pair(W, ldw, ws.Xc + (int64_t)j * n * p, ws.Xc + (int64_t)(co.r1 + j) * n * p, co.M_hat * co.w_hat_re[j],
+  const zd* Xs = nullptr;  // the poles' solutions, N x p each, pole j at Xs + j n p
+  if constexpr (ST<VT>::cplx) {
+    {
+      prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 2.0 * sizeof(VT) * n * p, s);
+      scale_copy(W, ldw, V, ldv, co.M_hat * co.c0, n, p, s);
+    }
+    CHK(poles_solve_all<VT>(F, Tb, p, ws.Xc, tol_inner, s, &Xs));
+    for (int j = 0; j < co.r1; ++j) {
+      prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 48.0 * n * p, s);
+      axpy_pair(W, ldw, Xs + (int64_t)j * n * p, Xs + (int64_t)(co.r1 + j) * n * p, co.M_hat * co.w_hat_re[j],
                 co.M_hat * co.w_hat_im[j], n, p, s);
-    else
-      axpy_re(W, ldw, ws.Xc + (int64_t)j * n * p, co.M_hat * co.w_hat_re[j], co.M_hat * co.w_hat_im[j], n, p, s);
+    }
+  } else {
+    // W = M c0 V + sum_j 2 Re(M w_j X_j) in one pass over V, the X_j and W
+    CHK(poles_solve_all<VT>(F, Tb, p, ws.Xc, tol_inner, s, &Xs));
+    GCombineCoef wc{};
+    for (int j = 0; j < co.r1; ++j) {
+      wc.wr[j] = co.M_hat * co.w_hat_re[j];
+      wc.wi[j] = co.M_hat * co.w_hat_im[j];
+    }
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, (16.0 + 16.0 * co.r1) * n * p, s);
+    g_combine_real(W, ldw, (const double*)V, ldv, co.M_hat * co.c0, Xs, n * p, wc, co.r1, n, p, s);
   }
   return ZOLO_OK;
 }

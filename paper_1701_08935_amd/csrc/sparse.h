@@ -28,6 +28,13 @@ void scale_copy(zd* W, int64_t ldw, const zd* V, int64_t ldv, double alpha, int6
 void axpy_pair(zd* W, int64_t ldw, const zd* X, const zd* Xc, double wr, double wi, int64_t n, int p, hipStream_t s);
 // W += 2 * Re(w * X)  (X complex, contiguous N x p)
 void axpy_re(double* W, int64_t ldw, const zd* X, double wr, double wi, int64_t n, int p, hipStream_t s);
+// W = alpha V + sum_{j < r} 2 Re(w_j X_j), X_j complex N x p (ld p) at X + j * xstride; r <= 16.
+// One pass, the terms added in the order scale_copy then axpy_re for j = 0, 1, ... would add them.
+struct GCombineCoef {
+  double wr[16], wi[16];
+};
+void g_combine_real(double* W, int64_t ldw, const double* V, int64_t ldv, double alpha, const zd* X, int64_t xstride,
+                    const GCombineCoef& w, int r, int64_t n, int p, hipStream_t s);
 // dst = conj(src)
 template <typename T>
 void conj_copy(T* dst, const T* src, int64_t n, hipStream_t s);

@@ -203,6 +203,21 @@ __global__ void axpy_re_kernel(double* __restrict__ W, int64_t ldw, const zd* __
   W[i * ldw + c] += 2.0 * (wr * x.re - wi * x.im);
 }
 
+__global__ void g_combine_real_kernel(double* __restrict__ W, int64_t ldw, const double* __restrict__ V, int64_t ldv,
+                                      double alpha, const zd* __restrict__ X, int64_t xstride, GCombineCoef w, int r,
+                                      int64_t n, int p) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * p) return;
+  int64_t i = e / p;
+  int c = (int)(e % p);
+  double acc = alpha * V[i * ldv + c];
+  for (int j = 0; j < r; ++j) {
+    const zd x = X[(int64_t)j * xstride + e];
+    acc += 2.0 * (w.wr[j] * x.re - w.wi[j] * x.im);
+  }
+  W[i * ldw + c] = acc;
+}
+
 __global__ void add_lowp_kernel(zd* __restrict__ X, const zf* __restrict__ D, int64_t n) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
@@ -329,6 +344,12 @@ void scale_copy(double* W, int64_t ldw, const double* V, int64_t ldv, double alp
 void axpy_re(double* W, int64_t ldw, const zd* X, double wr, double wi, int64_t n, int p, hipStream_t s) {
   if (n * p == 0) return;
   hipLaunchKernelGGL(axpy_re_kernel, dim3(nblk(n * p)), dim3(256), 0, s, W, ldw, X, wr, wi, n, p);
+}
+void g_combine_real(double* W, int64_t ldw, const double* V, int64_t ldv, double alpha, const zd* X, int64_t xstride,
+                    const GCombineCoef& w, int r, int64_t n, int p, hipStream_t s) {
+  if (n * p == 0) return;
+  hipLaunchKernelGGL(g_combine_real_kernel, dim3(nblk(n * p)), dim3(256), 0, s, W, ldw, V, ldv, alpha, X, xstride, w,
+                     r, n, p);
 }
 void add_lowp(zd* X, const zf* D, int64_t n, hipStream_t s) {
   if (n == 0) return;
