@@ -435,7 +435,7 @@ void run_gemm(const GemmDesc<T>* base, const GemmLaunch& L, hipStream_t s, int t
 // kSplitTarget workgroups.  Launches run one after another on a stream, so
 // they share one partial buffer and one tile-counter array, sized for the
 // largest launch; patch_split fills in the pointers once they exist.
-constexpr int kSplitBelow = 512, kSplitTarget = 1024, kMinSplitChunks = 8, kMaxSplit = 16;
+constexpr int kSplitBelow = 256, kSplitTarget = 512, kMinSplitChunks = 8, kMaxSplit = 16;
 struct SplitPlan {
   std::vector<std::pair<int, std::pair<int64_t, int64_t>>> at;  // descriptor -> (part offset, counter offset)
   int64_t part = 0, cnt = 0;                                    // sizes (real scalars, counters)
