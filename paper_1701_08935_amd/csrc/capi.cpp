@@ -2308,7 +2308,11 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
     HIPC(hipMemcpyAsync(&k, kdev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     HIPC(hipGetLastError());
-    if (k <= 0) {
+    if (k < 0) {
+      set_error("Rayleigh-Ritz: a Hermitian eigensolve did not converge");
+      return ZOLO_EBREAKDOWN;
+    }
+    if (k == 0) {
       set_error("Rayleigh-Ritz: filtered block has rank 0");
       return ZOLO_EBREAKDOWN;
     }

@@ -50,7 +50,8 @@ void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, zd* 
 
 // ---- Rayleigh-Ritz reduction on the device (single workgroup) ----
 // Inputs At, Bt (n x n, col-major, Hermitian).  Outputs theta[k] (ascending),
-// Cmat (n x k col-major, ld n) with X = Y Cmat B-orthonormal, *k_out.
+// Cmat (n x k col-major, ld n) with X = Y Cmat B-orthonormal, *k_out (-1 when
+// one of the two Hermitian eigensolves did not converge).
 // work: 6 n^2 T values + 2 n doubles + 2 n ints.
 template <typename T>
 void rr_reduce(const T* At, const T* Bt, int n, double tau_rank, double* theta, T* Cmat, int* k_out, T* work,

@@ -656,10 +656,10 @@ __device__ inline bool heev_negligible(double e, double d0, double d1) {
 // L: the matrix stage (A, then V) is in LDS.  A compile-time choice, so that every
 // matrix access has a fixed address space (LDS or global), never a flat one.
 template <typename T, bool L>
-__device__ __attribute__((always_inline)) void heev_run(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds) {
+__device__ __attribute__((always_inline)) bool heev_run(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int wv = tid >> 6, ln = tid & 63, nw = nt >> 6;
-  __shared__ int sw_l[2], sw_h[2], ql_done[2];
+  __shared__ int sw_l[2], sw_h[2], ql_done[2], q_capped;
   // vectors first, the matrix after them
   double* dd = (double*)lds;  // diagonal of T_r
   double* ee = dd + m;        // ee[k] couples k and k+1
@@ -782,6 +782,7 @@ __device__ __attribute__((always_inline)) void heev_run(T* __restrict__ Mg, T* _
   //    is [q_l, q_h]: everything below q_h has converged, ee[q_l - 1] is zero.
   int q_iter = 0, q_h = m - 1, q_l = 0;
   bool q_done = false;
+  if (tid == 0) q_capped = 0;  // read after the rounds, which end with a barrier
   for (int round = 0;; ++round) {
     const int b = round & 1;
     if (tid == 0) {
@@ -803,7 +804,10 @@ __device__ __attribute__((always_inline)) void heev_run(T* __restrict__ Mg, T* _
         if (nl > 0) ee[nl - 1] = 0.0;
         q_l = nl;
       }
-      if (!q_done && q_iter >= 30 * m) q_done = true;
+      if (!q_done && q_iter >= 30 * m) {  // not converged: reported to the caller
+        q_done = true;
+        q_capped = 1;
+      }
       if (!q_done) {
         l = q_l;
         h = q_h;
@@ -925,11 +929,14 @@ __device__ __attribute__((always_inline)) void heev_run(T* __restrict__ Mg, T* _
   for (int i = tid; i < m; i += nt) Mg[i + (int64_t)i * m] = cvt<T, double>(dd[i]);
   __threadfence_block();
   __syncthreads();
+  return q_capped == 0;
 }
 
+// returns false when the QR steps did not converge (iteration cap reached)
 template <typename T>
-__device__ __attribute__((always_inline)) void heev_tridiag(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds, size_t lds_bytes) {
-  if (m <= 0) return;
+__device__ __attribute__((always_inline)) bool heev_tridiag(T* __restrict__ Mg, T* __restrict__ Vg, int m, char* lds,
+                                                            size_t lds_bytes) {
+  if (m <= 0) return true;
   if (m == 1) {
     if (threadIdx.x == 0) {
       Vg[0] = ST<T>::one();
@@ -937,12 +944,10 @@ __device__ __attribute__((always_inline)) void heev_tridiag(T* __restrict__ Mg, 
     }
     __threadfence_block();
     __syncthreads();
-    return;
+    return true;
   }
-  if (heev_mat_off<T>(m) + (size_t)m * m * sizeof(T) <= lds_bytes)
-    heev_run<T, true>(Mg, Vg, m, lds);
-  else
-    heev_run<T, false>(Mg, Vg, m, lds);
+  if (heev_mat_off<T>(m) + (size_t)m * m * sizeof(T) <= lds_bytes) return heev_run<T, true>(Mg, Vg, m, lds);
+  return heev_run<T, false>(Mg, Vg, m, lds);
 }
 
 // dynamic LDS of the Rayleigh-Ritz kernel: the 160 KB of a CU less its few static words
@@ -984,7 +989,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  heev_tridiag<T>(Bs, U, n, rr_raw, kRrLdsBytes);
+  const bool ok_b = heev_tridiag<T>(Bs, U, n, rr_raw, kRrLdsBytes);
   __syncthreads();
   for (int i = tid; i < n; i += nt) sv[i] = re_(Bs[i + (int64_t)i * n]);
   __threadfence_block();
@@ -1031,7 +1036,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
   }
   __threadfence_block();
   __syncthreads();
-  heev_tridiag<T>(Bs, W, k, rr_raw, kRrLdsBytes);
+  const bool ok_a = heev_tridiag<T>(Bs, W, k, rr_raw, kRrLdsBytes);
   __syncthreads();
   // ascending order of the Ritz values
   for (int i = tid; i < k; i += nt) {
@@ -1053,7 +1058,7 @@ __global__ __launch_bounds__(1024) void rr_reduce_kernel(const T* __restrict__ A
     for (int t = 0; t < k; ++t) sacc = fma_(sacc, Tm[i + (int64_t)t * n], W[t + (int64_t)j * k]);
     Cmat[i + (int64_t)rank[j] * n] = scl(sacc, 1.0 / d[i]);
   }
-  if (tid == 0) *k_out = k;
+  if (tid == 0) *k_out = ok_b && ok_a ? k : -1;
 }
 
 constexpr int RN_ROWS = 512;
