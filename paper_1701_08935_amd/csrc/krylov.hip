@@ -122,8 +122,11 @@ template <typename T>
 __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict__ G, int p, double rel_shift,
                                                             T* __restrict__ Rg, T* __restrict__ Rinv, int* flag) {
   extern __shared__ __align__(16) char lds_raw[];
+  // LDS leading dimension p + 1: the row of A read across lanes at every step
+  // would otherwise sit in one bank (column stride a multiple of the 64 banks)
+  const int ld = p + 1;
   T* A = (T*)lds_raw;
-  T* Z = A + (int64_t)p * p;
+  T* Z = A + (int64_t)p * ld;
   const int tid = threadIdx.x, nt = blockDim.x, tx = tid & 31, ty = tid >> 5;
   __shared__ double trace_s;
   __shared__ int bad_s;
@@ -139,8 +142,8 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict_
     const int i = e % p, j = e / p;
     T v = (i <= j) ? G[e] : ST<T>::zero();
     if (i == j) v = cvt<T, double>(re_(v) + shift);
-    A[e] = v;
-    Z[e] = i == j ? ST<T>::one() : ST<T>::zero();
+    A[i + (int64_t)j * ld] = v;
+    Z[i + (int64_t)j * ld] = i == j ? ST<T>::one() : ST<T>::zero();
   }
   __syncthreads();
   double irk_prev = 1.0;
@@ -148,11 +151,11 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict_
     // scale row k - 1 (final values of R and of Y)
     if (k > 0) {
       const int r = k - 1;
-      for (int j = r + tid; j < p; j += nt) A[r + (int64_t)j * p] = scl(A[r + (int64_t)j * p], irk_prev);
-      for (int c = tid; c <= r; c += nt) Z[r + (int64_t)c * p] = scl(Z[r + (int64_t)c * p], irk_prev);
+      for (int j = r + tid; j < p; j += nt) A[r + (int64_t)j * ld] = scl(A[r + (int64_t)j * ld], irk_prev);
+      for (int c = tid; c <= r; c += nt) Z[r + (int64_t)c * ld] = scl(Z[r + (int64_t)c * ld], irk_prev);
     }
     if (k == p) break;
-    double dkk = re_(A[k + (int64_t)k * p]);
+    double dkk = re_(A[k + (int64_t)k * ld]);
     if (!(dkk > 1e-300)) {
       if (tid == 0) bad_s = 1;
       dkk = 1.0;
@@ -160,14 +163,14 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict_
     const double idk = 1.0 / dkk;
     irk_prev = 1.0 / sqrt(dkk);
     for (int j = k + 1 + ty; j < p; j += 32) {
-      const T akj = scl(A[k + (int64_t)j * p], idk);
+      const T akj = scl(A[k + (int64_t)j * ld], idk);
       for (int i = k + 1 + tx; i <= j; i += 32)
-        A[i + (int64_t)j * p] = sub(A[i + (int64_t)j * p], mul(conj_(A[k + (int64_t)i * p]), akj));
+        A[i + (int64_t)j * ld] = sub(A[i + (int64_t)j * ld], mul(conj_(A[k + (int64_t)i * ld]), akj));
     }
     for (int c = ty; c <= k; c += 32) {
-      const T zkc = scl(Z[k + (int64_t)c * p], idk);
+      const T zkc = scl(Z[k + (int64_t)c * ld], idk);
       for (int i = k + 1 + tx; i < p; i += 32)
-        Z[i + (int64_t)c * p] = sub(Z[i + (int64_t)c * p], mul(conj_(A[k + (int64_t)i * p]), zkc));
+        Z[i + (int64_t)c * ld] = sub(Z[i + (int64_t)c * ld], mul(conj_(A[k + (int64_t)i * ld]), zkc));
     }
     __syncthreads();
   }
@@ -175,8 +178,8 @@ __global__ __launch_bounds__(1024) void chol_inv_lds_kernel(const T* __restrict_
   if (tid == 0 && bad_s) *flag = 1;
   for (int e = tid; e < p * p; e += nt) {
     const int i = e % p, j = e / p;
-    Rg[e] = i <= j ? A[e] : ST<T>::zero();
-    Rinv[e] = i <= j ? conj_(Z[j + (int64_t)i * p]) : ST<T>::zero();
+    Rg[e] = i <= j ? A[i + (int64_t)j * ld] : ST<T>::zero();
+    Rinv[e] = i <= j ? conj_(Z[j + (int64_t)i * ld]) : ST<T>::zero();
   }
 }
 
@@ -1105,11 +1108,12 @@ void reduce_partials(T* out, int64_t ld_out, const T* partial, int S, int M, int
 template <typename T>
 void chol_upper_inv(const T* G, int p, double rel_shift, T* R, T* Rinv, int* flag, hipStream_t s) {
   const size_t one = sizeof(T) * (size_t)p * p;
+  const size_t one_pad = sizeof(T) * (size_t)p * (p + 1);  // chol_inv_lds_kernel: leading dimension p + 1
   const bool use_lds = one <= 160 * 1024 - 4096;
-  if (2 * one <= 160 * 1024 - 4096) {
+  if (2 * one_pad <= 160 * 1024 - 4096) {
     (void)hipFuncSetAttribute((const void*)chol_inv_lds_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)(2 * one));
-    hipLaunchKernelGGL(chol_inv_lds_kernel<T>, dim3(1), dim3(1024), 2 * one, s, G, p, rel_shift, R, Rinv, flag);
+                              (int)(2 * one_pad));
+    hipLaunchKernelGGL(chol_inv_lds_kernel<T>, dim3(1), dim3(1024), 2 * one_pad, s, G, p, rel_shift, R, Rinv, flag);
   } else if (use_lds) {
     const size_t lds = 2 * one <= 160 * 1024 - 4096 ? 2 * one : one;
     (void)hipFuncSetAttribute((const void*)chol_upper_inv_kernel<T, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
