@@ -496,40 +496,38 @@ int gemm_tn(Workspace& ws, const VT* X, int64_t ldx, const VT* Y, int64_t ldy, i
     return ZOLO_ENOMEM;
   }
   if (S > ws.gdesc_cap) S = ws.gdesc_cap;
-  int64_t chunk = (N + S - 1) / S;
+  const int64_t chunk = (N + S - 1) / S;
+  const int cnt = chunk > 0 ? (int)((N + chunk - 1) / chunk) : 0;  // chunks that hold rows
   VT* partial = (VT*)ws.partial;
-  std::vector<GemmDesc<VT>> h;
-  for (int64_t q = 0; q < S; ++q) {
-    int64_t r0 = q * chunk;
-    if (r0 >= N) break;
-    GemmDesc<VT> d{};
-    d.A = X + r0 * ldx;
-    d.lda = ldx;
-    d.B = Y + r0 * ldy;
-    d.ldb = ldy;
-    d.C = partial + (int64_t)h.size() * m * n;
-    d.ldc = m;
-    d.M = m;
-    d.N = n;
-    d.K = (int)std::min<int64_t>(chunk, N - r0);
-    d.flags = GF_TRANSB | (ST<VT>::cplx ? GF_CONJA : 0);
-    d.alpha = ST<VT>::one();
-    d.beta = ST<VT>::zero();
-    h.push_back(d);
-  }
+  // chunk q: rows [q chunk, min(N, (q + 1) chunk)) of X and Y into partial q
+  GemmDesc<VT> d{};
+  d.A = X;
+  d.lda = ldx;
+  d.B = Y;
+  d.ldb = ldy;
+  d.C = partial;
+  d.ldc = m;
+  d.M = m;
+  d.N = n;
+  d.K = (int)chunk;
+  d.flags = GF_TRANSB | (ST<VT>::cplx ? GF_CONJA : 0);
+  d.alpha = ST<VT>::one();
+  d.beta = ST<VT>::zero();
   GemmDesc<VT>* dg = (GemmDesc<VT>*)ws.gdesc;
-  HIPC(hipMemcpyAsync(dg, h.data(), h.size() * sizeof(GemmDesc<VT>), hipMemcpyHostToDevice, s));
+  gemm_desc_series<VT>(d, cnt, chunk * ldx, chunk * ldy, (int64_t)m * n, chunk, N, dg, s);
   {
     double fl = 0.0, by = 0.0;
-    for (auto& d : h) gemm_work(d, &fl, &by);
+    for (int q = 0; q < cnt; ++q) {
+      d.K = (int)std::min<int64_t>(chunk, N - q * chunk);
+      gemm_work(d, &fl, &by);
+    }
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<VT>(dg, (int)h.size(), m, n, s, 2);
+    gemm_batched<VT>(dg, cnt, m, n, s, 2);
   }
   {
-    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, (double)sizeof(VT) * m * n * (h.size() + 1), s);
-    reduce_partials<VT>(out, ldo, partial, (int)h.size(), m, n, add, s);
+    prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, (double)sizeof(VT) * m * n * (cnt + 1), s);
+    reduce_partials<VT>(out, ldo, partial, cnt, m, n, add, s);
   }
-  HIPC(hipStreamSynchronize(s));  // h is host memory
   return ZOLO_OK;
 }
 
@@ -555,14 +553,13 @@ int gemm_nt_big(Workspace& ws, VT* C, int64_t ldc, const VT* Cin, int64_t ldcin,
   d.N = (int)N;
   d.K = K;
   GemmDesc<VT>* dg = (GemmDesc<VT>*)ws.gdesc + ws.gdesc_cap;
-  HIPC(hipMemcpyAsync(dg, &d, sizeof(d), hipMemcpyHostToDevice, s));
+  gemm_desc_series<VT>(d, 1, 0, 0, 0, K, K, dg, s);
   {
     double fl = 0.0, by = 0.0;
     gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
     gemm_batched<VT>(dg, 1, p, (int)N, s, 2);
   }
-  HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
 }
 

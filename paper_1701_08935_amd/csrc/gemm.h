@@ -84,6 +84,15 @@ template <typename T>
 void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split = 1,
                   int grid_tiles = 0);
 
+// Writes count descriptors to the device array out, in stream order on s:
+// descriptor q is base with A, B and C advanced by q * a_step, q * b_step and
+// q * c_step elements and K = min(kchunk, ktotal - q * kchunk).  base travels
+// as a kernel argument, so nothing on the host has to outlive the call and the
+// caller need not wait for the copy.  count <= 1024.
+template <typename T>
+void gemm_desc_series(const GemmDesc<T>& base, int count, int64_t a_step, int64_t b_step, int64_t c_step,
+                      int64_t kchunk, int64_t ktotal, GemmDesc<T>* out, hipStream_t s);
+
 // Algorithmic work of one descriptor: entries of C computed and flops
 // (8 per complex multiply-add, 2 per real one), and the bytes a product
 // must move at least once: A, B, C written, Cin read.

@@ -553,8 +553,37 @@ void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStrea
     launch_cfg<T, 64, 96>(d_desc, n, maxM, maxN, s, tag, max_split, grid_tiles);
 }
 
+template <typename T>
+__global__ void gemm_desc_series_kernel(GemmDesc<T> base, int count, int64_t a_step, int64_t b_step, int64_t c_step,
+                                        int64_t kchunk, int64_t ktotal, GemmDesc<T>* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  GemmDesc<T> d = base;
+  d.A += q * a_step;
+  d.B += q * b_step;
+  d.C += q * c_step;
+  const int64_t k0 = q * kchunk;
+  d.K = (int)(ktotal - k0 < kchunk ? ktotal - k0 : kchunk);
+  out[q] = d;
+}
+
+template <typename T>
+void gemm_desc_series(const GemmDesc<T>& base, int count, int64_t a_step, int64_t b_step, int64_t c_step,
+                      int64_t kchunk, int64_t ktotal, GemmDesc<T>* out, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(gemm_desc_series_kernel<T>, dim3((count + 63) / 64), dim3(64), 0, s, base, count, a_step, b_step,
+                     c_step, kchunk, ktotal, out);
+}
+
 template void gemm_batched<double>(const GemmDesc<double>*, int, int, int, hipStream_t, int, int, int);
 template void gemm_batched<zd>(const GemmDesc<zd>*, int, int, int, hipStream_t, int, int, int);
 template void gemm_batched<zf>(const GemmDesc<zf>*, int, int, int, hipStream_t, int, int, int);
+#define ZOLO_SERIES(T)                                                                                         \
+  template void gemm_desc_series<T>(const GemmDesc<T>&, int, int64_t, int64_t, int64_t, int64_t, int64_t, GemmDesc<T>*, \
+                                    hipStream_t);
+ZOLO_SERIES(double)
+ZOLO_SERIES(zd)
+ZOLO_SERIES(zf)
+#undef ZOLO_SERIES
 
 }  // namespace zolo
