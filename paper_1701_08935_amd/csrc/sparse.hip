@@ -233,35 +233,69 @@ __global__ void add_same_kernel(zd* __restrict__ X, const zd* __restrict__ D, in
   X[e].im += D[e].im;
 }
 
-constexpr int CN_ROWS = 1024;  // rows per partial sum
+constexpr int CN_ROWS = 512;  // rows per partial sum (one workgroup)
 
-// partial[b][c] = sum over rows of chunk b of |x_ic|^2
 template <bool CPLX>
-__global__ void colnorm_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n, int p,
-                                       double* __restrict__ partial) {
+__device__ __forceinline__ double cn_sq(const double* __restrict__ X, int64_t row, int64_t ldx, int c) {
+  if (CPLX) {
+    const double re = X[2 * (row * ldx + c)], im = X[2 * (row * ldx + c) + 1];
+    return fma(re, re, im * im);
+  }
+  const double v = X[row * ldx + c];
+  return v * v;
+}
+
+// partial[b][c] = sum over the rows of chunk b of |x_ic|^2.  The four waves of
+// the workgroup take every fourth row of the chunk; lane l holds columns
+// c0 + l and c0 + 64 + l (so each row is read as one contiguous run across the
+// wave), with four rows in flight per column; the waves' sums meet in LDS.
+template <bool CPLX>
+__global__ __launch_bounds__(256) void colnorm_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
+                                                              int p, double* __restrict__ partial) {
+  __shared__ double red[4][128];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t r0 = (int64_t)blockIdx.x * CN_ROWS;
   const int64_t r1 = (r0 + CN_ROWS < n) ? r0 + CN_ROWS : n;
-  for (int c = threadIdx.x; c < p; c += blockDim.x) {
-    double s = 0.0;
-    for (int64_t i = r0; i < r1; ++i) {
-      if (CPLX) {
-        double re = X[2 * (i * ldx + c)], im = X[2 * (i * ldx + c) + 1];
-        s = fma(re, re, fma(im, im, s));
-      } else {
-        double v = X[i * ldx + c];
-        s = fma(v, v, s);
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int ca = c0 + lane, cb = c0 + 64 + lane;
+    const bool va = ca < p, vb = cb < p;
+    double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = r0 + w;
+    for (; i + 12 < r1; i += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (va) sa[u] += cn_sq<CPLX>(X, i + 4 * u, ldx, ca);
+        if (vb) sb[u] += cn_sq<CPLX>(X, i + 4 * u, ldx, cb);
       }
     }
-    partial[(int64_t)blockIdx.x * p + c] = s;
+    for (; i < r1; i += 4) {
+      if (va) sa[0] += cn_sq<CPLX>(X, i, ldx, ca);
+      if (vb) sb[0] += cn_sq<CPLX>(X, i, ldx, cb);
+    }
+    red[w][lane] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
+    red[w][64 + lane] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    __syncthreads();
+    if (tid < 128 && c0 + tid < p)
+      partial[(int64_t)blockIdx.x * p + c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+    __syncthreads();
   }
 }
 
-__global__ void colnorm_final_kernel(const double* __restrict__ partial, int nb, int p, double* __restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= p) return;
+// out[c] = sum over b of partial[b][c]: one workgroup per column, a fixed
+// summation order (strided partial sums, then a tree in LDS)
+__global__ __launch_bounds__(256) void colnorm_final_kernel(const double* __restrict__ partial, int nb, int p,
+                                                            double* __restrict__ out) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * p + c];
-  out[c] = s;
+  for (int b = tid; b < nb; b += 256) s += partial[(int64_t)b * p + c];
+  red[tid] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) out[c] = red[0];
 }
 
 inline unsigned nblk(int64_t tot) { return (unsigned)((tot + 255) / 256); }
@@ -364,16 +398,16 @@ int colnorm_partials(int64_t n) { return (int)((n + CN_ROWS - 1) / CN_ROWS); }
 
 void colnorm2_real(const double* X, int64_t ldx, int64_t n, int p, double* partial, double* out, hipStream_t s) {
   int nb = colnorm_partials(n);
-  if (nb == 0) return;
-  hipLaunchKernelGGL(colnorm_partial_kernel<false>, dim3(nb), dim3(128), 0, s, X, ldx, n, p, partial);
-  hipLaunchKernelGGL(colnorm_final_kernel, dim3((p + 127) / 128), dim3(128), 0, s, partial, nb, p, out);
+  if (nb == 0 || p <= 0) return;
+  hipLaunchKernelGGL(colnorm_partial_kernel<false>, dim3(nb), dim3(256), 0, s, X, ldx, n, p, partial);
+  hipLaunchKernelGGL(colnorm_final_kernel, dim3(p), dim3(256), 0, s, partial, nb, p, out);
 }
 void colnorm2_cplx(const zd* X, int64_t n, int p, double* partial, double* out, hipStream_t s) {
   int nb = colnorm_partials(n);
-  if (nb == 0) return;
-  hipLaunchKernelGGL(colnorm_partial_kernel<true>, dim3(nb), dim3(128), 0, s, (const double*)X, (int64_t)p, n, p,
+  if (nb == 0 || p <= 0) return;
+  hipLaunchKernelGGL(colnorm_partial_kernel<true>, dim3(nb), dim3(256), 0, s, (const double*)X, (int64_t)p, n, p,
                      partial);
-  hipLaunchKernelGGL(colnorm_final_kernel, dim3((p + 127) / 128), dim3(128), 0, s, partial, nb, p, out);
+  hipLaunchKernelGGL(colnorm_final_kernel, dim3(p), dim3(256), 0, s, partial, nb, p, out);
 }
 
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s) {
