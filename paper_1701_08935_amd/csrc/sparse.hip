@@ -233,7 +233,7 @@ __global__ void add_same_kernel(zd* __restrict__ X, const zd* __restrict__ D, in
   X[e].im += D[e].im;
 }
 
-constexpr int CN_ROWS = 512;  // rows per partial sum (one workgroup)
+constexpr int CN_ROWS = 256;  // rows per partial sum (one workgroup)
 
 template <bool CPLX>
 __device__ __forceinline__ double cn_sq(const double* __restrict__ X, int64_t row, int64_t ldx, int c) {
@@ -248,7 +248,7 @@ __device__ __forceinline__ double cn_sq(const double* __restrict__ X, int64_t ro
 // partial[b][c] = sum over the rows of chunk b of |x_ic|^2.  The four waves of
 // the workgroup take every fourth row of the chunk; lane l holds columns
 // c0 + l and c0 + 64 + l (so each row is read as one contiguous run across the
-// wave), with four rows in flight per column; the waves' sums meet in LDS.
+// wave), with eight rows in flight per column; the waves' sums meet in LDS.
 template <bool CPLX>
 __global__ __launch_bounds__(256) void colnorm_partial_kernel(const double* __restrict__ X, int64_t ldx, int64_t n,
                                                               int p, double* __restrict__ partial) {
@@ -259,11 +259,11 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const double* __re
   for (int c0 = 0; c0 < p; c0 += 128) {
     const int ca = c0 + lane, cb = c0 + 64 + lane;
     const bool va = ca < p, vb = cb < p;
-    double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+    double sa[8] = {}, sb[8] = {};
     int64_t i = r0 + w;
-    for (; i + 12 < r1; i += 16) {
+    for (; i + 28 < r1; i += 32) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         if (va) sa[u] += cn_sq<CPLX>(X, i + 4 * u, ldx, ca);
         if (vb) sb[u] += cn_sq<CPLX>(X, i + 4 * u, ldx, cb);
       }
@@ -272,8 +272,8 @@ __global__ __launch_bounds__(256) void colnorm_partial_kernel(const double* __re
       if (va) sa[0] += cn_sq<CPLX>(X, i, ldx, ca);
       if (vb) sb[0] += cn_sq<CPLX>(X, i, ldx, cb);
     }
-    red[w][lane] = (sa[0] + sa[1]) + (sa[2] + sa[3]);
-    red[w][64 + lane] = (sb[0] + sb[1]) + (sb[2] + sb[3]);
+    red[w][lane] = ((sa[0] + sa[1]) + (sa[2] + sa[3])) + ((sa[4] + sa[5]) + (sa[6] + sa[7]));
+    red[w][64 + lane] = ((sb[0] + sb[1]) + (sb[2] + sb[3])) + ((sb[4] + sb[5]) + (sb[6] + sb[7]));
     __syncthreads();
     if (tid < 128 && c0 + tid < p)
       partial[(int64_t)blockIdx.x * p + c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
