@@ -28,7 +28,7 @@ import pytest
 import pencils
 from oracle.dense import count_in, exact_filter, pencil_eigh_lapack
 from oracle.filt import FilterPlan
-from oracle.subspace import b_orthonormality, inf_norm, rel_residuals
+from oracle.subspace import b_orthonormality, e_lambda_x, inf_norm, norm2_est, rel_residuals
 
 from .conftest import golden
 
@@ -88,10 +88,15 @@ def _check_window_64(gp, w, eig, vec, st, rc):
     assert rel <= 1e-10
     X = vec.cpu().numpy()
     r = rel_residuals(A, B, eig, X, inf_norm(A), inf_norm(B))
+    r2 = rel_residuals(A, B, eig, X, norm2_est(A), norm2_est(B))
+    e = e_lambda_x(A, B, eig, X, w["a"], w["b"])
     bo = b_orthonormality(B, X)
-    say(f"  residual {np.max(r):.2e} B-orth {bo:.2e}")
-    assert np.max(r) <= 1e-8
+    say(f"  residual inf-norm {np.max(r):.2e} 2-norm {np.max(r2):.2e} B-orth {bo:.2e} "
+        f"e_lambda_x {e:.2e} (library {st['e_lambda_x']:.2e})")
+    assert np.max(r) <= 1e-8 and np.max(r2) <= 1e-8
     assert bo <= 1e-10
+    assert abs(st["max_resid"] - np.max(r)) <= 0.05 * np.max(r) + 1e-14
+    assert abs(st["e_lambda_x"] - e) <= 0.05 * e + 1e-14
     # Kato-Temple: every theta is within kt_i of a true eigenvalue, with gap from the stored spectrum
     R = A @ X - (B @ X) * eig[None, :]
     lmin_b = _gershgorin_min(B)
