@@ -92,7 +92,9 @@ typedef struct {
   int precision;           /* zolo_precision                                        */
   uint64_t seed;           /* start block when none is passed                       */
   int max_refine;          /* mixed precision: refinement steps per pole solve      */
-  double tol_refine;       /* mixed precision: inner relative residual              */
+  double tol_refine;       /* mixed precision: inner relative residual target at the
+                              first GMRES step; step k relaxes it to
+                              min(1e-2, tol_refine / outer residual of step k-1)     */
 } zolo_opts;
 
 typedef struct {
@@ -101,6 +103,10 @@ typedef struct {
   int n_gmres_last;
   long long n_solv;        /* RHS solves: r1 * n_ss * n_gmres (x2 complex pencils)  */
   long long n_refine;      /* extra FP32 solves (mixed)                             */
+  int refine_sweeps_max;   /* mixed: most corrections one pole refinement took      */
+  int refine_missed;       /* mixed: refinements stopped above their target
+                              (max_refine reached, or a sweep gained < 2x)          */
+  double refine_worst;     /* mixed: largest relative residual such a refinement left */
   int n_found;
   double max_resid;        /* spec residual over returned pairs               */
   double e_lambda_x;       /* eq. (relerr)                                          */
@@ -179,7 +185,7 @@ zolo_status zolo_filter_plan(double a_minus, double a_plus, double b_minus, doub
  * symmetric LDL^T for real pencils, LU = L D U for complex Hermitian pencils
  * (whose conjugate poles are solved with K_j^-H).  Poles are factored
  * concurrently on streams of their own and joined to `stream`.
- * precision ZOLO_PREC_MIXED stores complex64 factors (real pencils only).
+ * precision ZOLO_PREC_MIXED stores complex64 factors (FP32 accumulation).
  * Errors: ZOLO_EBREAKDOWN (zero pivot), ZOLO_ENOMEM, ZOLO_EDEVICE.
  */
 zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* p, const zolo_filter_coeffs* co, int precision,
@@ -190,6 +196,18 @@ void zolo_factors_free(zolo_factors* f);
  * the ORIGINAL ordering, double for real pencils, complex128 for complex ones. */
 zolo_status zolo_spmm(zolo_pencil* p, int which, const void* d_X, int64_t ldx, int ncols, void* d_Y, int64_t ldy,
                       void* stream);
+
+/* Residual norms of approximate eigenpairs (x_c, lam_c) of the pencil, the
+ * accuracy measure of an eigenpair of eq. (IGEVP) (Sec. 1):
+ *   d_out[c] = ||A x_c - lam_c B x_c||_2 / ((||A||_inf + |lam_c| ||B||_inf) ||x_c||_2)
+ * for c < ncols <= 512.  d_X: N x ncols row-major (ld ldx >= ncols), original
+ * ordering, the pencil's scalar type; d_lambda, d_out: ncols doubles, device.
+ * Caller-owned buffers; the library allocates (and on return releases) its
+ * partial sums, so the call blocks until the norms are written.  A zero-norm
+ * column gives 0 (zero residual) or +inf.  Errors: ZOLO_EINVAL (null
+ * pointers, ld < ncols, ncols above the limit), ZOLO_ENOMEM. */
+zolo_status zolo_residuals(zolo_pencil* p, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
+                           double* d_out, void* stream);
 
 /* d_X (complex128, N x p) = K_j^-1 d_T for pole j (0-based) (eq. solve).
  * Real pencils: j < r1, d_T real.  Complex Hermitian pencils: d_T complex128,
@@ -230,8 +248,9 @@ zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, i
  * n_lambda_est: estimated count (footnote of Sec. 1); opts may be NULL.
  * d_Q0 (may be NULL): N x n_ss start block (row-major, ld n_ss) in the
  * original ordering, of the pencil's scalar type (double or complex128);
- * NULL draws a Gaussian block from opts->seed.  Complex Hermitian pencils
- * run with FP64 factors only (ZOLO_EINVAL for ZOLO_PREC_MIXED).
+ * NULL draws a Gaussian block from opts->seed.  ZOLO_PREC_MIXED factors in
+ * complex64 (both pencil types) and refines every pole solve against FP64
+ * residuals.
  * The result holds Ritz pairs with a < theta < b and residual <= tol_resid;
  * its vectors are complex128 for complex pencils.  An interval with no
  * eigenvalue returns count 0 once two filtered iterations select none.

@@ -47,7 +47,8 @@ class zolo_opts(ctypes.Structure):
 
 class zolo_stats(ctypes.Structure):
     _fields_ = [("n_iter", _i), ("n_gmres_total", _i), ("n_gmres_last", _i), ("n_solv", ctypes.c_longlong),
-                ("n_refine", ctypes.c_longlong), ("n_found", _i), ("max_resid", _d), ("e_lambda_x", _d),
+                ("n_refine", ctypes.c_longlong), ("refine_sweeps_max", _i), ("refine_missed", _i),
+                ("refine_worst", _d), ("n_found", _i), ("max_resid", _d), ("e_lambda_x", _d),
                 ("b_orth", _d), ("t_plan", _d), ("t_symbolic", _d), ("t_factor", _d), ("t_iter", _d),
                 ("t_total", _d), ("gmres_resid", _d), ("norm_a", _d), ("norm_b", _d), ("r1", _i), ("r2", _i),
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
@@ -98,6 +99,7 @@ _SIGS = {
     "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
     "zolo_factors_free": (None, [_vp]),
     "zolo_spmm": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
+    "zolo_residuals": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
     "zolo_pole_solve": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_apply_G": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
@@ -262,6 +264,16 @@ def zolo_spmm(pencil: Pencil, which: int, X):
     Y = torch.empty_like(X)
     _check(lib().zolo_spmm(pencil.h, int(which), _ptr(X), X.stride(0), X.shape[1], _ptr(Y), Y.stride(0), _stream()))
     return Y
+
+
+def zolo_residuals(pencil: Pencil, X, lam):
+    """Per-column ||A x - lam B x|| / ((||A||_inf + |lam| ||B||_inf) ||x||) on the device
+    (X: N x k tensor of the pencil's scalar type, lam: k float64 tensor on the same device)."""
+    import torch
+
+    out = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
+    _check(lib().zolo_residuals(pencil.h, _ptr(X), X.stride(0), X.shape[1], _ptr(lam), _ptr(out), _stream()))
+    return out
 
 
 def zolo_pole_solve(f: Factors, j: int, T):

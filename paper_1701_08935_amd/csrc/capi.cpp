@@ -396,8 +396,11 @@ struct zolo_factors {
   std::unique_ptr<Workspace> ws;
   double t_factor = 0.0;
   int max_refine = 8;
-  double tol_refine = 1e-13;
+  double tol_refine = 1e-8;
   long long n_refine = 0;
+  int refine_sweeps_max = 0;  // most corrections one refinement took
+  int refine_missed = 0;      // refinements that stopped above their target
+  double refine_worst = 0.0;  // largest relative residual such a refinement left
   long long n_solv = 0;
   int64_t bytes = 0;
 };
@@ -589,7 +592,7 @@ extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
   o->precision = ZOLO_PREC_FP64;
   o->seed = 2;
   o->max_refine = 8;
-  o->tol_refine = 1e-13;
+  o->tol_refine = 1e-8;
   return ZOLO_OK;
 }
 
@@ -1842,8 +1845,8 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   char* gd = nullptr;
   CHK(ws->mem.alloc(&gd, sizeof(GemmDesc<zd>) * (ws->gdesc_cap + 4)));
   ws->gdesc = gd;
-  CHK(ws->mem.alloc(&ws->cn_partial, (size_t)colnorm_partials(n) * p + 16));
-  CHK(ws->mem.alloc(&ws->cn_out, (size_t)p));
+  CHK(ws->mem.alloc(&ws->cn_partial, (size_t)colnorm_partials(n) * p * np + 16));
+  CHK(ws->mem.alloc(&ws->cn_out, (size_t)p * np));
   HlsState& h = ws->hls;
   h.ldr = Mp;
   h.mmax = mmax;
@@ -1869,11 +1872,14 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
 }
 
 // X_j (zd, N x p, new ordering, at X + j n p) = K_j^{-1} T for every pole j
-// (T real, new ordering, ld p).  Mixed precision: complex64 factors, and
-// iterative refinement against FP64 residuals R_j = T - (A - sigma_j B) X_j
-// until max_j ||R_j|| / ||T|| <= tol_inner (column-wise).
-// Complex Hermitian pencils (VT = zd, FP64 factors): X_j = K_j^-1 T for
-// j < r1 and X_{r1+j} = K_j^-H T.
+// (T of the block scalar type, new ordering, ld p).  Complex Hermitian pencils
+// also solve the conjugate poles: X_{r1+j} = K_j^-H T = (A - conj(sigma_j) B)^-1 T.
+// FP64 factors: one supernodal solve of all poles.  Mixed precision: complex64
+// factors, then iterative refinement against FP64 residuals
+// R_j = T - (A - sigma_j B) X_j, all poles per sweep with one host
+// synchronization, until max_j,c ||R_j,c|| / ||T_c|| <= tol_inner, or until a
+// sweep gains less than a factor 2 (the FP64 residual floor of an
+// ill-conditioned pole), or after max_refine corrections.
 // Xres (optional): where the solutions are left.  FP64 factors: the solve
 // program's own buffer (valid until its next solve), so nothing is copied to X.
 template <typename VT>
@@ -1881,7 +1887,8 @@ zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double t
                             const zd** Xres = nullptr) {
   zolo_pencil* P = F->P;
   const int64_t n = P->n;
-  const int np = F->co.r1 * (P->cplx() ? 2 : 1);
+  const int r1 = F->co.r1;
+  const int np = r1 * (P->cplx() ? 2 : 1);
   const int64_t npx = n * p;
   if (F->precision == ZOLO_PREC_FP64) {
     SolveProg<zd>* G = get_prog<zd>(F, p);
@@ -1894,39 +1901,57 @@ zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double t
     F->n_solv += (long long)p * np;
     return ZOLO_OK;
   }
-  if constexpr (ST<VT>::cplx) {
-    set_error("complex pencils: mixed precision is not available");
-    return ZOLO_EINVAL;
-  } else {
   SolveProg<zf>* G = get_prog<zf>(F, p);
   if (!G) return ZOLO_ENOMEM;
   Workspace& ws = *F->ws;
-  run_solve<double, zf>(F, G, T, p, false, s);
+  run_solve<VT, zf>(F, G, T, p, false, s);
   HIPC(hipMemsetAsync(X, 0, sizeof(zd) * npx * np, s));
   add_lowp(X, G->X, npx * np, s);
   F->n_solv += (long long)p * np;
-  std::vector<double> tn(p), rn(p);
-  colnorm2_real(T, p, n, p, ws.cn_partial, ws.cn_out, s);
+  const int64_t cnp = (int64_t)colnorm_partials(n) * p;
+  std::vector<double> tn(p), rn((size_t)np * p);
+  if constexpr (ST<VT>::cplx)
+    colnorm2_cplx(T, n, p, ws.cn_partial, ws.cn_out, s);
+  else
+    colnorm2_real(T, p, n, p, ws.cn_partial, ws.cn_out, s);
   HIPC(hipMemcpyAsync(tn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
   HIPC(hipStreamSynchronize(s));
-  for (int it = 0; it < F->max_refine; ++it) {
-    double worst = 0.0;
+  for (double& v : tn) v = std::sqrt(std::max(v, 1e-300));
+  double prev = HUGE_VAL, worst = HUGE_VAL;
+  int sweeps = 0;
+  for (;;) {
     for (int j = 0; j < np; ++j) {
-      spmm_shift_resid(n, P->prow, P->pcol, P->pa, P->pb, F->co.sigma_hat_re[j], F->co.sigma_hat_im[j], X + j * npx,
-                       T, p, p, ws.Rc + j * npx, s);
-      colnorm2_cplx(ws.Rc + j * npx, n, p, ws.cn_partial, ws.cn_out, s);
-      HIPC(hipMemcpyAsync(rn.data(), ws.cn_out, sizeof(double) * p, hipMemcpyDeviceToHost, s));
-      HIPC(hipStreamSynchronize(s));
-      for (int c = 0; c < p; ++c) worst = std::max(worst, std::sqrt(rn[c]) / std::max(std::sqrt(tn[c]), 1e-300));
+      const int q = j % r1;
+      const double sr = F->co.sigma_hat_re[q], si = (j < r1 ? 1.0 : -1.0) * F->co.sigma_hat_im[q];
+      {
+        prof::Scope ps(ZOLO_PROF_SPMM, 8.0 * P->nnz * p, (ST<VT>::cplx ? 36.0 : 20.0) * P->nnz + 48.0 * n * p, s);
+        if constexpr (ST<VT>::cplx)
+          spmm_shift_resid(n, P->prow, P->pcol, P->za, P->zb, sr, si, X + j * npx, T, p, p, ws.Rc + j * npx, s);
+        else
+          spmm_shift_resid(n, P->prow, P->pcol, P->pa, P->pb, sr, si, X + j * npx, T, p, p, ws.Rc + j * npx, s);
+      }
+      prof::Scope ps(ZOLO_PROF_ELEMWISE, 0.0, 16.0 * n * p, s);
+      colnorm2_cplx(ws.Rc + j * npx, n, p, ws.cn_partial + j * cnp, ws.cn_out + (int64_t)j * p, s);
     }
-    if (worst <= tol_inner) break;
+    HIPC(hipMemcpyAsync(rn.data(), ws.cn_out, sizeof(double) * np * p, hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    worst = 0.0;
+    for (int j = 0; j < np; ++j)
+      for (int c = 0; c < p; ++c) worst = std::max(worst, std::sqrt(rn[(size_t)j * p + c]) / tn[c]);
+    if (worst <= tol_inner || sweeps >= F->max_refine || worst > 0.5 * prev) break;
     run_solve<zd, zf>(F, G, ws.Rc, p, true, s);
     add_lowp(X, G->X, npx * np, s);
     F->n_refine += (long long)p * np;
+    ++sweeps;
+    prev = worst;
+  }
+  F->refine_sweeps_max = std::max(F->refine_sweeps_max, sweeps);
+  if (worst > tol_inner) {
+    ++F->refine_missed;
+    F->refine_worst = std::max(F->refine_worst, worst);
   }
   if (Xres) *Xres = X;
   return ZOLO_OK;
-  }
 }
 
 // W (N x p, ld ldw) = G V (V: N x p new ordering, ld ldv).  Proposition 2:
@@ -2030,8 +2055,8 @@ zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, V
   bool exhausted = false;
   for (int k = 0; k < maxit; ++k) {
     // inexact inner solves (mixed precision): the tolerance grows as the outer
-    // residual falls, tol_refine / ||r_{k-1}|| capped at 1e-4
-    const double tol_inner = std::min(1e-4, F->tol_refine / std::max(worst, 1e-300));
+    // residual falls, tol_refine / ||r_{k-1}|| capped at 1e-2
+    const double tol_inner = std::min(1e-2, F->tol_refine / std::max(worst, 1e-300));
     CHK(apply_G_new<VT>(F, Vb + (int64_t)k * p, Mp, p, W, p, tol_inner, s));
     const int kp1 = (k + 1) * p;
     for (int pass = 0; pass < 2; ++pass) {
@@ -2159,6 +2184,44 @@ extern "C" zolo_status zolo_spmm(zolo_pencil* P, int which, const void* d_X, int
   return spmm_abi<double>(P, which, (const double*)d_X, ldx, ncols, (double*)d_Y, ldy, s);
 }
 
+namespace {
+zolo_status residuals_check(const zolo_pencil* P, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
+                            const double* d_out, const char* who) {
+  if (!P || ncols < 0 || (ncols > 0 && (!d_X || !d_lambda || !d_out || ldx < ncols))) {
+    set_error("%s: invalid argument", who);
+    return ZOLO_EINVAL;
+  }
+  if (ncols > kResidMaxCols) {
+    set_error("%s: %d columns exceed the limit of %d", who, ncols, kResidMaxCols);
+    return ZOLO_EINVAL;
+  }
+  return ZOLO_OK;
+}
+
+zolo_status residuals_run(zolo_pencil* P, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
+                          double* d_out, double* partial, hipStream_t s) {
+  if (P->cplx())
+    eig_resid_norms<zd>(P->n, P->prow, P->pcol, P->za, P->zb, P->perm, (const zd*)d_X, ldx, ncols, d_lambda,
+                        P->normA, P->normB, partial, d_out, s);
+  else
+    eig_resid_norms<double>(P->n, P->prow, P->pcol, P->pa, P->pb, P->perm, (const double*)d_X, ldx, ncols, d_lambda,
+                            P->normA, P->normB, partial, d_out, s);
+  HIPC(hipGetLastError());
+  return ZOLO_OK;
+}
+}  // namespace
+
+extern "C" zolo_status zolo_residuals(zolo_pencil* P, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
+                                      double* d_out, void* stream) {
+  CHK(residuals_check(P, d_X, ldx, ncols, d_lambda, d_out, "zolo_residuals"));
+  if (ncols == 0) return ZOLO_OK;
+  hipStream_t s = as_stream(stream);
+  DevArena tmp;  // released (after a device synchronization) on return
+  double* partial = nullptr;
+  CHK(tmp.alloc(&partial, (size_t)kResidGroups * 2 * ncols));
+  return residuals_run(P, d_X, ldx, ncols, d_lambda, d_out, partial, s);
+}
+
 extern "C" zolo_status zolo_pole_solve(zolo_factors* F, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
                                        int64_t ldx, void* stream) {
   const int nj = F ? F->co.r1 * (F->P->cplx() ? 2 : 1) : 0;
@@ -2233,7 +2296,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   CHK(zolo_factor(ctx, P, &co, o.precision, stream, &Fp));
   std::unique_ptr<zolo_factors> F(Fp);
   F->max_refine = o.max_refine > 0 ? o.max_refine : 8;
-  F->tol_refine = o.tol_refine > 0 ? o.tol_refine : 1e-13;
+  F->tol_refine = o.tol_refine > 0 ? o.tol_refine : 1e-8;
   st.t_factor = now_s() - t0;
   st.factor_bytes = F->bytes;
   st.nnz_l = P->S.panel_entries + P->S.inv_entries;
@@ -2351,6 +2414,9 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   st.t_iter = now_s() - t0;
   st.n_solv = F->n_solv;
   st.n_refine = F->n_refine;
+  st.refine_sweeps_max = F->refine_sweeps_max;
+  st.refine_missed = F->refine_missed;
+  st.refine_worst = F->refine_worst;
   // results: selected pairs, original ordering
   const int cnt = (int)sel.size();
   R->count = cnt;
@@ -2423,10 +2489,6 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     return ZOLO_EINVAL;
   }
   HIPC(hipSetDevice(ctx->device));
-  if (P->cplx() && o.precision != ZOLO_PREC_FP64) {
-    set_error("zolo_solve: complex pencils are solved with FP64 factors only");
-    return ZOLO_EINVAL;
-  }
   if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
   return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
 }

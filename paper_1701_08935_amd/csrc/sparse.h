@@ -15,6 +15,9 @@ void spmm_cplx(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd
 // R = T - (A - sigma B) X  with X complex, T real (refinement residual, FP64).
 void spmm_shift_resid(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* a, const double* b,
                       double sr, double si, const zd* X, const double* T, int64_t ldt, int p, zd* R, hipStream_t s);
+// complex Hermitian pencils: the same with complex values and a complex T
+void spmm_shift_resid(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd* a, const zd* b, double sr,
+                      double si, const zd* X, const zd* T, int64_t ldt, int p, zd* R, hipStream_t s);
 // row permutations of N x p blocks: gather dst[i] = src[idx[i]], scatter dst[idx[i]] = src[i]
 template <typename T>
 void rows_gather(T* dst, int64_t ldd, const T* src, int64_t lds, const int32_t* idx, int64_t n, int p, hipStream_t s);
@@ -45,7 +48,17 @@ void add_same(zd* X, const zd* D, int64_t n, hipStream_t s);
 void colnorm2_real(const double* X, int64_t ldx, int64_t n, int p, double* partial, double* out, hipStream_t s);
 void colnorm2_cplx(const zd* X, int64_t n, int p, double* partial, double* out, hipStream_t s);
 int colnorm_partials(int64_t n);
-// C = Y + V (both N x p real, row-major), used for Y = V/2 + ...
+// Residual norms of approximate eigenpairs of (A, B) (rows in the pencil's ordering, X
+// in the caller's: X row perm[i] belongs to pencil row i):
+//   out[c] = ||A x_c - lam_c B x_c||_2 / ((normA + |lam_c| normB) ||x_c||_2),  c < p <= kResidMaxCols.
+// partial: kResidGroups * 2 * p doubles of device scratch (fully overwritten); lam, out: device.
+constexpr int kResidGroups = 512;
+constexpr int kResidMaxCols = 512;
+template <typename T>
+void eig_resid_norms(int64_t n, const int64_t* rowptr, const int32_t* colind, const T* a, const T* b,
+                     const int32_t* perm, const T* X, int64_t ldx, int p, const double* lam, double normA,
+                     double normB, double* partial, double* out, hipStream_t s);
+// asynchronous clear of device memory
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace zolo

@@ -105,6 +105,86 @@ __global__ __launch_bounds__(256) void spmm_cplx_kernel(int64_t n, const int64_t
   }
 }
 
+// Residual norms of approximate eigenpairs, ||A x_c - lam_c B x_c||^2 and ||x_c||^2,
+// fused into one pass over the CSR rows: the rows are in the pencil's ordering,
+// the block X in the caller's (X row of pencil row i is perm[i]), so every row of
+// the residual is formed from gathered X rows and squared at once; nothing N x p
+// is written.  A fixed grid of kResidGroups workgroups: each wave sums a
+// contiguous range of rows (ranges of one XCD are contiguous), the four waves of
+// a workgroup are added through LDS and the workgroup writes 2 p partial sums.
+template <typename T>
+__global__ __launch_bounds__(256) void eig_resid_partial_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ ci,
+                                                                const T* __restrict__ a, const T* __restrict__ b,
+                                                                const int32_t* __restrict__ perm,
+                                                                const T* __restrict__ X, int64_t ldx, int p,
+                                                                const double* __restrict__ lam,
+                                                                double* __restrict__ partial) {
+  __shared__ double red[2][4][kResidMaxCols];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x) * 4 + wv;
+  const int64_t per = (n + nw - 1) / nw;
+  const int64_t i0 = w * per < n ? w * per : n;
+  const int64_t i1 = i0 + per < n ? i0 + per : n;
+  const int nch = (p + 63) >> 6;
+  double rr[kResidMaxCols / 64], xx[kResidMaxCols / 64], lm[kResidMaxCols / 64];
+#pragma unroll
+  for (int h = 0; h < kResidMaxCols / 64; ++h) {
+    rr[h] = 0.0;
+    xx[h] = 0.0;
+    const int c = h * 64 + lane;
+    lm[h] = c < p ? lam[c] : 0.0;
+  }
+  for (int64_t i = i0; i < i1; ++i) {
+    const int64_t e0 = rp[i], e1 = rp[i + 1];
+    const T* xo = X + (int64_t)perm[i] * ldx;
+#pragma unroll
+    for (int h = 0; h < kResidMaxCols / 64; ++h) {
+      if (h >= nch) break;
+      const int c = h * 64 + lane;
+      const int lc = c < p ? c : p - 1;  // loads stay in the row; the sums of unused lanes are never read
+      T sa = ST<T>::zero(), sb = ST<T>::zero();
+      for (int64_t q = e0; q < e1; ++q) {
+        const T xv = X[(int64_t)perm[ci[q]] * ldx + lc];
+        sa = fma_(sa, a[q], xv);
+        sb = fma_(sb, b[q], xv);
+      }
+      rr[h] += abs2(sub(sa, scl(sb, lm[h])));
+      xx[h] += abs2(xo[lc]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < kResidMaxCols / 64; ++h) {
+    if (h >= nch) break;
+    red[0][wv][h * 64 + lane] = rr[h];
+    red[1][wv][h * 64 + lane] = xx[h];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < p; c += blockDim.x) {
+    double* o = partial + (int64_t)blockIdx.x * 2 * p;
+    o[c] = ((red[0][0][c] + red[0][1][c]) + red[0][2][c]) + red[0][3][c];
+    o[p + c] = ((red[1][0][c] + red[1][1][c]) + red[1][2][c]) + red[1][3][c];
+  }
+}
+
+// out[c] = sqrt(sum |r|^2) / ((normA + |lam_c| normB) sqrt(sum |x|^2)), partial
+// sums added in workgroup order (the result does not depend on timing)
+__global__ void eig_resid_final_kernel(const double* __restrict__ partial, int groups, int p,
+                                       const double* __restrict__ lam, double normA, double normB,
+                                       double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= p) return;
+  double sr = 0.0, sx = 0.0;
+  for (int g = 0; g < groups; ++g) {
+    sr += partial[(int64_t)g * 2 * p + c];
+    sx += partial[(int64_t)g * 2 * p + p + c];
+  }
+  const double den = (normA + fabs(lam[c]) * normB) * sqrt(sx);
+  out[c] = den > 0.0 ? sqrt(sr) / den : (sr == 0.0 ? 0.0 : INFINITY);
+}
+
 // R = T - (A - sigma B) X  (X complex, ld p; T real, ld ldt; R complex, ld p)
 __global__ __launch_bounds__(256) void spmm_shift_resid_kernel(int64_t n, const int64_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
@@ -133,6 +213,36 @@ __global__ __launch_bounds__(256) void spmm_shift_resid_kernel(int64_t n, const 
     }
     if (v1) R[i * p + c1] = zd{T[i * ldt + c1] - r1, -i1};
     if (v2) R[i * p + c2] = zd{T[i * ldt + c2] - r2, -i2};
+  }
+}
+
+// complex Hermitian pencils: R = T - (A - sigma B) X  (X, T, R complex; A, B complex values)
+__global__ __launch_bounds__(256) void spmm_shift_resid_cplx_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                                    const int32_t* __restrict__ ci,
+                                                                    const zd* __restrict__ a,
+                                                                    const zd* __restrict__ b, double sr, double si,
+                                                                    const zd* __restrict__ X, const zd* __restrict__ T,
+                                                                    int64_t ldt, int p, zd* __restrict__ R) {
+  const int64_t i = spmm_row();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t e0 = rp[i], e1 = rp[i + 1];
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c1 = c0 + lane, c2 = c1 + 64;
+    const bool v1 = c1 < p, v2 = c2 < p;
+    const int l1 = v1 ? c1 : p - 1, l2 = v2 ? c2 : p - 1;  // loads stay in the row; unused lanes are not stored
+    zd s1{0.0, 0.0}, s2{0.0, 0.0};
+#pragma unroll 4
+    for (int64_t q = e0; q < e1; ++q) {
+      const zd* xr = X + (int64_t)ci[q] * p;
+      const zd x1 = xr[l1], x2 = xr[l2];
+      const zd av = a[q], bv = b[q];
+      const zd kv{av.re - (sr * bv.re - si * bv.im), av.im - (sr * bv.im + si * bv.re)};  // (A - sigma B)_iq
+      s1 = fma_(s1, kv, x1);
+      s2 = fma_(s2, kv, x2);
+    }
+    if (v1) R[i * p + c1] = sub(T[i * ldt + c1], s1);
+    if (v2) R[i * p + c2] = sub(T[i * ldt + c2], s2);
   }
 }
 
@@ -353,6 +463,13 @@ void spmm_shift_resid(int64_t n, const int64_t* rp, const int32_t* ci, const dou
                      R);
 }
 
+void spmm_shift_resid(int64_t n, const int64_t* rp, const int32_t* ci, const zd* a, const zd* b, double sr,
+                      double si, const zd* X, const zd* T, int64_t ldt, int p, zd* R, hipStream_t s) {
+  if (n * p == 0) return;
+  hipLaunchKernelGGL(spmm_shift_resid_cplx_kernel, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, sr, si, X, T,
+                     ldt, p, R);
+}
+
 template <typename T>
 void rows_gather(T* dst, int64_t ldd, const T* src, int64_t lds, const int32_t* idx, int64_t n, int p,
                  hipStream_t s) {
@@ -409,6 +526,23 @@ void colnorm2_cplx(const zd* X, int64_t n, int p, double* partial, double* out, 
                      partial);
   hipLaunchKernelGGL(colnorm_final_kernel, dim3(p), dim3(256), 0, s, partial, nb, p, out);
 }
+
+template <typename T>
+void eig_resid_norms(int64_t n, const int64_t* rp, const int32_t* ci, const T* a, const T* b, const int32_t* perm,
+                     const T* X, int64_t ldx, int p, const double* lam, double normA, double normB, double* partial,
+                     double* out, hipStream_t s) {
+  if (p <= 0) return;
+  hipLaunchKernelGGL(eig_resid_partial_kernel<T>, dim3(kResidGroups), dim3(256), 0, s, n, rp, ci, a, b, perm, X, ldx, p,
+                     lam, partial);
+  hipLaunchKernelGGL(eig_resid_final_kernel, dim3((p + 127) / 128), dim3(128), 0, s, partial, kResidGroups, p, lam,
+                     normA, normB, out);
+}
+template void eig_resid_norms<double>(int64_t, const int64_t*, const int32_t*, const double*, const double*,
+                                      const int32_t*, const double*, int64_t, int, const double*, double, double,
+                                      double*, double*, hipStream_t);
+template void eig_resid_norms<zd>(int64_t, const int64_t*, const int32_t*, const zd*, const zd*, const int32_t*,
+                                  const zd*, int64_t, int, const double*, double, double, double*, double*,
+                                  hipStream_t);
 
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s) {
   if (bytes) (void)hipMemsetAsync(p, 0, bytes, s);

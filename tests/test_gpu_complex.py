@@ -73,14 +73,16 @@ def test_complex_spmm(ctx, pencil7, p):
         assert np.max(np.abs(Y - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("leaf", [16, 64])
-def test_complex_pole_solves(ctx, pencil7, leaf):
+@pytest.mark.parametrize("leaf,precision", [(16, 0), (64, 0), (16, 1), (64, 1)])
+def test_complex_pole_solves(ctx, pencil7, leaf, precision):
+    """K^-1 and K^-H solves of the LU factors against dense solves; in mixed precision
+    (complex64 LU) after refinement against FP64 residuals."""
     gp, A, B, lam, X = pencil7
     w = _window(lam, 150, 10)
-    say(f"complex LU pole solves, K^-1 and K^-H, leaf {leaf}")
+    say(f"complex LU pole solves, K^-1 and K^-H, leaf {leaf} precision {precision}")
     co = zolo.zolo_filter_plan(w["a_minus"], w["a_plus"], w["b_minus"], w["b_plus"], 2, 3)
     P = zolo.Pencil.from_grid(ctx, gp, leaf_size=leaf)
-    F = zolo.Factors(ctx, P, co, zolo.ZOLO_PREC_FP64)
+    F = zolo.Factors(ctx, P, co, precision)
     V = pencils.gaussian_block(gp.n, 7, seed=4, complex_=True)
     T = B @ V
     Ad, Bd = A.toarray(), B.toarray()
@@ -117,14 +119,14 @@ def test_complex_G_and_filter(ctx, pencil7):
         assert ey < 1e-9
 
 
-@pytest.mark.parametrize("start,count", [(150, 12), (0, 8)])
-def test_complex_solve_window(ctx, pencil7, start, count):
+@pytest.mark.parametrize("start,count,precision", [(150, 12, 0), (0, 8, 0), (150, 12, 1), (0, 8, 1)])
+def test_complex_solve_window(ctx, pencil7, start, count, precision):
     gp, A, B, lam, X = pencil7
     w = _window(lam, start, count)
-    say(f"complex zolo_solve grid27p 7x8x6 window start {start} count {count}")
+    say(f"complex zolo_solve grid27p 7x8x6 window start {start} count {count} precision {precision}")
     P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
     nss = count + 8
-    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss)
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss, precision=precision)
     Q0 = pencils.gaussian_block(gp.n, nss, seed=2, complex_=True)
     eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], count, o, Q0=_dev(Q0))
     say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e}")
@@ -138,8 +140,8 @@ def test_complex_solve_window(ctx, pencil7, start, count):
     assert b_orthonormality(B, Xg) <= 1e-10
 
 
-@pytest.mark.parametrize("n,nss", [(24, 96), (32, 96), (24, 110)])
-def test_complex_window_stored(ctx, n, nss):
+@pytest.mark.parametrize("n,nss,precision", [(24, 96, 0), (32, 96, 0), (24, 110, 0), (24, 96, 1), (32, 96, 1)])
+def test_complex_window_stored(ctx, n, nss, precision):
     """The complex workload pencils (grid27p n^3, window of 64 near 0, block 96) against the
     oracle's stored window: count = inertia count, eigenvalues 1e-10, residual 1e-8,
     B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors.  With a
@@ -154,14 +156,15 @@ def test_complex_window_stored(ctx, n, nss):
     if not os.path.exists(path):
         pytest.skip("window fixture not generated")
     w = json.load(open(path))
-    say(f"complex zolo_solve grid27p {n}^3 window 64 block {nss}")
+    say(f"complex zolo_solve grid27p {n}^3 window 64 block {nss} precision {precision}")
     gp = pencils.grid27p(n)
     A, B = gp.scipy()
     P = zolo.Pencil.from_grid(ctx, gp, leaf_size=64)
-    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss)
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss, precision=precision)
     Q0 = pencils.gaussian_block(gp.n, nss, seed=2, complex_=True)
     eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, o, Q0=_dev(Q0))
-    say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e}")
+    say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e} "
+        f"refine {st['n_refine']} (max sweeps {st['refine_sweeps_max']}, missed {st['refine_missed']})")
     assert rc == 0 and len(eig) == w["inertia_count"] == 64
     eig = np.array(eig)
     ref = np.array(w["eigenvalues"])

@@ -180,3 +180,30 @@ def test_solve_window_10_large_subspace(ctx):
         (inf_norm(A) + np.abs(eig) * inf_norm(B)) * np.linalg.norm(X, axis=0))
     assert np.max(r) < 1e-8
     assert np.max(np.abs(X.T @ (B @ X) - np.eye(16))) < 1e-10
+
+
+@pytest.mark.parametrize("gen,shape,p", [("grid7", (13, 9, 11), 1), ("grid7", (13, 9, 11), 130),
+                                         ("grid7", (10, 10, 10), 64), ("grid27p", (7, 8, 6), 37),
+                                         ("grid27p", (5, 5, 5), 200)])
+def test_residuals_parity(ctx, gen, shape, p):
+    """zolo_residuals against the oracle's residual definition: random pairs (O(1)
+    residuals) and, on grid7 10^3, exact eigenpairs (residuals at rounding level)."""
+    say(f"residuals {gen} {shape} p={p}")
+    gp = getattr(pencils, gen)(shape[0], ny=shape[1], nz=shape[2])
+    A, B = gp.scipy()
+    cx = gen == "grid27p"
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=16)
+    X = pencils.gaussian_block(gp.n, p, seed=5, complex_=cx)
+    lam = np.random.Generator(np.random.PCG64(6)).uniform(-3.0, 9.0, p)
+    nA, nB = inf_norm(A), inf_norm(B)
+    got = zolo.zolo_residuals(P, _dev(X), _dev(lam)).cpu().numpy()
+    ref = rel_residuals(A, B, lam, X, nA, nB)
+    assert np.max(np.abs(got - ref) / ref) < 1e-12
+    if shape == (10, 10, 10):
+        ev, V = pencil_eigh_lapack(A.toarray(), B.toarray())
+        idx = np.arange(100, 100 + p)
+        Xe, le = np.ascontiguousarray(V[:, idx]), ev[idx]
+        got = zolo.zolo_residuals(P, _dev(Xe), _dev(le)).cpu().numpy()
+        ref = rel_residuals(A, B, le, Xe, nA, nB)
+        say(f"  exact pairs: max {got.max():.2e} (oracle {ref.max():.2e})")
+        assert got.max() < 1e-14 and np.max(np.abs(got - ref)) < 1e-14
