@@ -396,7 +396,7 @@ struct zolo_factors {
   std::unique_ptr<Workspace> ws;
   double t_factor = 0.0;
   int max_refine = 8;
-  double tol_refine = 1e-8;
+  double tol_refine = 1e-13;  // zolo_factor: pole solves refined to FP64 accuracy; zolo_solve sets its own
   long long n_refine = 0;
   int refine_sweeps_max = 0;  // most corrections one refinement took
   int refine_missed = 0;      // refinements that stopped above their target
