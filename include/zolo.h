@@ -209,6 +209,20 @@ zolo_status zolo_spmm(zolo_pencil* p, int which, const void* d_X, int64_t ldx, i
 zolo_status zolo_residuals(zolo_pencil* p, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
                            double* d_out, void* stream);
 
+/* zolo_residuals for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same norms from the same kernels, with the partial sums in a static
+ * device array of the library (4 MiB per GPU, held until the process ends;
+ * its address is looked up when a context is created on the device).  No
+ * hipMalloc/hipFree and no host synchronization: the norms are ready when
+ * `stream` reaches them.  Limit: ncols <= 512 (ZOLO_EINVAL beyond, with a
+ * message).  All calls on one GPU share the array, so calls that overlap on
+ * one GPU (other streams or threads) race and must be serialized by the
+ * caller.  Errors: as zolo_residuals, and ZOLO_EDEVICE if the array's
+ * address cannot be obtained. */
+zolo_status zolo_residuals_noalloc(zolo_pencil* p, const void* d_X, int64_t ldx, int ncols, const double* d_lambda,
+                                   double* d_out, void* stream);
+
 /* d_X (complex128, N x p) = K_j^-1 d_T for pole j (0-based) (eq. solve).
  * Real pencils: j < r1, d_T real.  Complex Hermitian pencils: d_T complex128,
  * j < r1 gives K_j^-1 and r1 <= j < 2 r1 gives K_{j-r1}^-H

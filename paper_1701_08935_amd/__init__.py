@@ -100,6 +100,7 @@ _SIGS = {
     "zolo_factors_free": (None, [_vp]),
     "zolo_spmm": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_residuals": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
+    "zolo_residuals_noalloc": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
     "zolo_pole_solve": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_apply_G": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
@@ -273,6 +274,13 @@ def zolo_residuals(pencil: Pencil, X, lam):
 
     out = torch.empty(X.shape[1], dtype=torch.float64, device=X.device)
     _check(lib().zolo_residuals(pencil.h, _ptr(X), X.stride(0), X.shape[1], _ptr(lam), _ptr(out), _stream()))
+    return out
+
+
+def zolo_residuals_noalloc(pencil: Pencil, X, lam, out):
+    """zolo_residuals into a caller-provided `out` (k float64 on the device) through the
+    entry point that allocates nothing (the library's static scratch)."""
+    _check(lib().zolo_residuals_noalloc(pencil.h, _ptr(X), X.stride(0), X.shape[1], _ptr(lam), _ptr(out), _stream()))
     return out
 
 

@@ -596,6 +596,41 @@ extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
   return ZOLO_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static device scratch for zolo_residuals_noalloc: the partial sums of the
+// fused residual kernel (kResidGroups workgroups x 2 sums x at most
+// kResidMaxCols columns, 4 MiB).  Each GPU holds its own copy for the life of
+// the process.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in): the device address of each GPU's copy is looked
+// up once, with that device current, and kept in g_scratch_dev.  The array has
+// external linkage: with internal linkage the compiler keeps it a local symbol
+// of the device code object, which the loader cannot resolve by name, and the
+// runtime's symbol lookup then fails.
+__device__ __align__(256) double zolo_noalloc_scratch[(size_t)kResidGroups * 2 * kResidMaxCols];
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on device dev (which must be current)
+zolo_status scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d beyond the %d devices the static scratch table holds", dev, kMaxDevices);
+    return ZOLO_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return ZOLO_OK;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(zolo_noalloc_scratch));
+  if (e != hipSuccess || !ptr) {
+    set_error("hipGetSymbolAddress of the static scratch failed on device %d: %s", dev, hipGetErrorString(e));
+    return ZOLO_EDEVICE;
+  }
+  g_scratch_dev[dev] = (double*)ptr;
+  return ZOLO_OK;
+}
+}  // namespace
+
 extern "C" zolo_status zolo_ctx_create(int dev, zolo_ctx** out) {
   if (!out) {
     set_error("null output");
@@ -608,6 +643,7 @@ extern "C" zolo_status zolo_ctx_create(int dev, zolo_ctx** out) {
     return ZOLO_EINVAL;
   }
   HIPC(hipSetDevice(dev));
+  CHK(scratch_setup(dev));
   auto* c = new zolo_ctx();
   c->device = dev;
   *out = c;
@@ -2220,6 +2256,26 @@ extern "C" zolo_status zolo_residuals(zolo_pencil* P, const void* d_X, int64_t l
   double* partial = nullptr;
   CHK(tmp.alloc(&partial, (size_t)kResidGroups * 2 * ncols));
   return residuals_run(P, d_X, ldx, ncols, d_lambda, d_out, partial, s);
+}
+
+extern "C" zolo_status zolo_residuals_noalloc(zolo_pencil* P, const void* d_X, int64_t ldx, int ncols,
+                                              const double* d_lambda, double* d_out, void* stream) {
+  CHK(residuals_check(P, d_X, ldx, ncols, d_lambda, d_out, "zolo_residuals_noalloc"));
+  if (ncols == 0) return ZOLO_OK;
+  const int dev = P->ctx->device;
+  double* ptr = (dev >= 0 && dev < kMaxDevices) ? g_scratch_dev[dev] : nullptr;
+  if (!ptr) {
+    int cur = 0;
+    HIPC(hipGetDevice(&cur));
+    if (cur != dev) {
+      set_error("zolo_residuals_noalloc: device %d is not current (and its scratch is not set up)", dev);
+      return ZOLO_EDEVICE;
+    }
+    CHK(scratch_setup(dev));
+    ptr = g_scratch_dev[dev];
+  }
+  // every workgroup overwrites its 2 * ncols partial sums, so nothing needs clearing
+  return residuals_run(P, d_X, ldx, ncols, d_lambda, d_out, ptr, as_stream(stream));
 }
 
 extern "C" zolo_status zolo_pole_solve(zolo_factors* F, int j, const double* d_T, int64_t ldt, int ncols, void* d_X,
