@@ -140,6 +140,13 @@ zolo_status zolo_opts_default(zolo_opts* out);
  * same size; destroying a context returns the cached blocks to HIP. */
 zolo_status zolo_ctx_create(int hip_device, zolo_ctx** out);
 void zolo_ctx_destroy(zolo_ctx* ctx);
+/* Device-memory budget of the context's device (bytes; 0 = none, the
+ * default).  Every device allocation of the library (factors, solve programs,
+ * Krylov bases, results) counts against it while it is held; one that would
+ * exceed it fails with ZOLO_ENOMEM and a message, before any hipMalloc.
+ * zolo_ctx_hbm_in_use reports the bytes currently held. */
+zolo_status zolo_ctx_set_hbm_budget(zolo_ctx* ctx, size_t bytes);
+zolo_status zolo_ctx_hbm_in_use(const zolo_ctx* ctx, size_t* bytes);
 
 /*
  * Upload a pencil (host CSR) and run nested dissection + symbolic analysis on
@@ -268,7 +275,9 @@ zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, i
  * The result holds Ritz pairs with a < theta < b and residual <= tol_resid;
  * its vectors are complex128 for complex pencils.  An interval with no
  * eigenvalue returns count 0 once two filtered iterations select none.
- * Errors: ZOLO_ENOCONV (best results and stats still filled),
+ * Errors: ZOLO_EGAP (best results and stats still filled: a Ritz value
+ * converged inside a stated eigengap, so the gaps given are wrong),
+ * ZOLO_ENOCONV (best results and stats still filled),
  * ZOLO_ESUBSPACE (found >= n_ss - 1), ZOLO_EINVAL.
  */
 zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* p, double a, double b, int n_lambda_est, const zolo_opts* opts,
@@ -278,6 +287,12 @@ int64_t zolo_result_count(const zolo_result* r);
 const double* zolo_result_eigenvalues(const zolo_result* r);
 /* copy the B-orthonormal eigenvectors (N x count, row-major, ld) to a device buffer */
 zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_dst, int64_t ld, void* stream);
+/* the same to a host buffer (blocking copy over PCIe) */
+zolo_status zolo_result_copy_vectors_host(const zolo_result* r, void* h_dst, int64_t ld);
+/* the result's own device copy of the eigenvectors (N x count row-major, ld
+ * returned in *ld = count; double, or interleaved complex128 for complex
+ * pencils); owned by r and valid until zolo_result_free; NULL when count = 0 */
+const void* zolo_result_device_vectors(const zolo_result* r, int64_t* ld);
 zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out);
 void zolo_result_free(zolo_result* r);
 

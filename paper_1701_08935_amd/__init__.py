@@ -89,6 +89,8 @@ _SIGS = {
     "zolo_opts_default": (_i, [ctypes.POINTER(zolo_opts)]),
     "zolo_ctx_create": (_i, [_i, ctypes.POINTER(_vp)]),
     "zolo_ctx_destroy": (None, [_vp]),
+    "zolo_ctx_set_hbm_budget": (_i, [_vp, ctypes.c_size_t]),
+    "zolo_ctx_hbm_in_use": (_i, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
     "zolo_pencil_create": (_i, [_vp, _i64, _vp, _vp, _vp, _vp, _i, _vp, _i, ctypes.POINTER(_vp)]),
     "zolo_pencil_free": (None, [_vp]),
     "zolo_pencil_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
@@ -108,6 +110,8 @@ _SIGS = {
     "zolo_result_count": (_i64, [_vp]),
     "zolo_result_eigenvalues": (ctypes.POINTER(_d), [_vp]),
     "zolo_result_copy_vectors": (_i, [_vp, _vp, _i64, _vp]),
+    "zolo_result_copy_vectors_host": (_i, [_vp, _vp, _i64]),
+    "zolo_result_device_vectors": (_vp, [_vp, ctypes.POINTER(_i64)]),
     "zolo_result_stats": (_i, [_vp, ctypes.POINTER(zolo_stats)]),
     "zolo_result_free": (None, [_vp]),
     "zolo_profile_enable": (_i, [_i]),
@@ -198,6 +202,15 @@ class Context:
         _check(lib().zolo_ctx_create(int(device), ctypes.byref(h)))
         self.h = h
         self.device = device
+
+    def set_hbm_budget(self, nbytes: int):
+        """zolo_ctx_set_hbm_budget: device-memory budget of the library on this device (0 = none)."""
+        _check(lib().zolo_ctx_set_hbm_budget(self.h, int(nbytes)))
+
+    def hbm_in_use(self) -> int:
+        v = ctypes.c_size_t()
+        _check(lib().zolo_ctx_hbm_in_use(self.h, ctypes.byref(v)))
+        return v.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -312,8 +325,11 @@ def zolo_filter_apply(f: Factors, V, tol=1e-10, max_iter=60, allow_noconv=False)
 
 
 def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None,
-               allow=(ZOLO_ENOCONV,)):
-    """Returns (eigenvalues list, vectors tensor N x count (device), stats dict, status)."""
+               allow=(ZOLO_ENOCONV,), host_vectors=False):
+    """Returns (eigenvalues list, vectors N x count, stats dict, status).  The vectors
+    are a device tensor (zolo_result_copy_vectors), or with host_vectors=True a numpy
+    array (zolo_result_copy_vectors_host)."""
+    import numpy as np
     import torch
 
     if opts is None:
@@ -328,10 +344,15 @@ def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts
         cnt = L.zolo_result_count(h)
         ev = L.zolo_result_eigenvalues(h)
         eig = [ev[i] for i in range(cnt)]
-        vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.complex128 if pencil.cplx else torch.float64,
-                          device=f"cuda:{ctx.device}")
-        if cnt:
-            _check(L.zolo_result_copy_vectors(h, _ptr(vec), vec.stride(0), _stream()))
+        if host_vectors:
+            vec = np.empty((pencil.n, max(cnt, 1)), dtype=np.complex128 if pencil.cplx else np.float64)
+            if cnt:
+                _check(L.zolo_result_copy_vectors_host(h, _np_ptr(vec), vec.shape[1]))
+        else:
+            vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.complex128 if pencil.cplx else torch.float64,
+                              device=f"cuda:{ctx.device}")
+            if cnt:
+                _check(L.zolo_result_copy_vectors(h, _ptr(vec), vec.stride(0), _stream()))
         st = zolo_stats()
         _check(L.zolo_result_stats(h, ctypes.byref(st)))
     finally:

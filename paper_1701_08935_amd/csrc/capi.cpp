@@ -98,6 +98,31 @@ class DevicePool {
     free_.insert({bytes, {dev, p}});
     cached_ += bytes;
   }
+  // Device-memory budget per device (0 = none): blocks handed out to arenas
+  // and not yet released count against it.
+  bool charge(int dev, size_t bytes) {
+    std::lock_guard<std::mutex> lk(m_);
+    if (dev < 0 || dev >= kDev) return true;
+    if (budget_[dev] && in_use_[dev] + bytes > budget_[dev]) return false;
+    in_use_[dev] += bytes;
+    return true;
+  }
+  void uncharge(int dev, size_t bytes) {
+    std::lock_guard<std::mutex> lk(m_);
+    if (dev >= 0 && dev < kDev) in_use_[dev] -= std::min(bytes, in_use_[dev]);
+  }
+  void set_budget(int dev, size_t bytes) {
+    std::lock_guard<std::mutex> lk(m_);
+    if (dev >= 0 && dev < kDev) budget_[dev] = bytes;
+  }
+  size_t budget(int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    return (dev >= 0 && dev < kDev) ? budget_[dev] : 0;
+  }
+  size_t in_use(int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    return (dev >= 0 && dev < kDev) ? in_use_[dev] : 0;
+  }
   void trim() {
     std::lock_guard<std::mutex> lk(m_);
     if (free_.empty()) return;
@@ -108,9 +133,12 @@ class DevicePool {
   }
 
  private:
+  static constexpr int kDev = 64;
   std::mutex m_;
   std::multimap<size_t, std::pair<int, void*>> free_;  // block size -> (device, pointer)
   size_t cached_ = 0;
+  size_t budget_[kDev] = {};
+  size_t in_use_[kDev] = {};
 };
 
 // RAII owner of device allocations (through the cache above)
@@ -125,7 +153,10 @@ struct DevArena {
   void release() {
     if (ptrs.empty()) return;
     (void)hipDeviceSynchronize();  // no kernel may still use a block handed out again
-    for (const Block& b : ptrs) DevicePool::get().give(b.p, b.bytes, b.dev);
+    for (const Block& b : ptrs) {
+      DevicePool::get().give(b.p, b.bytes, b.dev);
+      DevicePool::get().uncharge(b.dev, b.bytes);
+    }
     ptrs.clear();
   }
   template <typename T>
@@ -133,6 +164,11 @@ struct DevArena {
     const size_t bytes = DevicePool::round(std::max<size_t>(count, 1) * sizeof(T));
     int dev = 0;
     (void)hipGetDevice(&dev);
+    if (!DevicePool::get().charge(dev, bytes)) {
+      set_error("device memory budget of %zu bytes exceeded (%zu in use, %zu more requested)",
+                DevicePool::get().budget(dev), DevicePool::get().in_use(dev), bytes);
+      return ZOLO_ENOMEM;
+    }
     void* p = DevicePool::get().take(bytes, dev);
     if (!p) {
       hipError_t e = hipMalloc(&p, bytes);
@@ -141,6 +177,7 @@ struct DevArena {
         e = hipMalloc(&p, bytes);
       }
       if (e != hipSuccess) {
+        DevicePool::get().uncharge(dev, bytes);
         set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
         return ZOLO_ENOMEM;
       }
@@ -650,6 +687,24 @@ extern "C" zolo_status zolo_ctx_create(int dev, zolo_ctx** out) {
   return ZOLO_OK;
 }
 
+extern "C" zolo_status zolo_ctx_set_hbm_budget(zolo_ctx* c, size_t bytes) {
+  if (!c) {
+    set_error("zolo_ctx_set_hbm_budget: null context");
+    return ZOLO_EINVAL;
+  }
+  DevicePool::get().set_budget(c->device, bytes);
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_ctx_hbm_in_use(const zolo_ctx* c, size_t* bytes) {
+  if (!c || !bytes) {
+    set_error("zolo_ctx_hbm_in_use: null argument");
+    return ZOLO_EINVAL;
+  }
+  *bytes = DevicePool::get().in_use(c->device);
+  return ZOLO_OK;
+}
+
 extern "C" void zolo_ctx_destroy(zolo_ctx* c) {
   delete c;
   DevicePool::get().trim();  // return cached device memory
@@ -941,6 +996,10 @@ extern "C" zolo_status zolo_pencil_create(zolo_ctx* ctx, int64_t n, const int64_
           std::fabs(bt.re - be.re) > 1e-14 * sb || std::fabs(bt.im + be.im) > 1e-14 * sb) {
         set_error("A or B not Hermitian at (%lld, %d)", (long long)i, (int)j);
         return ZOLO_ENOTHERM;
+      }
+      if (j == i && !(be.re > 0.0)) {  // a Hermitian positive definite B has a positive diagonal
+        set_error("B is not positive definite: B(%lld, %lld) = %g", (long long)i, (long long)i, be.re);
+        return ZOLO_EINVAL;
       }
     }
     na = std::max(na, ra);
@@ -2467,6 +2526,25 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
       empty_runs = 0;
     }
   }
+  // Ritz values that have converged inside a stated eigengap (a_-, a_+) or
+  // (b_-, b_+), away from its ends, contradict the caller's gaps
+  int in_gap = 0;
+  double gap_theta = 0.0;
+  if (converged) {
+    const double gl[2] = {o.a_minus, o.b_minus}, gh[2] = {o.a_plus, o.b_plus};
+    for (int c = 0; c < k; ++c) {
+      const double r = std::sqrt(rnh[3 * c]) / ((P->normA + std::fabs(th[c]) * P->normB) * std::sqrt(rnh[3 * c + 1]));
+      if (!(r <= o.tol_resid)) continue;
+      for (int g = 0; g < 2; ++g) {
+        double m = 1e-9 * std::max({1.0, std::fabs(th[c]), std::isfinite(gl[g]) ? std::fabs(gl[g]) : 0.0,
+                                     std::isfinite(gh[g]) ? std::fabs(gh[g]) : 0.0});
+        if (th[c] > gl[g] + m && th[c] < gh[g] - m) {
+          ++in_gap;
+          gap_theta = th[c];
+        }
+      }
+    }
+  }
   st.t_iter = now_s() - t0;
   st.n_solv = F->n_solv;
   st.n_refine = F->n_refine;
@@ -2520,6 +2598,11 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   if (!converged) {
     set_error("subspace iteration did not reach tol_resid (worst %.3e)", st.max_resid);
     return ZOLO_ENOCONV;
+  }
+  if (in_gap) {
+    set_error("%d converged Ritz value(s) inside a stated eigengap (e.g. %.15g): the eigengaps are wrong", in_gap,
+              gap_theta);
+    return ZOLO_EGAP;
   }
   return frc == ZOLO_ENOCONV ? ZOLO_ENOCONV : ZOLO_OK;
 }
@@ -2581,6 +2664,20 @@ extern "C" zolo_status zolo_result_copy_vectors(const zolo_result* r, void* d_ds
   HIPC(hipMemcpy2DAsync(d_dst, e * ld, r->vec, e * r->count, e * r->count, r->n, hipMemcpyDeviceToDevice, s));
   HIPC(hipStreamSynchronize(s));
   return ZOLO_OK;
+}
+extern "C" zolo_status zolo_result_copy_vectors_host(const zolo_result* r, void* h_dst, int64_t ld) {
+  if (!r || !h_dst || ld < r->count) {
+    set_error("zolo_result_copy_vectors_host: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  if (r->count == 0) return ZOLO_OK;
+  const size_t e = sizeof(double) * r->ef;
+  HIPC(hipMemcpy2D(h_dst, e * ld, r->vec, e * r->count, e * r->count, r->n, hipMemcpyDeviceToHost));
+  return ZOLO_OK;
+}
+extern "C" const void* zolo_result_device_vectors(const zolo_result* r, int64_t* ld) {
+  if (ld) *ld = r ? r->count : 0;
+  return (r && r->count > 0) ? (const void*)r->vec : nullptr;
 }
 extern "C" zolo_status zolo_result_stats(const zolo_result* r, zolo_stats* out) {
   if (!r || !out) {

@@ -207,3 +207,81 @@ def test_residuals_parity(ctx, gen, shape, p):
         ref = rel_residuals(A, B, le, Xe, nA, nB)
         say(f"  exact pairs: max {got.max():.2e} (oracle {ref.max():.2e})")
         assert got.max() < 1e-14 and np.max(np.abs(got - ref)) < 1e-14
+
+
+def test_result_vector_accessors(ctx):
+    """The host copy of the eigenvectors equals the device copy, and the result's own
+    device pointer is exported with ld = count."""
+    say("result accessors: host copy, device copy, device pointer (grid 10^3)")
+    w = _window(10)
+    gp = pencils.grid7(10)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    Q0 = _dev(pencils.gaussian_block(gp.n, 24, seed=2))
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=24)
+    eig_d, vec_d, _, rc_d = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts, Q0=Q0)
+    eig_h, vec_h, _, rc_h = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts, Q0=Q0, host_vectors=True)
+    assert rc_d == rc_h == 0 and eig_d == eig_h
+    assert isinstance(vec_h, np.ndarray) and np.array_equal(vec_d.cpu().numpy(), vec_h)
+    import ctypes
+
+    L = zolo.lib()
+    h = ctypes.c_void_p()
+    rc = L.zolo_solve(ctx.h, P.h, w["a"], w["b"], 16, ctypes.byref(opts), ctypes.c_void_p(Q0.data_ptr()),
+                      zolo._stream(), ctypes.byref(h))
+    try:
+        assert rc == 0
+        ld = ctypes.c_int64(-1)
+        ptr = L.zolo_result_device_vectors(h, ctypes.byref(ld))
+        assert ptr and ld.value == L.zolo_result_count(h) == 16
+    finally:
+        L.zolo_result_free(h)
+
+
+def test_wrong_eigengap_returns_egap(ctx):
+    """A stated gap (a_-, a_+) that contains an eigenvalue (a_+ moved past the first
+    eigenvalue of the window): the eigenvalue still converges inside (a, b), and the
+    call reports ZOLO_EGAP with the results filled."""
+    say("EGAP: grid 10^3 window with a_+ moved past the first eigenvalue")
+    w = dict(_window(10))
+    lam = np.array(w["eigenvalues"])
+    w["a_plus"] = 0.5 * (lam[0] + lam[1])
+    gp = pencils.grid7(10)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    Q0 = _dev(pencils.gaussian_block(gp.n, 24, seed=2))
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=24, max_subspace_iter=8)
+    eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts, Q0=Q0,
+                                       allow=(zolo.ZOLO_EGAP, zolo.ZOLO_ENOCONV))
+    say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} resid={st['max_resid']:.2e}")
+    assert rc == zolo.ZOLO_EGAP
+    assert "eigengap" in zolo.lib().zolo_last_error().decode()
+    assert len(eig) == 16 and abs(eig[0] - lam[0]) <= 1e-10 * abs(lam[0])
+
+
+def test_hbm_budget(ctx):
+    """A device-memory budget below what a query needs fails the query with ZOLO_ENOMEM
+    (before any allocation beyond it); lifting it lets the same query run."""
+    say("HBM budget: grid 10^3 query under a 1 MiB budget, then without a budget")
+    w = _window(10)
+    gp = pencils.grid7(10)
+    P = zolo.Pencil.from_grid(ctx, gp, leaf_size=32)
+    opts = zolo.opts_from_window(w, r1=2, r2=0, n_ss=24)
+    ctx.set_hbm_budget(1 << 20)
+    try:
+        with pytest.raises(zolo.ZoloError) as ei:
+            zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts)
+        assert ei.value.status == zolo.ZOLO_ENOMEM and "budget" in str(ei.value)
+    finally:
+        ctx.set_hbm_budget(0)
+    eig, _, _, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 16, opts)
+    assert rc == 0 and len(eig) == 16
+
+
+def test_b_not_positive_definite_rejected(ctx):
+    say("pencil with a non-positive diagonal entry of B")
+    gp = pencils.grid7(4)
+    bv = np.array(gp.b_vals, dtype=np.float64)
+    d = [e for i in range(gp.n) for e in range(gp.rowptr[i], gp.rowptr[i + 1]) if gp.colind[e] == i]
+    bv[d[5]] = -0.5
+    with pytest.raises(zolo.ZoloError) as ei:
+        zolo.Pencil(ctx, gp.rowptr, gp.colind, gp.a_vals, bv, gp.grid, 16)
+    assert ei.value.status == zolo.ZOLO_EINVAL and "positive definite" in str(ei.value)
