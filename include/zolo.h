@@ -80,8 +80,10 @@ typedef struct {
 } zolo_filter_coeffs;
 
 typedef struct {
-  double a_minus, a_plus, b_minus, b_plus; /* eigengaps; a_minus may be -INF or b_plus +INF */
-  int r1;                  /* number of factorizations (inner order)               */
+  double a_minus, a_plus, b_minus, b_plus; /* eigengaps; a_minus may be -INF or b_plus +INF;
+                              all four NaN: estimated by inertia counts on the device */
+  int r1;                  /* number of factorizations (inner order); 0 = fewest
+                              (<= 4) giving an outer modulus l2 >= 0.2             */
   int r2;                  /* outer order; 0 = smallest r2 with delta0 <= filter_eps */
   double filter_eps;       /* target delta0 when r2 == 0 (Remark after Algorithm 2) */
   int n_ss;                /* subspace size; 0 = ceil(1.5 n_lambda_est)             */
@@ -119,6 +121,10 @@ typedef struct {
   long long factor_bytes;  /* device bytes of all factors                           */
   long long nnz_l;         /* entries of one factor (panel + diagonal-block inverse) */
   double factor_flops;     /* per pole                                              */
+  long long inertia_count; /* eigenvalues in (a, b) by inertia (eigengaps estimated),
+                              -1 when the caller gave the gaps                      */
+  double t_gaps;           /* seconds spent estimating the eigengaps                */
+  double a_minus, a_plus, b_minus, b_plus;  /* the eigengaps the filter used        */
 } zolo_stats;
 
 typedef struct zolo_ctx zolo_ctx;
@@ -198,6 +204,17 @@ zolo_status zolo_filter_plan(double a_minus, double a_plus, double b_minus, doub
 zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* p, const zolo_filter_coeffs* co, int precision,
                         void* stream, zolo_factors** out);
 void zolo_factors_free(zolo_factors* f);
+
+/* Sylvester inertia (Sec. 1: the number of eigenvalues of the pencil in an
+ * interval, which sizes the subspace; Alg. 2 line 1: the eigengaps):
+ * counts[k] = number of eigenvalues of (A, B) below sigmas[k], for
+ * 1 <= nshift <= ZOLO_MAX_R real shifts (host arrays).  Each shift is an
+ * unpivoted LDL^T (complex Hermitian pencils: L D L^H) of A - sigma_k B in the
+ * nested-dissection order on the device, counting negative pivots; the shifts
+ * are factored concurrently.  Blocking.  Errors: ZOLO_EBREAKDOWN (a zero pivot:
+ * the shift is numerically an eigenvalue), ZOLO_ENOMEM, ZOLO_EINVAL. */
+zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* p, const double* sigmas, int nshift, int64_t* counts,
+                         void* stream);
 
 /* d_Y = A d_X or B d_X (which = 0 for A, 1 for B); N x p row-major blocks in
  * the ORIGINAL ordering, double for real pencils, complex128 for complex ones. */

@@ -52,7 +52,8 @@ class zolo_stats(ctypes.Structure):
                 ("b_orth", _d), ("t_plan", _d), ("t_symbolic", _d), ("t_factor", _d), ("t_iter", _d),
                 ("t_total", _d), ("gmres_resid", _d), ("norm_a", _d), ("norm_b", _d), ("r1", _i), ("r2", _i),
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
-                ("nnz_l", ctypes.c_longlong), ("factor_flops", _d)]
+                ("nnz_l", ctypes.c_longlong), ("factor_flops", _d), ("inertia_count", ctypes.c_longlong),
+                ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d)]
 
 
 class zolo_kernel_profile(ctypes.Structure):
@@ -100,6 +101,7 @@ _SIGS = {
     "zolo_filter_plan": (_i, [_d, _d, _d, _d, _i, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
     "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
     "zolo_factors_free": (None, [_vp]),
+    "zolo_inertia": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
     "zolo_spmm": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_residuals": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
     "zolo_residuals_noalloc": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
@@ -270,6 +272,16 @@ class Factors:
         if getattr(self, "h", None) and _lib is not None:
             _lib.zolo_factors_free(self.h)
             self.h = None
+
+
+def zolo_inertia(ctx: Context, pencil: Pencil, sigmas):
+    """Number of eigenvalues of the pencil below each real shift (device LDL^T inertia)."""
+    import numpy as np
+
+    s = np.ascontiguousarray(sigmas, dtype=np.float64)
+    out = np.zeros(s.shape[0], dtype=np.int64)
+    _check(lib().zolo_inertia(ctx.h, pencil.h, _np_ptr(s), int(s.shape[0]), _np_ptr(out), _stream()))
+    return out
 
 
 def zolo_spmm(pencil: Pencil, which: int, X):

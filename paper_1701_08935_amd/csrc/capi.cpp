@@ -1658,6 +1658,49 @@ extern "C" zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* P, const zolo_fil
 
 extern "C" void zolo_factors_free(zolo_factors* f) { delete f; }
 
+// Sylvester inertia on the device: for real shifts sigma_k, K = A - sigma_k B
+// is Hermitian (real symmetric for real pencils), its unpivoted LDL^T (LU =
+// L D L^H for complex pencils) in the nested-dissection order is a congruence,
+// so the number of negative pivots of D is the number of eigenvalues of (A, B)
+// below sigma_k.  All shifts of a call are factored concurrently (one stream
+// each), in complex128 with zero imaginary shift.
+extern "C" zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* P, const double* sigmas, int nshift,
+                                    int64_t* counts, void* stream) {
+  if (!ctx || !P || !sigmas || !counts || nshift < 1 || nshift > ZOLO_MAX_R) {
+    set_error("zolo_inertia: invalid argument (1 <= nshift <= %d)", ZOLO_MAX_R);
+    return ZOLO_EINVAL;
+  }
+  for (int k = 0; k < nshift; ++k)
+    if (!std::isfinite(sigmas[k])) {
+      set_error("zolo_inertia: shift %d is not finite", k);
+      return ZOLO_EINVAL;
+    }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  zolo_filter_coeffs co{};
+  co.r1 = nshift;
+  co.r2 = 1;
+  for (int k = 0; k < nshift; ++k) co.sigma_hat_re[k] = sigmas[k];
+  std::unique_ptr<zolo_factors> F(new zolo_factors());
+  F->P = P;
+  F->co = co;
+  F->precision = ZOLO_PREC_FP64;
+  zolo_status rc = factor_all<zd>(F.get(), P, &co, &F->pd, s);
+  if (rc == ZOLO_EBREAKDOWN) {
+    set_error("zolo_inertia: zero pivot (a shift is numerically an eigenvalue); move the shift slightly");
+    return rc;
+  }
+  CHK(rc);
+  std::vector<zd> d(P->n);
+  for (int k = 0; k < nshift; ++k) {
+    HIPC(hipMemcpy(d.data(), F->pd[k].dvec, sizeof(zd) * P->n, hipMemcpyDeviceToHost));
+    int64_t neg = 0;
+    for (const zd& v : d) neg += v.re < 0.0;
+    counts[k] = neg;
+  }
+  return ZOLO_OK;
+}
+
 // ===========================================================================
 // supernodal solves
 // ===========================================================================
@@ -2378,13 +2421,102 @@ extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int
 // ===========================================================================
 namespace {
 // Algorithm 1 on blocks of scalar VT (double: real pencils, zd: complex Hermitian pencils)
+// Eigengaps when the caller gives none (Alg. 2, line 1; the paper leaves the
+// estimate open).  Inertia counts at a - d_a, a + d_a, b - d_b, b + d_b (and at
+// a, b for the exact count) find eigenvalue-free intervals around a and b: the
+// half-widths start at a quarter of the mean eigenvalue spacing in (a, b) and a
+// side whose interval holds an eigenvalue is shrunk 4x and counted again (at most
+// 8 rounds).  No eigenvalue below a + d_a makes a_- = -inf, none above b - d_b
+// makes b_+ = +inf.  Narrower gaps than the true ones are safe: the filter is
+// planned on a wider transition band.
+struct GapInfo {
+  int64_t count = -1;  // eigenvalues in (a, b) by inertia, -1 if not computed
+  double t_gaps = 0.0;
+};
+
+zolo_status estimate_gaps(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_est, zolo_opts* o, GapInfo* gi,
+                          hipStream_t s) {
+  const double t0 = now_s();
+  const double spacing = (b - a) / std::max(n_est, 1);
+  double da = 0.25 * spacing, db = 0.25 * spacing;
+  bool ok_a = false, ok_b = false;
+  int64_t nu_a = -1, nu_b = -1;
+  for (int round = 0; round < 8 && !(ok_a && ok_b); ++round) {
+    std::vector<double> sh;
+    if (round == 0) {
+      sh.push_back(a);
+      sh.push_back(b);
+    }
+    const int ia = (int)sh.size();
+    if (!ok_a) {
+      sh.push_back(a - da);
+      sh.push_back(a + da);
+    }
+    const int ib = (int)sh.size();
+    if (!ok_b) {
+      sh.push_back(b - db);
+      sh.push_back(b + db);
+    }
+    std::vector<int64_t> cnt(sh.size());
+    CHK(zolo_inertia(ctx, P, sh.data(), (int)sh.size(), cnt.data(), s));
+    if (round == 0) {
+      nu_a = cnt[0];
+      nu_b = cnt[1];
+    }
+    if (!ok_a) {
+      if (cnt[ia] == cnt[ia + 1]) {
+        ok_a = true;
+        o->a_minus = cnt[ia] == 0 ? -INFINITY : a - da;
+        o->a_plus = a + da;
+      } else {
+        da *= 0.25;
+      }
+    }
+    if (!ok_b) {
+      if (cnt[ib] == cnt[ib + 1]) {
+        ok_b = true;
+        o->b_minus = b - db;
+        o->b_plus = cnt[ib] == P->n ? INFINITY : b + db;
+      } else {
+        db *= 0.25;
+      }
+    }
+  }
+  if (!ok_a || !ok_b) {
+    set_error("eigengap estimate: an eigenvalue lies within %.3g of %s", ok_a ? db : da, ok_a ? "b" : "a");
+    return ZOLO_EGAP;
+  }
+  if (std::isinf(o->a_minus) && std::isinf(o->b_plus)) o->b_plus = b + db;  // at most one infinite end
+  gi->count = nu_b - nu_a;
+  gi->t_gaps = now_s() - t0;
+  return ZOLO_OK;
+}
+
+// r1 = 0 (Remark after Alg. 2 leaves the split open): the fewest inner poles
+// (factorizations, at most 4) whose inner error delta_1 leaves the outer modulus
+// l2 = (1 - delta_1)/(1 + delta_1) >= 0.2, so that the outer shifted systems
+// stay well separated from the spectrum of G and block GMRES needs few steps.
+zolo_status choose_r1(zolo_opts* o) {
+  for (int r1 = 1; r1 <= 4; ++r1) {
+    zolo_filter_coeffs co;
+    CHK(zolo_filter_plan(o->a_minus, o->a_plus, o->b_minus, o->b_plus, r1, o->r2, o->filter_eps, &co));
+    if (co.l2 >= 0.2 || r1 == 4) {
+      o->r1 = r1;
+      return ZOLO_OK;
+    }
+  }
+  return ZOLO_OK;
+}
+
 template <typename VT>
 zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est, zolo_opts o,
-                       const double* d_Q0, void* stream, zolo_result** out) {
+                       const double* d_Q0, void* stream, zolo_result** out, const GapInfo& gi) {
   hipStream_t s = as_stream(stream);
-  const double t_start = now_s();
+  const double t_start = now_s() - gi.t_gaps;
   const int64_t n = P->n;
-  int nss = o.n_ss > 0 ? o.n_ss : (int)std::ceil(1.5 * std::max(n_lambda_est, 1));
+  // with an exact count from the inertia, the subspace follows it
+  const int n_for_ss = gi.count >= 0 ? (int)gi.count : n_lambda_est;
+  int nss = o.n_ss > 0 ? o.n_ss : (int)std::max<int64_t>((int64_t)std::ceil(1.5 * std::max(n_for_ss, 1)), n_for_ss + 8);
   nss = (int)std::min<int64_t>(nss, n);
   if (nss > 512) {
     set_error("zolo_solve: subspace size %d above 512", nss);
@@ -2398,6 +2530,12 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   zolo_filter_coeffs co;
   CHK(zolo_filter_plan(o.a_minus, o.a_plus, o.b_minus, o.b_plus, o.r1, o.r2, o.filter_eps, &co));
   st.t_plan = now_s() - t0;
+  st.t_gaps = gi.t_gaps;
+  st.inertia_count = gi.count;
+  st.a_minus = o.a_minus;
+  st.a_plus = o.a_plus;
+  st.b_minus = o.b_minus;
+  st.b_plus = o.b_plus;
   st.t_symbolic = P->t_symbolic;
   st.r1 = co.r1;
   st.r2 = co.r2;
@@ -2619,17 +2757,21 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     o = *opts_in;
   else
     zolo_opts_default(&o);
-  if (std::isnan(o.a_minus) || std::isnan(o.a_plus) || std::isnan(o.b_minus) || std::isnan(o.b_plus)) {
-    set_error("zolo_solve: eigengaps (a_minus, a_plus, b_minus, b_plus) must be given");
+  const int n_nan = std::isnan(o.a_minus) + std::isnan(o.a_plus) + std::isnan(o.b_minus) + std::isnan(o.b_plus);
+  if (n_nan != 0 && n_nan != 4) {
+    set_error("zolo_solve: give all four eigengap ends, or none (NaN) to have them estimated");
     return ZOLO_EINVAL;
   }
+  HIPC(hipSetDevice(ctx->device));
+  GapInfo gi;
+  if (n_nan == 4) CHK(estimate_gaps(ctx, P, a, b, n_lambda_est, &o, &gi, as_stream(stream)));
   if (!(o.a_minus < a && a < o.a_plus && o.b_minus < b && b < o.b_plus)) {
     set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
     return ZOLO_EINVAL;
   }
-  HIPC(hipSetDevice(ctx->device));
-  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
-  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out);
+  if (o.r1 == 0) CHK(choose_r1(&o));
+  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
+  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
 }
 
 extern "C" zolo_status zolo_profile_enable(int on) {
