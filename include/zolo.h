@@ -97,6 +97,9 @@ typedef struct {
   double tol_refine;       /* mixed precision: inner relative residual target at the
                               first GMRES step; step k relaxes it to
                               min(1e-2, tol_refine / outer residual of step k-1)     */
+  int block_cols;          /* > 0: apply the filter to column sub-blocks of at most
+                              this many columns (block GMRES per sub-block; the
+                              Krylov basis then holds block_cols columns), 0 = all */
 } zolo_opts;
 
 typedef struct {
@@ -181,6 +184,12 @@ zolo_status zolo_pencil_info(const zolo_pencil* p, int64_t* n_fronts, int64_t* n
 zolo_status zolo_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colind, const int32_t* grid, int leaf_size,
                           int32_t* perm, double* info);
 /* Nested-dissection permutation: perm[new] = old (host array of n). */
+/* Entries (scalars of the factor type) of one pole's numeric factorization,
+ * from the symbolic analysis: out[0] panels, out[1] L11^-1 blocks, out[2] the
+ * update-block pool (level-scoped), out[3] all update blocks together,
+ * out[4], out[5] per-level temporaries (inverse doubling, solve panels).
+ * LU (complex Hermitian pencils) doubles out[0], out[1], out[4], out[5]. */
+zolo_status zolo_pencil_memory(const zolo_pencil* p, int64_t* out);
 zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm);
 
 /*

@@ -42,7 +42,7 @@ class zolo_opts(ctypes.Structure):
     _fields_ = [("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d), ("r1", _i), ("r2", _i),
                 ("filter_eps", _d), ("n_ss", _i), ("max_subspace_iter", _i), ("max_gmres_iter", _i),
                 ("tol_resid", _d), ("tol_gmres", _d), ("precision", _i), ("seed", ctypes.c_uint64),
-                ("max_refine", _i), ("tol_refine", _d)]
+                ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i)]
 
 
 class zolo_stats(ctypes.Structure):
@@ -97,6 +97,7 @@ _SIGS = {
     "zolo_pencil_info": (_i, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                               ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
     "zolo_pencil_perm": (_i, [_vp, _vp]),
+    "zolo_pencil_memory": (_i, [_vp, _vp]),
     "zolo_symbolic": (_i, [_i64, _vp, _vp, _vp, _i, _vp, _vp]),
     "zolo_filter_plan": (_i, [_d, _d, _d, _d, _i, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
     "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
@@ -251,6 +252,15 @@ class Pencil:
         _check(lib().zolo_pencil_info(self.h, ctypes.byref(nf), ctypes.byref(nl), ctypes.byref(nnz), ctypes.byref(fl),
                                       ctypes.byref(mf)))
         return {"fronts": nf.value, "levels": nl.value, "nnz_l": nnz.value, "flops": fl.value, "max_front": mf.value}
+
+    def memory(self):
+        """Factor-side entry counts of one pole (zolo_pencil_memory)."""
+        import numpy as np
+
+        out = np.zeros(6, dtype=np.int64)
+        _check(lib().zolo_pencil_memory(self.h, _np_ptr(out)))
+        return dict(zip(["panels", "inverses", "update_pool", "update_all", "inv_scratch", "conv_scratch"],
+                        out.tolist()))
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

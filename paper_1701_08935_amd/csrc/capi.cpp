@@ -142,6 +142,7 @@ class DevicePool {
 };
 
 // RAII owner of device allocations (through the cache above)
+constexpr size_t kReserve = (size_t)4 << 30;
 struct DevArena {
   struct Block {
     void* p;
@@ -171,6 +172,10 @@ struct DevArena {
     }
     void* p = DevicePool::get().take(bytes, dev);
     if (!p) {
+      // keep room for the runtime's own allocations (kernel scratch, queues): when
+      // a new block would leave less than kReserve free, return the cache first
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve) DevicePool::get().trim();
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) {
         DevicePool::get().trim();
@@ -321,7 +326,8 @@ struct zolo_pencil {
   std::vector<int> lvl_order;       // fronts ordered by level
   std::vector<int64_t> panel_off, inv_off, upd_off;
   std::vector<int64_t> lvl_panel_begin, lvl_panel_end, lvl_inv_begin, lvl_inv_end, lvl_upd_begin, lvl_upd_end;
-  int64_t panel_total = 0, inv_total = 0, upd_total = 0;
+  int64_t panel_total = 0, inv_total = 0, upd_total = 0;  // upd_total: the level-scoped update pool
+  int64_t upd_sum = 0;                                     // all fronts' update blocks together
   int64_t* asm_dst = nullptr;
   int64_t* asm_src = nullptr;
   int64_t* asm_src_t = nullptr;  // complex pencils: the CSR entry transposed to asm_src's
@@ -630,6 +636,7 @@ extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
   o->seed = 2;
   o->max_refine = 8;
   o->tol_refine = 1e-8;
+  o->block_cols = 0;
   return ZOLO_OK;
 }
 
@@ -776,15 +783,12 @@ zolo_status build_layout(zolo_pencil* P) {
   P->lvl_panel_end.assign(nl, 0);
   P->lvl_inv_begin.assign(nl, 0);
   P->lvl_inv_end.assign(nl, 0);
-  P->lvl_upd_begin.assign(nl, 0);
-  P->lvl_upd_end.assign(nl, 0);
   int64_t po = 0, io = 0, uo = 0;
   P->inv_scratch = 0;
   P->conv_scratch = 0;
   for (int L = 0; L < nl; ++L) {
     P->lvl_panel_begin[L] = po;
     P->lvl_inv_begin[L] = io;
-    P->lvl_upd_begin[L] = uo;
     int64_t scr = 0;
     for (int f : S.levels[L]) {
       const Front& F = S.fronts[f];
@@ -793,7 +797,7 @@ zolo_status build_layout(zolo_pencil* P) {
       po += k * F.ns;
       P->inv_off[f] = io;
       io += (int64_t)F.ns * F.ns;
-      P->upd_off[f] = uo;
+      P->upd_off[f] = uo;  // within the level's range for now (placed below)
       uo += (int64_t)F.nb * F.nb;
       P->lvl_order.push_back(f);
     }
@@ -819,11 +823,48 @@ zolo_status build_layout(zolo_pencil* P) {
     P->conv_scratch = std::max(P->conv_scratch, cv);
     P->lvl_panel_end[L] = po;
     P->lvl_inv_end[L] = io;
-    P->lvl_upd_end[L] = uo;
   }
   P->panel_total = po;
   P->inv_total = io;
-  P->upd_total = uo;
+  P->upd_sum = uo;
+  // Update-block pool.  The update block of a front of level L is written at
+  // level L (the extend-add scatters into it, then the Schur update adds to it)
+  // and read at its parent's level, after which it is dead.  Each level gets one
+  // contiguous range (cleared when the level starts), placed first-fit among
+  // the ranges still live, and released after the last level that reads any of
+  // its blocks, so the pool holds a few levels' blocks instead of all of them.
+  {
+    struct Rng {
+      int64_t off, len;
+      int last;
+    };
+    std::vector<Rng> live;
+    int64_t pool = 0;
+    P->lvl_upd_begin.assign(nl, 0);
+    P->lvl_upd_end.assign(nl, 0);
+    for (int L = 0; L < nl; ++L) {
+      int64_t len = 0;
+      int last = L;
+      for (int f : S.levels[L]) {
+        len += (int64_t)S.fronts[f].nb * S.fronts[f].nb;
+        if (S.fronts[f].parent >= 0) last = std::max(last, (int)S.fronts[S.fronts[f].parent].level);
+      }
+      live.erase(std::remove_if(live.begin(), live.end(), [L](const Rng& r) { return r.last < L; }), live.end());
+      std::sort(live.begin(), live.end(), [](const Rng& x, const Rng& y) { return x.off < y.off; });
+      int64_t base = 0;
+      for (const Rng& r : live) {
+        if (r.off - base >= len) break;
+        base = std::max(base, r.off + r.len);
+      }
+      const int64_t lvl0 = P->upd_off[S.levels[L].empty() ? 0 : S.levels[L][0]];
+      for (int f : S.levels[L]) P->upd_off[f] = P->upd_off[f] - lvl0 + base;
+      P->lvl_upd_begin[L] = base;
+      P->lvl_upd_end[L] = base + len;
+      if (len > 0) live.push_back({base, len, last});
+      pool = std::max(pool, base + len);
+    }
+    P->upd_total = pool;
+  }
   // assembly lists in level order
   std::vector<int64_t> dst, src;
   P->lvl_asm_begin.assign(nl, 0);
@@ -1087,6 +1128,20 @@ extern "C" zolo_status zolo_symbolic(int64_t n, const int64_t* rowptr, const int
     info[6] = (double)S.struct_total;
     info[7] = S.flops;
   }
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_pencil_memory(const zolo_pencil* p, int64_t* out) {
+  if (!p || !out) {
+    set_error("zolo_pencil_memory: null argument");
+    return ZOLO_EINVAL;
+  }
+  out[0] = p->panel_total;
+  out[1] = p->inv_total;
+  out[2] = p->upd_total;
+  out[3] = p->upd_sum;
+  out[4] = p->inv_scratch;
+  out[5] = p->conv_scratch;
   return ZOLO_OK;
 }
 
@@ -1460,7 +1515,6 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
     HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
     HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
     HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
-    HIPC(hipMemsetAsync(upd, 0, sizeof(T) * P->upd_total, s));
     if (lu) {
       HIPC(hipMemsetAsync(pole->upanel, 0, sizeof(T) * P->panel_total, s));
       HIPC(hipMemsetAsync(pole->uinv, 0, sizeof(T) * P->inv_total, s));
@@ -1476,6 +1530,8 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
     case 0: {
       prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
       const int64_t na = P->lvl_asm_end[L] - P->lvl_asm_begin[L];
+      if (P->lvl_upd_end[L] > P->lvl_upd_begin[L])  // this level's update blocks start from zero
+        HIPC(hipMemsetAsync(upd + P->lvl_upd_begin[L], 0, sizeof(T) * (P->lvl_upd_end[L] - P->lvl_upd_begin[L]), s));
       if (lu) {
         // asm_src holds the CSR entry (j, i) for the lower position (i, j) (equal for symmetric
         // matrices); the L panel takes (i, j) itself, the transposed U panel takes (j, i)
@@ -1677,27 +1733,39 @@ extern "C" zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* P, const double*
     }
   HIPC(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
-  zolo_filter_coeffs co{};
-  co.r1 = nshift;
-  co.r2 = 1;
-  for (int k = 0; k < nshift; ++k) co.sigma_hat_re[k] = sigmas[k];
-  std::unique_ptr<zolo_factors> F(new zolo_factors());
-  F->P = P;
-  F->co = co;
-  F->precision = ZOLO_PREC_FP64;
-  zolo_status rc = factor_all<zd>(F.get(), P, &co, &F->pd, s);
-  if (rc == ZOLO_EBREAKDOWN) {
-    set_error("zolo_inertia: zero pivot (a shift is numerically an eigenvalue); move the shift slightly");
-    return rc;
-  }
-  CHK(rc);
+  // shifts factored together: as many as 80% of the free device memory holds
+  const int64_t lu = P->cplx() ? 2 : 1;
+  const int64_t per_shift =
+      (int64_t)sizeof(zd) * (lu * (P->panel_total + P->inv_total + P->n) + P->upd_total +
+                             lu * (P->inv_scratch + P->conv_scratch));
+  size_t free_b = 0, total_b = 0;
+  HIPC(hipMemGetInfo(&free_b, &total_b));
+  const int group = (int)std::max<int64_t>(1, std::min<int64_t>(nshift, (int64_t)(0.8 * (double)free_b) / per_shift));
   std::vector<zd> d(P->n);
-  for (int k = 0; k < nshift; ++k) {
-    HIPC(hipMemcpy(d.data(), F->pd[k].dvec, sizeof(zd) * P->n, hipMemcpyDeviceToHost));
-    int64_t neg = 0;
-    for (const zd& v : d) neg += v.re < 0.0;
-    counts[k] = neg;
+  for (int k0 = 0; k0 < nshift; k0 += group) {
+    const int ng = std::min(group, nshift - k0);
+    zolo_filter_coeffs co{};
+    co.r1 = ng;
+    co.r2 = 1;
+    for (int k = 0; k < ng; ++k) co.sigma_hat_re[k] = sigmas[k0 + k];
+    std::unique_ptr<zolo_factors> F(new zolo_factors());
+    F->P = P;
+    F->co = co;
+    F->precision = ZOLO_PREC_FP64;
+    zolo_status rc = factor_all<zd>(F.get(), P, &co, &F->pd, s);
+    if (rc == ZOLO_EBREAKDOWN) {
+      set_error("zolo_inertia: zero pivot (a shift is numerically an eigenvalue); move the shift slightly");
+      return rc;
+    }
+    CHK(rc);
+    for (int k = 0; k < ng; ++k) {
+      HIPC(hipMemcpy(d.data(), F->pd[k].dvec, sizeof(zd) * P->n, hipMemcpyDeviceToHost));
+      int64_t neg = 0;
+      for (const zd& v : d) neg += v.re < 0.0;
+      counts[k0 + k] = neg;
+    }
   }
+  DevicePool::get().trim();  // the shifts' factors are one-off: give their memory back
   return ZOLO_OK;
 }
 
@@ -2422,13 +2490,15 @@ extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int
 namespace {
 // Algorithm 1 on blocks of scalar VT (double: real pencils, zd: complex Hermitian pencils)
 // Eigengaps when the caller gives none (Alg. 2, line 1; the paper leaves the
-// estimate open).  Inertia counts at a - d_a, a + d_a, b - d_b, b + d_b (and at
-// a, b for the exact count) find eigenvalue-free intervals around a and b: the
-// half-widths start at a quarter of the mean eigenvalue spacing in (a, b) and a
-// side whose interval holds an eigenvalue is shrunk 4x and counted again (at most
-// 8 rounds).  No eigenvalue below a + d_a makes a_- = -inf, none above b - d_b
-// makes b_+ = +inf.  Narrower gaps than the true ones are safe: the filter is
-// planned on a wider transition band.
+// estimate open).  Inertia counts nu(x) (eigenvalues below x) find
+// eigenvalue-free intervals on each side of a and of b separately:
+// (a - l, a) is free when nu(a - l) = nu(a), (a, a + u) when nu(a + u) = nu(a),
+// and likewise at b.  Each half-width starts at half the mean eigenvalue
+// spacing in (a, b) and is halved (and counted again) while its side holds an
+// eigenvalue, at most 10 times; all pending sides are counted together.  No
+// eigenvalue below a - l makes a_- = -inf, none above b + u makes b_+ = +inf.
+// Gaps narrower than the true ones are safe (the filter is planned on a wider
+// transition band); they only raise the filter degree.
 struct GapInfo {
   int64_t count = -1;  // eigenvalues in (a, b) by inertia, -1 if not computed
   double t_gaps = 0.0;
@@ -2438,55 +2508,54 @@ zolo_status estimate_gaps(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int
                           hipStream_t s) {
   const double t0 = now_s();
   const double spacing = (b - a) / std::max(n_est, 1);
-  double da = 0.25 * spacing, db = 0.25 * spacing;
-  bool ok_a = false, ok_b = false;
+  // sides: 0 = below a, 1 = above a, 2 = below b, 3 = above b
+  double hw[4] = {0.5 * spacing, 0.5 * spacing, 0.5 * spacing, 0.5 * spacing};
+  bool ok[4] = {false, false, false, false};
+  int64_t nu_side[4] = {0, 0, 0, 0};
   int64_t nu_a = -1, nu_b = -1;
-  for (int round = 0; round < 8 && !(ok_a && ok_b); ++round) {
+  for (int round = 0; round < 11 && !(ok[0] && ok[1] && ok[2] && ok[3]); ++round) {
     std::vector<double> sh;
+    std::vector<int> who;
     if (round == 0) {
       sh.push_back(a);
       sh.push_back(b);
+      who.push_back(-1);
+      who.push_back(-2);
     }
-    const int ia = (int)sh.size();
-    if (!ok_a) {
-      sh.push_back(a - da);
-      sh.push_back(a + da);
-    }
-    const int ib = (int)sh.size();
-    if (!ok_b) {
-      sh.push_back(b - db);
-      sh.push_back(b + db);
-    }
+    for (int q = 0; q < 4; ++q)
+      if (!ok[q]) {
+        const double x = (q < 2 ? a : b) + (q % 2 ? hw[q] : -hw[q]);
+        sh.push_back(x);
+        who.push_back(q);
+      }
     std::vector<int64_t> cnt(sh.size());
     CHK(zolo_inertia(ctx, P, sh.data(), (int)sh.size(), cnt.data(), s));
-    if (round == 0) {
-      nu_a = cnt[0];
-      nu_b = cnt[1];
+    for (size_t i = 0; i < sh.size(); ++i) {
+      if (who[i] == -1) nu_a = cnt[i];
+      if (who[i] == -2) nu_b = cnt[i];
     }
-    if (!ok_a) {
-      if (cnt[ia] == cnt[ia + 1]) {
-        ok_a = true;
-        o->a_minus = cnt[ia] == 0 ? -INFINITY : a - da;
-        o->a_plus = a + da;
+    for (size_t i = 0; i < sh.size(); ++i) {
+      const int q = who[i];
+      if (q < 0) continue;
+      const int64_t ref = q < 2 ? nu_a : nu_b;
+      if (cnt[i] == ref) {
+        ok[q] = true;
+        nu_side[q] = cnt[i];
       } else {
-        da *= 0.25;
-      }
-    }
-    if (!ok_b) {
-      if (cnt[ib] == cnt[ib + 1]) {
-        ok_b = true;
-        o->b_minus = b - db;
-        o->b_plus = cnt[ib] == P->n ? INFINITY : b + db;
-      } else {
-        db *= 0.25;
+        hw[q] *= 0.5;
       }
     }
   }
-  if (!ok_a || !ok_b) {
-    set_error("eigengap estimate: an eigenvalue lies within %.3g of %s", ok_a ? db : da, ok_a ? "b" : "a");
-    return ZOLO_EGAP;
-  }
-  if (std::isinf(o->a_minus) && std::isinf(o->b_plus)) o->b_plus = b + db;  // at most one infinite end
+  for (int q = 0; q < 4; ++q)
+    if (!ok[q]) {
+      set_error("eigengap estimate: an eigenvalue lies within %.3g of %s", hw[q], q < 2 ? "a" : "b");
+      return ZOLO_EGAP;
+    }
+  o->a_minus = nu_side[0] == 0 ? -INFINITY : a - hw[0];
+  o->a_plus = a + hw[1];
+  o->b_minus = b - hw[2];
+  o->b_plus = nu_side[3] == P->n ? INFINITY : b + hw[3];
+  if (std::isinf(o->a_minus) && std::isinf(o->b_plus)) o->b_plus = b + hw[3];  // at most one infinite end
   gi->count = nu_b - nu_a;
   gi->t_gaps = now_s() - t0;
   return ZOLO_OK;
@@ -2556,8 +2625,22 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   st.factor_flops = P->S.flops;
   const int maxit = o.max_gmres_iter > 0 ? o.max_gmres_iter : 60;
   const double tol_g = o.tol_gmres > 0 ? o.tol_gmres : 1e-10;
-  CHK(ensure_ws(F.get(), nss, maxit));
-  Workspace& ws = *F->ws;
+  // Column sub-blocks of the filter (block GMRES over pb columns at a time):
+  // the filter acts column by column, so splitting the block changes only how
+  // the Krylov spaces are shared, and the basis needs pb, not nss, columns.
+  const int nsub = o.block_cols > 0 ? (nss + o.block_cols - 1) / o.block_cols : 1;
+  const int pb = (nss + nsub - 1) / nsub;
+  CHK(ensure_ws(F.get(), pb, maxit));
+  // products of the Rayleigh-Ritz step: partial sums and descriptors only
+  Workspace ws;
+  ws.partial_len = std::max<int64_t>((int64_t)nss * nss * 256, 1 << 20);
+  CHK(ws.mem.alloc(&ws.partial, ws.partial_len * (ST<VT>::cplx ? 2 : 1)));
+  ws.gdesc_cap = 1024;
+  {
+    char* gd = nullptr;
+    CHK(ws.mem.alloc(&gd, sizeof(GemmDesc<zd>) * (ws.gdesc_cap + 4)));
+    ws.gdesc = gd;
+  }
   // subspace buffers (new ordering)
   DevArena mem;
   VT *Q, *Y, *AY, *BY, *X, *AX, *BX, *At, *Bt, *Cm, *work, *Gx;
@@ -2596,13 +2679,20 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   bool converged = false;
   zolo_status frc = ZOLO_OK;
   for (int it = 1; it <= std::max(1, o.max_subspace_iter); ++it) {
-    zolo_filter_stats fs{};
-    frc = filter_apply_new<VT>(F.get(), Q, nss, nss, Y, nss, tol_g, maxit, &fs, s);
-    if (frc != ZOLO_OK && frc != ZOLO_ENOCONV) return frc;
+    frc = ZOLO_OK;
+    st.n_gmres_last = 0;
+    st.gmres_resid = 0.0;
+    for (int b0 = 0; b0 < nss; b0 += pb) {
+      zolo_filter_stats fs{};
+      const int pc = std::min(pb, nss - b0);
+      zolo_status rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, &fs, s);
+      if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
+      if (rc == ZOLO_ENOCONV) frc = rc;
+      st.n_gmres_total += fs.n_gmres;
+      st.n_gmres_last = std::max(st.n_gmres_last, fs.n_gmres);
+      st.gmres_resid = std::max(st.gmres_resid, fs.worst_resid);
+    }
     st.n_iter = it;
-    st.n_gmres_total += fs.n_gmres;
-    st.n_gmres_last = fs.n_gmres;
-    st.gmres_resid = fs.worst_resid;
     // Rayleigh-Ritz
     {
       prof::Scope ps(ZOLO_PROF_SPMM, 4.0 * P->nnz * nss * (ST<VT>::cplx ? 4 : 1),

@@ -140,13 +140,16 @@ def test_complex_solve_window(ctx, pencil7, start, count, precision):
     assert b_orthonormality(B, Xg) <= 1e-10
 
 
-@pytest.mark.parametrize("n,nss,precision", [(24, 96, 0), (32, 96, 0), (24, 110, 0), (24, 96, 1), (32, 96, 1)])
-def test_complex_window_stored(ctx, n, nss, precision):
+@pytest.mark.parametrize("n,nss,precision,block", [(24, 96, 0, 0), (32, 96, 0, 0), (24, 110, 0, 0), (24, 96, 1, 0),
+                                                   (32, 96, 1, 0), (24, 128, 0, 64), (48, 96, 0, 0), (48, 96, 1, 48)])
+def test_complex_window_stored(ctx, n, nss, precision, block):
     """The complex workload pencils (grid27p n^3, window of 64 near 0, block 96) against the
     oracle's stored window: count = inertia count, eigenvalues 1e-10, residual 1e-8,
     B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors.  With a
     block of 110 the 110 x 110 complex Rayleigh-Ritz Gram matrix (190 KB) is eigensolved
-    from global memory instead of LDS."""
+    from global memory instead of LDS.  With block > 0 the filter runs on column
+    sub-blocks of that width (block GMRES per sub-block).  48^3 is the largest grid of
+    this construction the oracle certifies (shift-invert Lanczos and inertia)."""
     import json
     import os
 
@@ -156,11 +159,11 @@ def test_complex_window_stored(ctx, n, nss, precision):
     if not os.path.exists(path):
         pytest.skip("window fixture not generated")
     w = json.load(open(path))
-    say(f"complex zolo_solve grid27p {n}^3 window 64 block {nss} precision {precision}")
+    say(f"complex zolo_solve grid27p {n}^3 window 64 block {nss} precision {precision} sub-blocks {block}")
     gp = pencils.grid27p(n)
     A, B = gp.scipy()
     P = zolo.Pencil.from_grid(ctx, gp, leaf_size=64)
-    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss, precision=precision)
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=nss, precision=precision, block_cols=block)
     Q0 = pencils.gaussian_block(gp.n, nss, seed=2, complex_=True)
     eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], 64, o, Q0=_dev(Q0))
     say(f"  rc={rc} found={len(eig)} iter={st['n_iter']} gmres={st['n_gmres_total']} resid={st['max_resid']:.2e} "
