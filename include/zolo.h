@@ -83,7 +83,8 @@ typedef struct {
   double a_minus, a_plus, b_minus, b_plus; /* eigengaps; a_minus may be -INF or b_plus +INF;
                               all four NaN: estimated by inertia counts on the device */
   int r1;                  /* number of factorizations (inner order); 0 = fewest
-                              (<= 4) giving an outer modulus l2 >= 0.2             */
+                              (<= 4) giving an outer modulus l2 >= 0.2, and no more
+                              than half the free device memory holds               */
   int r2;                  /* outer order; 0 = smallest r2 with delta0 <= filter_eps */
   double filter_eps;       /* target delta0 when r2 == 0 (Remark after Algorithm 2) */
   int n_ss;                /* subspace size; 0 = ceil(1.5 n_lambda_est)             */
@@ -190,6 +191,13 @@ zolo_status zolo_symbolic(int64_t n, const int64_t* rowptr, const int32_t* colin
  * out[4], out[5] per-level temporaries (inverse doubling, solve panels).
  * LU (complex Hermitian pencils) doubles out[0], out[1], out[4], out[5]. */
 zolo_status zolo_pencil_memory(const zolo_pencil* p, int64_t* out);
+/* Algorithmic real flops of one pole from the symbolic analysis (complex
+ * arithmetic, 8 real flops per complex multiply-add; LU twice LDL^T):
+ * out[0] the elimination of every front (LDL^T: sum of 8 (k^3 - nb^3) / 6 over
+ * fronts of k rows with nb update rows), out[1] the same with the L11^-1
+ * blocks the solves use, out[2] a forward plus backward solve per right-hand
+ * side column (16 nnz(L)). */
+zolo_status zolo_pencil_flops(const zolo_pencil* p, double* out);
 zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm);
 
 /*

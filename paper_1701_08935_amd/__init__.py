@@ -98,6 +98,7 @@ _SIGS = {
                               ctypes.POINTER(_d), ctypes.POINTER(_i64)]),
     "zolo_pencil_perm": (_i, [_vp, _vp]),
     "zolo_pencil_memory": (_i, [_vp, _vp]),
+    "zolo_pencil_flops": (_i, [_vp, _vp]),
     "zolo_symbolic": (_i, [_i64, _vp, _vp, _vp, _i, _vp, _vp]),
     "zolo_filter_plan": (_i, [_d, _d, _d, _d, _i, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
     "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
@@ -252,6 +253,14 @@ class Pencil:
         _check(lib().zolo_pencil_info(self.h, ctypes.byref(nf), ctypes.byref(nl), ctypes.byref(nnz), ctypes.byref(fl),
                                       ctypes.byref(mf)))
         return {"fronts": nf.value, "levels": nl.value, "nnz_l": nnz.value, "flops": fl.value, "max_front": mf.value}
+
+    def flops(self):
+        """Algorithmic flops of one pole (zolo_pencil_flops)."""
+        import numpy as np
+
+        out = np.zeros(3, dtype=np.float64)
+        _check(lib().zolo_pencil_flops(self.h, _np_ptr(out)))
+        return dict(zip(["elimination", "with_inverses", "solve_per_column"], out.tolist()))
 
     def memory(self):
         """Factor-side entry counts of one pole (zolo_pencil_memory)."""

@@ -1145,6 +1145,20 @@ extern "C" zolo_status zolo_pencil_memory(const zolo_pencil* p, int64_t* out) {
   return ZOLO_OK;
 }
 
+extern "C" zolo_status zolo_pencil_flops(const zolo_pencil* p, double* out) {
+  if (!p || !out) {
+    set_error("zolo_pencil_flops: null argument");
+    return ZOLO_EINVAL;
+  }
+  const double lu = p->cplx() ? 2.0 : 1.0;
+  int64_t nnzl = 0;
+  for (const Front& F : p->S.fronts) nnzl += ((int64_t)F.ns + F.nb) * F.ns;
+  out[0] = lu * p->S.elim_flops;
+  out[1] = lu * p->S.flops;
+  out[2] = lu * 16.0 * (double)nnzl;
+  return ZOLO_OK;
+}
+
 extern "C" zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm) {
   if (!p || !perm) {
     set_error("null argument");
@@ -2564,12 +2578,22 @@ zolo_status estimate_gaps(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int
 // r1 = 0 (Remark after Alg. 2 leaves the split open): the fewest inner poles
 // (factorizations, at most 4) whose inner error delta_1 leaves the outer modulus
 // l2 = (1 - delta_1)/(1 + delta_1) >= 0.2, so that the outer shifted systems
-// stay well separated from the spectrum of G and block GMRES needs few steps.
-zolo_status choose_r1(zolo_opts* o) {
-  for (int r1 = 1; r1 <= 4; ++r1) {
+// stay well separated from the spectrum of G and block GMRES needs few steps;
+// at most as many poles as leave half of the free device memory to the solves
+// and the Krylov basis.
+zolo_status choose_r1(const zolo_pencil* P, zolo_opts* o, int nss) {
+  size_t free_b = 0, total_b = 0;
+  int r_mem = 4;
+  if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+    const int maxit = o->max_gmres_iter > 0 ? o->max_gmres_iter : 60;
+    while (r_mem > 1 &&
+           query_bytes_estimate(P, r_mem, nss, maxit, o->precision, o->block_cols) > (int64_t)(0.9 * (double)free_b))
+      --r_mem;
+  }
+  for (int r1 = 1; r1 <= r_mem; ++r1) {
     zolo_filter_coeffs co;
     CHK(zolo_filter_plan(o->a_minus, o->a_plus, o->b_minus, o->b_plus, r1, o->r2, o->filter_eps, &co));
-    if (co.l2 >= 0.2 || r1 == 4) {
+    if (co.l2 >= 0.2 || r1 == r_mem) {
       o->r1 = r1;
       return ZOLO_OK;
     }
@@ -2859,7 +2883,11 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
     return ZOLO_EINVAL;
   }
-  if (o.r1 == 0) CHK(choose_r1(&o));
+  if (o.r1 == 0) {
+    const int n_for_ss = gi.count >= 0 ? (int)gi.count : n_lambda_est;
+    const int nss = o.n_ss > 0 ? o.n_ss : (int)std::max<int64_t>((int64_t)std::ceil(1.5 * std::max(n_for_ss, 1)), n_for_ss + 8);
+    CHK(choose_r1(P, &o, (int)std::min<int64_t>(nss, P->n)));
+  }
   if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
   return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
 }
@@ -2926,18 +2954,20 @@ extern "C" void zolo_result_free(zolo_result* r) { delete r; }
 // ===========================================================================
 namespace zolo {
 
-int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision) {
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols) {
   const int64_t n = P->n;
   const int64_t elem = precision == ZOLO_PREC_FP64 ? 16 : 8;
   const int64_t lu = P->cplx() ? 2 : 1;  // LU: two panels and inverses; K^-1 and K^-H solves
   const int64_t vb = P->cplx() ? 16 : 8;  // bytes per block entry
   const int64_t factors = (int64_t)r1 * lu * (P->panel_total + P->inv_total + n) * elem;
   const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + lu * (P->inv_scratch + P->conv_scratch)) * elem;
-  const int64_t p = nss;
+  // the filter runs on column sub-blocks of p columns
+  const int64_t nsub = block_cols > 0 ? (nss + block_cols - 1) / block_cols : 1;
+  const int64_t p = (nss + nsub - 1) / nsub;
   const int64_t solve = (int64_t)r1 * lu * (6 * n * p) * elem;         // W, U, Xb, t, Y, X of the solve program
   const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * vb  // basis, W, T1, Tb
                          + 2 * (int64_t)r1 * lu * n * p * 16;              // per-pole solutions and residuals
-  const int64_t subspace = 8 * n * p * vb;                                  // Q, Y, AY, BY, X, AX, BX, result
+  const int64_t subspace = 8 * n * (int64_t)nss * vb;                       // Q, Y, AY, BY, X, AX, BX, result
   const int64_t total = factors + std::max(factor_tmp, solve + krylov) + subspace;
   return total + total / 10 + ((int64_t)64 << 20);
 }

@@ -80,7 +80,7 @@ std::vector<zolo_query*> head_batch(zolo_server* S, int* cols) {
 
 size_t batch_bytes(const zolo_query* h, int cols) {
   const int maxit = h->o.max_gmres_iter > 0 ? h->o.max_gmres_iter : 60;
-  return (size_t)zolo::query_bytes_estimate(h->P, std::max(h->o.r1, 1), cols, maxit, h->o.precision);
+  return (size_t)zolo::query_bytes_estimate(h->P, std::max(h->o.r1, 1), cols, maxit, h->o.precision, h->o.block_cols);
 }
 
 void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status rc, zolo_result* res, double t_start,

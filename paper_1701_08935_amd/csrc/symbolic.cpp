@@ -413,6 +413,7 @@ int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, co
   S->panel_entries = S->inv_entries = S->update_entries = S->struct_total = 0;
   S->max_front = 0;
   S->flops = 0.0;
+  S->elim_flops = 0.0;
   for (const Front& F : S->fronts) {
     int64_t k = (int64_t)F.ns + F.nb;
     S->panel_entries += k * F.ns;
@@ -425,6 +426,7 @@ int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, co
     // unit lower diagonal block costs about ns^3/6 complex multiply-adds.
     double kk = (double)k, nbb = (double)F.nb, nss = (double)F.ns;
     S->flops += 8.0 * ((kk * kk * kk - nbb * nbb * nbb) / 6.0) + 8.0 * nss * nss * nss / 6.0;
+    S->elim_flops += 8.0 * ((kk * kk * kk - nbb * nbb * nbb) / 6.0);
   }
   return ZOLO_OK;
 }

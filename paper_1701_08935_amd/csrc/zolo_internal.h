@@ -57,7 +57,8 @@ struct Symbolic {
   int64_t struct_total = 0;    // sum nb
   int64_t max_front = 0;
   int max_children = 0;
-  double flops = 0.0;          // real flops of one complex factorization
+  double flops = 0.0;          // real flops of one complex factorization (with the L11^-1 blocks)
+  double elim_flops = 0.0;     // the elimination alone (complex LDL^T: sum over fronts of 8 (k^3 - nb^3) / 6)
 };
 
 // Build the symbolic structure.  grid may be null.  Returns ZOLO_OK or an error code.
@@ -67,7 +68,7 @@ int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, co
 // For the serving loop: device bytes one query needs at most (factors of r1
 // poles, solve program, Krylov basis of maxit block steps, subspace blocks);
 // a deep copy of a result; the seeded Gaussian start block zolo_solve draws.
-int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision);
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols);
 int64_t pencil_n(const zolo_pencil* P);
 zolo_result* result_clone(const zolo_result* r);
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
