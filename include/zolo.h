@@ -312,10 +312,24 @@ zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, i
  * Errors: ZOLO_EGAP (best results and stats still filled: a Ritz value
  * converged inside a stated eigengap, so the gaps given are wrong),
  * ZOLO_ENOCONV (best results and stats still filled),
- * ZOLO_ESUBSPACE (found >= n_ss - 1), ZOLO_EINVAL.
+ * ZOLO_ESUBSPACE (found >= n_ss - 1 and the inertia count of (a, b) differs), ZOLO_EINVAL.
  */
 zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* p, double a, double b, int n_lambda_est, const zolo_opts* opts,
                        const double* d_Q0, void* stream, zolo_result** out);
+/*
+ * Spectrum slicing (Sec. 1; the independent intervals are the parallel work of
+ * Sec. 3.2): all eigenpairs of (A, B) in (lo, hi), computed as n_slices
+ * adjacent slices of about equal width, each one Algorithm 1 query with its
+ * eigengaps, count and r1 estimated by inertia (opts' gaps and n_ss are
+ * ignored; its r1, precision, tolerances and block_cols apply).  Inner slice
+ * ends are moved off eigenvalues by inertia before the queries run.  The
+ * result joins the slices' pairs in ascending order (stats: sums of the
+ * slices' counts and times, worst residuals).  Errors: as zolo_solve, ZOLO_EGAP
+ * when no slice end can be placed away from the eigenvalues, ZOLO_ENOCONV
+ * (result filled) when the pairs found differ from the inertia count.
+ */
+zolo_status zolo_slice(zolo_ctx* ctx, zolo_pencil* p, double lo, double hi, int n_slices, const zolo_opts* opts,
+                       void* stream, zolo_result** out);
 int64_t zolo_result_count(const zolo_result* r);
 /* ascending eigenvalues, host array of zolo_result_count entries, owned by r */
 const double* zolo_result_eigenvalues(const zolo_result* r);

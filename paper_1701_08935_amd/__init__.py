@@ -111,6 +111,7 @@ _SIGS = {
     "zolo_apply_G": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
     "zolo_solve": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, _vp, ctypes.POINTER(_vp)]),
+    "zolo_slice": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, ctypes.POINTER(_vp)]),
     "zolo_result_count": (_i64, [_vp]),
     "zolo_result_eigenvalues": (ctypes.POINTER(_d), [_vp]),
     "zolo_result_copy_vectors": (_i, [_vp, _vp, _i64, _vp]),
@@ -353,6 +354,33 @@ def zolo_filter_apply(f: Factors, V, tol=1e-10, max_iter=60, allow_noconv=False)
                                    int(max_iter), ctypes.byref(st), _stream()),
            allow=(ZOLO_ENOCONV,) if allow_noconv else ())
     return Y, struct_dict(st)
+
+
+def zolo_slice(ctx: Context, pencil: Pencil, lo, hi, n_slices, opts: zolo_opts = None, allow=(ZOLO_ENOCONV,)):
+    """Spectrum slicing: (eigenvalues, vectors N x count on the device, stats, status) of (lo, hi)."""
+    import torch
+
+    if opts is None:
+        opts = zolo_opts_default()
+    h = _vp()
+    rc = lib().zolo_slice(ctx.h, pencil.h, float(lo), float(hi), int(n_slices), ctypes.byref(opts), _stream(),
+                          ctypes.byref(h))
+    if rc != ZOLO_OK and (rc not in allow or not h):
+        raise ZoloError(rc, lib().zolo_last_error().decode())
+    try:
+        L = lib()
+        cnt = L.zolo_result_count(h)
+        ev = L.zolo_result_eigenvalues(h)
+        eig = [ev[i] for i in range(cnt)]
+        vec = torch.empty((pencil.n, max(cnt, 1)), dtype=torch.complex128 if pencil.cplx else torch.float64,
+                          device=f"cuda:{ctx.device}")
+        if cnt:
+            _check(L.zolo_result_copy_vectors(h, _ptr(vec), vec.stride(0), _stream()))
+        st = zolo_stats()
+        _check(L.zolo_result_stats(h, ctypes.byref(st)))
+    finally:
+        lib().zolo_result_free(h)
+    return eig, vec[:, :cnt], struct_dict(st), rc
 
 
 def zolo_solve(ctx: Context, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None,

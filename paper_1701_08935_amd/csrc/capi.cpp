@@ -2843,9 +2843,23 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   }
   st.t_total = now_s() - t_start;
   *out = R.release();
+  // A subspace (nearly) filled by converged pairs cannot tell whether more lie
+  // in (a, b): then the inertia count decides (computed here when the caller
+  // gave the eigengaps).
   if (cnt >= nss - 1) {
-    set_error("found %d eigenpairs with a subspace of %d: estimate too small", cnt, nss);
-    return ZOLO_ESUBSPACE;
+    int64_t count = gi.count;
+    if (count < 0) {
+      double ab[2] = {a, b};
+      int64_t nu[2];
+      CHK(zolo_inertia(ctx, P, ab, 2, nu, stream));
+      count = nu[1] - nu[0];
+      (*out)->st.inertia_count = count;
+    }
+    if (count != cnt) {
+      set_error("found %d eigenpairs with a subspace of %d, inertia counts %lld: estimate too small", cnt, nss,
+                (long long)count);
+      return ZOLO_ESUBSPACE;
+    }
   }
   if (!converged) {
     set_error("subspace iteration did not reach tol_resid (worst %.3e)", st.max_resid);
@@ -2890,6 +2904,130 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
   }
   if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
   return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
+}
+
+// Spectrum slicing (Sec. 1: the eigenpairs of a long interval, computed as
+// many adjacent intervals, each its own filter; independent, so the natural
+// unit of parallel work): (lo, hi) is cut into n_slices slices of equal width
+// whose inner ends are moved off eigenvalues (an inner end x is kept when
+// (x - d, x + d) holds no eigenvalue by inertia, d a tenth of the mean spacing;
+// else it moves by a third of the spacing, up to 8 tries), every slice is one
+// zolo_solve with its eigengaps and count estimated by inertia, all sharing the
+// pencil's ordering and symbolic analysis, and the results are joined in
+// ascending order.
+extern "C" zolo_status zolo_slice(zolo_ctx* ctx, zolo_pencil* P, double lo, double hi, int n_slices,
+                                  const zolo_opts* opts_in, void* stream, zolo_result** out) {
+  if (!ctx || !P || !out || !(lo < hi) || n_slices < 1 || n_slices > 4096) {
+    set_error("zolo_slice: invalid argument");
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  zolo_opts base;
+  if (opts_in)
+    base = *opts_in;
+  else
+    zolo_opts_default(&base);
+  base.a_minus = base.a_plus = base.b_minus = base.b_plus = NAN;
+  base.n_ss = 0;
+  int64_t ends[2];
+  double lh[2] = {lo, hi};
+  CHK(zolo_inertia(ctx, P, lh, 2, ends, stream));
+  const int64_t total = ends[1] - ends[0];
+  const double spacing = (hi - lo) / (double)std::max<int64_t>(total, 1);
+  std::vector<double> x(n_slices + 1);
+  for (int k = 0; k <= n_slices; ++k) x[k] = lo + (hi - lo) * k / n_slices;
+  x[n_slices] = hi;
+  // inner ends off the eigenvalues
+  std::vector<int> pending;
+  for (int k = 1; k < n_slices; ++k) pending.push_back(k);
+  const double d = 0.1 * spacing;
+  for (int attempt = 0; attempt < 8 && !pending.empty(); ++attempt) {
+    std::vector<double> sh;
+    for (int k : pending) {
+      sh.push_back(x[k] - d);
+      sh.push_back(x[k] + d);
+    }
+    std::vector<int64_t> c(sh.size());
+    for (size_t q0 = 0; q0 < sh.size(); q0 += ZOLO_MAX_R) {
+      const int nq = (int)std::min<size_t>(ZOLO_MAX_R, sh.size() - q0);
+      CHK(zolo_inertia(ctx, P, sh.data() + q0, nq, c.data() + q0, stream));
+    }
+    std::vector<int> still;
+    for (size_t i = 0; i < pending.size(); ++i)
+      if (c[2 * i] != c[2 * i + 1]) {
+        const int k = pending[i];
+        x[k] += (attempt % 2 ? -1.0 : 1.0) * (attempt + 1) * spacing / 3.0;
+        still.push_back(k);
+      }
+    pending.swap(still);
+  }
+  for (int k = 1; k <= n_slices; ++k)
+    if (!(x[k] > x[k - 1]) || (k < n_slices && !(x[k] < hi))) {
+      set_error("zolo_slice: slices too narrow for the eigenvalue spacing (use fewer slices)");
+      return ZOLO_EINVAL;
+    }
+  if (!pending.empty()) {
+    set_error("zolo_slice: could not place a slice end away from the eigenvalues");
+    return ZOLO_EGAP;
+  }
+  std::unique_ptr<zolo_result> R(new zolo_result());
+  R->n = P->n;
+  R->ef = P->cplx() ? 2 : 1;
+  std::vector<std::unique_ptr<zolo_result>> parts;
+  zolo_status worst_rc = ZOLO_OK;
+  zolo_stats& st = R->st;
+  const double t0 = now_s();
+  for (int k = 0; k < n_slices; ++k) {
+    double xx[2] = {x[k], x[k + 1]};
+    int64_t cc[2];
+    CHK(zolo_inertia(ctx, P, xx, 2, cc, stream));
+    if (cc[1] == cc[0]) continue;  // an empty slice
+    zolo_result* r = nullptr;
+    zolo_status rc = zolo_solve(ctx, P, x[k], x[k + 1], (int)(cc[1] - cc[0]), &base, nullptr, stream, &r);
+    if (!r) return rc;
+    if (rc != ZOLO_OK) worst_rc = rc;
+    st.n_iter = std::max(st.n_iter, r->st.n_iter);
+    st.n_gmres_total += r->st.n_gmres_total;
+    st.n_solv += r->st.n_solv;
+    st.n_refine += r->st.n_refine;
+    st.max_resid = std::max(st.max_resid, r->st.max_resid);
+    st.e_lambda_x = std::max(st.e_lambda_x, r->st.e_lambda_x);
+    st.b_orth = std::max(st.b_orth, r->st.b_orth);
+    st.t_factor += r->st.t_factor;
+    st.t_iter += r->st.t_iter;
+    st.t_gaps += r->st.t_gaps;
+    st.r1 = std::max(st.r1, r->st.r1);
+    st.r2 = std::max(st.r2, r->st.r2);
+    R->count += r->count;
+    parts.emplace_back(r);
+  }
+  st.inertia_count = total;
+  st.n_found = (int)R->count;
+  st.norm_a = P->normA;
+  st.norm_b = P->normB;
+  st.t_symbolic = P->t_symbolic;
+  if (R->count > 0) {
+    CHK(R->mem.alloc(&R->vec, (size_t)P->n * R->count * R->ef));
+    const size_t e = sizeof(double) * R->ef;
+    int64_t c0 = 0;
+    for (auto& r : parts) {
+      if (r->count == 0) continue;
+      HIPC(hipMemcpy2DAsync(R->vec + c0 * R->ef, e * R->count, r->vec, e * r->count, e * r->count, P->n,
+                            hipMemcpyDeviceToDevice, s));
+      R->eig.insert(R->eig.end(), r->eig.begin(), r->eig.end());
+      c0 += r->count;
+    }
+    HIPC(hipStreamSynchronize(s));
+  }
+  st.t_total = now_s() - t0;
+  *out = R.release();
+  if (worst_rc != ZOLO_OK) return worst_rc;
+  if ((*out)->count != total) {
+    set_error("zolo_slice: found %lld eigenpairs, inertia counts %lld", (long long)(*out)->count, (long long)total);
+    return ZOLO_ENOCONV;
+  }
+  return ZOLO_OK;
 }
 
 extern "C" zolo_status zolo_profile_enable(int on) {

@@ -15,6 +15,14 @@ Sec. 3.1 and 3.2):
   A_ij = -exp(i theta_ij) for the 26 neighbours j > i, theta ~ U[0, 2 pi),
   A_ji = conj(A_ij); B = I + 0.05 * S27, S27 = (I + 26-neighbour adjacency)/27.
 
+* ``gaussian_wells`` : the 3-D Hamiltonian H = -(1/2) Laplacian + V of the
+  paper's first experiment (Sec. 3.1) on [0,1)^3 with Dirichlet boundaries,
+  n interior points per dimension, spacing h = 1/(n+1), 7-point stencil:
+  A = (1/(2h^2)) (6 I - face adjacency) + diag(V(x_i)), x_i = h (i+1);
+  V(x) = -sum_{k=1..3} d_k exp(-|x - c_k|^2 / rho^2), depths d_k ~ U(0,1],
+  centres c_k ~ U[0,1)^3, rho = 0.2 (the wells' radius); B = I (stored with
+  the stencil's pattern, zero off the diagonal).
+
 Grid index of (x, y, z) on an n^3 grid is x + n*y + n^2*z.
 """
 from __future__ import annotations
@@ -25,6 +33,7 @@ __all__ = [
     "GridPencil",
     "grid7",
     "grid27p",
+    "gaussian_wells",
     "gaussian_block",
     "window_from_eigenvalues",
     "serving_stream",
@@ -146,6 +155,27 @@ def grid27p(n: int, seed_v: int = 0, seed_theta: int = 1, ny: int | None = None,
     a_vals[diag] = v[rows[diag]]
     b_vals = np.where(diag, 1.0 + 0.05 / 27.0, 0.05 / 27.0).astype(np.complex128)
     return GridPencil(N, rowptr, colind, a_vals, b_vals, (n, ny, nz), 27)
+
+
+def gaussian_wells(n: int, seed: int = 0, wells: int = 3, radius: float = 0.2) -> GridPencil:
+    """-(1/2) Laplacian + V with `wells` Gaussian wells (see module docstring);
+    depths and centres drawn with numpy PCG64(seed)."""
+    N = n * n * n
+    rowptr, colind, rows = _pattern(n, n, n, 7)
+    g = np.random.Generator(np.random.PCG64(seed))
+    depth = 1.0 - g.uniform(0.0, 1.0, size=wells)  # in (0, 1]
+    centre = g.uniform(0.0, 1.0, size=(wells, 3))
+    h = 1.0 / (n + 1)
+    idx = np.arange(N, dtype=np.int64)
+    pos = np.stack([idx % n, (idx // n) % n, idx // (n * n)], axis=1).astype(np.float64) * h + h
+    V = np.zeros(N)
+    for k in range(wells):
+        V -= depth[k] * np.exp(-np.sum((pos - centre[k]) ** 2, axis=1) / radius**2)
+    diag = rows == colind
+    s = 0.5 / (h * h)
+    a_vals = np.where(diag, 6.0 * s + V[rows], -s)
+    b_vals = np.where(diag, 1.0, 0.0)
+    return GridPencil(N, rowptr, colind, a_vals.astype(np.float64), b_vals.astype(np.float64), (n, n, n), 7)
 
 
 def gaussian_block(n: int, p: int, seed: int = 2, complex_: bool = False) -> np.ndarray:

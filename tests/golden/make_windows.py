@@ -8,6 +8,7 @@ from the repository root:
     python tests/golden/make_windows.py small       # the small parity pencils
     python tests/golden/make_windows.py serving     # eigenvalue clusters of the serving pencils
     python tests/golden/make_windows.py c3 32       # complex Hermitian 27-point Peierls pencil, 32^3
+    python tests/golden/make_windows.py e1 12 24    # Gaussian-well Hamiltonian, the 88 smallest eigenpairs
 
 Each fixture stores the workload recipe (grid, seeds), the window of
 eigenvalues (ascending, the oracle's values) and the eigengaps
@@ -121,6 +122,46 @@ def c3_window(n=32, n_lambda=64, sigma0=0.0, k=80, verify=True):
     _dump(f"window_grid27p_{n}.json", w)
 
 
+def e1_window(n, k=89, seed_max=64):
+    """The paper's first experiment (Sec. 3.1): -(1/2) Laplacian + Gaussian wells,
+    B = I, the k - 1 = 88 smallest eigenpairs with a_- = -inf, a_+ = lambda_1,
+    b_- = lambda_88, b_+ = lambda_89.  As in the paper, potentials are drawn (seed
+    0, 1, ...) until the relative eigengap delta = min(a_+ - a_-, b_+ - b_-) /
+    (b_- - a_+) = (lambda_89 - lambda_88) / (lambda_88 - lambda_1) lies in
+    [1e-4, 1e-3].  Dense LAPACK up to N = 4096, shift-invert Lanczos below the
+    spectrum (sigma0 = 0) above, with the count checked by inertia."""
+    for seed in range(seed_max):
+        p = pencils.gaussian_wells(n, seed=seed)
+        A, B = p.scipy()
+        t = time.time()
+        if p.n <= 4096:
+            lam, _ = pencil_eigh_lapack(A.toarray(), B.toarray())
+            lam = lam[:k]
+            src = "oracle.dense.pencil_eigh_lapack (LAPACK generalized Hermitian)"
+        else:
+            lam, _ = window_near(A.tocsc(), B.tocsc(), 0.0, k)
+            src = "oracle.sparse.window_near (shift-invert Lanczos below the spectrum, ARPACK)"
+        t_eig = time.time() - t
+        delta = (lam[k - 1] - lam[k - 2]) / (lam[k - 2] - lam[0])
+        print(f"n={n} seed={seed}: delta={delta:.3e} ({t_eig:.1f}s)", flush=True)
+        if 1e-4 <= delta <= 1e-3:
+            break
+    else:
+        raise RuntimeError("no potential with a relative eigengap in [1e-4, 1e-3]")
+    a, b = float(lam[0] - 1.0), float(0.5 * (lam[k - 2] + lam[k - 1]))
+    cnt, t_cnt = None, None
+    if p.n <= 40000:
+        t = time.time()
+        cnt = count_interval(A, B, a, b)
+        t_cnt = time.time() - t
+    w = {"a": a, "b": b, "a_minus": float("-inf"), "a_plus": float(lam[0]), "b_minus": float(lam[k - 2]),
+         "b_plus": float(lam[k - 1]), "n_lambda": k - 1, "delta_lambda": float(delta),
+         "workload": f"gaussian_wells {n}^3 (-1/2 Laplacian + 3 Gaussian wells, B = I), the {k - 1} smallest eigenpairs",
+         "grid": [n, n, n], "seed": seed, "eigenvalues": [float(x) for x in lam[: k - 1]], "neighbours": [float(lam[k - 1])],
+         "inertia_count": cnt, "source": src, "seconds": {"eig": t_eig, "inertia": t_cnt}}
+    _dump(f"window_e1_{n}.json", w)
+
+
 SERVING_GRIDS = [16, 20, 24, 28, 32]
 SERVING_CENTERS = [4.0, 5.5, 7.0, 8.5]
 SERVING_K = 150
@@ -157,6 +198,9 @@ if __name__ == "__main__":
         c1_window()
     elif what == "serving":
         serving_clusters()
+    elif what == "e1":
+        for n in [int(x) for x in sys.argv[2:]] or [12, 24]:
+            e1_window(n)
     elif what == "c3":
         c3_window(n=int(sys.argv[2]) if len(sys.argv) > 2 else 32)
     elif what.startswith("grid"):
