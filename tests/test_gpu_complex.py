@@ -141,15 +141,16 @@ def test_complex_solve_window(ctx, pencil7, start, count, precision):
 
 
 @pytest.mark.parametrize("n,nss,precision,block", [(24, 96, 0, 0), (32, 96, 0, 0), (24, 110, 0, 0), (24, 96, 1, 0),
-                                                   (32, 96, 1, 0), (24, 128, 0, 64), (48, 96, 0, 0), (48, 96, 1, 48)])
+                                                   (32, 96, 1, 0), (24, 128, 0, 64), (48, 96, 0, 0), (48, 96, 1, 48),
+                                                   (64, 96, 0, 0)])
 def test_complex_window_stored(ctx, n, nss, precision, block):
     """The complex workload pencils (grid27p n^3, window of 64 near 0, block 96) against the
     oracle's stored window: count = inertia count, eigenvalues 1e-10, residual 1e-8,
     B-orthonormality 1e-10, and Kato-Temple enclosures from the returned vectors.  With a
     block of 110 the 110 x 110 complex Rayleigh-Ritz Gram matrix (190 KB) is eigensolved
     from global memory instead of LDS.  With block > 0 the filter runs on column
-    sub-blocks of that width (block GMRES per sub-block).  48^3 is the largest grid of
-    this construction the oracle certifies (shift-invert Lanczos and inertia)."""
+    sub-blocks of that width (block GMRES per sub-block).  64^3 is the largest grid of
+    this construction the oracle certifies here (shift-invert Lanczos and inertia)."""
     import json
     import os
 
