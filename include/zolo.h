@@ -129,6 +129,7 @@ typedef struct {
                               -1 when the caller gave the gaps                      */
   double t_gaps;           /* seconds spent estimating the eigengaps                */
   double a_minus, a_plus, b_minus, b_plus;  /* the eigengaps the filter used        */
+  int factors_reused;      /* 1: resident factors of an earlier query were used     */
 } zolo_stats;
 
 typedef struct zolo_ctx zolo_ctx;
@@ -382,16 +383,21 @@ zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out);
  *  - Admission: a query's device memory is estimated before it starts
  *    (factors of its r1 poles from the pencil's symbolic analysis, the block
  *    Krylov basis of max_gmres_iter steps, subspace and solve buffers); queued
- *    queries start in arrival order while the estimates of the running ones
- *    plus the next stay within hbm_budget_bytes (0 = 80% of the free device
- *    memory at creation).  A query whose estimate alone exceeds the budget
- *    fails with ZOLO_ENOMEM.
- *  - Batching: queued queries with the same pencil, interval, eigengaps,
- *    r1, r2 and precision share one filter (the same poles and factors); the
- *    worker that starts the first takes the others with it and runs one
- *    Algorithm 1 on their concatenated start blocks (block GMRES over all
- *    their columns, up to 512).  Each of them receives the eigenpairs of
- *    (a, b) found by that joint run.
+ *    queries start in arrival order while the estimates of the running ones,
+ *    the resident factorizations that cannot be evicted, plus the next stay
+ *    within hbm_budget_bytes (0 = 80% of the free device memory at
+ *    creation).  A query whose estimate alone exceeds the budget fails with
+ *    ZOLO_ENOMEM.
+ *  - Batching: queued queries asking for the same result (same pencil,
+ *    interval, eigengaps, r1, r2, precision, tolerances and limits) are
+ *    answered by one run, with the start block of the member with the
+ *    largest subspace; each receives a copy of its eigenpairs.
+ *  - Residency: a query's factorization stays on the device after it
+ *    finishes and serves later queries of the same filter (pencil, eigengaps,
+ *    r1, r2, filter_eps, precision), one query at a time; resident
+ *    factorizations count against the budget and the least recently used
+ *    idle ones are freed when a query needs their memory.
+ *    zolo_server_get_info reports them (hits: runs that reused one).
  *  - zolo_submit copies opts and the optional host start block (N x n_ss
  *    row-major, n_ss = opts->n_ss or ceil(1.5 n_lambda_est); NULL draws it
  *    from opts->seed) and returns at once.  The pencil must outlive the query.
@@ -415,6 +421,16 @@ zolo_status zolo_submit(zolo_server* srv, zolo_pencil* p, double a, double b, in
                         const double* h_Q0, zolo_query** out);
 zolo_status zolo_wait(zolo_query* q, int timeout_ms, zolo_result** out);
 zolo_status zolo_query_get_info(const zolo_query* q, zolo_query_info* out);
+typedef struct {
+  long long budget_bytes;           /* admission budget                       */
+  long long running_bytes;          /* estimates of the queries running now   */
+  int resident_factors;             /* factorizations kept after their query  */
+  long long resident_bytes;
+  long long factor_hits;            /* runs that used a resident factorization */
+  long long factor_misses;          /* runs that factored                     */
+  int queued;
+} zolo_server_info;
+zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* out);
 /* frees a query handle; waits for the query if it is still queued or running */
 void zolo_query_free(zolo_query* q);
 void zolo_server_destroy(zolo_server* srv);

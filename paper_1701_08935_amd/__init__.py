@@ -53,7 +53,8 @@ class zolo_stats(ctypes.Structure):
                 ("t_total", _d), ("gmres_resid", _d), ("norm_a", _d), ("norm_b", _d), ("r1", _i), ("r2", _i),
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
                 ("nnz_l", ctypes.c_longlong), ("factor_flops", _d), ("inertia_count", ctypes.c_longlong),
-                ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d)]
+                ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d),
+                ("factors_reused", _i)]
 
 
 class zolo_kernel_profile(ctypes.Structure):
@@ -67,6 +68,12 @@ PROF_CLASSES = ["spmm", "gemm_factor", "gemm_solve", "gemm_krylov", "front_other
 class zolo_query_info(ctypes.Structure):
     _fields_ = [("t_submit", _d), ("t_start", _d), ("t_end", _d), ("batch", _i), ("est_bytes", ctypes.c_longlong),
                 ("done", _i)]
+
+
+class zolo_server_info(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_longlong), ("running_bytes", ctypes.c_longlong),
+                ("resident_factors", _i), ("resident_bytes", ctypes.c_longlong),
+                ("factor_hits", ctypes.c_longlong), ("factor_misses", ctypes.c_longlong), ("queued", _i)]
 
 
 class zolo_filter_stats(ctypes.Structure):
@@ -126,6 +133,7 @@ _SIGS = {
     "zolo_wait": (_i, [_vp, _i, ctypes.POINTER(_vp)]),
     "zolo_query_get_info": (_i, [_vp, ctypes.POINTER(zolo_query_info)]),
     "zolo_query_free": (None, [_vp]),
+    "zolo_server_get_info": (_i, [_vp, ctypes.POINTER(zolo_server_info)]),
     "zolo_server_destroy": (None, [_vp]),
 }
 
@@ -425,25 +433,39 @@ class Server:
     that share a filter."""
 
     def __init__(self, ctx: Context, slots: int = 4, budget_bytes: int = 0):
+        import weakref
+
         h = _vp()
         _check(lib().zolo_server_create(ctx.h, int(slots), int(budget_bytes), ctypes.byref(h)))
         self.h = h
         self.ctx = ctx
+        self._queries = weakref.WeakSet()
 
     def submit(self, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None) -> "Query":
-        """Q0: optional host numpy array N x n_ss (row-major float64)."""
+        """Q0: optional host numpy array N x n_ss (row-major; float64, or complex128 for
+        complex pencils)."""
         import numpy as np
 
         if opts is None:
             opts = zolo_opts_default()
-        q0 = None if Q0 is None else np.ascontiguousarray(Q0, dtype=np.float64)
+        q0 = None if Q0 is None else np.ascontiguousarray(Q0, dtype=np.complex128 if pencil.cplx else np.float64)
         h = _vp()
         _check(lib().zolo_submit(self.h, pencil.h, float(a), float(b), int(n_lambda_est), ctypes.byref(opts),
                                  None if q0 is None else _np_ptr(q0), ctypes.byref(h)))
-        return Query(h, pencil, self)
+        q = Query(h, pencil, self)
+        self._queries.add(q)
+        return q
+
+    def info(self) -> dict:
+        inf = zolo_server_info()
+        _check(lib().zolo_server_get_info(self.h, ctypes.byref(inf)))
+        return struct_dict(inf)
 
     def close(self):
+        """Frees the queries still held (waiting for them), then the server."""
         if getattr(self, "h", None) and _lib is not None:
+            for q in list(self._queries):
+                q.free()
             _lib.zolo_server_destroy(self.h)
             self.h = None
 
@@ -488,9 +510,10 @@ class Query:
         return struct_dict(inf)
 
     def free(self):
-        if getattr(self, "h", None) and _lib is not None:
+        # a closed server has freed its queries already
+        if getattr(self, "h", None) and _lib is not None and getattr(self.server, "h", None):
             _lib.zolo_query_free(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.free()

@@ -2603,7 +2603,8 @@ zolo_status choose_r1(const zolo_pencil* P, zolo_opts* o, int nss) {
 
 template <typename VT>
 zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est, zolo_opts o,
-                       const double* d_Q0, void* stream, zolo_result** out, const GapInfo& gi) {
+                       const double* d_Q0, void* stream, zolo_result** out, const GapInfo& gi,
+                       zolo_factors* F_in = nullptr, zolo_factors** F_keep = nullptr) {
   hipStream_t s = as_stream(stream);
   const double t_start = now_s() - gi.t_gaps;
   const int64_t n = P->n;
@@ -2638,12 +2639,40 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   st.norm_a = P->normA;
   st.norm_b = P->normB;
   t0 = now_s();
-  zolo_factors* Fp = nullptr;
-  CHK(zolo_factor(ctx, P, &co, o.precision, stream, &Fp));
-  std::unique_ptr<zolo_factors> F(Fp);
+  // resident factors of the same filter (serving) or a new factorization
+  std::unique_ptr<zolo_factors> F_own;
+  zolo_factors* Fu = F_in;
+  if (Fu && (Fu->P != P || Fu->precision != o.precision || Fu->co.r1 != co.r1 || Fu->co.r2 != co.r2 ||
+             Fu->co.a_minus != co.a_minus || Fu->co.a_plus != co.a_plus || Fu->co.b_minus != co.b_minus ||
+             Fu->co.b_plus != co.b_plus))
+    Fu = nullptr;  // not this query's filter: factor anew
+  if (!Fu) {
+    zolo_factors* Fp = nullptr;
+    CHK(zolo_factor(ctx, P, &co, o.precision, stream, &Fp));
+    F_own.reset(Fp);
+    Fu = Fp;
+  } else {
+    st.factors_reused = 1;
+  }
+  Fu->n_solv = Fu->n_refine = 0;
+  Fu->refine_sweeps_max = Fu->refine_missed = 0;
+  Fu->refine_worst = 0.0;
+  struct Keep {
+    std::unique_ptr<zolo_factors>& own;
+    zolo_factors** keep;
+    ~Keep() {
+      if (keep && own) *keep = own.release();
+    }
+  } keep_guard{F_own, F_keep};
+  zolo_factors* const F_ptr = Fu;
+  struct FRef {
+    zolo_factors* p;
+    zolo_factors* get() const { return p; }
+    zolo_factors* operator->() const { return p; }
+  } F{F_ptr};
   F->max_refine = o.max_refine > 0 ? o.max_refine : 8;
   F->tol_refine = o.tol_refine > 0 ? o.tol_refine : 1e-8;
-  st.t_factor = now_s() - t0;
+  st.t_factor = st.factors_reused ? 0.0 : now_s() - t0;
   st.factor_bytes = F->bytes;
   st.nnz_l = P->S.panel_entries + P->S.inv_entries;
   st.factor_flops = P->S.flops;
@@ -2874,8 +2903,10 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
 }
 }  // namespace
 
-extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
-                                  const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_result** out) {
+namespace zolo {
+zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
+                           const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_factors* F_in,
+                           zolo_factors** F_keep, zolo_result** out) {
   if (!ctx || !P || !out || !(a < b) || n_lambda_est < 0) {
     set_error("zolo_solve: invalid argument");
     return ZOLO_EINVAL;
@@ -2902,8 +2933,17 @@ extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, doubl
     const int nss = o.n_ss > 0 ? o.n_ss : (int)std::max<int64_t>((int64_t)std::ceil(1.5 * std::max(n_for_ss, 1)), n_for_ss + 8);
     CHK(choose_r1(P, &o, (int)std::min<int64_t>(nss, P->n)));
   }
-  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
-  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi);
+  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
+  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
+}
+
+const zolo_filter_coeffs* factors_coeffs(const zolo_factors* F) { return &F->co; }
+int64_t factors_bytes(const zolo_factors* F) { return F->bytes; }
+}  // namespace zolo
+
+extern "C" zolo_status zolo_solve(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
+                                  const zolo_opts* opts_in, const double* d_Q0, void* stream, zolo_result** out) {
+  return zolo::solve_resident(ctx, P, a, b, n_lambda_est, opts_in, d_Q0, stream, nullptr, nullptr, out);
 }
 
 // Spectrum slicing (Sec. 1: the eigenpairs of a long interval, computed as
@@ -3111,6 +3151,7 @@ int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, i
 }
 
 int64_t pencil_n(const zolo_pencil* P) { return P->n; }
+bool pencil_cplx(const zolo_pencil* P) { return P->cplx(); }
 
 zolo_result* result_clone(const zolo_result* r) {
   std::unique_ptr<zolo_result> c(new zolo_result());

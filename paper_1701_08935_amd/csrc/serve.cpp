@@ -1,8 +1,10 @@
 // Serving loop: queued interval queries on resident pencils, admitted by a
 // device-memory estimate, run by worker threads that each own a HIP stream
-// (so queries overlap on the GPU), with queries that share a filter batched
-// into one joint Algorithm 1 run.  The arithmetic is zolo_solve's; this file
-// only schedules it.
+// (so queries overlap on the GPU).  Queued queries asking for the same result
+// (same pencil, interval, filter and tolerances) are answered by one run;
+// factorizations stay resident after their query and serve later queries of
+// the same filter (least recently used evicted first when admission needs the
+// memory).  The arithmetic is zolo_solve's; this file only schedules it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +14,7 @@
 #include <deque>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -39,7 +42,20 @@ struct zolo_query {
   bool done = false;
   zolo_status rc = ZOLO_OK;
   zolo_result* res = nullptr;
+  std::string err;  // the worker's error message
   zolo_query_info info{};
+};
+
+// a resident factorization: the filter it belongs to, in use by at most one
+// query at a time
+struct FactorEntry {
+  zolo_pencil* P = nullptr;
+  double am = 0, ap = 0, bm = 0, bp = 0, eps = 0;
+  int r1 = 0, r2 = 0, prec = 0;
+  zolo_factors* F = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+  double last = 0.0;
 };
 
 struct zolo_server {
@@ -51,17 +67,48 @@ struct zolo_server {
   std::deque<zolo_query*> queue;
   bool stop = false;
   std::vector<std::thread> workers;
+  std::vector<FactorEntry> fcache;  // resident factorizations (guarded by m)
+  size_t cached = 0;                // their bytes
+  long long hits = 0, misses = 0;
 };
 
 namespace {
 
+// the same result: pencil, interval, filter, precision and every tolerance and limit
 bool same_filter(const zolo_query* x, const zolo_query* y) {
-  return x->P == y->P && x->a == y->a && x->b == y->b && x->o.a_minus == y->o.a_minus && x->o.a_plus == y->o.a_plus &&
-         x->o.b_minus == y->o.b_minus && x->o.b_plus == y->o.b_plus && x->o.r1 == y->o.r1 && x->o.r2 == y->o.r2 &&
-         x->o.filter_eps == y->o.filter_eps && x->o.precision == y->o.precision;
+  const zolo_opts &u = x->o, &v = y->o;
+  auto eq = [](double p, double q) { return p == q || (std::isnan(p) && std::isnan(q)); };
+  return x->P == y->P && x->a == y->a && x->b == y->b && eq(u.a_minus, v.a_minus) && eq(u.a_plus, v.a_plus) &&
+         eq(u.b_minus, v.b_minus) && eq(u.b_plus, v.b_plus) && u.r1 == v.r1 && u.r2 == v.r2 &&
+         u.filter_eps == v.filter_eps && u.precision == v.precision && u.tol_resid == v.tol_resid &&
+         u.tol_gmres == v.tol_gmres && u.max_subspace_iter == v.max_subspace_iter &&
+         u.max_gmres_iter == v.max_gmres_iter && u.max_refine == v.max_refine && u.tol_refine == v.tol_refine &&
+         u.block_cols == v.block_cols;
 }
 
-// The head query and the queued queries sharing its filter, in arrival order.
+bool entry_matches(const FactorEntry& e, const zolo_query* q) {
+  const zolo_opts& o = q->o;
+  return e.P == q->P && e.am == o.a_minus && e.ap == o.a_plus && e.bm == o.b_minus && e.bp == o.b_plus &&
+         e.r1 == o.r1 && e.r2 == o.r2 && e.eps == o.filter_eps && e.prec == o.precision;
+}
+
+// free least recently used idle factorizations until `need` more bytes fit
+// beside the running queries and the remaining cache (caller holds S->m)
+void evict_for(zolo_server* S, size_t need, std::vector<zolo_factors*>* to_free) {
+  while (S->in_use + S->cached + need > S->budget) {
+    int lru = -1;
+    for (int i = 0; i < (int)S->fcache.size(); ++i)
+      if (!S->fcache[i].busy && (lru < 0 || S->fcache[i].last < S->fcache[lru].last)) lru = i;
+    if (lru < 0) return;
+    S->cached -= S->fcache[lru].bytes;
+    to_free->push_back(S->fcache[lru].F);
+    S->fcache.erase(S->fcache.begin() + lru);
+  }
+}
+
+// The head query and the queued queries asking for the same result, in
+// arrival order; they are answered by one run with the largest subspace among
+// them (cols).
 std::vector<zolo_query*> head_batch(zolo_server* S, int* cols) {
   std::vector<zolo_query*> batch;
   zolo_query* h = S->queue.front();
@@ -69,9 +116,9 @@ std::vector<zolo_query*> head_batch(zolo_server* S, int* cols) {
   int c = h->nss;
   for (size_t i = 1; i < S->queue.size(); ++i) {
     zolo_query* q = S->queue[i];
-    if (same_filter(q, h) && c + q->nss <= kMaxJointColumns) {
+    if (same_filter(q, h)) {
       batch.push_back(q);
-      c += q->nss;
+      c = std::max(c, q->nss);
     }
   }
   *cols = c;
@@ -86,6 +133,7 @@ size_t batch_bytes(const zolo_query* h, int cols) {
 void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status rc, zolo_result* res, double t_start,
             size_t est) {
   const double t_end = now_s();
+  const std::string err = rc == ZOLO_OK ? std::string() : std::string(zolo_last_error());
   std::vector<zolo_result*> out(batch.size(), nullptr);
   if (res) {
     out[0] = res;
@@ -96,6 +144,7 @@ void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status r
     zolo_query* q = batch[i];
     q->rc = (res && !out[i]) ? ZOLO_ENOMEM : rc;
     q->res = out[i];
+    q->err = err;
     q->info.t_start = t_start;
     q->info.t_end = t_end;
     q->info.batch = (int)batch.size();
@@ -115,6 +164,8 @@ void worker(zolo_server* S) {
     int cols = 0;
     size_t est = 0;
     bool too_big = false;
+    zolo_factors* F_in = nullptr;
+    std::vector<zolo_factors*> to_free;
     {
       std::unique_lock<std::mutex> lk(S->m);
       S->cv_work.wait(lk, [&] {
@@ -122,7 +173,11 @@ void worker(zolo_server* S) {
         int c = 0;
         std::vector<zolo_query*> b = head_batch(S, &c);
         const size_t e = batch_bytes(b[0], c);
-        return e > S->budget || S->in_use + e <= S->budget;
+        if (e > S->budget || S->in_use + S->cached + e <= S->budget) return true;
+        size_t idle = 0;  // resident factorizations that could be evicted
+        for (const FactorEntry& fe : S->fcache)
+          if (!fe.busy) idle += fe.bytes;
+        return S->in_use + S->cached - idle + e <= S->budget;
       });
       if (S->queue.empty()) break;  // stop requested and nothing left
       batch = head_batch(S, &cols);
@@ -131,52 +186,90 @@ void worker(zolo_server* S) {
         too_big = true;
         batch.resize(1);
       } else {
+        evict_for(S, est, &to_free);
         S->in_use += est;
+        for (FactorEntry& fe : S->fcache)
+          if (!fe.busy && entry_matches(fe, batch[0])) {
+            fe.busy = true;
+            F_in = fe.F;
+            ++S->hits;
+            break;
+          }
+        if (!F_in) ++S->misses;
       }
       for (zolo_query* q : batch) S->queue.erase(std::find(S->queue.begin(), S->queue.end(), q));
     }
+    for (zolo_factors* f : to_free) zolo_factors_free(f);
+    to_free.clear();
     S->cv_work.notify_all();  // the next head may fit beside this one
     const double t_start = now_s();
     if (too_big) {
       finish(S, batch, ZOLO_ENOMEM, nullptr, t_start, est);
       continue;
     }
-    // joint start block: every query's own block, side by side (N x cols row-major)
+    // one run for the batch: the start block of its member with the largest
+    // subspace (its own block, or the Gaussian block of its seed)
     zolo_query* h = batch[0];
+    for (zolo_query* q : batch)
+      if (q->nss > h->nss) h = q;
     const int64_t n = zolo::pencil_n(h->P);
-    std::vector<double> hq((size_t)n * cols);
-    int c0 = 0;
-    for (zolo_query* q : batch) {
-      std::vector<double> g;
-      const std::vector<double>* src = &q->Q0;
-      if (q->Q0.empty()) {
-        zolo::gaussian_block(q->o.seed, (size_t)n * q->nss, &g);
-        src = &g;
-      }
-      for (int64_t i = 0; i < n; ++i)
-        std::copy(src->begin() + i * q->nss, src->begin() + (i + 1) * q->nss, hq.begin() + i * cols + c0);
-      c0 += q->nss;
+    std::vector<double> g;
+    const std::vector<double>* src = &h->Q0;
+    if (h->Q0.empty()) {
+      zolo::gaussian_block(h->o.seed, (size_t)n * h->nss * (zolo::pencil_cplx(h->P) ? 2 : 1), &g);
+      src = &g;
     }
     zolo_status rc = ZOLO_OK;
     zolo_result* res = nullptr;
+    zolo_factors* F_new = nullptr;
     double* dq = nullptr;
-    if (hipMalloc(&dq, sizeof(double) * hq.size()) != hipSuccess) {
+    if (hipMalloc(&dq, sizeof(double) * src->size()) != hipSuccess) {
       rc = ZOLO_ENOMEM;
-    } else if (hipMemcpyAsync(dq, hq.data(), sizeof(double) * hq.size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+    } else if (hipMemcpyAsync(dq, src->data(), sizeof(double) * src->size(), hipMemcpyHostToDevice, st) != hipSuccess) {
       rc = ZOLO_EDEVICE;
     } else {
       zolo_opts o = h->o;
-      o.n_ss = cols;
-      int nl = 0;
-      for (zolo_query* q : batch) nl += q->n_lambda;
-      rc = zolo_solve(S->ctx, h->P, h->a, h->b, nl, &o, dq, st, &res);
+      o.n_ss = h->nss;
+      rc = zolo::solve_resident(S->ctx, h->P, h->a, h->b, h->n_lambda, &o, dq, st, F_in, F_in ? nullptr : &F_new,
+                                &res);
     }
     if (dq) (void)hipFree(dq);
     finish(S, batch, rc, res, t_start, est);
     {
       std::lock_guard<std::mutex> lk(S->m);
       S->in_use -= est;
+      const double t = now_s();
+      for (FactorEntry& fe : S->fcache)
+        if (fe.F == F_in) {
+          fe.busy = false;
+          fe.last = t;
+        }
+      // keep the new factorization resident when it fits beside the running queries
+      if (F_new) {
+        const size_t fb = (size_t)zolo::factors_bytes(F_new);
+        evict_for(S, fb, &to_free);
+        if (S->in_use + S->cached + fb <= S->budget) {
+          FactorEntry fe;
+          fe.P = h->P;
+          fe.am = h->o.a_minus;
+          fe.ap = h->o.a_plus;
+          fe.bm = h->o.b_minus;
+          fe.bp = h->o.b_plus;
+          fe.eps = h->o.filter_eps;
+          fe.r1 = h->o.r1;
+          fe.r2 = h->o.r2;
+          fe.prec = h->o.precision;
+          fe.F = F_new;
+          fe.bytes = fb;
+          fe.last = t;
+          S->fcache.push_back(fe);
+          S->cached += fb;
+          F_new = nullptr;
+        }
+      }
     }
+    if (F_new) zolo_factors_free(F_new);
+    for (zolo_factors* f : to_free) zolo_factors_free(f);
     S->cv_work.notify_all();
   }
   if (st) (void)hipStreamDestroy(st);
@@ -233,7 +326,7 @@ extern "C" zolo_status zolo_submit(zolo_server* srv, zolo_pencil* p, double a, d
     return ZOLO_EINVAL;
   }
   q->nss = nss;
-  if (h_Q0) q->Q0.assign(h_Q0, h_Q0 + (size_t)n * nss);
+  if (h_Q0) q->Q0.assign(h_Q0, h_Q0 + (size_t)n * nss * (zolo::pencil_cplx(p) ? 2 : 1));
   q->info.t_submit = now_s();
   q->info.batch = 0;
   zolo_query* qp = q.release();
@@ -268,7 +361,7 @@ extern "C" zolo_status zolo_wait(zolo_query* q, int timeout_ms, zolo_result** ou
     *out = q->res;
     q->res = nullptr;
   }
-  if (q->rc != ZOLO_OK) zolo::set_error("query finished with status %d", (int)q->rc);
+  if (q->rc != ZOLO_OK) zolo::set_error("query finished with status %d: %s", (int)q->rc, q->err.c_str());
   return q->rc;
 }
 
@@ -293,6 +386,22 @@ extern "C" void zolo_query_free(zolo_query* q) {
   delete q;
 }
 
+extern "C" zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* out) {
+  if (!srv || !out) {
+    zolo::set_error("zolo_server_get_info: null argument");
+    return ZOLO_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(srv->m);
+  out->budget_bytes = (long long)srv->budget;
+  out->running_bytes = (long long)srv->in_use;
+  out->resident_factors = (int)srv->fcache.size();
+  out->resident_bytes = (long long)srv->cached;
+  out->factor_hits = srv->hits;
+  out->factor_misses = srv->misses;
+  out->queued = (int)srv->queue.size();
+  return ZOLO_OK;
+}
+
 extern "C" void zolo_server_destroy(zolo_server* srv) {
   if (!srv) return;
   {
@@ -301,5 +410,6 @@ extern "C" void zolo_server_destroy(zolo_server* srv) {
   }
   srv->cv_work.notify_all();
   for (std::thread& t : srv->workers) t.join();
+  for (FactorEntry& fe : srv->fcache) zolo_factors_free(fe.F);
   delete srv;
 }

@@ -68,8 +68,16 @@ int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, co
 // For the serving loop: device bytes one query needs at most (factors of r1
 // poles, solve program, Krylov basis of maxit block steps, subspace blocks);
 // a deep copy of a result; the seeded Gaussian start block zolo_solve draws.
+// zolo_solve with resident factors of the same filter (F_in, used and kept by
+// the caller) or, with F_in null and F_keep non-null, handing the new
+// factorization to the caller instead of freeing it (serving loop)
+zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_lambda_est,
+                           const zolo_opts* opts, const double* d_Q0, void* stream, zolo_factors* F_in,
+                           zolo_factors** F_keep, zolo_result** out);
+int64_t factors_bytes(const zolo_factors* F);
 int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols);
 int64_t pencil_n(const zolo_pencil* P);
+bool pencil_cplx(const zolo_pencil* P);
 zolo_result* result_clone(const zolo_result* r);
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
 

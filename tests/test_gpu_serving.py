@@ -5,8 +5,10 @@
   each query's eigenvalues match its solo run to 1e-12 relative and the
   oracle's stored values to 1e-10, its eigenvector block spans the same
   space (B-inner products of the two bases: singular values within 1e-8 of 1).
-* Batching: queries that share a filter and wait in the queue behind another
-  query run as one joint Algorithm 1; each gets the full set of eigenpairs.
+* Batching: queries asking for the same result that wait in the queue behind
+  another query are answered by one run; each gets the full set of eigenpairs
+  (also when their options, seeds included, are identical).
+* Residency: a later query of an earlier query's filter reuses its factors.
 * Admission: a budget below one query's estimate fails it with ZOLO_ENOMEM;
   a budget for one query at a time serializes queries.
 * zolo_wait with a zero timeout on a queued query returns ZOLO_ETIMEOUT.
@@ -189,4 +191,61 @@ def test_wait_timeout(ctx, clusters, resident):
     hb.wait()
     h.free()
     hb.free()
+    srv.close()
+
+
+def test_identical_default_queries_answered_once(ctx, clusters, resident):
+    """Two queries with default options (the same seed) for the same interval, queued
+    behind a blocker: one run answers both (batch 2), with a B-orthonormal basis
+    of the right count, not a rank-deficient joint block."""
+    gp16, P16 = resident[16]
+    gp24, P24 = resident[24]
+    A, B = gp16.scipy()
+    lam = np.asarray(clusters["clusters"]["16:4.0"])
+    w = pencils.window_from_eigenvalues(lam, 50, 10)
+    wb = pencils.window_from_eigenvalues(np.asarray(clusters["clusters"]["24:8.5"]), 40, 48)
+    say("identical default-option queries behind a blocker, one slot")
+    srv = zolo.Server(ctx, slots=1)
+    hb = srv.submit(P24, wb["a"], wb["b"], 48, _opts(wb, 76, 1))
+    o = zolo.opts_from_window(w, r1=2, r2=0)
+    hs = [srv.submit(P16, w["a"], w["b"], 10, o) for _ in range(2)]
+    assert hb.wait()[3] == 0
+    ref = lam[50:60]
+    for h in hs:
+        eig, vec, st, rc, info = h.wait()
+        say(f"  rc={rc} found={len(eig)} batch={info['batch']}")
+        assert rc == 0 and info["batch"] == 2 and len(eig) == 10
+        assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) <= 1e-10
+        X = vec.cpu().numpy()
+        assert np.max(np.abs(X.T @ (B @ X) - np.eye(10))) <= 1e-10
+        h.free()
+    hb.free()
+    srv.close()
+
+
+def test_factor_residency(ctx, clusters, resident):
+    """A later query with the filter of an earlier one reuses its resident
+    factorization (server hit, stats.factors_reused) and returns the same
+    eigenvalues; a query with another filter factors anew."""
+    gp, P = resident[20]
+    lam = np.asarray(clusters["clusters"]["20:5.5"])
+    w = pencils.window_from_eigenvalues(lam, 40, 16)
+    w2 = pencils.window_from_eigenvalues(lam, 90, 16)
+    say("residency: the same filter twice, then another filter, one slot")
+    srv = zolo.Server(ctx, slots=1)
+    out = []
+    for i, ww in enumerate((w, w, w2)):
+        h = srv.submit(P, ww["a"], ww["b"], 16, _opts(ww, 28, 300 + i))
+        eig, vec, st, rc, info = h.wait()
+        say(f"  query {i}: rc={rc} found={len(eig)} factors_reused={st['factors_reused']} t_factor={st['t_factor']:.4f}")
+        assert rc == 0 and len(eig) == 16
+        out.append((np.array(eig), st))
+        h.free()
+    inf = srv.info()
+    say(f"  server: {inf}")
+    assert out[0][1]["factors_reused"] == 0 and out[1][1]["factors_reused"] == 1 and out[2][1]["factors_reused"] == 0
+    assert inf["factor_hits"] == 1 and inf["factor_misses"] == 2 and inf["resident_factors"] == 2
+    assert np.max(np.abs(out[1][0] - out[0][0]) / np.abs(out[0][0])) <= 1e-12
+    ref = lam[40:56]
+    assert np.max(np.abs(out[1][0] - ref) / np.abs(ref)) <= 1e-10
     srv.close()
