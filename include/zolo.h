@@ -385,7 +385,7 @@ zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out);
  *    Krylov basis of max_gmres_iter steps, subspace and solve buffers); queued
  *    queries start in arrival order while the estimates of the running ones,
  *    the resident factorizations that cannot be evicted, plus the next stay
- *    within hbm_budget_bytes (0 = 80% of the free device memory at
+ *    within hbm_budget_bytes (0 = 60% of the free device memory at
  *    creation).  A query whose estimate alone exceeds the budget fails with
  *    ZOLO_ENOMEM.
  *  - Batching: queued queries asking for the same result (same pencil,

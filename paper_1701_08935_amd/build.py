@@ -41,6 +41,12 @@ def build(verbose: bool = True) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    # every symbol of the library's own namespace must be defined (a missing
+    # template instantiation would otherwise only show when the library loads)
+    nm = subprocess.run(["nm", "-C", "-u", OUT + ".tmp"], capture_output=True, text=True)
+    missing = [ln.strip() for ln in nm.stdout.splitlines() if "zolo::" in ln]
+    if missing:
+        raise RuntimeError("undefined symbols in libzolo.so:\n" + "\n".join(missing))
     os.replace(OUT + ".tmp", OUT)
     if verbose:
         print("built", OUT)

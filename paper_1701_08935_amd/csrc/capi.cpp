@@ -31,6 +31,10 @@ using namespace zolo;
 
 namespace zolo {
 static thread_local std::string g_err;
+// shifts one zolo_inertia call factors together at most (0 = as many as 80% of
+// the free device memory holds); a serving worker sets it so that its share of
+// the device stays within what admission reserved for it
+static thread_local int g_inertia_cap = 0;
 void set_error(const char* fmt, ...) {
   char buf[1024];
   va_list ap;
@@ -93,11 +97,18 @@ class DevicePool {
       }
     return nullptr;
   }
+  // keeps the block for reuse while the cache stays under kCacheCap (a block
+  // that would exceed it is freed; the caller has synchronized the device)
   void give(void* p, size_t bytes, int dev) {
     std::lock_guard<std::mutex> lk(m_);
+    if (cached_ + bytes > kCacheCap) {
+      (void)hipFree(p);
+      return;
+    }
     free_.insert({bytes, {dev, p}});
     cached_ += bytes;
   }
+  static constexpr size_t kCacheCap = (size_t)48 << 30;
   // Device-memory budget per device (0 = none): blocks handed out to arenas
   // and not yet released count against it.
   bool charge(int dev, size_t bytes) {
@@ -142,7 +153,7 @@ class DevicePool {
 };
 
 // RAII owner of device allocations (through the cache above)
-constexpr size_t kReserve = (size_t)4 << 30;
+constexpr size_t kReserve = (size_t)8 << 30;
 struct DevArena {
   struct Block {
     void* p;
@@ -434,6 +445,7 @@ struct zolo_factors {
   DevArena mem;
   std::vector<PoleMF<zd>> pd;
   std::vector<PoleMF<zf>> pf;
+  std::vector<PoleMF<double>> pr;  // real LDL^T (inertia counts of real pencils at real shifts)
   std::map<int, std::unique_ptr<SolveProg<zd>>> prog_d;
   std::map<int, std::unique_ptr<SolveProg<zf>>> prog_f;
   std::unique_ptr<Workspace> ws;
@@ -1209,6 +1221,7 @@ struct FactorWork {
   StackDesc<T>* dstk = nullptr;
   std::vector<FactorLevelG> lg;
   double sr = 0.0, si = 0.0;
+  bool pivots_only = false;  // inertia counts: D alone, no L11^-1 blocks or solve panels
 };
 
 template <typename T>
@@ -1593,6 +1606,10 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
       run_gemm<T>(dgd, lg[L].schur, s, 0);
       c->stage = 3;
       c->idx = 0;
+      if (fw->pivots_only) {  // the next level needs only the update blocks
+        c->stage = 0;
+        if (++c->L >= nl) c->done = true;
+      }
       break;
     case 3: {
       const size_t I = c->idx;
@@ -1629,12 +1646,13 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
 // all poles: plan each, run each on its own stream, wait, check pivots
 template <typename T>
 zolo_status factor_all(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs* co, std::vector<PoleMF<T>>* poles,
-                       hipStream_t s) {
+                       hipStream_t s, bool pivots_only = false) {
   const int np = co->r1;
   poles->assign(np, PoleMF<T>());
   std::vector<std::unique_ptr<FactorWork<T>>> fw(np);
   for (int j = 0; j < np; ++j) {
     fw[j].reset(new FactorWork<T>());
+    fw[j]->pivots_only = pivots_only;
     CHK(factor_plan<T>(F, P, co->sigma_hat_re[j], co->sigma_hat_im[j], &(*poles)[j], fw[j].get()));
   }
   // pole 0 on the caller's stream, the others on streams of their own that
@@ -1750,12 +1768,14 @@ extern "C" zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* P, const double*
   // shifts factored together: as many as 80% of the free device memory holds
   const int64_t lu = P->cplx() ? 2 : 1;
   const int64_t per_shift =
-      (int64_t)sizeof(zd) * (lu * (P->panel_total + P->inv_total + P->n) + P->upd_total +
-                             lu * (P->inv_scratch + P->conv_scratch));
+      (int64_t)(P->cplx() ? sizeof(zd) : sizeof(double)) * (lu * (P->panel_total + P->inv_total + P->n) +
+                                                              P->upd_total + lu * (P->inv_scratch + P->conv_scratch));
   size_t free_b = 0, total_b = 0;
   HIPC(hipMemGetInfo(&free_b, &total_b));
-  const int group = (int)std::max<int64_t>(1, std::min<int64_t>(nshift, (int64_t)(0.8 * (double)free_b) / per_shift));
-  std::vector<zd> d(P->n);
+  int group = (int)std::max<int64_t>(1, std::min<int64_t>(nshift, (int64_t)(0.8 * (double)free_b) / per_shift));
+  if (g_inertia_cap > 0) group = std::min(group, g_inertia_cap);
+  std::vector<zd> d(P->cplx() ? P->n : 0);
+  std::vector<double> dr(P->cplx() ? 0 : P->n);
   for (int k0 = 0; k0 < nshift; k0 += group) {
     const int ng = std::min(group, nshift - k0);
     zolo_filter_coeffs co{};
@@ -1766,16 +1786,24 @@ extern "C" zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* P, const double*
     F->P = P;
     F->co = co;
     F->precision = ZOLO_PREC_FP64;
-    zolo_status rc = factor_all<zd>(F.get(), P, &co, &F->pd, s);
+    // real pencils at real shifts: a real symmetric LDL^T; complex Hermitian
+    // pencils: LDL^H in complex arithmetic (D real up to rounding)
+    zolo_status rc = P->cplx() ? factor_all<zd>(F.get(), P, &co, &F->pd, s, true)
+                               : factor_all<double>(F.get(), P, &co, &F->pr, s, true);
     if (rc == ZOLO_EBREAKDOWN) {
       set_error("zolo_inertia: zero pivot (a shift is numerically an eigenvalue); move the shift slightly");
       return rc;
     }
     CHK(rc);
     for (int k = 0; k < ng; ++k) {
-      HIPC(hipMemcpy(d.data(), F->pd[k].dvec, sizeof(zd) * P->n, hipMemcpyDeviceToHost));
       int64_t neg = 0;
-      for (const zd& v : d) neg += v.re < 0.0;
+      if (P->cplx()) {
+        HIPC(hipMemcpy(d.data(), F->pd[k].dvec, sizeof(zd) * P->n, hipMemcpyDeviceToHost));
+        for (const zd& v : d) neg += v.re < 0.0;
+      } else {
+        HIPC(hipMemcpy(dr.data(), F->pr[k].dvec, sizeof(double) * P->n, hipMemcpyDeviceToHost));
+        for (double v : dr) neg += v < 0.0;
+      }
       counts[k0 + k] = neg;
     }
   }
@@ -2508,8 +2536,9 @@ namespace {
 // eigenvalue-free intervals on each side of a and of b separately:
 // (a - l, a) is free when nu(a - l) = nu(a), (a, a + u) when nu(a + u) = nu(a),
 // and likewise at b.  Each half-width starts at half the mean eigenvalue
-// spacing in (a, b) and is halved (and counted again) while its side holds an
-// eigenvalue, at most 10 times; all pending sides are counted together.  No
+// spacing in (a, b) (from the count nu(b) - nu(a), taken first) and is halved
+// (and counted again) while its side holds an eigenvalue, at most 10 times;
+// all pending sides are counted together.  No
 // eigenvalue below a - l makes a_- = -inf, none above b + u makes b_+ = +inf.
 // Gaps narrower than the true ones are safe (the filter is planned on a wider
 // transition band); they only raise the filter degree.
@@ -2521,21 +2550,24 @@ struct GapInfo {
 zolo_status estimate_gaps(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_est, zolo_opts* o, GapInfo* gi,
                           hipStream_t s) {
   const double t0 = now_s();
-  const double spacing = (b - a) / std::max(n_est, 1);
+  // the count in (a, b) first: it sets the mean spacing the searches start from
+  int64_t nu_a = -1, nu_b = -1;
+  {
+    double ab[2] = {a, b};
+    int64_t nu[2];
+    CHK(zolo_inertia(ctx, P, ab, 2, nu, s));
+    nu_a = nu[0];
+    nu_b = nu[1];
+  }
+  const double spacing = (b - a) / (double)std::max<int64_t>(nu_b - nu_a, 1);
+  (void)n_est;
   // sides: 0 = below a, 1 = above a, 2 = below b, 3 = above b
   double hw[4] = {0.5 * spacing, 0.5 * spacing, 0.5 * spacing, 0.5 * spacing};
   bool ok[4] = {false, false, false, false};
   int64_t nu_side[4] = {0, 0, 0, 0};
-  int64_t nu_a = -1, nu_b = -1;
   for (int round = 0; round < 11 && !(ok[0] && ok[1] && ok[2] && ok[3]); ++round) {
     std::vector<double> sh;
     std::vector<int> who;
-    if (round == 0) {
-      sh.push_back(a);
-      sh.push_back(b);
-      who.push_back(-1);
-      who.push_back(-2);
-    }
     for (int q = 0; q < 4; ++q)
       if (!ok[q]) {
         const double x = (q < 2 ? a : b) + (q % 2 ? hw[q] : -hw[q]);
@@ -2938,6 +2970,12 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
 }
 
 const zolo_filter_coeffs* factors_coeffs(const zolo_factors* F) { return &F->co; }
+void set_inertia_cap(int shifts) { g_inertia_cap = shifts; }
+int64_t inertia_shift_bytes(const zolo_pencil* P) {
+  const int64_t lu = P->cplx() ? 2 : 1;
+  return (int64_t)(P->cplx() ? sizeof(zd) : sizeof(double)) *
+         (lu * (P->panel_total + P->inv_total + P->n) + P->upd_total + lu * (P->inv_scratch + P->conv_scratch));
+}
 int64_t factors_bytes(const zolo_factors* F) { return F->bytes; }
 }  // namespace zolo
 

@@ -155,5 +155,9 @@ template <>
 __host__ __device__ inline float cvt<float, double>(double x) { return (float)x; }
 template <>
 __host__ __device__ inline double cvt<double, float>(float x) { return (double)x; }
+// real factorizations (real shifts of real pencils, for inertia counts) take the
+// real part of an entry whose imaginary part is zero by construction
+template <>
+__host__ __device__ inline double cvt<double, zd>(zd x) { return x.re; }
 
 }  // namespace zolo

@@ -117,12 +117,14 @@ __device__ inline zf recip(zf a) {
   const float s = 1.0f / (a.re * a.re + a.im * a.im);
   return zf{a.re * s, -a.im * s};
 }
+__device__ inline double recip(double a) { return 1.0 / a; }
 
 // Component-wise select.  Writing c ? a : b on the complex structs makes the
 // compiler select between their addresses, which keeps register arrays of
 // them in scratch memory.
 __device__ inline zd sel(bool c, zd a, zd b) { return zd{c ? a.re : b.re, c ? a.im : b.im}; }
 __device__ inline zf sel(bool c, zf a, zf b) { return zf{c ? a.re : b.re, c ? a.im : b.im}; }
+__device__ inline double sel(bool c, double a, double b) { return c ? a : b; }
 
 template <typename T, bool LU>
 __global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel, T* __restrict__ upanel,
@@ -557,6 +559,7 @@ void front_stack(const StackDesc<T>* d, int nd, int64_t max_cols, hipStream_t s)
   template void front_stack<T>(const StackDesc<T>*, int, int64_t, hipStream_t);
 INST(zd)
 INST(zf)
+INST(double)
 #undef INST
 #define INST_FILL(Ts, T)                                                                                    \
   template void solve_fill<Ts, T>(T*, int64_t, const Ts*, int64_t, int64_t, const T*, int64_t, const int32_t*, \

@@ -52,6 +52,15 @@ struct FactorEntry {
   zolo_pencil* P = nullptr;
   double am = 0, ap = 0, bm = 0, bp = 0, eps = 0;
   int r1 = 0, r2 = 0, prec = 0;
+  // queries that left the eigengaps (and r1) to the library: their interval and
+  // estimate, and the gaps and r1 the library chose (reused instead of a new
+  // inertia search)
+  bool estimated = false;
+  double a = 0, b = 0;
+  int n_est = 0, r1_asked = 0;
+  double e_am = 0, e_ap = 0, e_bm = 0, e_bp = 0;
+  int e_r1 = 0;
+  long long e_count = -1;
   zolo_factors* F = nullptr;
   size_t bytes = 0;
   bool busy = false;
@@ -86,10 +95,15 @@ bool same_filter(const zolo_query* x, const zolo_query* y) {
          u.block_cols == v.block_cols;
 }
 
+bool gaps_estimated(const zolo_opts& o) { return std::isnan(o.a_minus); }
+
 bool entry_matches(const FactorEntry& e, const zolo_query* q) {
   const zolo_opts& o = q->o;
-  return e.P == q->P && e.am == o.a_minus && e.ap == o.a_plus && e.bm == o.b_minus && e.bp == o.b_plus &&
-         e.r1 == o.r1 && e.r2 == o.r2 && e.eps == o.filter_eps && e.prec == o.precision;
+  if (e.P != q->P || e.r2 != o.r2 || e.eps != o.filter_eps || e.prec != o.precision) return false;
+  if (gaps_estimated(o))
+    return e.estimated && e.a == q->a && e.b == q->b && e.n_est == q->n_lambda && e.r1_asked == o.r1;
+  return !e.estimated && e.am == o.a_minus && e.ap == o.a_plus && e.bm == o.b_minus && e.bp == o.b_plus &&
+         e.r1 == o.r1;
 }
 
 // free least recently used idle factorizations until `need` more bytes fit
@@ -125,9 +139,19 @@ std::vector<zolo_query*> head_batch(zolo_server* S, int* cols) {
   return batch;
 }
 
+// shifts a worker's inertia counts (eigengap estimates) factor together
+constexpr int kInertiaShifts = 2;
+
+// device bytes a run needs: the query's estimate (r1 = 0 counted as the
+// largest choice, 4 poles) and, when the library estimates the eigengaps,
+// the inertia factorizations that precede it
 size_t batch_bytes(const zolo_query* h, int cols) {
   const int maxit = h->o.max_gmres_iter > 0 ? h->o.max_gmres_iter : 60;
-  return (size_t)zolo::query_bytes_estimate(h->P, std::max(h->o.r1, 1), cols, maxit, h->o.precision, h->o.block_cols);
+  const int r1 = h->o.r1 > 0 ? h->o.r1 : 4;
+  size_t e = (size_t)zolo::query_bytes_estimate(h->P, r1, cols, maxit, h->o.precision, h->o.block_cols);
+  if (std::isnan(h->o.a_minus))
+    e = std::max(e, (size_t)(kInertiaShifts * zolo::inertia_shift_bytes(h->P)));
+  return e;
 }
 
 void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status rc, zolo_result* res, double t_start,
@@ -157,6 +181,7 @@ void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status r
 
 void worker(zolo_server* S) {
   (void)hipSetDevice(S->device);
+  zolo::set_inertia_cap(kInertiaShifts);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
   for (;;) {
@@ -165,6 +190,7 @@ void worker(zolo_server* S) {
     size_t est = 0;
     bool too_big = false;
     zolo_factors* F_in = nullptr;
+    FactorEntry hit;
     std::vector<zolo_factors*> to_free;
     {
       std::unique_lock<std::mutex> lk(S->m);
@@ -192,6 +218,7 @@ void worker(zolo_server* S) {
           if (!fe.busy && entry_matches(fe, batch[0])) {
             fe.busy = true;
             F_in = fe.F;
+            hit = fe;
             ++S->hits;
             break;
           }
@@ -213,23 +240,48 @@ void worker(zolo_server* S) {
     for (zolo_query* q : batch)
       if (q->nss > h->nss) h = q;
     const int64_t n = zolo::pencil_n(h->P);
-    std::vector<double> g;
-    const std::vector<double>* src = &h->Q0;
-    if (h->Q0.empty()) {
-      zolo::gaussian_block(h->o.seed, (size_t)n * h->nss * (zolo::pencil_cplx(h->P) ? 2 : 1), &g);
-      src = &g;
-    }
     zolo_status rc = ZOLO_OK;
     zolo_result* res = nullptr;
     zolo_factors* F_new = nullptr;
     double* dq = nullptr;
-    if (hipMalloc(&dq, sizeof(double) * src->size()) != hipSuccess) {
+    // eigengaps left to the library and no subspace size given: the subspace
+    // follows the inertia count, and the library draws its own start block
+    const bool free_nss = gaps_estimated(h->o) && h->o.n_ss <= 0 && h->Q0.empty();
+    std::vector<double> g;
+    const std::vector<double>* src = &h->Q0;
+    if (!free_nss && h->Q0.empty()) {
+      zolo::gaussian_block(h->o.seed, (size_t)n * h->nss * (zolo::pencil_cplx(h->P) ? 2 : 1), &g);
+      src = &g;
+    }
+    if (free_nss) {
+      zolo_opts o = h->o;
+      if (F_in && hit.estimated) {
+        o.a_minus = hit.e_am;
+        o.a_plus = hit.e_ap;
+        o.b_minus = hit.e_bm;
+        o.b_plus = hit.e_bp;
+        o.r1 = hit.e_r1;
+        if (hit.e_count >= 0)
+          o.n_ss = (int)std::max<long long>((long long)std::ceil(1.5 * std::max<long long>(hit.e_count, 1)),
+                                            hit.e_count + 8);
+      }
+      rc = zolo::solve_resident(S->ctx, h->P, h->a, h->b, h->n_lambda, &o, nullptr, st, F_in,
+                                F_in ? nullptr : &F_new, &res);
+    } else if (hipMalloc(&dq, sizeof(double) * src->size()) != hipSuccess) {
       rc = ZOLO_ENOMEM;
     } else if (hipMemcpyAsync(dq, src->data(), sizeof(double) * src->size(), hipMemcpyHostToDevice, st) != hipSuccess) {
       rc = ZOLO_EDEVICE;
     } else {
       zolo_opts o = h->o;
       o.n_ss = h->nss;
+      if (F_in && hit.estimated) {  // the gaps and r1 the library chose for this interval before
+        o.a_minus = hit.e_am;
+        o.a_plus = hit.e_ap;
+        o.b_minus = hit.e_bm;
+        o.b_plus = hit.e_bp;
+        o.r1 = hit.e_r1;
+        if (o.n_ss == 0 && hit.n_est > 0) o.n_ss = h->nss;
+      }
       rc = zolo::solve_resident(S->ctx, h->P, h->a, h->b, h->n_lambda, &o, dq, st, F_in, F_in ? nullptr : &F_new,
                                 &res);
     }
@@ -259,6 +311,21 @@ void worker(zolo_server* S) {
           fe.r1 = h->o.r1;
           fe.r2 = h->o.r2;
           fe.prec = h->o.precision;
+          if (gaps_estimated(h->o) && res) {
+            zolo_stats rs{};
+            zolo_result_stats(res, &rs);
+            fe.estimated = true;
+            fe.a = h->a;
+            fe.b = h->b;
+            fe.n_est = h->n_lambda;
+            fe.r1_asked = h->o.r1;
+            fe.e_am = rs.a_minus;
+            fe.e_ap = rs.a_plus;
+            fe.e_bm = rs.b_minus;
+            fe.e_bp = rs.b_plus;
+            fe.e_r1 = rs.r1;
+            fe.e_count = rs.inertia_count;
+          }
           fe.F = F_new;
           fe.bytes = fb;
           fe.last = t;
@@ -294,7 +361,7 @@ extern "C" zolo_status zolo_server_create(zolo_ctx* ctx, int slots, size_t hbm_b
       zolo::set_error("zolo_server_create: hipMemGetInfo failed");
       return ZOLO_EDEVICE;
     }
-    budget = fr / 10 * 8;
+    budget = fr / 10 * 6;
   }
   S->budget = budget;
   for (int i = 0; i < slots; ++i) S->workers.emplace_back(worker, S.get());

@@ -419,6 +419,7 @@ void conj_copy(T* dst, const T* src, int64_t n, hipStream_t s) {
 }
 template void conj_copy<zd>(zd*, const zd*, int64_t, hipStream_t);
 template void conj_copy<zf>(zf*, const zf*, int64_t, hipStream_t);
+template void conj_copy<double>(double*, const double*, int64_t, hipStream_t);
 
 void spmm_cplx(int64_t n, const int64_t* rowptr, const int32_t* colind, const zd* a, const zd* b, const zd* X,
                int64_t ldx, int p, zd* Ya, int64_t ldya, zd* Yb, int64_t ldyb, hipStream_t s) {

@@ -75,6 +75,10 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
                            const zolo_opts* opts, const double* d_Q0, void* stream, zolo_factors* F_in,
                            zolo_factors** F_keep, zolo_result** out);
 int64_t factors_bytes(const zolo_factors* F);
+// the calling thread's cap on the shifts zolo_inertia factors together (0 = none)
+void set_inertia_cap(int shifts);
+// device bytes of one real-shift factorization of the inertia count
+int64_t inertia_shift_bytes(const zolo_pencil* P);
 int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols);
 int64_t pencil_n(const zolo_pencil* P);
 bool pencil_cplx(const zolo_pencil* P);

@@ -37,6 +37,7 @@ __all__ = [
     "gaussian_block",
     "window_from_eigenvalues",
     "serving_stream",
+    "c4_stream",
 ]
 
 
@@ -260,4 +261,41 @@ def serving_queries(clusters: dict, n_queries: int, rate: float, seed: int = 3, 
         w = window_from_eigenvalues(lam, start, nl)
         w["eigenvalues"] = [float(x) for x in lam[start : start + nl]]
         out.append({"t": q["t"], "grid": n, "center": c, "window": w})
+    return out
+
+
+C4_GRIDS = [32, 39, 46, 53, 59, 66, 73, 80]
+
+
+def c4_stream(n_queries: int, rate: float, seed: int = 3, windows_per_pencil: int = 3,
+              lo: float = 0.0, hi: float = 12.6):
+    """The serving workload over eight grid7 pencils 32^3 ... 80^3 (N 32768 - 512000).
+
+    Each pencil gets `windows_per_pencil` intervals (drawn once, PCG64(seed + 1)):
+    a centre uniform over the middle 80% of the spectrum's range [lo, hi] (grid7:
+    about [0, 12.6]) and a width holding about n_lambda eigenvalues, n_lambda
+    log-uniform in [8, 128], from the mean eigenvalue density N / (hi - lo).  The
+    queries (Poisson arrivals at `rate`, PCG64(seed)) pick a pencil uniformly and
+    one of its intervals uniformly, so intervals repeat.  Only (a, b, n_lambda)
+    are given: eigengaps and counts are left to the eigensolver.
+    """
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    wins = {}
+    for n in C4_GRIDS:
+        N = n ** 3
+        for k in range(windows_per_pencil):
+            nl = int(np.rint(np.exp(g.uniform(np.log(8.0), np.log(128.0)))))
+            c = lo + (hi - lo) * g.uniform(0.1, 0.9)
+            w = nl * (hi - lo) / N
+            wins[(n, k)] = {"a": float(c - 0.5 * w), "b": float(c + 0.5 * w), "n_lambda": nl}
+    q = np.random.Generator(np.random.PCG64(seed))
+    gaps = q.exponential(1.0 / rate, size=n_queries)
+    t = np.cumsum(gaps) - gaps[0]
+    pen = q.integers(0, len(C4_GRIDS), size=n_queries)
+    win = q.integers(0, windows_per_pencil, size=n_queries)
+    out = []
+    for i in range(n_queries):
+        n = C4_GRIDS[int(pen[i])]
+        w = wins[(n, int(win[i]))]
+        out.append({"t": float(t[i]), "grid": n, "window_id": int(win[i]), **w})
     return out
