@@ -2971,6 +2971,11 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
 
 const zolo_filter_coeffs* factors_coeffs(const zolo_factors* F) { return &F->co; }
 void set_inertia_cap(int shifts) { g_inertia_cap = shifts; }
+void factors_keep_only(zolo_factors* F) {
+  F->ws.reset();
+  F->prog_d.clear();
+  F->prog_f.clear();
+}
 int64_t inertia_shift_bytes(const zolo_pencil* P) {
   const int64_t lu = P->cplx() ? 2 : 1;
   return (int64_t)(P->cplx() ? sizeof(zd) : sizeof(double)) *

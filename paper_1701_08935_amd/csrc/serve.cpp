@@ -287,6 +287,9 @@ void worker(zolo_server* S) {
     }
     if (dq) (void)hipFree(dq);
     finish(S, batch, rc, res, t_start, est);
+    // a resident factorization keeps only its factors (this worker holds both)
+    if (F_in) zolo::factors_keep_only(F_in);
+    if (F_new) zolo::factors_keep_only(F_new);
     {
       std::lock_guard<std::mutex> lk(S->m);
       S->in_use -= est;

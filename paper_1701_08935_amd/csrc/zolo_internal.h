@@ -75,6 +75,9 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
                            const zolo_opts* opts, const double* d_Q0, void* stream, zolo_factors* F_in,
                            zolo_factors** F_keep, zolo_result** out);
 int64_t factors_bytes(const zolo_factors* F);
+// drops the solve programs and the Krylov workspace, keeping the factors (a
+// resident factorization holds only what its bytes count)
+void factors_keep_only(zolo_factors* F);
 // the calling thread's cap on the shifts zolo_inertia factors together (0 = none)
 void set_inertia_cap(int shifts);
 // device bytes of one real-shift factorization of the inertia count
