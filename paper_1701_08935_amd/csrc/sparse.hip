@@ -64,6 +64,44 @@ __global__ __launch_bounds__(256) void spmm_real_kernel(int64_t n, const int64_t
   }
 }
 
+// The same with 16-byte loads: lane l takes columns 2l and 2l + 1 of a pass of
+// 128, so a 96-column block is one pass of 48 lanes (one load instruction per
+// nonzero instead of two); needs p and the leading dimensions even and the
+// blocks 16-byte aligned.
+template <bool HB>
+__global__ __launch_bounds__(256) void spmm_real2_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                         const int32_t* __restrict__ ci, const double* __restrict__ a,
+                                                         const double* __restrict__ b, const double* __restrict__ X,
+                                                         int64_t ldx, int p, double* __restrict__ Ya, int64_t ldya,
+                                                         double* __restrict__ Yb, int64_t ldyb) {
+  const int64_t i = spmm_row();
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t e0 = rp[i], e1 = rp[i + 1];
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c = c0 + 2 * lane;
+    const bool v = c < p;
+    const int lc = v ? c : p - 2;  // loads stay in the row; unused lanes are not stored
+    double2 sa = {0.0, 0.0}, sb = {0.0, 0.0};
+#pragma unroll 4
+    for (int64_t q = e0; q < e1; ++q) {
+      const double2 x = *reinterpret_cast<const double2*>(X + (int64_t)ci[q] * ldx + lc);
+      const double av = a[q];
+      sa.x = fma(av, x.x, sa.x);
+      sa.y = fma(av, x.y, sa.y);
+      if constexpr (HB) {
+        const double bv = b[q];
+        sb.x = fma(bv, x.x, sb.x);
+        sb.y = fma(bv, x.y, sb.y);
+      }
+    }
+    if (v) {
+      *reinterpret_cast<double2*>(Ya + i * ldya + c) = sa;
+      if constexpr (HB) *reinterpret_cast<double2*>(Yb + i * ldyb + c) = sb;
+    }
+  }
+}
+
 // complex Hermitian pencils: complex values, complex blocks
 template <bool HB>
 __global__ __launch_bounds__(256) void spmm_cplx_kernel(int64_t n, const int64_t* __restrict__ rp,
@@ -449,6 +487,16 @@ void axpy_pair(zd* W, int64_t ldw, const zd* X, const zd* Xc, double wr, double 
 void spmm_real(int64_t n, const int64_t* rp, const int32_t* ci, const double* a, const double* b, const double* X,
                int64_t ldx, int p, double* Ya, int64_t ldya, double* Yb, int64_t ldyb, hipStream_t s) {
   if (n * p == 0) return;
+  auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+  if (p % 2 == 0 && ldx % 2 == 0 && ldya % 2 == 0 && al16(X) && al16(Ya) && (!Yb || (ldyb % 2 == 0 && al16(Yb)))) {
+    if (Yb)
+      hipLaunchKernelGGL(spmm_real2_kernel<true>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+                         ldya, Yb, ldyb);
+    else
+      hipLaunchKernelGGL(spmm_real2_kernel<false>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+                         ldya, Yb, ldyb);
+    return;
+  }
   if (Yb)
     hipLaunchKernelGGL(spmm_real_kernel<true>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
                        ldya, Yb, ldyb);
