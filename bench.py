@@ -395,6 +395,48 @@ def run_e1(n=52, seeds=(2, 3, 4, 5, 6)):
             "paper_table1": PAPER_E1_52}
 
 
+def run_filters(n=64, leaf=128, tol_gmres=1e-8):
+    """Filter ablation (Sec. 2.2, Figs. 2-3) on the c1 pencil and window: the
+    composite filter against Zolo(r) (the inner function alone) and the contour
+    rules CITZ / CIGQ on the circle through a and b, each as one full query
+    (factorizations, subspace iterations, Rayleigh-Ritz) to resid <= 1e-8 with the
+    same start block, verified against the oracle's window."""
+    import numpy as np
+    import torch
+
+    import paper_1701_08935_amd as z
+    import pencils
+
+    w = json.load(open(os.path.join(ROOT, "tests", "golden", f"window_grid7_{n}.json")))
+    gp = pencils.grid7(n)
+    ctx = z.Context(0)
+    P = z.Pencil.from_grid(ctx, gp, leaf_size=leaf)
+    ref = np.array(w["eigenvalues"])
+    Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, 96, seed=2)).to("cuda:0")
+    cases = [("hybrid", z.ZOLO_FILTER_HYBRID, 2), ("zolo", z.ZOLO_FILTER_ZOLO, 2), ("zolo", z.ZOLO_FILTER_ZOLO, 4),
+             ("citz", z.ZOLO_FILTER_TRAPEZOID, 8), ("cigq", z.ZOLO_FILTER_GAUSS, 8)]
+    out = []
+    for name, kind, r in cases:
+        o = z.opts_from_window(w, r1=r, r2=0, n_ss=96, tol_gmres=tol_gmres, filter_kind=kind, max_subspace_iter=60)
+        if kind in (z.ZOLO_FILTER_TRAPEZOID, z.ZOLO_FILTER_GAUSS):
+            o.a_minus = o.a_plus = o.b_minus = o.b_plus = math.nan
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        eig, vec, st, rc = z.zolo_solve(ctx, P, w["a"], w["b"], 64, o, Q0=Q0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        del vec
+        err = float(np.max(np.abs(np.array(eig) - ref) / np.abs(ref))) if len(eig) == len(ref) else float("inf")
+        ok = rc == 0 and len(eig) == len(ref) and st["max_resid"] <= 1e-8 and err <= 1e-10
+        log(f"[bench] filter {name} r={r}: {dt:.3f}s rc={rc} found={len(eig)} iter={st['n_iter']} "
+            f"solves={st['n_solv']} resid={st['max_resid']:.2e}")
+        out.append({"filter": name, "factorizations": r, "s": dt, "verified": ok, "n_iter": st["n_iter"],
+                    "n_gmres": st["n_gmres_total"], "rhs_solves": st["n_solv"], "t_factor_s": st["t_factor"],
+                    "t_iter_s": st["t_iter"], "max_resid": st["max_resid"], "rc": rc})
+    return {"workload": f"grid7 {n}^3 (N={gp.n}), the c1 window of 64 eigenvalues, block 96, one query per filter",
+            "runs": out}
+
+
 def roofline(prof, steps, fp32=False, method_factor_flops=None, kernel=None):
     """Roofline of one kernel class: by default the class with the most summed
     kernel time (the factorization products, which rocprofv3 also ranks first).
@@ -520,6 +562,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the complex Hermitian 96^3 leg")
     ap.add_argument("--no-e1", action="store_true", help="skip the Gaussian-well Hamiltonian 52^3 leg")
+    ap.add_argument("--no-filters", action="store_true", help="skip the filter ablation (Zolo(r), CITZ, CIGQ)")
     ap.add_argument("--c3-grid", type=int, default=96, help="grid of the complex Hermitian leg")
     ap.add_argument("--c3-only", action="store_true", help="run only the complex Hermitian leg (one JSON line)")
     ap.add_argument("--tol-refine", type=float, default=1e-5,
@@ -626,6 +669,8 @@ def main():
         out["c3"] = c3
     if args.config == "c1" and not args.no_e1:
         out["e1"] = run_e1()
+    if args.config == "c1" and not args.no_filters:
+        out["filters"] = run_filters(leaf=args.leaf, tol_gmres=args.tol_gmres)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -77,7 +77,20 @@ typedef struct {
   double M;
   double a[ZOLO_MAX_R], c[ZOLO_MAX_R];         /* c_{2j-1} of Z_2r2(.; l2) */
   double delta_S, delta0;                      /* composite error; delta0 = delta_S/2 */
+  int kind;  /* ZOLO_FILTER_*: 0 the composite Zolotarev filter (outer stage by
+                multi-shift GMRES); otherwise a one-stage filter applied as
+                R(B^-1 A) V = s0 V + s1 G V with G as above */
 } zolo_filter_coeffs;
+
+/* Filters (Sec. 2.2): the paper's composite Zolotarev filter, and the
+ * comparison filters of its Figs. 2-3, applied with one factorization per
+ * conjugate pair of poles on the same kernels. */
+enum {
+  ZOLO_FILTER_HYBRID = 0,     /* (Z_2r2(Zhat_2r1(T(x))) + 1)/2, Algorithm 2       */
+  ZOLO_FILTER_ZOLO = 1,       /* (Zhat_2r(T(x)) + 1)/2: the inner function alone  */
+  ZOLO_FILTER_TRAPEZOID = 2,  /* contour integral, trapezoidal rule (CITZ)        */
+  ZOLO_FILTER_GAUSS = 3       /* contour integral, Gauss-Legendre rule (CIGQ)     */
+};
 
 typedef struct {
   double a_minus, a_plus, b_minus, b_plus; /* eigengaps; a_minus may be -INF or b_plus +INF;
@@ -101,6 +114,8 @@ typedef struct {
   int block_cols;          /* > 0: apply the filter to column sub-blocks of at most
                               this many columns (block GMRES per sub-block; the
                               Krylov basis then holds block_cols columns), 0 = all */
+  int filter_kind;         /* ZOLO_FILTER_*; for the comparison filters r1 is the
+                              number of factorizations (poles per half-plane)      */
 } zolo_opts;
 
 typedef struct {
@@ -207,6 +222,12 @@ zolo_status zolo_pencil_perm(const zolo_pencil* p, int32_t* perm);
  * r2 == 0 selects the smallest r2 <= 16 with delta0 <= eps (Remark).
  * Host only.  Errors: ZOLO_EINVAL (gaps not ordered, r out of range).
  */
+/* Coefficients of any filter kind (ZOLO_FILTER_*) with r factorizations: the
+ * composite (r1 = r, r2 by the Remark), Zolo(r) (the inner function alone, from
+ * the eigengaps), or a contour rule on the circle through a and b with r poles
+ * in the upper half-plane (2r in all).  Host only; errors: ZOLO_EINVAL. */
+zolo_status zolo_filter_plan_kind(int kind, double a, double b, double a_minus, double a_plus, double b_minus,
+                                  double b_plus, int r, double eps, zolo_filter_coeffs* out);
 zolo_status zolo_filter_plan(double a_minus, double a_plus, double b_minus, double b_plus, int r1, int r2,
                              double eps, zolo_filter_coeffs* out);
 
@@ -295,6 +316,9 @@ typedef struct {
  * scalar type.  tol_gmres <= 0 and max_iter <= 0 take the defaults.  Returns
  * ZOLO_ENOCONV (with d_Y filled by the best iterate) if max_iter steps do
  * not reach tol_gmres.
+ * Factors of a comparison filter (coefficients of kind != ZOLO_FILTER_HYBRID)
+ * apply their one-stage R instead, with no GMRES (tolerances ignored, st
+ * zeroed): Zolo(r) gives (G V + V)/2, the contour rules G V.
  */
 zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_Y,
                               int64_t ldy, double tol_gmres, int max_iter, zolo_filter_stats* st, void* stream);

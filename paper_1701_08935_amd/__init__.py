@@ -19,6 +19,7 @@ ZOLO_EGAP, ZOLO_ESUBSPACE, ZOLO_EDEVICE, ZOLO_EBREAKDOWN, ZOLO_ETIMEOUT = 5, 6, 
 ZOLO_REAL64, ZOLO_COMPLEX128 = 0, 1
 ZOLO_PREC_FP64, ZOLO_PREC_MIXED = 0, 1
 ZOLO_MAX_R = 16
+ZOLO_FILTER_HYBRID, ZOLO_FILTER_ZOLO, ZOLO_FILTER_TRAPEZOID, ZOLO_FILTER_GAUSS = 0, 1, 2, 3
 STATUS_NAMES = {0: "ZOLO_OK", 1: "ZOLO_EINVAL", 2: "ZOLO_ENOTHERM", 3: "ZOLO_ENOMEM", 4: "ZOLO_ENOCONV",
                 5: "ZOLO_EGAP", 6: "ZOLO_ESUBSPACE", 7: "ZOLO_EDEVICE", 8: "ZOLO_EBREAKDOWN",
                 9: "ZOLO_ETIMEOUT"}
@@ -35,14 +36,14 @@ class zolo_filter_coeffs(ctypes.Structure):
                 ("l1", _d), ("l2", _d), ("alpha", _d), ("beta", _d), ("gamma", _d), ("M_hat", _d), ("c0", _d),
                 ("delta1", _d), ("sigma_hat_re", _d * _R), ("sigma_hat_im", _d * _R), ("w_hat_re", _d * _R),
                 ("w_hat_im", _d * _R), ("a_hat", _d * _R), ("c_hat", _d * _R), ("M", _d), ("a", _d * _R),
-                ("c", _d * _R), ("delta_S", _d), ("delta0", _d)]
+                ("c", _d * _R), ("delta_S", _d), ("delta0", _d), ("kind", _i)]
 
 
 class zolo_opts(ctypes.Structure):
     _fields_ = [("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d), ("r1", _i), ("r2", _i),
                 ("filter_eps", _d), ("n_ss", _i), ("max_subspace_iter", _i), ("max_gmres_iter", _i),
                 ("tol_resid", _d), ("tol_gmres", _d), ("precision", _i), ("seed", ctypes.c_uint64),
-                ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i)]
+                ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i), ("filter_kind", _i)]
 
 
 class zolo_stats(ctypes.Structure):
@@ -108,6 +109,7 @@ _SIGS = {
     "zolo_pencil_flops": (_i, [_vp, _vp]),
     "zolo_symbolic": (_i, [_i64, _vp, _vp, _vp, _i, _vp, _vp]),
     "zolo_filter_plan": (_i, [_d, _d, _d, _d, _i, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
+    "zolo_filter_plan_kind": (_i, [_i, _d, _d, _d, _d, _d, _d, _i, _d, ctypes.POINTER(zolo_filter_coeffs)]),
     "zolo_factor": (_i, [_vp, _vp, ctypes.POINTER(zolo_filter_coeffs), _i, _vp, ctypes.POINTER(_vp)]),
     "zolo_factors_free": (None, [_vp]),
     "zolo_inertia": (_i, [_vp, _vp, _vp, _i, _vp, _vp]),
@@ -184,6 +186,14 @@ def zolo_filter_plan(a_minus, a_plus, b_minus, b_plus, r1, r2=0, eps=1e-10) -> z
     co = zolo_filter_coeffs()
     _check(lib().zolo_filter_plan(float(a_minus), float(a_plus), float(b_minus), float(b_plus), int(r1), int(r2),
                                   float(eps), ctypes.byref(co)))
+    return co
+
+
+def zolo_filter_plan_kind(kind, a, b, a_minus=float("nan"), a_plus=float("nan"), b_minus=float("nan"),
+                          b_plus=float("nan"), r=2, eps=1e-10) -> zolo_filter_coeffs:
+    co = zolo_filter_coeffs()
+    _check(lib().zolo_filter_plan_kind(int(kind), float(a), float(b), float(a_minus), float(a_plus), float(b_minus),
+                                       float(b_plus), int(r), float(eps), ctypes.byref(co)))
     return co
 
 

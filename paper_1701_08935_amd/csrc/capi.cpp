@@ -649,6 +649,7 @@ extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
   o->max_refine = 8;
   o->tol_refine = 1e-8;
   o->block_cols = 0;
+  o->filter_kind = ZOLO_FILTER_HYBRID;
   return ZOLO_OK;
 }
 
@@ -1192,6 +1193,27 @@ extern "C" zolo_status zolo_filter_plan(double am, double ap, double bm, double 
   return (zolo_status)rc;
 }
 
+extern "C" zolo_status zolo_filter_plan_kind(int kind, double a, double b, double am, double ap, double bm,
+                                             double bp, int r, double eps, zolo_filter_coeffs* out) {
+  if (!out) {
+    set_error("null output");
+    return ZOLO_EINVAL;
+  }
+  char err[256] = {0};
+  int rc;
+  if (kind == ZOLO_FILTER_HYBRID || kind == ZOLO_FILTER_ZOLO) {
+    rc = plan_filter(am, ap, bm, bp, r, kind == ZOLO_FILTER_ZOLO ? 1 : 0, eps > 0 ? eps : 1e-10, out, err, sizeof(err));
+    if (rc == ZOLO_OK) out->kind = kind;
+  } else if (kind == ZOLO_FILTER_TRAPEZOID || kind == ZOLO_FILTER_GAUSS) {
+    rc = plan_contour(kind, a, b, r, out, err, sizeof(err));
+  } else {
+    snprintf(err, sizeof(err), "unknown filter kind %d", kind);
+    rc = ZOLO_EINVAL;
+  }
+  if (rc != ZOLO_OK) set_error("%s", err);
+  return (zolo_status)rc;
+}
+
 // ===========================================================================
 // numeric factorization
 // ===========================================================================
@@ -1722,6 +1744,10 @@ extern "C" zolo_status zolo_factor(zolo_ctx* ctx, zolo_pencil* P, const zolo_fil
   }
   if (co->r1 < 1 || co->r1 > ZOLO_MAX_R || co->r2 < 1 || co->r2 > ZOLO_MAX_R) {
     set_error("zolo_factor: coefficients not planned (r1=%d, r2=%d)", co->r1, co->r2);
+    return ZOLO_EINVAL;
+  }
+  if (co->kind < ZOLO_FILTER_HYBRID || co->kind > ZOLO_FILTER_GAUSS) {
+    set_error("zolo_factor: unknown filter kind %d", co->kind);
     return ZOLO_EINVAL;
   }
   if (precision != ZOLO_PREC_FP64 && precision != ZOLO_PREC_MIXED) {
@@ -2345,6 +2371,17 @@ zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, V
   return ZOLO_OK;
 }
 
+// Y = R(B^-1 A) V for a one-stage filter (kind != 0): R = s0 + s1 g with g in
+// the pole form of G (Zolo(r): (g + 1)/2; contour rules: g itself), one pole
+// solve per pole, no outer Krylov stage.
+template <typename VT>
+zolo_status rational_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, hipStream_t s) {
+  CHK(ensure_ws(F, p, 1));
+  CHK(apply_G_new<VT>(F, V, ldv, p, Y, ldy, F->tol_refine, s));
+  if (F->co.kind == ZOLO_FILTER_ZOLO) axpby_rows<VT>(Y, ldy, V, ldv, 0.5, 0.5, F->P->n, p, s);
+  return ZOLO_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2412,7 +2449,13 @@ zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int nc
   CHK(tmp.alloc(&vn, n * ncols));
   CHK(tmp.alloc(&yn, n * ncols));
   rows_gather<VT>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
-  zolo_status rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
+  zolo_status rc = ZOLO_OK;
+  if (F->co.kind == ZOLO_FILTER_HYBRID) {
+    rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
+  } else {
+    CHK(rational_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, s));
+    if (st) *st = zolo_filter_stats{0, 0.0, 0};
+  }
   if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
   rows_scatter<VT>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
   HIPC(hipStreamSynchronize(s));
@@ -2654,7 +2697,10 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   zolo_stats& st = R->st;
   double t0 = now_s();
   zolo_filter_coeffs co;
-  CHK(zolo_filter_plan(o.a_minus, o.a_plus, o.b_minus, o.b_plus, o.r1, o.r2, o.filter_eps, &co));
+  if (o.filter_kind == ZOLO_FILTER_HYBRID)
+    CHK(zolo_filter_plan(o.a_minus, o.a_plus, o.b_minus, o.b_plus, o.r1, o.r2, o.filter_eps, &co));
+  else
+    CHK(zolo_filter_plan_kind(o.filter_kind, a, b, o.a_minus, o.a_plus, o.b_minus, o.b_plus, o.r1, o.filter_eps, &co));
   st.t_plan = now_s() - t0;
   st.t_gaps = gi.t_gaps;
   st.inertia_count = gi.count;
@@ -2674,7 +2720,8 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   // resident factors of the same filter (serving) or a new factorization
   std::unique_ptr<zolo_factors> F_own;
   zolo_factors* Fu = F_in;
-  if (Fu && (Fu->P != P || Fu->precision != o.precision || Fu->co.r1 != co.r1 || Fu->co.r2 != co.r2 ||
+  if (Fu && (Fu->P != P || Fu->precision != o.precision || Fu->co.kind != co.kind || Fu->co.r1 != co.r1 ||
+             Fu->co.r2 != co.r2 || Fu->co.sigma_hat_re[0] != co.sigma_hat_re[0] ||
              Fu->co.a_minus != co.a_minus || Fu->co.a_plus != co.a_plus || Fu->co.b_minus != co.b_minus ||
              Fu->co.b_plus != co.b_plus))
     Fu = nullptr;  // not this query's filter: factor anew
@@ -2770,7 +2817,11 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
     for (int b0 = 0; b0 < nss; b0 += pb) {
       zolo_filter_stats fs{};
       const int pc = std::min(pb, nss - b0);
-      zolo_status rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, &fs, s);
+      zolo_status rc = ZOLO_OK;
+      if (co.kind == ZOLO_FILTER_HYBRID)
+        rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, &fs, s);
+      else
+        CHK(rational_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, s));
       if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
       if (rc == ZOLO_ENOCONV) frc = rc;
       st.n_gmres_total += fs.n_gmres;
@@ -2948,18 +2999,36 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
     o = *opts_in;
   else
     zolo_opts_default(&o);
+  if (o.filter_kind < ZOLO_FILTER_HYBRID || o.filter_kind > ZOLO_FILTER_GAUSS) {
+    set_error("zolo_solve: unknown filter kind %d", o.filter_kind);
+    return ZOLO_EINVAL;
+  }
+  HIPC(hipSetDevice(ctx->device));
+  GapInfo gi;
+  if (o.filter_kind == ZOLO_FILTER_TRAPEZOID || o.filter_kind == ZOLO_FILTER_GAUSS) {
+    // contour rules need no eigengaps; the count sizes the subspace when the
+    // caller gives no estimate
+    if (o.r1 == 0) o.r1 = 8;
+    if (n_lambda_est == 0 && o.n_ss <= 0) {
+      double ab[2] = {a, b};
+      int64_t nu[2];
+      CHK(zolo_inertia(ctx, P, ab, 2, nu, stream));
+      gi.count = nu[1] - nu[0];
+    }
+    if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
+    return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
+  }
   const int n_nan = std::isnan(o.a_minus) + std::isnan(o.a_plus) + std::isnan(o.b_minus) + std::isnan(o.b_plus);
   if (n_nan != 0 && n_nan != 4) {
     set_error("zolo_solve: give all four eigengap ends, or none (NaN) to have them estimated");
     return ZOLO_EINVAL;
   }
-  HIPC(hipSetDevice(ctx->device));
-  GapInfo gi;
   if (n_nan == 4) CHK(estimate_gaps(ctx, P, a, b, n_lambda_est, &o, &gi, as_stream(stream)));
   if (!(o.a_minus < a && a < o.a_plus && o.b_minus < b && b < o.b_plus)) {
     set_error("zolo_solve: need a in (a_minus, a_plus) and b in (b_minus, b_plus)");
     return ZOLO_EINVAL;
   }
+  if (o.r1 == 0 && o.filter_kind == ZOLO_FILTER_ZOLO) o.r1 = 4;
   if (o.r1 == 0) {
     const int n_for_ss = gi.count >= 0 ? (int)gi.count : n_lambda_est;
     const int nss = o.n_ss > 0 ? o.n_ss : (int)std::max<int64_t>((int64_t)std::ceil(1.5 * std::max(n_for_ss, 1)), n_for_ss + 8);

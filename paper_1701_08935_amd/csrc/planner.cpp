@@ -266,4 +266,77 @@ int plan_filter(double am, double ap, double bm, double bp, int r1, int r2, doub
   return ZOLO_OK;
 }
 
+// Comparison filters (Sec. 2.2, Figs. 2-3): quadratures of the contour integral
+// (1/(2 pi i)) oint dz / (z - x) over the circle through a and b, centre c,
+// radius rho, z(theta) = c + rho e^{i theta}.  A rule {theta_k, omega_k} in
+// conjugate pairs gives, for real x, R(x) = sum over upper nodes of
+// 2 Re(alpha_k / (z_k - x)) with alpha_k = omega_k rho e^{i theta_k} / (2 pi),
+// which is the pole form g(x) = M_hat [c0 + sum 2 Re(w_hat_k / (x - sigma_hat_k))]
+// with sigma_hat_k = z_k, w_hat_k = -alpha_k, c0 = 0, M_hat = 1.
+//   kind 2, trapezoidal rule: p = 2 npole nodes theta_k = pi (2k + 1) / p,
+//     weights 2 pi / p;
+//   kind 3, Gauss-Legendre rule: npole nodes on the upper half-circle,
+//     theta in (0, pi), and their mirror images.
+// Legendre nodes by Newton's method on the three-term recurrence from the
+// asymptotic guesses cos(pi (i + 3/4) / (q + 1/2)).
+int plan_contour(int kind, double a, double b, int npole, zolo_filter_coeffs* out, char* err, size_t errlen) {
+  std::memset(out, 0, sizeof(*out));
+  if (!(a < b) || !std::isfinite(a) || !std::isfinite(b)) {
+    snprintf(err, errlen, "contour filter: need finite a < b");
+    return ZOLO_EINVAL;
+  }
+  if (npole < 1 || npole > ZOLO_MAX_R || (kind != 2 && kind != 3)) {
+    snprintf(err, errlen, "contour filter: kind 2 or 3 and 1 <= poles <= %d", ZOLO_MAX_R);
+    return ZOLO_EINVAL;
+  }
+  const ld pi = 3.14159265358979323846264338327950288L;
+  const ld c = 0.5L * ((ld)a + (ld)b), rho = 0.5L * ((ld)b - (ld)a);
+  ld theta[ZOLO_MAX_R], omega[ZOLO_MAX_R];
+  const int q = npole;
+  if (kind == 2) {
+    const int p = 2 * q;
+    for (int k = 0; k < q; ++k) {
+      theta[k] = pi * (2.0L * k + 1.0L) / p;
+      omega[k] = 2.0L * pi / p;
+    }
+  } else {
+    for (int i = 0; i < q; ++i) {
+      ld x = cosl(pi * (i + 0.75L) / (q + 0.5L));
+      ld dp = 1.0L;
+      for (int it = 0; it < 100; ++it) {
+        ld p0 = 1.0L, p1 = x;  // P_0, P_1
+        for (int m = 2; m <= q; ++m) {
+          ld p2 = ((2.0L * m - 1.0L) * x * p1 - (m - 1.0L) * p0) / m;
+          p0 = p1;
+          p1 = p2;
+        }
+        if (q == 1) p1 = x, p0 = 1.0L;
+        dp = q * (x * p1 - p0) / (x * x - 1.0L);  // P_q'
+        ld dx = p1 / dp;
+        x -= dx;
+        if (fabsl(dx) < 1e-19L) break;
+      }
+      const ld w = 2.0L / ((1.0L - x * x) * dp * dp);
+      theta[i] = 0.5L * pi * (x + 1.0L);  // [-1, 1] onto (0, pi)
+      omega[i] = 0.5L * pi * w;
+    }
+  }
+  out->kind = kind;
+  out->r1 = q;
+  out->r2 = 1;
+  out->M_hat = 1.0;
+  out->c0 = 0.0;
+  out->a_minus = out->a_plus = out->b_minus = out->b_plus = NAN;
+  for (int k = 0; k < q; ++k) {
+    const std::complex<ld> e(cosl(theta[k]), sinl(theta[k]));
+    const std::complex<ld> z = c + rho * e;
+    const std::complex<ld> alpha = omega[k] * rho * e / (2.0L * pi);
+    out->sigma_hat_re[k] = (double)z.real();
+    out->sigma_hat_im[k] = (double)z.imag();
+    out->w_hat_re[k] = -(double)alpha.real();
+    out->w_hat_im[k] = -(double)alpha.imag();
+  }
+  return ZOLO_OK;
+}
+
 }  // namespace zolo

@@ -51,7 +51,7 @@ struct zolo_query {
 struct FactorEntry {
   zolo_pencil* P = nullptr;
   double am = 0, ap = 0, bm = 0, bp = 0, eps = 0;
-  int r1 = 0, r2 = 0, prec = 0;
+  int r1 = 0, r2 = 0, prec = 0, kind = 0;
   // queries that left the eigengaps (and r1) to the library: their interval and
   // estimate, and the gaps and r1 the library chose (reused instead of a new
   // inertia search)
@@ -92,14 +92,15 @@ bool same_filter(const zolo_query* x, const zolo_query* y) {
          u.filter_eps == v.filter_eps && u.precision == v.precision && u.tol_resid == v.tol_resid &&
          u.tol_gmres == v.tol_gmres && u.max_subspace_iter == v.max_subspace_iter &&
          u.max_gmres_iter == v.max_gmres_iter && u.max_refine == v.max_refine && u.tol_refine == v.tol_refine &&
-         u.block_cols == v.block_cols;
+         u.block_cols == v.block_cols && u.filter_kind == v.filter_kind;
 }
 
 bool gaps_estimated(const zolo_opts& o) { return std::isnan(o.a_minus); }
 
 bool entry_matches(const FactorEntry& e, const zolo_query* q) {
   const zolo_opts& o = q->o;
-  if (e.P != q->P || e.r2 != o.r2 || e.eps != o.filter_eps || e.prec != o.precision) return false;
+  if (e.P != q->P || e.r2 != o.r2 || e.eps != o.filter_eps || e.prec != o.precision || e.kind != o.filter_kind)
+    return false;
   if (gaps_estimated(o))
     return e.estimated && e.a == q->a && e.b == q->b && e.n_est == q->n_lambda && e.r1_asked == o.r1;
   return !e.estimated && e.am == o.a_minus && e.ap == o.a_plus && e.bm == o.b_minus && e.bp == o.b_plus &&
@@ -314,6 +315,7 @@ void worker(zolo_server* S) {
           fe.r1 = h->o.r1;
           fe.r2 = h->o.r2;
           fe.prec = h->o.precision;
+          fe.kind = h->o.filter_kind;
           if (gaps_estimated(h->o) && res) {
             zolo_stats rs{};
             zolo_result_stats(res, &rs);

@@ -58,6 +58,9 @@ template <typename T>
 void eig_resid_norms(int64_t n, const int64_t* rowptr, const int32_t* colind, const T* a, const T* b,
                      const int32_t* perm, const T* X, int64_t ldx, int p, const double* lam, double normA,
                      double normB, double* partial, double* out, hipStream_t s);
+// Y = s1 Y + s0 V (N x p row-major blocks)
+template <typename T>
+void axpby_rows(T* Y, int64_t ldy, const T* V, int64_t ldv, double s0, double s1, int64_t n, int p, hipStream_t s);
 // asynchronous clear of device memory
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
 

@@ -284,6 +284,17 @@ __global__ __launch_bounds__(256) void spmm_shift_resid_cplx_kernel(int64_t n, c
   }
 }
 
+// Y = s1 Y + s0 V (N x p blocks, real or complex, real scalars)
+template <typename T>
+__global__ void axpby_rows_kernel(T* __restrict__ Y, int64_t ldy, const T* __restrict__ V, int64_t ldv, double s0,
+                                  double s1, int64_t n, int p) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * p) return;
+  const int64_t i = e / p;
+  const int c = (int)(e % p);
+  Y[i * ldy + c] = add(scl(Y[i * ldy + c], s1), scl(V[i * ldv + c], s0));
+}
+
 template <typename T>
 __global__ void rows_gather_kernel(T* __restrict__ dst, int64_t ldd, const T* __restrict__ src, int64_t lds,
                                    const int32_t* __restrict__ idx, int64_t n, int p) {
@@ -592,6 +603,14 @@ template void eig_resid_norms<double>(int64_t, const int64_t*, const int32_t*, c
 template void eig_resid_norms<zd>(int64_t, const int64_t*, const int32_t*, const zd*, const zd*, const int32_t*,
                                   const zd*, int64_t, int, const double*, double, double, double*, double*,
                                   hipStream_t);
+
+template <typename T>
+void axpby_rows(T* Y, int64_t ldy, const T* V, int64_t ldv, double s0, double s1, int64_t n, int p, hipStream_t s) {
+  if (n * p == 0) return;
+  hipLaunchKernelGGL(axpby_rows_kernel<T>, dim3(nblk(n * p)), dim3(256), 0, s, Y, ldy, V, ldv, s0, s1, n, p);
+}
+template void axpby_rows<double>(double*, int64_t, const double*, int64_t, double, double, int64_t, int, hipStream_t);
+template void axpby_rows<zd>(zd*, int64_t, const zd*, int64_t, double, double, int64_t, int, hipStream_t);
 
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s) {
   if (bytes) (void)hipMemsetAsync(p, 0, bytes, s);

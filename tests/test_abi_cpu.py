@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import pencils
+from oracle.contour import ContourFilter, SingleZolo
 from oracle.filt import FilterPlan
 
 from .conftest import ROOT
@@ -83,6 +84,57 @@ def test_planner_auto_r2_and_errors():
         zolo.zolo_filter_plan(*g, 0, 2)
     with pytest.raises(zolo.ZoloError):
         zolo.zolo_filter_plan(*g, 2, 99)
+
+
+def _pole_form(co, x):
+    """R(x) = s0 + s1 M_hat [c0 + sum 2 Re(w_hat_j / (x - sigma_hat_j))] from the coefficient set."""
+    r = co.r1
+    sig = np.array(co.sigma_hat_re[:r]) + 1j * np.array(co.sigma_hat_im[:r])
+    w = np.array(co.w_hat_re[:r]) + 1j * np.array(co.w_hat_im[:r])
+    g = co.M_hat * (co.c0 + sum(2.0 * np.real(wj / (x - sj)) for sj, wj in zip(sig, w)))
+    return 0.5 * (g + 1.0) if co.kind == zolo.ZOLO_FILTER_ZOLO else g
+
+
+@pytest.mark.parametrize("kind,name", [(zolo.ZOLO_FILTER_TRAPEZOID, "trapezoid"), (zolo.ZOLO_FILTER_GAUSS, "gauss")])
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 8, 16])
+@pytest.mark.parametrize("ab", [(-1.0, 1.0), (5.8877, 6.0119), (-3.0, 4.0)])
+def test_contour_plan_matches_oracle(kind, name, q, ab):
+    co = zolo.zolo_filter_plan_kind(kind, *ab, r=q)
+    f = ContourFilter(name, *ab, 2 * q)
+    assert co.kind == kind and co.r1 == q
+    sig = np.array(co.sigma_hat_re[:q]) + 1j * np.array(co.sigma_hat_im[:q])
+    order = np.argsort(sig.real)
+    ref = np.argsort(f.z.real)
+    span = max(abs(ab[0]), abs(ab[1]))
+    assert np.max(np.abs(sig[order] - f.z[ref])) < 1e-14 * span
+    assert np.all(sig.imag > 0)
+    c, rho = 0.5 * (ab[0] + ab[1]), 0.5 * (ab[1] - ab[0])
+    x = np.concatenate([np.linspace(ab[0] - 3 * rho, ab[1] + 3 * rho, 997), [c, ab[0] - 10 * rho]])
+    assert np.max(np.abs(_pole_form(co, x) - f.R(x))) < 1e-13
+
+
+@pytest.mark.parametrize("g", GAPS[:5])
+@pytest.mark.parametrize("r", [1, 2, 3, 5])
+def test_single_zolo_plan_matches_oracle(g, r):
+    co = zolo.zolo_filter_plan_kind(zolo.ZOLO_FILTER_ZOLO, 0.5 * (g[0] + g[1]), 0.5 * (g[2] + g[3]), *g, r=r)
+    f = SingleZolo(*g, r)
+    assert co.kind == zolo.ZOLO_FILTER_ZOLO and co.r1 == r
+    lo, hi = g[0] - (g[3] - g[0]), g[3] + (g[3] - g[0])
+    x = np.linspace(lo, hi, 1501)
+    x = x[np.min(np.abs(x[:, None] - np.array(co.sigma_hat_re[:r])[None, :]), axis=1) > 1e-9 * (hi - lo)]
+    assert np.max(np.abs(_pole_form(co, x) - f.R(x))) < 1e-10
+
+
+def test_filter_plan_kind_errors():
+    for args in [(7, -1.0, 1.0), (zolo.ZOLO_FILTER_TRAPEZOID, 1.0, -1.0), (zolo.ZOLO_FILTER_GAUSS, -1.0, 1.0, 0),
+                 (zolo.ZOLO_FILTER_GAUSS, -1.0, math.inf)]:
+        kind, a, b = args[:3]
+        r = args[3] if len(args) > 3 else 4
+        with pytest.raises(zolo.ZoloError) as e:
+            zolo.zolo_filter_plan_kind(kind, a, b, r=r)
+        assert e.value.status == zolo.ZOLO_EINVAL
+    with pytest.raises(zolo.ZoloError):
+        zolo.zolo_filter_plan_kind(zolo.ZOLO_FILTER_ZOLO, -1.0, 1.0, r=2)  # gaps required
 
 
 def _check_nd(p, perm, info):
