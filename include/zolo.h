@@ -102,7 +102,7 @@ typedef struct {
   double filter_eps;       /* target delta0 when r2 == 0 (Remark after Algorithm 2) */
   int n_ss;                /* subspace size; 0 = ceil(1.5 n_lambda_est)             */
   int max_subspace_iter;   /* Algorithm 1 iterations                                */
-  int max_gmres_iter;      /* block GMRES steps per filter application              */
+  int max_gmres_iter;      /* block GMRES steps per filter application (all cycles) */
   double tol_resid;        /* ||Ax - lam Bx|| / ((||A|| + |lam| ||B||) ||x||)        */
   double tol_gmres;        /* per shift and column, relative LS residual            */
   int precision;           /* zolo_precision                                        */
@@ -116,6 +116,9 @@ typedef struct {
                               Krylov basis then holds block_cols columns), 0 = all */
   int filter_kind;         /* ZOLO_FILTER_*; for the comparison filters r1 is the
                               number of factorizations (poles per half-plane)      */
+  int gmres_restart;       /* block GMRES restarts every this many steps (collinear
+                              residuals, see zolo_filter_apply); the basis holds
+                              that many blocks.  0 = no restart (max_gmres_iter)   */
 } zolo_opts;
 
 typedef struct {
@@ -145,6 +148,7 @@ typedef struct {
   double t_gaps;           /* seconds spent estimating the eigengaps                */
   double a_minus, a_plus, b_minus, b_plus;  /* the eigengaps the filter used        */
   int factors_reused;      /* 1: resident factors of an earlier query were used     */
+  int n_restart;           /* block GMRES restarts summed over iterations           */
 } zolo_stats;
 
 typedef struct zolo_ctx zolo_ctx;
@@ -157,7 +161,8 @@ const char* zolo_last_error(void);
 const char* zolo_version(void);
 
 /* Defaults: r1 = 2, r2 = 0 (auto), filter_eps = 1e-10, tol_resid = 1e-8,
- * tol_gmres = 1e-10, max_subspace_iter = 6, max_gmres_iter = 60, FP64. */
+ * tol_gmres = 1e-10, max_subspace_iter = 6, max_gmres_iter = 60,
+ * gmres_restart = 30, FP64, the composite filter. */
 zolo_status zolo_opts_default(zolo_opts* out);
 
 /* Context on one HIP device: selects the device, creates nothing else.
@@ -305,6 +310,7 @@ typedef struct {
   int n_gmres;             /* block GMRES steps                                  */
   double worst_resid;      /* max over shifts and columns of the relative LS residual */
   int breakdown;           /* 1 if the block Krylov space was exhausted          */
+  int restarts;            /* restart cycles                                     */
 } zolo_filter_stats;
 
 /*
@@ -316,12 +322,21 @@ typedef struct {
  * scalar type.  tol_gmres <= 0 and max_iter <= 0 take the defaults.  Returns
  * ZOLO_ENOCONV (with d_Y filled by the best iterate) if max_iter steps do
  * not reach tol_gmres.
+ * restart > 0 (and < max_iter): the basis holds restart blocks; after each
+ * cycle the shift with the largest residual (the base) takes its
+ * minimal-residual update and every other shift the update that keeps its
+ * residual a multiple of the base's residual block (collinear restarts for
+ * shifted systems, Frommer and Glaessner 1998, in block form), so the next
+ * cycle again serves all shifts from one basis.  Real pencils continue on the
+ * 2 ncols real columns [Re R, Im R] of the complex base residual R (twice the
+ * pole solves per step after the first restart).
  * Factors of a comparison filter (coefficients of kind != ZOLO_FILTER_HYBRID)
  * apply their one-stage R instead, with no GMRES (tolerances ignored, st
  * zeroed): Zolo(r) gives (G V + V)/2, the contour rules G V.
  */
 zolo_status zolo_filter_apply(zolo_factors* f, const double* d_V, int64_t ldv, int ncols, double* d_Y,
-                              int64_t ldy, double tol_gmres, int max_iter, zolo_filter_stats* st, void* stream);
+                              int64_t ldy, double tol_gmres, int max_iter, int restart, zolo_filter_stats* st,
+                              void* stream);
 
 /*
  * Eigenpairs of (A, B) in (a, b) (Algorithm 1 with Algorithm 2).

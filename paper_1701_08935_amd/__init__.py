@@ -43,7 +43,8 @@ class zolo_opts(ctypes.Structure):
     _fields_ = [("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d), ("r1", _i), ("r2", _i),
                 ("filter_eps", _d), ("n_ss", _i), ("max_subspace_iter", _i), ("max_gmres_iter", _i),
                 ("tol_resid", _d), ("tol_gmres", _d), ("precision", _i), ("seed", ctypes.c_uint64),
-                ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i), ("filter_kind", _i)]
+                ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i), ("filter_kind", _i),
+                ("gmres_restart", _i)]
 
 
 class zolo_stats(ctypes.Structure):
@@ -55,7 +56,7 @@ class zolo_stats(ctypes.Structure):
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
                 ("nnz_l", ctypes.c_longlong), ("factor_flops", _d), ("inertia_count", ctypes.c_longlong),
                 ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d),
-                ("factors_reused", _i)]
+                ("factors_reused", _i), ("n_restart", _i)]
 
 
 class zolo_kernel_profile(ctypes.Structure):
@@ -78,7 +79,7 @@ class zolo_server_info(ctypes.Structure):
 
 
 class zolo_filter_stats(ctypes.Structure):
-    _fields_ = [("n_gmres", _i), ("worst_resid", _d), ("breakdown", _i)]
+    _fields_ = [("n_gmres", _i), ("worst_resid", _d), ("breakdown", _i), ("restarts", _i)]
 
 
 def struct_dict(s) -> dict:
@@ -118,7 +119,7 @@ _SIGS = {
     "zolo_residuals_noalloc": (_i, [_vp, _vp, _i64, _i, _vp, _vp, _vp]),
     "zolo_pole_solve": (_i, [_vp, _i, _vp, _i64, _i, _vp, _i64, _vp]),
     "zolo_apply_G": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _vp]),
-    "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
+    "zolo_filter_apply": (_i, [_vp, _vp, _i64, _i, _vp, _i64, _d, _i, _i, ctypes.POINTER(zolo_filter_stats), _vp]),
     "zolo_solve": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, _vp, ctypes.POINTER(_vp)]),
     "zolo_slice": (_i, [_vp, _vp, _d, _d, _i, ctypes.POINTER(zolo_opts), _vp, ctypes.POINTER(_vp)]),
     "zolo_result_count": (_i64, [_vp]),
@@ -363,13 +364,13 @@ def zolo_apply_G(f: Factors, V):
     return W
 
 
-def zolo_filter_apply(f: Factors, V, tol=1e-10, max_iter=60, allow_noconv=False):
+def zolo_filter_apply(f: Factors, V, tol=1e-10, max_iter=60, restart=0, allow_noconv=False):
     import torch
 
     Y = torch.empty_like(V)
     st = zolo_filter_stats()
     _check(lib().zolo_filter_apply(f.h, _ptr(V), V.stride(0), V.shape[1], _ptr(Y), Y.stride(0), float(tol),
-                                   int(max_iter), ctypes.byref(st), _stream()),
+                                   int(max_iter), int(restart), ctypes.byref(st), _stream()),
            allow=(ZOLO_ENOCONV,) if allow_noconv else ())
     return Y, struct_dict(st)
 

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <complex>
+#include <type_traits>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -548,8 +550,10 @@ int gemm_tn(Workspace& ws, const VT* X, int64_t ldx, const VT* Y, int64_t ldy, i
             int64_t ldo, bool add, hipStream_t s) {
   int tiles = gemm_tiles(m, n);
   int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
-  while (S * (int64_t)m * n > ws.partial_len && S > 1) S /= 2;
-  if (S * (int64_t)m * n > ws.partial_len) {
+  // partial_len counts entries of the workspace's own block type (ef doubles)
+  const int64_t cap = ws.partial_len * ws.ef / (ST<VT>::cplx ? 2 : 1);
+  while (S * (int64_t)m * n > cap && S > 1) S /= 2;
+  if (S * (int64_t)m * n > cap) {
     set_error("gemm_tn: partial buffer too small");
     return ZOLO_ENOMEM;
   }
@@ -650,6 +654,7 @@ extern "C" zolo_status zolo_opts_default(zolo_opts* o) {
   o->tol_refine = 1e-8;
   o->block_cols = 0;
   o->filter_kind = ZOLO_FILTER_HYBRID;
+  o->gmres_restart = 30;
   return ZOLO_OK;
 }
 
@@ -2083,7 +2088,7 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   Workspace* ws = F->ws.get();
   const bool cx = F->P->cplx();
   const int nshift = F->co.r2 * (cx ? 2 : 1);  // complex pencils: +i sqrt(c_j) and -i sqrt(c_j)
-  if (ws && ws->p == p && ws->mmax >= mmax && ws->nshift == nshift) return ZOLO_OK;
+  if (ws && ws->p >= p && ws->mmax >= mmax && ws->nshift == nshift) return ZOLO_OK;
   F->ws.reset(new Workspace());
   ws = F->ws.get();
   const int64_t n = F->P->n;
@@ -2296,76 +2301,359 @@ zolo_status cholqr2(zolo_factors* F, const VT* Win, int64_t ldin, VT* Qout, int6
   return ZOLO_OK;
 }
 
-// Y (ld ldy) = R_ab(B^-1 A) V, everything in the new ordering
-template <typename VT>
-zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, double tol,
-                             int maxit, zolo_filter_stats* st, hipStream_t s) {
-  CHK(ensure_ws(F, p, maxit));
+// W (b x nrhs, col-major) = T^-1 W for a b x b col-major T, Gaussian
+// elimination with partial pivoting on the host; false if T is singular
+bool dense_solve_host(std::vector<std::complex<double>>& T, std::vector<std::complex<double>>& W, int b, int nrhs) {
+  for (int k = 0; k < b; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < b; ++i)
+      if (std::abs(T[i + (size_t)k * b]) > std::abs(T[piv + (size_t)k * b])) piv = i;
+    if (T[piv + (size_t)k * b] == std::complex<double>(0.0, 0.0)) return false;
+    if (piv != k) {
+      for (int j = 0; j < b; ++j) std::swap(T[k + (size_t)j * b], T[piv + (size_t)j * b]);
+      for (int j = 0; j < nrhs; ++j) std::swap(W[k + (size_t)j * b], W[piv + (size_t)j * b]);
+    }
+    const std::complex<double> d = T[k + (size_t)k * b];
+    for (int i = k + 1; i < b; ++i) {
+      const std::complex<double> l = T[i + (size_t)k * b] / d;
+      if (l == std::complex<double>(0.0, 0.0)) continue;
+      for (int j = k + 1; j < b; ++j) T[i + (size_t)j * b] -= l * T[k + (size_t)j * b];
+      for (int j = 0; j < nrhs; ++j) W[i + (size_t)j * b] -= l * W[k + (size_t)j * b];
+    }
+  }
+  for (int j = 0; j < nrhs; ++j)
+    for (int k = b - 1; k >= 0; --k) {
+      std::complex<double> v = W[k + (size_t)j * b];
+      for (int t = k + 1; t < b; ++t) v -= T[k + (size_t)t * b] * W[t + (size_t)j * b];
+      W[k + (size_t)j * b] = v / T[k + (size_t)k * b];
+    }
+  return true;
+}
+
+// Thin QR of a rows x p col-major complex matrix on the host by Householder
+// reflections: A = Q R, Q rows x p with orthonormal columns (whatever the rank
+// of A), R p x p upper triangular.
+void householder_qr_host(const std::vector<std::complex<double>>& A, int64_t rows, int p,
+                         std::vector<std::complex<double>>* Q, std::vector<std::complex<double>>* R) {
+  using cd = std::complex<double>;
+  std::vector<cd> W(A);
+  std::vector<std::vector<cd>> vs(p);
+  std::vector<double> taus(p, 0.0);
+  for (int k = 0; k < p; ++k) {
+    cd* col = W.data() + (size_t)k * rows;
+    double nrm2 = 0.0;
+    for (int64_t i = k; i < rows; ++i) nrm2 += std::norm(col[i]);
+    const double nrm = std::sqrt(nrm2), a0 = std::abs(col[k]);
+    const cd ph = a0 > 0.0 ? col[k] / a0 : cd(1.0, 0.0);
+    std::vector<cd> v(col + k, col + rows);
+    v[0] += ph * nrm;
+    double vn2 = 0.0;
+    for (const cd& x : v) vn2 += std::norm(x);
+    const double t = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    for (int j = k; j < p; ++j) {  // columns k.. of W: x -= t v (v^H x)
+      cd* x = W.data() + (size_t)j * rows + k;
+      cd d(0.0, 0.0);
+      for (size_t i = 0; i < v.size(); ++i) d += std::conj(v[i]) * x[i];
+      d *= t;
+      for (size_t i = 0; i < v.size(); ++i) x[i] -= d * v[i];
+    }
+    vs[k] = std::move(v);
+    taus[k] = t;
+  }
+  R->assign((size_t)p * p, cd(0.0, 0.0));
+  for (int j = 0; j < p; ++j)
+    for (int i = 0; i <= j; ++i) (*R)[i + (size_t)j * p] = W[i + (size_t)j * rows];
+  // Q = H_0 ... H_{p-1} [I; 0]
+  Q->assign((size_t)rows * p, cd(0.0, 0.0));
+  for (int j = 0; j < p; ++j) (*Q)[j + (size_t)j * rows] = cd(1.0, 0.0);
+  for (int k = p - 1; k >= 0; --k) {
+    const std::vector<cd>& v = vs[k];
+    for (int j = 0; j < p; ++j) {
+      cd* x = Q->data() + (size_t)j * rows + k;
+      cd d(0.0, 0.0);
+      for (size_t i = 0; i < v.size(); ++i) d += std::conj(v[i]) * x[i];
+      d *= taus[k];
+      for (size_t i = 0; i < v.size(); ++i) x[i] -= d * v[i];
+    }
+  }
+}
+
+// State of a restarted multi-shift block GMRES run across its cycles
+struct GmresRun {
+  int total = 0, restarts = 0;
+  double worst = 1.0;
+  bool exhausted = false, done = false;
+  std::vector<std::complex<double>> G0;  // per-shift right-hand sides of the next cycle (p x p each)
+  // complex pencils restart the - shifts after the + shifts: their start block
+  // (N x p), right-hand sides and residual while they wait
+  DevArena mem;
+  zd* pend_start = nullptr;
+  std::vector<std::complex<double>> pend_G0;
+  bool pending = false;
+  double pend_worst = 0.0;
+};
+
+// One cycle of multi-shift block GMRES on blocks of scalar KT (the pencil's
+// type in the first cycle, complex after a restart), then either the final
+// minimal-residual updates or a collinear restart (see filter_apply_new).
+template <typename VT, typename KT>
+zolo_status gmres_cycle(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, double tol, int mr,
+                        int maxit, bool first, const std::vector<double>& r0n, GmresRun& run, hipStream_t s) {
+  using cd = std::complex<double>;
+  constexpr bool same = std::is_same<VT, KT>::value;  // false: a real pencil on a complex basis
+  DevArena rmem;  // this cycle's restart buffers
   Workspace& ws = *F->ws;
   const int64_t n = F->P->n;
-  const int64_t Mp = ws.ldh;
+  const int64_t Mp = same ? ws.ldh : ws.ldh / 2;  // ld of the basis and rows of H, in KT
   const int ns = ws.nshift;
-  VT *Vb = (VT*)ws.Vb, *W = (VT*)ws.W, *H = (VT*)ws.H, *hbuf = (VT*)ws.hbuf, *R0 = (VT*)ws.R0, *Rk = (VT*)ws.Rk;
-  bool bd = false;
-  // V = V0 R0
-  CHK(cholqr2<VT>(F, V, ldv, Vb, Mp, p, &bd, s));
-  if (bd) {
-    set_error("filter: input block is rank deficient");
-    return ZOLO_EBREAKDOWN;
+  KT *Vb = (KT*)ws.Vb, *W = (KT*)ws.W, *H = (KT*)ws.H, *hbuf = (KT*)ws.hbuf;
+  ws.hls.p = p;
+  ws.hls.ldr = (int64_t)(ws.mmax + 1) * p;
+  if (first) {
+    hls_init<KT>(ws.hls, (const KT*)ws.R0, s);
+  } else {
+    zd* g0 = nullptr;
+    CHK(rmem.alloc(&g0, run.G0.size()));
+    HIPC(hipMemcpyAsync(g0, run.G0.data(), sizeof(zd) * run.G0.size(), hipMemcpyHostToDevice, s));
+    hls_init_multi(ws.hls, g0, s);
   }
-  HIPC(hipMemcpyAsync(R0, Rk, sizeof(VT) * p * p, hipMemcpyDeviceToDevice, s));
-  std::vector<VT> r0(p * p);
-  std::vector<double> r0n(p, 0.0);
-  HIPC(hipMemcpyAsync(r0.data(), R0, sizeof(VT) * p * p, hipMemcpyDeviceToHost, s));
-  HIPC(hipStreamSynchronize(s));
-  for (int c = 0; c < p; ++c)
-    for (int i = 0; i <= c; ++i) r0n[c] += abs2(r0[i + c * p]);
-  for (int c = 0; c < p; ++c) r0n[c] = std::sqrt(r0n[c]);
-  hls_init<VT>(ws.hls, R0, s);
-  HIPC(hipMemsetAsync(H, 0, sizeof(VT) * Mp * (int64_t)maxit * p, s));
-  std::vector<double> res((size_t)ns * p);
+  HIPC(hipMemsetAsync(H, 0, sizeof(KT) * Mp * (int64_t)mr * p, s));
+  std::vector<double> res((size_t)ns * p), wq(ns, 0.0);
+  bool bd = false;
   int m = 0;
-  double worst = 1.0;
-  bool exhausted = false;
-  for (int k = 0; k < maxit; ++k) {
+  for (int k = 0; k < mr && run.total < maxit; ++k) {
     // inexact inner solves (mixed precision): the tolerance grows as the outer
     // residual falls, tol_refine / ||r_{k-1}|| capped at 1e-2
-    const double tol_inner = std::min(1e-2, F->tol_refine / std::max(worst, 1e-300));
-    CHK(apply_G_new<VT>(F, Vb + (int64_t)k * p, Mp, p, W, p, tol_inner, s));
+    const double tol_inner = std::min(1e-2, F->tol_refine / std::max(run.worst, 1e-300));
+    if constexpr (same)
+      CHK(apply_G_new<VT>(F, Vb + (int64_t)k * p, Mp, p, W, p, tol_inner, s));
+    else  // G is real: the complex block is the real block of its 2p interleaved columns
+      CHK(apply_G_new<double>(F, (const double*)(Vb + (int64_t)k * p), 2 * Mp, 2 * p, (double*)W, 2 * p, tol_inner,
+                              s));
     const int kp1 = (k + 1) * p;
     for (int pass = 0; pass < 2; ++pass) {
-      CHK(gemm_tn<VT>(ws, Vb, Mp, W, p, n, kp1, p, hbuf, kp1, false, s));
-      CHK(gemm_nt_big<VT>(ws, W, p, W, p, 1.0, -1.0, hbuf, kp1, true, Vb, Mp, n, p, kp1, s));
-      reduce_partials<VT>(H + (int64_t)k * p * Mp, Mp, hbuf, 1, kp1, p, true, s);
+      CHK(gemm_tn<KT>(ws, Vb, Mp, W, p, n, kp1, p, hbuf, kp1, false, s));
+      CHK(gemm_nt_big<KT>(ws, W, p, W, p, 1.0, -1.0, hbuf, kp1, true, Vb, Mp, n, p, kp1, s));
+      reduce_partials<KT>(H + (int64_t)k * p * Mp, Mp, hbuf, 1, kp1, p, true, s);
     }
-    CHK(cholqr2<VT>(F, W, p, Vb + (int64_t)kp1, Mp, p, &bd, s));
-    put_block<VT>(H, Mp, kp1, (int64_t)k * p, Rk, p, s);
+    CHK(cholqr2<KT>(F, W, p, Vb + (int64_t)kp1, Mp, p, &bd, s));
+    put_block<KT>(H, Mp, kp1, (int64_t)k * p, (const KT*)ws.Rk, p, s);
     {
       prof::Scope ps(ZOLO_PROF_HLS, 0.0, 0.0, s);
-      hls_step<VT>(ws.hls, H, Mp, k, ws.res, s);
+      hls_step<KT>(ws.hls, H, Mp, k, ws.res, s);
     }
     HIPC(hipMemcpyAsync(res.data(), ws.res, sizeof(double) * ns * p, hipMemcpyDeviceToHost, s));
     HIPC(hipStreamSynchronize(s));
     HIPC(hipGetLastError());
-    worst = 0.0;
-    for (int q = 0; q < ns; ++q)
-      for (int c = 0; c < p; ++c) worst = std::max(worst, res[(size_t)q * p + c] / std::max(r0n[c], 1e-300));
+    run.worst = 0.0;
+    for (int q = 0; q < ns; ++q) {
+      wq[q] = 0.0;
+      for (int c = 0; c < p; ++c) wq[q] = std::max(wq[q], res[(size_t)q * p + c] / std::max(r0n[c], 1e-300));
+      run.worst = std::max(run.worst, wq[q]);
+    }
     m = k + 1;
-    if (bd) exhausted = true;
-    if (worst <= tol || exhausted) break;
+    ++run.total;
+    if (bd) run.exhausted = true;
+    if (run.worst <= tol || run.exhausted) {
+      run.done = true;
+      break;
+    }
   }
-  hls_backsolve(ws.hls, m, ws.Ys, s);
-  hls_combine(ws.Ys, m, p, ns, ws.coef, (VT*)ws.Cm, s);
-  // Y = V/2 + V_m C
-  CHK(gemm_nt_big<VT>(ws, Y, ldy, V, ldv, 0.5, 1.0, (VT*)ws.Cm, (int64_t)m * p, true, Vb, Mp, n, p, m * p, s));
+  const bool restart = !run.done && run.total < maxit;
+  const int64_t rows = (int64_t)(m + 1) * p, mp = (int64_t)m * p;
+  const HlsState& hs = ws.hls;
+  // shift groups with a base each: one group, or at a complex pencil's first
+  // restart the + shifts [0, r2) and the - shifts [r2, 2 r2), which continue
+  // one after the other (a - shift's residual is not a multiple of a + shift's)
+  const bool split = ST<VT>::cplx && restart && run.restarts == 0 && ns >= 2;
+  const int ngroups = split ? 2 : 1;
+  auto group_of = [&](int q) { return split && q >= ns / 2 ? 1 : 0; };
+  zd* E[2] = {nullptr, nullptr};  // orthonormal bases Q_Z of the bases' residual blocks, rows x p
+  int base[2] = {-1, -1};
+  std::vector<cd> wsol, rz[2];
+  if (restart) {
+    ++run.restarts;
+    for (int g = 0; g < ngroups; ++g) {
+      double best = -1.0;
+      for (int q = 0; q < ns; ++q)
+        if (group_of(q) == g && wq[q] > best) {
+          best = wq[q];
+          base[g] = q;
+        }
+      if (g == 1) run.pend_worst = best;
+    }
+    // Z = Q_base [0; g_base(mp:(m+1)p, :)]: a base's residual block in the
+    // basis; Z = Q_Z R_Z on the host (Householder: Q_Z orthonormal at any rank)
+    zd *Z = nullptr, *T = nullptr, *Wd = nullptr;
+    CHK(rmem.alloc(&Z, (size_t)rows * p));
+    CHK(rmem.alloc(&T, (size_t)ns * rows * p));
+    CHK(rmem.alloc(&Wd, (size_t)ns * p * p));
+    for (int g = 0; g < ngroups; ++g) {
+      CHK(rmem.alloc(&E[g], (size_t)rows * p));
+      HIPC(hipMemsetAsync(Z, 0, sizeof(zd) * rows * p, s));
+      HIPC(hipMemcpy2DAsync(Z + mp, sizeof(zd) * rows, hs.g + (int64_t)base[g] * hs.ldr * p + mp,
+                            sizeof(zd) * hs.ldr, sizeof(zd) * p, p, hipMemcpyDeviceToDevice, s));
+      hls_apply_q(hs, base[g], m, Z, rows, 0, p, false, s);
+      std::vector<cd> zh((size_t)rows * p), qz;
+      HIPC(hipMemcpyAsync(zh.data(), Z, sizeof(zd) * zh.size(), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      householder_qr_host(zh, rows, p, &qz, &rz[g]);
+      HIPC(hipMemcpyAsync(E[g], qz.data(), sizeof(zd) * qz.size(), hipMemcpyHostToDevice, s));
+    }
+    // T_s = Q_s^H Q_Z(group of s) for every shift; W_s = T_s,bot^-1 g_s,bot on
+    // the host: shift s's residual becomes V_{m+1} Q_Z W_s (bases and shifts
+    // with no right-hand side keep W_s = 0)
+    for (int q = 0; q < ns; ++q)
+      HIPC(hipMemcpyAsync(T + (int64_t)q * rows * p, E[group_of(q)], sizeof(zd) * rows * p, hipMemcpyDeviceToDevice,
+                          s));
+    hls_apply_q(hs, -1, m, T, rows, rows * p, p, true, s);
+    std::vector<cd> tb((size_t)ns * p * p), gb((size_t)ns * p * p);
+    for (int q = 0; q < ns; ++q) {
+      HIPC(hipMemcpy2DAsync(tb.data() + (size_t)q * p * p, sizeof(zd) * p, T + (int64_t)q * rows * p + mp,
+                            sizeof(zd) * rows, sizeof(zd) * p, p, hipMemcpyDeviceToHost, s));
+      HIPC(hipMemcpy2DAsync(gb.data() + (size_t)q * p * p, sizeof(zd) * p, hs.g + (int64_t)q * hs.ldr * p + mp,
+                            sizeof(zd) * hs.ldr, sizeof(zd) * p, p, hipMemcpyDeviceToHost, s));
+    }
+    HIPC(hipStreamSynchronize(s));
+    wsol.assign((size_t)ns * p * p, cd(0.0, 0.0));
+    for (int q = 0; q < ns; ++q) {
+      if (q == base[0] || q == base[1]) continue;
+      std::vector<cd> Wq(gb.begin() + (size_t)q * p * p, gb.begin() + (size_t)(q + 1) * p * p);
+      bool any = false;
+      for (const cd& x : Wq) any = any || x != cd(0.0, 0.0);
+      if (!any) continue;
+      std::vector<cd> Tq(tb.begin() + (size_t)q * p * p, tb.begin() + (size_t)(q + 1) * p * p);
+      if (!dense_solve_host(Tq, Wq, p, p)) {
+        set_error("block GMRES restart: singular collinearity system for shift %d", q);
+        return ZOLO_EBREAKDOWN;
+      }
+      std::copy(Wq.begin(), Wq.end(), wsol.begin() + (size_t)q * p * p);
+    }
+    HIPC(hipMemcpyAsync(Wd, wsol.data(), sizeof(zd) * wsol.size(), hipMemcpyHostToDevice, s));
+    hls_collinear_rhs(hs, m, T, rows * p, Wd, -1, s);
+  }
+  // the cycle's updates (after a restart: the base's minimal residual, the
+  // others' collinear ones), Y = V/2 + V_m C or Y += V_m C
+  hls_backsolve(hs, m, ws.Ys, s);
+  if constexpr (same) {
+    hls_combine(ws.Ys, m, p, ns, ws.coef, (VT*)ws.Cm, s);
+    if (first)
+      CHK(gemm_nt_big<VT>(ws, Y, ldy, V, ldv, 0.5, 1.0, (VT*)ws.Cm, mp, true, Vb, Mp, n, p, (int)mp, s));
+    else
+      CHK(gemm_nt_big<VT>(ws, Y, ldy, Y, ldy, 1.0, 1.0, (VT*)ws.Cm, mp, true, Vb, Mp, n, p, (int)mp, s));
+  } else {
+    // real pencil, complex basis: Y += Re(V_m C) = [Re V_m, Im V_m] [Re C; -Im C],
+    // the interleaved real view of V_m times that of conj(C)
+    hls_combine(ws.Ys, m, p, ns, ws.coef, (zd*)ws.Cm, s);
+    conj_copy<zd>((zd*)ws.Cm, (const zd*)ws.Cm, mp * p, s);
+    CHK(gemm_nt_big<double>(ws, (double*)Y, ldy, (const double*)Y, ldy, 1.0, 1.0, (const double*)ws.Cm, 2 * mp, true,
+                            (const double*)Vb, 2 * Mp, n, p, (int)(2 * mp), s));
+  }
+  if (!restart) return ZOLO_OK;
+  // next start block V_{m+1} Q_Z, orthonormal (complex; for a real pencil's
+  // first cycle the real basis times the interleaved real columns of Q_Z); a
+  // waiting group's start block is kept beside it
+  zd* Bn = nullptr;
+  CHK(rmem.alloc(&Bn, (size_t)n * p));
+  if constexpr (std::is_same<KT, double>::value) {
+    double* Er = nullptr;
+    CHK(rmem.alloc(&Er, (size_t)rows * 2 * p));
+    cols_re_im(E[0], rows, rows, p, Er, s);
+    CHK(gemm_nt_big<double>(ws, (double*)Bn, 2 * p, nullptr, 0, 0.0, 1.0, Er, rows, true, Vb, Mp, n, 2 * p, (int)rows,
+                            s));
+  } else {
+    CHK(gemm_nt_big<zd>(ws, Bn, p, nullptr, 0, 0.0, 1.0, E[0], rows, true, Vb, Mp, n, p, (int)rows, s));
+    if (split) {
+      CHK(run.mem.alloc(&run.pend_start, (size_t)n * p));
+      CHK(gemm_nt_big<zd>(ws, run.pend_start, p, nullptr, 0, 0.0, 1.0, E[1], rows, true, Vb, Mp, n, p, (int)rows, s));
+    }
+  }
+  // a real pencil's workspace grows to hold complex blocks (2p real columns)
+  if (!ST<VT>::cplx && F->ws->p < 2 * p) CHK(ensure_ws(F, 2 * p, mr));
+  Workspace& wn = *F->ws;
+  const int64_t Mn = ST<VT>::cplx ? wn.ldh : wn.ldh / 2;
+  HIPC(hipMemcpy2DAsync(wn.Vb, sizeof(zd) * Mn, Bn, sizeof(zd) * p, sizeof(zd) * p, n, hipMemcpyDeviceToDevice, s));
+  // next right-hand sides: a base's residual is V_1' R_Z, shift s's V_1' W_s;
+  // shifts of the other group get none
+  run.G0.assign((size_t)ns * p * p, cd(0.0, 0.0));
+  if (split) run.pend_G0.assign((size_t)ns * p * p, cd(0.0, 0.0));
+  for (int q = 0; q < ns; ++q) {
+    const int g = group_of(q);
+    const cd* src = q == base[g] ? rz[g].data() : wsol.data() + (size_t)q * p * p;
+    std::copy(src, src + (size_t)p * p, (g == 0 ? run.G0 : run.pend_G0).begin() + (size_t)q * p * p);
+  }
+  if (split) run.pending = true;
+  HIPC(hipStreamSynchronize(s));
+  return ZOLO_OK;
+}
+
+// Y (ld ldy) = R_ab(B^-1 A) V, everything in the new ordering: multi-shift
+// block GMRES on G (eq. solve2, Corollary 1) over the outer shifts, every
+// shift's least-squares problem on one shared block Krylov basis (shift
+// invariance of the Krylov space), Y = V/2 + sum_s coef_s X_s.
+//
+// Restarts (every `restart` steps, 0 = none): after a cycle of m steps the
+// shift with the largest residual (the base) takes its minimal-residual
+// update, whose residual is V_{m+1} Z with Z = Q_base [0; g_base,bot].  Every
+// other shift s takes the update that makes its residual a multiple of the
+// same block: [H_s, Z] [y_s; W_s] = E1 S M_s, square, solved through shift
+// s's own QR of H_s (T = Q_s^H Z; W_s = T_bot^-1 g_s,bot;
+// y_s = R_s^-1 (g_s,top - T_top W_s)).  The next cycle starts from the
+// orthonormalized block V_{m+1} Z = V1' S' and gives shift s the right-hand
+// side E1 S' W_s, so all shifts still share one Krylov basis (collinear
+// restarts of shifted GMRES, Frommer and Glaessner, 1998, in block form).
+// The base residual of a real pencil is complex: its later cycles run on a
+// complex basis (G applied to the 2p interleaved real columns), solving only
+// the + shifts, Y += Re(V_m C).
+template <typename VT>
+zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, double tol,
+                             int maxit, int restart, zolo_filter_stats* st, hipStream_t s) {
+  const int mr = restart > 0 && restart < maxit ? restart : maxit;
+  CHK(ensure_ws(F, p, mr));
+  bool bd = false;
+  {
+    Workspace& ws = *F->ws;
+    // V = V0 R0
+    CHK(cholqr2<VT>(F, V, ldv, (VT*)ws.Vb, ws.ldh, p, &bd, s));
+    if (bd) {
+      set_error("filter: input block is rank deficient");
+      return ZOLO_EBREAKDOWN;
+    }
+    HIPC(hipMemcpyAsync(ws.R0, ws.Rk, sizeof(VT) * p * p, hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<VT> r0((size_t)p * p);
+  std::vector<double> r0n(p, 0.0);
+  HIPC(hipMemcpyAsync(r0.data(), F->ws->R0, sizeof(VT) * p * p, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  for (int c = 0; c < p; ++c)
+    for (int i = 0; i <= c; ++i) r0n[c] += abs2(r0[i + c * p]);
+  for (int c = 0; c < p; ++c) r0n[c] = std::sqrt(r0n[c]);
+  GmresRun run;
+  CHK((gmres_cycle<VT, VT>(F, V, ldv, p, Y, ldy, tol, mr, maxit, true, r0n, run, s)));
+  while (run.total < maxit) {
+    if (run.done) {
+      if (!run.pending) break;
+      // the + shifts have converged: the - shifts continue from their own block
+      Workspace& ws = *F->ws;
+      HIPC(hipMemcpy2DAsync(ws.Vb, sizeof(zd) * ws.ldh, run.pend_start, sizeof(zd) * p, sizeof(zd) * p, F->P->n,
+                            hipMemcpyDeviceToDevice, s));
+      run.G0.swap(run.pend_G0);
+      run.pending = run.done = run.exhausted = false;
+      run.worst = run.pend_worst;
+    }
+    CHK((gmres_cycle<VT, zd>(F, V, ldv, p, Y, ldy, tol, mr, maxit, false, r0n, run, s)));
+  }
+  if (run.pending) run.worst = std::max(run.worst, run.pend_worst);
   HIPC(hipStreamSynchronize(s));
   if (st) {
-    st->n_gmres = m;
-    st->worst_resid = worst;
-    st->breakdown = exhausted ? 1 : 0;
+    st->n_gmres = run.total;
+    st->worst_resid = run.worst;
+    st->breakdown = run.exhausted ? 1 : 0;
+    st->restarts = run.restarts;
   }
-  if (worst > tol && !exhausted) {
-    set_error("block GMRES reached %d steps with relative residual %.3e > %.3e", m, worst, tol);
+  if (run.worst > tol && !run.exhausted) {
+    set_error("block GMRES reached %d steps (%d restarts) with relative residual %.3e > %.3e", run.total,
+              run.restarts, run.worst, tol);
     return ZOLO_ENOCONV;
   }
   return ZOLO_OK;
@@ -2442,7 +2730,7 @@ zolo_status apply_G_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int ncols, 
 
 template <typename VT>
 zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int ncols, VT* d_Y, int64_t ldy, double tol,
-                             int maxit, zolo_filter_stats* st, hipStream_t s) {
+                             int maxit, int restart, zolo_filter_stats* st, hipStream_t s) {
   const int64_t n = F->P->n;
   DevArena tmp;
   VT *vn = nullptr, *yn = nullptr;
@@ -2451,10 +2739,10 @@ zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int nc
   rows_gather<VT>(vn, ncols, d_V, ldv, F->P->perm, n, ncols, s);
   zolo_status rc = ZOLO_OK;
   if (F->co.kind == ZOLO_FILTER_HYBRID) {
-    rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, st, s);
+    rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, restart, st, s);
   } else {
     CHK(rational_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, s));
-    if (st) *st = zolo_filter_stats{0, 0.0, 0};
+    if (st) *st = zolo_filter_stats{0, 0.0, 0, 0};
   }
   if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
   rows_scatter<VT>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
@@ -2557,16 +2845,18 @@ extern "C" zolo_status zolo_apply_G(zolo_factors* F, const double* d_V, int64_t 
 }
 
 extern "C" zolo_status zolo_filter_apply(zolo_factors* F, const double* d_V, int64_t ldv, int ncols, double* d_Y,
-                                         int64_t ldy, double tol, int maxit, zolo_filter_stats* st, void* stream) {
-  if (!F || !d_V || !d_Y || ncols <= 0 || ldv < ncols || ldy < ncols) {
+                                         int64_t ldy, double tol, int maxit, int restart, zolo_filter_stats* st,
+                                         void* stream) {
+  if (!F || !d_V || !d_Y || ncols <= 0 || ldv < ncols || ldy < ncols || restart < 0) {
     set_error("zolo_filter_apply: invalid argument");
     return ZOLO_EINVAL;
   }
   if (tol <= 0) tol = 1e-10;
   if (maxit <= 0) maxit = 60;
   hipStream_t s = as_stream(stream);
-  if (F->P->cplx()) return filter_apply_abi<zd>(F, (const zd*)d_V, ldv, ncols, (zd*)d_Y, ldy, tol, maxit, st, s);
-  return filter_apply_abi<double>(F, d_V, ldv, ncols, d_Y, ldy, tol, maxit, st, s);
+  if (F->P->cplx())
+    return filter_apply_abi<zd>(F, (const zd*)d_V, ldv, ncols, (zd*)d_Y, ldy, tol, maxit, restart, st, s);
+  return filter_apply_abi<double>(F, d_V, ldv, ncols, d_Y, ldy, tol, maxit, restart, st, s);
 }
 
 // ===========================================================================
@@ -2662,7 +2952,8 @@ zolo_status choose_r1(const zolo_pencil* P, zolo_opts* o, int nss) {
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
     const int maxit = o->max_gmres_iter > 0 ? o->max_gmres_iter : 60;
     while (r_mem > 1 &&
-           query_bytes_estimate(P, r_mem, nss, maxit, o->precision, o->block_cols) > (int64_t)(0.9 * (double)free_b))
+           query_bytes_estimate(P, r_mem, nss, maxit, o->gmres_restart, o->precision, o->block_cols) >
+               (int64_t)(0.9 * (double)free_b))
       --r_mem;
   }
   for (int r1 = 1; r1 <= r_mem; ++r1) {
@@ -2762,9 +3053,10 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   // the Krylov spaces are shared, and the basis needs pb, not nss, columns.
   const int nsub = o.block_cols > 0 ? (nss + o.block_cols - 1) / o.block_cols : 1;
   const int pb = (nss + nsub - 1) / nsub;
-  CHK(ensure_ws(F.get(), pb, maxit));
+  CHK(ensure_ws(F.get(), pb, o.gmres_restart > 0 && o.gmres_restart < maxit ? o.gmres_restart : maxit));
   // products of the Rayleigh-Ritz step: partial sums and descriptors only
   Workspace ws;
+  ws.ef = ST<VT>::cplx ? 2 : 1;
   ws.partial_len = std::max<int64_t>((int64_t)nss * nss * 256, 1 << 20);
   CHK(ws.mem.alloc(&ws.partial, ws.partial_len * (ST<VT>::cplx ? 2 : 1)));
   ws.gdesc_cap = 1024;
@@ -2819,7 +3111,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
       const int pc = std::min(pb, nss - b0);
       zolo_status rc = ZOLO_OK;
       if (co.kind == ZOLO_FILTER_HYBRID)
-        rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, &fs, s);
+        rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, o.gmres_restart, &fs, s);
       else
         CHK(rational_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, s));
       if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
@@ -2827,6 +3119,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
       st.n_gmres_total += fs.n_gmres;
       st.n_gmres_last = std::max(st.n_gmres_last, fs.n_gmres);
       st.gmres_resid = std::max(st.gmres_resid, fs.worst_resid);
+      st.n_restart += fs.restarts;
     }
     st.n_iter = it;
     // Rayleigh-Ritz
@@ -3244,20 +3537,26 @@ extern "C" void zolo_result_free(zolo_result* r) { delete r; }
 // ===========================================================================
 namespace zolo {
 
-int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols) {
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int restart, int precision,
+                             int block_cols) {
   const int64_t n = P->n;
   const int64_t elem = precision == ZOLO_PREC_FP64 ? 16 : 8;
   const int64_t lu = P->cplx() ? 2 : 1;  // LU: two panels and inverses; K^-1 and K^-H solves
   const int64_t vb = P->cplx() ? 16 : 8;  // bytes per block entry
   const int64_t factors = (int64_t)r1 * lu * (P->panel_total + P->inv_total + n) * elem;
   const int64_t factor_tmp = (int64_t)r1 * (P->upd_total + lu * (P->inv_scratch + P->conv_scratch)) * elem;
-  // the filter runs on column sub-blocks of p columns
+  // the filter runs on column sub-blocks of p columns; the basis holds mmax
+  // blocks, and a restarted real pencil continues on 2p columns (with a
+  // second solve program)
   const int64_t nsub = block_cols > 0 ? (nss + block_cols - 1) / block_cols : 1;
   const int64_t p = (nss + nsub - 1) / nsub;
-  const int64_t solve = (int64_t)r1 * lu * (6 * n * p) * elem;         // W, U, Xb, t, Y, X of the solve program
-  const int64_t krylov = ((int64_t)(maxit + 2) * n * p + 3 * n * p) * vb  // basis, W, T1, Tb
-                         + 2 * (int64_t)r1 * lu * n * p * 16;              // per-pole solutions and residuals
-  const int64_t subspace = 8 * n * (int64_t)nss * vb;                       // Q, Y, AY, BY, X, AX, BX, result
+  const bool restarts = restart > 0 && restart < maxit;
+  const int64_t mmax = restarts ? restart : maxit;
+  const int64_t pk = restarts && !P->cplx() ? 2 * p : p;
+  const int64_t solve = (int64_t)r1 * lu * (6 * n * (p + (pk > p ? pk : 0))) * elem;  // W, U, Xb, t, Y, X
+  const int64_t krylov = ((mmax + 2) * n * pk + 3 * n * pk) * vb                      // basis, W, T1, Tb
+                         + 2 * (int64_t)r1 * lu * n * pk * 16;                        // pole solutions, residuals
+  const int64_t subspace = 8 * n * (int64_t)nss * vb;  // Q, Y, AY, BY, X, AX, BX, result
   const int64_t total = factors + std::max(factor_tmp, solve + krylov) + subspace;
   return total + total / 10 + ((int64_t)64 << 20);
 }

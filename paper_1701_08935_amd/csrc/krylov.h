@@ -43,6 +43,19 @@ template <typename T>
 void hls_step(const HlsState& st, const T* H, int64_t ldh, int k, double* res, hipStream_t s);
 // Y_s = R_s^{-1} g_s (first mp rows), Y: per shift (m p) x p col-major ld m p
 void hls_backsolve(const HlsState& st, int m, zd* Y, hipStream_t s);
+// Restarted multi-shift block GMRES with collinear residuals:
+// g_s = G0_s (p x p col-major at G0 + s p p) in the first p rows, zero below
+void hls_init_multi(const HlsState& st, const zd* G0, hipStream_t s);
+// columns of Z (ld ldz, rows [0, (m+1)p)) times Q_s (adjoint: Q_s^H), Q_s the
+// product of shift s's reflectors of blocks 0..m-1; shift < 0: every shift, its
+// columns at Z + s zstride
+void hls_apply_q(const HlsState& st, int shift, int m, zd* Z, int64_t ldz, int64_t zstride, int ncols, bool adjoint,
+                 hipStream_t s);
+// g_s(0:mp, :) -= T_s(0:mp, :) W_s for every shift s != skip (T_s: (m+1)p x p
+// col-major at T + s tstride, W_s: p x p col-major at W + s p p)
+void hls_collinear_rhs(const HlsState& st, int m, const zd* T, int64_t tstride, const zd* W, int skip, hipStream_t s);
+// Er (rows x 2p col-major doubles): columns 2c, 2c + 1 = Re, Im of column c of Z (ld ldz)
+void cols_re_im(const zd* Z, int64_t ldz, int64_t rows, int p, double* Er, hipStream_t s);
 // C(i,c) = sum_s coef[s] * Y_s(i,c): real part for real pencils (double C),
 // complex for complex pencils (zd C).  C: (m p) x p col-major
 void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, double* C, hipStream_t s);

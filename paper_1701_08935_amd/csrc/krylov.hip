@@ -589,6 +589,87 @@ __global__ __launch_bounds__(64) void hls_backsolve_kernel(HlsState st, int m, z
   }
 }
 
+// ---- restarts (collinear residuals) ----
+// g_s = per-shift right-hand side G0_s (p x p col-major at G0 + s p p) in the
+// first p rows, zero below
+__global__ void hls_init_multi_kernel(HlsState st, const zd* __restrict__ G0) {
+  const int s = blockIdx.y;
+  const int64_t tot = st.ldr * st.p;
+  zd* g = st.g + (int64_t)s * tot;
+  const zd* g0 = G0 + (int64_t)s * st.p * st.p;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = e % st.ldr, c = e / st.ldr;
+    g[e] = (i < st.p) ? g0[i + c * st.p] : zd{0.0, 0.0};
+  }
+}
+
+// one wave per (column c, shift): Z_c <- Q_s Z_c (adjoint = 0: reflectors of the
+// first m blocks in reverse order) or Q_s^H Z_c (adjoint = 1: forward order);
+// rows [0, (m+1) p) of each column.  shift < 0: blockIdx.y is the shift and its
+// columns start at Z + y zstride; otherwise every column uses that one shift.
+__global__ __launch_bounds__(64) void hls_apply_q_kernel(HlsState st, int shift, int m, zd* __restrict__ Z,
+                                                          int64_t ldz, int64_t zstride, int adjoint) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int s = shift < 0 ? (int)blockIdx.y : shift;
+  const int p = st.p;
+  zd* col = Z + (shift < 0 ? (int64_t)blockIdx.y * zstride : 0) + (int64_t)c * ldz;
+  const zd* refl = st.refl + (int64_t)s * st.mmax * p * (p + 1);
+  const double* tau = st.tau + (int64_t)s * st.mmax * p;
+  const int nref = m * p;
+  for (int r = 0; r < nref; ++r) {
+    const int idx = adjoint ? r : nref - 1 - r;  // reflector j p + q acts on rows [idx, idx + p]
+    const zd* v = refl + (int64_t)idx * (p + 1);
+    const double t = tau[idx];
+    const int i0 = (int)((lane - idx % 64 + 64) % 64);
+    double dr = 0.0, di = 0.0;
+    for (int i = i0; i <= p; i += 64) {
+      zd vv = v[i], x = col[idx + i];
+      dr += vv.re * x.re + vv.im * x.im;
+      di += vv.re * x.im - vv.im * x.re;
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double fr = t * dr, fi = t * di;
+    for (int i = i0; i <= p; i += 64) {
+      zd vv = v[i], x = col[idx + i];
+      x.re -= fr * vv.re - fi * vv.im;
+      x.im -= fr * vv.im + fi * vv.re;
+      col[idx + i] = x;
+    }
+  }
+}
+
+// g_s(i, c) -= sum_t T_s(i, t) W_s(t, c) for i < m p, every shift but `skip`
+// (T_s: (m+1) p x p col-major at T + s tstride; W_s: p x p col-major)
+__global__ void hls_collinear_rhs_kernel(HlsState st, int m, const zd* __restrict__ T, int64_t tstride,
+                                         const zd* __restrict__ Wc, int skip) {
+  const int s = blockIdx.y;
+  if (s == skip) return;
+  const int p = st.p;
+  const int64_t mp = (int64_t)m * p, ldt = (int64_t)(m + 1) * p;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp * p) return;
+  const int64_t i = e % mp;
+  const int c = (int)(e / mp);
+  const zd* Ts = T + (int64_t)s * tstride;
+  const zd* Ws = Wc + (int64_t)s * p * p;
+  zd acc{0.0, 0.0};
+  for (int t = 0; t < p; ++t) acc = fma_(acc, Ts[i + t * ldt], Ws[t + (int64_t)c * p]);
+  zd* g = st.g + (int64_t)s * st.ldr * p + (int64_t)c * st.ldr + i;
+  *g = sub(*g, acc);
+}
+
+// Er (rows x 2p col-major doubles): column 2c = Re Z(:, c), 2c + 1 = Im Z(:, c)
+__global__ void cols_re_im_kernel(const zd* __restrict__ Z, int64_t ldz, int64_t rows, int p, double* __restrict__ Er) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * p) return;
+  const int64_t i = e % rows;
+  const int c = (int)(e / rows);
+  const zd z = Z[i + (int64_t)c * ldz];
+  Er[i + (int64_t)(2 * c) * rows] = z.re;
+  Er[i + (int64_t)(2 * c + 1) * rows] = z.im;
+}
+
 __global__ void hls_combine_real_kernel(const zd* __restrict__ Y, int64_t mp, int p, int nshift,
                                         const double* __restrict__ coef, double* __restrict__ C) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1162,6 +1243,31 @@ void hls_step(const HlsState& st, const T* H, int64_t ldh, int k, double* res, h
 
 void hls_backsolve(const HlsState& st, int m, zd* Y, hipStream_t s) {
   hipLaunchKernelGGL(hls_backsolve_kernel, dim3(st.p, st.nshift), dim3(64), 0, s, st, m, Y);
+}
+
+void hls_init_multi(const HlsState& st, const zd* G0, hipStream_t s) {
+  hipLaunchKernelGGL(hls_init_multi_kernel, dim3(64, st.nshift), dim3(256), 0, s, st, G0);
+}
+
+void hls_apply_q(const HlsState& st, int shift, int m, zd* Z, int64_t ldz, int64_t zstride, int ncols, bool adjoint,
+                 hipStream_t s) {
+  if (ncols <= 0 || m <= 0) return;
+  hipLaunchKernelGGL(hls_apply_q_kernel, dim3(ncols, shift < 0 ? st.nshift : 1), dim3(64), 0, s, st, shift, m, Z, ldz,
+                     zstride, adjoint ? 1 : 0);
+}
+
+void hls_collinear_rhs(const HlsState& st, int m, const zd* T, int64_t tstride, const zd* W, int skip,
+                       hipStream_t s) {
+  const int64_t tot = (int64_t)m * st.p * st.p;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(hls_collinear_rhs_kernel, dim3((unsigned)((tot + 255) / 256), st.nshift), dim3(256), 0, s, st, m,
+                     T, tstride, W, skip);
+}
+
+void cols_re_im(const zd* Z, int64_t ldz, int64_t rows, int p, double* Er, hipStream_t s) {
+  const int64_t tot = rows * p;
+  if (tot == 0) return;
+  hipLaunchKernelGGL(cols_re_im_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Z, ldz, rows, p, Er);
 }
 
 void hls_combine(const zd* Y, int m, int p, int nshift, const double* coef, double* C, hipStream_t s) {

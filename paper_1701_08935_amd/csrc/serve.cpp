@@ -92,7 +92,7 @@ bool same_filter(const zolo_query* x, const zolo_query* y) {
          u.filter_eps == v.filter_eps && u.precision == v.precision && u.tol_resid == v.tol_resid &&
          u.tol_gmres == v.tol_gmres && u.max_subspace_iter == v.max_subspace_iter &&
          u.max_gmres_iter == v.max_gmres_iter && u.max_refine == v.max_refine && u.tol_refine == v.tol_refine &&
-         u.block_cols == v.block_cols && u.filter_kind == v.filter_kind;
+         u.block_cols == v.block_cols && u.filter_kind == v.filter_kind && u.gmres_restart == v.gmres_restart;
 }
 
 bool gaps_estimated(const zolo_opts& o) { return std::isnan(o.a_minus); }
@@ -149,7 +149,7 @@ constexpr int kInertiaShifts = 2;
 size_t batch_bytes(const zolo_query* h, int cols) {
   const int maxit = h->o.max_gmres_iter > 0 ? h->o.max_gmres_iter : 60;
   const int r1 = h->o.r1 > 0 ? h->o.r1 : 4;
-  size_t e = (size_t)zolo::query_bytes_estimate(h->P, r1, cols, maxit, h->o.precision, h->o.block_cols);
+  size_t e = (size_t)zolo::query_bytes_estimate(h->P, r1, cols, maxit, h->o.gmres_restart, h->o.precision, h->o.block_cols);
   if (std::isnan(h->o.a_minus))
     e = std::max(e, (size_t)(kInertiaShifts * zolo::inertia_shift_bytes(h->P)));
   return e;

@@ -83,7 +83,8 @@ void set_inertia_cap(int shifts);
 // device bytes of one real-shift factorization of the inertia count
 int64_t inertia_shift_bytes(const zolo_pencil* P);
 int plan_contour(int kind, double a, double b, int npole, zolo_filter_coeffs* out, char* err, size_t errlen);
-int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int precision, int block_cols);
+int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, int restart, int precision,
+                             int block_cols);
 int64_t pencil_n(const zolo_pencil* P);
 bool pencil_cplx(const zolo_pencil* P);
 zolo_result* result_clone(const zolo_result* r);
