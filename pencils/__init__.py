@@ -115,11 +115,13 @@ def _pattern(nx: int, ny: int, nz: int, stencil: int):
     return rowptr, cols.astype(np.int32), rows
 
 
-def grid7(n: int, seed_v: int = 0, ny: int | None = None, nz: int | None = None) -> GridPencil:
+def grid7(n: int, seed_v: int = 0, ny: int | None = None, nz: int | None = None, v_scale: float = 1.0) -> GridPencil:
     """Real 7-point pencil on an n x ny x nz grid (defaults: a cube).
 
-    A = stencil(6, -1) + diag(v), v ~ U[-1,1] drawn with numpy PCG64(seed_v);
-    B = I + 0.1*(I + face adjacency)/7.
+    A = stencil(6, -1) + diag(v_scale v), v ~ U[-1,1] drawn with numpy PCG64(seed_v);
+    B = I + 0.1*(I + face adjacency)/7.  v_scale = 0 on a cube gives A and B that
+    are polynomials in the same adjacency, so the pencil's eigenvalues are
+    degenerate (clusters of 3 and 6 from the permutations of the three directions).
     """
     ny = n if ny is None else ny
     nz = n if nz is None else nz
@@ -127,7 +129,7 @@ def grid7(n: int, seed_v: int = 0, ny: int | None = None, nz: int | None = None)
     rowptr, colind, rows = _pattern(n, ny, nz, 7)
     v = np.random.Generator(np.random.PCG64(seed_v)).uniform(-1.0, 1.0, size=N)
     diag = rows == colind
-    a_vals = np.where(diag, 6.0 + v[rows], -1.0)
+    a_vals = np.where(diag, 6.0 + v_scale * v[rows], -1.0)
     b_vals = np.where(diag, 1.0 + 0.1 / 7.0, 0.1 / 7.0)
     return GridPencil(N, rowptr, colind, a_vals.astype(np.float64), b_vals.astype(np.float64), (n, ny, nz), 7)
 
