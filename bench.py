@@ -439,13 +439,11 @@ def run_filters(n=64, leaf=128, tol_gmres=1e-8):
 
 def roofline(prof, steps, fp32=False, method_factor_flops=None, kernel=None):
     """Roofline of one kernel class: by default the class with the most summed
-    kernel time (the factorization products, which rocprofv3 also ranks first).
-    For the factorization products the algorithmic work is the elimination
-    alone (method_factor_flops per query: sum over fronts of 8 (k^3 - nb^3)/6
-    per pole, times r1), not the executed products, which also form the L11^-1
-    blocks and the solve panels.  The r1 poles are factored concurrently on r1
-    streams, so each launch's event interval also covers the other poles'
-    kernels sharing the device: the rate is a lower bound."""
+    kernel time (the dominant kernel).  For the factorization products the
+    algorithmic work is the elimination alone (method_factor_flops per query:
+    sum over fronts of 8 (k^3 - nb^3)/6 per pole, times r1), not the executed
+    products, which also form the L11^-1 blocks and the solve panels.  Every
+    factorization launch holds all r1 poles' products of one step."""
     if not prof:
         return None
     cand = {k: v for k, v in prof.items() if k in ("gemm_factor", "gemm_solve", "gemm_krylov", "spmm") and v["ms"] > 0}
@@ -647,6 +645,8 @@ def main():
         "t_symbolic_s": res["t_sym"],
         "roofline": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1,
                              method_factor_flops=res["pflops"]["elimination"] * st["r1"]),
+        "roofline_factor": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1,
+                                    method_factor_flops=res["pflops"]["elimination"] * st["r1"], kernel="gemm_factor"),
         "roofline_solve": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1, kernel="gemm_solve"),
         "spmm": spmm_rate(res["prof"]),
         "profile": res["prof"],

@@ -501,32 +501,34 @@ struct SplitPlan {
   int64_t part = 0, cnt = 0;                                    // sizes (real scalars, counters)
 };
 template <typename T>
-void plan_split(std::vector<GemmDesc<T>>& gd, GemmLaunch& g, SplitPlan* sp) {
+void plan_split(std::vector<GemmDesc<T>>& gd, GemmLaunch& g, SplitPlan* sp, int tag) {
   if (g.cnt <= 0 || g.maxM <= 0 || g.maxN <= 0) return;
-  const int tn = gemm_tile_n(g.maxN), tk = tn == 96 ? 8 : 16;
+  const int tk = gemm_tile_k(g.maxM, g.maxN, tag);
   // longest products first, so that the launch's last workgroups are short ones
   // (the products of a launch are independent; their order is free)
   std::stable_sort(gd.begin() + g.off, gd.begin() + g.off + g.cnt, [&](const GemmDesc<T>& x, const GemmDesc<T>& y) {
-    return (double)gemm_desc_tiles(x.M, x.N, x.flags, x.tri_off, g.maxN) * x.K >
-           (double)gemm_desc_tiles(y.M, y.N, y.flags, y.tri_off, g.maxN) * y.K;
+    return (double)gemm_desc_tiles(x.M, x.N, x.flags, x.tri_off, g.maxM, g.maxN, tag) * x.K >
+           (double)gemm_desc_tiles(y.M, y.N, y.flags, y.tri_off, g.maxM, g.maxN, tag) * y.K;
   });
   int64_t total = 0;
   g.grid_tiles = 0;
   for (int i = g.off; i < g.off + g.cnt; ++i) {
-    const int t = gemm_desc_tiles(gd[i].M, gd[i].N, gd[i].flags, gd[i].tri_off, g.maxN);
+    const int t = gemm_desc_tiles(gd[i].M, gd[i].N, gd[i].flags, gd[i].tri_off, g.maxM, g.maxN, tag);
     g.grid_tiles = std::max(g.grid_tiles, t);
     total += t;
   }
   if (total >= kSplitBelow) return;
   const int goal = (int)std::min<int64_t>(kMaxSplit, (kSplitTarget + total - 1) / std::max<int64_t>(total, 1));
-  const int64_t pe = gemm_part_elems(g.maxN, ST<T>::cplx);
+  const int64_t pe = gemm_part_elems(g.maxM, g.maxN, tag, ST<T>::cplx);
   int64_t po = 0, co = 0;
   for (int i = g.off; i < g.off + g.cnt; ++i) {
     GemmDesc<T>& d = gd[i];
     const int chunks = (d.K + tk - 1) / tk;
     const int S = std::min(goal, chunks / kMinSplitChunks);
     if (S < 2) continue;
-    const int64_t t = gemm_tiles(d.M, d.N);
+    // tiles of this product in the launch's tile shape (the counter and
+    // partial-sum slots its splits index)
+    const int64_t t = gemm_desc_tiles(d.M, d.N, 0, 0, g.maxM, g.maxN, tag);
     d.splitk = S;
     sp->at.push_back({i, {po, co}});
     po += (int64_t)S * t * pe;
@@ -548,7 +550,7 @@ void patch_split(std::vector<GemmDesc<T>>& gd, const SplitPlan& sp, typename ST<
 template <typename VT>
 int gemm_tn(Workspace& ws, const VT* X, int64_t ldx, const VT* Y, int64_t ldy, int64_t N, int m, int n, VT* out,
             int64_t ldo, bool add, hipStream_t s) {
-  int tiles = gemm_tiles(m, n);
+  int tiles = gemm_tiles(m, n, 2);
   int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
   // partial_len counts entries of the workspace's own block type (ef doubles)
   const int64_t cap = ws.partial_len * ws.ef / (ST<VT>::cplx ? 2 : 1);
@@ -1229,14 +1231,16 @@ namespace {
 // (synchronous host work); factor_step only enqueues kernels on a stream, a
 // few launches at a time, so several poles run concurrently on their own streams.
 struct FactorLevelG {
-  std::vector<GemmLaunch> trsm;   // per step J: panel rows below the diagonal block
-  std::vector<GemmLaunch> trail;  // per step J
+  std::vector<GemmLaunch> trsm;       // per step J: panel rows below the diagonal block
+  std::vector<GemmLaunch> trail;      // per step J: columns up to the end of its outer block
+  std::vector<GemmLaunch> trail_out;  // per step J: at an outer block's end, the columns after it
   GemmLaunch schur;
   std::vector<GemmLaunch> inv1, inv2;  // per block row I >= 1
   GemmLaunch conv;                     // -L21 L11^-1 of every front (solve panel, lower part)
   int stk_off = 0, stk_cnt = 0;        // stacking of the solve panels
   int64_t stk_max = 0;                 // largest ns (panel columns) of the level
 };
+// one pole's temporaries
 template <typename T>
 struct FactorWork {
   DevArena tmp;
@@ -1244,41 +1248,55 @@ struct FactorWork {
   T* scratch = nullptr;
   T* ctmp = nullptr;  // -L21 L11^-1 of one level's fronts before stacking
   int* flag = nullptr;
+};
+// The factorization program of all poles: every launch runs one step of every
+// pole (the GEMM launches hold all poles' products, the front kernels take the
+// pole as a grid dimension), on one stream.
+template <typename T>
+struct FactorProg {
+  DevArena mem;
   GemmDesc<T>* dgd = nullptr;
   StackDesc<T>* dstk = nullptr;
+  PoleBase<T>* dpb = nullptr;
   std::vector<FactorLevelG> lg;
-  double sr = 0.0, si = 0.0;
+  int np = 0;
   bool pivots_only = false;  // inertia counts: D alone, no L11^-1 blocks or solve panels
 };
 
 template <typename T>
-zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, PoleMF<T>* pole, FactorWork<T>* fw) {
+zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs* co_, std::vector<PoleMF<T>>& poles,
+                        std::vector<std::unique_ptr<FactorWork<T>>>& fws, FactorProg<T>* prog) {
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
   const bool lu = P->cplx();
-  CHK(F->mem.alloc(&pole->panel, P->panel_total));
-  CHK(F->mem.alloc(&pole->inv, P->inv_total));
-  CHK(F->mem.alloc(&pole->dvec, P->n));
-  F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
-  if (lu) {
-    CHK(F->mem.alloc(&pole->upanel, P->panel_total));
-    CHK(F->mem.alloc(&pole->uinv, P->inv_total));
-    CHK(F->mem.alloc(&pole->dconj, P->n));
+  const int np = (int)poles.size();
+  std::vector<PoleBase<T>> pb(np);
+  for (int jp = 0; jp < np; ++jp) {
+    PoleMF<T>* pole = &poles[jp];
+    FactorWork<T>* fw = fws[jp].get();
+    CHK(F->mem.alloc(&pole->panel, P->panel_total));
+    CHK(F->mem.alloc(&pole->inv, P->inv_total));
+    CHK(F->mem.alloc(&pole->dvec, P->n));
     F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
+    if (lu) {
+      CHK(F->mem.alloc(&pole->upanel, P->panel_total));
+      CHK(F->mem.alloc(&pole->uinv, P->inv_total));
+      CHK(F->mem.alloc(&pole->dconj, P->n));
+      F->bytes += (int64_t)sizeof(T) * (P->panel_total + P->inv_total + P->n);
+    }
+    DevArena& tmp = fw->tmp;
+    CHK(tmp.alloc(&fw->upd, P->upd_total));
+    CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch * (lu ? 2 : 1), 1)));
+    CHK(tmp.alloc(&fw->ctmp, std::max<int64_t>(P->conv_scratch * (lu ? 2 : 1), 1)));
+    CHK(tmp.alloc(&fw->flag, 1));
+    pb[jp] = PoleBase<T>{pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, fw->upd, fw->flag,
+                         co_->sigma_hat_re[jp], co_->sigma_hat_im[jp]};
   }
-  fw->sr = sr;
-  fw->si = si;
-  DevArena& tmp = fw->tmp;
-  CHK(tmp.alloc(&fw->upd, P->upd_total));
-  CHK(tmp.alloc(&fw->scratch, std::max<int64_t>(P->inv_scratch * (lu ? 2 : 1), 1)));
-  CHK(tmp.alloc(&fw->ctmp, std::max<int64_t>(P->conv_scratch * (lu ? 2 : 1), 1)));
-  CHK(tmp.alloc(&fw->flag, 1));
-  T* upd = fw->upd;
-  T* scratch = fw->scratch;
-  // GEMM descriptors of the whole program (pointers into this pole's arrays)
+  // GEMM descriptors of the whole program: every launch holds the products of
+  // all poles (each pole's descriptors point into its own arrays)
   std::vector<GemmDesc<T>> gd;
   std::vector<StackDesc<T>> stk;
-  std::vector<FactorLevelG>& lg = fw->lg;
+  std::vector<FactorLevelG>& lg = prog->lg;
   lg.assign(nl, FactorLevelG());
   const T one = ST<T>::one(), mone = neg(ST<T>::one()), zero = ST<T>::zero();
   for (int L = 0; L < nl; ++L) {
@@ -1294,7 +1312,9 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     for (int J = 0; J < maxns; J += FB) {
       GemmLaunch g;
       g.off = (int)gd.size();
+      for (int jp = 0; jp < np; ++jp)
       for (int f : fs) {
+        const PoleMF<T>* pole = &poles[jp];
         const Front& Fr = S.fronts[f];
         if (Fr.ns <= J) continue;
         const int jb = std::min(FB, Fr.ns - J);
@@ -1327,53 +1347,77 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       g.cnt = (int)gd.size() - g.off;
       lg[L].trsm.push_back(g);
     }
-    // trailing updates inside the panel, per step J
+    // trailing updates inside the panel, per step J, blocked in two levels: step
+    // J updates only the columns of its outer block of FOB columns, and the
+    // last step of an outer block updates every column after it with the
+    // whole outer block at once (inner dimension FOB instead of FB)
+    auto trail_desc = [&](const PoleMF<T>* pole, const Front& Fr, int f, int side, int c0, int kc, int c1,
+                          GemmLaunch* g) {
+      // rows and columns from c0 on, columns below c1, rank kc from columns c0 - kc
+      const int64_t k = (int64_t)Fr.ns + Fr.nb;
+      T* Pn = pole->panel + P->panel_off[f];
+      T* Un = lu ? pole->upanel + P->panel_off[f] : Pn;
+      // LDL^T: L(r0:, r0:) -= L(r0:, J) D L(r0:, J)^T; LU: the same for L with U^T
+      // on the right, and for U^T with L on the right
+      T* Cb = side == 0 ? Pn : Un;
+      T* Bb = side == 0 ? Un : Pn;
+      const int J = c0 - kc;
+      GemmDesc<T> d{};
+      d.C = Cb + c0 + (int64_t)c0 * k;
+      d.Cin = d.C;
+      d.ldc = d.ldcin = k;
+      d.A = Cb + c0 + (int64_t)J * k;
+      d.lda = k;
+      d.B = Bb + c0 + (int64_t)J * k;
+      d.ldb = k;
+      d.dk = pole->dvec + Fr.first + J;
+      d.M = (int)(k - c0);
+      d.N = c1 - c0;
+      d.K = kc;
+      d.flags = GF_TRANSB | GF_TRI;
+      d.tri_off = 0;
+      d.alpha = mone;
+      d.beta = one;
+      gd.push_back(d);
+      gemm_work(d, &g->flops, &g->bytes);
+      g->maxM = std::max(g->maxM, d.M);
+      g->maxN = std::max(g->maxN, d.N);
+    };
     for (int J = 0; J < maxns; J += FB) {
-      GemmLaunch g;
+      const int Jo = J / FOB * FOB;
+      GemmLaunch g, go;
       g.off = (int)gd.size();
-      for (int f : fs) {
-        const Front& Fr = S.fronts[f];
-        int jb = std::min(FB, Fr.ns - J);
-        if (Fr.ns <= J + jb) continue;
-        int64_t k = (int64_t)Fr.ns + Fr.nb;
-        T* Pn = pole->panel + P->panel_off[f];
-        T* Un = lu ? pole->upanel + P->panel_off[f] : Pn;
-        const int r0 = J + jb;
-        // LDL^T: L(r0:, r0:) -= L(r0:, J) D L(r0:, J)^T; LU: the same for L with U^T
-        // on the right, and for U^T with L on the right
-        for (int side = 0; side < (lu ? 2 : 1); ++side) {
-          T* Cb = side == 0 ? Pn : Un;
-          T* Bb = side == 0 ? Un : Pn;
-          GemmDesc<T> d{};
-          d.C = Cb + r0 + (int64_t)r0 * k;
-          d.Cin = d.C;
-          d.ldc = d.ldcin = k;
-          d.A = Cb + r0 + (int64_t)J * k;
-          d.lda = k;
-          d.B = Bb + r0 + (int64_t)J * k;
-          d.ldb = k;
-          d.dk = pole->dvec + Fr.first + J;
-          d.M = (int)(k - r0);
-          d.N = Fr.ns - r0;
-          d.K = jb;
-          d.flags = GF_TRANSB | GF_TRI;
-          d.tri_off = 0;
-          d.alpha = mone;
-          d.beta = one;
-          gd.push_back(d);
-          gemm_work(d, &g.flops, &g.bytes);
-          g.maxM = std::max(g.maxM, d.M);
-          g.maxN = std::max(g.maxN, d.N);
+      for (int jp = 0; jp < np; ++jp)
+        for (int f : fs) {
+          const Front& Fr = S.fronts[f];
+          const int jb = std::min(FB, Fr.ns - J);
+          if (Fr.ns <= J + jb) continue;
+          const int r0 = J + jb, c1 = std::min(Fr.ns, Jo + FOB);
+          if (c1 > r0)
+            for (int side = 0; side < (lu ? 2 : 1); ++side) trail_desc(&poles[jp], Fr, f, side, r0, jb, c1, &g);
         }
-      }
       g.cnt = (int)gd.size() - g.off;
+      go.off = (int)gd.size();
+      for (int jp = 0; jp < np; ++jp)
+        for (int f : fs) {
+          const Front& Fr = S.fronts[f];
+          const int jb = std::min(FB, Fr.ns - J);
+          if (Fr.ns <= J + jb || J + jb != Jo + FOB) continue;  // only at the end of a full outer block
+          for (int side = 0; side < (lu ? 2 : 1); ++side)
+            trail_desc(&poles[jp], Fr, f, side, Jo + FOB, FOB, Fr.ns, &go);
+        }
+      go.cnt = (int)gd.size() - go.off;
       lg[L].trail.push_back(g);
+      lg[L].trail_out.push_back(go);
     }
     // Schur complement update U -= L21 D L21^T (lower)
     {
       GemmLaunch g;
       g.off = (int)gd.size();
+      for (int jp = 0; jp < np; ++jp)
       for (int f : fs) {
+        const PoleMF<T>* pole = &poles[jp];
+        T* upd = fws[jp]->upd;
         const Front& Fr = S.fronts[f];
         if (Fr.nb == 0) continue;
         int64_t k = (int64_t)Fr.ns + Fr.nb;
@@ -1413,7 +1457,10 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
       GemmLaunch g1, g2;
       g1.off = (int)gd.size();
       std::vector<GemmDesc<T>> second;
+      for (int jp = 0; jp < np; ++jp)
       for (int side = 0; side < (lu ? 2 : 1); ++side) {
+        const PoleMF<T>* pole = &poles[jp];
+        T* scratch = fws[jp]->scratch;
         int64_t so = 0;
         for (int f : fs) {
           const Front& Fr = S.fronts[f];
@@ -1478,6 +1525,9 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     {
       GemmLaunch g;
       g.off = (int)gd.size();
+      for (int jp = 0; jp < np; ++jp) {
+      const PoleMF<T>* pole = &poles[jp];
+      FactorWork<T>* fw = fws[jp].get();
       int64_t co = 0;
       for (int side = 0; side < (lu ? 2 : 1); ++side)
         for (int f : fs) {
@@ -1510,6 +1560,7 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
           g.maxN = std::max(g.maxN, d.N);
           co += (int64_t)Fr.nb * Fr.ns;
         }
+      }
       g.cnt = (int)gd.size() - g.off;
       lg[L].conv = g;
       lg[L].stk_cnt = (int)stk.size() - lg[L].stk_off;
@@ -1518,13 +1569,15 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
   // inner-dimension splits of launches with few tiles
   SplitPlan sp;
   for (FactorLevelG& l : lg) {
-    for (GemmLaunch& g : l.trsm) plan_split(gd, g, &sp);
-    for (GemmLaunch& g : l.trail) plan_split(gd, g, &sp);
-    plan_split(gd, l.schur, &sp);
-    for (GemmLaunch& g : l.inv1) plan_split(gd, g, &sp);
-    for (GemmLaunch& g : l.inv2) plan_split(gd, g, &sp);
-    plan_split(gd, l.conv, &sp);
+    for (GemmLaunch& g : l.trsm) plan_split(gd, g, &sp, 0);
+    for (GemmLaunch& g : l.trail) plan_split(gd, g, &sp, 0);
+    for (GemmLaunch& g : l.trail_out) plan_split(gd, g, &sp, 0);
+    plan_split(gd, l.schur, &sp, 0);
+    for (GemmLaunch& g : l.inv1) plan_split(gd, g, &sp, 0);
+    for (GemmLaunch& g : l.inv2) plan_split(gd, g, &sp, 0);
+    plan_split(gd, l.conv, &sp, 0);
   }
+  DevArena& tmp = prog->mem;
   if (!sp.at.empty()) {
     typename ST<T>::real* part = nullptr;
     int* cnt = nullptr;
@@ -1533,14 +1586,16 @@ zolo_status factor_plan(zolo_factors* F, zolo_pencil* P, double sr, double si, P
     HIPC(hipMemset(cnt, 0, sizeof(int) * sp.cnt));
     patch_split(gd, sp, part, cnt);
   }
-  CHK(tmp.upload(&fw->dgd, gd.data(), gd.size()));
-  CHK(tmp.upload(&fw->dstk, stk.data(), stk.size()));
+  CHK(tmp.upload(&prog->dgd, gd.data(), gd.size()));
+  CHK(tmp.upload(&prog->dstk, stk.data(), stk.size()));
+  CHK(tmp.upload(&prog->dpb, pb.data(), pb.size()));
+  prog->np = np;
   return ZOLO_OK;
 }
 
-// Where one pole's factorization program stands: level L, and within it the
-// stage (0 assembly and extend-add, 1 diagonal-block chain, 2 Schur update,
-// 3 inverse doubling, 4 conversion and panel stacking) and the index inside a
+// Where the factorization program stands: level L, and within it the stage
+// (0 assembly and extend-add, 1 diagonal-block chain, 2 Schur update, 3
+// inverse doubling, 4 conversion and panel stacking) and the index inside a
 // multi-launch stage.
 struct FactorCursor {
   int L = -1;  // -1: buffers not cleared yet
@@ -1549,29 +1604,28 @@ struct FactorCursor {
   bool done = false;
 };
 
-// Enqueue the next short group of launches of one pole's factorization on s
-// and advance the cursor.  The poles' groups are enqueued round-robin, so that
-// every pole's stream has work queued from the start: a pole enqueued whole
-// before the next fills the device queue, and the host then blocks until it
-// drains, holding back the other poles.
+// Enqueue the next short group of launches of the program on s and advance
+// the cursor.
 template <typename T>
-zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipStream_t s, FactorCursor* c) {
+zolo_status factor_step(zolo_pencil* P, std::vector<PoleMF<T>>& poles, std::vector<std::unique_ptr<FactorWork<T>>>& fws,
+                        const FactorProg<T>& prog, hipStream_t s, FactorCursor* c) {
   const Symbolic& S = P->S;
   const int nl = (int)S.levels.size();
-  T* upd = fw->upd;
-  int* flag = fw->flag;
-  const GemmDesc<T>* dgd = fw->dgd;
-  const std::vector<FactorLevelG>& lg = fw->lg;
-  const double sr = fw->sr, si = fw->si;
+  const int np = prog.np;
+  const GemmDesc<T>* dgd = prog.dgd;
+  const std::vector<FactorLevelG>& lg = prog.lg;
   const bool lu = P->cplx();
   if (c->done) return ZOLO_OK;
   if (c->L < 0) {
-    HIPC(hipMemsetAsync(flag, 0, sizeof(int), s));
-    HIPC(hipMemsetAsync(pole->panel, 0, sizeof(T) * P->panel_total, s));
-    HIPC(hipMemsetAsync(pole->inv, 0, sizeof(T) * P->inv_total, s));
-    if (lu) {
-      HIPC(hipMemsetAsync(pole->upanel, 0, sizeof(T) * P->panel_total, s));
-      HIPC(hipMemsetAsync(pole->uinv, 0, sizeof(T) * P->inv_total, s));
+    for (int j = 0; j < np; ++j) {
+      const PoleMF<T>& pole = poles[j];
+      HIPC(hipMemsetAsync(fws[j]->flag, 0, sizeof(int), s));
+      HIPC(hipMemsetAsync(pole.panel, 0, sizeof(T) * P->panel_total, s));
+      HIPC(hipMemsetAsync(pole.inv, 0, sizeof(T) * P->inv_total, s));
+      if (lu) {
+        HIPC(hipMemsetAsync(pole.upanel, 0, sizeof(T) * P->panel_total, s));
+        HIPC(hipMemsetAsync(pole.uinv, 0, sizeof(T) * P->inv_total, s));
+      }
     }
     c->L = 0;
     c->stage = 0;
@@ -1585,21 +1639,22 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
       prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
       const int64_t na = P->lvl_asm_end[L] - P->lvl_asm_begin[L];
       if (P->lvl_upd_end[L] > P->lvl_upd_begin[L])  // this level's update blocks start from zero
-        HIPC(hipMemsetAsync(upd + P->lvl_upd_begin[L], 0, sizeof(T) * (P->lvl_upd_end[L] - P->lvl_upd_begin[L]), s));
+        for (int j = 0; j < np; ++j)
+          HIPC(hipMemsetAsync(fws[j]->upd + P->lvl_upd_begin[L], 0,
+                              sizeof(T) * (P->lvl_upd_end[L] - P->lvl_upd_begin[L]), s));
       if (lu) {
         // asm_src holds the CSR entry (j, i) for the lower position (i, j) (equal for symmetric
         // matrices); the L panel takes (i, j) itself, the transposed U panel takes (j, i)
-        front_assemble_cplx<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src_t + P->lvl_asm_begin[L], na,
-                               P->za, P->zb, sr, si, s);
-        front_assemble_cplx<T>(pole->upanel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L], na,
-                               P->za, P->zb, sr, si, s);
+        front_assemble_cplx<T>(prog.dpb, np, false, P->asm_dst + P->lvl_asm_begin[L],
+                               P->asm_src_t + P->lvl_asm_begin[L], na, P->za, P->zb, s);
+        front_assemble_cplx<T>(prog.dpb, np, true, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L],
+                               na, P->za, P->zb, s);
         for (const GemmLaunch& g : P->lvl_ext[L])
-          front_extend_add_lu<T>(pole->panel, pole->upanel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+          front_extend_add_lu<T>(prog.dpb, np, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
       } else {
-        front_assemble<T>(pole->panel, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L], na, P->pa,
-                          P->pb, sr, si, s);
-        for (const GemmLaunch& g : P->lvl_ext[L])
-          front_extend_add<T>(pole->panel, upd, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
+        front_assemble<T>(prog.dpb, np, P->asm_dst + P->lvl_asm_begin[L], P->asm_src + P->lvl_asm_begin[L], na, P->pa,
+                          P->pb, s);
+        for (const GemmLaunch& g : P->lvl_ext[L]) front_extend_add<T>(prog.dpb, np, P->pmap, P->ext + g.off, g.cnt, g.tiles, s);
       }
       c->stage = 1;
       c->idx = 0;
@@ -1614,13 +1669,14 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
         {
           prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
           if (lu)
-            front_diag_block_lu<T>(pole->panel, pole->upanel, pole->inv, pole->uinv, pole->dvec, dd, nd, J, flag, s);
+            front_diag_block_lu<T>(prog.dpb, np, dd, nd, J, s);
           else
-            front_diag_block<T>(pole->panel, pole->inv, pole->dvec, dd, nd, J, flag, s);
+            front_diag_block<T>(prog.dpb, np, dd, nd, J, s);
         }
         // LDL^T: L21 = F21 L11^-T D^-1; LU: L21 = F21 U11^-1 D^-1 and U12^T = F12^T L11^-T D^-1
         run_gemm<T>(dgd, lg[L].trsm[jj], s, 0);
         run_gemm<T>(dgd, lg[L].trail[jj], s, 0);
+        run_gemm<T>(dgd, lg[L].trail_out[jj], s, 0);
         ++c->idx;
       }
       if (c->idx >= P->lvl_diag_nJ[L].size()) {
@@ -1633,7 +1689,7 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
       run_gemm<T>(dgd, lg[L].schur, s, 0);
       c->stage = 3;
       c->idx = 0;
-      if (fw->pivots_only) {  // the next level needs only the update blocks
+      if (prog.pivots_only) {  // the next level needs only the update blocks
         c->stage = 0;
         if (++c->L >= nl) c->done = true;
       }
@@ -1655,12 +1711,13 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
       run_gemm<T>(dgd, lg[L].conv, s, 0);
       {
         prof::Scope ps(ZOLO_PROF_FRONT_OTHER, 0.0, 0.0, s);
-        front_stack<T>(fw->dstk + lg[L].stk_off, lg[L].stk_cnt, lg[L].stk_max, s);
+        front_stack<T>(prog.dstk + lg[L].stk_off, lg[L].stk_cnt, lg[L].stk_max, s);
       }
       c->stage = 0;
       c->idx = 0;
       if (++c->L >= nl) {
-        if (lu) conj_copy(pole->dconj, pole->dvec, P->n, s);
+        if (lu)
+          for (int j = 0; j < np; ++j) conj_copy(poles[j].dconj, poles[j].dvec, P->n, s);
         c->done = true;
       }
       break;
@@ -1670,60 +1727,21 @@ zolo_status factor_step(zolo_pencil* P, PoleMF<T>* pole, FactorWork<T>* fw, hipS
   return ZOLO_OK;
 }
 
-// all poles: plan each, run each on its own stream, wait, check pivots
+// all poles: one program whose launches run every pole, on the caller's
+// stream; wait, check pivots
 template <typename T>
 zolo_status factor_all(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs* co, std::vector<PoleMF<T>>* poles,
                        hipStream_t s, bool pivots_only = false) {
   const int np = co->r1;
   poles->assign(np, PoleMF<T>());
   std::vector<std::unique_ptr<FactorWork<T>>> fw(np);
-  for (int j = 0; j < np; ++j) {
-    fw[j].reset(new FactorWork<T>());
-    fw[j]->pivots_only = pivots_only;
-    CHK(factor_plan<T>(F, P, co->sigma_hat_re[j], co->sigma_hat_im[j], &(*poles)[j], fw[j].get()));
-  }
-  // pole 0 on the caller's stream, the others on streams of their own that
-  // start after the work already queued on it and end before it continues
-  std::vector<hipStream_t> ss(np, s);
-  std::vector<hipEvent_t> ev;
-  zolo_status rc = ZOLO_OK;
-  hipEvent_t start = nullptr;
-  HIPC(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-  HIPC(hipEventRecord(start, s));
-  for (int j = 1; j < np && rc == ZOLO_OK; ++j) {
-    if (hipStreamCreateWithFlags(&ss[j], hipStreamNonBlocking) != hipSuccess) {
-      ss[j] = s;
-      continue;
-    }
-    if (hipStreamWaitEvent(ss[j], start, 0) != hipSuccess) rc = ZOLO_EDEVICE;
-  }
-  std::vector<FactorCursor> cur(np);
-  for (bool left = true; left && rc == ZOLO_OK;) {
-    left = false;
-    for (int j = 0; j < np && rc == ZOLO_OK; ++j) {
-      if (cur[j].done) continue;
-      rc = factor_step<T>(P, &(*poles)[j], fw[j].get(), ss[j], &cur[j]);
-      left = left || !cur[j].done;
-    }
-  }
-  for (int j = 1; j < np; ++j) {
-    if (ss[j] == s) continue;
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
-      (void)hipEventRecord(e, ss[j]);
-      (void)hipStreamWaitEvent(s, e, 0);
-      ev.push_back(e);
-    }
-  }
-  hipError_t se = hipStreamSynchronize(s);
-  for (int j = 1; j < np; ++j)
-    if (ss[j] != s) {
-      (void)hipStreamSynchronize(ss[j]);
-      (void)hipStreamDestroy(ss[j]);
-    }
-  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  (void)hipEventDestroy(start);
-  if (rc != ZOLO_OK) return rc;
+  for (int j = 0; j < np; ++j) fw[j].reset(new FactorWork<T>());
+  FactorProg<T> prog;
+  prog.pivots_only = pivots_only;
+  CHK(factor_plan<T>(F, P, co, *poles, fw, &prog));
+  FactorCursor cur;
+  while (!cur.done) CHK(factor_step<T>(P, *poles, fw, prog, s, &cur));
+  const hipError_t se = hipStreamSynchronize(s);
   if (se != hipSuccess) {
     set_error("HIP error in the factorization: %s", hipGetErrorString(se));
     return ZOLO_EDEVICE;
@@ -2019,8 +2037,8 @@ zolo_status build_solve_prog(zolo_factors* F, int p, SolveProg<T>* G, const std:
   // inner-dimension splits of launches with few tiles (the top levels)
   SplitPlan sp;
   for (int L = 0; L < nl; ++L) {
-    plan_split(gd, G->fw[L], &sp);
-    plan_split(gd, G->bw[L], &sp);
+    plan_split(gd, G->fw[L], &sp, 1);
+    plan_split(gd, G->bw[L], &sp, 1);
   }
   if (!sp.at.empty()) {
     typename ST<T>::real* part = nullptr;

@@ -8,6 +8,7 @@
 namespace zolo {
 
 constexpr int FB = 64;  // block size of the blocked partial factorization
+constexpr int FOB = 256;  // outer block of the trailing updates (a multiple of FB)
 
 // One extend-add: child contribution block (nb_c x nb_c, column-major, lower
 // triangle) into the parent front (panel k_p x ns_p col-major + update block
@@ -36,33 +37,51 @@ struct SolveDesc {
   int32_t first, ns, nb, k;
 };
 
+// A pole's arrays for the factorization kernels, which run one step for a
+// batch of poles at once (the pole is the last grid dimension; pb is a device
+// array of np entries): its panels, diagonal-block inverses, pivots, update
+// blocks, breakdown flag and shift sigma = sr + i si.
+template <typename T>
+struct PoleBase {
+  T* panel;
+  T* upanel;  // LU only
+  T* inv;
+  T* uinv;    // LU only
+  T* dvec;
+  T* upd;
+  int* flag;
+  double sr, si;
+};
+
 // assembly: panel[dst[e]] = a[src[e]] - sigma * b[src[e]]  (real pencil values)
 template <typename T>
-void front_assemble(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const double* a, const double* b,
-                    double sig_re, double sig_im, hipStream_t s);
+void front_assemble(const PoleBase<T>* pb, int np, const int64_t* dst, const int64_t* src, int64_t n, const double* a,
+                    const double* b, hipStream_t s);
 
 template <typename T>
-void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb, hipStream_t s);
+void front_extend_add(const PoleBase<T>* pb, int np, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
+                      hipStream_t s);
 
 // Factor the FB x FB (or smaller) diagonal block at step J of each listed front,
 // write L (unit lower, strictly lower part), D (into dvec at first + J + c and the
-// panel diagonal) and the inverse of the unit lower block into the inverse array.
+// panel diagonal) and the inverse of the unit lower block into the inverse array;
+// a zero pivot sets the pole's flag.
 template <typename T>
-void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s);
+void front_diag_block(const PoleBase<T>* pb, int np, const DiagDesc* d, int nd, int J, hipStream_t s);
 
 // LU fronts of complex Hermitian pencils (no pivoting).  Each front keeps an
 // L panel (k x ns: the front's lower part) and a U panel of the same layout
 // holding the transpose of its upper part, so L, U^T, their diagonal-block
-// inverses and D are laid out as in the LDL^T case.
+// inverses and D are laid out as in the LDL^T case.  upper: assemble into the
+// U panels.
 template <typename T>
-void front_assemble_cplx(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const zd* a, const zd* b,
-                         double sr, double si, hipStream_t s);
+void front_assemble_cplx(const PoleBase<T>* pb, int np, bool upper, const int64_t* dst, const int64_t* src, int64_t n,
+                         const zd* a, const zd* b, hipStream_t s);
 template <typename T>
-void front_extend_add_lu(T* panel, T* upanel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
+void front_extend_add_lu(const PoleBase<T>* pb, int np, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
                          hipStream_t s);
 template <typename T>
-void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
-                         int* breakdown, hipStream_t s);
+void front_diag_block_lu(const PoleBase<T>* pb, int np, const DiagDesc* d, int nd, int J, hipStream_t s);
 
 // Forward right-hand sides of one level for np solves at once.  Row r of the
 // level's W (its fronts' k x p blocks one after the other, row-major; solve j

@@ -8,12 +8,17 @@
 namespace zolo {
 namespace {
 
+// Every kernel of the factorization runs the same step for a batch of poles
+// at once: the pole is the last grid dimension and pb[pole] its arrays.
 template <typename T>
-__global__ void assemble_kernel(T* __restrict__ panel, const int64_t* __restrict__ dst, const int64_t* __restrict__ src,
-                                int64_t n, const double* __restrict__ a, const double* __restrict__ b, double sr,
-                                double si) {
+__global__ void assemble_kernel(const PoleBase<T>* __restrict__ pb, const int64_t* __restrict__ dst,
+                                const int64_t* __restrict__ src, int64_t n, const double* __restrict__ a,
+                                const double* __restrict__ b) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  const PoleBase<T>& q = pb[blockIdx.y];
+  T* panel = q.panel;
+  const double sr = q.sr, si = q.si;
   int64_t s = src[e];
   double av = a[s], bv = b[s];
   zd v{av - sr * bv, -si * bv};
@@ -22,11 +27,14 @@ __global__ void assemble_kernel(T* __restrict__ panel, const int64_t* __restrict
 
 // complex Hermitian pencils: a, b interleaved complex values
 template <typename T>
-__global__ void assemble_cplx_kernel(T* __restrict__ panel, const int64_t* __restrict__ dst,
+__global__ void assemble_cplx_kernel(const PoleBase<T>* __restrict__ pb, bool upper, const int64_t* __restrict__ dst,
                                      const int64_t* __restrict__ src, int64_t n, const zd* __restrict__ a,
-                                     const zd* __restrict__ b, double sr, double si) {
+                                     const zd* __restrict__ b) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  const PoleBase<T>& q = pb[blockIdx.y];
+  T* panel = upper ? q.upanel : q.panel;
+  const double sr = q.sr, si = q.si;
   int64_t s = src[e];
   zd av = a[s], bv = b[s];
   zd v{av.re - (sr * bv.re - si * bv.im), av.im - (sr * bv.im + si * bv.re)};
@@ -38,9 +46,13 @@ __global__ void assemble_cplx_kernel(T* __restrict__ panel, const int64_t* __res
 // (upper part, stored transposed so that it is laid out like L), or its
 // update block.
 template <typename T>
-__global__ void extend_add_lu_kernel(T* __restrict__ panel, T* __restrict__ upanel, T* __restrict__ upd,
-                                     const int32_t* __restrict__ pmap, const ExtDesc* __restrict__ descs) {
+__global__ void extend_add_lu_kernel(const PoleBase<T>* __restrict__ pb, const int32_t* __restrict__ pmap,
+                                     const ExtDesc* __restrict__ descs) {
   const ExtDesc d = descs[blockIdx.y];
+  const PoleBase<T>& q = pb[blockIdx.z];
+  T* panel = q.panel;
+  T* upanel = q.upanel;
+  T* upd = q.upd;
   const int64_t nb = d.nb_c;
   const int64_t j = blockIdx.x;
   if (j >= nb) return;
@@ -63,9 +75,12 @@ __global__ void extend_add_lu_kernel(T* __restrict__ panel, T* __restrict__ upan
 }
 
 template <typename T>
-__global__ void extend_add_kernel(T* __restrict__ panel, T* __restrict__ upd, const int32_t* __restrict__ pmap,
+__global__ void extend_add_kernel(const PoleBase<T>* __restrict__ pb, const int32_t* __restrict__ pmap,
                                   const ExtDesc* __restrict__ descs) {
   const ExtDesc d = descs[blockIdx.y];
+  const PoleBase<T>& q = pb[blockIdx.z];
+  T* panel = q.panel;
+  T* upd = q.upd;
   const int64_t nb = d.nb_c;
   // column j of the child block handled by blockIdx.x, rows by threads
   const int64_t j = blockIdx.x;
@@ -127,11 +142,16 @@ __device__ inline zf sel(bool c, zf a, zf b) { return zf{c ? a.re : b.re, c ? a.
 __device__ inline double sel(bool c, double a, double b) { return c ? a : b; }
 
 template <typename T, bool LU>
-__global__ __launch_bounds__(256) void diag_blocked_kernel(T* __restrict__ panel, T* __restrict__ upanel,
-                                                           T* __restrict__ inv, T* __restrict__ uinv,
-                                                           T* __restrict__ dvec, const DiagDesc* __restrict__ descs,
-                                                           int J, int* breakdown) {
+__global__ __launch_bounds__(256) void diag_blocked_kernel(const PoleBase<T>* __restrict__ pb,
+                                                           const DiagDesc* __restrict__ descs, int J) {
   const DiagDesc d = descs[blockIdx.x];
+  const PoleBase<T>& q = pb[blockIdx.y];
+  T* panel = q.panel;
+  T* upanel = q.upanel;
+  T* inv = q.inv;
+  T* uinv = q.uinv;
+  T* dvec = q.dvec;
+  int* breakdown = q.flag;
   if (J >= d.ns) return;
   const int jb = (d.ns - J) < FB ? (d.ns - J) : FB;
   __shared__ T A[FB][FB + 1];
@@ -479,47 +499,45 @@ __global__ __launch_bounds__(256) void stack_kernel(const StackDesc<T>* __restri
 }  // namespace
 
 template <typename T>
-void front_assemble(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const double* a, const double* b,
-                    double sr, double si, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, panel, dst, src, n, a, b,
-                     sr, si);
+void front_assemble(const PoleBase<T>* pb, int np, const int64_t* dst, const int64_t* src, int64_t n, const double* a,
+                    const double* b, hipStream_t s) {
+  if (n <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)((n + 255) / 256), np), dim3(256), 0, s, pb, dst, src, n, a,
+                     b);
 }
 
 template <typename T>
-void front_assemble_cplx(T* panel, const int64_t* dst, const int64_t* src, int64_t n, const zd* a, const zd* b,
-                         double sr, double si, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(assemble_cplx_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, panel, dst, src, n,
-                     a, b, sr, si);
+void front_assemble_cplx(const PoleBase<T>* pb, int np, bool upper, const int64_t* dst, const int64_t* src, int64_t n,
+                         const zd* a, const zd* b, hipStream_t s) {
+  if (n <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(assemble_cplx_kernel<T>, dim3((unsigned)((n + 255) / 256), np), dim3(256), 0, s, pb, upper, dst,
+                     src, n, a, b);
 }
 
 template <typename T>
-void front_extend_add_lu(T* panel, T* upanel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
+void front_extend_add_lu(const PoleBase<T>* pb, int np, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
                          hipStream_t s) {
-  if (nd <= 0 || max_nb <= 0) return;
-  hipLaunchKernelGGL(extend_add_lu_kernel<T>, dim3(max_nb, nd), dim3(256), 0, s, panel, upanel, upd, pmap, d);
+  if (nd <= 0 || max_nb <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(extend_add_lu_kernel<T>, dim3(max_nb, nd, np), dim3(256), 0, s, pb, pmap, d);
 }
 
 template <typename T>
-void front_diag_block_lu(T* panel, T* upanel, T* inv, T* uinv, T* dvec, const DiagDesc* d, int nd, int J,
-                         int* breakdown, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL((diag_blocked_kernel<T, true>), dim3(nd), dim3(256), 0, s, panel, upanel, inv, uinv, dvec, d, J,
-                     breakdown);
+void front_diag_block_lu(const PoleBase<T>* pb, int np, const DiagDesc* d, int nd, int J, hipStream_t s) {
+  if (nd <= 0 || np <= 0) return;
+  hipLaunchKernelGGL((diag_blocked_kernel<T, true>), dim3(nd, np), dim3(256), 0, s, pb, d, J);
 }
 
 template <typename T>
-void front_extend_add(T* panel, T* upd, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb, hipStream_t s) {
-  if (nd <= 0 || max_nb <= 0) return;
-  hipLaunchKernelGGL(extend_add_kernel<T>, dim3(max_nb, nd), dim3(256), 0, s, panel, upd, pmap, d);
+void front_extend_add(const PoleBase<T>* pb, int np, const int32_t* pmap, const ExtDesc* d, int nd, int max_nb,
+                      hipStream_t s) {
+  if (nd <= 0 || max_nb <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(extend_add_kernel<T>, dim3(max_nb, nd, np), dim3(256), 0, s, pb, pmap, d);
 }
 
 template <typename T>
-void front_diag_block(T* panel, T* inv, T* dvec, const DiagDesc* d, int nd, int J, int* breakdown, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL((diag_blocked_kernel<T, false>), dim3(nd), dim3(256), 0, s, panel, nullptr, inv, nullptr, dvec,
-                     d, J, breakdown);
+void front_diag_block(const PoleBase<T>* pb, int np, const DiagDesc* d, int nd, int J, hipStream_t s) {
+  if (nd <= 0 || np <= 0) return;
+  hipLaunchKernelGGL((diag_blocked_kernel<T, false>), dim3(nd, np), dim3(256), 0, s, pb, d, J);
 }
 
 template <typename Ts, typename T>
@@ -546,14 +564,15 @@ void front_stack(const StackDesc<T>* d, int nd, int64_t max_cols, hipStream_t s)
 }
 
 #define INST(T)                                                                                                      \
-  template void front_assemble<T>(T*, const int64_t*, const int64_t*, int64_t, const double*, const double*, double, \
-                                  double, hipStream_t);                                                              \
-  template void front_extend_add<T>(T*, T*, const int32_t*, const ExtDesc*, int, int, hipStream_t);                  \
-  template void front_assemble_cplx<T>(T*, const int64_t*, const int64_t*, int64_t, const zd*, const zd*, double,    \
-                                       double, hipStream_t);                                                         \
-  template void front_extend_add_lu<T>(T*, T*, T*, const int32_t*, const ExtDesc*, int, int, hipStream_t);           \
-  template void front_diag_block_lu<T>(T*, T*, T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);            \
-  template void front_diag_block<T>(T*, T*, T*, const DiagDesc*, int, int, int*, hipStream_t);                       \
+  template void front_assemble<T>(const PoleBase<T>*, int, const int64_t*, const int64_t*, int64_t, const double*,   \
+                                  const double*, hipStream_t);                                                        \
+  template void front_extend_add<T>(const PoleBase<T>*, int, const int32_t*, const ExtDesc*, int, int, hipStream_t);  \
+  template void front_assemble_cplx<T>(const PoleBase<T>*, int, bool, const int64_t*, const int64_t*, int64_t,        \
+                                       const zd*, const zd*, hipStream_t);                                            \
+  template void front_extend_add_lu<T>(const PoleBase<T>*, int, const int32_t*, const ExtDesc*, int, int,             \
+                                       hipStream_t);                                                                  \
+  template void front_diag_block_lu<T>(const PoleBase<T>*, int, const DiagDesc*, int, int, hipStream_t);             \
+  template void front_diag_block<T>(const PoleBase<T>*, int, const DiagDesc*, int, int, hipStream_t);                \
   template void solve_gather_back<T>(T*, const T*, const T*, const int32_t*, const SolveDesc*, int, int, int,        \
                                      hipStream_t);                                                                   \
   template void front_stack<T>(const StackDesc<T>*, int, int64_t, hipStream_t);

@@ -63,17 +63,18 @@ struct GemmDesc {
   T alpha, beta;
 };
 
-// Tile shape the launcher picks: 64 rows; 96 columns when the launch's
-// largest N is in (64, 96], else 64.
-int gemm_tile_m(int maxM);
-int gemm_tile_n(int maxN);
-// workgroups per product (and per split) of a launch with these bounds
-int gemm_tiles(int maxM, int maxN);
+// Tile shape the launcher picks for a launch of tag `tag` whose products are
+// at most maxM x maxN: 64 rows; 96 columns when maxN is in (64, 96], else 64.
+int gemm_tile_m(int maxM, int maxN, int tag);
+int gemm_tile_n(int maxM, int maxN, int tag);
+int gemm_tile_k(int maxM, int maxN, int tag);  // inner chunk of that shape
+// workgroups of one maxM x maxN product (per split) in such a launch
+int gemm_tiles(int maxM, int maxN, int tag);
 // real scalars of partial sums one split of one tile writes
-int64_t gemm_part_elems(int maxN, bool cplx);
-// workgroups (per split) one descriptor needs in a launch whose widest product
-// has maxN columns: its tiles, or only those holding kept entries for GF_TRI
-int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxN);
+int64_t gemm_part_elems(int maxM, int maxN, int tag, bool cplx);
+// workgroups (per split) one M x N descriptor needs in a launch with bounds
+// maxM x maxN: its tiles, or only those holding kept entries for GF_TRI
+int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxM, int maxN, int tag);
 
 // d_desc: device array of n descriptors; maxM / maxN: upper bounds of every
 // descriptor's M and N (they size the grid and select the tile shape);

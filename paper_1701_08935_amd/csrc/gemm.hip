@@ -526,15 +526,20 @@ void launch_cfg(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_
 
 }  // namespace
 
-int gemm_tile_m(int) { return 64; }
-int gemm_tile_n(int maxN) { return (maxN > 64 && maxN <= 96) ? 96 : 64; }
-int gemm_tiles(int maxM, int maxN) {
-  const int tm = gemm_tile_m(maxM), tn = gemm_tile_n(maxN);
+// The tag is part of the interface so that a use class can get shapes of its
+// own; every class shares these today.
+int gemm_tile_m(int, int, int) { return 64; }
+int gemm_tile_n(int, int maxN, int) { return (maxN > 64 && maxN <= 96) ? 96 : 64; }
+int gemm_tile_k(int maxM, int maxN, int tag) { return gemm_tile_n(maxM, maxN, tag) == 96 ? 8 : 16; }
+int gemm_tiles(int maxM, int maxN, int tag) {
+  const int tm = gemm_tile_m(maxM, maxN, tag), tn = gemm_tile_n(maxM, maxN, tag);
   return ((maxM + tm - 1) / tm) * ((maxN + tn - 1) / tn);
 }
-int64_t gemm_part_elems(int maxN, bool cplx) { return (int64_t)64 * gemm_tile_n(maxN) * (cplx ? 2 : 1); }
-int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxN) {
-  const int tn = gemm_tile_n(maxN);
+int64_t gemm_part_elems(int maxM, int maxN, int tag, bool cplx) {
+  return (int64_t)gemm_tile_m(maxM, maxN, tag) * gemm_tile_n(maxM, maxN, tag) * (cplx ? 2 : 1);
+}
+int gemm_desc_tiles(int M, int N, int flags, int tri_off, int maxM, int maxN, int tag) {
+  const int tn = gemm_tile_n(maxM, maxN, tag);
   const int tilesM = (M + 63) / 64, tilesN = (N + tn - 1) / tn;
   if (!(flags & GF_TRI)) return tilesM * tilesN;
   int n = 0;
@@ -547,7 +552,7 @@ template <typename T>
 void gemm_batched(const GemmDesc<T>* d_desc, int n, int maxM, int maxN, hipStream_t s, int tag, int max_split,
                   int grid_tiles) {
   if (n <= 0 || maxM <= 0 || maxN <= 0) return;
-  if (gemm_tile_n(maxN) == 64)
+  if (gemm_tile_n(maxM, maxN, tag) == 64)
     launch_cfg<T, 64, 64>(d_desc, n, maxM, maxN, s, tag, max_split, grid_tiles);
   else
     launch_cfg<T, 64, 96>(d_desc, n, maxM, maxN, s, tag, max_split, grid_tiles);
