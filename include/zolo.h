@@ -97,7 +97,7 @@ typedef struct {
                               all four NaN: estimated by inertia counts on the device */
   int r1;                  /* number of factorizations (inner order); 0 = fewest
                               (<= 4) giving an outer modulus l2 >= 0.2, and no more
-                              than half the free device memory holds               */
+                              than the free device memory holds                    */
   int r2;                  /* outer order; 0 = smallest r2 with delta0 <= filter_eps */
   double filter_eps;       /* target delta0 when r2 == 0 (Remark after Algorithm 2) */
   int n_ss;                /* subspace size; 0 = ceil(1.5 n_lambda_est)             */

@@ -99,18 +99,25 @@ class DevicePool {
       }
     return nullptr;
   }
-  // keeps the block for reuse while the cache stays under kCacheCap (a block
-  // that would exceed it is freed; the caller has synchronized the device)
+  // keeps the block for reuse while the cache stays under its cap, three
+  // quarters of the device's memory (a block that would exceed it is freed;
+  // the caller has synchronized the device).  Mapping fresh device memory
+  // costs about 45 GB/s, so a query that reallocates its ~100 GB of factors
+  // pays seconds; allocations that find too little free memory empty the
+  // cache first (DevArena::alloc).
   void give(void* p, size_t bytes, int dev) {
     std::lock_guard<std::mutex> lk(m_);
-    if (cached_ + bytes > kCacheCap) {
+    if (cap_ == 0) {
+      size_t fr = 0, tot = 0;
+      cap_ = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 4 * 3 : ((size_t)48 << 30);
+    }
+    if (cached_ + bytes > cap_) {
       (void)hipFree(p);
       return;
     }
     free_.insert({bytes, {dev, p}});
     cached_ += bytes;
   }
-  static constexpr size_t kCacheCap = (size_t)48 << 30;
   // Device-memory budget per device (0 = none): blocks handed out to arenas
   // and not yet released count against it.
   bool charge(int dev, size_t bytes) {
@@ -132,6 +139,13 @@ class DevicePool {
     std::lock_guard<std::mutex> lk(m_);
     return (dev >= 0 && dev < kDev) ? budget_[dev] : 0;
   }
+  size_t cached(int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    size_t c = 0;
+    for (const auto& kv : free_)
+      if (kv.second.first == dev) c += kv.first;
+    return c;
+  }
   size_t in_use(int dev) {
     std::lock_guard<std::mutex> lk(m_);
     return (dev >= 0 && dev < kDev) ? in_use_[dev] : 0;
@@ -144,12 +158,29 @@ class DevicePool {
     free_.clear();
     cached_ = 0;
   }
+  // frees cached blocks of device dev, largest first, until `need` bytes are
+  // released (the rest of the cache stays for the next queries)
+  void trim_for(size_t need, int dev) {
+    std::lock_guard<std::mutex> lk(m_);
+    if (free_.empty()) return;
+    (void)hipDeviceSynchronize();
+    size_t got = 0;
+    for (auto it = free_.end(); it != free_.begin() && got < need;) {
+      --it;
+      if (it->second.first != dev) continue;
+      (void)hipFree(it->second.second);
+      got += it->first;
+      cached_ -= it->first;
+      it = free_.erase(it);
+    }
+  }
 
  private:
   static constexpr int kDev = 64;
   std::mutex m_;
   std::multimap<size_t, std::pair<int, void*>> free_;  // block size -> (device, pointer)
   size_t cached_ = 0;
+  size_t cap_ = 0;  // set at the first release
   size_t budget_[kDev] = {};
   size_t in_use_[kDev] = {};
 };
@@ -186,9 +217,10 @@ struct DevArena {
     void* p = DevicePool::get().take(bytes, dev);
     if (!p) {
       // keep room for the runtime's own allocations (kernel scratch, queues): when
-      // a new block would leave less than kReserve free, return the cache first
+      // a new block would leave less than kReserve free, return cached blocks first
       size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve) DevicePool::get().trim();
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr < bytes + kReserve)
+        DevicePool::get().trim_for(bytes + kReserve - fr, dev);
       hipError_t e = hipMalloc(&p, bytes);
       if (e != hipSuccess) {
         DevicePool::get().trim();
@@ -1856,7 +1888,6 @@ extern "C" zolo_status zolo_inertia(zolo_ctx* ctx, zolo_pencil* P, const double*
       counts[k0 + k] = neg;
     }
   }
-  DevicePool::get().trim();  // the shifts' factors are one-off: give their memory back
   return ZOLO_OK;
 }
 
@@ -2960,14 +2991,22 @@ zolo_status estimate_gaps(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int
 
 // r1 = 0 (Remark after Alg. 2 leaves the split open): the fewest inner poles
 // (factorizations, at most 4) whose inner error delta_1 leaves the outer modulus
-// l2 = (1 - delta_1)/(1 + delta_1) >= 0.2, so that the outer shifted systems
-// stay well separated from the spectrum of G and block GMRES needs few steps;
-// at most as many poles as leave half of the free device memory to the solves
-// and the Krylov basis.
+// l2 = (1 - delta_1)/(1 + delta_1) >= kMinL2.  Fewer poles are often faster on
+// this GPU (a factorization and a pole solve of the block cost more than the
+// extra block GMRES steps: grid7 64^3 window of 64, block 96, r1 = 1, 2, 3 take
+// 9, 7, 7 steps and 0.24, 0.32, 0.44 s per query), but at l2 near 0.01 the step
+// count can also run past the GMRES limit (complex 7 x 8 x 6 pencil sliced into
+// windows of 40: 60 steps, residual 5e-2), so the automatic choice keeps the
+// outer systems well separated.  At most as many poles as leave the free device
+// memory (cached blocks counted as free) to the solves and the Krylov basis.
+constexpr double kMinL2 = 0.2;
 zolo_status choose_r1(const zolo_pencil* P, zolo_opts* o, int nss) {
   size_t free_b = 0, total_b = 0;
   int r_mem = 4;
   if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    free_b += DevicePool::get().cached(dev);
     const int maxit = o->max_gmres_iter > 0 ? o->max_gmres_iter : 60;
     while (r_mem > 1 &&
            query_bytes_estimate(P, r_mem, nss, maxit, o->gmres_restart, o->precision, o->block_cols) >
@@ -2977,7 +3016,7 @@ zolo_status choose_r1(const zolo_pencil* P, zolo_opts* o, int nss) {
   for (int r1 = 1; r1 <= r_mem; ++r1) {
     zolo_filter_coeffs co;
     CHK(zolo_filter_plan(o->a_minus, o->a_plus, o->b_minus, o->b_plus, r1, o->r2, o->filter_eps, &co));
-    if (co.l2 >= 0.2 || r1 == r_mem) {
+    if (co.l2 >= kMinL2 || r1 == r_mem) {
       o->r1 = r1;
       return ZOLO_OK;
     }
