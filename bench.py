@@ -200,15 +200,17 @@ def run_serving(n_queries=48, rate=6.0, slots=4, seed=3, precision=0, tol_gmres=
             "mean_batch": float(np.mean(batches)) if batches else None, "wall_s": wall}
 
 
-def run_serving_c4(n_queries=32, rate=1.0, slots=4, seed=3, windows_per_pencil=3, tol_gmres=1e-8):
+def run_serving_c4(n_queries=32, rate=1.0, slots=4, seed=3, windows_per_pencil=3, tol_gmres=1e-8, precision=0,
+                   tol_refine=1e-5):
     """The serving workload's own shape: eight resident grid7 pencils 32^3 ... 80^3
     (N 32768 - 512000), a Poisson stream of interval queries (pencil uniform, n_lambda
     log-uniform in [8, 128], a few intervals per pencil so that filters repeat)
     giving only (a, b, n_lambda): eigengaps, counts and r1 are the library's
-    (inertia), factorizations stay resident for repeated filters.  FP64 factors
-    (mixed precision needs several refinement sweeps per step on windows this narrow
-    and loses to FP64).  Verification: status, residual <= 1e-8 and found = the
-    inertia count (the count of a window is the library's own: parity unpinned)."""
+    (inertia), factorizations stay resident for repeated filters.  precision 0: FP64
+    factors; 1: complex64 factors refined against FP64 residuals (the workload's
+    named form, slower here: several refinement sweeps per step on windows this
+    narrow).  Verification: status, residual <= 1e-8 and found = the inertia count
+    (the count of a window is the library's own: parity unpinned)."""
     import numpy as np
     import torch
 
@@ -229,7 +231,9 @@ def run_serving_c4(n_queries=32, rate=1.0, slots=4, seed=3, windows_per_pencil=3
         if dt > 0:
             time.sleep(dt)
         o = z.zolo_opts_default()
-        o.r1, o.tol_gmres, o.max_subspace_iter = 0, tol_gmres, 4
+        o.r1, o.tol_gmres, o.max_subspace_iter, o.precision = 0, tol_gmres, 4, precision
+        if precision == 1:
+            o.tol_refine = tol_refine
         handles.append(srv.submit(resident[q["grid"]], q["a"], q["b"], q["n_lambda"], o))
     counts, lat, batches, verified, bad, t_last, t_first = {}, [], [], 0, 0, 0.0, None
     rows = []
@@ -250,24 +254,32 @@ def run_serving_c4(n_queries=32, rate=1.0, slots=4, seed=3, windows_per_pencil=3
         ok = rc == 0 and st["max_resid"] <= 1e-8 and counts.get(key) == found
         verified += found if ok else 0
         bad += 0 if ok else 1
+        if not ok:
+            log(f"[serving-c4] unverified: grid {key[0]}^3 window {key[1]} rc={rc} found={found} "
+                f"count={counts.get(key)} resid={st['max_resid']:.2e} iter={st['n_iter']} gmres={st['n_gmres_total']} "
+                f"refine_missed={st['refine_missed']} refine_worst={st['refine_worst']:.1e}")
         lat.append(info["t_end"] - info["t_submit"])
         batches.append(info["batch"])
         t_last = max(t_last, info["t_end"])
         t_first = info["t_submit"] if t_first is None else min(t_first, info["t_submit"])
     inf = srv.info()
     srv.close()
+    fallbacks = sum(1 for _, _, st, _, _ in rows if st.get("precision_fallback", 0))
     wall = t_last - t_first if lat else float("nan")
-    log(f"[serving-c4] {len(lat)} queries, {verified} verified pairs in {wall:.1f}s, p50 {pct(lat, 0.5):.2f}s "
-        f"p99 {pct(lat, 0.99):.2f}s, hits {inf['factor_hits']} misses {inf['factor_misses']}, failed {bad}")
+    log(f"[serving-c4] {'mixed' if precision else 'fp64'} rate {rate} q/s: {len(lat)} queries, {verified} verified "
+        f"pairs in {wall:.1f}s, p50 {pct(lat, 0.5):.2f}s "
+        f"p99 {pct(lat, 0.99):.2f}s, hits {inf['factor_hits']} misses {inf['factor_misses']}, failed {bad}, "
+        f"FP64 fallbacks {fallbacks}")
     return {"workload": f"grid7 {pencils.C4_GRIDS[0]}^3 .. {pencils.C4_GRIDS[-1]}^3 (8 resident pencils, "
                         f"N 32768-512000), {n_queries} interval queries, {windows_per_pencil} intervals per pencil",
-            "queries": n_queries, "rate_qps": rate, "slots": slots, "precision": "fp64",
+            "queries": n_queries, "rate_qps": rate, "slots": slots, "precision": "mixed" if precision else "fp64",
             "eigenpairs_per_s": verified / wall if wall > 0 else None,
             "queries_per_s": len(lat) / wall if wall > 0 else None,
             "latency_s": {"p50": pct(lat, 0.5), "p99": pct(lat, 0.99)}, "failed_or_unverified": bad,
             "mean_batch": float(np.mean(batches)) if batches else None, "wall_s": wall, "setup_s": t_setup,
             "factor_hits": inf["factor_hits"], "factor_misses": inf["factor_misses"],
             "resident_factors": inf["resident_factors"], "resident_bytes": inf["resident_bytes"],
+            "precision_fallbacks": fallbacks,
             "count_note": "counts by the library's inertia; parity unpinned"}
 
 
@@ -562,6 +574,8 @@ def main():
     ap.add_argument("--no-e1", action="store_true", help="skip the Gaussian-well Hamiltonian 52^3 leg")
     ap.add_argument("--no-filters", action="store_true", help="skip the filter ablation (Zolo(r), CITZ, CIGQ)")
     ap.add_argument("--no-r1-sweep", action="store_true", help="skip the r1 = 1, 2, 3 sweep on the c1 window")
+    ap.add_argument("--no-c4-sweep", action="store_true", help="skip the 8-pencil stream at half and twice the rate")
+    ap.add_argument("--no-c4-mixed", action="store_true", help="skip the 8-pencil stream in mixed precision")
     ap.add_argument("--c3-grid", type=int, default=96, help="grid of the complex Hermitian leg")
     ap.add_argument("--c3-only", action="store_true", help="run only the complex Hermitian leg (one JSON line)")
     ap.add_argument("--tol-refine", type=float, default=1e-5,
@@ -680,6 +694,14 @@ def main():
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, tol_gmres=args.tol_gmres)
         out["serving_c4"] = run_serving_c4(args.c4_queries, args.c4_rate, tol_gmres=args.tol_gmres)
+        if not args.no_c4_sweep:
+            # the same stream at half and twice the rate the main leg runs at (its
+            # capacity is about 0.55 queries/s), fewer queries each
+            out["serving_c4_rates"] = [run_serving_c4(8, args.c4_rate / 2, tol_gmres=args.tol_gmres),
+                                       run_serving_c4(12, args.c4_rate * 2, tol_gmres=args.tol_gmres)]
+        if not args.no_c4_mixed:
+            out["serving_c4_mixed"] = run_serving_c4(12, args.c4_rate, tol_gmres=args.tol_gmres, precision=1,
+                                                     tol_refine=args.tol_refine)
     if c3 is not None:
         out["c3"] = c3
     if args.config == "c1" and not args.no_e1:

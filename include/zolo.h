@@ -149,6 +149,9 @@ typedef struct {
   double a_minus, a_plus, b_minus, b_plus;  /* the eigengaps the filter used        */
   int factors_reused;      /* 1: resident factors of an earlier query were used     */
   int n_restart;           /* block GMRES restarts summed over iterations           */
+  int precision_fallback;  /* 1: ZOLO_PREC_MIXED was asked, but the complex64 factors'
+                              refinement diverged (poles too close to the spectrum)
+                              and the query ran again with FP64 factors            */
 } zolo_stats;
 
 typedef struct zolo_ctx zolo_ctx;

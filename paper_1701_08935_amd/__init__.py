@@ -56,7 +56,7 @@ class zolo_stats(ctypes.Structure):
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
                 ("nnz_l", ctypes.c_longlong), ("factor_flops", _d), ("inertia_count", ctypes.c_longlong),
                 ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d),
-                ("factors_reused", _i), ("n_restart", _i)]
+                ("factors_reused", _i), ("n_restart", _i), ("precision_fallback", _i)]
 
 
 class zolo_kernel_profile(ctypes.Structure):

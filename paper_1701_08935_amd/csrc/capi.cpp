@@ -2427,6 +2427,13 @@ void householder_qr_host(const std::vector<std::complex<double>>& A, int64_t row
   }
 }
 
+// Internal status (never returned through the ABI): the complex64 factors'
+// refinement diverges (relative residual above 1 after the sweeps: kappa u_32
+// beyond 1 for poles this close to the spectrum), so the query must be run
+// again with FP64 factors.
+constexpr int kNeedFP64 = 100;
+bool refinement_diverged(const zolo_factors* F) { return F->precision == ZOLO_PREC_MIXED && F->refine_worst > 1.0; }
+
 // State of a restarted multi-shift block GMRES run across its cycles
 struct GmresRun {
   int total = 0, restarts = 0;
@@ -2479,6 +2486,11 @@ zolo_status gmres_cycle(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y,
     else  // G is real: the complex block is the real block of its 2p interleaved columns
       CHK(apply_G_new<double>(F, (const double*)(Vb + (int64_t)k * p), 2 * Mp, 2 * p, (double*)W, 2 * p, tol_inner,
                               s));
+    if (refinement_diverged(F)) {
+      set_error("complex64 factors: the refinement of the pole solves diverges (relative residual %.1e)",
+                F->refine_worst);
+      return (zolo_status)kNeedFP64;
+    }
     const int kp1 = (k + 1) * p;
     for (int pass = 0; pass < 2; ++pass) {
       CHK(gemm_tn<KT>(ws, Vb, Mp, W, p, n, kp1, p, hbuf, kp1, false, s));
@@ -2715,6 +2727,11 @@ template <typename VT>
 zolo_status rational_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y, int64_t ldy, hipStream_t s) {
   CHK(ensure_ws(F, p, 1));
   CHK(apply_G_new<VT>(F, V, ldv, p, Y, ldy, F->tol_refine, s));
+  if (refinement_diverged(F)) {
+    set_error("complex64 factors: the refinement of the pole solves diverges (relative residual %.1e)",
+              F->refine_worst);
+    return (zolo_status)kNeedFP64;
+  }
   if (F->co.kind == ZOLO_FILTER_ZOLO) axpby_rows<VT>(Y, ldy, V, ldv, 0.5, 0.5, F->P->n, p, s);
   return ZOLO_OK;
 }
@@ -2790,9 +2807,10 @@ zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int nc
   if (F->co.kind == ZOLO_FILTER_HYBRID) {
     rc = filter_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, tol, maxit, restart, st, s);
   } else {
-    CHK(rational_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, s));
+    rc = rational_apply_new<VT>(F, vn, ncols, ncols, yn, ncols, s);
     if (st) *st = zolo_filter_stats{0, 0.0, 0, 0};
   }
+  if (rc == kNeedFP64) return ZOLO_ENOCONV;  // the message says why; factor in FP64
   if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
   rows_scatter<VT>(d_Y, ldy, yn, ncols, F->P->perm, n, ncols, s);
   HIPC(hipStreamSynchronize(s));
@@ -3170,7 +3188,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
       if (co.kind == ZOLO_FILTER_HYBRID)
         rc = filter_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, tol_g, maxit, o.gmres_restart, &fs, s);
       else
-        CHK(rational_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, s));
+        rc = rational_apply_new<VT>(F.get(), Q + b0, nss, pc, Y + b0, nss, s);
       if (rc != ZOLO_OK && rc != ZOLO_ENOCONV) return rc;
       if (rc == ZOLO_ENOCONV) frc = rc;
       st.n_gmres_total += fs.n_gmres;
@@ -3384,8 +3402,22 @@ zolo_status solve_resident(zolo_ctx* ctx, zolo_pencil* P, double a, double b, in
     const int nss = o.n_ss > 0 ? o.n_ss : (int)std::max<int64_t>((int64_t)std::ceil(1.5 * std::max(n_for_ss, 1)), n_for_ss + 8);
     CHK(choose_r1(P, &o, (int)std::min<int64_t>(nss, P->n)));
   }
-  if (P->cplx()) return solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
-  return solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, F_in, F_keep);
+  auto run = [&](zolo_factors* fin) {
+    return P->cplx() ? solve_impl<zd>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, fin, F_keep)
+                     : solve_impl<double>(ctx, P, a, b, n_lambda_est, o, d_Q0, stream, out, gi, fin, F_keep);
+  };
+  zolo_status rc = run(F_in);
+  if ((int)rc == kNeedFP64) {
+    // complex64 factors useless for these poles: the same query with FP64 factors
+    if (F_keep && *F_keep) {
+      zolo_factors_free(*F_keep);
+      *F_keep = nullptr;
+    }
+    o.precision = ZOLO_PREC_FP64;
+    rc = run(nullptr);
+    if (*out) (*out)->st.precision_fallback = 1;
+  }
+  return rc;
 }
 
 const zolo_filter_coeffs* factors_coeffs(const zolo_factors* F) { return &F->co; }
