@@ -74,6 +74,18 @@ double now_s() {
 // hipMalloc / hipFree of their multi-gigabyte factors.  When hipMalloc fails
 // the cached blocks are freed and the allocation is tried once more.  The
 // cache is never destroyed (it lives until the process ends).
+// The stream a released block was used on and an event recorded there at its
+// release: the block is handed out again only once the event has completed,
+// whatever the new owner does with it first (kernels on any stream, or
+// synchronous copies and clears).
+struct ReleaseMark {
+  hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;
+  ~ReleaseMark() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
 class DevicePool {
  public:
   static DevicePool& get() {
@@ -87,16 +99,21 @@ class DevicePool {
     while (r < bytes) r <<= 1;
     return r;
   }
+  // a cached block of [bytes, 9/8 bytes] on device dev that is free of pending
+  // work: released after a device synchronization, or whose release event has
+  // completed
   void* take(size_t bytes, int dev) {
     std::lock_guard<std::mutex> lk(m_);
     auto it = free_.lower_bound(bytes);
-    for (; it != free_.end() && it->first <= bytes + bytes / 8; ++it)
-      if (it->second.first == dev) {
-        void* p = it->second.second;
-        cached_ -= it->first;
-        free_.erase(it);
-        return p;
-      }
+    for (; it != free_.end() && it->first <= bytes + bytes / 8; ++it) {
+      const Cached& c = it->second;
+      if (c.dev != dev) continue;
+      if (c.mark && hipEventQuery(c.mark->ev) != hipSuccess) continue;
+      void* p = c.p;
+      cached_ -= it->first;
+      free_.erase(it);
+      return p;
+    }
     return nullptr;
   }
   // keeps the block for reuse while the cache stays under its cap, three
@@ -105,17 +122,18 @@ class DevicePool {
   // costs about 45 GB/s, so a query that reallocates its ~100 GB of factors
   // pays seconds; allocations that find too little free memory empty the
   // cache first (DevArena::alloc).
-  void give(void* p, size_t bytes, int dev) {
+  void give(void* p, size_t bytes, int dev, const std::shared_ptr<ReleaseMark>& mark) {
     std::lock_guard<std::mutex> lk(m_);
     if (cap_ == 0) {
       size_t fr = 0, tot = 0;
       cap_ = hipMemGetInfo(&fr, &tot) == hipSuccess ? tot / 4 * 3 : ((size_t)48 << 30);
     }
     if (cached_ + bytes > cap_) {
+      if (mark) (void)hipEventSynchronize(mark->ev);
       (void)hipFree(p);
       return;
     }
-    free_.insert({bytes, {dev, p}});
+    free_.insert({bytes, Cached{dev, p, mark}});
     cached_ += bytes;
   }
   // Device-memory budget per device (0 = none): blocks handed out to arenas
@@ -143,7 +161,7 @@ class DevicePool {
     std::lock_guard<std::mutex> lk(m_);
     size_t c = 0;
     for (const auto& kv : free_)
-      if (kv.second.first == dev) c += kv.first;
+      if (kv.second.dev == dev) c += kv.first;
     return c;
   }
   size_t in_use(int dev) {
@@ -154,7 +172,7 @@ class DevicePool {
     std::lock_guard<std::mutex> lk(m_);
     if (free_.empty()) return;
     (void)hipDeviceSynchronize();
-    for (auto& kv : free_) (void)hipFree(kv.second.second);
+    for (auto& kv : free_) (void)hipFree(kv.second.p);
     free_.clear();
     cached_ = 0;
   }
@@ -167,8 +185,8 @@ class DevicePool {
     size_t got = 0;
     for (auto it = free_.end(); it != free_.begin() && got < need;) {
       --it;
-      if (it->second.first != dev) continue;
-      (void)hipFree(it->second.second);
+      if (it->second.dev != dev) continue;
+      (void)hipFree(it->second.p);
       got += it->first;
       cached_ -= it->first;
       it = free_.erase(it);
@@ -178,7 +196,12 @@ class DevicePool {
  private:
   static constexpr int kDev = 64;
   std::mutex m_;
-  std::multimap<size_t, std::pair<int, void*>> free_;  // block size -> (device, pointer)
+  struct Cached {
+    int dev;
+    void* p;
+    std::shared_ptr<ReleaseMark> mark;  // null: released after a device synchronization
+  };
+  std::multimap<size_t, Cached> free_;  // block size -> block
   size_t cached_ = 0;
   size_t cap_ = 0;  // set at the first release
   size_t budget_[kDev] = {};
@@ -194,12 +217,29 @@ struct DevArena {
     int dev;
   };
   std::vector<Block> ptrs;
+  // An arena whose blocks are used on one stream only (set_stream) hands them
+  // back with an event recorded on that stream, so its release waits for
+  // nothing; otherwise the release synchronizes the device first.
+  bool ordered = false;
+  hipStream_t stream = nullptr;
+  void set_stream(hipStream_t s) {
+    ordered = true;
+    stream = s;
+  }
   ~DevArena() { release(); }
   void release() {
     if (ptrs.empty()) return;
-    (void)hipDeviceSynchronize();  // no kernel may still use a block handed out again
+    std::shared_ptr<ReleaseMark> mark;
+    if (ordered) {
+      mark = std::make_shared<ReleaseMark>();
+      mark->stream = stream;
+      if (hipEventCreateWithFlags(&mark->ev, hipEventDisableTiming) != hipSuccess ||
+          hipEventRecord(mark->ev, stream) != hipSuccess)
+        mark.reset();
+    }
+    if (!mark) (void)hipDeviceSynchronize();  // no kernel may still use a block handed out again
     for (const Block& b : ptrs) {
-      DevicePool::get().give(b.p, b.bytes, b.dev);
+      DevicePool::get().give(b.p, b.bytes, b.dev, mark);
       DevicePool::get().uncharge(b.dev, b.bytes);
     }
     ptrs.clear();
@@ -1767,8 +1807,12 @@ zolo_status factor_all(zolo_factors* F, zolo_pencil* P, const zolo_filter_coeffs
   const int np = co->r1;
   poles->assign(np, PoleMF<T>());
   std::vector<std::unique_ptr<FactorWork<T>>> fw(np);
-  for (int j = 0; j < np; ++j) fw[j].reset(new FactorWork<T>());
+  for (int j = 0; j < np; ++j) {
+    fw[j].reset(new FactorWork<T>());
+    fw[j]->tmp.set_stream(s);
+  }
   FactorProg<T> prog;
+  prog.mem.set_stream(s);
   prog.pivots_only = pivots_only;
   CHK(factor_plan<T>(F, P, co, *poles, fw, &prog));
   FactorCursor cur;
@@ -2458,6 +2502,7 @@ zolo_status gmres_cycle(zolo_factors* F, const VT* V, int64_t ldv, int p, VT* Y,
   using cd = std::complex<double>;
   constexpr bool same = std::is_same<VT, KT>::value;  // false: a real pencil on a complex basis
   DevArena rmem;  // this cycle's restart buffers
+  rmem.set_stream(s);
   Workspace& ws = *F->ws;
   const int64_t n = F->P->n;
   const int64_t Mp = same ? ws.ldh : ws.ldh / 2;  // ld of the basis and rows of H, in KT
@@ -2690,6 +2735,7 @@ zolo_status filter_apply_new(zolo_factors* F, const VT* V, int64_t ldv, int p, V
     for (int i = 0; i <= c; ++i) r0n[c] += abs2(r0[i + c * p]);
   for (int c = 0; c < p; ++c) r0n[c] = std::sqrt(r0n[c]);
   GmresRun run;
+  run.mem.set_stream(s);
   CHK((gmres_cycle<VT, VT>(F, V, ldv, p, Y, ldy, tol, mr, maxit, true, r0n, run, s)));
   while (run.total < maxit) {
     if (run.done) {
@@ -2747,6 +2793,7 @@ template <typename VT>
 zolo_status spmm_abi(zolo_pencil* P, int which, const VT* d_X, int64_t ldx, int ncols, VT* d_Y, int64_t ldy,
                      hipStream_t s) {
   DevArena tmp;
+  tmp.set_stream(s);
   VT *xn = nullptr, *yn = nullptr;
   const int64_t n = P->n;
   CHK(tmp.alloc(&xn, n * ncols));
@@ -2768,6 +2815,7 @@ zolo_status pole_solve_abi(zolo_factors* F, int j, const VT* d_T, int64_t ldt, i
   CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
   const int64_t n = F->P->n;
   DevArena tmp;
+  tmp.set_stream(s);
   VT* tn = nullptr;
   CHK(tmp.alloc(&tn, n * ncols));
   rows_gather<VT>(tn, ncols, d_T, ldt, F->P->perm, n, ncols, s);
@@ -2783,6 +2831,7 @@ zolo_status apply_G_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int ncols, 
   CHK(ensure_ws(F, ncols, F->ws ? std::max(F->ws->mmax, 1) : 1));
   const int64_t n = F->P->n;
   DevArena tmp;
+  tmp.set_stream(s);
   VT *vn = nullptr, *wn = nullptr;
   CHK(tmp.alloc(&vn, n * ncols));
   CHK(tmp.alloc(&wn, n * ncols));
@@ -2799,6 +2848,7 @@ zolo_status filter_apply_abi(zolo_factors* F, const VT* d_V, int64_t ldv, int nc
                              int maxit, int restart, zolo_filter_stats* st, hipStream_t s) {
   const int64_t n = F->P->n;
   DevArena tmp;
+  tmp.set_stream(s);
   VT *vn = nullptr, *yn = nullptr;
   CHK(tmp.alloc(&vn, n * ncols));
   CHK(tmp.alloc(&yn, n * ncols));
@@ -2862,7 +2912,8 @@ extern "C" zolo_status zolo_residuals(zolo_pencil* P, const void* d_X, int64_t l
   CHK(residuals_check(P, d_X, ldx, ncols, d_lambda, d_out, "zolo_residuals"));
   if (ncols == 0) return ZOLO_OK;
   hipStream_t s = as_stream(stream);
-  DevArena tmp;  // released (after a device synchronization) on return
+  DevArena tmp;  // released on return, ordered after this call's kernels on s
+  tmp.set_stream(s);
   double* partial = nullptr;
   CHK(tmp.alloc(&partial, (size_t)kResidGroups * 2 * ncols));
   return residuals_run(P, d_X, ldx, ncols, d_lambda, d_out, partial, s);
@@ -3131,6 +3182,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   CHK(ensure_ws(F.get(), pb, o.gmres_restart > 0 && o.gmres_restart < maxit ? o.gmres_restart : maxit));
   // products of the Rayleigh-Ritz step: partial sums and descriptors only
   Workspace ws;
+  ws.mem.set_stream(s);
   ws.ef = ST<VT>::cplx ? 2 : 1;
   ws.partial_len = std::max<int64_t>((int64_t)nss * nss * 256, 1 << 20);
   CHK(ws.mem.alloc(&ws.partial, ws.partial_len * (ST<VT>::cplx ? 2 : 1)));
@@ -3142,6 +3194,7 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   }
   // subspace buffers (new ordering)
   DevArena mem;
+  mem.set_stream(s);
   VT *Q, *Y, *AY, *BY, *X, *AX, *BX, *At, *Bt, *Cm, *work, *Gx;
   double *theta, *rp, *rn;
   int* kdev;
