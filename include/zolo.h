@@ -119,6 +119,13 @@ typedef struct {
   int gmres_restart;       /* block GMRES restarts every this many steps (collinear
                               residuals, see zolo_filter_apply); the basis holds
                               that many blocks.  0 = no restart (max_gmres_iter)   */
+  int reuse_subspace;      /* serving only (zolo_submit), default 0.  1: the server
+                              keeps this query's eigenpairs resident, and answers it
+                              from the resident eigenpairs of an earlier query for
+                              the same result (pencil, interval, filter, tolerances
+                              and limits alike, subspace no larger) when their
+                              residuals, recomputed now, meet tol_resid
+                              (stats.subspace_reused); else it runs as usual       */
 } zolo_opts;
 
 typedef struct {
@@ -152,6 +159,9 @@ typedef struct {
   int precision_fallback;  /* 1: ZOLO_PREC_MIXED was asked, but the complex64 factors'
                               refinement diverged (poles too close to the spectrum)
                               and the query ran again with FP64 factors            */
+  int subspace_reused;     /* serving: 1 when the eigenpairs are a resident subspace
+                              of an earlier query for the same result; max_resid is
+                              then recomputed and t_total is the check's time       */
 } zolo_stats;
 
 typedef struct zolo_ctx zolo_ctx;
@@ -471,6 +481,10 @@ typedef struct {
   long long factor_hits;            /* runs that used a resident factorization */
   long long factor_misses;          /* runs that factored                     */
   int queued;
+  long long subspace_hits;          /* queries answered from a resident subspace
+                                       (eigenpairs of an earlier query for the
+                                       same result, residuals recomputed)      */
+  int resident_subspaces;
 } zolo_server_info;
 zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* out);
 /* frees a query handle; waits for the query if it is still queued or running */

@@ -44,7 +44,7 @@ class zolo_opts(ctypes.Structure):
                 ("filter_eps", _d), ("n_ss", _i), ("max_subspace_iter", _i), ("max_gmres_iter", _i),
                 ("tol_resid", _d), ("tol_gmres", _d), ("precision", _i), ("seed", ctypes.c_uint64),
                 ("max_refine", _i), ("tol_refine", _d), ("block_cols", _i), ("filter_kind", _i),
-                ("gmres_restart", _i)]
+                ("gmres_restart", _i), ("reuse_subspace", _i)]
 
 
 class zolo_stats(ctypes.Structure):
@@ -56,7 +56,7 @@ class zolo_stats(ctypes.Structure):
                 ("l1", _d), ("l2", _d), ("delta0", _d), ("factor_bytes", ctypes.c_longlong),
                 ("nnz_l", ctypes.c_longlong), ("factor_flops", _d), ("inertia_count", ctypes.c_longlong),
                 ("t_gaps", _d), ("a_minus", _d), ("a_plus", _d), ("b_minus", _d), ("b_plus", _d),
-                ("factors_reused", _i), ("n_restart", _i), ("precision_fallback", _i)]
+                ("factors_reused", _i), ("n_restart", _i), ("precision_fallback", _i), ("subspace_reused", _i)]
 
 
 class zolo_kernel_profile(ctypes.Structure):
@@ -75,7 +75,8 @@ class zolo_query_info(ctypes.Structure):
 class zolo_server_info(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_longlong), ("running_bytes", ctypes.c_longlong),
                 ("resident_factors", _i), ("resident_bytes", ctypes.c_longlong),
-                ("factor_hits", ctypes.c_longlong), ("factor_misses", ctypes.c_longlong), ("queued", _i)]
+                ("factor_hits", ctypes.c_longlong), ("factor_misses", ctypes.c_longlong), ("queued", _i),
+                ("subspace_hits", ctypes.c_longlong), ("resident_subspaces", _i)]
 
 
 class zolo_filter_stats(ctypes.Structure):

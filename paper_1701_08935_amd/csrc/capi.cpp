@@ -3721,6 +3721,34 @@ zolo_result* result_clone(const zolo_result* r) {
   return c.release();
 }
 
+int64_t result_bytes(const zolo_result* r) { return (int64_t)sizeof(double) * r->n * r->count * r->ef; }
+
+zolo_status result_verify(zolo_pencil* P, const zolo_result* r, void* stream, double* worst) {
+  *worst = 0.0;
+  if (r->count == 0) return ZOLO_OK;
+  hipStream_t s = as_stream(stream);
+  DevArena tmp;
+  tmp.set_stream(s);
+  double *dl = nullptr, *dout = nullptr;
+  CHK(tmp.alloc(&dl, r->count));
+  CHK(tmp.alloc(&dout, r->count));
+  HIPC(hipMemcpyAsync(dl, r->eig.data(), sizeof(double) * r->count, hipMemcpyHostToDevice, s));
+  for (int64_t c0 = 0; c0 < r->count; c0 += 512)  // the residual call's column limit
+    CHK(zolo_residuals(P, r->vec + c0 * r->ef, r->count, (int)std::min<int64_t>(512, r->count - c0), dl + c0,
+                       dout + c0, s));
+  std::vector<double> h(r->count);
+  HIPC(hipMemcpyAsync(h.data(), dout, sizeof(double) * r->count, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  for (double x : h) *worst = std::max(*worst, x);
+  return ZOLO_OK;
+}
+
+void result_mark_reused(zolo_result* r, double max_resid, double t_check) {
+  r->st.subspace_reused = 1;
+  r->st.max_resid = max_resid;
+  r->st.t_total = t_check;
+}
+
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out) { gaussian_host(seed, n, out); }
 
 }  // namespace zolo

@@ -3,8 +3,12 @@
 // (so queries overlap on the GPU).  Queued queries asking for the same result
 // (same pencil, interval, filter and tolerances) are answered by one run;
 // factorizations stay resident after their query and serve later queries of
-// the same filter (least recently used evicted first when admission needs the
-// memory).  The arithmetic is zolo_solve's; this file only schedules it.
+// the same filter.  Queries that opt in keep the eigenpairs (the subspace) they
+// returned resident too: a later such query asking for the same result gets
+// them back once their residuals, recomputed on the device, still meet its
+// tolerance.  Least recently used factorizations and subspaces are evicted
+// first when admission needs the memory.  The arithmetic is zolo_solve's; this
+// file only schedules it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,6 +16,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <list>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -67,6 +72,19 @@ struct FactorEntry {
   double last = 0.0;
 };
 
+// a resident subspace: the eigenpairs a finished query returned, for later
+// queries asking for the same result
+struct SubspaceEntry {
+  zolo_pencil* P = nullptr;
+  double a = 0.0, b = 0.0;
+  zolo_opts o{};
+  int nss = 0;  // subspace size of the run
+  zolo_result* res = nullptr;
+  size_t bytes = 0;
+  bool busy = false;
+  double last = 0.0;
+};
+
 struct zolo_server {
   zolo_ctx* ctx = nullptr;
   int device = 0;
@@ -77,22 +95,36 @@ struct zolo_server {
   bool stop = false;
   std::vector<std::thread> workers;
   std::vector<FactorEntry> fcache;  // resident factorizations (guarded by m)
-  size_t cached = 0;                // their bytes
-  long long hits = 0, misses = 0;
+  std::list<SubspaceEntry> scache;  // resident subspaces (guarded by m)
+  size_t cached = 0;                // bytes of both
+  long long hits = 0, misses = 0, sub_hits = 0;
 };
 
 namespace {
 
 // the same result: pencil, interval, filter, precision and every tolerance and limit
-bool same_filter(const zolo_query* x, const zolo_query* y) {
-  const zolo_opts &u = x->o, &v = y->o;
+bool same_request(const zolo_pencil* P1, double a1, double b1, const zolo_opts& u, const zolo_pencil* P2, double a2,
+                  double b2, const zolo_opts& v) {
   auto eq = [](double p, double q) { return p == q || (std::isnan(p) && std::isnan(q)); };
-  return x->P == y->P && x->a == y->a && x->b == y->b && eq(u.a_minus, v.a_minus) && eq(u.a_plus, v.a_plus) &&
+  return P1 == P2 && a1 == a2 && b1 == b2 && eq(u.a_minus, v.a_minus) && eq(u.a_plus, v.a_plus) &&
          eq(u.b_minus, v.b_minus) && eq(u.b_plus, v.b_plus) && u.r1 == v.r1 && u.r2 == v.r2 &&
          u.filter_eps == v.filter_eps && u.precision == v.precision && u.tol_resid == v.tol_resid &&
          u.tol_gmres == v.tol_gmres && u.max_subspace_iter == v.max_subspace_iter &&
          u.max_gmres_iter == v.max_gmres_iter && u.max_refine == v.max_refine && u.tol_refine == v.tol_refine &&
          u.block_cols == v.block_cols && u.filter_kind == v.filter_kind && u.gmres_restart == v.gmres_restart;
+}
+bool same_filter(const zolo_query* x, const zolo_query* y) {
+  return same_request(x->P, x->a, x->b, x->o, y->P, y->a, y->b, y->o);
+}
+// a resident subspace answers a query for the same result whose subspace is
+// no larger than the one the subspace was computed with
+bool subspace_matches(const SubspaceEntry& e, const zolo_query* q) {
+  return q->o.reuse_subspace && q->nss <= e.nss && same_request(e.P, e.a, e.b, e.o, q->P, q->a, q->b, q->o);
+}
+SubspaceEntry* find_subspace(zolo_server* S, const zolo_query* q) {
+  for (SubspaceEntry& e : S->scache)
+    if (!e.busy && subspace_matches(e, q)) return &e;
+  return nullptr;
 }
 
 bool gaps_estimated(const zolo_opts& o) { return std::isnan(o.a_minus); }
@@ -107,17 +139,30 @@ bool entry_matches(const FactorEntry& e, const zolo_query* q) {
          e.r1 == o.r1;
 }
 
-// free least recently used idle factorizations until `need` more bytes fit
-// beside the running queries and the remaining cache (caller holds S->m)
-void evict_for(zolo_server* S, size_t need, std::vector<zolo_factors*>* to_free) {
+// free least recently used idle factorizations and subspaces until `need` more
+// bytes fit beside the running queries and the remaining cache (caller holds
+// S->m; the caller frees what lands in to_free / to_free_res)
+void evict_for(zolo_server* S, size_t need, std::vector<zolo_factors*>* to_free,
+               std::vector<zolo_result*>* to_free_res) {
   while (S->in_use + S->cached + need > S->budget) {
     int lru = -1;
     for (int i = 0; i < (int)S->fcache.size(); ++i)
       if (!S->fcache[i].busy && (lru < 0 || S->fcache[i].last < S->fcache[lru].last)) lru = i;
-    if (lru < 0) return;
-    S->cached -= S->fcache[lru].bytes;
-    to_free->push_back(S->fcache[lru].F);
-    S->fcache.erase(S->fcache.begin() + lru);
+    auto lrs = S->scache.end();
+    for (auto it = S->scache.begin(); it != S->scache.end(); ++it)
+      if (!it->busy && (lrs == S->scache.end() || it->last < lrs->last)) lrs = it;
+    const bool sub = lrs != S->scache.end() && (lru < 0 || lrs->last < S->fcache[lru].last);
+    if (sub) {
+      S->cached -= lrs->bytes;
+      to_free_res->push_back(lrs->res);
+      S->scache.erase(lrs);
+    } else if (lru >= 0) {
+      S->cached -= S->fcache[lru].bytes;
+      to_free->push_back(S->fcache[lru].F);
+      S->fcache.erase(S->fcache.begin() + lru);
+    } else {
+      return;
+    }
   }
 }
 
@@ -192,11 +237,14 @@ void worker(zolo_server* S) {
     bool too_big = false;
     zolo_factors* F_in = nullptr;
     FactorEntry hit;
+    SubspaceEntry* sub = nullptr;
     std::vector<zolo_factors*> to_free;
+    std::vector<zolo_result*> to_free_res;
     {
       std::unique_lock<std::mutex> lk(S->m);
       S->cv_work.wait(lk, [&] {
         if (S->queue.empty()) return S->stop;
+        if (find_subspace(S, S->queue.front())) return true;  // answered from a resident subspace
         int c = 0;
         std::vector<zolo_query*> b = head_batch(S, &c);
         const size_t e = batch_bytes(b[0], c);
@@ -208,12 +256,18 @@ void worker(zolo_server* S) {
       });
       if (S->queue.empty()) break;  // stop requested and nothing left
       batch = head_batch(S, &cols);
-      est = batch_bytes(batch[0], cols);
-      if (est > S->budget) {  // cannot run even alone: fail the head query only
+      sub = find_subspace(S, batch[0]);
+      est = sub ? 0 : batch_bytes(batch[0], cols);
+      if (sub) {
+        batch.erase(std::remove_if(batch.begin(), batch.end(),
+                                   [&](const zolo_query* q) { return !subspace_matches(*sub, q); }),
+                    batch.end());
+        sub->busy = true;
+      } else if (est > S->budget) {  // cannot run even alone: fail the head query only
         too_big = true;
         batch.resize(1);
       } else {
-        evict_for(S, est, &to_free);
+        evict_for(S, est, &to_free, &to_free_res);
         S->in_use += est;
         for (FactorEntry& fe : S->fcache)
           if (!fe.busy && entry_matches(fe, batch[0])) {
@@ -228,11 +282,43 @@ void worker(zolo_server* S) {
       for (zolo_query* q : batch) S->queue.erase(std::find(S->queue.begin(), S->queue.end(), q));
     }
     for (zolo_factors* f : to_free) zolo_factors_free(f);
+    for (zolo_result* r : to_free_res) zolo_result_free(r);
     to_free.clear();
+    to_free_res.clear();
     S->cv_work.notify_all();  // the next head may fit beside this one
     const double t_start = now_s();
     if (too_big) {
       finish(S, batch, ZOLO_ENOMEM, nullptr, t_start, est);
+      continue;
+    }
+    if (sub) {
+      // the eigenpairs of an earlier query for the same result, handed out
+      // again once their residuals, recomputed now, meet this query's tolerance
+      const double tol = batch[0]->o.tol_resid > 0 ? batch[0]->o.tol_resid : 1e-8;
+      double worst = 0.0;
+      const bool ok = zolo::result_verify(sub->P, sub->res, st, &worst) == ZOLO_OK && worst <= tol;
+      zolo_result* out = ok ? zolo::result_clone(sub->res) : nullptr;
+      if (out) zolo::result_mark_reused(out, worst, now_s() - t_start);
+      {
+        std::lock_guard<std::mutex> lk(S->m);
+        sub->busy = false;
+        sub->last = now_s();
+        if (out) S->sub_hits += (long long)batch.size();
+        if (!out) {  // stale, or no memory for the copy: drop it and queue the batch again
+          S->cached -= sub->bytes;
+          to_free_res.push_back(sub->res);
+          for (auto it = S->scache.begin(); it != S->scache.end(); ++it)
+            if (&*it == sub) {
+              S->scache.erase(it);
+              break;
+            }
+          for (auto it = batch.rbegin(); it != batch.rend(); ++it) S->queue.push_front(*it);
+        }
+      }
+      for (zolo_result* r : to_free_res) zolo_result_free(r);
+      to_free_res.clear();
+      if (out) finish(S, batch, ZOLO_OK, out, t_start, 0);
+      S->cv_work.notify_all();
       continue;
     }
     // one run for the batch: the start block of its member with the largest
@@ -287,6 +373,7 @@ void worker(zolo_server* S) {
                                 &res);
     }
     if (dq) (void)hipFree(dq);
+    zolo_result* res_copy = (rc == ZOLO_OK && res && h->o.reuse_subspace) ? zolo::result_clone(res) : nullptr;
     finish(S, batch, rc, res, t_start, est);
     // a resident factorization keeps only its factors (this worker holds both)
     if (F_in) zolo::factors_keep_only(F_in);
@@ -303,7 +390,7 @@ void worker(zolo_server* S) {
       // keep the new factorization resident when it fits beside the running queries
       if (F_new) {
         const size_t fb = (size_t)zolo::factors_bytes(F_new);
-        evict_for(S, fb, &to_free);
+        evict_for(S, fb, &to_free, &to_free_res);
         if (S->in_use + S->cached + fb <= S->budget) {
           FactorEntry fe;
           fe.P = h->P;
@@ -340,8 +427,31 @@ void worker(zolo_server* S) {
         }
       }
     }
+    // keep the eigenpairs resident for later queries asking for the same result
+    zolo_result* keep = res_copy;
+    if (keep) {
+      std::lock_guard<std::mutex> lk(S->m);
+      const size_t rb = (size_t)zolo::result_bytes(keep);
+      evict_for(S, rb, &to_free, &to_free_res);
+      if (S->in_use + S->cached + rb <= S->budget && !find_subspace(S, h)) {
+        SubspaceEntry e;
+        e.P = h->P;
+        e.a = h->a;
+        e.b = h->b;
+        e.o = h->o;
+        e.nss = h->nss;
+        e.res = keep;
+        e.bytes = rb;
+        e.last = now_s();
+        S->scache.push_back(e);
+        S->cached += rb;
+        keep = nullptr;
+      }
+    }
+    if (keep) zolo_result_free(keep);
     if (F_new) zolo_factors_free(F_new);
     for (zolo_factors* f : to_free) zolo_factors_free(f);
+    for (zolo_result* r : to_free_res) zolo_result_free(r);
     S->cv_work.notify_all();
   }
   if (st) (void)hipStreamDestroy(st);
@@ -471,6 +581,8 @@ extern "C" zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* 
   out->factor_hits = srv->hits;
   out->factor_misses = srv->misses;
   out->queued = (int)srv->queue.size();
+  out->subspace_hits = srv->sub_hits;
+  out->resident_subspaces = (int)srv->scache.size();
   return ZOLO_OK;
 }
 
@@ -483,5 +595,6 @@ extern "C" void zolo_server_destroy(zolo_server* srv) {
   srv->cv_work.notify_all();
   for (std::thread& t : srv->workers) t.join();
   for (FactorEntry& fe : srv->fcache) zolo_factors_free(fe.F);
+  for (SubspaceEntry& e : srv->scache) zolo_result_free(e.res);
   delete srv;
 }

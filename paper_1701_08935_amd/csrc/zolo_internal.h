@@ -88,6 +88,13 @@ int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, i
 int64_t pencil_n(const zolo_pencil* P);
 bool pencil_cplx(const zolo_pencil* P);
 zolo_result* result_clone(const zolo_result* r);
+// device bytes of a result's vectors
+int64_t result_bytes(const zolo_result* r);
+// max over the result's pairs of the residual norm of zolo_residuals, on stream s
+zolo_status result_verify(zolo_pencil* P, const zolo_result* r, void* s, double* worst);
+// marks a copy handed out from a resident subspace: its max_resid recomputed
+// now, t_total the time of that check
+void result_mark_reused(zolo_result* r, double max_resid, double t_check);
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
 
 }  // namespace zolo

@@ -8,7 +8,9 @@
 * Batching: queries asking for the same result that wait in the queue behind
   another query are answered by one run; each gets the full set of eigenpairs
   (also when their options, seeds included, are identical).
-* Residency: a later query of an earlier query's filter reuses its factors.
+* Residency: a later query of an earlier query's filter reuses its factors;
+  queries that opt in get the resident eigenpairs of an earlier query for the
+  same result back, residuals recomputed (1e-8), eigenvalues identical.
 * Admission: a budget below one query's estimate fails it with ZOLO_ENOMEM;
   a budget for one query at a time serializes queries.
 * zolo_wait with a zero timeout on a queued query returns ZOLO_ETIMEOUT.
@@ -248,4 +250,42 @@ def test_factor_residency(ctx, clusters, resident):
     assert np.max(np.abs(out[1][0] - out[0][0]) / np.abs(out[0][0])) <= 1e-12
     ref = lam[40:56]
     assert np.max(np.abs(out[1][0] - ref) / np.abs(ref)) <= 1e-10
+    srv.close()
+
+
+def test_subspace_residency(ctx, clusters, resident):
+    """Queries that opt in (reuse_subspace) keep their eigenpairs resident: a
+    later query for the same result (another seed, a smaller subspace) gets
+    them back with recomputed residuals (stats.subspace_reused, server
+    subspace_hits), the same eigenvalues and an equal span; a query that does
+    not opt in, or asks for a larger subspace, runs (and reuses the factors)."""
+    gp, P = resident[20]
+    A, B = gp.scipy()
+    lam = np.asarray(clusters["clusters"]["20:5.5"])
+    w = pencils.window_from_eigenvalues(lam, 40, 16)
+    say("subspace residency: four queries of one window, one slot")
+    srv = zolo.Server(ctx, slots=1)
+    plan = [(28, 1, 1), (24, 2, 1), (28, 3, 0), (32, 4, 1)]  # (n_ss, seed, reuse_subspace)
+    out = []
+    for nss, seed, reuse in plan:
+        o = _opts(w, nss, seed)
+        o.reuse_subspace = reuse
+        h = srv.submit(P, w["a"], w["b"], 16, o)
+        eig, vec, st, rc, info = h.wait()
+        say(f"  n_ss={nss} reuse={reuse}: rc={rc} found={len(eig)} subspace_reused={st['subspace_reused']} "
+            f"factors_reused={st['factors_reused']} resid={st['max_resid']:.2e} t_total={st['t_total']:.4f}s")
+        assert rc == 0 and len(eig) == 16
+        out.append((np.array(eig), vec.cpu().numpy(), st))
+        h.free()
+    inf = srv.info()
+    say(f"  server: {inf}")
+    assert [x[2]["subspace_reused"] for x in out] == [0, 1, 0, 0]
+    assert [x[2]["factors_reused"] for x in out] == [0, 0, 1, 1]
+    assert inf["subspace_hits"] == 1 and inf["resident_subspaces"] == 2
+    assert out[1][2]["max_resid"] <= 1e-8
+    assert np.array_equal(out[1][0], out[0][0])
+    assert _span_check(B, out[1][1], out[0][1]) <= 1e-8
+    ref = lam[40:56]
+    for eig, _, _ in out:
+        assert np.max(np.abs(eig - ref) / np.abs(ref)) <= 1e-10
     srv.close()
