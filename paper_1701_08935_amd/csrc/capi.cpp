@@ -680,21 +680,36 @@ int gemm_nt_big(Workspace& ws, VT* C, int64_t ldc, const VT* Cin, int64_t ldcin,
   d.ldcin = ldcin;
   d.beta = cvt<VT, double>(beta);
   d.alpha = cvt<VT, double>(alpha);
-  d.A = Msmall;
-  d.lda = ldm;
-  d.flags = transM ? GF_TRANSA : 0;
-  d.B = Bv;
-  d.ldb = ldb;
-  d.M = p;
-  d.N = (int)N;
   d.K = K;
+  // A block of 65 to 96 columns is computed as C_rm = Bv opM^T (row-major C,
+  // N rows): one 96-column tile per 64 rows of Bv, so Bv is read once and no
+  // tile is padded, where p x N in 64 x 64 tiles pads p to 128 and reads each
+  // slab of Bv twice.
+  const bool rows = p > 64 && p <= 96;
+  if (rows) {
+    d.A = Bv;
+    d.lda = ldb;
+    d.B = Msmall;
+    d.ldb = ldm;
+    d.flags = GF_TRANSA | GF_TRANSC | (transM ? 0 : GF_TRANSB);
+    d.M = (int)N;
+    d.N = p;
+  } else {
+    d.A = Msmall;
+    d.lda = ldm;
+    d.flags = transM ? GF_TRANSA : 0;
+    d.B = Bv;
+    d.ldb = ldb;
+    d.M = p;
+    d.N = (int)N;
+  }
   GemmDesc<VT>* dg = (GemmDesc<VT>*)ws.gdesc + ws.gdesc_cap;
   gemm_desc_series<VT>(d, 1, 0, 0, 0, K, K, dg, s);
   {
     double fl = 0.0, by = 0.0;
     gemm_work(d, &fl, &by);
     prof::Scope ps(ZOLO_PROF_GEMM_KRYLOV, fl, by, s);
-    gemm_batched<VT>(dg, 1, p, (int)N, s, 2);
+    gemm_batched<VT>(dg, 1, d.M, d.N, s, 2);
   }
   return ZOLO_OK;
 }

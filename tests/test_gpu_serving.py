@@ -1,7 +1,8 @@
 """Serving loop (zolo_server_*, zolo_submit, zolo_wait) on the GPU.
 
-* Alone vs in the mix: queries on several resident pencils run one by one
-  through zolo_solve and then together through a server with several slots;
+* Alone vs in the mix (FP64 and mixed-precision factors): queries on several
+  resident pencils run one by one through zolo_solve and then together
+  through a server with several slots;
   each query's eigenvalues match its solo run to 1e-12 relative and the
   oracle's stored values to 1e-10, its eigenvector block spans the same
   space (B-inner products of the two bases: singular values within 1e-8 of 1).
@@ -57,8 +58,8 @@ def resident(ctx):
     return out
 
 
-def _opts(w, n_ss, seed):
-    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=n_ss)
+def _opts(w, n_ss, seed, precision=0):
+    o = zolo.opts_from_window(w, r1=2, r2=0, n_ss=n_ss, precision=precision)
     o.seed = seed
     return o
 
@@ -72,7 +73,8 @@ def _span_check(B, X1, X2):
     return float(np.max(np.abs(s - 1.0)))
 
 
-def test_alone_vs_mix(ctx, clusters, resident):
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "mixed"])
+def test_alone_vs_mix(ctx, clusters, resident, precision):
     qs = [q for q in pencils.serving_queries(clusters, 24, rate=50.0, seed=5, max_lambda=48) if q["grid"] in resident][:8]
     assert len(qs) >= 5
     solo = []
@@ -80,7 +82,8 @@ def test_alone_vs_mix(ctx, clusters, resident):
         gp, P = resident[q["grid"]]
         w = q["window"]
         say(f"solo query {i}: grid {q['grid']} center {q['center']} n_lambda {w['n_lambda']}")
-        eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], w["n_lambda"], _opts(w, _nss(w["n_lambda"]), 100 + i))
+        eig, vec, st, rc = zolo.zolo_solve(ctx, P, w["a"], w["b"], w["n_lambda"],
+                                           _opts(w, _nss(w["n_lambda"]), 100 + i, precision))
         assert rc == 0
         solo.append((np.array(eig), vec.cpu().numpy()))
     say("same queries through a server with 3 slots")
@@ -89,7 +92,7 @@ def test_alone_vs_mix(ctx, clusters, resident):
     for i, q in enumerate(qs):
         gp, P = resident[q["grid"]]
         w = q["window"]
-        handles.append(srv.submit(P, w["a"], w["b"], w["n_lambda"], _opts(w, _nss(w["n_lambda"]), 100 + i)))
+        handles.append(srv.submit(P, w["a"], w["b"], w["n_lambda"], _opts(w, _nss(w["n_lambda"]), 100 + i, precision)))
     overlap = 0
     infos = []
     for i, (q, h) in enumerate(zip(qs, handles)):
