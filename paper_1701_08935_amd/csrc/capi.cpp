@@ -622,8 +622,10 @@ void patch_split(std::vector<GemmDesc<T>>& gd, const SplitPlan& sp, typename ST<
 template <typename VT>
 int gemm_tn(Workspace& ws, const VT* X, int64_t ldx, const VT* Y, int64_t ldy, int64_t N, int m, int n, VT* out,
             int64_t ldo, bool add, hipStream_t s) {
+  // row chunks: about 2048 workgroups (eight per CU) of at least 256 rows each,
+  // so that the long inner loops of these tall products keep the chip busy
   int tiles = gemm_tiles(m, n, 2);
-  int64_t S = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (N + 2047) / 2048));
+  int64_t S = std::max<int64_t>(1, std::min<int64_t>((2048 + tiles - 1) / tiles, N / 256));
   // partial_len counts entries of the workspace's own block type (ef doubles)
   const int64_t cap = ws.partial_len * ws.ef / (ST<VT>::cplx ? 2 : 1);
   while (S * (int64_t)m * n > cap && S > 1) S /= 2;
@@ -2218,7 +2220,8 @@ int ensure_ws(zolo_factors* F, int p, int mmax) {
   ws->ldh = Mp;
   CHK(ws->mem.alloc(&ws->H, Mp * (int64_t)mmax * p * ef));
   CHK(ws->mem.alloc(&ws->hbuf, Mp * p * ef));
-  ws->partial_len = std::max<int64_t>(Mp * p * 8, (int64_t)p * p * 256);
+  // gemm_tn's row-chunk partial sums: about 2048 tiles of at most 64 x 96
+  ws->partial_len = std::max<int64_t>({Mp * p * 8, (int64_t)p * p * 256, (int64_t)2048 * 64 * 96});
   CHK(ws->mem.alloc(&ws->partial, ws->partial_len * ef));
   for (double** q : {&ws->G, &ws->R1, &ws->R1i, &ws->R2, &ws->R2i, &ws->R0, &ws->Rk})
     CHK(ws->mem.alloc(q, (size_t)p * p * ef));
@@ -3712,7 +3715,8 @@ int64_t query_bytes_estimate(const zolo_pencil* P, int r1, int nss, int maxit, i
   const int64_t pk = restarts && !P->cplx() ? 2 * p : p;
   const int64_t solve = (int64_t)r1 * lu * (6 * n * (p + (pk > p ? pk : 0))) * elem;  // W, U, Xb, t, Y, X
   const int64_t krylov = ((mmax + 2) * n * pk + 3 * n * pk) * vb                      // basis, W, T1, Tb
-                         + 2 * (int64_t)r1 * lu * n * pk * 16;                        // pole solutions, residuals
+                         + 2 * (int64_t)r1 * lu * n * pk * 16                         // pole solutions, residuals
+                         + (int64_t)2048 * 64 * 96 * vb;                              // Gram partial sums
   const int64_t subspace = 8 * n * (int64_t)nss * vb;  // Q, Y, AY, BY, X, AX, BX, result
   const int64_t total = factors + std::max(factor_tmp, solve + krylov) + subspace;
   return total + total / 10 + ((int64_t)64 << 20);

@@ -8,9 +8,12 @@ namespace zolo {
 // Functions templated on the block scalar T: double (real pencils) or zd
 // (complex Hermitian pencils); "^T" below reads "^H" for complex T.
 
-// out(i,j) (ld_out) = [out +] sum_s partial[s](i,j)  (each partial M x N col-major, ld M)
+// out(i,j) (ld_out) = [out +] sum_s partial[s](i,j)  (each partial M x N col-major, ld M),
+// summed in a fixed order (groups of kReduceGroup consecutive partials, then
+// the groups); with S > kReduceGroup the partials are overwritten.
+constexpr int kReduceGroup = 32;
 template <typename T>
-void reduce_partials(T* out, int64_t ld_out, const T* partial, int S, int M, int N, bool add, hipStream_t s);
+void reduce_partials(T* out, int64_t ld_out, T* partial, int S, int M, int N, bool add, hipStream_t s);
 
 // Cholesky of a p x p Hermitian positive matrix G (col-major): G + shift*I = R^H R,
 // R upper; writes R and R^{-1} (col-major p x p).  flag[0] = 1 on a nonpositive pivot.

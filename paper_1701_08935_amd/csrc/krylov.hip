@@ -22,17 +22,30 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// partial q sits at partial + q * step * M N; summed in q order
 template <typename T>
-__global__ void reduce_partials_kernel(T* __restrict__ out, int64_t ld_out, const T* __restrict__ partial, int S, int M,
-                                       int N, int addto) {
+__global__ void reduce_partials_kernel(T* __restrict__ out, int64_t ld_out, const T* __restrict__ partial, int S,
+                                       int step, int M, int N, int addto) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t MN = (int64_t)M * N;
   if (e >= MN) return;
   T s = ST<T>::zero();
-  for (int q = 0; q < S; ++q) s = add(s, partial[q * MN + e]);
+  for (int q = 0; q < S; ++q) s = add(s, partial[(int64_t)q * step * MN + e]);
   int64_t i = e % M, j = e / M;
   T* o = out + i + j * ld_out;
   *o = addto ? add(*o, s) : s;
+}
+
+// First level of a long reduction: group g of gs consecutive partials is
+// summed, in order, into its first partial (grid.y = number of groups).
+template <typename T>
+__global__ void reduce_groups_kernel(T* __restrict__ partial, int S, int gs, int64_t MN) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= MN) return;
+  const int q0 = (int)blockIdx.y * gs, q1 = q0 + gs < S ? q0 + gs : S;
+  T s = partial[(int64_t)q0 * MN + e];
+  for (int q = q0 + 1; q < q1; ++q) s = add(s, partial[(int64_t)q * MN + e]);
+  partial[(int64_t)q0 * MN + e] = s;
 }
 
 // single workgroup; G is read, R/Rinv written (all col-major p x p).  With
@@ -1179,11 +1192,19 @@ __global__ void resid_final_kernel(const double* __restrict__ partial, int nb, i
 }  // namespace
 
 template <typename T>
-void reduce_partials(T* out, int64_t ld_out, const T* partial, int S, int M, int N, bool add, hipStream_t s) {
+void reduce_partials(T* out, int64_t ld_out, T* partial, int S, int M, int N, bool add, hipStream_t s) {
   int64_t MN = (int64_t)M * N;
   if (MN == 0) return;
-  hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, out, ld_out,
-                     partial, S, M, N, add ? 1 : 0);
+  const unsigned nb = (unsigned)((MN + 255) / 256);
+  int step = 1;
+  if (S > kReduceGroup) {  // groups of kReduceGroup in parallel, then the group sums
+    const int groups = (S + kReduceGroup - 1) / kReduceGroup;
+    hipLaunchKernelGGL(reduce_groups_kernel<T>, dim3(nb, groups), dim3(256), 0, s, partial, S, kReduceGroup, MN);
+    S = groups;
+    step = kReduceGroup;
+  }
+  hipLaunchKernelGGL(reduce_partials_kernel<T>, dim3(nb), dim3(256), 0, s, out, ld_out, (const T*)partial, S, step, M,
+                     N, add ? 1 : 0);
 }
 
 template <typename T>
@@ -1299,7 +1320,7 @@ void resid_norms(const T* AX, const T* BX, const T* X, const double* theta, int6
 }
 
 #define KRYLOV_INST(T)                                                                                        \
-  template void reduce_partials<T>(T*, int64_t, const T*, int, int, int, bool, hipStream_t);                 \
+  template void reduce_partials<T>(T*, int64_t, T*, int, int, int, bool, hipStream_t);                        \
   template void chol_upper_inv<T>(const T*, int, double, T*, T*, int*, hipStream_t);                         \
   template void upper_mul<T>(const T*, const T*, T*, int, hipStream_t);                                      \
   template void put_block<T>(T*, int64_t, int64_t, int64_t, const T*, int, hipStream_t);                     \
