@@ -452,7 +452,12 @@ zolo_status zolo_profile_query(int cls, zolo_kernel_profile* out);
  *    zolo_server_get_info reports them (hits: runs that reused one).
  *  - zolo_submit copies opts and the optional host start block (N x n_ss
  *    row-major, n_ss = opts->n_ss or ceil(1.5 n_lambda_est); NULL draws it
- *    from opts->seed) and returns at once.  The pencil must outlive the query.
+ *    from opts->seed) and returns at once.  The pencil must outlive the query,
+ *    and, since resident factorizations and subspaces refer to it, either the
+ *    server or a zolo_server_drop_pencil call for it.
+ *  - zolo_server_drop_pencil waits until no queued or running query uses the
+ *    pencil and frees its resident factorizations and subspaces; afterwards
+ *    the pencil may be freed (queries submitted on it later make new ones).
  *  - zolo_wait returns the query's status and hands over its result (freed
  *    by the caller with zolo_result_free); timeout_ms < 0 waits forever; on
  *    ZOLO_ETIMEOUT nothing is handed over and the query keeps running.
@@ -487,6 +492,7 @@ typedef struct {
   int resident_subspaces;
 } zolo_server_info;
 zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* out);
+zolo_status zolo_server_drop_pencil(zolo_server* srv, zolo_pencil* p);
 /* frees a query handle; waits for the query if it is still queued or running */
 void zolo_query_free(zolo_query* q);
 void zolo_server_destroy(zolo_server* srv);

@@ -138,6 +138,7 @@ _SIGS = {
     "zolo_query_get_info": (_i, [_vp, ctypes.POINTER(zolo_query_info)]),
     "zolo_query_free": (None, [_vp]),
     "zolo_server_get_info": (_i, [_vp, ctypes.POINTER(zolo_server_info)]),
+    "zolo_server_drop_pencil": (_i, [_vp, _vp]),
     "zolo_server_destroy": (None, [_vp]),
 }
 
@@ -452,6 +453,9 @@ class Server:
         self.h = h
         self.ctx = ctx
         self._queries = weakref.WeakSet()
+        # pencils the server has run queries on: its resident factorizations and
+        # subspaces refer to them, so they stay alive until dropped or closed
+        self._pencils = {}
 
     def submit(self, pencil: Pencil, a, b, n_lambda_est, opts: zolo_opts = None, Q0=None) -> "Query":
         """Q0: optional host numpy array N x n_ss (row-major; float64, or complex128 for
@@ -466,7 +470,14 @@ class Server:
                                  None if q0 is None else _np_ptr(q0), ctypes.byref(h)))
         q = Query(h, pencil, self)
         self._queries.add(q)
+        self._pencils[id(pencil)] = pencil
         return q
+
+    def drop_pencil(self, pencil: Pencil):
+        """zolo_server_drop_pencil: waits for the pencil's queued and running
+        queries and frees its resident factorizations and subspaces."""
+        _check(lib().zolo_server_drop_pencil(self.h, pencil.h))
+        self._pencils.pop(id(pencil), None)
 
     def info(self) -> dict:
         inf = zolo_server_info()
@@ -480,6 +491,7 @@ class Server:
                 q.free()
             _lib.zolo_server_destroy(self.h)
             self.h = None
+            self._pencils = {}
 
     def __del__(self):
         self.close()

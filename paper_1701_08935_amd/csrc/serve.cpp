@@ -79,6 +79,7 @@ struct SubspaceEntry {
   double a = 0.0, b = 0.0;
   zolo_opts o{};
   int nss = 0;  // subspace size of the run
+  int64_t n = 0;  // the pencil's size when the entry was made
   zolo_result* res = nullptr;
   size_t bytes = 0;
   bool busy = false;
@@ -98,6 +99,7 @@ struct zolo_server {
   std::list<SubspaceEntry> scache;  // resident subspaces (guarded by m)
   size_t cached = 0;                // bytes of both
   long long hits = 0, misses = 0, sub_hits = 0;
+  std::vector<zolo_pencil*> running;  // pencil of each run in progress (guarded by m)
 };
 
 namespace {
@@ -200,6 +202,12 @@ size_t batch_bytes(const zolo_query* h, int cols) {
   return e;
 }
 
+// the run on pencil P has ended and left whatever it keeps resident (caller holds S->m)
+void unmark_running(zolo_server* S, zolo_pencil* P) {
+  auto it = std::find(S->running.begin(), S->running.end(), P);
+  if (it != S->running.end()) S->running.erase(it);
+}
+
 void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status rc, zolo_result* res, double t_start,
             size_t est) {
   const double t_end = now_s();
@@ -280,6 +288,7 @@ void worker(zolo_server* S) {
         if (!F_in) ++S->misses;
       }
       for (zolo_query* q : batch) S->queue.erase(std::find(S->queue.begin(), S->queue.end(), q));
+      S->running.push_back(batch[0]->P);
     }
     for (zolo_factors* f : to_free) zolo_factors_free(f);
     for (zolo_result* r : to_free_res) zolo_result_free(r);
@@ -289,6 +298,11 @@ void worker(zolo_server* S) {
     const double t_start = now_s();
     if (too_big) {
       finish(S, batch, ZOLO_ENOMEM, nullptr, t_start, est);
+      {
+        std::lock_guard<std::mutex> lk(S->m);
+        unmark_running(S, batch[0]->P);
+      }
+      S->cv_done.notify_all();
       continue;
     }
     if (sub) {
@@ -296,13 +310,15 @@ void worker(zolo_server* S) {
       // again once their residuals, recomputed now, meet this query's tolerance
       const double tol = batch[0]->o.tol_resid > 0 ? batch[0]->o.tol_resid : 1e-8;
       double worst = 0.0;
-      const bool ok = zolo::result_verify(sub->P, sub->res, st, &worst) == ZOLO_OK && worst <= tol;
+      const bool ok = zolo::pencil_n(sub->P) == sub->n && zolo::result_verify(sub->P, sub->res, st, &worst) == ZOLO_OK &&
+                      worst <= tol;
       zolo_result* out = ok ? zolo::result_clone(sub->res) : nullptr;
       if (out) zolo::result_mark_reused(out, worst, now_s() - t_start);
       {
         std::lock_guard<std::mutex> lk(S->m);
         sub->busy = false;
         sub->last = now_s();
+        unmark_running(S, batch[0]->P);
         if (out) S->sub_hits += (long long)batch.size();
         if (!out) {  // stale, or no memory for the copy: drop it and queue the batch again
           S->cached -= sub->bytes;
@@ -319,6 +335,7 @@ void worker(zolo_server* S) {
       to_free_res.clear();
       if (out) finish(S, batch, ZOLO_OK, out, t_start, 0);
       S->cv_work.notify_all();
+      S->cv_done.notify_all();
       continue;
     }
     // one run for the batch: the start block of its member with the largest
@@ -440,6 +457,7 @@ void worker(zolo_server* S) {
         e.b = h->b;
         e.o = h->o;
         e.nss = h->nss;
+        e.n = n;
         e.res = keep;
         e.bytes = rb;
         e.last = now_s();
@@ -448,11 +466,16 @@ void worker(zolo_server* S) {
         keep = nullptr;
       }
     }
+    {
+      std::lock_guard<std::mutex> lk(S->m);
+      unmark_running(S, batch[0]->P);
+    }
     if (keep) zolo_result_free(keep);
     if (F_new) zolo_factors_free(F_new);
     for (zolo_factors* f : to_free) zolo_factors_free(f);
     for (zolo_result* r : to_free_res) zolo_result_free(r);
     S->cv_work.notify_all();
+    S->cv_done.notify_all();
   }
   if (st) (void)hipStreamDestroy(st);
 }
@@ -583,6 +606,46 @@ extern "C" zolo_status zolo_server_get_info(zolo_server* srv, zolo_server_info* 
   out->queued = (int)srv->queue.size();
   out->subspace_hits = srv->sub_hits;
   out->resident_subspaces = (int)srv->scache.size();
+  return ZOLO_OK;
+}
+
+extern "C" zolo_status zolo_server_drop_pencil(zolo_server* srv, zolo_pencil* p) {
+  if (!srv || !p) {
+    zolo::set_error("zolo_server_drop_pencil: null argument");
+    return ZOLO_EINVAL;
+  }
+  std::vector<zolo_factors*> ff;
+  std::vector<zolo_result*> rr;
+  {
+    std::unique_lock<std::mutex> lk(srv->m);
+    // no queued or running query on p: nothing can make p's entries busy or add new ones
+    srv->cv_done.wait(lk, [&] {
+      for (const zolo_query* q : srv->queue)
+        if (q->P == p) return false;
+      return std::find(srv->running.begin(), srv->running.end(), p) == srv->running.end();
+    });
+    for (auto it = srv->fcache.begin(); it != srv->fcache.end();) {
+      if (it->P == p) {
+        srv->cached -= it->bytes;
+        ff.push_back(it->F);
+        it = srv->fcache.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    for (auto it = srv->scache.begin(); it != srv->scache.end();) {
+      if (it->P == p) {
+        srv->cached -= it->bytes;
+        rr.push_back(it->res);
+        it = srv->scache.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (zolo_factors* f : ff) zolo_factors_free(f);
+  for (zolo_result* r : rr) zolo_result_free(r);
+  srv->cv_work.notify_all();  // the freed memory may admit a waiting query
   return ZOLO_OK;
 }
 

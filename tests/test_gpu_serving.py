@@ -15,6 +15,7 @@
 * Admission: a budget below one query's estimate fails it with ZOLO_ENOMEM;
   a budget for one query at a time serializes queries.
 * zolo_wait with a zero timeout on a queued query returns ZOLO_ETIMEOUT.
+* zolo_server_drop_pencil frees a pencil's resident entries.
 """
 import json
 import sys
@@ -291,4 +292,35 @@ def test_subspace_residency(ctx, clusters, resident):
     ref = lam[40:56]
     for eig, _, _ in out:
         assert np.max(np.abs(eig - ref) / np.abs(ref)) <= 1e-10
+    srv.close()
+
+
+def test_drop_pencil(ctx, clusters, resident):
+    """zolo_server_drop_pencil frees the pencil's resident factorization and
+    subspace (after its queries are done); a later query on it factors anew and
+    still returns the oracle's eigenvalues."""
+    gp, P = resident[16]
+    lam = np.asarray(clusters["clusters"]["16:5.5"])
+    w = pencils.window_from_eigenvalues(lam, 40, 12)
+    say("drop_pencil: one query kept resident, dropped, then run again")
+    srv = zolo.Server(ctx, slots=2)
+    o = _opts(w, 20, 1)
+    o.reuse_subspace = 1
+    h = srv.submit(P, w["a"], w["b"], 12, o)
+    eig0 = np.array(h.wait()[0])
+    h.free()
+    inf = srv.info()
+    say(f"  before drop: {inf}")
+    assert inf["resident_factors"] == 1 and inf["resident_subspaces"] == 1 and inf["resident_bytes"] > 0
+    srv.drop_pencil(P)
+    inf = srv.info()
+    say(f"  after drop: {inf}")
+    assert inf["resident_factors"] == 0 and inf["resident_subspaces"] == 0 and inf["resident_bytes"] == 0
+    h = srv.submit(P, w["a"], w["b"], 12, o)
+    eig, vec, st, rc, info = h.wait()
+    h.free()
+    assert rc == 0 and st["factors_reused"] == 0 and st["subspace_reused"] == 0
+    ref = lam[40:52]
+    assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) <= 1e-10
+    assert np.max(np.abs(np.array(eig) - eig0) / np.abs(eig0)) <= 1e-12
     srv.close()
