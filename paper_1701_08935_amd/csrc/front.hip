@@ -441,45 +441,71 @@ __global__ __launch_bounds__(256) void diag_blocked_kernel(const PoleBase<T>* __
   }
 }
 
-// one wave per W row, lanes over the p columns
+// Half a wave (32 lanes) per W row, eight rows per workgroup: a lane takes
+// columns c, c + 32 and c + 64 of each 96-column pass, so a 96-column block
+// keeps every lane busy (one wave per row left a third of the lanes idle in
+// the second pass) and each contribution row is read with three independent
+// loads per lane.
+constexpr int kRowLanes = 32, kRowsPerGroup = 256 / kRowLanes, kColsPerLane = 3;
+
 template <typename Ts, typename T>
 __global__ __launch_bounds__(256) void solve_fill_kernel(T* __restrict__ W, int64_t wstride, const Ts* __restrict__ src,
                                                          int64_t ldsrc, int64_t sstride, const T* __restrict__ U,
                                                          int64_t ustride, const int32_t* __restrict__ own,
                                                          const int32_t* __restrict__ cbeg,
                                                          const int32_t* __restrict__ cidx, int64_t rows, int p) {
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t r = (int64_t)blockIdx.x * 4 + w;
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerGroup + (threadIdx.x / kRowLanes);
   if (r >= rows) return;
-  const int j = blockIdx.y, lane = threadIdx.x & 63;
+  const int j = blockIdx.y, lane = threadIdx.x % kRowLanes;
   const int o = own[r], q0 = cbeg[r], q1 = cbeg[r + 1];
   T* wr = W + (int64_t)j * wstride + r * p;
   const Ts* sr = src + (int64_t)j * sstride + (int64_t)(o < 0 ? 0 : o) * ldsrc;
   const T* ub = U + (int64_t)j * ustride;
-  for (int c = lane; c < p; c += 64) {
-    T acc = o >= 0 ? cvt<T, Ts>(sr[c]) : ST<T>::zero();
-    for (int q = q0; q < q1; ++q) acc = add(acc, ub[(int64_t)cidx[q] * p + c]);
-    wr[c] = acc;
+  for (int c0 = 0; c0 < p; c0 += kRowLanes * kColsPerLane) {
+    T acc[kColsPerLane];
+    int cc[kColsPerLane];
+#pragma unroll
+    for (int u = 0; u < kColsPerLane; ++u) {
+      const int c = c0 + lane + kRowLanes * u;
+      cc[u] = c < p ? c : p - 1;  // loads stay in the row; columns past p are not stored
+      acc[u] = o >= 0 ? cvt<T, Ts>(sr[cc[u]]) : ST<T>::zero();
+    }
+    for (int q = q0; q < q1; ++q) {
+      const T* ur = ub + (int64_t)cidx[q] * p;
+#pragma unroll
+      for (int u = 0; u < kColsPerLane; ++u) acc[u] = add(acc[u], ur[cc[u]]);
+    }
+#pragma unroll
+    for (int u = 0; u < kColsPerLane; ++u)
+      if (c0 + lane + kRowLanes * u < p) wr[c0 + lane + kRowLanes * u] = acc[u];
   }
 }
 
-// one wave per row of a front's W, lanes over the p columns
+// the same layout: half a wave per row of a front's W
 template <typename T>
 __global__ __launch_bounds__(256) void gather_back_kernel(T* __restrict__ W, const T* __restrict__ Y,
                                                           const T* __restrict__ X, const int32_t* __restrict__ srows,
                                                           const SolveDesc* __restrict__ descs, int p) {
   const SolveDesc d = descs[blockIdx.y];
-  const int64_t r = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t r = (int64_t)blockIdx.x * kRowsPerGroup + (threadIdx.x / kRowLanes);
   if (r >= d.k) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x % kRowLanes;
   T* wr = W + d.w + r * p;
-  if (r < d.ns) {
-    const T dinv = inv_(((const T*)d.dv)[d.first + r]);
-    const T* yr = Y + d.xo + (d.first + r) * p;
-    for (int c = lane; c < p; c += 64) wr[c] = mul(yr[c], dinv);
-  } else {
-    const T* xr = X + d.xo + (int64_t)srows[d.srow + r - d.ns] * p;
-    for (int c = lane; c < p; c += 64) wr[c] = xr[c];
+  const bool top = r < d.ns;
+  const T dinv = top ? inv_(((const T*)d.dv)[d.first + r]) : ST<T>::one();
+  const T* xr = top ? Y + d.xo + (d.first + r) * p : X + d.xo + (int64_t)srows[d.srow + r - d.ns] * p;
+  for (int c0 = 0; c0 < p; c0 += kRowLanes * kColsPerLane) {
+    T v[kColsPerLane];
+#pragma unroll
+    for (int u = 0; u < kColsPerLane; ++u) {
+      const int c = c0 + lane + kRowLanes * u;
+      v[u] = xr[c < p ? c : p - 1];  // loads stay in the row; columns past p are not stored
+    }
+#pragma unroll
+    for (int u = 0; u < kColsPerLane; ++u) {
+      const int c = c0 + lane + kRowLanes * u;
+      if (c < p) wr[c] = top ? mul(v[u], dinv) : v[u];
+    }
   }
 }
 
@@ -545,7 +571,8 @@ void solve_fill(T* W, int64_t wstride, const Ts* src, int64_t ldsrc, int64_t sst
                 const int32_t* own, const int32_t* cbeg, const int32_t* cidx, int64_t rows, int p, int np,
                 hipStream_t s) {
   if (rows <= 0 || p <= 0 || np <= 0) return;
-  hipLaunchKernelGGL((solve_fill_kernel<Ts, T>), dim3((unsigned)((rows + 3) / 4), np), dim3(256), 0, s, W, wstride,
+  hipLaunchKernelGGL((solve_fill_kernel<Ts, T>), dim3((unsigned)((rows + kRowsPerGroup - 1) / kRowsPerGroup), np),
+                     dim3(256), 0, s, W, wstride,
                      src, ldsrc, sstride, U, ustride, own, cbeg, cidx, rows, p);
 }
 
@@ -553,8 +580,8 @@ template <typename T>
 void solve_gather_back(T* W, const T* Y, const T* X, const int32_t* srows, const SolveDesc* d, int nd, int p,
                        int max_k, hipStream_t s) {
   if (nd <= 0 || max_k <= 0) return;
-  hipLaunchKernelGGL(gather_back_kernel<T>, dim3((unsigned)((max_k + 3) / 4), nd), dim3(256), 0, s, W, Y, X, srows, d,
-                     p);
+  hipLaunchKernelGGL(gather_back_kernel<T>, dim3((unsigned)((max_k + kRowsPerGroup - 1) / kRowsPerGroup), nd), dim3(256),
+                     0, s, W, Y, X, srows, d, p);
 }
 
 template <typename T>
