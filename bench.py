@@ -492,12 +492,14 @@ def roofline(prof, steps, fp32=False, method_factor_flops=None, kernel=None):
     return out
 
 
-def spmm_rate(prof):
-    """The CSR SpMM launches' algorithmic HBM rate (matrix values and indices,
-    the X block read once, the outputs written once) against the HBM peak."""
-    if not prof or not prof.get("spmm") or prof["spmm"]["ms"] <= 0:
+def spmm_rate(prof, cls="spmm"):
+    """The algorithmic HBM rate of an HBM-bound kernel class against the HBM
+    peak: the CSR SpMMs (matrix values and indices, the X block read once, the
+    outputs written once), or with cls="solve_gather" the solves' right-hand-side
+    gathers (each front row written once and its source rows read once)."""
+    if not prof or not prof.get(cls) or prof[cls]["ms"] <= 0 or prof[cls]["bytes"] <= 0:
         return None
-    v = prof["spmm"]
+    v = prof[cls]
     ach = v["bytes"] / (v["ms"] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
             "launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / max(v["launches"], 1)}
@@ -664,6 +666,7 @@ def main():
                                     method_factor_flops=res["pflops"]["elimination"] * st["r1"], kernel="gemm_factor"),
         "roofline_solve": roofline(res["prof"], args.steps, fp32=wl["precision"] == 1, kernel="gemm_solve"),
         "spmm": spmm_rate(res["prof"]),
+        "solve_gather": spmm_rate(res["prof"], "solve_gather"),
         "profile": res["prof"],
     }
     if args.config in ("c1", "m32") and not args.no_mixed:

@@ -432,6 +432,9 @@ struct zolo_pencil {
   int32_t* fill_cbeg = nullptr;
   int32_t* fill_cidx = nullptr;
   std::vector<int64_t> lvl_fill_off, lvl_fill_rows;
+  // per level, for the byte counts of the solves' gathers: contribution rows
+  // added by the fill, rows taken from the right-hand side, and sum of k
+  std::vector<int64_t> lvl_fill_adds, lvl_fill_src, lvl_k;
   bool cplx() const { return scalar == ZOLO_COMPLEX128; }
 };
 
@@ -846,8 +849,12 @@ zolo_status build_fill(zolo_pencil* P) {
   std::vector<int32_t> own, cbeg, cidx, cnt;
   P->lvl_fill_off.assign(nl, 0);
   P->lvl_fill_rows.assign(nl, 0);
+  P->lvl_fill_adds.assign(nl, 0);
+  P->lvl_fill_src.assign(nl, 0);
+  P->lvl_k.assign(nl, 0);
   for (int L = 0; L < nl; ++L) {
     P->lvl_fill_off[L] = (int64_t)own.size();
+    const int64_t adds0 = (int64_t)cidx.size();
     for (int f : S.levels[L]) {
       const Front& Fr = S.fronts[f];
       const int k = Fr.ns + Fr.nb;
@@ -870,6 +877,11 @@ zolo_status build_fill(zolo_pencil* P) {
       }
     }
     P->lvl_fill_rows[L] = (int64_t)own.size() - P->lvl_fill_off[L];
+    P->lvl_fill_adds[L] = (int64_t)cidx.size() - adds0;
+    for (int f : S.levels[L]) {
+      P->lvl_fill_src[L] += S.fronts[f].ns;
+      P->lvl_k[L] += S.fronts[f].ns + S.fronts[f].nb;
+    }
   }
   cbeg.push_back((int32_t)cidx.size());
   if (own.empty()) own.push_back(-1);
@@ -2176,9 +2188,15 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, boo
   zolo_pencil* P = F->P;
   const int nl = (int)P->S.levels.size();
   const int p = G->p;
+  // algorithmic bytes of the gathers: every row written once, every row read
+  // once (the shared right-hand side once for all poles), the index tables
+  const double vt = sizeof(T), vs = sizeof(Ts), npd = G->np;
   for (int L = 0; L < nl; ++L) {
     {
-      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
+      const double by = npd * p * vt * (P->lvl_fill_rows[L] + P->lvl_fill_adds[L]) +
+                        (per_pole ? npd : 1.0) * p * vs * P->lvl_fill_src[L] +
+                        4.0 * (2.0 * P->lvl_fill_rows[L] + P->lvl_fill_adds[L]);
+      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, by, s);
       solve_fill<Ts, T>(G->W, G->wstride, src, lds, per_pole ? G->xstride : 0, G->U, G->ustride,
                         G->own + G->lvl_row_off[L], G->cbeg + G->lvl_row_off[L], G->cidx, G->lvl_rows[L], p, G->np, s);
     }
@@ -2186,7 +2204,8 @@ void run_solve(zolo_factors* F, SolveProg<T>* G, const Ts* src, int64_t lds, boo
   }
   for (int L = nl - 1; L >= 0; --L) {
     {
-      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, 0.0, s);
+      const double by = 2.0 * npd * p * vt * P->lvl_k[L];  // each row of W written, its source row read
+      prof::Scope ps(ZOLO_PROF_SOLVE_GATHER, 0.0, by, s);
       solve_gather_back<T>(G->W, G->Y, G->X, P->struct_rows, G->sd + G->lvl_sd_off[L], G->lvl_sd_cnt[L], p,
                            G->lvl_maxk[L], s);
     }
