@@ -208,10 +208,12 @@ void unmark_running(zolo_server* S, zolo_pencil* P) {
   if (it != S->running.end()) S->running.erase(it);
 }
 
+// hands the result to the batch (copies for all but the first) and marks it
+// done; err: the run's error message (null: the calling thread's last error)
 void finish(zolo_server* S, const std::vector<zolo_query*>& batch, zolo_status rc, zolo_result* res, double t_start,
-            size_t est) {
+            size_t est, const std::string* err_in = nullptr) {
   const double t_end = now_s();
-  const std::string err = rc == ZOLO_OK ? std::string() : std::string(zolo_last_error());
+  const std::string err = rc == ZOLO_OK ? std::string() : err_in ? *err_in : std::string(zolo_last_error());
   std::vector<zolo_result*> out(batch.size(), nullptr);
   if (res) {
     out[0] = res;
@@ -297,12 +299,14 @@ void worker(zolo_server* S) {
     S->cv_work.notify_all();  // the next head may fit beside this one
     const double t_start = now_s();
     if (too_big) {
-      finish(S, batch, ZOLO_ENOMEM, nullptr, t_start, est);
+      zolo::set_error("zolo_submit: the query needs about %zu bytes, above the server's budget of %zu", est,
+                      S->budget);
+      const std::string err = zolo_last_error();
       {
         std::lock_guard<std::mutex> lk(S->m);
         unmark_running(S, batch[0]->P);
       }
-      S->cv_done.notify_all();
+      finish(S, batch, ZOLO_ENOMEM, nullptr, t_start, est, &err);
       continue;
     }
     if (sub) {
@@ -390,8 +394,11 @@ void worker(zolo_server* S) {
                                 &res);
     }
     if (dq) (void)hipFree(dq);
-    zolo_result* res_copy = (rc == ZOLO_OK && res && h->o.reuse_subspace) ? zolo::result_clone(res) : nullptr;
-    finish(S, batch, rc, res, t_start, est);
+    const std::string err = rc == ZOLO_OK ? std::string() : std::string(zolo_last_error());
+    // The server's state is brought up to date before the queries are marked
+    // done, so that what a caller sees after zolo_wait (zolo_server_get_info,
+    // residency) already includes this run.
+    zolo_result* keep = (rc == ZOLO_OK && res && h->o.reuse_subspace) ? zolo::result_clone(res) : nullptr;
     // a resident factorization keeps only its factors (this worker holds both)
     if (F_in) zolo::factors_keep_only(F_in);
     if (F_new) zolo::factors_keep_only(F_new);
@@ -443,37 +450,33 @@ void worker(zolo_server* S) {
           F_new = nullptr;
         }
       }
-    }
-    // keep the eigenpairs resident for later queries asking for the same result
-    zolo_result* keep = res_copy;
-    if (keep) {
-      std::lock_guard<std::mutex> lk(S->m);
-      const size_t rb = (size_t)zolo::result_bytes(keep);
-      evict_for(S, rb, &to_free, &to_free_res);
-      if (S->in_use + S->cached + rb <= S->budget && !find_subspace(S, h)) {
-        SubspaceEntry e;
-        e.P = h->P;
-        e.a = h->a;
-        e.b = h->b;
-        e.o = h->o;
-        e.nss = h->nss;
-        e.n = n;
-        e.res = keep;
-        e.bytes = rb;
-        e.last = now_s();
-        S->scache.push_back(e);
-        S->cached += rb;
-        keep = nullptr;
+      // keep the eigenpairs resident for later queries asking for the same result
+      if (keep) {
+        const size_t rb = (size_t)zolo::result_bytes(keep);
+        evict_for(S, rb, &to_free, &to_free_res);
+        if (S->in_use + S->cached + rb <= S->budget && !find_subspace(S, h)) {
+          SubspaceEntry e;
+          e.P = h->P;
+          e.a = h->a;
+          e.b = h->b;
+          e.o = h->o;
+          e.nss = h->nss;
+          e.n = n;
+          e.res = keep;
+          e.bytes = rb;
+          e.last = t;
+          S->scache.push_back(e);
+          S->cached += rb;
+          keep = nullptr;
+        }
       }
-    }
-    {
-      std::lock_guard<std::mutex> lk(S->m);
       unmark_running(S, batch[0]->P);
     }
     if (keep) zolo_result_free(keep);
     if (F_new) zolo_factors_free(F_new);
     for (zolo_factors* f : to_free) zolo_factors_free(f);
     for (zolo_result* r : to_free_res) zolo_result_free(r);
+    finish(S, batch, rc, res, t_start, est, &err);
     S->cv_work.notify_all();
     S->cv_done.notify_all();
   }

@@ -323,4 +323,14 @@ def test_drop_pencil(ctx, clusters, resident):
     ref = lam[40:52]
     assert np.max(np.abs(np.array(eig) - ref) / np.abs(ref)) <= 1e-10
     assert np.max(np.abs(np.array(eig) - eig0) / np.abs(eig0)) <= 1e-12
+    # dropped while its query is queued or running: the call waits for it
+    h = srv.submit(P, w["a"], w["b"], 12, o)
+    srv.drop_pencil(P)
+    inf = srv.info()
+    say(f"  dropped during a query: {inf}")
+    assert inf["resident_factors"] == 0 and inf["resident_subspaces"] == 0 and inf["queued"] == 0
+    eig, vec, st, rc, info = h.wait()
+    h.free()
+    assert rc == 0 and info["done"] == 1
+    assert np.max(np.abs(np.array(eig) - eig0) / np.abs(eig0)) <= 1e-12
     srv.close()
