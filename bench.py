@@ -449,6 +449,85 @@ def run_filters(n=64, leaf=128, tol_gmres=1e-8):
             "runs": out}
 
 
+def run_mixed_low(n=64, leaf=128, count_target=64, tol_gmres=1e-8, tol_refine=1e-7, reps=2):
+    """The precision form where its poles sit far from the spectrum: the lowest
+    eigenvalues of the c1 pencil (a- = -inf).  b is placed by inertia bisection
+    so that about count_target eigenvalues lie below it; a first FP64 query
+    estimates the eigengaps (inertia bisection, reported, not timed); then the
+    same query with those gaps in FP64 and with complex64 factors (FP64
+    residuals, refinement target tol_refine), the faster of `reps` runs each.
+    Verified: count = inertia, residual <= 1e-8, and the two precisions'
+    eigenvalues agree to 1e-10 (the window is beyond the oracle's windows:
+    parity unpinned; the oracle's shift-invert runs stop at smaller grids)."""
+    import numpy as np
+    import torch
+
+    import paper_1701_08935_amd as z
+    import pencils
+
+    gp = pencils.grid7(n)
+    ctx = z.Context(0)
+    P = z.Pencil.from_grid(ctx, gp, leaf_size=leaf)
+    a = -3.0  # below the spectrum: the potential is >= -1, the Laplacian >= 0, B is SPD with diagonal >= 1
+    if int(z.zolo_inertia(ctx, P, [a])[0]) != 0:
+        return {"error": "the lower bound is not below the spectrum"}
+    lo, hi = a, 2.0
+    b = hi
+    for _ in range(60):
+        m = 0.5 * (lo + hi)
+        c = int(z.zolo_inertia(ctx, P, [m])[0])
+        b = m
+        if c < count_target:
+            lo = m
+        elif c > count_target + 1:
+            hi = m
+        else:
+            break
+    count = int(z.zolo_inertia(ctx, P, [b])[0])
+    nss = int(math.ceil(1.5 * count)) + 8
+    Q0 = torch.from_numpy(pencils.gaussian_block(gp.n, nss, seed=2)).to("cuda:0")  # resident, as in c1
+    o = z.zolo_opts_default()
+    o.r1, o.n_ss, o.tol_gmres = 2, nss, tol_gmres
+    t = time.perf_counter()
+    eig0, vec0, st0, rc0 = z.zolo_solve(ctx, P, a, b, count, o, Q0=Q0)
+    t_first = time.perf_counter() - t
+    del vec0
+    gaps = (st0["a_minus"], st0["a_plus"], st0["b_minus"], st0["b_plus"])
+    runs = {}
+    for name, prec in (("fp64", 0), ("mixed", 1)):
+        o = z.zolo_opts_default()
+        o.a_minus, o.a_plus, o.b_minus, o.b_plus = gaps
+        o.r1, o.n_ss, o.tol_gmres, o.precision, o.tol_refine = 2, nss, tol_gmres, prec, tol_refine
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            eig, vec, st, rc = z.zolo_solve(ctx, P, a, b, count, o, Q0=Q0)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            del vec
+            if best is None or dt < best[0]:
+                best = (dt, np.array(eig), st, rc)
+        dt, eig, st, rc = best
+        log(f"[bench] lowest {count} eigenvalues {name}: {dt:.3f}s rc={rc} found={len(eig)} gmres={st['n_gmres_total']} "
+            f"iter={st['n_iter']} sweeps={st['refine_sweeps_max']} t_factor={st['t_factor']:.3f} resid={st['max_resid']:.2e}")
+        runs[name] = {"s": dt, "rc": rc, "found": len(eig), "eig": eig, "n_gmres": st["n_gmres_total"],
+                      "n_iter": st["n_iter"], "refine_sweeps_max": st["refine_sweeps_max"],
+                      "precision_fallback": st["precision_fallback"], "t_factor_s": st["t_factor"],
+                      "t_iter_s": st["t_iter"], "max_resid": st["max_resid"]}
+    e64, e32 = runs["fp64"]["eig"], runs["mixed"]["eig"]
+    diff = float(np.max(np.abs(e64 - e32) / np.abs(e64))) if len(e64) == len(e32) == count else float("inf")
+    ok = all(r["rc"] == 0 and r["found"] == count and r["max_resid"] <= 1e-8 for r in runs.values()) and diff <= 1e-10
+    for r in runs.values():
+        del r["eig"]
+    return {"workload": f"grid7 {n}^3 (N={gp.n}), the {count} lowest eigenvalues (a- = -inf, b by inertia), "
+                        f"block {nss}, r1=2, tol_refine {tol_refine:g}",
+            "count_inertia": count, "count_note": "count by the library's inertia; parity unpinned",
+            "first_query_s": t_first, "t_gaps_s": st0["t_gaps"], "verified": ok, "eig_rel_diff": diff,
+            "fp64": runs["fp64"], "mixed": runs["mixed"],
+            "speedup_vs_fp64": runs["fp64"]["s"] / runs["mixed"]["s"] if runs["mixed"]["s"] > 0 else None}
+
+
 def roofline(prof, steps, fp32=False, method_factor_flops=None, kernel=None):
     """Roofline of one kernel class: by default the class with the most summed
     kernel time (the dominant kernel).  For the factorization products the
@@ -570,6 +649,8 @@ def main():
                     help="nested-dissection leaf size (cells per leaf subdomain); 128 is fastest on the 64^3 query")
     ap.add_argument("--r1", type=int, default=2)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison run")
+    ap.add_argument("--no-mixed-low", action="store_true",
+                    help="skip the FP64 vs complex64 comparison on the lowest eigenvalues of the c1 pencil")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-c3", action="store_true", help="skip the complex Hermitian 96^3 leg")
@@ -680,6 +761,8 @@ def main():
                         "n_refine": ms_["n_refine"], "refine_sweeps_max": ms_["refine_sweeps_max"],
                         "refine_missed": ms_["refine_missed"], "tol_refine": args.tol_refine,
                         "t_factor_s": ms_["t_factor"], "t_iter_s": ms_["t_iter"]}
+    if args.config == "c1" and not args.no_mixed and not args.no_mixed_low:
+        out["mixed_low"] = [run_mixed_low(leaf=args.leaf, count_target=c, tol_gmres=args.tol_gmres) for c in (64, 16)]
     if args.config == "c1" and not args.no_r1_sweep:
         # the split of the filter's order between factored poles and GMRES shifts (the
         # Remark after Algorithm 2 leaves it open); the headline keeps the two factored
