@@ -123,3 +123,45 @@ def test_top_slice_b_plus_infinite(ctx, gen):
     say(f"  estimated gaps: rc={rc2} found {len(eig2)} count {st2['inertia_count']} b_plus {st2['b_plus']}")
     assert rc2 == 0 and len(eig2) == k and st2["inertia_count"] == k
     assert math.isinf(st2["b_plus"])
+
+
+
+@pytest.mark.parametrize("case", ["pattern", "real_values", "complex_values", "b_not_positive"])
+def test_pencil_rejects_bad_pencils(ctx, case):
+    """zolo_pencil_create checks what the method assumes (Sec. 1: A Hermitian,
+    B Hermitian positive definite; A and B share one CSR pattern) before
+    anything reaches the device: an unsymmetric pattern, unsymmetric real values
+    and complex values with A_ij != conj(A_ji) give ZOLO_ENOTHERM; a B with a
+    non-positive diagonal entry gives ZOLO_EINVAL."""
+    import scipy.sparse as sp
+
+    gp = pencils.grid7(4)
+    A, B = gp.scipy()
+    A = A.tocsr().astype(np.complex128 if case == "complex_values" else np.float64)
+    B = B.tocsr().astype(A.dtype)
+    n = gp.n
+    want = zolo.ZOLO_ENOTHERM
+    if case == "pattern":  # an entry (0, n-1) without its mirror (n-1, 0), in both matrices
+        E = sp.csr_matrix(([1.0], ([0], [n - 1])), shape=A.shape)
+        A = (A + 0.5 * E).tocsr()
+        B = (B + 1e-3 * E).tocsr()
+    elif case == "real_values":
+        A = A.tolil()
+        A[0, 1] = A[0, 1] + 0.25
+    elif case == "complex_values":
+        A = A.tolil()
+        A[0, 1] = A[0, 1] + 0.3j
+        A[1, 0] = A[1, 0] + 0.3j  # equal imaginary parts: not conjugate
+    else:  # b_not_positive
+        B = B.tolil()
+        B[3, 3] = -1.0
+        want = zolo.ZOLO_EINVAL
+    A, B = A.tocsr(), B.tocsr()
+    A.sort_indices()
+    B.sort_indices()
+    assert np.array_equal(A.indptr, B.indptr) and np.array_equal(A.indices, B.indices)
+    say(f"bad pencil case {case}")
+    with pytest.raises(zolo.ZoloError) as e:
+        zolo.Pencil(ctx, A.indptr, A.indices, A.data, B.data)
+    say(f"  status {e.value.status}: {e.value}")
+    assert e.value.status == want
