@@ -20,6 +20,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -86,6 +87,19 @@ struct ReleaseMark {
   }
 };
 
+// Streams whose release events the pool may query later: the null stream and
+// the streams the library creates itself (serving workers), which retire
+// through retire_stream before they are destroyed.  An event recorded on a
+// stream the caller may destroy at any time is not queried; arenas on such
+// streams synchronize the device when they release.
+std::mutex g_streams_m;
+std::set<hipStream_t> g_owned_streams;
+bool stream_marks_ok(hipStream_t s) {
+  if (!s) return true;
+  std::lock_guard<std::mutex> lk(g_streams_m);
+  return g_owned_streams.count(s) != 0;
+}
+
 class DevicePool {
  public:
   static DevicePool& get() {
@@ -108,13 +122,30 @@ class DevicePool {
     for (; it != free_.end() && it->first <= bytes + bytes / 8; ++it) {
       const Cached& c = it->second;
       if (c.dev != dev) continue;
-      if (c.mark && hipEventQuery(c.mark->ev) != hipSuccess) continue;
+      if (c.mark && !mark_done(*c.mark)) continue;
       void* p = c.p;
       cached_ -= it->first;
       free_.erase(it);
       return p;
     }
     return nullptr;
+  }
+  // the blocks released on stream s no longer wait for their events (the
+  // stream has been synchronized and is about to be destroyed)
+  void drop_marks(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(m_);
+    for (auto& kv : free_)
+      if (kv.second.mark && kv.second.mark->stream == s) kv.second.mark.reset();
+  }
+  // whether a release event has completed; a pending query result (not ready)
+  // is taken off the thread's last-error state, which the caller's own launch
+  // checks read, unless an error was already pending there
+  static bool mark_done(const ReleaseMark& m) {
+    if (hipPeekAtLastError() != hipSuccess) return false;
+    const hipError_t e = hipEventQuery(m.ev);
+    if (e == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
   }
   // keeps the block for reuse while the cache stays under its cap, three
   // quarters of the device's memory (a block that would exceed it is freed;
@@ -230,7 +261,7 @@ struct DevArena {
   void release() {
     if (ptrs.empty()) return;
     std::shared_ptr<ReleaseMark> mark;
-    if (ordered) {
+    if (ordered && stream_marks_ok(stream)) {
       mark = std::make_shared<ReleaseMark>();
       mark->stream = stream;
       if (hipEventCreateWithFlags(&mark->ev, hipEventDisableTiming) != hipSuccess ||
@@ -3785,6 +3816,20 @@ void result_mark_reused(zolo_result* r, double max_resid, double t_check) {
   r->st.subspace_reused = 1;
   r->st.max_resid = max_resid;
   r->st.t_total = t_check;
+}
+
+void register_stream(void* s) {
+  std::lock_guard<std::mutex> lk(g_streams_m);
+  g_owned_streams.insert((hipStream_t)s);
+}
+
+void retire_stream(void* s) {
+  (void)hipStreamSynchronize((hipStream_t)s);
+  {
+    std::lock_guard<std::mutex> lk(g_streams_m);
+    g_owned_streams.erase((hipStream_t)s);
+  }
+  DevicePool::get().drop_marks((hipStream_t)s);
 }
 
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out) { gaussian_host(seed, n, out); }

@@ -240,6 +240,7 @@ void worker(zolo_server* S) {
   zolo::set_inertia_cap(kInertiaShifts);
   hipStream_t st = nullptr;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+  if (st) zolo::register_stream(st);
   for (;;) {
     std::vector<zolo_query*> batch;
     int cols = 0;
@@ -480,7 +481,10 @@ void worker(zolo_server* S) {
     S->cv_work.notify_all();
     S->cv_done.notify_all();
   }
-  if (st) (void)hipStreamDestroy(st);
+  if (st) {
+    zolo::retire_stream(st);
+    (void)hipStreamDestroy(st);
+  }
 }
 
 }  // namespace

@@ -95,6 +95,10 @@ zolo_status result_verify(zolo_pencil* P, const zolo_result* r, void* s, double*
 // marks a copy handed out from a resident subspace: its max_resid recomputed
 // now, t_total the time of that check
 void result_mark_reused(zolo_result* r, double max_resid, double t_check);
+// a stream the library created: its release events may be queried until
+// retire_stream (which synchronizes it) is called before it is destroyed
+void register_stream(void* s);
+void retire_stream(void* s);
 void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
 
 }  // namespace zolo
