@@ -16,6 +16,12 @@ namespace {
 // neighbouring matrix rows share are fetched into one L2, not several.
 constexpr int kSpmmRows = 4;  // rows (waves) per 256-thread workgroup
 
+// streaming (non-temporal) stores of a 16-byte pair
+__device__ inline void store_stream(double* p, double2 v) {
+  __builtin_nontemporal_store(v.x, p);
+  __builtin_nontemporal_store(v.y, p + 1);
+}
+
 // logical workgroup of physical workgroup blk in a grid of nb8 (a multiple of 8)
 __device__ inline int64_t xcd_block(int64_t blk, int64_t nb8) { return (blk & 7) * (nb8 >> 3) + (blk >> 3); }
 inline unsigned xcd_grid(int64_t rows) { return (unsigned)((((rows + kSpmmRows - 1) / kSpmmRows) + 7) & ~int64_t(7)); }
@@ -64,40 +70,61 @@ __global__ __launch_bounds__(256) void spmm_real_kernel(int64_t n, const int64_t
   }
 }
 
-// The same with 16-byte loads: lane l takes columns 2l and 2l + 1 of a pass of
-// 128, so a 96-column block is one pass of 48 lanes (one load instruction per
-// nonzero instead of two); needs p and the leading dimensions even and the
-// blocks 16-byte aligned.
+// Eight lanes per matrix row and eight rows per wave (32 per workgroup): a
+// lane holds columns 2 (l + 8 u), u < 6, of each 96-column pass as 16-byte
+// pairs, so every lane is busy at 96 columns, a wave keeps eight rows' index
+// and value loads and their X rows in flight at once (one wave per row left
+// the dependent loads of a row exposed), and the products are written with
+// streaming stores, which leave the L2 to the X rows that neighbouring rows
+// share.  Each entry sums the row's nonzeros in order, as spmm_real_kernel does.  On
+// the 64^3 7-point stencil in the dissection order, 96 columns: B X 158 ->
+// 86 us, A X and B X 241 -> 138 us.  Needs p and the leading dimensions even
+// and the blocks 16-byte aligned.
+constexpr int kR8Lanes = 8, kR8Rows = 256 / kR8Lanes, kR8Pairs = 6;
+inline unsigned r8_grid(int64_t rows) { return (unsigned)((((rows + kR8Rows - 1) / kR8Rows) + 7) & ~int64_t(7)); }
+
 template <bool HB>
-__global__ __launch_bounds__(256) void spmm_real2_kernel(int64_t n, const int64_t* __restrict__ rp,
-                                                         const int32_t* __restrict__ ci, const double* __restrict__ a,
-                                                         const double* __restrict__ b, const double* __restrict__ X,
-                                                         int64_t ldx, int p, double* __restrict__ Ya, int64_t ldya,
-                                                         double* __restrict__ Yb, int64_t ldyb) {
-  const int64_t i = spmm_row();
+__global__ __launch_bounds__(256) void spmm_real_r8_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci, const double* __restrict__ a,
+                                                           const double* __restrict__ b, const double* __restrict__ X,
+                                                           int64_t ldx, int p, double* __restrict__ Ya, int64_t ldya,
+                                                           double* __restrict__ Yb, int64_t ldyb) {
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kR8Rows + (threadIdx.x / kR8Lanes);
   if (i >= n) return;
-  const int lane = threadIdx.x & 63;
+  const int l = threadIdx.x % kR8Lanes;
   const int64_t e0 = rp[i], e1 = rp[i + 1];
-  for (int c0 = 0; c0 < p; c0 += 128) {
-    const int c = c0 + 2 * lane;
-    const bool v = c < p;
-    const int lc = v ? c : p - 2;  // loads stay in the row; unused lanes are not stored
-    double2 sa = {0.0, 0.0}, sb = {0.0, 0.0};
-#pragma unroll 4
+  for (int c0 = 0; c0 < p; c0 += 2 * kR8Lanes * kR8Pairs) {
+    double2 sa[kR8Pairs], sb[kR8Pairs];
+    int cc[kR8Pairs];
+#pragma unroll
+    for (int u = 0; u < kR8Pairs; ++u) {
+      const int c = c0 + 2 * (l + kR8Lanes * u);
+      cc[u] = c < p ? c : p - 2;  // loads stay in the row; columns past p are not stored
+      sa[u] = double2{0.0, 0.0};
+      sb[u] = double2{0.0, 0.0};
+    }
     for (int64_t q = e0; q < e1; ++q) {
-      const double2 x = *reinterpret_cast<const double2*>(X + (int64_t)ci[q] * ldx + lc);
+      const double* xr = X + (int64_t)ci[q] * ldx;
       const double av = a[q];
-      sa.x = fma(av, x.x, sa.x);
-      sa.y = fma(av, x.y, sa.y);
-      if constexpr (HB) {
-        const double bv = b[q];
-        sb.x = fma(bv, x.x, sb.x);
-        sb.y = fma(bv, x.y, sb.y);
+      const double bv = HB ? b[q] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kR8Pairs; ++u) {
+        const double2 x = *reinterpret_cast<const double2*>(xr + cc[u]);
+        sa[u].x = fma(av, x.x, sa[u].x);
+        sa[u].y = fma(av, x.y, sa[u].y);
+        if constexpr (HB) {
+          sb[u].x = fma(bv, x.x, sb[u].x);
+          sb[u].y = fma(bv, x.y, sb[u].y);
+        }
       }
     }
-    if (v) {
-      *reinterpret_cast<double2*>(Ya + i * ldya + c) = sa;
-      if constexpr (HB) *reinterpret_cast<double2*>(Yb + i * ldyb + c) = sb;
+#pragma unroll
+    for (int u = 0; u < kR8Pairs; ++u) {
+      const int c = c0 + 2 * (l + kR8Lanes * u);
+      if (c < p) {
+        store_stream(Ya + i * ldya + c, sa[u]);
+        if constexpr (HB) store_stream(Yb + i * ldyb + c, sb[u]);
+      }
     }
   }
 }
@@ -501,10 +528,10 @@ void spmm_real(int64_t n, const int64_t* rp, const int32_t* ci, const double* a,
   auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
   if (p % 2 == 0 && ldx % 2 == 0 && ldya % 2 == 0 && al16(X) && al16(Ya) && (!Yb || (ldyb % 2 == 0 && al16(Yb)))) {
     if (Yb)
-      hipLaunchKernelGGL(spmm_real2_kernel<true>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+      hipLaunchKernelGGL(spmm_real_r8_kernel<true>, dim3(r8_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
                          ldya, Yb, ldyb);
     else
-      hipLaunchKernelGGL(spmm_real2_kernel<false>, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
+      hipLaunchKernelGGL(spmm_real_r8_kernel<false>, dim3(r8_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, X, ldx, p, Ya,
                          ldya, Yb, ldyb);
     return;
   }
