@@ -77,9 +77,10 @@ __global__ __launch_bounds__(256) void spmm_real_kernel(int64_t n, const int64_t
 // the dependent loads of a row exposed), and the products are written with
 // streaming stores, which leave the L2 to the X rows that neighbouring rows
 // share.  Each entry sums the row's nonzeros in order, as spmm_real_kernel does.  On
-// the 64^3 7-point stencil in the dissection order, 96 columns: B X 158 ->
-// 86 us, A X and B X 241 -> 138 us.  Needs p and the leading dimensions even
-// and the blocks 16-byte aligned.
+// the 64^3 7-point stencil in the dissection order, a contiguous 96-column
+// block: B X 158 -> 86 us, A X and B X 241 -> 138 us (a 96-column slice of a
+// wider basis gains less: 161 -> 133 us).  Needs p and the leading dimensions
+// even and the blocks 16-byte aligned.
 constexpr int kR8Lanes = 8, kR8Rows = 256 / kR8Lanes, kR8Pairs = 6;
 inline unsigned r8_grid(int64_t rows) { return (unsigned)((((rows + kR8Rows - 1) / kR8Rows) + 7) & ~int64_t(7)); }
 
