@@ -324,24 +324,6 @@ struct DevArena {
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 // splitmix64 + Box-Muller Gaussian start block (used when none is passed in)
-void gaussian_host(uint64_t seed, size_t n, std::vector<double>* out) {
-  out->resize(n);
-  uint64_t x = seed * 0x9E3779B97F4A7C15ULL + 0x1234567ULL;
-  auto next = [&x]() {
-    uint64_t z = (x += 0x9E3779B97F4A7C15ULL);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-  };
-  for (size_t i = 0; i < n; i += 2) {
-    double u1 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-    double u2 = ((next() >> 11) + 0.5) * (1.0 / 9007199254740992.0);
-    double r = std::sqrt(-2.0 * std::log(u1));
-    (*out)[i] = r * std::cos(2.0 * M_PI * u2);
-    if (i + 1 < n) (*out)[i + 1] = r * std::sin(2.0 * M_PI * u2);
-  }
-}
-
 struct GemmLaunch {
   int off = 0, cnt = 0, tiles = 0;
   int maxM = 0, maxN = 0;  // bounds over the launch's products (GEMM launches)
@@ -3285,10 +3267,10 @@ zolo_status solve_impl(zolo_ctx* ctx, zolo_pencil* P, double a, double b, int n_
   if (d_Q0) {
     rows_gather<VT>(Q, nss, (const VT*)d_Q0, nss, P->perm, n, nss, s);
   } else {
-    // seeded Gaussian start block (complex pencils: independent real and imaginary parts)
-    std::vector<double> g;
-    gaussian_host(o.seed, (size_t)n * nss * (ST<VT>::cplx ? 2 : 1), &g);
-    HIPC(hipMemcpy(X, g.data(), sizeof(double) * g.size(), hipMemcpyHostToDevice));  // X as staging
+    // seeded Gaussian start block (complex pencils: independent real and imaginary
+    // parts), drawn on the device into X as staging
+    gaussian_fill(o.seed, (int64_t)n * nss * (ST<VT>::cplx ? 2 : 1), (double*)X, s);
+    HIPC(hipGetLastError());
     rows_gather<VT>(Q, nss, X, nss, P->perm, n, nss, s);
   }
   t0 = now_s();
@@ -3832,6 +3814,8 @@ void retire_stream(void* s) {
   DevicePool::get().drop_marks((hipStream_t)s);
 }
 
-void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out) { gaussian_host(seed, n, out); }
+void gaussian_device(uint64_t seed, int64_t n, double* d_out, void* stream) {
+  gaussian_fill(seed, n, d_out, as_stream(stream));
+}
 
 }  // namespace zolo

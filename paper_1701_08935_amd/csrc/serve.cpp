@@ -356,12 +356,9 @@ void worker(zolo_server* S) {
     // eigengaps left to the library and no subspace size given: the subspace
     // follows the inertia count, and the library draws its own start block
     const bool free_nss = gaps_estimated(h->o) && h->o.n_ss <= 0 && h->Q0.empty();
-    std::vector<double> g;
-    const std::vector<double>* src = &h->Q0;
-    if (!free_nss && h->Q0.empty()) {
-      zolo::gaussian_block(h->o.seed, (size_t)n * h->nss * (zolo::pencil_cplx(h->P) ? 2 : 1), &g);
-      src = &g;
-    }
+    // the start block: the caller's (copied to the device) or the seeded Gaussian
+    // block, drawn on the device
+    const size_t q0_len = (size_t)n * h->nss * (zolo::pencil_cplx(h->P) ? 2 : 1);
     if (free_nss) {
       zolo_opts o = h->o;
       if (F_in && hit.estimated) {
@@ -376,11 +373,13 @@ void worker(zolo_server* S) {
       }
       rc = zolo::solve_resident(S->ctx, h->P, h->a, h->b, h->n_lambda, &o, nullptr, st, F_in,
                                 F_in ? nullptr : &F_new, &res);
-    } else if (hipMalloc(&dq, sizeof(double) * src->size()) != hipSuccess) {
+    } else if (hipMalloc(&dq, sizeof(double) * q0_len) != hipSuccess) {
       rc = ZOLO_ENOMEM;
-    } else if (hipMemcpyAsync(dq, src->data(), sizeof(double) * src->size(), hipMemcpyHostToDevice, st) != hipSuccess) {
+    } else if (!h->Q0.empty() &&
+               hipMemcpyAsync(dq, h->Q0.data(), sizeof(double) * q0_len, hipMemcpyHostToDevice, st) != hipSuccess) {
       rc = ZOLO_EDEVICE;
     } else {
+      if (h->Q0.empty()) zolo::gaussian_device(h->o.seed, (int64_t)q0_len, dq, st);
       zolo_opts o = h->o;
       o.n_ss = h->nss;
       if (F_in && hit.estimated) {  // the gaps and r1 the library chose for this interval before

@@ -61,6 +61,9 @@ void eig_resid_norms(int64_t n, const int64_t* rowptr, const int32_t* colind, co
 // Y = s1 Y + s0 V (N x p row-major blocks)
 template <typename T>
 void axpby_rows(T* Y, int64_t ldy, const T* V, int64_t ldv, double s0, double s1, int64_t n, int p, hipStream_t s);
+// out[0 .. n) = i.i.d. N(0, 1) draws of the seeded generator (the start block
+// zolo_solve and the serving loop draw when the caller passes none)
+void gaussian_fill(uint64_t seed, int64_t n, double* out, hipStream_t s);
 // asynchronous clear of device memory
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t s);
 

@@ -487,6 +487,27 @@ __global__ __launch_bounds__(256) void colnorm_final_kernel(const double* __rest
 
 inline unsigned nblk(int64_t tot) { return (unsigned)((tot + 255) / 256); }
 
+// Seeded Gaussian block: splitmix64 (a Weyl sequence x0 + k gamma through the
+// splitmix finalizer, so draw k is a function of k alone) and the Box-Muller
+// transform, one thread per pair of values (draws 2j+1 and 2j+2 of the
+// sequence give out[2j] = r cos(2 pi u2), out[2j+1] = r sin(2 pi u2)).
+__device__ inline uint64_t splitmix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__global__ void gaussian_fill_kernel(uint64_t x0, int64_t n, double* __restrict__ out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (2 * j >= n) return;
+  constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ULL;
+  const double u1 = ((splitmix(x0 + (uint64_t)(2 * j + 1) * kGamma) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = ((splitmix(x0 + (uint64_t)(2 * j + 2) * kGamma) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double r = sqrt(-2.0 * log(u1));
+  const double t = 6.283185307179586 * u2;
+  out[2 * j] = r * cos(t);
+  if (2 * j + 1 < n) out[2 * j + 1] = r * sin(t);
+}
+
 }  // namespace
 
 template <typename T>
@@ -631,6 +652,12 @@ template void eig_resid_norms<double>(int64_t, const int64_t*, const int32_t*, c
 template void eig_resid_norms<zd>(int64_t, const int64_t*, const int32_t*, const zd*, const zd*, const int32_t*,
                                   const zd*, int64_t, int, const double*, double, double, double*, double*,
                                   hipStream_t);
+
+void gaussian_fill(uint64_t seed, int64_t n, double* out, hipStream_t s) {
+  if (n <= 0) return;
+  const uint64_t x0 = seed * 0x9E3779B97F4A7C15ULL + 0x1234567ULL;
+  hipLaunchKernelGGL(gaussian_fill_kernel, dim3(nblk((n + 1) / 2)), dim3(256), 0, s, x0, n, out);
+}
 
 template <typename T>
 void axpby_rows(T* Y, int64_t ldy, const T* V, int64_t ldv, double s0, double s1, int64_t n, int p, hipStream_t s) {

@@ -67,7 +67,7 @@ int symbolic_analyze(int64_t n, const int64_t* rowptr, const int32_t* colind, co
 
 // For the serving loop: device bytes one query needs at most (factors of r1
 // poles, solve program, Krylov basis of maxit block steps, subspace blocks);
-// a deep copy of a result; the seeded Gaussian start block zolo_solve draws.
+// a deep copy of a result.
 // zolo_solve with resident factors of the same filter (F_in, used and kept by
 // the caller) or, with F_in null and F_keep non-null, handing the new
 // factorization to the caller instead of freeing it (serving loop)
@@ -99,6 +99,7 @@ void result_mark_reused(zolo_result* r, double max_resid, double t_check);
 // retire_stream (which synchronizes it) is called before it is destroyed
 void register_stream(void* s);
 void retire_stream(void* s);
-void gaussian_block(uint64_t seed, size_t n, std::vector<double>* out);
+// the seeded Gaussian start block zolo_solve draws, written on the device (n doubles)
+void gaussian_device(uint64_t seed, int64_t n, double* d_out, void* stream);
 
 }  // namespace zolo
