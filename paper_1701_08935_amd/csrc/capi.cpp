@@ -2327,8 +2327,7 @@ zolo_status poles_solve_all(zolo_factors* F, const VT* T, int p, zd* X, double t
   if (!G) return ZOLO_ENOMEM;
   Workspace& ws = *F->ws;
   run_solve<VT, zf>(F, G, T, p, false, s);
-  HIPC(hipMemsetAsync(X, 0, sizeof(zd) * npx * np, s));
-  add_lowp(X, G->X, npx * np, s);
+  set_lowp(X, G->X, npx * np, s);
   F->n_solv += (long long)p * np;
   const int64_t cnp = (int64_t)colnorm_partials(n) * p;
   std::vector<double> tn(p), rn((size_t)np * p);

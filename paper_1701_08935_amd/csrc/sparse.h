@@ -41,7 +41,8 @@ void g_combine_real(double* W, int64_t ldw, const double* V, int64_t ldv, double
 // dst = conj(src)
 template <typename T>
 void conj_copy(T* dst, const T* src, int64_t n, hipStream_t s);
-// X += cvt(D)
+// X = cvt(D); X += cvt(D)
+void set_lowp(zd* X, const zf* D, int64_t n, hipStream_t s);
 void add_lowp(zd* X, const zf* D, int64_t n, hipStream_t s);
 void add_same(zd* X, const zd* D, int64_t n, hipStream_t s);
 // column sums of |x|^2 (N x p row-major, real or complex) into out[p] (device)
