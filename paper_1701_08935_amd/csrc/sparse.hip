@@ -21,10 +21,6 @@ __device__ inline void store_stream(double* p, double2 v) {
   __builtin_nontemporal_store(v.x, p);
   __builtin_nontemporal_store(v.y, p + 1);
 }
-__device__ inline void store_stream(zd* p, zd v) {
-  __builtin_nontemporal_store(v.re, &p->re);
-  __builtin_nontemporal_store(v.im, &p->im);
-}
 
 // logical workgroup of physical workgroup blk in a grid of nb8 (a multiple of 8)
 __device__ inline int64_t xcd_block(int64_t blk, int64_t nb8) { return (blk & 7) * (nb8 >> 3) + (blk >> 3); }
@@ -255,47 +251,34 @@ __global__ void eig_resid_final_kernel(const double* __restrict__ partial, int g
   out[c] = den > 0.0 ? sqrt(sr) / den : (sr == 0.0 ? 0.0 : INFINITY);
 }
 
-// R = T - (A - sigma B) X  (X complex, ld p; T real, ld ldt; R complex, ld p), eight
-// lanes per row and eight rows per wave (the layout of spmm_real_r8_kernel): a
-// lane takes complex columns c0 + l + 8 u, u < 12, of each 96-column pass; the
-// multiply-adds in the order of the one-wave-per-row kernel it replaces.
-constexpr int kR8Cplx = 12;
-__global__ __launch_bounds__(256) void spmm_shift_resid_r8_kernel(int64_t n, const int64_t* __restrict__ rp,
-                                                                  const int32_t* __restrict__ ci,
-                                                                  const double* __restrict__ a,
-                                                                  const double* __restrict__ b, double sr, double si,
-                                                                  const zd* __restrict__ X,
-                                                                  const double* __restrict__ T, int64_t ldt, int p,
-                                                                  zd* __restrict__ R) {
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kR8Rows + (threadIdx.x / kR8Lanes);
+// R = T - (A - sigma B) X  (X complex, ld p; T real, ld ldt; R complex, ld p)
+__global__ __launch_bounds__(256) void spmm_shift_resid_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const double* __restrict__ a,
+                                                               const double* __restrict__ b, double sr, double si,
+                                                               const zd* __restrict__ X, const double* __restrict__ T,
+                                                               int64_t ldt, int p, zd* __restrict__ R) {
+  const int64_t i = spmm_row();
   if (i >= n) return;
-  const int l = threadIdx.x % kR8Lanes;
+  const int lane = threadIdx.x & 63;
   const int64_t e0 = rp[i], e1 = rp[i + 1];
-  for (int c0 = 0; c0 < p; c0 += kR8Lanes * kR8Cplx) {
-    double re[kR8Cplx], im[kR8Cplx];
-    int cc[kR8Cplx];
-#pragma unroll
-    for (int u = 0; u < kR8Cplx; ++u) {
-      const int c = c0 + l + kR8Lanes * u;
-      cc[u] = c < p ? c : p - 1;  // loads stay in the row; columns past p are not stored
-      re[u] = 0.0;
-      im[u] = 0.0;
-    }
+  for (int c0 = 0; c0 < p; c0 += 128) {
+    const int c1 = c0 + lane, c2 = c1 + 64;
+    const bool v1 = c1 < p, v2 = c2 < p;
+    const int l1 = v1 ? c1 : p - 1, l2 = v2 ? c2 : p - 1;  // loads stay in the row; unused lanes are not stored
+    double r1 = 0.0, i1 = 0.0, r2 = 0.0, i2 = 0.0;
+#pragma unroll 4
     for (int64_t q = e0; q < e1; ++q) {
       const zd* xr = X + (int64_t)ci[q] * p;
+      const zd x1 = xr[l1], x2 = xr[l2];
       const double kr = a[q] - sr * b[q], ki = -si * b[q];  // (A - sigma B)_iq
-#pragma unroll
-      for (int u = 0; u < kR8Cplx; ++u) {
-        const zd x = xr[cc[u]];
-        re[u] = fma(kr, x.re, fma(-ki, x.im, re[u]));
-        im[u] = fma(kr, x.im, fma(ki, x.re, im[u]));
-      }
+      r1 = fma(kr, x1.re, fma(-ki, x1.im, r1));
+      i1 = fma(kr, x1.im, fma(ki, x1.re, i1));
+      r2 = fma(kr, x2.re, fma(-ki, x2.im, r2));
+      i2 = fma(kr, x2.im, fma(ki, x2.re, i2));
     }
-#pragma unroll
-    for (int u = 0; u < kR8Cplx; ++u) {
-      const int c = c0 + l + kR8Lanes * u;
-      if (c < p) store_stream(R + i * p + c, zd{T[i * ldt + c] - re[u], -im[u]});
-    }
+    if (v1) R[i * p + c1] = zd{T[i * ldt + c1] - r1, -i1};
+    if (v2) R[i * p + c2] = zd{T[i * ldt + c2] - r2, -i2};
   }
 }
 
@@ -592,8 +575,8 @@ void spmm_real(int64_t n, const int64_t* rp, const int32_t* ci, const double* a,
 void spmm_shift_resid(int64_t n, const int64_t* rp, const int32_t* ci, const double* a, const double* b, double sr,
                       double si, const zd* X, const double* T, int64_t ldt, int p, zd* R, hipStream_t s) {
   if (n * p == 0) return;
-  hipLaunchKernelGGL(spmm_shift_resid_r8_kernel, dim3(r8_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, sr, si, X, T, ldt,
-                     p, R);
+  hipLaunchKernelGGL(spmm_shift_resid_kernel, dim3(xcd_grid(n)), dim3(256), 0, s, n, rp, ci, a, b, sr, si, X, T, ldt, p,
+                     R);
 }
 
 void spmm_shift_resid(int64_t n, const int64_t* rp, const int32_t* ci, const zd* a, const zd* b, double sr,
